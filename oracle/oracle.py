@@ -1,0 +1,251 @@
+"""ctypes binding of the FP64 CPU oracle (test infrastructure only).
+
+Only the test-suite, the smoke check and the benchmark's CPU-baseline leg use
+this module.  It compiles ``liboracle.so`` from ``pmc_oracle.c`` with gcc when
+the library is missing or older than its source.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "pmc_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+NO_STRAGGLE, NO_MCS, NO_NUCLEAR = 1, 2, 4
+_lock = threading.Lock()
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle (gcc -O2, OpenMP, no fast-math)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < max(
+            os.path.getmtime(SRC), os.path.getmtime(os.path.join(HERE, "pmc_oracle.h"))):
+        tmp = LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fopenmp", "-fPIC",
+                               "-shared", "-Wall", "-Wno-unknown-pragmas", SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class Params(C.Structure):
+    _fields_ = [("f_mcs", C.c_double), ("s_min_cm", C.c_double), ("k_batches", C.c_int32),
+                ("flags", C.c_uint32), ("n_threads", C.c_int32)]
+
+
+class MaterialTable(C.Structure):
+    _fields_ = [("n_bins", C.c_int32), ("hu_lo", C.c_void_p), ("rho_lo", C.c_void_p),
+                ("rho_hi", C.c_void_p), ("mass_frac", C.c_void_p), ("i_ev", C.c_void_p),
+                ("own_table", C.c_void_p)]
+
+
+class NuclearData(C.Structure):
+    _fields_ = [("sigma_ne", C.c_void_p), ("sigma_el", C.c_void_p), ("mult_cdf", C.c_void_p),
+                ("f_local", C.c_void_p), ("x_cdf", C.c_void_p), ("mu_cdf", C.c_void_p)]
+
+
+class Summary(C.Structure):
+    _fields_ = [("incident", C.c_double), ("deposited", C.c_double), ("escaped", C.c_double),
+                ("neutral", C.c_double), ("histories", C.c_uint64), ("steps", C.c_uint64),
+                ("secondaries", C.c_uint64), ("n_elastic", C.c_uint64),
+                ("n_nonelastic", C.c_uint64), ("interactions", (C.c_uint64 * 7) * 2),
+                ("total_weight", C.c_double), ("wall_s", C.c_double), ("threads", C.c_int32)]
+
+
+class Diag(C.Structure):
+    _fields_ = [("uid_begin", C.c_uint64), ("uid_end", C.c_uint64), ("batch_tally", C.c_void_p),
+                ("first_nuclear_z_cm", C.c_void_p), ("escape_log", C.c_void_p),
+                ("escape_cap", C.c_uint64), ("escape_count", C.c_uint64)]
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build()
+            L = C.CDLL(LIB)
+            d, u32p = C.c_double, C.POINTER(C.c_uint32)
+            L.oracle_create.argtypes = [C.POINTER(C.c_void_p), C.POINTER(Params)]
+            L.oracle_destroy.argtypes = [C.c_void_p]
+            L.oracle_load_physics.argtypes = [C.c_void_p, C.POINTER(NuclearData)]
+            L.oracle_load_geometry.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int,
+                                               C.c_float, C.c_float, C.c_float,
+                                               C.POINTER(MaterialTable)]
+            L.oracle_run_spots.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_uint64, C.c_uint64,
+                                           C.c_void_p, C.c_void_p, C.POINTER(Summary),
+                                           C.POINTER(Diag)]
+            L.oracle_philox4x32_10.argtypes = [u32p, u32p, u32p]
+            L.oracle_philox4x32_10.restype = None
+            L.oracle_u01.argtypes = [C.c_uint32]
+            for name, args in [("oracle_normal_quantile", [d]),
+                               ("oracle_bethe_bloch", [d, d, d]),
+                               ("oracle_stopping_power", [d, d, d]),
+                               ("oracle_bb_peak_energy", [d, d]),
+                               ("oracle_radiation_length", [C.POINTER(C.c_double)]),
+                               ("oracle_water_z_over_a", []),
+                               ("oracle_range", [C.c_void_p, C.c_int, d]),
+                               ("oracle_energy_at_range", [C.c_void_p, C.c_int, d]),
+                               ("oracle_highland_theta0", [d, d, d, d]),
+                               ("oracle_straggling_variance", [d, d, d, d]),
+                               ("oracle_sigma", [C.c_void_p, C.c_int, C.c_int, d]),
+                               ("oracle_u01", [C.c_uint32])]:
+                f = getattr(L, name)
+                f.argtypes = args
+                f.restype = d
+            L.oracle_material_info.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_double)]
+            L.oracle_elastic_sample.argtypes = [C.c_int, d, d, d, C.POINTER(C.c_double)]
+            L.oracle_secondary_sample.argtypes = [C.c_void_p, C.c_int, d, C.c_uint64, C.c_uint32,
+                                                  C.c_uint64, d, C.POINTER(C.c_int),
+                                                  C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                                  C.POINTER(C.c_double)]
+            L.oracle_rotate.argtypes = [C.POINTER(C.c_double), d, d, d]
+            L.oracle_rotate.restype = None
+            _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def philox(key, ctr):
+    """Philox4x32-10 block for key (2 u32) and counter (4 u32)."""
+    k = (C.c_uint32 * 2)(*[int(x) & 0xFFFFFFFF for x in key])
+    c = (C.c_uint32 * 4)(*[int(x) & 0xFFFFFFFF for x in ctr])
+    o = (C.c_uint32 * 4)()
+    lib().oracle_philox4x32_10(k, c, o)
+    return list(o)
+
+
+def elastic_sample(mass_number, t_mev, u_comp, u_t):
+    out = (C.c_double * 7)()
+    lib().oracle_elastic_sample(int(mass_number), t_mev, u_comp, u_t, out)
+    return list(out)
+
+
+def rotate(d, ct, st, phi_rev):
+    arr = (C.c_double * 3)(*d)
+    lib().oracle_rotate(arr, ct, st, phi_rev)
+    return list(arr)
+
+
+def radiation_length(w):
+    arr = (C.c_double * 7)(*[float(x) for x in w])
+    return lib().oracle_radiation_length(arr)
+
+
+class Oracle:
+    """One oracle context: physics tables + one geometry."""
+
+    def __init__(self, f_mcs=1.07, s_min_cm=1e-4, k_batches=10, flags=0, n_threads=0):
+        L = lib()
+        self._p = Params(f_mcs, s_min_cm, k_batches, flags, n_threads)
+        h = C.c_void_p()
+        rc = L.oracle_create(C.byref(h), C.byref(self._p))
+        if rc:
+            raise ValueError("oracle_create failed: %d" % rc)
+        self.h = h
+        self.k_batches = k_batches
+        self._keep = []
+        self.shape = None
+
+    def close(self):
+        if self.h:
+            lib().oracle_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def load_physics(self, nd: dict):
+        arrs = [np.ascontiguousarray(nd[k], dtype=np.float32)
+                for k in ("sigma_ne", "sigma_el", "mult_cdf", "f_local", "x_cdf", "mu_cdf")]
+        self._phys = arrs
+        s = NuclearData(*[_ptr(a) for a in arrs])
+        rc = lib().oracle_load_physics(self.h, C.byref(s))
+        if rc:
+            raise ValueError("oracle_load_physics failed: %d" % rc)
+
+    def load_geometry(self, hu, voxel_cm, mt: dict):
+        hu = np.ascontiguousarray(hu, dtype=np.int16)
+        nz, ny, nx = hu.shape
+        arrs = [np.ascontiguousarray(mt["hu_lo"], dtype=np.int16),
+                np.ascontiguousarray(mt["rho_lo"], dtype=np.float32),
+                np.ascontiguousarray(mt["rho_hi"], dtype=np.float32),
+                np.ascontiguousarray(mt["mass_frac"], dtype=np.float32),
+                np.ascontiguousarray(mt["i_ev"], dtype=np.float32),
+                np.ascontiguousarray(mt["own_table"], dtype=np.int32)]
+        t = MaterialTable(len(arrs[0]), *[_ptr(a) for a in arrs])
+        rc = lib().oracle_load_geometry(self.h, _ptr(hu), nx, ny, nz, float(voxel_cm[0]),
+                                        float(voxel_cm[1]), float(voxel_cm[2]), C.byref(t))
+        if rc:
+            raise ValueError("oracle_load_geometry failed: %d" % rc)
+        self.shape = (nz, ny, nx)
+
+    def run_spots(self, spots, n_histories, seed, batch_tally=False, first_nuclear=False,
+                  escape_cap=0, uid_range=None):
+        spots = np.ascontiguousarray(spots, dtype=np.float32).reshape(-1, 6)
+        dose = np.zeros(self.shape, dtype=np.float64)
+        var = np.zeros(self.shape, dtype=np.float64)
+        s = Summary()
+        dg = Diag()
+        out = {}
+        if uid_range is not None:
+            dg.uid_begin, dg.uid_end = int(uid_range[0]), int(uid_range[1])
+        if batch_tally:
+            bt = np.zeros(self.shape + (self.k_batches,), dtype=np.float64)
+            dg.batch_tally = _ptr(bt)
+            out["batch_tally"] = bt
+        if first_nuclear:
+            fz = np.zeros(int(n_histories), dtype=np.float64)
+            dg.first_nuclear_z_cm = _ptr(fz)
+            out["first_nuclear_z"] = fz
+        if escape_cap:
+            el = np.zeros((int(escape_cap), 8), dtype=np.float64)
+            dg.escape_log = _ptr(el)
+            dg.escape_cap = int(escape_cap)
+        rc = lib().oracle_run_spots(self.h, _ptr(spots), len(spots), int(n_histories), int(seed),
+                                    _ptr(dose), _ptr(var), C.byref(s), C.byref(dg))
+        if rc:
+            raise ValueError("oracle_run_spots failed: %d" % rc)
+        if escape_cap:
+            out["escapes"] = el[:min(int(dg.escape_count), int(escape_cap))]
+        summ = {f[0]: getattr(s, f[0]) for f in Summary._fields_ if f[0] != "interactions"}
+        summ["interactions"] = np.array([[s.interactions[a][e] for e in range(7)]
+                                         for a in range(2)], dtype=np.int64)
+        out.update(dose=dose, var=var, summary=summ)
+        return out
+
+    # ---- pieces for pins ----
+    def range(self, t_mev, table=0):
+        return lib().oracle_range(self.h, table, float(t_mev))
+
+    def energy_at_range(self, r, table=0):
+        return lib().oracle_energy_at_range(self.h, table, float(r))
+
+    def material_info(self, m):
+        out = (C.c_double * 6)()
+        if lib().oracle_material_info(self.h, m, out):
+            raise ValueError("bad material index")
+        keys = ("z_over_a", "i_ev", "f", "x0_g_cm2", "own", "nuclei_per_g")
+        return dict(zip(keys, list(out)))
+
+    def sigma(self, process, element, t_mev):
+        return lib().oracle_sigma(self.h, process, element, float(t_mev))
+
+    def secondary_sample(self, element, t_mev, uid, k, seed, u_mult):
+        n = C.c_int()
+        e = (C.c_double * 4)()
+        mu = (C.c_double * 4)()
+        fl = C.c_double()
+        lib().oracle_secondary_sample(self.h, element, t_mev, uid, k, seed, u_mult, C.byref(n),
+                                      e, mu, C.byref(fl))
+        return n.value, list(e)[:n.value], list(mu)[:n.value], fl.value

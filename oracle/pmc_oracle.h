@@ -1,0 +1,128 @@
+/*
+ * pmc_oracle.h - plain double-precision CPU reference of condensed-history
+ * proton transport with dose scoring, after Wan Chan Tseung, Ma & Beltran,
+ * "A fast GPU-based Monte Carlo simulation of proton transport with detailed
+ * modeling of non-elastic interactions" (arXiv:1409.8336), Sec. II.A-II.B.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  The product path (the
+ * HIP engine) never calls it and shares no code with it.
+ *
+ * Conventions (identical to the engine's public interface, restated here):
+ *   - HU grid, dose and variance are [nz][ny][nx], x fastest.
+ *   - The grid occupies [0,nx*dx) x [0,ny*dy) x [0,nz*dz) cm; spots start on
+ *     the z = 0 face travelling along +z.
+ *   - Element order everywhere: H, C, N, O, P, Ca, Ti.
+ *   - Tabulated cross sections live on E_i = 0.1*2500^(i/999) MeV, i<1000,
+ *     and are interpolated linearly in ln E.
+ * All functions return 0 on success and a negative code on error.
+ */
+#ifndef PMC_ORACLE_H
+#define PMC_ORACLE_H
+#include <stddef.h>
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORA_NEL 7
+#define ORA_NE 1000
+#define ORA_SEC_NUCLEI 6
+#define ORA_SEC_EBINS 25
+#define ORA_SEC_MULT 5
+#define ORA_SEC_NCDF 32
+
+enum { ORA_NO_STRAGGLE = 1, ORA_NO_MCS = 2, ORA_NO_NUCLEAR = 4 };
+
+typedef struct {
+    double f_mcs;        /* Highland multiplier (1.07, Sec. II.A.2) */
+    double s_min_cm;     /* shortest non-range-limited step (1e-4 cm) */
+    int32_t k_batches;   /* statistical groups (10, Sec. II.B.2) */
+    uint32_t flags;      /* ORA_NO_* switches for the closed-form pins */
+    int32_t n_threads;   /* OpenMP threads, 0 = runtime default */
+} ora_params;
+
+typedef struct {
+    int32_t n_bins;
+    const int16_t* hu_lo;
+    const float* rho_lo;
+    const float* rho_hi;
+    const float* mass_frac;  /* n_bins x 7 */
+    const float* i_ev;
+    const int32_t* own_table;
+} ora_material_table;
+
+typedef struct {
+    const float* sigma_ne;   /* 7 x 1000 barn */
+    const float* sigma_el;   /* 7 x 1000 barn */
+    const float* mult_cdf;   /* 6 x 25 x 5 */
+    const float* f_local;    /* 6 x 25 */
+    const float* x_cdf;      /* 6 x 25 x 33 */
+    const float* mu_cdf;     /* 6 x 25 x 33 */
+} ora_nuclear_data;
+
+typedef struct {
+    float x_cm, y_cm, e_mev, sigma_x_cm, sigma_y_cm, weight;
+} ora_spot;
+
+typedef struct {
+    double incident, deposited, escaped, neutral;   /* weighted MeV */
+    uint64_t histories, steps, secondaries, n_elastic, n_nonelastic;
+    uint64_t interactions[2][ORA_NEL];              /* [elastic, non-elastic][element] */
+    double total_weight;
+    double wall_s;
+    int32_t threads;
+} ora_summary;
+
+/* Optional diagnostics; any pointer may be NULL. */
+typedef struct {
+    uint64_t uid_begin, uid_end;   /* simulate only these primaries (end 0 = all) */
+    double* batch_tally;           /* nvox x K raw weighted MeV */
+    double* first_nuclear_z_cm;    /* per primary uid: depth of its first nuclear event, NaN if none */
+    double* escape_log;            /* cap x 8: x,y,z (cm), u,v,w, E, weight */
+    uint64_t escape_cap;
+    uint64_t escape_count;         /* out */
+} ora_diag;
+
+typedef struct ora_ctx ora_ctx;
+
+int oracle_create(ora_ctx** out, const ora_params* p);
+int oracle_destroy(ora_ctx* c);
+int oracle_load_physics(ora_ctx* c, const ora_nuclear_data* nd);
+int oracle_load_geometry(ora_ctx* c, const int16_t* hu, int nx, int ny, int nz,
+                         float dx, float dy, float dz, const ora_material_table* mt);
+int oracle_run_spots(ora_ctx* c, const ora_spot* spots, int n_spots, uint64_t n_histories,
+                     uint64_t seed, double* dose_gy, double* var_gy2, ora_summary* s,
+                     ora_diag* diag);
+
+/* ---- individual pieces, exported for the closed-form pins ---- */
+void oracle_philox4x32_10(const uint32_t key[2], const uint32_t ctr[4], uint32_t out[4]);
+double oracle_u01(uint32_t x);
+double oracle_normal_quantile(double u);
+double oracle_bethe_bloch(double t_mev, double z_over_a, double i_ev);
+double oracle_stopping_power(double t_mev, double z_over_a, double i_ev);
+double oracle_bb_peak_energy(double z_over_a, double i_ev);
+double oracle_radiation_length(const double w[ORA_NEL]);
+double oracle_water_z_over_a(void);
+/* table 0 = water; table m+1 = own table of material bin m */
+double oracle_range(const ora_ctx* c, int table, double t_mev);
+double oracle_energy_at_range(const ora_ctx* c, int table, double r);
+int oracle_material_info(const ora_ctx* c, int m, double out[6]); /* za, I, f, X0 g/cm2, own, n/rho total */
+double oracle_highland_theta0(double t_mev, double s_cm, double x0_cm, double f);
+double oracle_straggling_variance(double t_mev, double s_cm, double rho, double za);
+double oracle_sigma(const ora_ctx* c, int process, int element, double t_mev);
+/* Ranft elastic (A>=2) or isotropic p-p (A==1) at kinetic energy T:
+   out = {|t| MeV^2, recoil kinetic energy, scattered kinetic energy,
+          cos theta_lab, sin theta_lab, cos recoil, sin recoil} */
+int oracle_elastic_sample(int mass_number, double t_mev, double u_comp, double u_t, double out[7]);
+/* Non-elastic secondaries on nucleus element index e (1..6) at T.
+   Writes n (<=4) energies, cosines and the local fraction. */
+int oracle_secondary_sample(const ora_ctx* c, int element, double t_mev, uint64_t uid,
+                            uint32_t k, uint64_t seed, double u_mult, int* n_out,
+                            double e_out[4], double mu_out[4], double* f_local);
+void oracle_rotate(double dir[3], double cos_t, double sin_t, double phi_rev);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
