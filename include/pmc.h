@@ -1,0 +1,195 @@
+/*
+ * pmc.h - C ABI of the MI355X (gfx950) proton-transport Monte Carlo engine.
+ *
+ * The engine computes dose by condensed-history Monte Carlo transport of
+ * proton histories through a voxelised CT, following Wan Chan Tseung, Ma &
+ * Beltran, "A fast GPU-based Monte Carlo simulation of proton transport with
+ * detailed modeling of non-elastic interactions" (arXiv:1409.8336):
+ *   - geometry from HU via a piecewise material table (Sec. II.A.1);
+ *   - stopping power with water scaling, Eq. 1, and range scaling, Eq. 2
+ *     (Sec. II.A.2); titanium-like bins use their own tables;
+ *   - Highland multiple scattering x F (Sec. II.A.2), Gaussian straggling;
+ *   - steps limited by the nuclear distance, the voxel boundary and the
+ *     residual range, with a random hinge (Sec. II.A.3);
+ *   - nuclear elastic scattering, Eq. 3 (Sec. II.A.5), and non-elastic events
+ *     emitting secondary protons from a per-nucleus table (Sec. II.A.4);
+ *   - N histories in K statistical groups, dose and its variance
+ *     (Sec. II.B.2).
+ *
+ * Every entry point is a plain C function taking plain pointers and sizes and
+ * returning a pmc_status; no C++ exception crosses this boundary.  On error
+ * the outputs are left untouched and pmc_last_error() returns a message.
+ *
+ * Conventions used throughout:
+ *   - 3-D arrays (HU, dose, variance) are [nz][ny][nx], x fastest.
+ *   - The grid spans [0,nx*dx) x [0,ny*dy) x [0,nz*dz) cm.  Beam spots start
+ *     on the z = 0 face, travelling along +z, with zero divergence.
+ *   - Element order of every per-element array: H, C, N, O, P, Ca, Ti.
+ *   - Tabulated nuclear data live on the energy grid
+ *     E_i = 0.1 * 2500^(i/999) MeV, i = 0..999, linear in ln E between points.
+ *   - Dose is dose to medium in Gy per unit primary weight; variance is the
+ *     variance of that estimate from the K groups, in Gy^2.
+ *   - Random numbers: Philox4x32-10 keyed by the run seed, counter =
+ *     (particle uid, step index, tag); results depend only on the seed and the
+ *     inputs, not on launch shape, up to the order of floating-point sums.
+ *   - Threading: a context may be used by one host thread at a time.
+ */
+#ifndef PMC_H
+#define PMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PMC_OK = 0,
+    PMC_ERR_ARG = -1,            /* NULL pointer, bad size or inconsistent table */
+    PMC_ERR_RANGE = -2,          /* spot energy outside (0.1, 250] MeV, negative weight or width */
+    PMC_ERR_NOMEM = -3,          /* device or host allocation failed */
+    PMC_ERR_DEVICE = -4,         /* HIP runtime error (message in pmc_last_error) */
+    PMC_ERR_QUEUE_OVERFLOW = -5, /* secondary queue full: dose incomplete, energy counted as overflow */
+    PMC_ERR_STATE = -6           /* call order: physics and geometry must be loaded first */
+} pmc_status;
+
+/* Test switches: the closed-form special cases of the method. */
+enum {
+    PMC_NO_STRAGGLE = 1u,  /* mean energy loss only */
+    PMC_NO_MCS = 2u,       /* no angular deflection */
+    PMC_NO_NUCLEAR = 4u    /* no elastic or non-elastic nuclear events */
+};
+
+typedef struct {
+    double f_mcs;            /* Highland width multiplier; 1.07 in the paper (Sec. II.A.2) */
+    double s_min_cm;         /* shortest step unless range-limited; 1e-4 cm */
+    int32_t k_batches;       /* statistical groups; 10 in the paper (Sec. II.B.2), 2..64 */
+    uint32_t flags;          /* PMC_NO_* */
+    uint32_t queue_capacity; /* secondary-queue entries per generation; 0 = automatic */
+    int32_t block_threads;   /* transport workgroup size (64..1024, multiple of 64); 0 = tuned */
+    int32_t blocks_per_cu;   /* resident workgroups per CU for the persistent grid; 0 = occupancy */
+    int32_t refill_lanes;    /* a wave refills when at least this many of its 64 lanes are idle; 0 = tuned */
+    int32_t batch_events;    /* a wave handles pending nuclear events once this many lanes wait; 0 = tuned */
+} pmc_params;
+
+/* Fill *p with the defaults above.  Never fails for a non-NULL p. */
+pmc_status pmc_default_params(pmc_params* p);
+
+typedef struct {
+    float x_cm, y_cm;          /* spot centre on the z = 0 face */
+    float e_mev;               /* kinetic energy, (0.1, 250] */
+    float sigma_x_cm, sigma_y_cm; /* Gaussian lateral widths (>= 0) */
+    float weight;              /* relative weight (>= 0); histories are shared in proportion */
+} pmc_spot;
+
+/* HU -> material conversion (Sec. II.A.1).  Bin b covers HU in
+ * [hu_lo[b], hu_lo[b+1]) (the last bin ends at 3000); density rises linearly
+ * from rho_lo[b] to rho_hi[b] across the bin; composition and mean excitation
+ * energy are constant within a bin.  own_table[b] != 0 marks a bin (at most
+ * one, titanium in the paper) whose stopping power comes from its own
+ * Bethe-Bloch table instead of water scaling.  HU outside [-1000, 3000] is
+ * clipped.  All arrays hold n_bins entries (mass_frac n_bins x 7, rows sum to
+ * 1); hu_lo ascending with hu_lo[0] <= -1000; 1 <= n_bins <= 16. */
+typedef struct {
+    int32_t n_bins;
+    const int16_t* hu_lo;
+    const float* rho_lo;     /* g/cm^3 */
+    const float* rho_hi;     /* g/cm^3 */
+    const float* mass_frac;  /* n_bins x 7 */
+    const float* i_ev;       /* mean excitation energy, eV */
+    const int32_t* own_table;
+} pmc_material_table;
+
+/* Nuclear data (Sec. II.A.4-5).  Cross sections per element on the energy
+ * grid; non-elastic secondaries per nucleus C..Ti (6) and incident-energy bin
+ * of 10 MeV (25 bins):
+ *   mult_cdf[n][j][m]  P(secondary protons <= m), m = 0..4, last entry 1
+ *   f_local[n][j]      fraction of the incident energy deposited locally
+ *   x_cdf[n][j][i]     CDF of E_secondary/E_incident at i/32, i = 0..32
+ *   mu_cdf[n][j][i]    CDF of the polar cosine at -1 + 2i/32, i = 0..32 */
+typedef struct {
+    const float* sigma_ne_barn;   /* 7 x 1000 */
+    const float* sigma_el_barn;   /* 7 x 1000 */
+    const float* mult_cdf;        /* 6 x 25 x 5 */
+    const float* f_local;         /* 6 x 25 */
+    const float* x_cdf;           /* 6 x 25 x 33 */
+    const float* mu_cdf;          /* 6 x 25 x 33 */
+} pmc_nuclear_data;
+
+/* Run ledger and counters.  Energies are weighted MeV; the identity
+ * incident = deposited + escaped + neutral + overflow holds to rounding. */
+typedef struct {
+    double incident, deposited, escaped, neutral, overflow;
+    uint64_t histories, steps, secondaries, n_elastic, n_nonelastic, n_overflow;
+    double total_weight;   /* sum of primary weights (dose normalisation) */
+    double device_ms;      /* device time of the run, HIP events */
+    double transport_ms;   /* sum over transport launches of their HIP-event durations */
+    int32_t generations;   /* transport launches (primaries + secondary generations) */
+    int32_t reserved;
+} pmc_summary;
+
+typedef struct pmc_ctx pmc_ctx;
+
+/* Create a context on HIP device `device` with params p (NULL = defaults).
+ * *out receives the context, owned by the caller until pmc_destroy.
+ * Errors: PMC_ERR_ARG (out NULL, params out of range), PMC_ERR_DEVICE. */
+pmc_status pmc_create(pmc_ctx** out, int device, const pmc_params* p);
+
+/* Release every device buffer of the context.  NULL is accepted. */
+pmc_status pmc_destroy(pmc_ctx* c);
+
+/* Message for the last error on this context (never NULL; "" if none).
+ * With c == NULL: the last error of pmc_create on this thread. */
+const char* pmc_last_error(const pmc_ctx* c);
+
+/* Upload nuclear data (copied; the caller keeps ownership of nd).
+ * Errors: PMC_ERR_ARG (NULL arrays, negative cross sections, CDFs that do
+ * not start at 0 and end at 1), PMC_ERR_NOMEM, PMC_ERR_DEVICE. */
+pmc_status pmc_load_physics(pmc_ctx* c, const pmc_nuclear_data* nd);
+
+/* Build the voxel records (density, material) of an HU grid and the
+ * per-material tables (Sec. II.A.1-2, Eq. 1-2).  hu has nx*ny*nz int16 in
+ * [nz][ny][nx] order, copied to the device; dx,dy,dz voxel size in cm.
+ * Replaces the previous geometry.  Errors: PMC_ERR_ARG (dims <= 0, voxel
+ * size <= 0, bad material table), PMC_ERR_NOMEM, PMC_ERR_DEVICE. */
+pmc_status pmc_load_geometry(pmc_ctx* c, const int16_t* hu, int nx, int ny, int nz,
+                             float dx_cm, float dy_cm, float dz_cm,
+                             const pmc_material_table* mt);
+
+/* Transport n_histories primaries shared over the spots in proportion to
+ * their weights (largest remainder), seed = Philox key, and write dose and
+ * variance (host arrays of nx*ny*nz doubles) and the ledger (summary may be
+ * NULL).  Errors: PMC_ERR_STATE (no physics/geometry), PMC_ERR_ARG (NULL
+ * outputs, n_spots <= 0 with n_histories > 0), PMC_ERR_RANGE (spot values),
+ * PMC_ERR_QUEUE_OVERFLOW (outputs written, dose incomplete), PMC_ERR_NOMEM,
+ * PMC_ERR_DEVICE.  n_histories == 0 writes zeros. */
+pmc_status pmc_run_spots(pmc_ctx* c, const pmc_spot* spots, int n_spots, uint64_t n_histories,
+                         uint64_t seed, double* dose_out, double* var_out, pmc_summary* summary);
+
+/* As pmc_run_spots, with dose and variance written into caller-owned device
+ * buffers (nx*ny*nz doubles each; var may be NULL) in stream order on
+ * `hip_stream` (a hipStream_t; NULL = the null stream).  spots is a host
+ * array.  The call returns after the run has completed on the stream. */
+pmc_status pmc_run_spots_dev(pmc_ctx* c, const pmc_spot* spots, int n_spots, uint64_t n_histories,
+                             uint64_t seed, double* d_dose, double* d_var, void* hip_stream,
+                             pmc_summary* summary);
+
+/* Host-side tables the engine built for the loaded physics and geometry, for
+ * inspection (no device work).  out_lnr_water/out_lnr_own receive the 1000
+ * float32 ln(range) entries (entry 0 is -inf: zero range at 0.1 MeV) of water
+ * and of the own-table bin (zeros if none); out_sigma_per_g receives n_bins x
+ * 1000 float32 total nuclear cross sections per gram (cm^2/g);
+ * out_material receives n_bins x 4 doubles (water-equivalence factor f of
+ * Eq. 1, radiation length g/cm^2, Z/A, own-table flag).  Any output may be
+ * NULL.  Errors: PMC_ERR_STATE before both loads. */
+pmc_status pmc_inspect_tables(const pmc_ctx* c, float* out_lnr_water, float* out_lnr_own,
+                              float* out_sigma_per_g, double* out_material, int32_t* out_n_bins);
+
+/* Library version string, e.g. "pmc 0.1 gfx950". */
+const char* pmc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PMC_H */

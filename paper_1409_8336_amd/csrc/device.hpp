@@ -1,0 +1,68 @@
+// Device-side data layout shared by the transport kernels and the host
+// engine.  Everything the hot loop touches per step is either in registers
+// (particle state), in LDS (range and cross-section tables) or one 8-byte
+// voxel record gather plus one FP64 atomic tally update.
+#pragma once
+
+#include <cstdint>
+
+namespace pmc {
+
+constexpr int kWave = 64;
+constexpr int kQueuePlanes = 11;   // px py pz ux uy uz E w uid_lo uid_hi batch
+constexpr int kMaxGenerations = 64;
+
+// LDS blob layout, in 32-bit words
+constexpr int kOffLnrWater = 0;
+constexpr int kOffLnrOwn = 1000;
+constexpr int kOffInvWater = 2000;   // 1024 uint16 = 512 words
+constexpr int kOffInvOwn = 2512;
+constexpr int kOffSigma = 3024;      // n_mat x 1000 total cross section per gram
+// then n_mat x 4 words: f (Eq. 1; 1 for own-table bins), X0 (g/cm^2), Z/A, own flag
+
+struct KernelArgs {
+    // geometry: voxel record = {density as float bits, material bin}
+    const uint2* vox;
+    int nx, ny, nz;
+    float vs[3];        // voxel size, cm
+    float ivs[3];       // 1 / voxel size
+    // hot tables (staged into LDS)
+    const float* blob;
+    int blob_words;
+    int n_mat;
+    float r_first[2];   // range at grid point 1 (water, own)
+    float ln_r1[2];     // ln of it
+    float inv_step[2];  // coarse-index cells per unit ln(range)
+    // rare-path tables (global / L2)
+    const float* el_sig;    // [2][7][1000] barn, process 0 elastic, 1 non-elastic
+    const float* mat_npg;   // [n_mat][7] nuclei per gram per barn
+    const float* elem;      // [7][8]: target mass MeV, a1, b1, a2, b2 (Eq. 3)
+    const float* sec_mult;  // [6][25][5]
+    const float* sec_floc;  // [6][25]
+    const float* sec_x;     // [6][25][33]
+    const float* sec_mu;    // [6][25][33]
+    // run
+    uint32_t seed_lo, seed_hi;
+    int k_batches;
+    uint32_t flags;
+    float f_mcs, s_min;
+    // primaries (generation 0): spots[s*8 + {x/dx, y/dy, E, sx/dx, sy/dy, weight}]
+    const float* spots;
+    const unsigned long long* spot_start;   // [n_spots + 1]
+    int n_spots;
+    unsigned long long n_primary;
+    // secondary queues: plane p of entry i at q[p * q_cap + i]
+    const uint32_t* q_in;
+    uint32_t* q_out;
+    unsigned long long q_cap;
+    unsigned long long* gen_counters;   // [gen][2] = {entries produced for gen, entries claimed}
+    int gen;
+    // outputs
+    double* tally;                  // [nvox][k_batches] weighted MeV
+    double* ledger;                 // escaped, neutral, overflow
+    unsigned long long* counters;   // steps, elastic events, non-elastic events
+    int refill_lanes;
+    int batch_events;
+};
+
+}  // namespace pmc

@@ -1,0 +1,691 @@
+// Transport kernels for gfx950: persistent condensed-history stepping of
+// proton histories (arXiv:1409.8336, Sec. II.A.2-5 physics, Sec. II.B
+// parallelisation: one history per lane), dose statistics and helpers.
+//
+// Design (CDNA4):
+//   - one history per lane, state in registers for its whole residency;
+//   - persistent waves refill idle lanes from a global claim counter (primary
+//     uids in generation 0, the previous generation's secondary queue later)
+//     with one atomic per wave, so lanes stay busy without any host loop;
+//   - nuclear events are rare and long: lanes that reach one wait, and the
+//     wave processes several of them together, then appends the emitted
+//     protons to the next generation's queue with one atomic per wave;
+//   - range/cross-section tables live in LDS; the voxel record is one 8-byte
+//     gather; the dose is one FP64 atomic add per step into [voxel][group].
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+
+namespace pmc {
+
+#define DEV __device__ __forceinline__
+
+constexpr float kMp = 938.272088f;
+constexpr float kECut = 0.1f;
+constexpr float kLnE0 = -2.302585093f;            // ln 0.1
+constexpr float kInvH = 999.0f / 7.824046011f;    // 1 / (ln(2500)/999)
+constexpr float kH = 7.824046011f / 999.0f;
+constexpr float kStraggleK = 0.156914976f;        // K m_e c^2, MeV^2 cm^2 / g
+constexpr float kInf = 3.0e38f;
+constexpr uint32_t kMaxSteps = 1u << 20;
+constexpr uint32_t kNoStraggle = 1u, kNoMcs = 2u, kNoNuclear = 4u;
+
+// ---------------------------------------------------------------- helpers
+
+DEV float fln(float x) { return __builtin_amdgcn_logf(x) * 0.693147181f; }
+DEV float fexp(float x) { return __builtin_amdgcn_exp2f(x * 1.442695041f); }
+DEV float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+DEV float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+DEV float fsin_rev(float r) { return __builtin_amdgcn_sinf(r); }   // sin(2 pi r)
+DEV float fcos_rev(float r) { return __builtin_amdgcn_cosf(r); }   // cos(2 pi r)
+
+// Philox4x32-10 (Salmon et al. 2011); key = run seed, counter = (uid, k, tag)
+DEV uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+// strictly inside (0,1), exactly representable in float
+DEV float u01(uint32_t x) { return ((float)(x >> 9) + 0.5f) * (1.0f / 8388608.0f); }
+
+DEV int mbcnt(unsigned long long m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+DEV unsigned long long bcast0(unsigned long long v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// rotate direction by polar cos/sin and azimuth phi (revolutions)
+DEV void rotate(float& ux, float& uy, float& uz, float ct, float st, float phi)
+{
+    const float cp = fcos_rev(phi), sp = fsin_rev(phi);
+    const float perp = fsqrt(ux * ux + uy * uy);
+    if (perp < 1.0e-6f) {
+        ux = st * cp;
+        uy = st * sp;
+        uz = uz >= 0.f ? ct : -ct;
+        return;
+    }
+    const float ip = frcp(perp);
+    const float nx = ux * ct + st * (ux * uz * cp - uy * sp) * ip;
+    const float ny = uy * ct + st * (uy * uz * cp + ux * sp) * ip;
+    const float nz = uz * ct - st * cp * perp;
+    ux = nx;
+    uy = ny;
+    uz = nz;
+}
+
+// voxel containing p (voxel units); on a face, the voxel being entered
+DEV bool locate_axis(float p, float d, int n, int& v)
+{
+    const float f = floorf(p);
+    int i = (int)f;
+    if (p == f && d < 0.f) --i;
+    v = i;
+    return i >= 0 && i < n;
+}
+
+// grid position of energy e: bin i in [0, 998] and fraction t
+DEV void grid_pos(float e, int& i, float& t)
+{
+    const float x = (fln(e) - kLnE0) * kInvH;
+    int j = (int)x;
+    j = j < 0 ? 0 : (j > 998 ? 998 : j);
+    float f = x - (float)j;
+    f = f < 0.f ? 0.f : (f > 1.f ? 1.f : f);
+    i = j;
+    t = f;
+}
+
+DEV float inv_cdf33(const float* __restrict__ cdf, float u, float lo, float hi)
+{
+    int l = 0, h = 32;
+    while (h - l > 1) {
+        const int mid = (l + h) >> 1;
+        if (cdf[mid] <= u) l = mid;
+        else h = mid;
+    }
+    const float c0 = cdf[l], c1 = cdf[l + 1];
+    const float frac = (u - c0) / (c1 - c0);
+    return lo + (hi - lo) * ((float)l + frac) * (1.0f / 32.0f);
+}
+
+// -------------------------------------------------------------- the kernel
+
+__global__ void __launch_bounds__(256) transport_kernel(KernelArgs a)
+{
+    extern __shared__ float lds[];
+    for (int i = threadIdx.x; i < a.blob_words; i += blockDim.x) lds[i] = a.blob[i];
+    __syncthreads();
+
+    const float* lnr_w = lds + kOffLnrWater;
+    const float* lnr_o = lds + kOffLnrOwn;
+    const uint16_t* inv_w = reinterpret_cast<const uint16_t*>(lds + kOffInvWater);
+    const uint16_t* inv_o = reinterpret_cast<const uint16_t*>(lds + kOffInvOwn);
+    const float* sig = lds + kOffSigma;
+    const float* mc = lds + kOffSigma + 1000 * a.n_mat;
+
+    const int lane = threadIdx.x & (kWave - 1);
+    const int gen = a.gen;
+    unsigned long long* const claim = &a.gen_counters[2 * gen + 1];
+    unsigned long long* const out_reserve = &a.gen_counters[2 * (gen + 1)];
+    unsigned long long limit = a.n_primary;
+    if (gen > 0) {
+        const unsigned long long produced = a.gen_counters[2 * gen];
+        limit = produced < a.q_cap ? produced : a.q_cap;
+    }
+    const int K = a.k_batches;
+    const uint32_t flags = a.flags;
+
+    // particle state
+    float px = 0, py = 0, pz = 0, ux = 0, uy = 0, uz = 1, E = 0, mfp = 0, w = 0;
+    uint32_t uid_lo = 0, uid_hi = 0, k = 0, batch = 0;
+    int vx = 0, vy = 0, vz = 0;
+    bool alive = false, pend = false;
+
+    double acc_esc = 0.0, acc_neu = 0.0, acc_ovf = 0.0;
+    unsigned long long n_steps = 0, n_el = 0, n_ne = 0;
+    bool exhausted = false;
+
+    for (;;) {
+        // ---------------------------------------------------------- refill
+        const unsigned long long idle = __ballot(!alive);
+        const int n_idle = __popcll(idle);
+        if (!exhausted && n_idle > 0 && (n_idle == kWave || n_idle >= a.refill_lanes)) {
+            unsigned long long base = 0;
+            if (lane == 0) base = atomicAdd(claim, (unsigned long long)n_idle);
+            base = bcast0(base);
+            if (base + (unsigned long long)n_idle >= limit) exhausted = true;
+            if (!alive) {
+                const unsigned long long idx = base + (unsigned long long)mbcnt(idle);
+                if (idx < limit) {
+                    if (gen == 0) {
+                        // source: Gaussian spot on the z = 0 face (K1 role)
+                        int lo = 0, hi = a.n_spots;
+                        while (hi - lo > 1) {
+                            const int mid = (lo + hi) >> 1;
+                            if (a.spot_start[mid] <= idx) lo = mid;
+                            else hi = mid;
+                        }
+                        const float* sp = a.spots + 8 * lo;
+                        const unsigned long long s0 = a.spot_start[lo], s1 = a.spot_start[lo + 1];
+                        uid_lo = (uint32_t)idx;
+                        uid_hi = (uint32_t)(idx >> 32);
+                        const uint4 r = philox(uid_lo, uid_hi, 0u, 0u, a.seed_lo, a.seed_hi);
+                        const float rr = fsqrt(-2.0f * fln(u01(r.x)));
+                        const float ph = u01(r.y);
+                        px = sp[0] + sp[3] * rr * fcos_rev(ph);
+                        py = sp[1] + sp[4] * rr * fsin_rev(ph);
+                        pz = 0.f;
+                        ux = 0.f;
+                        uy = 0.f;
+                        uz = 1.f;
+                        E = sp[2];
+                        w = sp[5];
+                        mfp = -fln(u01(r.z));
+                        batch = (uint32_t)(((idx - s0) * (unsigned long long)K) / (s1 - s0));
+                    } else {
+                        const uint32_t* q = a.q_in + idx;
+                        const unsigned long long c = a.q_cap;
+                        px = __uint_as_float(q[0]);
+                        py = __uint_as_float(q[c]);
+                        pz = __uint_as_float(q[2 * c]);
+                        ux = __uint_as_float(q[3 * c]);
+                        uy = __uint_as_float(q[4 * c]);
+                        uz = __uint_as_float(q[5 * c]);
+                        E = __uint_as_float(q[6 * c]);
+                        w = __uint_as_float(q[7 * c]);
+                        uid_lo = q[8 * c];
+                        uid_hi = q[9 * c];
+                        batch = q[10 * c];
+                        const uint4 r = philox(uid_lo, uid_hi, 0u, 0u, a.seed_lo, a.seed_hi);
+                        mfp = -fln(u01(r.z));
+                    }
+                    k = 0;
+                    alive = locate_axis(px, ux, a.nx, vx) && locate_axis(py, uy, a.ny, vy) &&
+                            locate_axis(pz, uz, a.nz, vz);
+                    if (!alive) acc_esc += (double)w * (double)E;
+                }
+            }
+        }
+        const unsigned long long busy = __ballot(alive);
+        if (busy == 0) {
+            if (exhausted) break;
+            continue;
+        }
+
+        // ------------------------------------------------------------ step
+        bool stepped = false;
+        if (alive && !pend) {
+            const unsigned long long vi = ((unsigned long long)vz * a.ny + vy) * a.nx + vx;
+            const uint2 rec = a.vox[vi];
+            const float rho = __uint_as_float(rec.x);
+            const int m = (int)rec.y;
+            const float mf = mc[4 * m + 0];
+            const float mx0 = mc[4 * m + 1];
+            const float mza = mc[4 * m + 2];
+            const bool own = mc[4 * m + 3] != 0.f;
+            const float scale = rho * mf;                          // Eq. 1-2
+            const float* lnr = own ? lnr_o : lnr_w;
+            const uint16_t* inv = own ? inv_o : inv_w;
+            const float r_first = own ? a.r_first[1] : a.r_first[0];
+            const float ln_r1 = own ? a.ln_r1[1] : a.ln_r1[0];
+            const float inv_step = own ? a.inv_step[1] : a.inv_step[0];
+
+            int gi;
+            float gt;
+            grid_pos(E, gi, gt);
+            float range;
+            if (gi == 0) range = gt * r_first;
+            else range = fexp(lnr[gi] + gt * (lnr[gi + 1] - lnr[gi]));
+            const float s_range = range * frcp(scale);
+            float sigma = 0.f;
+            if (!(flags & kNoNuclear)) {
+                const float* sm = sig + 1000 * m;
+                sigma = rho * (sm[gi] + gt * (sm[gi + 1] - sm[gi]));
+            }
+            const float s_nuc = sigma > 0.f ? mfp * frcp(sigma) : kInf;
+            // distance to the voxel boundary
+            float d = kInf;
+            int axis = 2;
+            {
+                float da;
+                if (ux != 0.f) {
+                    da = ((float)(ux > 0.f ? vx + 1 : vx) - px) * a.vs[0] * frcp(ux);
+                    if (da < d) { d = da; axis = 0; }
+                }
+                if (uy != 0.f) {
+                    da = ((float)(uy > 0.f ? vy + 1 : vy) - py) * a.vs[1] * frcp(uy);
+                    if (da < d) { d = da; axis = 1; }
+                }
+                if (uz != 0.f) {
+                    da = ((float)(uz > 0.f ? vz + 1 : vz) - pz) * a.vs[2] * frcp(uz);
+                    if (da < d) { d = da; axis = 2; }
+                }
+            }
+            bool stop_here = (s_range <= d && s_range <= s_nuc);
+            const bool nuc = s_nuc < d;
+            float s = nuc ? s_nuc : d;
+            s = s < a.s_min ? a.s_min : s;
+            if (s >= s_range) stop_here = true;
+            if (stop_here) {
+                // range-limited: the proton stops in this voxel
+                unsafeAtomicAdd(&a.tally[vi * K + batch], (double)w * (double)E);
+                alive = false;
+            } else {
+                // mean loss from the range table (Eq. 2 water-equivalent path)
+                const float r1 = range - s * scale;
+                float e1;
+                if (r1 <= r_first) {
+                    e1 = fexp(kLnE0 + (r1 > 0.f ? r1 : 0.f) * frcp(r_first) * kH);
+                } else {
+                    const float lr = fln(r1);
+                    int c = (int)((lr - ln_r1) * inv_step);
+                    c = c < 0 ? 0 : (c > 1023 ? 1023 : c);
+                    int j = inv[c];
+                    while (j < 998 && lnr[j + 1] <= lr) ++j;
+                    const float tt = (lr - lnr[j]) / (lnr[j + 1] - lnr[j]);
+                    e1 = fexp(kLnE0 + ((float)j + tt) * kH);
+                }
+                float de_mean = E - e1;
+                de_mean = de_mean > 0.f ? de_mean : 0.f;
+                const float emid = E - 0.5f * de_mean;
+                const uint4 r = philox(uid_lo, uid_hi, k, 1u, a.seed_lo, a.seed_hi);
+                const float e_tot = emid + kMp;
+                const float ie_tot = frcp(e_tot);
+                const float pv = emid * (emid + 2.f * kMp) * ie_tot;      // p beta c
+                const float b2 = pv * ie_tot;
+                float de = de_mean;
+                if (!(flags & kNoStraggle)) {
+                    const float g = e_tot * (1.0f / kMp);
+                    const float var = kStraggleK * rho * mza * s * g * g * (1.f - 0.5f * b2);
+                    const float z = 1.414213562f * erfinvf(2.f * u01(r.w) - 1.f);
+                    de = de_mean + fsqrt(var) * z;
+                    de = de < 0.f ? 0.f : (de > E ? E : de);
+                }
+                float theta = 0.f;
+                if (!(flags & kNoMcs)) {
+                    const float x0 = mx0 * frcp(rho);
+                    float br = 1.f + 0.038f * fln(s * frcp(x0 * b2));
+                    br = br > 0.f ? br : 0.f;
+                    const float th0 = a.f_mcs * 13.6f * frcp(pv) * fsqrt(s * frcp(x0)) * br;
+                    theta = th0 * fsqrt(-2.f * fln(u01(r.y)));
+                }
+                // random hinge at a uniform fraction of the step
+                const float h1 = u01(r.x) * s, h2 = s - h1;
+                px += h1 * ux * a.ivs[0];
+                py += h1 * uy * a.ivs[1];
+                pz += h1 * uz * a.ivs[2];
+                if (theta != 0.f) {
+                    const float tr = theta * 0.159154943f;
+                    rotate(ux, uy, uz, fcos_rev(tr), fsin_rev(tr), u01(r.z));
+                }
+                px += h2 * ux * a.ivs[0];
+                py += h2 * uy * a.ivs[1];
+                pz += h2 * uz * a.ivs[2];
+                if (!nuc && theta == 0.f) {
+                    if (axis == 0) px = (float)(ux > 0.f ? vx + 1 : vx);
+                    else if (axis == 1) py = (float)(uy > 0.f ? vy + 1 : vy);
+                    else pz = (float)(uz > 0.f ? vz + 1 : vz);
+                }
+                const float e_new = E - de;
+                unsafeAtomicAdd(&a.tally[vi * K + batch], (double)w * ((double)E - (double)e_new));
+                mfp = nuc ? 0.f : fmaxf(mfp - sigma * s, 0.f);
+                E = e_new;
+                ++k;
+                stepped = true;
+                if (E <= kECut || k >= kMaxSteps) {
+                    // below the cut-off (or past the step cap that guards
+                    // against non-terminating histories): deposit the rest
+                    unsafeAtomicAdd(&a.tally[vi * K + batch], (double)w * (double)E);
+                    alive = false;
+                } else if (!(locate_axis(px, ux, a.nx, vx) && locate_axis(py, uy, a.ny, vy) &&
+                             locate_axis(pz, uz, a.nz, vz))) {
+                    acc_esc += (double)w * (double)E;
+                    alive = false;
+                } else if (nuc) {
+                    pend = true;
+                }
+            }
+        }
+        n_steps += __popcll(__ballot(stepped));
+
+        // ------------------------------------------- batched nuclear events
+        const unsigned long long pm = __ballot(pend);
+        if (pm == 0) continue;
+        {
+            const int np = __popcll(pm);
+            const int occ = __popcll(__ballot(alive));
+            int need = occ >> 3;
+            need = need < 1 ? 1 : need;
+            need = need < a.batch_events ? need : a.batch_events;
+            if (np < need && np < occ) continue;
+        }
+        int n_out = 0;
+        float ce0 = 0.f, ce1 = 0.f, ce2 = 0.f, ce3 = 0.f;   // emitted energies (0 = not emitted)
+        float rdx = 0.f, rdy = 0.f, rdz = 0.f;              // recoil-proton direction
+        float odx = ux, ody = uy, odz = uz;                 // parent direction at the event
+        float ox = px, oy = py, oz = pz;
+        bool recoil = false, ev_el = false, ev_ne = false;
+        uint32_t ks = k - 1u;
+        int sec_row = 0;
+        if (pend) {
+            pend = false;
+            const unsigned long long vi = ((unsigned long long)vz * a.ny + vy) * a.nx + vx;
+            const uint2 rec = a.vox[vi];
+            const int m = (int)rec.y;
+            const float T = E;
+            int gi;
+            float gt;
+            grid_pos(T, gi, gt);
+            const uint4 r3 = philox(uid_lo, uid_hi, ks, 3u, a.seed_lo, a.seed_hi);
+            float pe[7], pn[7];
+            float s_el = 0.f, s_ne = 0.f;
+#pragma unroll
+            for (int e = 0; e < 7; ++e) {
+                const float npg = a.mat_npg[7 * m + e];
+                const float* te = a.el_sig + e * 1000;
+                const float* tn = a.el_sig + (7 + e) * 1000;
+                pe[e] = npg > 0.f ? npg * (te[gi] + gt * (te[gi + 1] - te[gi])) : 0.f;
+                pn[e] = npg > 0.f ? npg * (tn[gi] + gt * (tn[gi + 1] - tn[gi])) : 0.f;
+                s_el += pe[e];
+                s_ne += pn[e];
+            }
+            if (!(s_el + s_ne > 0.f)) {
+                mfp = -fln(u01(r3.w));
+            } else {
+                const bool elastic = u01(r3.x) * (s_el + s_ne) < s_el;
+                const float target = u01(r3.y) * (elastic ? s_el : s_ne);
+                float cum = 0.f;
+                int el = 0;
+                bool done = false;
+#pragma unroll
+                for (int e = 0; e < 7; ++e) {
+                    const float part = elastic ? pe[e] : pn[e];
+                    if (!done && part > 0.f) {
+                        el = e;
+                        cum += part;
+                        if (target < cum) done = true;
+                    }
+                }
+                const uint4 r4 = philox(uid_lo, uid_hi, ks, 4u, a.seed_lo, a.seed_hi);
+                const float* ec = a.elem + 8 * el;
+                ev_el = elastic;
+                ev_ne = !elastic;
+                if (elastic) {
+                    // Eq. 3 (A >= 2) or isotropic-CM p-p; exact two-body kinematics
+                    const float bm = ec[0];
+                    const float sm = (kMp + bm) * (kMp + bm) + 2.f * bm * T;
+                    const float pcm2 = bm * bm * T * (T + 2.f * kMp) / sm;
+                    float tabs;
+                    if (el == 0) {
+                        tabs = 4.f * pcm2 * (1.f - u01(r4.x));
+                    } else {
+                        const float tmax = 4.f * pcm2 * 1.0e-6f;
+                        const float c1 = -expm1f(-ec[2] * tmax), c2 = -expm1f(-ec[4] * tmax);
+                        const float w1 = ec[1] * c1 / ec[2], w2 = ec[3] * c2 / ec[4];
+                        const bool first = u01(r3.z) * (w1 + w2) < w1;
+                        const float b = first ? ec[2] : ec[4];
+                        const float cc = first ? c1 : c2;
+                        tabs = -log1pf(-u01(r4.x) * cc) / b * 1.0e6f;
+                    }
+                    const float trr = tabs / (2.f * bm);
+                    const float tn = T - trr;
+                    const float p = sqrtf(T * (T + 2.f * kMp));
+                    const float pn2 = tn > 0.f ? tn * (tn + 2.f * kMp) : 0.f;
+                    const float pnn = sqrtf(pn2);
+                    float ct = 1.f, st = 0.f, cr = 1.f, sr = 0.f;
+                    if (pnn > 0.f && trr > 0.f) {
+                        const float dp = trr * (T + tn + 2.f * kMp) / (p + pnn);
+                        const float q2 = trr * (trr + 2.f * bm);
+                        float omc = (q2 - dp * dp) / (2.f * p * pnn);
+                        omc = omc < 0.f ? 0.f : (omc > 2.f ? 2.f : omc);
+                        ct = 1.f - omc;
+                        st = sqrtf(omc * (2.f - omc));
+                        const float pr = sqrtf(q2);
+                        cr = (dp + pnn * omc) / pr;
+                        sr = pnn * st / pr;
+                    }
+                    const float phi = u01(r4.y);
+                    const float tn_f = tn;
+                    const float tr_f = T - tn_f;
+                    const unsigned long long vi2 = vi * K + batch;
+                    if (el == 0 && tr_f > kECut) {
+                        recoil = true;
+                        ce0 = tr_f;
+                        n_out = 1;
+                        rdx = ux;
+                        rdy = uy;
+                        rdz = uz;
+                        rotate(rdx, rdy, rdz, cr, sr, phi + 0.5f);
+                        const double resid = (double)T - (double)tn_f - (double)tr_f;
+                        if (resid != 0.0) unsafeAtomicAdd(&a.tally[vi2], (double)w * resid);
+                    } else {
+                        unsafeAtomicAdd(&a.tally[vi2], (double)w * ((double)T - (double)tn_f));
+                    }
+                    rotate(ux, uy, uz, ct, st, phi);
+                    E = tn_f;
+                    if (E <= kECut) {
+                        unsafeAtomicAdd(&a.tally[vi2], (double)w * (double)E);
+                        alive = false;
+                    } else {
+                        mfp = -fln(u01(r3.w));
+                    }
+                } else {
+                    // non-elastic: secondary protons from the per-nucleus table
+                    const int nu = el - 1;
+                    int j = (int)(T * 0.1f);
+                    j = j > 24 ? 24 : j;
+                    const int row = nu * 25 + j;
+                    sec_row = row;
+                    const float* mc5 = a.sec_mult + 5 * row;
+                    const float um = u01(r4.x);
+                    int n = 0;
+                    while (n < 4 && !(um < mc5[n])) ++n;
+                    const float fl = a.sec_floc[row];
+                    const float* xr = a.sec_x + 33 * row;
+                    float sum = 0.f;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        float ev = 0.f;
+                        if (c < n) {
+                            const uint4 rc = philox(uid_lo, uid_hi, ks, 17u + c, a.seed_lo, a.seed_hi);
+                            ev = inv_cdf33(xr, u01(rc.x), 0.f, 1.f) * T;
+                        }
+                        if (c == 0) ce0 = ev;
+                        if (c == 1) ce1 = ev;
+                        if (c == 2) ce2 = ev;
+                        if (c == 3) ce3 = ev;
+                        sum += ev;
+                    }
+                    const float avail = (1.f - fl) * T;
+                    if (sum > avail) {
+                        const float rs = avail / sum;
+                        ce0 *= rs;
+                        ce1 *= rs;
+                        ce2 *= rs;
+                        ce3 *= rs;
+                    }
+                    const double loc = (double)fl * (double)T;
+                    double local = loc;
+                    const double carried = (double)ce0 + (double)ce1 + (double)ce2 + (double)ce3;
+                    if (n > 0 && ce0 <= kECut) { local += ce0; ce0 = 0.f; }
+                    if (n > 1 && ce1 <= kECut) { local += ce1; ce1 = 0.f; }
+                    if (n > 2 && ce2 <= kECut) { local += ce2; ce2 = 0.f; }
+                    if (n > 3 && ce3 <= kECut) { local += ce3; ce3 = 0.f; }
+                    n_out = (ce0 > 0.f) + (ce1 > 0.f) + (ce2 > 0.f) + (ce3 > 0.f);
+                    unsafeAtomicAdd(&a.tally[vi * K + batch], (double)w * local);
+                    acc_neu += (double)w * ((double)T - loc - carried);
+                    alive = false;
+                }
+            }
+        }
+        n_el += __popcll(__ballot(ev_el));
+        n_ne += __popcll(__ballot(ev_ne));
+        // append emitted protons to the next generation's queue
+        {
+            const unsigned long long b0 = __ballot(n_out & 1), b1 = __ballot(n_out & 2),
+                                     b2 = __ballot(n_out & 4);
+            const int total = __popcll(b0) + 2 * __popcll(b1) + 4 * __popcll(b2);
+            if (total == 0) continue;
+            const int off = mbcnt(b0) + 2 * mbcnt(b1) + 4 * mbcnt(b2);
+            unsigned long long base = 0;
+            if (lane == 0) base = atomicAdd(out_reserve, (unsigned long long)total);
+            base = bcast0(base);
+            if (n_out > 0) {
+                unsigned long long slot = base + off;
+                const unsigned long long cap = a.q_cap;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const float ev = c == 0 ? ce0 : (c == 1 ? ce1 : (c == 2 ? ce2 : ce3));
+                    if (ev > 0.f) {
+                        float dx = rdx, dy = rdy, dz = rdz;
+                        const uint32_t jj = recoil ? 0u : (uint32_t)(c + 1);
+                        if (!recoil) {
+                            const uint4 rc = philox(uid_lo, uid_hi, ks, 16u + jj, a.seed_lo, a.seed_hi);
+                            const float mu = inv_cdf33(a.sec_mu + 33 * sec_row, u01(rc.y), -1.f, 1.f);
+                            dx = odx;
+                            dy = ody;
+                            dz = odz;
+                            rotate(dx, dy, dz, mu, sqrtf(fmaxf(0.f, 1.f - mu * mu)), u01(rc.z));
+                        }
+                        const uint4 cu = philox(uid_lo, uid_hi, ks, 0xC0000000u | jj, a.seed_lo,
+                                                a.seed_hi);
+                        if (slot < cap) {
+                            uint32_t* q = a.q_out + slot;
+                            q[0] = __float_as_uint(ox);
+                            q[cap] = __float_as_uint(oy);
+                            q[2 * cap] = __float_as_uint(oz);
+                            q[3 * cap] = __float_as_uint(dx);
+                            q[4 * cap] = __float_as_uint(dy);
+                            q[5 * cap] = __float_as_uint(dz);
+                            q[6 * cap] = __float_as_uint(ev);
+                            q[7 * cap] = __float_as_uint(w);
+                            q[8 * cap] = cu.x;
+                            q[9 * cap] = cu.y;
+                            q[10 * cap] = batch;
+                        } else {
+                            acc_ovf += (double)w * (double)ev;
+                        }
+                        ++slot;
+                    }
+                }
+            }
+        }
+    }
+
+    // -------------------------------------------------- flush the ledger
+    for (int o = 32; o > 0; o >>= 1) {
+        acc_esc += __shfl_xor(acc_esc, o);
+        acc_neu += __shfl_xor(acc_neu, o);
+        acc_ovf += __shfl_xor(acc_ovf, o);
+    }
+    if (lane == 0) {
+        if (acc_esc != 0.0) unsafeAtomicAdd(&a.ledger[0], acc_esc);
+        if (acc_neu != 0.0) unsafeAtomicAdd(&a.ledger[1], acc_neu);
+        if (acc_ovf != 0.0) unsafeAtomicAdd(&a.ledger[2], acc_ovf);
+        atomicAdd(&a.counters[0], n_steps);
+        if (n_el) atomicAdd(&a.counters[1], n_el);
+        if (n_ne) atomicAdd(&a.counters[2], n_ne);
+    }
+}
+
+// dose statistics over the K groups: total, variance of the total, and the
+// deposited-energy sum (Sec. II.B.2)
+__global__ void __launch_bounds__(256) stats_kernel(const double* __restrict__ tally,
+                                                    const uint2* __restrict__ vox,
+                                                    unsigned long long nvox, int K, double conv0,
+                                                    double* __restrict__ dose,
+                                                    double* __restrict__ var, double* dep_sum)
+{
+    double part = 0.0;
+    for (unsigned long long v = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; v < nvox;
+         v += (unsigned long long)gridDim.x * blockDim.x) {
+        const double* t = tally + v * K;
+        double tot = 0.0;
+        for (int b = 0; b < K; ++b) tot += t[b];
+        const double mean = tot / K;
+        double ss = 0.0;
+        for (int b = 0; b < K; ++b) {
+            const double dd = t[b] - mean;
+            ss += dd * dd;
+        }
+        const double conv = conv0 / (double)__uint_as_float(vox[v].x);
+        dose[v] = tot * conv;
+        if (var) var[v] = (double)K / (K - 1) * ss * conv * conv;
+        part += tot;
+    }
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+    if ((threadIdx.x & 63) == 0 && part != 0.0) unsafeAtomicAdd(dep_sum, part);
+}
+
+__global__ void zero_kernel(unsigned long long* __restrict__ p, unsigned long long n)
+{
+    for (unsigned long long i = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; i < n;
+         i += (unsigned long long)gridDim.x * blockDim.x)
+        p[i] = 0ull;
+}
+
+// ------------------------------------------------------------- launchers
+
+hipError_t launch_transport(const KernelArgs& a, int grid, int block, size_t lds_bytes,
+                            hipStream_t s)
+{
+    hipLaunchKernelGGL(transport_kernel, dim3(grid), dim3(block), lds_bytes, s, a);
+    return hipGetLastError();
+}
+
+hipError_t transport_occupancy(int block, size_t lds_bytes, int* blocks_per_cu)
+{
+    if (lds_bytes > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)transport_kernel,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel, block,
+                                                        lds_bytes);
+}
+
+hipError_t launch_stats(const double* tally, const uint2* vox, unsigned long long nvox, int K,
+                        double conv0, double* dose, double* var, double* dep_sum, hipStream_t s)
+{
+    unsigned long long blocks = (nvox + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks == 0) blocks = 1;
+    hipLaunchKernelGGL(stats_kernel, dim3((unsigned)blocks), dim3(256), 0, s, tally, vox, nvox, K,
+                       conv0, dose, var, dep_sum);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s)
+{
+    const unsigned long long n = bytes / 8;
+    if (n == 0) return hipSuccess;
+    unsigned long long blocks = (n + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
+                       (unsigned long long*)p, n);
+    return hipGetLastError();
+}
+
+}  // namespace pmc

@@ -1,0 +1,239 @@
+"""Thin ctypes binding of the engine's C ABI (``include/pmc.h``).
+
+Function names match the C entry points; this module only marshals
+arguments.  Every step of the transport runs in the HIP library
+``libpmc.so`` next to this file; importing fails loudly when it is missing.
+PyTorch is used only for device buffers and streams (``pmc_run_spots_dev``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpmc.so")
+
+PMC_OK, PMC_ERR_ARG, PMC_ERR_RANGE, PMC_ERR_NOMEM = 0, -1, -2, -3
+PMC_ERR_DEVICE, PMC_ERR_QUEUE_OVERFLOW, PMC_ERR_STATE = -4, -5, -6
+PMC_NO_STRAGGLE, PMC_NO_MCS, PMC_NO_NUCLEAR = 1, 2, 4
+
+# every symbol include/pmc.h declares
+EXPORTS = ("pmc_default_params", "pmc_create", "pmc_destroy", "pmc_last_error",
+           "pmc_load_physics", "pmc_load_geometry", "pmc_run_spots", "pmc_run_spots_dev",
+           "pmc_inspect_tables", "pmc_version")
+
+
+class PMCError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("pmc status %d: %s" % (status, message))
+        self.status = status
+
+
+class pmc_params(C.Structure):
+    _fields_ = [("f_mcs", C.c_double), ("s_min_cm", C.c_double), ("k_batches", C.c_int32),
+                ("flags", C.c_uint32), ("queue_capacity", C.c_uint32),
+                ("block_threads", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("refill_lanes", C.c_int32), ("batch_events", C.c_int32)]
+
+
+class pmc_spot(C.Structure):
+    _fields_ = [("x_cm", C.c_float), ("y_cm", C.c_float), ("e_mev", C.c_float),
+                ("sigma_x_cm", C.c_float), ("sigma_y_cm", C.c_float), ("weight", C.c_float)]
+
+
+class pmc_material_table(C.Structure):
+    _fields_ = [("n_bins", C.c_int32), ("hu_lo", C.c_void_p), ("rho_lo", C.c_void_p),
+                ("rho_hi", C.c_void_p), ("mass_frac", C.c_void_p), ("i_ev", C.c_void_p),
+                ("own_table", C.c_void_p)]
+
+
+class pmc_nuclear_data(C.Structure):
+    _fields_ = [("sigma_ne_barn", C.c_void_p), ("sigma_el_barn", C.c_void_p),
+                ("mult_cdf", C.c_void_p), ("f_local", C.c_void_p), ("x_cdf", C.c_void_p),
+                ("mu_cdf", C.c_void_p)]
+
+
+class pmc_summary(C.Structure):
+    _fields_ = [("incident", C.c_double), ("deposited", C.c_double), ("escaped", C.c_double),
+                ("neutral", C.c_double), ("overflow", C.c_double), ("histories", C.c_uint64),
+                ("steps", C.c_uint64), ("secondaries", C.c_uint64), ("n_elastic", C.c_uint64),
+                ("n_nonelastic", C.c_uint64), ("n_overflow", C.c_uint64),
+                ("total_weight", C.c_double), ("device_ms", C.c_double),
+                ("transport_ms", C.c_double), ("generations", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libpmc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libpmc.so is not built: run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, u64 = C.c_void_p, C.c_int, C.c_uint64
+        L.pmc_default_params.argtypes = [C.POINTER(pmc_params)]
+        L.pmc_create.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(pmc_params)]
+        L.pmc_destroy.argtypes = [vp]
+        L.pmc_last_error.argtypes = [vp]
+        L.pmc_last_error.restype = C.c_char_p
+        L.pmc_load_physics.argtypes = [vp, C.POINTER(pmc_nuclear_data)]
+        L.pmc_load_geometry.argtypes = [vp, vp, i32, i32, i32, C.c_float, C.c_float, C.c_float,
+                                        C.POINTER(pmc_material_table)]
+        L.pmc_run_spots.argtypes = [vp, vp, i32, u64, u64, vp, vp, C.POINTER(pmc_summary)]
+        L.pmc_run_spots_dev.argtypes = [vp, vp, i32, u64, u64, vp, vp, vp, C.POINTER(pmc_summary)]
+        L.pmc_inspect_tables.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.pmc_version.restype = C.c_char_p
+        for name in EXPORTS:
+            if name not in ("pmc_last_error", "pmc_version"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return C.c_void_p(a.ctypes.data)
+
+
+def _check(ctx, status):
+    if status != PMC_OK:
+        raise PMCError(status, pmc_last_error(ctx))
+
+
+def pmc_version() -> str:
+    return lib().pmc_version().decode()
+
+
+def pmc_last_error(ctx=None) -> str:
+    return lib().pmc_last_error(ctx).decode()
+
+
+def pmc_default_params(**overrides) -> pmc_params:
+    p = pmc_params()
+    lib().pmc_default_params(C.byref(p))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+def pmc_create(device: int = 0, params: pmc_params | None = None):
+    h = C.c_void_p()
+    st = lib().pmc_create(C.byref(h), int(device), C.byref(params) if params is not None else None)
+    _check(None, st)
+    return h
+
+
+def pmc_destroy(ctx):
+    lib().pmc_destroy(ctx)
+
+
+def pmc_load_physics(ctx, nd: dict):
+    arrs = [np.ascontiguousarray(nd[k], dtype=np.float32)
+            for k in ("sigma_ne", "sigma_el", "mult_cdf", "f_local", "x_cdf", "mu_cdf")]
+    s = pmc_nuclear_data(*[a.ctypes.data for a in arrs])
+    _check(ctx, lib().pmc_load_physics(ctx, C.byref(s)))
+
+
+def pmc_load_geometry(ctx, hu, voxel_cm, mt: dict):
+    hu = np.ascontiguousarray(hu, dtype=np.int16)
+    nz, ny, nx = hu.shape
+    arrs = [np.ascontiguousarray(mt["hu_lo"], dtype=np.int16),
+            np.ascontiguousarray(mt["rho_lo"], dtype=np.float32),
+            np.ascontiguousarray(mt["rho_hi"], dtype=np.float32),
+            np.ascontiguousarray(mt["mass_frac"], dtype=np.float32),
+            np.ascontiguousarray(mt["i_ev"], dtype=np.float32),
+            np.ascontiguousarray(mt["own_table"], dtype=np.int32)]
+    t = pmc_material_table(len(arrs[0]), *[a.ctypes.data for a in arrs])
+    _check(ctx, lib().pmc_load_geometry(ctx, _ptr(hu), nx, ny, nz, float(voxel_cm[0]),
+                                        float(voxel_cm[1]), float(voxel_cm[2]), C.byref(t)))
+    return (nz, ny, nx)
+
+
+def summary_dict(s: pmc_summary) -> dict:
+    return {f[0]: getattr(s, f[0]) for f in pmc_summary._fields_ if f[0] != "reserved"}
+
+
+def _spots(spots):
+    return np.ascontiguousarray(np.asarray(spots, dtype=np.float32).reshape(-1, 6))
+
+
+def pmc_run_spots(ctx, spots, n_histories, seed, shape):
+    """Host-buffer run: returns (dose, var, summary)."""
+    sp = _spots(spots)
+    dose = np.zeros(shape, np.float64)
+    var = np.zeros(shape, np.float64)
+    s = pmc_summary()
+    st = lib().pmc_run_spots(ctx, _ptr(sp), len(sp), int(n_histories), int(seed), _ptr(dose),
+                             _ptr(var), C.byref(s))
+    _check(ctx, st)
+    return dose, var, summary_dict(s)
+
+
+def pmc_run_spots_dev(ctx, spots, n_histories, seed, d_dose, d_var=None, stream=None):
+    """Device-buffer run into torch tensors (float64, nz*ny*nx elements) on
+    ``stream`` (a torch.cuda.Stream or raw handle; None = current stream)."""
+    import torch
+    sp = _spots(spots)
+    if d_dose.dtype != torch.float64 or not d_dose.is_cuda or not d_dose.is_contiguous():
+        raise ValueError("d_dose must be a contiguous float64 device tensor")
+    if d_var is not None and (d_var.dtype != torch.float64 or not d_var.is_contiguous()
+                              or d_var.numel() != d_dose.numel()):
+        raise ValueError("d_var must match d_dose")
+    if stream is None:
+        stream = torch.cuda.current_stream(d_dose.device)
+    handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+    s = pmc_summary()
+    st = lib().pmc_run_spots_dev(ctx, _ptr(sp), len(sp), int(n_histories), int(seed),
+                                 C.c_void_p(d_dose.data_ptr()),
+                                 C.c_void_p(d_var.data_ptr()) if d_var is not None else None,
+                                 C.c_void_p(handle), C.byref(s))
+    _check(ctx, st)
+    return summary_dict(s)
+
+
+def pmc_inspect_tables(ctx):
+    lnr_w = np.zeros(1000, np.float32)
+    lnr_o = np.zeros(1000, np.float32)
+    n = C.c_int32()
+    _check(ctx, lib().pmc_inspect_tables(ctx, None, None, None, None, C.byref(n)))
+    sig = np.zeros((n.value, 1000), np.float32)
+    mat = np.zeros((n.value, 4), np.float64)
+    _check(ctx, lib().pmc_inspect_tables(ctx, _ptr(lnr_w), _ptr(lnr_o), _ptr(sig), _ptr(mat),
+                                         C.byref(n)))
+    return {"lnr_water": lnr_w, "lnr_own": lnr_o, "sigma_per_g": sig, "material": mat}
+
+
+class Engine:
+    """Owns one context; convenience wrapper over the functions above."""
+
+    def __init__(self, device=0, **params):
+        self.params = pmc_default_params(**params)
+        self.ctx = pmc_create(device, self.params)
+        self.shape = None
+
+    def close(self):
+        if self.ctx:
+            pmc_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def load_physics(self, nd):
+        pmc_load_physics(self.ctx, nd)
+
+    def load_geometry(self, hu, voxel_cm, mt):
+        self.shape = pmc_load_geometry(self.ctx, hu, voxel_cm, mt)
+
+    def run_spots(self, spots, n_histories, seed):
+        return pmc_run_spots(self.ctx, spots, n_histories, seed, self.shape)
+
+    def run_spots_dev(self, spots, n_histories, seed, d_dose, d_var=None, stream=None):
+        return pmc_run_spots_dev(self.ctx, spots, n_histories, seed, d_dose, d_var, stream)

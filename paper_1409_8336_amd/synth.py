@@ -248,10 +248,15 @@ def ct_phantom(nx=128, ny=128, nz=160, voxel_cm=0.2, seed=2,
             c = rng.uniform([0.15 * lx, 0.15 * ly, 0.1 * lz],
                             [0.85 * lx, 0.85 * ly, 0.9 * lz])
             r = rng.uniform(1.0, 4.0, size=3)
-            q = (((xs[None, None, :] - c[0]) / r[0]) ** 2
-                 + ((ys[None, :, None] - c[1]) / r[1]) ** 2
-                 + ((zs[:, None, None] - c[2]) / r[2]) ** 2)
-            hu[q <= 1.0] = value
+            # evaluate only inside the ellipsoid's bounding box
+            i0 = [max(0, int(math.floor((c[a] - r[a]) / voxel_cm)) - 1) for a in range(3)]
+            i1 = [min(n, int(math.ceil((c[a] + r[a]) / voxel_cm)) + 1)
+                  for a, n in zip(range(3), (nx, ny, nz))]
+            q = (((xs[None, None, i0[0]:i1[0]] - c[0]) / r[0]) ** 2
+                 + ((ys[None, i0[1]:i1[1], None] - c[1]) / r[1]) ** 2
+                 + ((zs[i0[2]:i1[2], None, None] - c[2]) / r[2]) ** 2)
+            sub = hu[i0[2]:i1[2], i0[1]:i1[1], i0[0]:i1[0]]
+            sub[q <= 1.0] = value
     if ti_depth_cm is not None and ti_depth_cm < lz:
         cx = 0.5 * lx + ti_offset_cm
         q = ((xs[None, None, :] - cx) ** 2 + (zs[:, None, None] - ti_depth_cm) ** 2)

@@ -1,0 +1,68 @@
+"""Comparison metrics for GPU-vs-oracle dose parity (test infrastructure).
+
+IDD(z) = energy deposited per slice, R80 = distal depth where the IDD falls
+to 80% of its maximum (slice centres, linear interpolation), voxel z-scores
+from the two variance estimates."""
+import numpy as np
+
+from paper_1409_8336_amd import synth
+
+MEV_GY = 1.602176634e-10
+
+
+def density_grid(hu):
+    """Voxel density from the material table (restated HU -> rho map)."""
+    mt = synth.material_table()
+    lo = mt["hu_lo"].astype(np.int64)
+    h = np.clip(hu.astype(np.int64), -1000, 3000)
+    b = np.searchsorted(lo, h, side="right") - 1
+    hi = np.append(lo[1:], 3000)
+    span = (hi - lo)[b]
+    frac = np.where(span > 0, (h - lo[b]) / np.where(span > 0, span, 1), 0.0)
+    rho_lo = mt["rho_lo"].astype(np.float64)[b]
+    rho_hi = mt["rho_hi"].astype(np.float64)[b]
+    return rho_lo + (rho_hi - rho_lo) * frac
+
+
+def energy_grid(dose, rho, voxel_cm, total_weight):
+    vol = float(np.prod(np.float32(voxel_cm).astype(np.float64)))
+    return dose * rho * vol * total_weight / MEV_GY
+
+
+def idd(edep):
+    return edep.sum(axis=(1, 2))
+
+
+def r80(idd_z, dz):
+    m = int(np.argmax(idd_z))
+    peak = idd_z[m]
+    z = (np.arange(len(idd_z)) + 0.5) * dz
+    for i in range(m, len(idd_z) - 1):
+        if idd_z[i] >= 0.8 * peak > idd_z[i + 1]:
+            f = (idd_z[i] - 0.8 * peak) / (idd_z[i] - idd_z[i + 1])
+            return z[i] + f * dz
+    return z[-1]
+
+
+def compare(a_dose, a_var, b_dose, b_var, rho, voxel_cm, wa, wb):
+    ea = energy_grid(a_dose, rho, voxel_cm, wa)
+    eb = energy_grid(b_dose, rho, voxel_cm, wb)
+    ia, ib = idd(ea), idd(eb)
+    sel = b_dose >= 0.1 * b_dose.max()
+    sd = np.sqrt(a_var[sel] + b_var[sel])
+    z = (a_dose[sel] - b_dose[sel]) / np.where(sd > 0, sd, 1.0)
+    return {
+        "idd_max_rel": float(np.max(np.abs(ia - ib)) / ib.max()),
+        "r80_a": r80(ia, voxel_cm[2]), "r80_b": r80(ib, voxel_cm[2]),
+        "r80_diff_mm": 10.0 * abs(r80(ia, voxel_cm[2]) - r80(ib, voxel_cm[2])),
+        "n_sel": int(sel.sum()),
+        "frac_z_gt3": float(np.mean(np.abs(z) > 3.0)) if sel.any() else 0.0,
+        "z_mean": float(z.mean()) if sel.any() else 0.0,
+        "z_std": float(z.std()) if sel.any() else 0.0,
+        "all_within_3sigma": bool(np.all(np.abs(z) <= 3.0)),
+    }
+
+
+def ledger_residual(s):
+    return abs(s["incident"] - s["deposited"] - s["escaped"] - s["neutral"]
+               - s.get("overflow", 0.0)) / max(s["incident"], 1e-300)
