@@ -122,6 +122,7 @@ typedef struct {
 typedef struct {
     double incident, deposited, escaped, neutral, overflow;
     uint64_t histories, steps, secondaries, n_elastic, n_nonelastic, n_overflow;
+    uint64_t n_short_steps; /* steps lengthened to s_min (sub-micron boundary approaches) */
     double total_weight;   /* sum of primary weights (dose normalisation) */
     double device_ms;      /* device time of the run, HIP events */
     double transport_ms;   /* sum over transport launches of their HIP-event durations */

@@ -54,7 +54,8 @@ class Summary(C.Structure):
                 ("neutral", C.c_double), ("histories", C.c_uint64), ("steps", C.c_uint64),
                 ("secondaries", C.c_uint64), ("n_elastic", C.c_uint64),
                 ("n_nonelastic", C.c_uint64), ("interactions", (C.c_uint64 * 7) * 2),
-                ("total_weight", C.c_double), ("wall_s", C.c_double), ("threads", C.c_int32)]
+                ("total_weight", C.c_double), ("wall_s", C.c_double), ("threads", C.c_int32),
+                ("n_short_steps", C.c_uint64)]
 
 
 class Diag(C.Structure):

@@ -676,7 +676,7 @@ typedef struct {
 
 typedef struct {
     double escaped, neutral;
-    uint64_t steps, secondaries, n_el, n_ne;
+    uint64_t steps, secondaries, n_el, n_ne, n_short;
     uint64_t inter[2][ORA_NEL];
 } oacc;
 
@@ -859,7 +859,8 @@ static void transport(const ora_ctx* c, const orun* r, opart* q, ostack* st, oac
         }
         const int lim = (s_nuc < d) ? LIM_NUC : LIM_BND;
         double s = (lim == LIM_NUC) ? s_nuc : d;
-        if (s < c->p.s_min_cm) s = c->p.s_min_cm;
+        const int short_step = s < c->p.s_min_cm;
+        if (short_step) s = c->p.s_min_cm;
         if (s >= s_range) {
             deposit(c, r, vi, q->batch, q->w * q->e);
             return;
@@ -881,18 +882,33 @@ static void transport(const ora_ctx* c, const orun* r, opart* q, ostack* st, oac
         double theta = 0.0;
         if (!(flags & ORA_NO_MCS))
             theta = oracle_highland_theta0(e_mid, s, m->x0 / rho, c->p.f_mcs) * sqrt(-2.0 * log(u[1]));
-        /* random hinge: deflect at a uniform fraction u0 of the step */
+        /* random hinge: deflect at a uniform fraction u0 of the step.  On a
+         * boundary-limited step the remaining segment runs along the new
+         * direction to the crossed face plane and ends exactly on it, unless
+         * the deflection turned the proton back or that segment would exceed
+         * twice its nominal length. */
         for (int a = 0; a < 3; ++a) q->p[a] += u[0] * s * q->d[a] / c->vs[a];
+        const double d_axis_before = q->d[axis];
         if (theta != 0.0) oracle_rotate(q->d, cos(theta), sin(theta), u[2]);
-        for (int a = 0; a < 3; ++a) q->p[a] += (1.0 - u[0]) * s * q->d[a] / c->vs[a];
-        if (lim == LIM_BND && theta == 0.0)
-            q->p[axis] = (q->d[axis] > 0.0) ? (double)(v[axis] + 1) : (double)v[axis];
+        double rest = (1.0 - u[0]) * s;
+        int on_face = 0;
+        const double face = (d_axis_before > 0.0) ? (double)(v[axis] + 1) : (double)v[axis];
+        if (lim == LIM_BND && q->d[axis] * d_axis_before > 0.0) {
+            const double l2 = (face - q->p[axis]) * c->vs[axis] / q->d[axis];
+            if (l2 >= 0.0 && l2 <= 2.0 * rest) {
+                rest = l2;
+                on_face = 1;
+            }
+        }
+        for (int a = 0; a < 3; ++a) q->p[a] += rest * q->d[a] / c->vs[a];
+        if (on_face) q->p[axis] = face;
         const double e_new = q->e - de;
         deposit(c, r, vi, q->batch, q->w * (q->e - e_new));
         q->mfp = (lim == LIM_NUC) ? 0.0 : fmax(q->mfp - sig * s, 0.0);
         q->e = e_new;
         q->k = ks + 1;
         acc->steps++;
+        acc->n_short += short_step;
         if (q->e <= E_CUT) {
             deposit(c, r, vi, q->batch, q->w * q->e);
             return;
@@ -978,11 +994,11 @@ int oracle_run_spots(ora_ctx* c, const ora_spot* spots, int n_spots, uint64_t n_
         for (uint64_t h = 0; h < n_hist; ++h) diag->first_nuclear_z_cm[h] = NAN;
     orun run = {seed, tally, diag};
     double incident = 0.0, escaped = 0.0, neutral = 0.0;
-    uint64_t steps = 0, secs = 0, nel = 0, nne = 0, inter[2][ORA_NEL];
+    uint64_t steps = 0, secs = 0, nel = 0, nne = 0, nshort = 0, inter[2][ORA_NEL];
     memset(inter, 0, sizeof(inter));
     int nthreads = 1;
 #pragma omp parallel num_threads(c->p.n_threads > 0 ? c->p.n_threads : omp_get_max_threads()) \
-    reduction(+ : incident, escaped, neutral, steps, secs, nel, nne)
+    reduction(+ : incident, escaped, neutral, steps, secs, nel, nne, nshort)
     {
 #ifdef _OPENMP
 #pragma omp single
@@ -1032,6 +1048,7 @@ int oracle_run_spots(ora_ctx* c, const ora_spot* spots, int n_spots, uint64_t n_
         secs += acc.secondaries;
         nel += acc.n_el;
         nne += acc.n_ne;
+        nshort += acc.n_short;
 #pragma omp critical
         for (int a = 0; a < 2; ++a)
             for (int e = 0; e < ORA_NEL; ++e) inter[a][e] += acc.inter[a][e];
@@ -1065,6 +1082,7 @@ int oracle_run_spots(ora_ctx* c, const ora_spot* spots, int n_spots, uint64_t n_
     sum->n_nonelastic = nne;
     memcpy(sum->interactions, inter, sizeof(inter));
     sum->total_weight = wtot;
+    sum->n_short_steps = nshort;
     sum->threads = nthreads;
 #ifdef _OPENMP
     sum->wall_s = omp_get_wtime() - t0;

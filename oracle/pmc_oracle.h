@@ -72,6 +72,7 @@ typedef struct {
     double total_weight;
     double wall_s;
     int32_t threads;
+    uint64_t n_short_steps;                         /* steps lengthened to s_min */
 } ora_summary;
 
 /* Optional diagnostics; any pointer may be NULL. */

@@ -60,7 +60,7 @@ struct KernelArgs {
     // outputs
     double* tally;                  // [nvox][k_batches] weighted MeV
     double* ledger;                 // escaped, neutral, overflow
-    unsigned long long* counters;   // steps, elastic events, non-elastic events
+    unsigned long long* counters;   // steps, elastic events, non-elastic events, short steps
     int refill_lanes;
     int batch_events;
 };

@@ -19,6 +19,7 @@
 namespace pmc {
 hipError_t launch_transport(const KernelArgs& a, int grid, int block, size_t lds_bytes, hipStream_t s);
 hipError_t transport_occupancy(int block, size_t lds_bytes, int* blocks_per_cu);
+hipError_t transport_max_block(int* max_threads);
 hipError_t launch_stats(const double* tally, const uint2* vox, unsigned long long nvox, int K,
                         double conv0, double* dose, double* var, double* dep_sum, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
@@ -496,6 +497,9 @@ static pmc_status run_impl(pmc_ctx* c, const pmc_spot* spots, int n_spots, uint6
 
     const int block = c->p.block_threads;
     const size_t lds = c->blob.size() * 4;
+    int max_block = 0;
+    HIPCHK(transport_max_block(&max_block), "kernel attributes");
+    if (block > max_block) return fail(c, PMC_ERR_ARG, "block_threads exceeds the transport kernel's limit");
     int bpc = c->p.blocks_per_cu;
     if (bpc == 0) {
         HIPCHK(transport_occupancy(block, lds, &bpc), "occupancy");
@@ -555,6 +559,7 @@ static pmc_status run_impl(pmc_ctx* c, const pmc_spot* spots, int n_spots, uint6
         summary->n_nonelastic = c->h_pinned[10];
         summary->secondaries = produced_total;
         summary->n_overflow = overflow_n;
+        summary->n_short_steps = c->h_pinned[11];
         summary->total_weight = wtot;
         summary->device_ms = ms;
         summary->transport_ms = transport_ms;

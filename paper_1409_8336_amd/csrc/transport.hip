@@ -132,7 +132,7 @@ DEV float inv_cdf33(const float* __restrict__ cdf, float u, float lo, float hi)
 
 // -------------------------------------------------------------- the kernel
 
-__global__ void __launch_bounds__(256) transport_kernel(KernelArgs a)
+__global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
 {
     extern __shared__ float lds[];
     for (int i = threadIdx.x; i < a.blob_words; i += blockDim.x) lds[i] = a.blob[i];
@@ -164,7 +164,7 @@ __global__ void __launch_bounds__(256) transport_kernel(KernelArgs a)
     bool alive = false, pend = false;
 
     double acc_esc = 0.0, acc_neu = 0.0, acc_ovf = 0.0;
-    unsigned long long n_steps = 0, n_el = 0, n_ne = 0;
+    unsigned long long n_steps = 0, n_el = 0, n_ne = 0, n_short = 0;
     bool exhausted = false;
 
     for (;;) {
@@ -235,7 +235,7 @@ __global__ void __launch_bounds__(256) transport_kernel(KernelArgs a)
         }
 
         // ------------------------------------------------------------ step
-        bool stepped = false;
+        bool stepped = false, short_step = false;
         if (alive && !pend) {
             const unsigned long long vi = ((unsigned long long)vz * a.ny + vy) * a.nx + vx;
             const uint2 rec = a.vox[vi];
@@ -286,7 +286,8 @@ __global__ void __launch_bounds__(256) transport_kernel(KernelArgs a)
             bool stop_here = (s_range <= d && s_range <= s_nuc);
             const bool nuc = s_nuc < d;
             float s = nuc ? s_nuc : d;
-            s = s < a.s_min ? a.s_min : s;
+            short_step = s < a.s_min;
+            s = short_step ? a.s_min : s;
             if (s >= s_range) stop_here = true;
             if (stop_here) {
                 // range-limited: the proton stops in this voxel
@@ -331,22 +332,41 @@ __global__ void __launch_bounds__(256) transport_kernel(KernelArgs a)
                     const float th0 = a.f_mcs * 13.6f * frcp(pv) * fsqrt(s * frcp(x0)) * br;
                     theta = th0 * fsqrt(-2.f * fln(u01(r.y)));
                 }
-                // random hinge at a uniform fraction of the step
-                const float h1 = u01(r.x) * s, h2 = s - h1;
+                // random hinge at a uniform fraction of the step; on a
+                // boundary-limited step the second segment runs along the new
+                // direction to the crossed face plane and ends on it
+                const float h1 = u01(r.x) * s;
+                float h2 = s - h1;
                 px += h1 * ux * a.ivs[0];
                 py += h1 * uy * a.ivs[1];
                 pz += h1 * uz * a.ivs[2];
+                const float da_before = axis == 0 ? ux : (axis == 1 ? uy : uz);
+                const int va = axis == 0 ? vx : (axis == 1 ? vy : vz);
+                const float face = (float)(da_before > 0.f ? va + 1 : va);
                 if (theta != 0.f) {
                     const float tr = theta * 0.159154943f;
                     rotate(ux, uy, uz, fcos_rev(tr), fsin_rev(tr), u01(r.z));
                 }
+                bool on_face = false;
+                if (!nuc) {
+                    const float da = axis == 0 ? ux : (axis == 1 ? uy : uz);
+                    const float pa = axis == 0 ? px : (axis == 1 ? py : pz);
+                    if (da * da_before > 0.f) {
+                        const float vsa = axis == 0 ? a.vs[0] : (axis == 1 ? a.vs[1] : a.vs[2]);
+                        const float l2 = (face - pa) * vsa / da;
+                        if (l2 >= 0.f && l2 <= 2.f * h2) {
+                            h2 = l2;
+                            on_face = true;
+                        }
+                    }
+                }
                 px += h2 * ux * a.ivs[0];
                 py += h2 * uy * a.ivs[1];
                 pz += h2 * uz * a.ivs[2];
-                if (!nuc && theta == 0.f) {
-                    if (axis == 0) px = (float)(ux > 0.f ? vx + 1 : vx);
-                    else if (axis == 1) py = (float)(uy > 0.f ? vy + 1 : vy);
-                    else pz = (float)(uz > 0.f ? vz + 1 : vz);
+                if (on_face) {
+                    if (axis == 0) px = face;
+                    else if (axis == 1) py = face;
+                    else pz = face;
                 }
                 const float e_new = E - de;
                 unsafeAtomicAdd(&a.tally[vi * K + batch], (double)w * ((double)E - (double)e_new));
@@ -369,6 +389,7 @@ __global__ void __launch_bounds__(256) transport_kernel(KernelArgs a)
             }
         }
         n_steps += __popcll(__ballot(stepped));
+        n_short += __popcll(__ballot(stepped && short_step));
 
         // ------------------------------------------- batched nuclear events
         const unsigned long long pm = __ballot(pend);
@@ -607,6 +628,7 @@ __global__ void __launch_bounds__(256) transport_kernel(KernelArgs a)
         atomicAdd(&a.counters[0], n_steps);
         if (n_el) atomicAdd(&a.counters[1], n_el);
         if (n_ne) atomicAdd(&a.counters[2], n_ne);
+        if (n_short) atomicAdd(&a.counters[3], n_short);
     }
 }
 
@@ -653,6 +675,14 @@ hipError_t launch_transport(const KernelArgs& a, int grid, int block, size_t lds
 {
     hipLaunchKernelGGL(transport_kernel, dim3(grid), dim3(block), lds_bytes, s, a);
     return hipGetLastError();
+}
+
+hipError_t transport_max_block(int* max_threads)
+{
+    hipFuncAttributes attr;
+    hipError_t e = hipFuncGetAttributes(&attr, (const void*)transport_kernel);
+    if (e == hipSuccess) *max_threads = attr.maxThreadsPerBlock;
+    return e;
 }
 
 hipError_t transport_occupancy(int block, size_t lds_bytes, int* blocks_per_cu)

@@ -60,7 +60,7 @@ class pmc_summary(C.Structure):
                 ("neutral", C.c_double), ("overflow", C.c_double), ("histories", C.c_uint64),
                 ("steps", C.c_uint64), ("secondaries", C.c_uint64), ("n_elastic", C.c_uint64),
                 ("n_nonelastic", C.c_uint64), ("n_overflow", C.c_uint64),
-                ("total_weight", C.c_double), ("device_ms", C.c_double),
+                ("n_short_steps", C.c_uint64), ("total_weight", C.c_double), ("device_ms", C.c_double),
                 ("transport_ms", C.c_double), ("generations", C.c_int32),
                 ("reserved", C.c_int32)]
 
@@ -74,6 +74,12 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError("libpmc.so is not built: run __graft_entry__.build()")
+        # PyTorch ships its own HIP runtime; load it first so that this
+        # library binds to the same runtime (one HIP runtime per process)
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         vp, i32, u64 = C.c_void_p, C.c_int, C.c_uint64
         L.pmc_default_params.argtypes = [C.POINTER(pmc_params)]
