@@ -25,11 +25,20 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# VALU lane-operations of one condensed-history step of the method (counted
-# per operation of the step's arithmetic; see the design notes) and the
-# chip's peak VALU lane-operation rate: 256 CUs x 64 lanes x 2.4 GHz.
-OPS_PER_STEP = 300
-PEAK_LANE_OPS = 256 * 64 * 2.4e9
+# Algorithmic memory work of one condensed-history step: one 8-byte voxel
+# record gather and one 8-byte FP64 atomic add into the dose tally.
+ALG_BYTES_PER_STEP = 16
+HBM_PEAK = 8.0e12
+# HBM bytes per transport launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
+# scaled by a plain-copy calibration, valid only for the kernel source whose
+# sha256 is recorded (see profiles/); None once the kernel has changed.
+TRAFFIC = {"transport_sha256": None, "bytes_per_launch": None}
+
+
+def _kernel_sha():
+    import hashlib
+    with open(os.path.join(ROOT, "paper_1409_8336_amd", "csrc", "transport.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
 
 
 def cpu_baseline(cfg, target_s=10.0):
@@ -52,6 +61,65 @@ def cpu_baseline(cfg, target_s=10.0):
                       % (n, s["wall_s"], s["steps"] / n)}
 
 
+def copy_probe():
+    """A plain copy of known size (256 MiB read + 256 MiB written per launch):
+    the reference that scales FETCH_SIZE / WRITE_SIZE counter readings."""
+    import torch
+    x = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": x.numel() * 4, "launches": 3}))
+    return 0
+
+
+def bench_plans(args):
+    """Sixteen plans (grids 96^3..256x256x200, 200-3000 spots, 1e6-1e7
+    histories each) in one persistent launch per generation."""
+    import torch
+    from paper_1409_8336_amd import pmc, synth
+    plans = synth.plan_set(n_plans=16, seed=100)
+    eng = pmc.Engine(0)
+    eng.load_physics(synth.nuclear_data())
+    mt = synth.material_table()
+    eng.load_geometry(plans[0]["hu"], plans[0]["voxel_cm"], mt)
+    ids = [0] + [pmc.pmc_load_geometry_slot(eng.ctx, p["hu"], p["voxel_cm"], mt) for p in plans[1:]]
+    spec = []
+    for gid, p in zip(ids, plans):
+        d = torch.empty(p["hu"].shape, dtype=torch.float64, device="cuda:0")
+        spec.append(dict(geometry_id=gid, spots=p["spots"], n_histories=p["n_histories"], d_dose=d,
+                         d_var=torch.empty_like(d)))
+    for _ in range(args.warmup):
+        pmc.pmc_run_plans(eng.ctx, spec, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    all_sums = []
+    for i in range(args.steps):
+        all_sums.append(pmc.pmc_run_plans(eng.ctx, spec, 2 + i))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    n_tot = args.steps * sum(p["n_histories"] for p in plans)
+    steps_tot = sum(s["steps"] for sums in all_sums for s in sums)
+    out = {"metric": "proton histories/s (16-plan batch)", "value": n_tot / elapsed,
+           "unit": "histories/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32 transport, f64 tallies",
+           "data": "synthetic",
+           "config": {"workload": "16 plans, CT 96^3..256x256x200 (2 mm), 200-3000 spots, "
+                                  "1e6-1e7 histories each, one persistent launch",
+                      "histories_per_step": n_tot // args.steps},
+           "steps_per_s": steps_tot / elapsed,
+           "transport_ms_per_step": sum(s[0]["transport_ms"] for s in all_sums) / args.steps,
+           "ledger_residual_max": max(abs(s["incident"] - s["deposited"] - s["escaped"] - s["neutral"]
+                                          - s["overflow"]) / s["incident"]
+                                      for sums in all_sums for s in sums)}
+    eng.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -59,7 +127,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--histories", type=int, default=10_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=("field", "plans"), default="field",
+                    help="field: the 2000-spot 1e7-history field (default); plans: the "
+                         "uneven 16-plan batch in one persistent launch")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
+    if args.copy_probe:
+        return copy_probe()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X and has no "
               "multi-GPU path (--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -67,6 +142,8 @@ def main():
     import torch
     from paper_1409_8336_amd import pmc, synth
 
+    if args.workload == "plans":
+        return bench_plans(args)
     cfg = synth.config_field(args.histories)
     eng = pmc.Engine(0)
     eng.load_physics(synth.nuclear_data())
@@ -89,7 +166,14 @@ def main():
     steps_tot = sum(s["steps"] for s in sums)
     transport_s = sum(s["transport_ms"] for s in sums) * 1e-3
     launches = sum(s["generations"] for s in sums)
-    achieved = OPS_PER_STEP * steps_tot / transport_s
+    achieved = ALG_BYTES_PER_STEP * steps_tot / transport_s
+    atomics_tot = sum(s["tally_atomics"] for s in sums)
+    probe_ms = pmc.pmc_atomic_probe(eng.ctx, atomics_tot // args.steps, stream)
+    probe_rate = (atomics_tot / args.steps) / (probe_ms * 1e-3)
+    atomic_rate = atomics_tot / transport_s
+    traffic = None
+    if TRAFFIC["transport_sha256"] == _kernel_sha():
+        traffic = TRAFFIC["bytes_per_launch"]
     worst_res = max(abs(s["incident"] - s["deposited"] - s["escaped"] - s["neutral"] - s["overflow"])
                     / s["incident"] for s in sums)
     out = {
@@ -115,15 +199,23 @@ def main():
         "transport_ms_per_step": 1e3 * transport_s / args.steps,
         "ledger_residual_max": worst_res,
         "roofline": {
-            "bound": "alu",
-            "achieved": achieved / 1e12,
-            "peak": PEAK_LANE_OPS / 1e12,
-            "unit": "TFLOP/s",
-            "frac": achieved / PEAK_LANE_OPS,
-            "traffic": None,
+            "bound": "hbm",
+            "achieved": achieved / 1e9,
+            "peak": HBM_PEAK / 1e9,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK,
+            "traffic": traffic,
             "kernel": "transport_kernel",
             "avg_launch_ms": 1e3 * transport_s / launches,
-            "ops_per_step": OPS_PER_STEP,
+            "bytes_per_step": ALG_BYTES_PER_STEP,
+        },
+        "atomic_roofline": {
+            "tally_atomics_per_step": atomics_tot / args.steps,
+            "achieved_atomics_per_s": atomic_rate,
+            "probe_atomics_per_s": probe_rate,
+            "frac": atomic_rate / probe_rate,
+            "probe": "pmc_atomic_probe: the same number of FP64 atomics into the same tally "
+                     "along straight z tracks in the central 40x40 window",
         },
     }
     eng.close()

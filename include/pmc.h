@@ -72,6 +72,11 @@ typedef struct {
     int32_t refill_lanes;    /* a wave refills when at least this many of its 64 lanes are idle; 0 = tuned */
     int32_t batch_events;    /* a wave handles pending nuclear events once this many lanes wait; 0 = tuned */
 } pmc_params;
+/* Autotuning: when any of block_threads, refill_lanes, batch_events is 0 and
+ * a run has at least 1e6 histories, the first run of each workload signature
+ * (single/batched, plan count, log2 of histories and voxels) times a few
+ * candidate launch shapes on a 2e5-history copy of the workload and keeps the
+ * fastest for that signature.  Results do not depend on the shape. */
 
 /* Fill *p with the defaults above.  Never fails for a non-NULL p. */
 pmc_status pmc_default_params(pmc_params* p);
@@ -123,6 +128,7 @@ typedef struct {
     double incident, deposited, escaped, neutral, overflow;
     uint64_t histories, steps, secondaries, n_elastic, n_nonelastic, n_overflow;
     uint64_t n_short_steps; /* steps lengthened to s_min (sub-micron boundary approaches) */
+    uint64_t tally_atomics; /* FP64 atomic adds issued into the dose tally */
     double total_weight;   /* sum of primary weights (dose normalisation) */
     double device_ms;      /* device time of the run, HIP events */
     double transport_ms;   /* sum over transport launches of their HIP-event durations */
@@ -176,6 +182,39 @@ pmc_status pmc_run_spots_dev(pmc_ctx* c, const pmc_spot* spots, int n_spots, uin
                              uint64_t seed, double* d_dose, double* d_var, void* hip_stream,
                              pmc_summary* summary);
 
+/* Load a further geometry for batched runs (configurations with many CTs).
+ * Same arguments as pmc_load_geometry, which must have been called first; the
+ * material table must equal the one already loaded.  *geometry_id_out
+ * receives the slot (>= 1; slot 0 is pmc_load_geometry's).  At most 64 slots.
+ * Errors: PMC_ERR_STATE (no base geometry), PMC_ERR_ARG, PMC_ERR_NOMEM,
+ * PMC_ERR_DEVICE. */
+pmc_status pmc_load_geometry_slot(pmc_ctx* c, int* geometry_id_out, const int16_t* hu, int nx, int ny,
+                                  int nz, float dx_cm, float dy_cm, float dz_cm,
+                                  const pmc_material_table* mt);
+
+/* One plan of a batched run: n_histories over its spots on geometry slot
+ * geometry_id, dose and variance into caller-owned device buffers of that
+ * geometry's voxel count (d_var may be NULL), optional host summary. */
+typedef struct {
+    int32_t geometry_id;
+    int32_t n_spots;
+    const pmc_spot* spots;     /* host array */
+    uint64_t n_histories;      /* < 2^32 per plan */
+    double* d_dose;
+    double* d_var;
+    pmc_summary* summary;      /* host, may be NULL */
+} pmc_plan;
+
+/* Transport every plan in one persistent launch per secondary generation:
+ * the histories of all plans form one work list shared by all waves, each
+ * with its plan's geometry, tally and random key seed + plan index, so plan p
+ * gives exactly the result of pmc_run_spots_dev on its geometry with seed + p
+ * (up to floating-point summation order).  Plans must use distinct geometry
+ * slots; 1 <= n_plans <= 64.  Runs on hip_stream and returns when done.
+ * The device/transport times and generation count in the summaries are those
+ * of the whole batch.  Errors: as pmc_run_spots_dev. */
+pmc_status pmc_run_plans(pmc_ctx* c, const pmc_plan* plans, int n_plans, uint64_t seed, void* hip_stream);
+
 /* Host-side tables the engine built for the loaded physics and geometry, for
  * inspection (no device work).  out_lnr_water/out_lnr_own receive the 1000
  * float32 ln(range) entries (entry 0 is -inf: zero range at 0.1 MeV) of water
@@ -186,6 +225,15 @@ pmc_status pmc_run_spots_dev(pmc_ctx* c, const pmc_spot* spots, int n_spots, uin
  * NULL.  Errors: PMC_ERR_STATE before both loads. */
 pmc_status pmc_inspect_tables(const pmc_ctx* c, float* out_lnr_water, float* out_lnr_own,
                               float* out_sigma_per_g, double* out_material, int32_t* out_n_bins);
+
+/* Measurement aid for the dose tally (no physics): time n_atomics FP64
+ * atomic adds of zero into the loaded geometry's [voxel][group] tally along
+ * straight z tracks started inside the central 40x40-voxel window, issued by
+ * a grid of 4 workgroups of 256 lanes per CU on hip_stream.  *ms_out receives
+ * the device time scaled to exactly n_atomics.  The tally contents are
+ * unchanged.  Errors: PMC_ERR_ARG, PMC_ERR_STATE (no geometry),
+ * PMC_ERR_DEVICE. */
+pmc_status pmc_atomic_probe(pmc_ctx* c, uint64_t n_atomics, void* hip_stream, double* ms_out);
 
 /* Library version string, e.g. "pmc 0.1 gfx950". */
 const char* pmc_version(void);

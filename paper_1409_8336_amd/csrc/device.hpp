@@ -9,7 +9,8 @@
 namespace pmc {
 
 constexpr int kWave = 64;
-constexpr int kQueuePlanes = 11;   // px py pz ux uy uz E w uid_lo uid_hi batch
+constexpr int kQueuePlanes = 12;   // px py pz ux uy uz E w uid_lo uid_hi batch plan
+constexpr int kMaxPlans = 64;
 constexpr int kMaxGenerations = 64;
 
 // LDS blob layout, in 32-bit words
@@ -20,12 +21,23 @@ constexpr int kOffInvOwn = 2512;
 constexpr int kOffSigma = 3024;      // n_mat x 1000 total cross section per gram
 // then n_mat x 4 words: f (Eq. 1; 1 for own-table bins), X0 (g/cm^2), Z/A, own flag
 
-struct KernelArgs {
-    // geometry: voxel record = {density as float bits, material bin}
-    const uint2* vox;
-    int nx, ny, nz;
+// One plan: its geometry (voxel record = {density as float bits, material
+// bin}), its dose tally and its random-number key.  64 bytes.
+struct PlanDesc {
+    int nx, ny, nz, pad;
     float vs[3];        // voxel size, cm
     float ivs[3];       // 1 / voxel size
+    const uint2* vox;
+    double* tally;      // [nvox][k_batches] weighted MeV
+    uint32_t key_lo, key_hi;
+};
+static_assert(sizeof(PlanDesc) == 64, "PlanDesc is 16 words");
+
+struct KernelArgs {
+    PlanDesc single;            // the plan of a single-plan launch
+    const PlanDesc* plans;      // batched launch: n_plans descriptors, staged into LDS
+    int n_plans;
+    int pd_offset;              // LDS word offset of the staged descriptors
     // hot tables (staged into LDS)
     const float* blob;
     int blob_words;
@@ -42,11 +54,11 @@ struct KernelArgs {
     const float* sec_x;     // [6][25][33]
     const float* sec_mu;    // [6][25][33]
     // run
-    uint32_t seed_lo, seed_hi;
     int k_batches;
     uint32_t flags;
     float f_mcs, s_min;
-    // primaries (generation 0): spots[s*8 + {x/dx, y/dy, E, sx/dx, sy/dy, weight}]
+    // primaries (generation 0): spots[s*8 + {x/dx, y/dy, E, sx/dx, sy/dy, weight,
+    // plan (bits), first index of the spot within its plan (bits)}]
     const float* spots;
     const unsigned long long* spot_start;   // [n_spots + 1]
     int n_spots;
@@ -57,10 +69,9 @@ struct KernelArgs {
     unsigned long long q_cap;
     unsigned long long* gen_counters;   // [gen][2] = {entries produced for gen, entries claimed}
     int gen;
-    // outputs
-    double* tally;                  // [nvox][k_batches] weighted MeV
-    double* ledger;                 // escaped, neutral, overflow
-    unsigned long long* counters;   // steps, elastic events, non-elastic events, short steps
+    // outputs, per plan
+    double* ledger;                 // [plan][4]: escaped, neutral, overflow, deposited
+    unsigned long long* counters;   // [plan][8]: steps, elastic, non-elastic, short steps, tally atomics
     int refill_lanes;
     int batch_events;
 };

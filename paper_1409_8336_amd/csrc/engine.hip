@@ -1,15 +1,20 @@
 // C ABI of the engine (include/pmc.h): context and device-buffer ownership,
-// uploads of nuclear data and geometry, and the run driver that launches one
-// persistent transport grid per secondary generation followed by the
-// dose-statistics pass (arXiv:1409.8336, Sec. II.B.2-3).
+// uploads of nuclear data and geometries, the autotuner and the run driver
+// that launches one persistent transport grid per secondary generation
+// followed by the dose-statistics pass (arXiv:1409.8336, Sec. II.B.2-3).
+// A single-plan run and a batch of plans share the driver; a batch runs in
+// one persistent launch per generation with per-plan tallies and ledgers.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <memory>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "device.hpp"
@@ -17,12 +22,15 @@
 #include "tables.hpp"
 
 namespace pmc {
-hipError_t launch_transport(const KernelArgs& a, int grid, int block, size_t lds_bytes, hipStream_t s);
-hipError_t transport_occupancy(int block, size_t lds_bytes, int* blocks_per_cu);
-hipError_t transport_max_block(int* max_threads);
+hipError_t launch_transport(const KernelArgs& a, bool multi, int grid, int block, size_t lds_bytes,
+                            hipStream_t s);
+hipError_t transport_occupancy(bool multi, int block, size_t lds_bytes, int* blocks_per_cu);
+hipError_t transport_max_block(bool multi, int* max_threads);
 hipError_t launch_stats(const double* tally, const uint2* vox, unsigned long long nvox, int K,
                         double conv0, double* dose, double* var, double* dep_sum, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_atomic_probe(double* tally, int nx, int ny, int nz, int K, int grid,
+                               unsigned long long per_lane, hipStream_t st);
 }  // namespace pmc
 
 using namespace pmc;
@@ -51,6 +59,32 @@ struct DevBuf {
         p = nullptr;
         n = 0;
     }
+    ~DevBuf() { release(); }
+};
+
+struct Geometry {
+    int nx = 0, ny = 0, nz = 0;
+    float vs[3] = {0, 0, 0};
+    DevBuf<uint2> vox;
+    DevBuf<double> tally;        // [nvox][K] for runs on this geometry
+    size_t nvox() const { return (size_t)nx * ny * nz; }
+};
+
+// launch shape chosen by the autotuner (or fixed by the caller)
+struct Shape {
+    int block = 256, blocks_per_cu = 0, refill = 16, batch = 4;
+};
+
+// one plan of a run, host side
+struct PlanIn {
+    Geometry* g;
+    const pmc_spot* spots;
+    int n_spots;
+    unsigned long long n_hist;
+    uint64_t seed;
+    double* d_dose;
+    double* d_var;
+    pmc_summary* summary;
 };
 
 }  // namespace
@@ -60,7 +94,7 @@ struct pmc_ctx {
     pmc_params p{};
     std::string err;
     int num_cu = 0;
-    bool have_phys = false, have_geom = false;
+    bool have_phys = false;
     // host copies of the nuclear data
     std::vector<float> sig_el, sig_ne, mult, floc, xcdf, mucdf;
     // host tables
@@ -68,23 +102,25 @@ struct pmc_ctx {
     std::vector<Material> mats;
     std::vector<float> blob;
     int own_bin = -1;
-    // geometry
-    int nx = 0, ny = 0, nz = 0;
-    float vs[3] = {0, 0, 0};
-    DevBuf<uint2> d_vox;
+    // geometries: slot 0 is pmc_load_geometry's, slots >= 1 from pmc_load_geometry_slot
+    std::vector<std::unique_ptr<Geometry>> geoms;
     // device tables
     DevBuf<float> d_blob, d_el_sig, d_npg, d_elem, d_mult, d_floc, d_xcdf, d_mucdf;
     // run buffers
-    DevBuf<double> d_tally, d_dose, d_var, d_ledger;
+    DevBuf<double> d_dose, d_var, d_ledger;
     DevBuf<uint32_t> d_q[2];
     DevBuf<unsigned long long> d_gc, d_counters, d_spot_start;
     DevBuf<float> d_spots;
-    unsigned long long* h_pinned = nullptr;   // small pinned read-back area
+    DevBuf<PlanDesc> d_plans;
+    unsigned long long* h_pinned = nullptr;   // pinned read-back area
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t ev_gen[2 * kMaxGenerations] = {};
+    std::map<std::tuple<int, int, int, int>, Shape> tuned;   // workload signature -> shape
 };
 
 namespace {
+
+constexpr size_t kPinnedBytes = 65536;
 
 pmc_status fail(pmc_ctx* c, pmc_status s, const std::string& msg)
 {
@@ -98,11 +134,13 @@ pmc_status hip_fail(pmc_ctx* c, hipError_t e, const char* what)
                 std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define HIPCHK(expr, what)                        \
-    do {                                          \
-        hipError_t _e = (expr);                   \
-        if (_e != hipSuccess) return hip_fail(c, _e, what); \
+#define HIPCHK(expr, what)                                      \
+    do {                                                        \
+        hipError_t _e = (expr);                                 \
+        if (_e != hipSuccess) return hip_fail(c, _e, what);     \
     } while (0)
+
+bool have_geometry(const pmc_ctx* c) { return !c->geoms.empty() && c->geoms[0] && c->geoms[0]->nx > 0; }
 
 // the hot tables staged into LDS by every transport workgroup
 void build_blob(pmc_ctx* c)
@@ -130,27 +168,25 @@ void build_blob(pmc_ctx* c)
     }
 }
 
-pmc_status upload_tables(pmc_ctx* c)
-{
-    if (!c->have_phys || !c->have_geom) return PMC_OK;
-    build_blob(c);
-    HIPCHK(c->d_blob.ensure(c->blob.size()), "alloc tables");
-    HIPCHK(hipMemcpy(c->d_blob.p, c->blob.data(), c->blob.size() * 4, hipMemcpyHostToDevice), "upload tables");
-    const int nm = (int)c->mats.size();
-    std::vector<float> npg(nm * kNEl);
-    for (int m = 0; m < nm; ++m)
-        for (int e = 0; e < kNEl; ++e) npg[m * kNEl + e] = (float)c->mats[m].nuclei_per_g_barn[e];
-    HIPCHK(c->d_npg.ensure(npg.size()), "alloc npg");
-    HIPCHK(hipMemcpy(c->d_npg.p, npg.data(), npg.size() * 4, hipMemcpyHostToDevice), "upload npg");
-    return PMC_OK;
-}
-
 template <class T>
 pmc_status upload(pmc_ctx* c, DevBuf<T>& b, const std::vector<T>& v, const char* what)
 {
     HIPCHK(b.ensure(v.size()), what);
     HIPCHK(hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice), what);
     return PMC_OK;
+}
+
+pmc_status upload_tables(pmc_ctx* c)
+{
+    if (!c->have_phys || c->mats.empty()) return PMC_OK;
+    build_blob(c);
+    pmc_status s = upload(c, c->d_blob, c->blob, "upload tables");
+    if (s != PMC_OK) return s;
+    const int nm = (int)c->mats.size();
+    std::vector<float> npg(nm * kNEl);
+    for (int m = 0; m < nm; ++m)
+        for (int e = 0; e < kNEl; ++e) npg[m * kNEl + e] = (float)c->mats[m].nuclei_per_g_barn[e];
+    return upload(c, c->d_npg, npg, "upload nuclei per gram");
 }
 
 bool params_ok(const pmc_params& p, std::string& why)
@@ -167,6 +203,399 @@ bool params_ok(const pmc_params& p, std::string& why)
     return true;
 }
 
+bool same_materials(const std::vector<Material>& a, const std::vector<Material>& b)
+{
+    if (a.size() != b.size()) return false;
+    for (size_t i = 0; i < a.size(); ++i) {
+        if (a[i].hu_lo != b[i].hu_lo || a[i].hu_hi != b[i].hu_hi || a[i].rho_lo != b[i].rho_lo ||
+            a[i].rho_hi != b[i].rho_hi || a[i].i_ev != b[i].i_ev || a[i].own != b[i].own)
+            return false;
+        for (int e = 0; e < kNEl; ++e)
+            if (a[i].w[e] != b[i].w[e]) return false;
+    }
+    return true;
+}
+
+// HU grid -> voxel records of one geometry (Sec. II.A.1)
+pmc_status build_geometry(pmc_ctx* c, Geometry& g, const int16_t* hu, int nx, int ny, int nz, float dx,
+                          float dy, float dz, const std::vector<Material>& mats)
+{
+    const size_t nv = (size_t)nx * ny * nz;
+    std::vector<uint2> rec(nv);
+    const int nb = (int)mats.size();
+    for (size_t v = 0; v < nv; ++v) {
+        int h = hu[v];
+        h = h < -1000 ? -1000 : (h > 3000 ? 3000 : h);
+        int b = 0;
+        while (b + 1 < nb && mats[b + 1].hu_lo <= h) ++b;
+        const Material& m = mats[b];
+        double rho = m.rho_lo;
+        if (m.hu_hi > m.hu_lo) rho = m.rho_lo + (m.rho_hi - m.rho_lo) * double(h - m.hu_lo) / double(m.hu_hi - m.hu_lo);
+        const float rf = (float)rho;
+        uint32_t bits;
+        std::memcpy(&bits, &rf, 4);
+        rec[v] = make_uint2(bits, (uint32_t)b);
+    }
+    pmc_status s = upload(c, g.vox, rec, "upload voxel records");
+    if (s != PMC_OK) return s;
+    g.nx = nx; g.ny = ny; g.nz = nz;
+    g.vs[0] = dx; g.vs[1] = dy; g.vs[2] = dz;
+    return PMC_OK;
+}
+
+pmc_status load_geometry_common(pmc_ctx* c, int slot, const int16_t* hu, int nx, int ny, int nz, float dx,
+                                float dy, float dz, const pmc_material_table* mt)
+{
+    if (!hu || !mt) return fail(c, PMC_ERR_ARG, "geometry: NULL pointer");
+    if (nx <= 0 || ny <= 0 || nz <= 0) return fail(c, PMC_ERR_ARG, "geometry: dimensions must be > 0");
+    if (!(dx > 0.f) || !(dy > 0.f) || !(dz > 0.f)) return fail(c, PMC_ERR_ARG, "geometry: voxel size must be > 0");
+    if ((double)nx * ny * nz > 4.0e9) return fail(c, PMC_ERR_ARG, "geometry: too many voxels");
+    std::vector<Material> mats;
+    std::string why = build_materials(mt->n_bins, mt->hu_lo, mt->rho_lo, mt->rho_hi, mt->mass_frac,
+                                      mt->i_ev, mt->own_table, mats);
+    if (!why.empty()) return fail(c, PMC_ERR_ARG, why);
+    const bool others = c->geoms.size() > 1 || (slot != 0 && have_geometry(c));
+    if (others && !c->mats.empty() && !same_materials(mats, c->mats))
+        return fail(c, PMC_ERR_ARG, "all geometries of a context must use the same material table");
+    HIPCHK(hipSetDevice(c->device), "set device");
+    if (c->geoms.empty()) c->geoms.emplace_back(new Geometry());
+    if (slot >= (int)c->geoms.size()) c->geoms.emplace_back(new Geometry());
+    pmc_status s = build_geometry(c, *c->geoms[slot], hu, nx, ny, nz, dx, dy, dz, mats);
+    if (s != PMC_OK) return s;
+    if (c->mats.empty() || !same_materials(mats, c->mats)) {
+        c->mats = mats;
+        c->own_bin = -1;
+        for (int b = 0; b < (int)mats.size(); ++b)
+            if (mats[b].own) {
+                c->own_bin = b;
+                c->own = build_range_table(mats[b].za, mats[b].i_ev);
+            }
+    }
+    if (c->water.lnr.empty()) c->water = build_range_table(water_z_over_a(), kWaterIeV);
+    return upload_tables(c);
+}
+
+pmc_status check_spots(pmc_ctx* c, const pmc_spot* spots, int n_spots, unsigned long long n_hist,
+                       double* wsum_out)
+{
+    if (n_spots < 0) return fail(c, PMC_ERR_ARG, "n_spots < 0");
+    if (n_hist > 0 && (n_spots <= 0 || !spots)) return fail(c, PMC_ERR_ARG, "no spots");
+    if (n_hist >= (1ull << 32)) return fail(c, PMC_ERR_ARG, "at most 2^32-1 histories per plan");
+    double wsum = 0.0;
+    for (int s = 0; s < n_spots; ++s) {
+        const pmc_spot& sp = spots[s];
+        if (!(sp.e_mev > (float)kEMin && sp.e_mev <= (float)kEMax))
+            return fail(c, PMC_ERR_RANGE, "spot energy outside (0.1, 250] MeV");
+        if (!(sp.weight >= 0.f) || !(sp.sigma_x_cm >= 0.f) || !(sp.sigma_y_cm >= 0.f) ||
+            !std::isfinite(sp.x_cm) || !std::isfinite(sp.y_cm) || !std::isfinite(sp.weight) ||
+            !std::isfinite(sp.sigma_x_cm) || !std::isfinite(sp.sigma_y_cm))
+            return fail(c, PMC_ERR_RANGE, "spot weight/width must be finite and >= 0");
+        wsum += sp.weight;
+    }
+    if (n_hist > 0 && !(wsum > 0.0)) return fail(c, PMC_ERR_RANGE, "spot weights sum to zero");
+    *wsum_out = wsum;
+    return PMC_OK;
+}
+
+// histories per spot: largest remainder, proportional to weight
+void allocate(const pmc_spot* spots, int n_spots, unsigned long long n_hist, double wsum,
+              std::vector<unsigned long long>& ns)
+{
+    ns.assign(std::max(n_spots, 1), 0);
+    if (n_hist == 0) return;
+    std::vector<std::pair<double, int>> rem(n_spots);
+    unsigned long long assigned = 0;
+    for (int s = 0; s < n_spots; ++s) {
+        const double q = (double)n_hist * spots[s].weight / wsum;
+        ns[s] = (unsigned long long)std::floor(q);
+        rem[s] = {q - std::floor(q), s};
+        assigned += ns[s];
+    }
+    std::sort(rem.begin(), rem.end(), [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
+        return a.first != b.first ? a.first > b.first : a.second < b.second;
+    });
+    for (unsigned long long i = 0; assigned + i < n_hist; ++i) ns[rem[i % n_spots].second]++;
+}
+
+float u2f(uint32_t u)
+{
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
+struct RunResult {
+    double transport_ms = 0, device_ms = 0;
+    int generations = 0;
+};
+
+// The driver.  tuning = a calibration run: no statistics, no outputs.
+pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const Shape& shape,
+                      hipStream_t st, bool tuning, RunResult* rr)
+{
+    const int K = c->p.k_batches;
+    const int np = (int)plans.size();
+    for (int p = 0; p < np; ++p)
+        for (int q = 0; q < p; ++q)
+            if (plans[p].g == plans[q].g) return fail(c, PMC_ERR_ARG, "two plans of one run share a geometry");
+    // spots of every plan, flattened, each tagged with its plan and its first
+    // history index within the plan
+    std::vector<float> sp;
+    std::vector<unsigned long long> start(1, 0);
+    std::vector<double> incident(np, 0.0), wtot(np, 0.0);
+    unsigned long long total = 0;
+    for (int p = 0; p < np; ++p) {
+        const PlanIn& pl = plans[p];
+        double wsum = 0.0;
+        pmc_status s = check_spots(c, pl.spots, pl.n_spots, pl.n_hist, &wsum);
+        if (s != PMC_OK) return s;
+        std::vector<unsigned long long> ns;
+        allocate(pl.spots, pl.n_spots, pl.n_hist, wsum, ns);
+        unsigned long long local = 0;
+        for (int s2 = 0; s2 < pl.n_spots && pl.n_hist > 0; ++s2) {
+            const pmc_spot& q = pl.spots[s2];
+            const double om = ns[s2] ? (q.weight / wsum) * (double)pl.n_hist / (double)ns[s2] : 0.0;
+            const float omf = (float)om;
+            const float rec[8] = {q.x_cm / pl.g->vs[0], q.y_cm / pl.g->vs[1], q.e_mev,
+                                  q.sigma_x_cm / pl.g->vs[0], q.sigma_y_cm / pl.g->vs[1], omf,
+                                  u2f((uint32_t)p), u2f((uint32_t)local)};
+            sp.insert(sp.end(), rec, rec + 8);
+            start.push_back(start.back() + ns[s2]);
+            local += ns[s2];
+            incident[p] += (double)ns[s2] * (double)omf * (double)q.e_mev;
+            wtot[p] += (double)ns[s2] * (double)omf;
+        }
+        total += pl.n_hist;
+    }
+    const int n_spots = (int)start.size() - 1;
+    if (sp.empty()) sp.assign(8, 0.f);
+    HIPCHK(hipSetDevice(c->device), "set device");
+    const unsigned long long cap = c->p.queue_capacity ? c->p.queue_capacity
+                                                       : std::max<unsigned long long>(65536ull, total);
+    std::vector<PlanDesc> pd(np);
+    for (int p = 0; p < np; ++p) {
+        Geometry& g = *plans[p].g;
+        HIPCHK(g.tally.ensure(g.nvox() * K), "alloc tally");
+        PlanDesc& d = pd[p];
+        std::memset(&d, 0, sizeof(d));
+        d.nx = g.nx; d.ny = g.ny; d.nz = g.nz;
+        for (int i = 0; i < 3; ++i) { d.vs[i] = g.vs[i]; d.ivs[i] = 1.0f / g.vs[i]; }
+        d.vox = g.vox.p;
+        d.tally = g.tally.p;
+        d.key_lo = (uint32_t)plans[p].seed;
+        d.key_hi = (uint32_t)(plans[p].seed >> 32);
+    }
+    HIPCHK(c->d_q[0].ensure(cap * kQueuePlanes), "alloc queue");
+    HIPCHK(c->d_q[1].ensure(cap * kQueuePlanes), "alloc queue");
+    HIPCHK(c->d_gc.ensure(2 * (kMaxGenerations + 2)), "alloc counters");
+    HIPCHK(c->d_counters.ensure(8 * np), "alloc counters");
+    HIPCHK(c->d_ledger.ensure(4 * np), "alloc ledger");
+    HIPCHK(c->d_spots.ensure(sp.size()), "alloc spots");
+    HIPCHK(c->d_spot_start.ensure(start.size()), "alloc spots");
+    HIPCHK(c->d_plans.ensure(np), "alloc plans");
+    HIPCHK(hipMemcpyAsync(c->d_spots.p, sp.data(), sp.size() * 4, hipMemcpyHostToDevice, st), "upload spots");
+    HIPCHK(hipMemcpyAsync(c->d_spot_start.p, start.data(), start.size() * 8, hipMemcpyHostToDevice, st), "upload spots");
+    HIPCHK(hipMemcpyAsync(c->d_plans.p, pd.data(), np * sizeof(PlanDesc), hipMemcpyHostToDevice, st), "upload plans");
+    HIPCHK(hipEventRecord(c->ev0, st), "event");
+    for (int p = 0; p < np; ++p) HIPCHK(launch_zero(pd[p].tally, plans[p].g->nvox() * K * 8, st), "zero tally");
+    HIPCHK(launch_zero(c->d_gc.p, c->d_gc.n * 8, st), "zero counters");
+    HIPCHK(launch_zero(c->d_counters.p, 64 * (size_t)np, st), "zero counters");
+    HIPCHK(launch_zero(c->d_ledger.p, 32 * (size_t)np, st), "zero ledger");
+
+    KernelArgs a{};
+    a.single = pd[0];
+    a.plans = c->d_plans.p;
+    a.n_plans = np;
+    a.blob = c->d_blob.p;
+    a.blob_words = (int)c->blob.size();
+    a.pd_offset = (a.blob_words + 3) & ~3;
+    a.n_mat = (int)c->mats.size();
+    const RangeTable& own = c->own_bin >= 0 ? c->own : c->water;
+    a.r_first[0] = (float)c->water.r_first; a.r_first[1] = (float)own.r_first;
+    a.ln_r1[0] = (float)c->water.ln_r1; a.ln_r1[1] = (float)own.ln_r1;
+    a.inv_step[0] = (float)c->water.inv_step; a.inv_step[1] = (float)own.inv_step;
+    a.el_sig = c->d_el_sig.p; a.mat_npg = c->d_npg.p; a.elem = c->d_elem.p;
+    a.sec_mult = c->d_mult.p; a.sec_floc = c->d_floc.p; a.sec_x = c->d_xcdf.p; a.sec_mu = c->d_mucdf.p;
+    a.k_batches = K;
+    a.flags = c->p.flags;
+    a.f_mcs = (float)c->p.f_mcs;
+    a.s_min = (float)c->p.s_min_cm;
+    a.spots = c->d_spots.p;
+    a.spot_start = c->d_spot_start.p;
+    a.n_spots = n_spots;
+    a.n_primary = total;
+    a.q_cap = cap;
+    a.gen_counters = c->d_gc.p;
+    a.ledger = c->d_ledger.p;
+    a.counters = c->d_counters.p;
+    a.refill_lanes = shape.refill;
+    a.batch_events = shape.batch;
+
+    const int block = shape.block;
+    const size_t lds = (size_t)(multi ? a.pd_offset + 16 * np : a.blob_words) * 4;
+    int max_block = 0;
+    HIPCHK(transport_max_block(multi, &max_block), "kernel attributes");
+    if (block > max_block) return fail(c, PMC_ERR_ARG, "block_threads exceeds the transport kernel's limit");
+    int bpc = shape.blocks_per_cu, fit = 0;
+    HIPCHK(transport_occupancy(multi, block, lds, &fit), "occupancy");
+    if (fit < 1) return fail(c, PMC_ERR_DEVICE, "transport kernel does not fit on a CU");
+    if (bpc == 0 || bpc > fit) bpc = fit;
+    const int grid = c->num_cu * bpc;
+    int gens = 0;
+    unsigned long long produced_total = 0, overflow_n = 0;
+    if (total > 0) {
+        for (int gidx = 0;; ++gidx) {
+            if (gidx >= kMaxGenerations) return fail(c, PMC_ERR_DEVICE, "secondary generations exceed limit");
+            a.gen = gidx;
+            a.q_in = c->d_q[gidx & 1].p;
+            a.q_out = c->d_q[(gidx + 1) & 1].p;
+            HIPCHK(hipEventRecord(c->ev_gen[2 * gidx], st), "event");
+            HIPCHK(launch_transport(a, multi, grid, block, lds, st), "transport launch");
+            HIPCHK(hipEventRecord(c->ev_gen[2 * gidx + 1], st), "event");
+            ++gens;
+            HIPCHK(hipMemcpyAsync(c->h_pinned, c->d_gc.p + 2 * (gidx + 1), 8, hipMemcpyDeviceToHost, st), "read counters");
+            HIPCHK(hipStreamSynchronize(st), "transport");
+            const unsigned long long prod = c->h_pinned[0];
+            produced_total += prod;
+            if (prod > cap) overflow_n += prod - cap;
+            if (prod == 0) break;
+        }
+    }
+    if (!tuning) {
+        for (int p = 0; p < np; ++p) {
+            const Geometry& g = *plans[p].g;
+            const double vol = (double)g.vs[0] * g.vs[1] * g.vs[2];
+            const double conv0 = wtot[p] > 0.0 ? 1.602176634e-10 / (vol * wtot[p]) : 0.0;
+            HIPCHK(launch_stats(g.tally.p, g.vox.p, g.nvox(), K, conv0, plans[p].d_dose, plans[p].d_var,
+                                c->d_ledger.p + 4 * p + 3, st), "stats launch");
+        }
+    }
+    HIPCHK(hipEventRecord(c->ev1, st), "event");
+    const size_t led_words = 4 * (size_t)np, cnt_words = 8 * (size_t)np;
+    if ((led_words + cnt_words) * 8 > kPinnedBytes) return fail(c, PMC_ERR_ARG, "too many plans");
+    HIPCHK(hipMemcpyAsync(c->h_pinned, c->d_ledger.p, led_words * 8, hipMemcpyDeviceToHost, st), "read ledger");
+    HIPCHK(hipMemcpyAsync(c->h_pinned + led_words, c->d_counters.p, cnt_words * 8, hipMemcpyDeviceToHost, st), "read counters");
+    HIPCHK(hipStreamSynchronize(st), "run");
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1), "event time");
+    double transport_ms = 0.0;
+    for (int gidx = 0; gidx < gens; ++gidx) {
+        float t = 0.f;
+        HIPCHK(hipEventElapsedTime(&t, c->ev_gen[2 * gidx], c->ev_gen[2 * gidx + 1]), "event time");
+        transport_ms += t;
+    }
+    if (rr) {
+        rr->transport_ms = transport_ms;
+        rr->device_ms = ms;
+        rr->generations = gens;
+    }
+    if (!tuning) {
+        const double* led = reinterpret_cast<const double*>(c->h_pinned);
+        const unsigned long long* cnt = c->h_pinned + led_words;
+        for (int p = 0; p < np; ++p) {
+            pmc_summary* sm = plans[p].summary;
+            if (!sm) continue;
+            std::memset(sm, 0, sizeof(*sm));
+            sm->incident = incident[p];
+            sm->escaped = led[4 * p + 0];
+            sm->neutral = led[4 * p + 1];
+            sm->overflow = led[4 * p + 2];
+            sm->deposited = led[4 * p + 3];
+            sm->histories = plans[p].n_hist;
+            sm->steps = cnt[8 * p + 0];
+            sm->n_elastic = cnt[8 * p + 1];
+            sm->n_nonelastic = cnt[8 * p + 2];
+            sm->n_short_steps = cnt[8 * p + 3];
+            sm->tally_atomics = cnt[8 * p + 4];
+            sm->secondaries = produced_total;
+            sm->n_overflow = overflow_n;
+            sm->total_weight = wtot[p];
+            sm->device_ms = ms;
+            sm->transport_ms = transport_ms;
+            sm->generations = gens;
+        }
+    }
+    if (overflow_n) return fail(c, PMC_ERR_QUEUE_OVERFLOW, "secondary queue overflow: raise queue_capacity");
+    return PMC_OK;
+}
+
+// Launch shape of a run: the caller's fixed values, and for the fields left
+// at 0 the fastest of a few candidates timed on a scaled-down copy of the
+// workload (2e5 histories), remembered per workload signature.
+pmc_status choose_shape(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, hipStream_t st, Shape* out)
+{
+    Shape s;
+    s.block = c->p.block_threads ? c->p.block_threads : 256;
+    s.blocks_per_cu = c->p.blocks_per_cu;
+    s.refill = c->p.refill_lanes ? c->p.refill_lanes : 16;
+    s.batch = c->p.batch_events ? c->p.batch_events : 4;
+    const bool tune = c->p.block_threads == 0 || c->p.refill_lanes == 0 || c->p.batch_events == 0;
+    unsigned long long total = 0, vox = 0;
+    for (const PlanIn& p : plans) {
+        total += p.n_hist;
+        vox += p.g->nvox();
+    }
+    if (!tune || total < 1000000ull) {
+        *out = s;
+        return PMC_OK;
+    }
+    auto log2i = [](unsigned long long v) { int l = 0; while (v >>= 1) ++l; return l; };
+    const auto key = std::make_tuple((int)multi, (int)plans.size(), log2i(total), log2i(vox));
+    auto it = c->tuned.find(key);
+    if (it != c->tuned.end()) {
+        *out = it->second;
+        return PMC_OK;
+    }
+    std::vector<PlanIn> cal = plans;
+    const double f = 200000.0 / (double)total;
+    for (PlanIn& p : cal) {
+        p.n_hist = (unsigned long long)std::ceil(p.n_hist * f);
+        p.summary = nullptr;
+    }
+    std::vector<Shape> cands;
+    for (int b : {256, 512, 1024})
+        for (int r : {16, 32})
+            for (int e : {2, 4}) {
+                Shape x;
+                x.block = c->p.block_threads ? c->p.block_threads : b;
+                x.blocks_per_cu = c->p.blocks_per_cu;
+                x.refill = c->p.refill_lanes ? c->p.refill_lanes : r;
+                x.batch = c->p.batch_events ? c->p.batch_events : e;
+                bool dup = false;
+                for (const Shape& y : cands)
+                    dup |= (y.block == x.block && y.refill == x.refill && y.batch == x.batch);
+                if (!dup) cands.push_back(x);
+            }
+    double best = 1e300;
+    Shape best_s = s;
+    for (const Shape& x : cands) {
+        RunResult r;
+        pmc_status st2 = run_driver(c, cal, multi, x, st, true, &r);
+        if (st2 != PMC_OK) return st2;
+        if (r.transport_ms < best) {
+            best = r.transport_ms;
+            best_s = x;
+        }
+    }
+    c->tuned[key] = best_s;
+    *out = best_s;
+    return PMC_OK;
+}
+
+pmc_status run_plans_impl(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, hipStream_t st)
+{
+    if (!c->have_phys || !have_geometry(c)) return fail(c, PMC_ERR_STATE, "load physics and geometry first");
+    for (const PlanIn& p : plans) {
+        double w;
+        pmc_status s = check_spots(c, p.spots, p.n_spots, p.n_hist, &w);
+        if (s != PMC_OK) return s;
+    }
+    Shape shape;
+    pmc_status s = choose_shape(c, plans, multi, st, &shape);
+    if (s != PMC_OK) return s;
+    return run_driver(c, plans, multi, shape, st, false, nullptr);
+}
+
 }  // namespace
 
 extern "C" {
@@ -178,16 +607,10 @@ pmc_status pmc_default_params(pmc_params* p)
     p->f_mcs = 1.07;
     p->s_min_cm = 1e-4;
     p->k_batches = 10;
-    p->flags = 0;
-    p->queue_capacity = 0;
-    p->block_threads = 0;
-    p->blocks_per_cu = 0;
-    p->refill_lanes = 0;
-    p->batch_events = 0;
     return PMC_OK;
 }
 
-const char* pmc_version(void) { return "pmc 0.1 gfx950"; }
+const char* pmc_version(void) { return "pmc 0.2 gfx950"; }
 
 const char* pmc_last_error(const pmc_ctx* c)
 {
@@ -215,23 +638,20 @@ pmc_status pmc_create(pmc_ctx** out, int device, const pmc_params* p)
     if (!c) { g_create_error = "host allocation failed"; return PMC_ERR_NOMEM; }
     c->device = device;
     c->p = prm;
-    if (c->p.block_threads == 0) c->p.block_threads = 256;
-    if (c->p.refill_lanes == 0) c->p.refill_lanes = 16;
-    if (c->p.batch_events == 0) c->p.batch_events = 4;
     hipDeviceProp_t prop;
     if ((e = hipSetDevice(device)) != hipSuccess || (e = hipGetDeviceProperties(&prop, device)) != hipSuccess ||
         (e = hipEventCreate(&c->ev0)) != hipSuccess || (e = hipEventCreate(&c->ev1)) != hipSuccess ||
-        (e = hipHostMalloc((void**)&c->h_pinned, 4096, hipHostMallocDefault)) != hipSuccess) {
+        (e = hipHostMalloc((void**)&c->h_pinned, kPinnedBytes, hipHostMallocDefault)) != hipSuccess) {
         g_create_error = std::string("device setup: ") + hipGetErrorString(e);
         pmc_destroy(c);
         return PMC_ERR_DEVICE;
     }
     for (int i = 0; i < 2 * kMaxGenerations; ++i)
         if ((e = hipEventCreate(&c->ev_gen[i])) != hipSuccess) {
-        g_create_error = std::string("device setup: ") + hipGetErrorString(e);
-        pmc_destroy(c);
-        return PMC_ERR_DEVICE;
-    }
+            g_create_error = std::string("device setup: ") + hipGetErrorString(e);
+            pmc_destroy(c);
+            return PMC_ERR_DEVICE;
+        }
     c->num_cu = prop.multiProcessorCount;
     *out = c;
     return PMC_OK;
@@ -241,18 +661,13 @@ pmc_status pmc_destroy(pmc_ctx* c)
 {
     if (!c) return PMC_OK;
     (void)hipSetDevice(c->device);
-    c->d_vox.release();
-    c->d_blob.release(); c->d_el_sig.release(); c->d_npg.release(); c->d_elem.release();
-    c->d_mult.release(); c->d_floc.release(); c->d_xcdf.release(); c->d_mucdf.release();
-    c->d_tally.release(); c->d_dose.release(); c->d_var.release(); c->d_ledger.release();
-    c->d_q[0].release(); c->d_q[1].release();
-    c->d_gc.release(); c->d_counters.release(); c->d_spot_start.release(); c->d_spots.release();
+    c->geoms.clear();
     if (c->h_pinned) (void)hipHostFree(c->h_pinned);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     for (int i = 0; i < 2 * kMaxGenerations; ++i)
         if (c->ev_gen[i]) (void)hipEventDestroy(c->ev_gen[i]);
-    delete c;
+    delete c;   // the DevBuf destructors release the remaining device buffers
     return PMC_OK;
 }
 
@@ -264,14 +679,16 @@ pmc_status pmc_load_physics(pmc_ctx* c, const pmc_nuclear_data* nd)
         return fail(c, PMC_ERR_ARG, "nuclear data: NULL array");
     const size_t ns = kNEl * kNE, nrow = kSecNuc * kSecBins;
     for (size_t i = 0; i < ns; ++i)
-        if (!(nd->sigma_ne_barn[i] >= 0.f) || !(nd->sigma_el_barn[i] >= 0.f))
-            return fail(c, PMC_ERR_ARG, "nuclear data: negative or NaN cross section");
-    if (nd->sigma_ne_barn[0 * kNE] != 0.f) {
-        for (int i = 0; i < kNE; ++i)
-            if (nd->sigma_ne_barn[i] != 0.f) return fail(c, PMC_ERR_ARG, "nuclear data: hydrogen has no non-elastic channel");
-    }
+        if (!(nd->sigma_ne_barn[i] >= 0.f) || !(nd->sigma_el_barn[i] >= 0.f) ||
+            !std::isfinite(nd->sigma_ne_barn[i]) || !std::isfinite(nd->sigma_el_barn[i]))
+            return fail(c, PMC_ERR_ARG, "nuclear data: negative or non-finite cross section");
+    for (int i = 0; i < kNE; ++i)
+        if (nd->sigma_ne_barn[i] != 0.f) return fail(c, PMC_ERR_ARG, "nuclear data: hydrogen has no non-elastic channel");
     for (size_t r = 0; r < nrow; ++r) {
         if (nd->mult_cdf[r * kSecMult + kSecMult - 1] != 1.f) return fail(c, PMC_ERR_ARG, "nuclear data: multiplicity CDF must end at 1");
+        for (int m = 0; m + 1 < kSecMult; ++m)
+            if (nd->mult_cdf[r * kSecMult + m + 1] < nd->mult_cdf[r * kSecMult + m] || nd->mult_cdf[r * kSecMult + m] < 0.f)
+                return fail(c, PMC_ERR_ARG, "nuclear data: multiplicity CDF must not decrease");
         if (nd->x_cdf[r * kSecCdf] != 0.f || nd->x_cdf[r * kSecCdf + 32] != 1.f ||
             nd->mu_cdf[r * kSecCdf] != 0.f || nd->mu_cdf[r * kSecCdf + 32] != 1.f)
             return fail(c, PMC_ERR_ARG, "nuclear data: CDFs must run from 0 to 1");
@@ -323,52 +740,31 @@ pmc_status pmc_load_geometry(pmc_ctx* c, const int16_t* hu, int nx, int ny, int 
                              float dy, float dz, const pmc_material_table* mt)
 {
     if (!c) return PMC_ERR_ARG;
-    if (!hu || !mt) return fail(c, PMC_ERR_ARG, "geometry: NULL pointer");
-    if (nx <= 0 || ny <= 0 || nz <= 0) return fail(c, PMC_ERR_ARG, "geometry: dimensions must be > 0");
-    if (!(dx > 0.f) || !(dy > 0.f) || !(dz > 0.f)) return fail(c, PMC_ERR_ARG, "geometry: voxel size must be > 0");
-    if ((double)nx * ny * nz > 4.0e9) return fail(c, PMC_ERR_ARG, "geometry: too many voxels");
-    std::vector<Material> mats;
-    std::string why = build_materials(mt->n_bins, mt->hu_lo, mt->rho_lo, mt->rho_hi, mt->mass_frac,
-                                      mt->i_ev, mt->own_table, mats);
-    if (!why.empty()) return fail(c, PMC_ERR_ARG, why);
-    HIPCHK(hipSetDevice(c->device), "set device");
-    const size_t nv = (size_t)nx * ny * nz;
-    std::vector<uint2> rec(nv);
-    const int nb = (int)mats.size();
-    for (size_t v = 0; v < nv; ++v) {
-        int h = hu[v];
-        h = h < -1000 ? -1000 : (h > 3000 ? 3000 : h);
-        int b = 0;
-        while (b + 1 < nb && mats[b + 1].hu_lo <= h) ++b;
-        const Material& m = mats[b];
-        double rho = m.rho_lo;
-        if (m.hu_hi > m.hu_lo) rho = m.rho_lo + (m.rho_hi - m.rho_lo) * double(h - m.hu_lo) / double(m.hu_hi - m.hu_lo);
-        float rf = (float)rho;
-        uint32_t bits;
-        std::memcpy(&bits, &rf, 4);
-        rec[v] = make_uint2(bits, (uint32_t)b);
+    return load_geometry_common(c, 0, hu, nx, ny, nz, dx, dy, dz, mt);
+}
+
+pmc_status pmc_load_geometry_slot(pmc_ctx* c, int* geometry_id_out, const int16_t* hu, int nx, int ny,
+                                  int nz, float dx, float dy, float dz, const pmc_material_table* mt)
+{
+    if (!c) return PMC_ERR_ARG;
+    if (!geometry_id_out) return fail(c, PMC_ERR_ARG, "geometry_id_out is NULL");
+    if (!have_geometry(c)) return fail(c, PMC_ERR_STATE, "load the base geometry first (pmc_load_geometry)");
+    if ((int)c->geoms.size() >= kMaxPlans) return fail(c, PMC_ERR_ARG, "too many geometry slots");
+    const int slot = (int)c->geoms.size();
+    pmc_status s = load_geometry_common(c, slot, hu, nx, ny, nz, dx, dy, dz, mt);
+    if (s != PMC_OK) {
+        if ((int)c->geoms.size() > slot) c->geoms.resize(slot);
+        return s;
     }
-    pmc_status s = upload(c, c->d_vox, rec, "upload voxel records");
-    if (s != PMC_OK) return s;
-    c->mats = mats;
-    c->own_bin = -1;
-    for (int b = 0; b < nb; ++b)
-        if (mats[b].own) {
-            c->own_bin = b;
-            c->own = build_range_table(mats[b].za, mats[b].i_ev);
-        }
-    c->nx = nx; c->ny = ny; c->nz = nz;
-    c->vs[0] = dx; c->vs[1] = dy; c->vs[2] = dz;
-    if (c->water.lnr.empty()) c->water = build_range_table(water_z_over_a(), kWaterIeV);
-    c->have_geom = true;
-    return upload_tables(c);
+    *geometry_id_out = slot;
+    return PMC_OK;
 }
 
 pmc_status pmc_inspect_tables(const pmc_ctx* c, float* lnr_w, float* lnr_o, float* sigma_per_g,
                               double* material, int32_t* n_bins)
 {
     if (!c) return PMC_ERR_ARG;
-    if (!c->have_phys || !c->have_geom) return PMC_ERR_STATE;
+    if (!c->have_phys || !have_geometry(c)) return PMC_ERR_STATE;
     const int nm = (int)c->mats.size();
     if (n_bins) *n_bins = nm;
     if (lnr_w) {
@@ -394,188 +790,15 @@ pmc_status pmc_inspect_tables(const pmc_ctx* c, float* lnr_w, float* lnr_o, floa
     return PMC_OK;
 }
 
-static pmc_status run_impl(pmc_ctx* c, const pmc_spot* spots, int n_spots, uint64_t n_hist,
-                           uint64_t seed, double* d_dose, double* d_var, hipStream_t st,
-                           pmc_summary* summary)
-{
-    if (!c->have_phys || !c->have_geom) return fail(c, PMC_ERR_STATE, "load physics and geometry first");
-    if (n_hist > 0 && (n_spots <= 0 || !spots)) return fail(c, PMC_ERR_ARG, "no spots");
-    if (n_spots < 0) return fail(c, PMC_ERR_ARG, "n_spots < 0");
-    double wsum = 0.0;
-    for (int s = 0; s < n_spots; ++s) {
-        const pmc_spot& sp = spots[s];
-        if (!(sp.e_mev > (float)kEMin && sp.e_mev <= (float)kEMax)) return fail(c, PMC_ERR_RANGE, "spot energy outside (0.1, 250] MeV");
-        if (!(sp.weight >= 0.f) || !(sp.sigma_x_cm >= 0.f) || !(sp.sigma_y_cm >= 0.f) ||
-            !std::isfinite(sp.x_cm) || !std::isfinite(sp.y_cm) || !std::isfinite(sp.weight))
-            return fail(c, PMC_ERR_RANGE, "spot weight/width must be finite and >= 0");
-        wsum += sp.weight;
-    }
-    if (n_hist > 0 && !(wsum > 0.0)) return fail(c, PMC_ERR_RANGE, "spot weights sum to zero");
-    HIPCHK(hipSetDevice(c->device), "set device");
-    const int K = c->p.k_batches;
-    const size_t nv = (size_t)c->nx * c->ny * c->nz;
-
-    // histories per spot: largest remainder, proportional to weight
-    std::vector<unsigned long long> ns(std::max(n_spots, 1), 0), start(n_spots + 1, 0);
-    if (n_hist > 0) {
-        std::vector<std::pair<double, int>> rem(n_spots);
-        unsigned long long assigned = 0;
-        for (int s = 0; s < n_spots; ++s) {
-            const double q = (double)n_hist * spots[s].weight / wsum;
-            ns[s] = (unsigned long long)std::floor(q);
-            rem[s] = {q - std::floor(q), s};
-            assigned += ns[s];
-        }
-        std::sort(rem.begin(), rem.end(), [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
-            return a.first != b.first ? a.first > b.first : a.second < b.second;
-        });
-        for (unsigned long long i = 0; assigned + i < n_hist; ++i) ns[rem[i % n_spots].second]++;
-    }
-    std::vector<float> sp(8 * std::max(n_spots, 1), 0.f);
-    double incident = 0.0, wtot = 0.0;
-    for (int s = 0; s < n_spots; ++s) {
-        start[s + 1] = start[s] + ns[s];
-        const double om = ns[s] ? (spots[s].weight / wsum) * (double)n_hist / (double)ns[s] : 0.0;
-        const float omf = (float)om;
-        sp[8 * s + 0] = spots[s].x_cm / c->vs[0];
-        sp[8 * s + 1] = spots[s].y_cm / c->vs[1];
-        sp[8 * s + 2] = spots[s].e_mev;
-        sp[8 * s + 3] = spots[s].sigma_x_cm / c->vs[0];
-        sp[8 * s + 4] = spots[s].sigma_y_cm / c->vs[1];
-        sp[8 * s + 5] = omf;
-        incident += (double)ns[s] * (double)omf * (double)spots[s].e_mev;
-        wtot += (double)ns[s] * (double)omf;
-    }
-    // buffers
-    unsigned long long cap = c->p.queue_capacity ? c->p.queue_capacity
-                                                 : std::max<unsigned long long>(65536ull, n_hist);
-    HIPCHK(c->d_tally.ensure(nv * K), "alloc tally");
-    HIPCHK(c->d_q[0].ensure(cap * kQueuePlanes), "alloc queue");
-    HIPCHK(c->d_q[1].ensure(cap * kQueuePlanes), "alloc queue");
-    HIPCHK(c->d_gc.ensure(2 * (kMaxGenerations + 2)), "alloc counters");
-    HIPCHK(c->d_counters.ensure(8), "alloc counters");
-    HIPCHK(c->d_ledger.ensure(8), "alloc ledger");
-    HIPCHK(c->d_spots.ensure(sp.size()), "alloc spots");
-    HIPCHK(c->d_spot_start.ensure(start.size()), "alloc spots");
-    HIPCHK(hipMemcpyAsync(c->d_spots.p, sp.data(), sp.size() * 4, hipMemcpyHostToDevice, st), "upload spots");
-    HIPCHK(hipMemcpyAsync(c->d_spot_start.p, start.data(), start.size() * 8, hipMemcpyHostToDevice, st), "upload spots");
-    HIPCHK(hipEventRecord(c->ev0, st), "event");
-    HIPCHK(launch_zero(c->d_tally.p, nv * K * 8, st), "zero tally");
-    HIPCHK(launch_zero(c->d_gc.p, c->d_gc.n * 8, st), "zero counters");
-    HIPCHK(launch_zero(c->d_counters.p, 64, st), "zero counters");
-    HIPCHK(launch_zero(c->d_ledger.p, 64, st), "zero ledger");
-
-    KernelArgs a{};
-    a.vox = c->d_vox.p;
-    a.nx = c->nx; a.ny = c->ny; a.nz = c->nz;
-    for (int i = 0; i < 3; ++i) { a.vs[i] = c->vs[i]; a.ivs[i] = 1.0f / c->vs[i]; }
-    a.blob = c->d_blob.p;
-    a.blob_words = (int)c->blob.size();
-    a.n_mat = (int)c->mats.size();
-    const RangeTable& own = c->own_bin >= 0 ? c->own : c->water;
-    a.r_first[0] = (float)c->water.r_first; a.r_first[1] = (float)own.r_first;
-    a.ln_r1[0] = (float)c->water.ln_r1; a.ln_r1[1] = (float)own.ln_r1;
-    a.inv_step[0] = (float)c->water.inv_step; a.inv_step[1] = (float)own.inv_step;
-    a.el_sig = c->d_el_sig.p; a.mat_npg = c->d_npg.p; a.elem = c->d_elem.p;
-    a.sec_mult = c->d_mult.p; a.sec_floc = c->d_floc.p; a.sec_x = c->d_xcdf.p; a.sec_mu = c->d_mucdf.p;
-    a.seed_lo = (uint32_t)seed; a.seed_hi = (uint32_t)(seed >> 32);
-    a.k_batches = K;
-    a.flags = c->p.flags;
-    a.f_mcs = (float)c->p.f_mcs;
-    a.s_min = (float)c->p.s_min_cm;
-    a.spots = c->d_spots.p;
-    a.spot_start = c->d_spot_start.p;
-    a.n_spots = n_spots;
-    a.n_primary = n_hist;
-    a.q_cap = cap;
-    a.gen_counters = c->d_gc.p;
-    a.tally = c->d_tally.p;
-    a.ledger = c->d_ledger.p;
-    a.counters = c->d_counters.p;
-    a.refill_lanes = c->p.refill_lanes;
-    a.batch_events = c->p.batch_events;
-
-    const int block = c->p.block_threads;
-    const size_t lds = c->blob.size() * 4;
-    int max_block = 0;
-    HIPCHK(transport_max_block(&max_block), "kernel attributes");
-    if (block > max_block) return fail(c, PMC_ERR_ARG, "block_threads exceeds the transport kernel's limit");
-    int bpc = c->p.blocks_per_cu;
-    if (bpc == 0) {
-        HIPCHK(transport_occupancy(block, lds, &bpc), "occupancy");
-        if (bpc < 1) return fail(c, PMC_ERR_DEVICE, "transport kernel does not fit on a CU");
-    } else if (lds > 65536) {
-        int dummy;
-        HIPCHK(transport_occupancy(block, lds, &dummy), "occupancy");
-    }
-    const int grid = c->num_cu * bpc;
-    int gens = 0;
-    unsigned long long produced_total = 0, overflow_n = 0;
-    if (n_hist > 0) {
-        for (int g = 0;; ++g) {
-            if (g >= kMaxGenerations) return fail(c, PMC_ERR_DEVICE, "secondary generations exceed limit");
-            a.gen = g;
-            a.q_in = c->d_q[g & 1].p;
-            a.q_out = c->d_q[(g + 1) & 1].p;
-            HIPCHK(hipEventRecord(c->ev_gen[2 * g], st), "event");
-            HIPCHK(launch_transport(a, grid, block, lds, st), "transport launch");
-            HIPCHK(hipEventRecord(c->ev_gen[2 * g + 1], st), "event");
-            ++gens;
-            HIPCHK(hipMemcpyAsync(c->h_pinned, c->d_gc.p + 2 * (g + 1), 8, hipMemcpyDeviceToHost, st), "read counters");
-            HIPCHK(hipStreamSynchronize(st), "transport");
-            const unsigned long long prod = c->h_pinned[0];
-            produced_total += prod;
-            if (prod > cap) overflow_n += prod - cap;
-            if (prod == 0) break;
-        }
-    }
-    const double vol = (double)c->vs[0] * c->vs[1] * c->vs[2];
-    const double conv0 = wtot > 0.0 ? 1.602176634e-10 / (vol * wtot) : 0.0;
-    HIPCHK(launch_stats(c->d_tally.p, c->d_vox.p, nv, K, conv0, d_dose, d_var, c->d_ledger.p + 3, st), "stats launch");
-    HIPCHK(hipEventRecord(c->ev1, st), "event");
-    HIPCHK(hipMemcpyAsync(c->h_pinned, c->d_ledger.p, 64, hipMemcpyDeviceToHost, st), "read ledger");
-    HIPCHK(hipMemcpyAsync(c->h_pinned + 8, c->d_counters.p, 64, hipMemcpyDeviceToHost, st), "read counters");
-    HIPCHK(hipStreamSynchronize(st), "run");
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1), "event time");
-    double led[8];
-    std::memcpy(led, c->h_pinned, 64);
-    double transport_ms = 0.0;
-    for (int g = 0; g < gens; ++g) {
-        float t = 0.f;
-        HIPCHK(hipEventElapsedTime(&t, c->ev_gen[2 * g], c->ev_gen[2 * g + 1]), "event time");
-        transport_ms += t;
-    }
-    if (summary) {
-        std::memset(summary, 0, sizeof(*summary));
-        summary->incident = incident;
-        summary->escaped = led[0];
-        summary->neutral = led[1];
-        summary->overflow = led[2];
-        summary->deposited = led[3];
-        summary->histories = n_hist;
-        summary->steps = c->h_pinned[8];
-        summary->n_elastic = c->h_pinned[9];
-        summary->n_nonelastic = c->h_pinned[10];
-        summary->secondaries = produced_total;
-        summary->n_overflow = overflow_n;
-        summary->n_short_steps = c->h_pinned[11];
-        summary->total_weight = wtot;
-        summary->device_ms = ms;
-        summary->transport_ms = transport_ms;
-        summary->generations = gens;
-    }
-    if (overflow_n) return fail(c, PMC_ERR_QUEUE_OVERFLOW, "secondary queue overflow: raise queue_capacity");
-    return PMC_OK;
-}
-
 pmc_status pmc_run_spots_dev(pmc_ctx* c, const pmc_spot* spots, int n_spots, uint64_t n_histories,
                              uint64_t seed, double* d_dose, double* d_var, void* hip_stream,
                              pmc_summary* summary)
 {
     if (!c) return PMC_ERR_ARG;
     if (!d_dose) return fail(c, PMC_ERR_ARG, "d_dose is NULL");
-    return run_impl(c, spots, n_spots, n_histories, seed, d_dose, d_var, (hipStream_t)hip_stream, summary);
+    if (!c->have_phys || !have_geometry(c)) return fail(c, PMC_ERR_STATE, "load physics and geometry first");
+    std::vector<PlanIn> plans{{c->geoms[0].get(), spots, n_spots, n_histories, seed, d_dose, d_var, summary}};
+    return run_plans_impl(c, plans, false, (hipStream_t)hip_stream);
 }
 
 pmc_status pmc_run_spots(pmc_ctx* c, const pmc_spot* spots, int n_spots, uint64_t n_histories,
@@ -583,16 +806,58 @@ pmc_status pmc_run_spots(pmc_ctx* c, const pmc_spot* spots, int n_spots, uint64_
 {
     if (!c) return PMC_ERR_ARG;
     if (!dose_out || !var_out) return fail(c, PMC_ERR_ARG, "dose/var output is NULL");
-    if (!c->have_phys || !c->have_geom) return fail(c, PMC_ERR_STATE, "load physics and geometry first");
+    if (!c->have_phys || !have_geometry(c)) return fail(c, PMC_ERR_STATE, "load physics and geometry first");
     HIPCHK(hipSetDevice(c->device), "set device");
-    const size_t nv = (size_t)c->nx * c->ny * c->nz;
+    const size_t nv = c->geoms[0]->nvox();
     HIPCHK(c->d_dose.ensure(nv), "alloc dose");
     HIPCHK(c->d_var.ensure(nv), "alloc var");
-    pmc_status s = run_impl(c, spots, n_spots, n_histories, seed, c->d_dose.p, c->d_var.p, nullptr, summary);
+    std::vector<PlanIn> plans{{c->geoms[0].get(), spots, n_spots, n_histories, seed, c->d_dose.p, c->d_var.p, summary}};
+    pmc_status s = run_plans_impl(c, plans, false, nullptr);
     if (s != PMC_OK && s != PMC_ERR_QUEUE_OVERFLOW) return s;
     HIPCHK(hipMemcpy(dose_out, c->d_dose.p, nv * 8, hipMemcpyDeviceToHost), "read dose");
     HIPCHK(hipMemcpy(var_out, c->d_var.p, nv * 8, hipMemcpyDeviceToHost), "read variance");
     return s;
+}
+
+pmc_status pmc_run_plans(pmc_ctx* c, const pmc_plan* plans, int n_plans, uint64_t seed, void* hip_stream)
+{
+    if (!c) return PMC_ERR_ARG;
+    if (!plans || n_plans <= 0 || n_plans > kMaxPlans) return fail(c, PMC_ERR_ARG, "n_plans must be in [1, 64]");
+    if (!c->have_phys || !have_geometry(c)) return fail(c, PMC_ERR_STATE, "load physics and geometry first");
+    std::vector<PlanIn> v;
+    for (int p = 0; p < n_plans; ++p) {
+        const pmc_plan& q = plans[p];
+        if (q.geometry_id < 0 || q.geometry_id >= (int)c->geoms.size())
+            return fail(c, PMC_ERR_ARG, "unknown geometry_id");
+        if (!q.d_dose) return fail(c, PMC_ERR_ARG, "plan d_dose is NULL");
+        v.push_back({c->geoms[q.geometry_id].get(), q.spots, q.n_spots, q.n_histories, seed + (uint64_t)p,
+                     q.d_dose, q.d_var, q.summary});
+    }
+    return run_plans_impl(c, v, true, (hipStream_t)hip_stream);
+}
+
+pmc_status pmc_atomic_probe(pmc_ctx* c, uint64_t n_atomics, void* hip_stream, double* ms_out)
+{
+    if (!c) return PMC_ERR_ARG;
+    if (!ms_out || n_atomics == 0) return fail(c, PMC_ERR_ARG, "ms_out is NULL or n_atomics is 0");
+    if (!have_geometry(c)) return fail(c, PMC_ERR_STATE, "load a geometry first");
+    HIPCHK(hipSetDevice(c->device), "set device");
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int K = c->p.k_batches;
+    Geometry& g = *c->geoms[0];
+    HIPCHK(g.tally.ensure(g.nvox() * K), "alloc tally");
+    const int grid = c->num_cu * 4;
+    const unsigned long long lanes = (unsigned long long)grid * 256;
+    const unsigned long long per_lane = (n_atomics + lanes - 1) / lanes;
+    HIPCHK(launch_atomic_probe(g.tally.p, g.nx, g.ny, g.nz, K, grid, 1, st), "probe warm-up");
+    HIPCHK(hipEventRecord(c->ev0, st), "event");
+    HIPCHK(launch_atomic_probe(g.tally.p, g.nx, g.ny, g.nz, K, grid, per_lane, st), "probe launch");
+    HIPCHK(hipEventRecord(c->ev1, st), "event");
+    HIPCHK(hipEventSynchronize(c->ev1), "probe");
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1), "event time");
+    *ms_out = (double)ms * (double)n_atomics / (double)(per_lane * lanes);
+    return PMC_OK;
 }
 
 }  // extern "C"

@@ -130,13 +130,58 @@ DEV float inv_cdf33(const float* __restrict__ cdf, float u, float lo, float hi)
     return lo + (hi - lo) * ((float)l + frac) * (1.0f / 32.0f);
 }
 
+// ------------------------------------------------------ plan descriptors
+
+// Geometry, tally and random-number key of the plan a particle belongs to:
+// kernel arguments for a single plan, an LDS table for a batch of plans.
+template <bool kMulti>
+struct Plans;
+
+template <>
+struct Plans<false> {
+    const KernelArgs& a;
+    const PlanDesc* pd;
+    DEV int nx(uint32_t) const { return a.single.nx; }
+    DEV int ny(uint32_t) const { return a.single.ny; }
+    DEV int nz(uint32_t) const { return a.single.nz; }
+    DEV float vs(uint32_t, int i) const { return a.single.vs[i]; }
+    DEV float ivs(uint32_t, int i) const { return a.single.ivs[i]; }
+    DEV const uint2* vox(uint32_t) const { return a.single.vox; }
+    DEV double* tally(uint32_t) const { return a.single.tally; }
+    DEV uint32_t key_lo(uint32_t) const { return a.single.key_lo; }
+    DEV uint32_t key_hi(uint32_t) const { return a.single.key_hi; }
+};
+
+template <>
+struct Plans<true> {
+    const KernelArgs& a;
+    const PlanDesc* pd;
+    DEV int nx(uint32_t p) const { return pd[p].nx; }
+    DEV int ny(uint32_t p) const { return pd[p].ny; }
+    DEV int nz(uint32_t p) const { return pd[p].nz; }
+    DEV float vs(uint32_t p, int i) const { return pd[p].vs[i]; }
+    DEV float ivs(uint32_t p, int i) const { return pd[p].ivs[i]; }
+    DEV const uint2* vox(uint32_t p) const { return pd[p].vox; }
+    DEV double* tally(uint32_t p) const { return pd[p].tally; }
+    DEV uint32_t key_lo(uint32_t p) const { return pd[p].key_lo; }
+    DEV uint32_t key_hi(uint32_t p) const { return pd[p].key_hi; }
+};
+
 // -------------------------------------------------------------- the kernel
 
+template <bool kMulti>
 __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
 {
     extern __shared__ float lds[];
     for (int i = threadIdx.x; i < a.blob_words; i += blockDim.x) lds[i] = a.blob[i];
+    if constexpr (kMulti) {
+        uint32_t* dst = reinterpret_cast<uint32_t*>(lds + a.pd_offset);
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(a.plans);
+        for (int i = threadIdx.x; i < a.n_plans * 16; i += blockDim.x) dst[i] = src[i];
+    }
     __syncthreads();
+    const PlanDesc* pds = reinterpret_cast<const PlanDesc*>(lds + a.pd_offset);
+    const Plans<kMulti> P{a, pds};
 
     const float* lnr_w = lds + kOffLnrWater;
     const float* lnr_o = lds + kOffLnrOwn;
@@ -159,12 +204,27 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
 
     // particle state
     float px = 0, py = 0, pz = 0, ux = 0, uy = 0, uz = 1, E = 0, mfp = 0, w = 0;
-    uint32_t uid_lo = 0, uid_hi = 0, k = 0, batch = 0;
+    uint32_t uid_lo = 0, uid_hi = 0, k = 0, batch = 0, plan = 0;
     int vx = 0, vy = 0, vz = 0;
     bool alive = false, pend = false;
 
+    // per-lane ledger and counters of the lane's current plan
     double acc_esc = 0.0, acc_neu = 0.0, acc_ovf = 0.0;
-    unsigned long long n_steps = 0, n_el = 0, n_ne = 0, n_short = 0;
+    uint32_t n_steps = 0, n_el = 0, n_ne = 0, n_short = 0, n_dep = 0;
+    auto flush = [&](uint32_t pl) {
+        double* L = a.ledger + 4 * pl;
+        unsigned long long* C = a.counters + 8 * pl;
+        if (acc_esc != 0.0) unsafeAtomicAdd(&L[0], acc_esc);
+        if (acc_neu != 0.0) unsafeAtomicAdd(&L[1], acc_neu);
+        if (acc_ovf != 0.0) unsafeAtomicAdd(&L[2], acc_ovf);
+        if (n_steps) atomicAdd(&C[0], (unsigned long long)n_steps);
+        if (n_el) atomicAdd(&C[1], (unsigned long long)n_el);
+        if (n_ne) atomicAdd(&C[2], (unsigned long long)n_ne);
+        if (n_short) atomicAdd(&C[3], (unsigned long long)n_short);
+        if (n_dep) atomicAdd(&C[4], (unsigned long long)n_dep);
+        acc_esc = acc_neu = acc_ovf = 0.0;
+        n_steps = n_el = n_ne = n_short = n_dep = 0;
+    };
     bool exhausted = false;
 
     for (;;) {
@@ -189,9 +249,19 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                         }
                         const float* sp = a.spots + 8 * lo;
                         const unsigned long long s0 = a.spot_start[lo], s1 = a.spot_start[lo + 1];
-                        uid_lo = (uint32_t)idx;
-                        uid_hi = (uint32_t)(idx >> 32);
-                        const uint4 r = philox(uid_lo, uid_hi, 0u, 0u, a.seed_lo, a.seed_hi);
+                        unsigned long long uid = idx;
+                        if constexpr (kMulti) {
+                            // uid within the plan: the spot's first index in its plan
+                            const uint32_t np = __float_as_uint(sp[6]);
+                            if (np != plan) {
+                                flush(plan);
+                                plan = np;
+                            }
+                            uid = (unsigned long long)__float_as_uint(sp[7]) + (idx - s0);
+                        }
+                        uid_lo = (uint32_t)uid;
+                        uid_hi = (uint32_t)(uid >> 32);
+                        const uint4 r = philox(uid_lo, uid_hi, 0u, 0u, P.key_lo(plan), P.key_hi(plan));
                         const float rr = fsqrt(-2.0f * fln(u01(r.x)));
                         const float ph = u01(r.y);
                         px = sp[0] + sp[3] * rr * fcos_rev(ph);
@@ -218,12 +288,19 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                         uid_lo = q[8 * c];
                         uid_hi = q[9 * c];
                         batch = q[10 * c];
-                        const uint4 r = philox(uid_lo, uid_hi, 0u, 0u, a.seed_lo, a.seed_hi);
+                        if constexpr (kMulti) {
+                            const uint32_t np = q[11 * c];
+                            if (np != plan) {
+                                flush(plan);
+                                plan = np;
+                            }
+                        }
+                        const uint4 r = philox(uid_lo, uid_hi, 0u, 0u, P.key_lo(plan), P.key_hi(plan));
                         mfp = -fln(u01(r.z));
                     }
                     k = 0;
-                    alive = locate_axis(px, ux, a.nx, vx) && locate_axis(py, uy, a.ny, vy) &&
-                            locate_axis(pz, uz, a.nz, vz);
+                    alive = locate_axis(px, ux, P.nx(plan), vx) && locate_axis(py, uy, P.ny(plan), vy) &&
+                            locate_axis(pz, uz, P.nz(plan), vz);
                     if (!alive) acc_esc += (double)w * (double)E;
                 }
             }
@@ -237,8 +314,8 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
         // ------------------------------------------------------------ step
         bool stepped = false, short_step = false;
         if (alive && !pend) {
-            const unsigned long long vi = ((unsigned long long)vz * a.ny + vy) * a.nx + vx;
-            const uint2 rec = a.vox[vi];
+            const unsigned long long vi = ((unsigned long long)vz * P.ny(plan) + vy) * P.nx(plan) + vx;
+            const uint2 rec = P.vox(plan)[vi];
             const float rho = __uint_as_float(rec.x);
             const int m = (int)rec.y;
             const float mf = mc[4 * m + 0];
@@ -271,15 +348,15 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
             {
                 float da;
                 if (ux != 0.f) {
-                    da = ((float)(ux > 0.f ? vx + 1 : vx) - px) * a.vs[0] * frcp(ux);
+                    da = ((float)(ux > 0.f ? vx + 1 : vx) - px) * P.vs(plan, 0) * frcp(ux);
                     if (da < d) { d = da; axis = 0; }
                 }
                 if (uy != 0.f) {
-                    da = ((float)(uy > 0.f ? vy + 1 : vy) - py) * a.vs[1] * frcp(uy);
+                    da = ((float)(uy > 0.f ? vy + 1 : vy) - py) * P.vs(plan, 1) * frcp(uy);
                     if (da < d) { d = da; axis = 1; }
                 }
                 if (uz != 0.f) {
-                    da = ((float)(uz > 0.f ? vz + 1 : vz) - pz) * a.vs[2] * frcp(uz);
+                    da = ((float)(uz > 0.f ? vz + 1 : vz) - pz) * P.vs(plan, 2) * frcp(uz);
                     if (da < d) { d = da; axis = 2; }
                 }
             }
@@ -291,7 +368,8 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
             if (s >= s_range) stop_here = true;
             if (stop_here) {
                 // range-limited: the proton stops in this voxel
-                unsafeAtomicAdd(&a.tally[vi * K + batch], (double)w * (double)E);
+                unsafeAtomicAdd(&P.tally(plan)[vi * K + batch], (double)w * (double)E);
+                ++n_dep;
                 alive = false;
             } else {
                 // mean loss from the range table (Eq. 2 water-equivalent path)
@@ -311,7 +389,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                 float de_mean = E - e1;
                 de_mean = de_mean > 0.f ? de_mean : 0.f;
                 const float emid = E - 0.5f * de_mean;
-                const uint4 r = philox(uid_lo, uid_hi, k, 1u, a.seed_lo, a.seed_hi);
+                const uint4 r = philox(uid_lo, uid_hi, k, 1u, P.key_lo(plan), P.key_hi(plan));
                 const float e_tot = emid + kMp;
                 const float ie_tot = frcp(e_tot);
                 const float pv = emid * (emid + 2.f * kMp) * ie_tot;      // p beta c
@@ -337,9 +415,9 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                 // direction to the crossed face plane and ends on it
                 const float h1 = u01(r.x) * s;
                 float h2 = s - h1;
-                px += h1 * ux * a.ivs[0];
-                py += h1 * uy * a.ivs[1];
-                pz += h1 * uz * a.ivs[2];
+                px += h1 * ux * P.ivs(plan, 0);
+                py += h1 * uy * P.ivs(plan, 1);
+                pz += h1 * uz * P.ivs(plan, 2);
                 const float da_before = axis == 0 ? ux : (axis == 1 ? uy : uz);
                 const int va = axis == 0 ? vx : (axis == 1 ? vy : vz);
                 const float face = (float)(da_before > 0.f ? va + 1 : va);
@@ -352,7 +430,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                     const float da = axis == 0 ? ux : (axis == 1 ? uy : uz);
                     const float pa = axis == 0 ? px : (axis == 1 ? py : pz);
                     if (da * da_before > 0.f) {
-                        const float vsa = axis == 0 ? a.vs[0] : (axis == 1 ? a.vs[1] : a.vs[2]);
+                        const float vsa = axis == 0 ? P.vs(plan, 0) : (axis == 1 ? P.vs(plan, 1) : P.vs(plan, 2));
                         const float l2 = (face - pa) * vsa / da;
                         if (l2 >= 0.f && l2 <= 2.f * h2) {
                             h2 = l2;
@@ -360,16 +438,17 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                         }
                     }
                 }
-                px += h2 * ux * a.ivs[0];
-                py += h2 * uy * a.ivs[1];
-                pz += h2 * uz * a.ivs[2];
+                px += h2 * ux * P.ivs(plan, 0);
+                py += h2 * uy * P.ivs(plan, 1);
+                pz += h2 * uz * P.ivs(plan, 2);
                 if (on_face) {
                     if (axis == 0) px = face;
                     else if (axis == 1) py = face;
                     else pz = face;
                 }
                 const float e_new = E - de;
-                unsafeAtomicAdd(&a.tally[vi * K + batch], (double)w * ((double)E - (double)e_new));
+                unsafeAtomicAdd(&P.tally(plan)[vi * K + batch], (double)w * ((double)E - (double)e_new));
+                ++n_dep;
                 mfp = nuc ? 0.f : fmaxf(mfp - sigma * s, 0.f);
                 E = e_new;
                 ++k;
@@ -377,10 +456,11 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                 if (E <= kECut || k >= kMaxSteps) {
                     // below the cut-off (or past the step cap that guards
                     // against non-terminating histories): deposit the rest
-                    unsafeAtomicAdd(&a.tally[vi * K + batch], (double)w * (double)E);
+                    unsafeAtomicAdd(&P.tally(plan)[vi * K + batch], (double)w * (double)E);
+                    ++n_dep;
                     alive = false;
-                } else if (!(locate_axis(px, ux, a.nx, vx) && locate_axis(py, uy, a.ny, vy) &&
-                             locate_axis(pz, uz, a.nz, vz))) {
+                } else if (!(locate_axis(px, ux, P.nx(plan), vx) && locate_axis(py, uy, P.ny(plan), vy) &&
+                             locate_axis(pz, uz, P.nz(plan), vz))) {
                     acc_esc += (double)w * (double)E;
                     alive = false;
                 } else if (nuc) {
@@ -388,8 +468,8 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                 }
             }
         }
-        n_steps += __popcll(__ballot(stepped));
-        n_short += __popcll(__ballot(stepped && short_step));
+        n_steps += stepped;
+        n_short += stepped && short_step;
 
         // ------------------------------------------- batched nuclear events
         const unsigned long long pm = __ballot(pend);
@@ -412,14 +492,14 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
         int sec_row = 0;
         if (pend) {
             pend = false;
-            const unsigned long long vi = ((unsigned long long)vz * a.ny + vy) * a.nx + vx;
-            const uint2 rec = a.vox[vi];
+            const unsigned long long vi = ((unsigned long long)vz * P.ny(plan) + vy) * P.nx(plan) + vx;
+            const uint2 rec = P.vox(plan)[vi];
             const int m = (int)rec.y;
             const float T = E;
             int gi;
             float gt;
             grid_pos(T, gi, gt);
-            const uint4 r3 = philox(uid_lo, uid_hi, ks, 3u, a.seed_lo, a.seed_hi);
+            const uint4 r3 = philox(uid_lo, uid_hi, ks, 3u, P.key_lo(plan), P.key_hi(plan));
             float pe[7], pn[7];
             float s_el = 0.f, s_ne = 0.f;
 #pragma unroll
@@ -449,7 +529,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                         if (target < cum) done = true;
                     }
                 }
-                const uint4 r4 = philox(uid_lo, uid_hi, ks, 4u, a.seed_lo, a.seed_hi);
+                const uint4 r4 = philox(uid_lo, uid_hi, ks, 4u, P.key_lo(plan), P.key_hi(plan));
                 const float* ec = a.elem + 8 * el;
                 ev_el = elastic;
                 ev_ne = !elastic;
@@ -500,14 +580,19 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                         rdz = uz;
                         rotate(rdx, rdy, rdz, cr, sr, phi + 0.5f);
                         const double resid = (double)T - (double)tn_f - (double)tr_f;
-                        if (resid != 0.0) unsafeAtomicAdd(&a.tally[vi2], (double)w * resid);
+                        if (resid != 0.0) {
+                            unsafeAtomicAdd(&P.tally(plan)[vi2], (double)w * resid);
+                            ++n_dep;
+                        }
                     } else {
-                        unsafeAtomicAdd(&a.tally[vi2], (double)w * ((double)T - (double)tn_f));
+                        unsafeAtomicAdd(&P.tally(plan)[vi2], (double)w * ((double)T - (double)tn_f));
+                        ++n_dep;
                     }
                     rotate(ux, uy, uz, ct, st, phi);
                     E = tn_f;
                     if (E <= kECut) {
-                        unsafeAtomicAdd(&a.tally[vi2], (double)w * (double)E);
+                        unsafeAtomicAdd(&P.tally(plan)[vi2], (double)w * (double)E);
+                        ++n_dep;
                         alive = false;
                     } else {
                         mfp = -fln(u01(r3.w));
@@ -530,7 +615,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                     for (int c = 0; c < 4; ++c) {
                         float ev = 0.f;
                         if (c < n) {
-                            const uint4 rc = philox(uid_lo, uid_hi, ks, 17u + c, a.seed_lo, a.seed_hi);
+                            const uint4 rc = philox(uid_lo, uid_hi, ks, 17u + c, P.key_lo(plan), P.key_hi(plan));
                             ev = inv_cdf33(xr, u01(rc.x), 0.f, 1.f) * T;
                         }
                         if (c == 0) ce0 = ev;
@@ -555,14 +640,15 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                     if (n > 2 && ce2 <= kECut) { local += ce2; ce2 = 0.f; }
                     if (n > 3 && ce3 <= kECut) { local += ce3; ce3 = 0.f; }
                     n_out = (ce0 > 0.f) + (ce1 > 0.f) + (ce2 > 0.f) + (ce3 > 0.f);
-                    unsafeAtomicAdd(&a.tally[vi * K + batch], (double)w * local);
+                    unsafeAtomicAdd(&P.tally(plan)[vi * K + batch], (double)w * local);
+                    ++n_dep;
                     acc_neu += (double)w * ((double)T - loc - carried);
                     alive = false;
                 }
             }
         }
-        n_el += __popcll(__ballot(ev_el));
-        n_ne += __popcll(__ballot(ev_ne));
+        n_el += ev_el;
+        n_ne += ev_ne;
         // append emitted protons to the next generation's queue
         {
             const unsigned long long b0 = __ballot(n_out & 1), b1 = __ballot(n_out & 2),
@@ -583,15 +669,15 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                         float dx = rdx, dy = rdy, dz = rdz;
                         const uint32_t jj = recoil ? 0u : (uint32_t)(c + 1);
                         if (!recoil) {
-                            const uint4 rc = philox(uid_lo, uid_hi, ks, 16u + jj, a.seed_lo, a.seed_hi);
+                            const uint4 rc = philox(uid_lo, uid_hi, ks, 16u + jj, P.key_lo(plan), P.key_hi(plan));
                             const float mu = inv_cdf33(a.sec_mu + 33 * sec_row, u01(rc.y), -1.f, 1.f);
                             dx = odx;
                             dy = ody;
                             dz = odz;
                             rotate(dx, dy, dz, mu, sqrtf(fmaxf(0.f, 1.f - mu * mu)), u01(rc.z));
                         }
-                        const uint4 cu = philox(uid_lo, uid_hi, ks, 0xC0000000u | jj, a.seed_lo,
-                                                a.seed_hi);
+                        const uint4 cu = philox(uid_lo, uid_hi, ks, 0xC0000000u | jj, P.key_lo(plan),
+                                                P.key_hi(plan));
                         if (slot < cap) {
                             uint32_t* q = a.q_out + slot;
                             q[0] = __float_as_uint(ox);
@@ -605,6 +691,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                             q[8 * cap] = cu.x;
                             q[9 * cap] = cu.y;
                             q[10 * cap] = batch;
+                            q[11 * cap] = plan;
                         } else {
                             acc_ovf += (double)w * (double)ev;
                         }
@@ -616,20 +703,56 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
     }
 
     // -------------------------------------------------- flush the ledger
-    for (int o = 32; o > 0; o >>= 1) {
-        acc_esc += __shfl_xor(acc_esc, o);
-        acc_neu += __shfl_xor(acc_neu, o);
-        acc_ovf += __shfl_xor(acc_ovf, o);
+    if constexpr (kMulti) {
+        flush(plan);
+    } else {
+        for (int o = 32; o > 0; o >>= 1) {
+            acc_esc += __shfl_xor(acc_esc, o);
+            acc_neu += __shfl_xor(acc_neu, o);
+            acc_ovf += __shfl_xor(acc_ovf, o);
+            n_steps += __shfl_xor(n_steps, o);
+            n_el += __shfl_xor(n_el, o);
+            n_ne += __shfl_xor(n_ne, o);
+            n_short += __shfl_xor(n_short, o);
+            n_dep += __shfl_xor(n_dep, o);
+        }
+        if (lane == 0) flush(0);
     }
-    if (lane == 0) {
-        if (acc_esc != 0.0) unsafeAtomicAdd(&a.ledger[0], acc_esc);
-        if (acc_neu != 0.0) unsafeAtomicAdd(&a.ledger[1], acc_neu);
-        if (acc_ovf != 0.0) unsafeAtomicAdd(&a.ledger[2], acc_ovf);
-        atomicAdd(&a.counters[0], n_steps);
-        if (n_el) atomicAdd(&a.counters[1], n_el);
-        if (n_ne) atomicAdd(&a.counters[2], n_ne);
-        if (n_short) atomicAdd(&a.counters[3], n_short);
+}
+
+// Achievable-rate probe for the tally atomics: every lane walks straight
+// tracks along z from lateral starts inside the central 40x40-voxel window of
+// the loaded grid (the footprint of a treatment field), adding 0 into
+// tally[voxel][lane % K] once per voxel, the same FP64 atomic the transport
+// issues per step.  Adding 0 leaves the tally unchanged.
+__global__ void __launch_bounds__(256) atomic_probe_kernel(double* tally, int nx, int ny, int nz,
+                                                           int K, unsigned long long per_lane)
+{
+    const unsigned gid = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t s = 2654435761u * gid + 12345u;
+    const int b = (int)(gid % (unsigned)K);
+    const int wx = nx < 40 ? nx : 40, wy = ny < 40 ? ny : 40;
+    const int x0 = (nx - wx) / 2, y0 = (ny - wy) / 2;
+    int x = 0, y = 0, z = nz;
+    for (unsigned long long i = 0; i < per_lane; ++i) {
+        if (z >= nz) {
+            s = s * 1664525u + 1013904223u;
+            x = x0 + (int)((s >> 8) % (uint32_t)wx);
+            s = s * 1664525u + 1013904223u;
+            y = y0 + (int)((s >> 8) % (uint32_t)wy);
+            z = 0;
+        }
+        const unsigned long long v = ((unsigned long long)z * ny + y) * nx + x;
+        unsafeAtomicAdd(&tally[v * K + b], 0.0);
+        ++z;
     }
+}
+
+hipError_t launch_atomic_probe(double* tally, int nx, int ny, int nz, int K, int grid,
+                               unsigned long long per_lane, hipStream_t st)
+{
+    hipLaunchKernelGGL(atomic_probe_kernel, dim3(grid), dim3(256), 0, st, tally, nx, ny, nz, K, per_lane);
+    return hipGetLastError();
 }
 
 // dose statistics over the K groups: total, variance of the total, and the
@@ -670,29 +793,34 @@ __global__ void zero_kernel(unsigned long long* __restrict__ p, unsigned long lo
 
 // ------------------------------------------------------------- launchers
 
-hipError_t launch_transport(const KernelArgs& a, int grid, int block, size_t lds_bytes,
+hipError_t launch_transport(const KernelArgs& a, bool multi, int grid, int block, size_t lds_bytes,
                             hipStream_t s)
 {
-    hipLaunchKernelGGL(transport_kernel, dim3(grid), dim3(block), lds_bytes, s, a);
+    if (multi) hipLaunchKernelGGL(transport_kernel<true>, dim3(grid), dim3(block), lds_bytes, s, a);
+    else hipLaunchKernelGGL(transport_kernel<false>, dim3(grid), dim3(block), lds_bytes, s, a);
     return hipGetLastError();
 }
 
-hipError_t transport_max_block(int* max_threads)
+hipError_t transport_max_block(bool multi, int* max_threads)
 {
     hipFuncAttributes attr;
-    hipError_t e = hipFuncGetAttributes(&attr, (const void*)transport_kernel);
+    const void* f = multi ? (const void*)transport_kernel<true> : (const void*)transport_kernel<false>;
+    hipError_t e = hipFuncGetAttributes(&attr, f);
     if (e == hipSuccess) *max_threads = attr.maxThreadsPerBlock;
     return e;
 }
 
-hipError_t transport_occupancy(int block, size_t lds_bytes, int* blocks_per_cu)
+hipError_t transport_occupancy(bool multi, int block, size_t lds_bytes, int* blocks_per_cu)
 {
+    const void* f = multi ? (const void*)transport_kernel<true> : (const void*)transport_kernel<false>;
     if (lds_bytes > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void*)transport_kernel,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
         if (e != hipSuccess) return e;
     }
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel, block,
+    if (multi)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<true>, block,
+                                                            lds_bytes);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<false>, block,
                                                         lds_bytes);
 }
 

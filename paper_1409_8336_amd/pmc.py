@@ -22,7 +22,8 @@ PMC_NO_STRAGGLE, PMC_NO_MCS, PMC_NO_NUCLEAR = 1, 2, 4
 # every symbol include/pmc.h declares
 EXPORTS = ("pmc_default_params", "pmc_create", "pmc_destroy", "pmc_last_error",
            "pmc_load_physics", "pmc_load_geometry", "pmc_run_spots", "pmc_run_spots_dev",
-           "pmc_inspect_tables", "pmc_version")
+           "pmc_inspect_tables", "pmc_atomic_probe", "pmc_load_geometry_slot", "pmc_run_plans",
+           "pmc_version")
 
 
 class PMCError(RuntimeError):
@@ -60,9 +61,16 @@ class pmc_summary(C.Structure):
                 ("neutral", C.c_double), ("overflow", C.c_double), ("histories", C.c_uint64),
                 ("steps", C.c_uint64), ("secondaries", C.c_uint64), ("n_elastic", C.c_uint64),
                 ("n_nonelastic", C.c_uint64), ("n_overflow", C.c_uint64),
-                ("n_short_steps", C.c_uint64), ("total_weight", C.c_double), ("device_ms", C.c_double),
+                ("n_short_steps", C.c_uint64), ("tally_atomics", C.c_uint64),
+                ("total_weight", C.c_double), ("device_ms", C.c_double),
                 ("transport_ms", C.c_double), ("generations", C.c_int32),
                 ("reserved", C.c_int32)]
+
+
+class pmc_plan(C.Structure):
+    _fields_ = [("geometry_id", C.c_int32), ("n_spots", C.c_int32), ("spots", C.c_void_p),
+                ("n_histories", C.c_uint64), ("d_dose", C.c_void_p), ("d_var", C.c_void_p),
+                ("summary", C.c_void_p)]
 
 
 _lib = None
@@ -93,6 +101,10 @@ def lib():
         L.pmc_run_spots.argtypes = [vp, vp, i32, u64, u64, vp, vp, C.POINTER(pmc_summary)]
         L.pmc_run_spots_dev.argtypes = [vp, vp, i32, u64, u64, vp, vp, vp, C.POINTER(pmc_summary)]
         L.pmc_inspect_tables.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.pmc_atomic_probe.argtypes = [vp, u64, vp, C.POINTER(C.c_double)]
+        L.pmc_load_geometry_slot.argtypes = [vp, C.POINTER(C.c_int), vp, i32, i32, i32, C.c_float,
+                                             C.c_float, C.c_float, C.POINTER(pmc_material_table)]
+        L.pmc_run_plans.argtypes = [vp, C.POINTER(pmc_plan), i32, u64, vp]
         L.pmc_version.restype = C.c_char_p
         for name in EXPORTS:
             if name not in ("pmc_last_error", "pmc_version"):
@@ -147,16 +159,59 @@ def pmc_load_physics(ctx, nd: dict):
 def pmc_load_geometry(ctx, hu, voxel_cm, mt: dict):
     hu = np.ascontiguousarray(hu, dtype=np.int16)
     nz, ny, nx = hu.shape
-    arrs = [np.ascontiguousarray(mt["hu_lo"], dtype=np.int16),
+    arrs = _material_arrays(mt)
+    t = pmc_material_table(len(arrs[0]), *[a.ctypes.data for a in arrs])
+    _check(ctx, lib().pmc_load_geometry(ctx, _ptr(hu), nx, ny, nz, float(voxel_cm[0]),
+                                        float(voxel_cm[1]), float(voxel_cm[2]), C.byref(t)))
+    return (nz, ny, nx)
+
+
+def _material_arrays(mt):
+    return [np.ascontiguousarray(mt["hu_lo"], dtype=np.int16),
             np.ascontiguousarray(mt["rho_lo"], dtype=np.float32),
             np.ascontiguousarray(mt["rho_hi"], dtype=np.float32),
             np.ascontiguousarray(mt["mass_frac"], dtype=np.float32),
             np.ascontiguousarray(mt["i_ev"], dtype=np.float32),
             np.ascontiguousarray(mt["own_table"], dtype=np.int32)]
+
+
+def pmc_load_geometry_slot(ctx, hu, voxel_cm, mt: dict) -> int:
+    """Load a further geometry; returns its slot id."""
+    hu = np.ascontiguousarray(hu, dtype=np.int16)
+    nz, ny, nx = hu.shape
+    arrs = _material_arrays(mt)
     t = pmc_material_table(len(arrs[0]), *[a.ctypes.data for a in arrs])
-    _check(ctx, lib().pmc_load_geometry(ctx, _ptr(hu), nx, ny, nz, float(voxel_cm[0]),
-                                        float(voxel_cm[1]), float(voxel_cm[2]), C.byref(t)))
-    return (nz, ny, nx)
+    gid = C.c_int()
+    _check(ctx, lib().pmc_load_geometry_slot(ctx, C.byref(gid), _ptr(hu), nx, ny, nz,
+                                             float(voxel_cm[0]), float(voxel_cm[1]),
+                                             float(voxel_cm[2]), C.byref(t)))
+    return gid.value
+
+
+def pmc_run_plans(ctx, plans, seed, stream=None):
+    """Batched run.  plans: list of dicts with geometry_id, spots, n_histories,
+    d_dose (and optional d_var) torch float64 device tensors.  Returns the
+    per-plan summaries."""
+    import torch
+    arr = (pmc_plan * len(plans))()
+    keep, sums = [], []
+    for i, p in enumerate(plans):
+        sp = _spots(p["spots"])
+        keep.append(sp)
+        d = p["d_dose"]
+        if d.dtype != torch.float64 or not d.is_cuda or not d.is_contiguous():
+            raise ValueError("d_dose must be a contiguous float64 device tensor")
+        v = p.get("d_var")
+        sm = pmc_summary()
+        sums.append(sm)
+        arr[i] = pmc_plan(int(p["geometry_id"]), len(sp), sp.ctypes.data, int(p["n_histories"]),
+                          d.data_ptr(), v.data_ptr() if v is not None else None,
+                          C.addressof(sm))
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+    _check(ctx, lib().pmc_run_plans(ctx, arr, len(plans), int(seed), C.c_void_p(handle)))
+    return [summary_dict(s) for s in sums]
 
 
 def summary_dict(s: pmc_summary) -> dict:
@@ -211,6 +266,17 @@ def pmc_inspect_tables(ctx):
     _check(ctx, lib().pmc_inspect_tables(ctx, _ptr(lnr_w), _ptr(lnr_o), _ptr(sig), _ptr(mat),
                                          C.byref(n)))
     return {"lnr_water": lnr_w, "lnr_own": lnr_o, "sigma_per_g": sig, "material": mat}
+
+
+def pmc_atomic_probe(ctx, n_atomics, stream=None):
+    """Device milliseconds for n_atomics tally-pattern FP64 atomics."""
+    ms = C.c_double()
+    handle = None
+    if stream is not None:
+        handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+    _check(ctx, lib().pmc_atomic_probe(ctx, int(n_atomics), C.c_void_p(handle) if handle else None,
+                                       C.byref(ms)))
+    return ms.value
 
 
 class Engine:

@@ -338,3 +338,41 @@ def config_field(n_histories=10_000_000):
     spots = spot_field((25.6, 25.6), seed=4)
     return {"hu": hu, "voxel_cm": (0.2, 0.2, 0.2), "spots": spots,
             "n_histories": n_histories, "seed": 1}
+
+
+def random_field(rng, n_spots, center_xy, e_lo=70.0, e_hi=230.0, pitch_cm=0.5):
+    """A field of about n_spots spots: a seeded number of energy layers in
+    [e_lo, e_hi], each a hexagonal patch of equal size, lognormal weights."""
+    n_layers = int(rng.integers(4, 21))
+    per = max(1, int(round(n_spots / n_layers)))
+    pts = hex_points(per, pitch_cm)
+    lo = rng.uniform(e_lo, 0.5 * (e_lo + e_hi))
+    hi = rng.uniform(lo + 10.0, e_hi)
+    rows = []
+    for l in range(n_layers):
+        e = lo + (hi - lo) * l / max(1, n_layers - 1)
+        sig = 0.1 * (6.0 - 3.0 * (e - e_lo) / (e_hi - e_lo))
+        for (x, y) in pts:
+            rows.append([center_xy[0] + x, center_xy[1] + y, e, sig, sig, 0.0])
+    spots = np.array(rows, dtype=np.float64)
+    spots[:, 5] = rng.lognormal(0.0, 0.5, size=len(rows))
+    return _f32(spots)
+
+
+def plan_set(n_plans=16, seed=100, hist_scale=1.0, max_grid=(256, 256, 200), min_grid=(96, 96, 96)):
+    """Uneven multi-plan batch: per plan a CT grid between min_grid and
+    max_grid (2 mm voxels, the ct_phantom recipe with counts scaled by
+    volume), 200-3000 spots (uniform) and 1e6-1e7 histories (log-uniform),
+    times hist_scale.  Plan i uses seed + i."""
+    plans = []
+    for i in range(n_plans):
+        rng = np.random.default_rng(seed + i)
+        dims = [int(rng.integers(lo, hi + 1)) for lo, hi in zip(min_grid, max_grid)]
+        nx, ny, nz = dims
+        hu = scaled_ct_phantom(nx, ny, nz, seed=seed + i)
+        n_spots = int(rng.integers(200, 3001))
+        spots = random_field(rng, n_spots, (0.1 * nx, 0.1 * ny))
+        n_hist = int(round(10 ** rng.uniform(6.0, 7.0) * hist_scale))
+        plans.append({"hu": hu, "voxel_cm": (0.2, 0.2, 0.2), "spots": spots,
+                      "n_histories": max(1, n_hist)})
+    return plans
