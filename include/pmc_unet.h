@@ -1,0 +1,110 @@
+/*
+ * pmc_unet.h - C ABI of the learned Monte Carlo dose denoiser (gfx950).
+ *
+ * The transport of pmc.h estimates dose with statistical noise that falls as
+ * 1/sqrt(histories) (arXiv:1409.8336, Sec. II.B.2 and Eq. 5).  This library
+ * part trains and runs a 3-D U-Net that maps a low-history dose (plus the
+ * density map) to an estimate of the high-history dose, so that a plan can be
+ * evaluated from far fewer histories; plain Monte Carlo remains the fallback
+ * and the judge of its error (gamma index, Low et al., as used in the paper's
+ * Sec. II.D).  It has no counterpart in the paper.
+ *
+ * Network: 4 levels (16/32/64/128 channels), one 3x3x3 convolution + ReLU per
+ * level on the way down (2x2x2 average pooling between levels) and one per
+ * level on the way up (nearest 2x upsampling, concatenation with the skip),
+ * then a 1x1x1 head added to the normalised input dose (residual):
+ *   out = dose + scale * head(features),  scale = max(dose).
+ * Input channels: dose/scale and density/2.  BF16 activations and weights on
+ * the matrix cores with FP32 accumulation; FP32 master weights, Adam.
+ *
+ * Tensors are [n][d][h][w] float32 device arrays (w fastest); d, h and w must
+ * be multiples of 8.  Every call is stream-ordered on hip_stream (NULL = the
+ * null stream) and returns after enqueueing unless stated otherwise.
+ * Parameter vector (pmc_unet_get_params): for each convolution in the order
+ * enc1(2->16, input padded to 8 channels), enc2(16->32), enc3(32->64),
+ * enc4(64->128), dec3(192->64), dec2(96->32), dec1(48->16): weights
+ * [Cout][Kp] with Kp = 27*Cin rounded up to 32 (index tap*Cin + ci, tap =
+ * (kz*3+ky)*3+kx, zero padding), then bias [Cout]; finally the head weights
+ * [16] and bias [1].
+ */
+#ifndef PMC_UNET_H
+#define PMC_UNET_H
+
+#include <stdint.h>
+
+#include "pmc.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pmc_unet pmc_unet;
+
+/* Create a network for inputs of shape [n][d][h][w] on HIP device `device`,
+ * weights initialised from `seed` (He-normal convolutions, zero biases, head
+ * 1e-3).  Errors: PMC_ERR_ARG (shape not multiples of 8, n < 1),
+ * PMC_ERR_NOMEM, PMC_ERR_DEVICE. */
+pmc_status pmc_unet_create(pmc_unet** out, int device, int n, int d, int h, int w, uint64_t seed);
+pmc_status pmc_unet_destroy(pmc_unet* u);
+const char* pmc_unet_last_error(const pmc_unet* u);
+
+/* Number of float32 parameters (layout in the header comment). */
+pmc_status pmc_unet_param_count(const pmc_unet* u, int64_t* count);
+/* Copy the FP32 master parameters to / from host memory (count floats);
+ * set_params also refreshes the BF16 weight copies.  Synchronous. */
+pmc_status pmc_unet_get_params(pmc_unet* u, float* host_out);
+pmc_status pmc_unet_set_params(pmc_unet* u, const float* host_in);
+
+/* Denoise: d_out = network(d_dose, d_density). */
+pmc_status pmc_unet_forward(pmc_unet* u, const float* d_dose, const float* d_density, float* d_out,
+                            void* hip_stream);
+
+/* Forward, mean-squared error against d_target in units of max(d_dose), and
+ * backward; gradients are added to the gradient buffer, *loss_out (host,
+ * may be NULL) receives the loss.  Synchronous when loss_out != NULL. */
+pmc_status pmc_unet_backward(pmc_unet* u, const float* d_dose, const float* d_density,
+                             const float* d_target, double* loss_out, void* hip_stream);
+
+/* Gradient buffer to host (count floats, synchronous) / reset to zero. */
+pmc_status pmc_unet_get_grads(pmc_unet* u, float* host_out);
+pmc_status pmc_unet_zero_grads(pmc_unet* u, void* hip_stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with learning rate lr on
+ * the accumulated gradients, which it then resets to zero. */
+pmc_status pmc_unet_adam_step(pmc_unet* u, float lr, void* hip_stream);
+
+/* ---- single layers, for kernel tests (device pointers, BF16 as uint16) ----
+ * x: [n][d][h][w][cin] channels-last; w: [cout][Kp] (see above); y:
+ * [n][d][h][w][cout].  cin, cout multiples of 8, at least 8; the Kp - 27*cin
+ * padding columns of w must be zero.
+ * forward: y = conv(x, w) + bias (bias may be NULL), ReLU when relu != 0.
+ * backward_data: dx = conv^T(dy, w) (workspace allocated internally).
+ * backward_weight: dw[cout][Kp] (float32) += sum over voxels of dy (x) x. */
+pmc_status pmc_nn_conv3d_forward(const uint16_t* d_x, const uint16_t* d_w, const float* d_bias,
+                                 uint16_t* d_y, int n, int d, int h, int w, int cin, int cout,
+                                 int relu, void* hip_stream);
+pmc_status pmc_nn_conv3d_backward_data(const uint16_t* d_dy, const uint16_t* d_w, uint16_t* d_dx,
+                                       int n, int d, int h, int w, int cin, int cout,
+                                       void* hip_stream);
+pmc_status pmc_nn_conv3d_backward_weight(const uint16_t* d_x, const uint16_t* d_dy, float* d_dw,
+                                         int n, int d, int h, int w, int cin, int cout,
+                                         void* hip_stream);
+
+/* 3-D gamma index (global dose difference, distance to agreement), Low et
+ * al.: for every reference voxel with ref >= cutoff_frac * max(ref),
+ * gamma = min over points p of the evaluated distribution (trilinear, on a
+ * cubic grid of spacing step_cm within search_cm of the voxel centre) of
+ * sqrt(|p|^2/dta_cm^2 + (eval(p) - ref)^2 / (dose_frac * max(ref))^2).
+ * ref and eval: [nz][ny][nx] float64 device arrays; d_gamma (float32, may be
+ * NULL) receives gamma (or -1 below the cutoff).  *pass_rate (host) = the
+ * fraction of evaluated voxels with gamma <= 1; *n_eval their count.
+ * Synchronous. */
+pmc_status pmc_gamma_index(const double* d_ref, const double* d_eval, int nx, int ny, int nz,
+                           float dx_cm, float dy_cm, float dz_cm, float dose_frac, float dta_cm,
+                           float cutoff_frac, float search_cm, float step_cm, float* d_gamma,
+                           double* pass_rate, int64_t* n_eval, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PMC_UNET_H */

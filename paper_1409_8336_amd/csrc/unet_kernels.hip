@@ -1,0 +1,558 @@
+// Kernels of the 3-D U-Net dose denoiser (gfx950): BF16 activations and
+// weights on the matrix cores (v_mfma_f32_16x16x32_bf16) with FP32
+// accumulation, channels-last tensors [n][z][y][x][c].
+//
+// Convolutions are 3x3x3, stride 1, zero padding 1, as implicit GEMMs:
+//   forward       out[v][co]  = sum_{tap,ci} in[v+off(tap)][ci] * W[co][tap*Cin+ci]
+//   data grad     din[v][ci]  = forward of dout with W'[ci][tap'*Cout+co] = W[co][(26-tap')*Cin+ci]
+//   weight grad   dW[co][tap*Cin+ci] = sum_v dout[v][co] * in[v+off(tap)][ci]
+// MFMA operand layout (16x16x32, verified on gfx950): lane l holds
+// A[l%16][8(l/16)..+7], B[8(l/16)..+7][l%16]; the result D[4(l/16)+i][l%16].
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace pmc {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+#define DEV __device__ __forceinline__
+
+DEV float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// round-to-nearest-even float -> bf16 bits (finite inputs)
+DEV uint16_t f2bf(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    const uint32_t r = u + 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(r >> 16);
+}
+
+// ------------------------------------------------------------ convolution
+
+// One workgroup: 64 consecutive x positions of one (n, z, y) row (16 per
+// wave) and 16*NB output channels starting at blockIdx.y*16*NB.
+template <int NB>
+__global__ void __launch_bounds__(256) conv3d_fwd_kernel(const uint16_t* __restrict__ in,
+                                                         const uint16_t* __restrict__ wt,
+                                                         const float* __restrict__ bias,
+                                                         uint16_t* __restrict__ out, int D, int H,
+                                                         int W, int Cin, int Cout, int Kp, int relu)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nz = blockIdx.z;               // n * D + z
+    const int z = nz % D;
+    const int y = blockIdx.y % H;
+    const int cg = blockIdx.y / H;
+    const int x0 = blockIdx.x * 64 + wave * 16;
+    const int co0 = cg * 16 * NB;
+    const int K = 27 * Cin;
+    const int m = lane & 15, g = lane >> 4;
+    const int xa = x0 + m;                   // voxel of this lane's A row
+    const size_t plane = (size_t)H * W;
+    const size_t nbase = (size_t)(nz - z) * plane;   // n * D * H * W
+    f32x4 acc[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    for (int kc = 0; kc < Kp; kc += 32) {
+        const int kk = kc + 8 * g;
+        bf16x8 a = (bf16x8){};
+        if (kk < K && xa < W) {
+            const int tap = kk / Cin, ci = kk - tap * Cin;
+            const int kz = tap / 9, ky = (tap / 3) % 3, kx = tap % 3;
+            const int zz = z + kz - 1, yy = y + ky - 1, xx = xa + kx - 1;
+            if (zz >= 0 && zz < D && yy >= 0 && yy < H && xx >= 0 && xx < W) {
+                const size_t v = nbase + (size_t)zz * plane + (size_t)yy * W + xx;
+                a = *reinterpret_cast<const bf16x8*>(in + v * Cin + ci);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int co = co0 + 16 * j + m;
+            bf16x8 b = (bf16x8){};
+            if (co < Cout) b = *reinterpret_cast<const bf16x8*>(wt + (size_t)co * Kp + kk);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        const int co = co0 + 16 * j + m;
+        if (co >= Cout) continue;
+        const float bv = bias ? bias[co] : 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int x = x0 + 4 * g + i;
+            if (x >= W) continue;
+            float v = acc[j][i] + bv;
+            if (relu) v = v > 0.f ? v : 0.f;
+            const size_t vox = nbase + (size_t)z * plane + (size_t)y * W + x;
+            out[vox * Cout + co] = f2bf(v);
+        }
+    }
+}
+
+// W'[ci][tap'*Cout + co] = W[co][(26 - tap')*Cin + ci]  (row length Kp')
+__global__ void flip_weights_kernel(const uint16_t* __restrict__ w, uint16_t* __restrict__ wf, int Cin,
+                                    int Cout, int Kp, int Kpf)
+{
+    const int total = Cin * Kpf;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+        const int ci = i / Kpf, kk = i - ci * Kpf;
+        uint16_t v = 0;
+        if (kk < 27 * Cout) {
+            const int tp = kk / Cout, co = kk - tp * Cout;
+            v = w[(size_t)co * Kp + (26 - tp) * Cin + ci];
+        }
+        wf[i] = v;
+    }
+}
+
+// Weight gradient.  Workgroup = (a chunk of rows) x (kz) x (32-channel input
+// block) x (64-channel output block).  For each 32-voxel x segment the
+// output-gradient tile and the 3 input rows of kz (ky = 0..2) are staged in
+// LDS transposed (channel-major), then each wave accumulates 16x16 tiles of
+// dW[co][(kz*9+ky*3+kx)*Cin + ci] with K = 32 voxels per MFMA, and adds its
+// partial sums to the FP32 gradient with atomics at the end.
+constexpr int kWgTiles = 18;   // (4 co tiles x 9 (ky,kx) x 2 ci tiles) / 4 waves
+__global__ void __launch_bounds__(256) conv3d_wgrad_kernel(const uint16_t* __restrict__ in,
+                                                           const uint16_t* __restrict__ dout,
+                                                           float* __restrict__ dw, int N, int D,
+                                                           int H, int W, int Cin, int Cout, int Kp,
+                                                           int rows_per_block)
+{
+    __shared__ uint16_t sdo[64][40];        // [co][x] (32 used, padded)
+    __shared__ uint16_t sin[3][32][40];     // [ky][ci][x+1] (34 used, padded)
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m = lane & 15, g = lane >> 4;
+    const int n_ci_blk = (Cin + 31) / 32;
+    const int kz = blockIdx.y % 3;
+    const int cib = (blockIdx.y / 3) % n_ci_blk;
+    const int cob = blockIdx.y / (3 * n_ci_blk);
+    const int ci0 = cib * 32, co0 = cob * 64;
+    const int total_rows = N * D * H;
+    const int row0 = blockIdx.x * rows_per_block;
+    f32x4 acc[kWgTiles];
+#pragma unroll
+    for (int t = 0; t < kWgTiles; ++t) acc[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    // tile t of this wave: global tile id q = wave * 18 + t over (co tile 0..3) x (ky,kx 0..8) x (ci tile 0..1)
+    for (int r = row0; r < row0 + rows_per_block && r < total_rows; ++r) {
+        const int y = r % H, nz = r / H, z = nz % D;
+        const size_t plane = (size_t)H * W;
+        const size_t nbase = (size_t)(nz - z) * plane;
+        const int zz = z + kz - 1;
+        for (int xb = 0; xb < W; xb += 32) {
+            __syncthreads();
+            // stage dout[v][co0..co0+63] for x in [xb, xb+32)
+            for (int i = threadIdx.x; i < 64 * 32; i += 256) {
+                const int co = i & 63, x = i >> 6;
+                uint16_t v = 0;
+                if (co0 + co < Cout && xb + x < W)
+                    v = dout[(nbase + (size_t)z * plane + (size_t)y * W + xb + x) * Cout + co0 + co];
+                sdo[co][x] = v;
+            }
+            // stage in rows (zz, y+ky-1) at x in [xb-1, xb+33), channels ci0..ci0+31
+            for (int i = threadIdx.x; i < 3 * 32 * 34; i += 256) {
+                const int ci = i & 31, rest = i >> 5;
+                const int xo = rest % 34, ky = rest / 34;
+                const int yy = y + ky - 1, xx = xb + xo - 1;
+                uint16_t v = 0;
+                if (ci0 + ci < Cin && zz >= 0 && zz < D && yy >= 0 && yy < H && xx >= 0 && xx < W)
+                    v = in[(nbase + (size_t)zz * plane + (size_t)yy * W + xx) * Cin + ci0 + ci];
+                sin[ky][ci][xo] = v;
+            }
+            __syncthreads();
+            // A operand: dout^T rows = co, K = x  (lane: co = m, x = 8g..8g+7)
+#pragma unroll
+            for (int t = 0; t < kWgTiles; ++t) {
+                const int q = wave * kWgTiles + t;
+                const int ct = q / 18, rem = q % 18;
+                const int kyx = rem >> 1, cit = rem & 1;
+                const int ky = kyx / 3, kx = kyx % 3;
+                bf16x8 a, b;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const uint16_t av = sdo[ct * 16 + m][8 * g + e];
+                    const uint16_t bv = sin[ky][cit * 16 + m][8 * g + e + kx];
+                    a[e] = __builtin_bit_cast(__bf16, av);
+                    b[e] = __builtin_bit_cast(__bf16, bv);
+                }
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < kWgTiles; ++t) {
+        const int q = wave * kWgTiles + t;
+        const int ct = q / 18, rem = q % 18;
+        const int kyx = rem >> 1, cit = rem & 1;
+        const int tap = kz * 9 + kyx;
+        const int ci = ci0 + cit * 16 + m;
+        if (ci >= Cin) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int co = co0 + ct * 16 + 4 * g + i;
+            if (co < Cout && acc[t][i] != 0.f) atomicAdd(&dw[(size_t)co * Kp + tap * Cin + ci], acc[t][i]);
+        }
+    }
+}
+
+// ------------------------------------------------------------ elementwise
+
+// dy *= (y > 0)   (ReLU backward through the stored output)
+__global__ void relu_bwd_kernel(uint16_t* __restrict__ dy, const uint16_t* __restrict__ y, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        if (!(bf2f(y[i]) > 0.f)) dy[i] = 0;
+}
+
+// db[c] += sum_v dy[v][c]
+__global__ void bias_grad_kernel(const uint16_t* __restrict__ dy, float* __restrict__ db, size_t nvox, int C)
+{
+    const int c = threadIdx.x % C;
+    const int lanes_per_c = blockDim.x / C;
+    const int sub = threadIdx.x / C;
+    if (sub >= lanes_per_c) return;
+    float s = 0.f;
+    for (size_t v = (size_t)blockIdx.x * lanes_per_c + sub; v < nvox; v += (size_t)gridDim.x * lanes_per_c)
+        s += bf2f(dy[v * C + c]);
+    atomicAdd(&db[c], s);
+}
+
+// 2x2x2 average pooling, channels-last
+__global__ void pool_fwd_kernel(const uint16_t* __restrict__ in, uint16_t* __restrict__ out, int N, int D,
+                                int H, int W, int C)
+{
+    const int Do = D / 2, Ho = H / 2, Wo = W / 2;
+    const size_t total = (size_t)N * Do * Ho * Wo * C;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        size_t r = i / C;
+        const int x = (int)(r % Wo); r /= Wo;
+        const int y = (int)(r % Ho); r /= Ho;
+        const int z = (int)(r % Do);
+        const int n = (int)(r / Do);
+        float s = 0.f;
+        for (int dz = 0; dz < 2; ++dz)
+            for (int dy = 0; dy < 2; ++dy)
+                for (int dx = 0; dx < 2; ++dx)
+                    s += bf2f(in[((((size_t)n * D + 2 * z + dz) * H + 2 * y + dy) * W + 2 * x + dx) * C + c]);
+        out[i] = f2bf(0.125f * s);
+    }
+}
+
+// d_in[v][c] = add[v][c] + d_out[parent(v)][c] / 8   (add may be NULL)
+__global__ void pool_bwd_kernel(const uint16_t* __restrict__ dout, const uint16_t* __restrict__ add,
+                                uint16_t* __restrict__ din, int N, int D, int H, int W, int C)
+{
+    const size_t total = (size_t)N * D * H * W * C;
+    const int Ho = H / 2, Wo = W / 2, Do = D / 2;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        size_t r = i / C;
+        const int x = (int)(r % W); r /= W;
+        const int y = (int)(r % H); r /= H;
+        const int z = (int)(r % D);
+        const int n = (int)(r / D);
+        const size_t p = ((((size_t)n * Do + z / 2) * Ho + y / 2) * Wo + x / 2) * C + c;
+        float v = 0.125f * bf2f(dout[p]);
+        if (add) v += bf2f(add[i]);
+        din[i] = f2bf(v);
+    }
+}
+
+// cat[v] = (coarse[parent(v)][0..Cc), skip[v][0..Cs))  -- nearest 2x upsampling + concat
+__global__ void up_concat_kernel(const uint16_t* __restrict__ coarse, const uint16_t* __restrict__ skip,
+                                 uint16_t* __restrict__ cat, int N, int D, int H, int W, int Cc, int Cs)
+{
+    const int C = Cc + Cs;
+    const size_t total = (size_t)N * D * H * W * C;
+    const int Ho = H / 2, Wo = W / 2, Do = D / 2;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        const size_t v = i / C;
+        size_t r = v;
+        const int x = (int)(r % W); r /= W;
+        const int y = (int)(r % H); r /= H;
+        const int z = (int)(r % D);
+        const int n = (int)(r / D);
+        uint16_t val;
+        if (c < Cc) val = coarse[((((size_t)n * Do + z / 2) * Ho + y / 2) * Wo + x / 2) * Cc + c];
+        else val = skip[v * Cs + (c - Cc)];
+        cat[i] = val;
+    }
+}
+
+// backward of up_concat: d_coarse[p][c] = sum over the 8 children of dcat[v][c];
+// d_skip[v][c] = dcat[v][Cc + c]
+__global__ void up_concat_bwd_coarse_kernel(const uint16_t* __restrict__ dcat, uint16_t* __restrict__ dcoarse,
+                                            int N, int D, int H, int W, int Cc, int Cs)
+{
+    const int C = Cc + Cs;
+    const int Do = D / 2, Ho = H / 2, Wo = W / 2;
+    const size_t total = (size_t)N * Do * Ho * Wo * Cc;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % Cc);
+        size_t r = i / Cc;
+        const int x = (int)(r % Wo); r /= Wo;
+        const int y = (int)(r % Ho); r /= Ho;
+        const int z = (int)(r % Do);
+        const int n = (int)(r / Do);
+        float s = 0.f;
+        for (int dz = 0; dz < 2; ++dz)
+            for (int dy = 0; dy < 2; ++dy)
+                for (int dx = 0; dx < 2; ++dx)
+                    s += bf2f(dcat[((((size_t)n * D + 2 * z + dz) * H + 2 * y + dy) * W + 2 * x + dx) * C + c]);
+        dcoarse[i] = f2bf(s);
+    }
+}
+
+__global__ void up_concat_bwd_skip_kernel(const uint16_t* __restrict__ dcat, uint16_t* __restrict__ dskip,
+                                          size_t nvox, int Cc, int Cs)
+{
+    const int C = Cc + Cs;
+    const size_t total = nvox * Cs;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+        const size_t v = i / Cs;
+        const int c = (int)(i % Cs);
+        dskip[i] = dcat[v * C + Cc + c];
+    }
+}
+
+// network input: x[v] = (dose[v] * inv_scale, density[v] * 0.5, 0 x 6)
+__global__ void make_input_kernel(const float* __restrict__ dose, const float* __restrict__ rho,
+                                  const float* __restrict__ scale, uint16_t* __restrict__ x, size_t nvox)
+{
+    const float inv = 1.0f / fmaxf(scale[0], 1e-30f);
+    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < nvox; v += (size_t)gridDim.x * blockDim.x) {
+        uint16_t* o = x + 8 * v;
+        o[0] = f2bf(dose[v] * inv);
+        o[1] = f2bf(rho[v] * 0.5f);
+#pragma unroll
+        for (int c = 2; c < 8; ++c) o[c] = 0;
+    }
+}
+
+// scale[0] = max_v dose[v]  (non-negative input; scale must start at 0)
+__global__ void max_kernel(const float* __restrict__ a, size_t n, float* __restrict__ scale)
+{
+    float m = 0.f;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        m = fmaxf(m, a[i]);
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) atomicMax(reinterpret_cast<unsigned int*>(scale), __float_as_uint(m));
+}
+
+// head: out[v] = scale * (dose[v]/scale + sum_c w[c] d1[v][c] + b)  (1x1x1, 16 -> 1, residual)
+__global__ void head_fwd_kernel(const uint16_t* __restrict__ d1, const float* __restrict__ w,
+                                const float* __restrict__ b, const float* __restrict__ dose,
+                                const float* __restrict__ scale, float* __restrict__ out, size_t nvox, int C)
+{
+    const float sc = fmaxf(scale[0], 1e-30f);
+    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < nvox; v += (size_t)gridDim.x * blockDim.x) {
+        float s = b[0];
+        for (int c = 0; c < C; ++c) s += w[c] * bf2f(d1[v * C + c]);
+        out[v] = dose[v] + sc * s;
+    }
+}
+
+// MSE loss in normalised units over voxels with weight mask (all ones when
+// mask is NULL): L = sum_v m_v (out_v - t_v)^2 / scale^2 / sum m_v.  Writes
+// g[v] = dL/d(head pre-activation) = 2 m_v (out_v - t_v) / scale / sum m_v,
+// accumulates the head gradients and the loss.
+__global__ void loss_head_bwd_kernel(const float* __restrict__ out, const float* __restrict__ target,
+                                     const float* __restrict__ scale, const uint16_t* __restrict__ d1,
+                                     const float* __restrict__ w, uint16_t* __restrict__ dd1,
+                                     float* __restrict__ dw, float* __restrict__ db, double* __restrict__ loss,
+                                     size_t nvox, int C, float inv_count)
+{
+    const float sc = fmaxf(scale[0], 1e-30f);
+    const float isc = 1.0f / sc;
+    float gw[16];
+    for (int c = 0; c < 16; ++c) gw[c] = 0.f;
+    float gb = 0.f;
+    double l = 0.0;
+    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < nvox; v += (size_t)gridDim.x * blockDim.x) {
+        const float e = (out[v] - target[v]) * isc;
+        l += (double)e * e;
+        const float g = 2.f * e * inv_count;
+        gb += g;
+        for (int c = 0; c < C; ++c) {
+            gw[c] += g * bf2f(d1[v * C + c]);
+            dd1[v * C + c] = f2bf(g * w[c]);
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        gb += __shfl_xor(gb, o);
+        l += __shfl_xor(l, o);
+        for (int c = 0; c < 16; ++c) gw[c] += __shfl_xor(gw[c], o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(db, gb);
+        for (int c = 0; c < C; ++c) atomicAdd(&dw[c], gw[c]);
+        atomicAdd(loss, l * inv_count);
+    }
+}
+
+// Adam on FP32 master parameters; refreshes the BF16 copies of the
+// convolution weights (p_bf == NULL for parameters kept in FP32)
+__global__ void adam_kernel(float* __restrict__ p, float* __restrict__ g, float* __restrict__ m1,
+                            float* __restrict__ m2, uint16_t* __restrict__ p_bf, size_t n, float lr,
+                            float b1, float b2, float eps, float c1, float c2)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float a = b1 * m1[i] + (1.f - b1) * gi;
+        const float s = b2 * m2[i] + (1.f - b2) * gi * gi;
+        m1[i] = a;
+        m2[i] = s;
+        const float v = p[i] - lr * (a / c1) / (sqrtf(s / c2) + eps);
+        p[i] = v;
+        g[i] = 0.f;
+        if (p_bf) p_bf[i] = f2bf(v);
+    }
+}
+
+__global__ void f32_to_bf16_kernel(const float* __restrict__ a, uint16_t* __restrict__ b, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        b[i] = f2bf(a[i]);
+}
+
+__global__ void bf16_to_f32_kernel(const uint16_t* __restrict__ a, float* __restrict__ b, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        b[i] = bf2f(a[i]);
+}
+
+// ------------------------------------------------------------ launchers
+
+static unsigned grid_for(size_t n, unsigned block = 256, unsigned cap = 65536)
+{
+    size_t g = (n + block - 1) / block;
+    if (g > cap) g = cap;
+    if (g == 0) g = 1;
+    return (unsigned)g;
+}
+
+hipError_t nn_conv3d_fwd(const uint16_t* in, const uint16_t* wt, const float* bias, uint16_t* out, int N,
+                         int D, int H, int W, int Cin, int Cout, int Kp, int relu, hipStream_t s)
+{
+    const int nb = Cout >= 64 ? 4 : (Cout >= 32 ? 2 : 1);
+    const int cgroups = (Cout + 16 * nb - 1) / (16 * nb);
+    dim3 grid((W + 63) / 64, H * cgroups, N * D);
+    if (nb == 4) hipLaunchKernelGGL(conv3d_fwd_kernel<4>, grid, dim3(256), 0, s, in, wt, bias, out, D, H, W, Cin, Cout, Kp, relu);
+    else if (nb == 2) hipLaunchKernelGGL(conv3d_fwd_kernel<2>, grid, dim3(256), 0, s, in, wt, bias, out, D, H, W, Cin, Cout, Kp, relu);
+    else hipLaunchKernelGGL(conv3d_fwd_kernel<1>, grid, dim3(256), 0, s, in, wt, bias, out, D, H, W, Cin, Cout, Kp, relu);
+    return hipGetLastError();
+}
+
+hipError_t nn_flip_weights(const uint16_t* w, uint16_t* wf, int Cin, int Cout, int Kp, int Kpf, hipStream_t s)
+{
+    hipLaunchKernelGGL(flip_weights_kernel, dim3(grid_for((size_t)Cin * Kpf)), dim3(256), 0, s, w, wf, Cin, Cout, Kp, Kpf);
+    return hipGetLastError();
+}
+
+hipError_t nn_conv3d_wgrad(const uint16_t* in, const uint16_t* dout, float* dw, int N, int D, int H, int W,
+                           int Cin, int Cout, int Kp, hipStream_t s)
+{
+    const int total_rows = N * D * H;
+    const int n_ci = (Cin + 31) / 32, n_co = (Cout + 63) / 64;
+    const int others = 3 * n_ci * n_co;
+    // enough workgroups to fill the chip, each with a run of rows
+    int blocks_x = (2048 + others - 1) / others;
+    if (blocks_x > total_rows) blocks_x = total_rows;
+    if (blocks_x < 1) blocks_x = 1;
+    const int rows = (total_rows + blocks_x - 1) / blocks_x;
+    blocks_x = (total_rows + rows - 1) / rows;
+    hipLaunchKernelGGL(conv3d_wgrad_kernel, dim3(blocks_x, others), dim3(256), 0, s, in, dout, dw, N, D, H, W, Cin,
+                       Cout, Kp, rows);
+    return hipGetLastError();
+}
+
+hipError_t nn_relu_bwd(uint16_t* dy, const uint16_t* y, size_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(relu_bwd_kernel, dim3(grid_for(n)), dim3(256), 0, s, dy, y, n);
+    return hipGetLastError();
+}
+
+hipError_t nn_bias_grad(const uint16_t* dy, float* db, size_t nvox, int C, hipStream_t s)
+{
+    hipLaunchKernelGGL(bias_grad_kernel, dim3(1024), dim3(256), 0, s, dy, db, nvox, C);
+    return hipGetLastError();
+}
+
+hipError_t nn_pool_fwd(const uint16_t* in, uint16_t* out, int N, int D, int H, int W, int C, hipStream_t s)
+{
+    hipLaunchKernelGGL(pool_fwd_kernel, dim3(grid_for((size_t)N * D * H * W * C / 8)), dim3(256), 0, s, in, out, N, D, H, W, C);
+    return hipGetLastError();
+}
+
+hipError_t nn_pool_bwd(const uint16_t* dout, const uint16_t* add, uint16_t* din, int N, int D, int H, int W, int C,
+                       hipStream_t s)
+{
+    hipLaunchKernelGGL(pool_bwd_kernel, dim3(grid_for((size_t)N * D * H * W * C)), dim3(256), 0, s, dout, add, din, N, D, H, W, C);
+    return hipGetLastError();
+}
+
+hipError_t nn_up_concat(const uint16_t* coarse, const uint16_t* skip, uint16_t* cat, int N, int D, int H, int W,
+                        int Cc, int Cs, hipStream_t s)
+{
+    hipLaunchKernelGGL(up_concat_kernel, dim3(grid_for((size_t)N * D * H * W * (Cc + Cs))), dim3(256), 0, s, coarse, skip,
+                       cat, N, D, H, W, Cc, Cs);
+    return hipGetLastError();
+}
+
+hipError_t nn_up_concat_bwd(const uint16_t* dcat, uint16_t* dcoarse, uint16_t* dskip, int N, int D, int H, int W,
+                            int Cc, int Cs, hipStream_t s)
+{
+    hipLaunchKernelGGL(up_concat_bwd_coarse_kernel, dim3(grid_for((size_t)N * D * H * W * Cc / 8)), dim3(256), 0, s, dcat,
+                       dcoarse, N, D, H, W, Cc, Cs);
+    hipLaunchKernelGGL(up_concat_bwd_skip_kernel, dim3(grid_for((size_t)N * D * H * W * Cs)), dim3(256), 0, s, dcat, dskip,
+                       (size_t)N * D * H * W, Cc, Cs);
+    return hipGetLastError();
+}
+
+hipError_t nn_make_input(const float* dose, const float* rho, float* scale, uint16_t* x, size_t nvox, hipStream_t s)
+{
+    hipLaunchKernelGGL(max_kernel, dim3(grid_for(nvox, 256, 4096)), dim3(256), 0, s, dose, nvox, scale);
+    hipLaunchKernelGGL(make_input_kernel, dim3(grid_for(nvox)), dim3(256), 0, s, dose, rho, scale, x, nvox);
+    return hipGetLastError();
+}
+
+hipError_t nn_head_fwd(const uint16_t* d1, const float* w, const float* b, const float* dose, const float* scale,
+                       float* out, size_t nvox, int C, hipStream_t s)
+{
+    hipLaunchKernelGGL(head_fwd_kernel, dim3(grid_for(nvox)), dim3(256), 0, s, d1, w, b, dose, scale, out, nvox, C);
+    return hipGetLastError();
+}
+
+hipError_t nn_loss_head_bwd(const float* out, const float* target, const float* scale, const uint16_t* d1,
+                            const float* w, uint16_t* dd1, float* dw, float* db, double* loss, size_t nvox, int C,
+                            hipStream_t s)
+{
+    hipLaunchKernelGGL(loss_head_bwd_kernel, dim3(grid_for(nvox, 256, 2048)), dim3(256), 0, s, out, target, scale, d1, w,
+                       dd1, dw, db, loss, nvox, C, 1.0f / (float)nvox);
+    return hipGetLastError();
+}
+
+hipError_t nn_adam(float* p, float* g, float* m1, float* m2, uint16_t* p_bf, size_t n, float lr, float b1, float b2,
+                   float eps, float c1, float c2, hipStream_t s)
+{
+    hipLaunchKernelGGL(adam_kernel, dim3(grid_for(n)), dim3(256), 0, s, p, g, m1, m2, p_bf, n, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t nn_f32_to_bf16(const float* a, uint16_t* b, size_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(f32_to_bf16_kernel, dim3(grid_for(n)), dim3(256), 0, s, a, b, n);
+    return hipGetLastError();
+}
+
+hipError_t nn_bf16_to_f32(const uint16_t* a, float* b, size_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(bf16_to_f32_kernel, dim3(grid_for(n)), dim3(256), 0, s, a, b, n);
+    return hipGetLastError();
+}
+
+}  // namespace pmc

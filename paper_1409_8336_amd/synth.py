@@ -376,3 +376,65 @@ def plan_set(n_plans=16, seed=100, hist_scale=1.0, max_grid=(256, 256, 200), min
         plans.append({"hu": hu, "voxel_cm": (0.2, 0.2, 0.2), "spots": spots,
                       "n_histories": max(1, n_hist)})
     return plans
+
+
+# ---------------------------------------------------------------------------
+# Denoiser inputs
+# ---------------------------------------------------------------------------
+
+def bf16_bits(a) -> np.ndarray:
+    """Round float32 values to bfloat16 (nearest, ties to even); the bit
+    patterns as uint16."""
+    u = np.ascontiguousarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    r = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return r.astype(np.uint16)
+
+
+def bf16_values(bits) -> np.ndarray:
+    """float64 values of bfloat16 bit patterns."""
+    return (np.asarray(bits, np.uint16).astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def bf16_normal(rng, shape, sd=1.0):
+    """Normal samples rounded to bfloat16: (bits uint16, exact float64 values)."""
+    bits = bf16_bits(rng.normal(0.0, sd, size=shape).astype(np.float32))
+    return bits, bf16_values(bits)
+
+
+def conv_weights(rng, cin, cout, sd=None):
+    """A convolution weight matrix [cout][Kp] (Kp = 27*cin rounded up to 32,
+    index tap*cin + ci, zero padding columns) of bfloat16 values."""
+    k = (27 * cin + 31) // 32 * 32
+    sd = sd if sd is not None else (2.0 / (27 * cin)) ** 0.5
+    bits = np.zeros((cout, k), np.uint16)
+    bits[:, :27 * cin] = bf16_bits(rng.normal(0.0, sd, size=(cout, 27 * cin)).astype(np.float32))
+    return bits, bf16_values(bits)
+
+
+def training_field(rng, center_xy, e_lo=70.0, e_hi=230.0, pitch_cm=0.5):
+    """A small random field for denoiser data: 1-3 energy layers of 10-60
+    hexagonal-lattice spots each around a seeded offset from the centre,
+    lognormal(0, 0.5) weights."""
+    n_layers = int(rng.integers(1, 4))
+    rows = []
+    cx = center_xy[0] + rng.uniform(-3.0, 3.0)
+    cy = center_xy[1] + rng.uniform(-3.0, 3.0)
+    for _ in range(n_layers):
+        e = rng.uniform(e_lo, e_hi)
+        sig = 0.1 * (6.0 - 3.0 * (e - e_lo) / (e_hi - e_lo))
+        for (x, y) in hex_points(int(rng.integers(10, 61)), pitch_cm):
+            rows.append([cx + x, cy + y, e, sig, sig, 0.0])
+    spots = np.array(rows, dtype=np.float64)
+    spots[:, 5] = rng.lognormal(0.0, 0.5, size=len(rows))
+    return _f32(spots)
+
+
+def denoiser_case(index, nx=128, ny=128, nz=160):
+    """Case `index` of the denoiser data set: a ct_phantom-recipe CT with seed
+    1000 + index (2 mm voxels, titanium rod included) and a training_field
+    drawn from the same seed."""
+    seed = 1000 + index
+    rng = np.random.default_rng(seed)
+    hu = ct_phantom(nx, ny, nz, 0.2, seed=seed)
+    spots = training_field(rng, (0.1 * nx, 0.1 * ny))
+    return {"hu": hu, "voxel_cm": (0.2, 0.2, 0.2), "spots": spots}

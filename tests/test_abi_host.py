@@ -7,13 +7,13 @@ import re
 
 import pytest
 
-from paper_1409_8336_amd import pmc
+from paper_1409_8336_amd import pmc, unet
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared():
-    text = open(os.path.join(ROOT, "include", "pmc.h")).read()
+def _declared(header="pmc.h"):
+    text = open(os.path.join(ROOT, "include", header)).read()
     return sorted(set(re.findall(r"^\s*(?:pmc_status|const char\*)\s+(pmc_\w+)\s*\(", text, re.M)))
 
 
@@ -27,10 +27,11 @@ def lib():
 
 def test_header_declares_the_binding_names():
     assert _declared() == sorted(pmc.EXPORTS)
+    assert _declared("pmc_unet.h") == sorted(unet.EXPORTS)
 
 
 def test_every_declared_symbol_is_exported(lib):
-    for name in _declared():
+    for name in _declared() + _declared("pmc_unet.h"):
         assert hasattr(lib, name), name
 
 
@@ -56,3 +57,23 @@ def test_null_context_is_an_argument_error(lib):
     assert lib.pmc_load_physics(None, None) == pmc.PMC_ERR_ARG
     assert lib.pmc_run_spots(None, None, 0, 0, 0, None, None, None) == pmc.PMC_ERR_ARG
     assert lib.pmc_inspect_tables(None, None, None, None, None, None) == pmc.PMC_ERR_ARG
+
+
+def test_denoiser_and_gamma_reject_bad_arguments(lib):
+    L = unet.lib()
+    u = C.c_void_p()
+    assert L.pmc_unet_create(None, 0, 1, 8, 8, 8, 0) == pmc.PMC_ERR_ARG
+    for shape in ((0, 8, 8, 8), (1, 12, 8, 8), (1, 8, 4, 8), (1, 8, 8, 9)):
+        assert L.pmc_unet_create(C.byref(u), 0, *shape, 0) == pmc.PMC_ERR_ARG
+    assert L.pmc_unet_destroy(None) == pmc.PMC_OK
+    assert L.pmc_unet_forward(None, None, None, None, None) == pmc.PMC_ERR_ARG
+    assert L.pmc_unet_adam_step(None, 1e-3, None) == pmc.PMC_ERR_ARG
+    # channel counts must be multiples of 8
+    assert L.pmc_nn_conv3d_forward(None, None, None, None, 1, 8, 8, 8, 8, 16, 0, None) == pmc.PMC_ERR_ARG
+    one = C.c_void_p(1)
+    assert L.pmc_nn_conv3d_forward(one, one, None, one, 1, 8, 8, 8, 12, 16, 0, None) == pmc.PMC_ERR_ARG
+    rate, n = C.c_double(), C.c_int64()
+    assert L.pmc_gamma_index(one, one, 4, 4, 4, 0.2, 0.2, 0.2, 0.02, 0.0, 0.1, 0.6, 0.05, None,
+                             C.byref(rate), C.byref(n), None) == pmc.PMC_ERR_ARG
+    assert L.pmc_gamma_index(one, one, 4, 4, 4, 0.2, 0.2, 0.2, 0.02, 0.2, 0.1, 10.0, 0.05, None,
+                             C.byref(rate), C.byref(n), None) == pmc.PMC_ERR_ARG

@@ -1,0 +1,287 @@
+"""Pins of the denoiser / gamma oracle against facts that do not come from
+the oracle itself: impulse responses, a library convolution, inner-product
+identities of the adjoints, finite differences, closed forms of gamma, and a
+pure-Python brute force."""
+import numpy as np
+import pytest
+
+from oracle import denoiser_oracle as D
+from paper_1409_8336_amd import synth
+
+
+def _rand(rng, shape):
+    return rng.normal(size=shape)
+
+
+# ------------------------------------------------------------ convolution
+
+def test_conv_impulse_response():
+    """A unit impulse at voxel p, channel ci gives y[p - off(tap)][co] =
+    W[co][tap*cin + ci] for each tap, and zero elsewhere."""
+    rng = np.random.default_rng(1)
+    cin, cout = 3, 2
+    w = _rand(rng, (cout, D.kp(cin)))
+    x = np.zeros((1, 5, 6, 7, cin))
+    p = (2, 3, 3)
+    ci = 1
+    x[(0,) + p + (ci,)] = 1.0
+    y = D.conv3d(x, w)
+    expect = np.zeros_like(y)
+    for kz in range(3):
+        for ky in range(3):
+            for kx in range(3):
+                tap = (kz * 3 + ky) * 3 + kx
+                q = (p[0] - (kz - 1), p[1] - (ky - 1), p[2] - (kx - 1))
+                expect[(0,) + q] = w[:, tap * cin + ci]
+    np.testing.assert_array_equal(y, expect)
+
+
+def test_conv_matches_library_conv3d():
+    """Against torch.nn.functional.conv3d (FP64, padding 1) with the weight
+    matrix rearranged to [cout][cin][kz][ky][kx] by explicit loops."""
+    import torch
+    rng = np.random.default_rng(2)
+    n, d, h, w_, cin, cout = 2, 4, 5, 6, 3, 4
+    x = _rand(rng, (n, d, h, w_, cin))
+    w = _rand(rng, (cout, D.kp(cin)))
+    b = _rand(rng, cout)
+    wt = np.zeros((cout, cin, 3, 3, 3))
+    for co in range(cout):
+        for c in range(cin):
+            for kz in range(3):
+                for ky in range(3):
+                    for kx in range(3):
+                        wt[co, c, kz, ky, kx] = w[co, ((kz * 3 + ky) * 3 + kx) * cin + c]
+    ref = torch.nn.functional.conv3d(torch.tensor(x).permute(0, 4, 1, 2, 3), torch.tensor(wt),
+                                     torch.tensor(b), padding=1).permute(0, 2, 3, 4, 1).numpy()
+    np.testing.assert_allclose(D.conv3d(x, w, b), ref, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(D.conv3d(x, w, b, relu=True), np.maximum(ref, 0), rtol=1e-12, atol=1e-12)
+    pts = [(1, 0, 0, 0), (0, 3, 4, 5), (1, 2, 2, 3)]
+    np.testing.assert_allclose(D.conv3d_at(x, w, b, pts), np.array([ref[p] for p in pts]),
+                               rtol=1e-12, atol=1e-12)
+
+
+def test_conv_adjoints_inner_product_identity():
+    """<conv(x, W), g> = <x, conv_T(g, W)> = <W, dW(x, g)>: both backward
+    functions are the adjoints of the forward definition."""
+    rng = np.random.default_rng(3)
+    cin, cout = 5, 3
+    x = _rand(rng, (2, 4, 3, 5, cin))
+    w = _rand(rng, (cout, D.kp(cin)))
+    w[:, 27 * cin:] = 0.0
+    g = _rand(rng, (2, 4, 3, 5, cout))
+    lhs = (D.conv3d(x, w) * g).sum()
+    dx = D.conv3d_backward_data(g, w, cin)
+    dw = D.conv3d_backward_weight(x, g, D.kp(cin))
+    assert abs(lhs - (x * dx).sum()) <= 1e-10 * abs(lhs)
+    assert abs(lhs - (w * dw).sum()) <= 1e-10 * abs(lhs)
+    assert np.all(dw[:, 27 * cin:] == 0.0)
+
+
+def test_pool_and_upsample_closed_forms():
+    rng = np.random.default_rng(4)
+    x = _rand(rng, (1, 4, 6, 2, 3))
+    # upsampling then averaging returns the input exactly
+    np.testing.assert_allclose(D.pool_avg(D.upsample_nearest(x)), x, rtol=0, atol=1e-15)
+    # a constant field pools to itself; one voxel's pool is its 2x2x2 mean
+    np.testing.assert_allclose(D.pool_avg(np.full((1, 2, 2, 2, 1), 3.5)), 3.5)
+    y = D.pool_avg(x)
+    assert abs(y[0, 1, 2, 0, 1] - x[0, 2:4, 4:6, 0:2, 1].mean()) < 1e-15
+
+
+# ------------------------------------------------------------ network
+
+def _net_case(seed, shape=(1, 8, 8, 8)):
+    rng = np.random.default_rng(seed)
+    layout, ohw, ohb, n = D.param_layout()
+    p = np.zeros(n)
+    for name, ow, ob, cin, cout, k in layout:
+        sd = (2.0 / (27 * cin)) ** 0.5
+        w = rng.normal(0, sd, (cout, k))
+        w[:, 27 * cin:] = 0.0
+        if name == "enc1":
+            w[:, :27 * cin].reshape(cout, 27, cin)[:, :, 2:] = 0.0
+        p[ow:ow + cout * k] = w.ravel()
+        p[ob:ob + cout] = rng.normal(0, 0.05, cout)
+    p[ohw:ohw + 16] = rng.normal(0, 0.1, 16)
+    p[ohb] = 0.01
+    dose = rng.gamma(2.0, 1.0, shape)
+    rho = rng.uniform(0.2, 2.0, shape)
+    target = dose * rng.uniform(0.8, 1.2, shape)
+    return p, dose, rho, target
+
+
+def test_param_layout_matches_documented_sizes():
+    layout, ohw, ohb, n = D.param_layout()
+    expect = sum(cout * D.kp(cin) + cout for cin, cout in D.CONVS) + 17
+    assert n == expect and ohb == n - 1 and ohw == n - 17
+    # by hand: 16*224 + 32*448 + 64*864 + 128*1728 + 64*5184 + 32*2592 + 16*1312
+    # weights, 352 biases, 17 head parameters
+    assert n == 730481
+
+
+def test_residual_head_with_zero_head_returns_dose():
+    p, dose, rho, _ = _net_case(5)
+    _, ohw, ohb, _ = D.param_layout()
+    p[ohw:ohb + 1] = 0.0
+    np.testing.assert_array_equal(D.UNetOracle(p).forward(dose, rho), dose)
+
+
+def test_network_forward_matches_composition_of_definitions():
+    """The network forward rebuilt from the plain-sum conv3d, pool_avg and
+    upsample_nearest definitions above (channels-last numpy)."""
+    p, dose, rho, _ = _net_case(13, shape=(2, 8, 8, 16))
+    layout, ohw, ohb, _ = D.param_layout()
+    L = {l[0]: l for l in layout}
+
+    def conv(name, x):
+        _, ow, ob, cin, cout, k = L[name]
+        return D.conv3d(x, p[ow:ow + cout * k].reshape(cout, k), p[ob:ob + cout], relu=True)
+
+    scale = dose.max()
+    x = np.zeros(dose.shape + (8,))
+    x[..., 0] = dose / scale
+    x[..., 1] = rho / 2
+    e1 = conv("enc1", x)
+    e2 = conv("enc2", D.pool_avg(e1))
+    e3 = conv("enc3", D.pool_avg(e2))
+    e4 = conv("enc4", D.pool_avg(e3))
+    d3 = conv("dec3", np.concatenate([D.upsample_nearest(e4), e3], axis=-1))
+    d2 = conv("dec2", np.concatenate([D.upsample_nearest(d3), e2], axis=-1))
+    d1 = conv("dec1", np.concatenate([D.upsample_nearest(d2), e1], axis=-1))
+    out = dose + scale * (d1 @ p[ohw:ohw + 16] + p[ohb])
+    np.testing.assert_allclose(D.UNetOracle(p).forward(dose, rho), out, rtol=1e-12, atol=1e-12 * scale)
+
+
+def test_network_gradient_matches_finite_differences():
+    p, dose, rho, target = _net_case(6)
+    net = D.UNetOracle(p)
+    loss, grad, _ = net.loss_and_grad(dose, rho, target)
+    layout, ohw, ohb, n = D.param_layout()
+    rng = np.random.default_rng(7)
+    idx = [ohw + 3, ohb]
+    for name, ow, ob, cin, cout, k in layout:
+        cin_used = 2 if name == "enc1" else cin
+        for _ in range(3):
+            co, tap, ci = rng.integers(cout), rng.integers(27), rng.integers(cin_used)
+            idx.append(ow + co * k + tap * cin + ci)
+        idx.append(ob + rng.integers(cout))
+    h = 1e-6
+    gnorm = np.abs(grad).max()
+    for i in idx:
+        pp, pm = p.copy(), p.copy()
+        pp[i] += h
+        pm[i] -= h
+        fd = (D.UNetOracle(pp).loss(dose, rho, target) - D.UNetOracle(pm).loss(dose, rho, target)) / (2 * h)
+        assert abs(fd - grad[i]) <= 1e-6 * gnorm + 1e-6 * abs(fd), (i, fd, grad[i])
+
+
+def test_adam_first_step_moves_each_parameter_by_lr():
+    """With zero moments the first bias-corrected Adam step is lr * sign(g)
+    (up to eps)."""
+    p, dose, rho, target = _net_case(8)
+    net = D.UNetOracle(p)
+    g = np.random.default_rng(9).normal(size=p.size)
+    net.adam_step(g, np.zeros_like(g), np.zeros_like(g), 1, 1e-3)
+    # |g| / (|g| + eps) differs from 1 by at most eps / |g|
+    dev = np.abs((net.params - p) + 1e-3 * np.sign(g))
+    assert np.all(dev <= 1e-3 * 1e-8 / np.abs(g) + 1e-15)
+
+
+# ------------------------------------------------------------ gamma
+
+def test_gamma_identical_is_zero():
+    rng = np.random.default_rng(10)
+    ref = rng.gamma(2.0, 1.0, (6, 7, 8))
+    g, rate, n = D.gamma_index(ref, ref, (0.2, 0.2, 0.2), cutoff_frac=0.0)
+    assert n == ref.size and rate == 1.0 and np.all(g == 0.0)
+
+
+def test_gamma_uniform_scaling_closed_form():
+    """A uniform reference against eval = (1 + e) * ref: no spatial offset
+    can lower the dose difference, so gamma = e * ref / (frac * max)."""
+    ref = np.full((5, 5, 5), 2.0)
+    for e in (0.01, 0.03):
+        g, rate, n = D.gamma_index(ref, ref * (1 + e), (0.2, 0.2, 0.2), dose_frac=0.02)
+        np.testing.assert_allclose(g, e / 0.02, rtol=1e-12)
+        assert rate == (1.0 if e / 0.02 <= 1 else 0.0)
+
+
+def test_gamma_shifted_ramp_closed_form():
+    """ref(z) = a + b z and eval(z) = ref(z - s) along z: at interior voxels
+    gamma^2 = min over grid offsets t in [-R, R] of t^2/dta^2 + (b (t - s) / c)^2,
+    c = frac * max(ref) (offsets across z only add distance)."""
+    nz, ny, nx = 40, 5, 5
+    dz = 0.2
+    z = np.arange(nz) * dz
+    a, b, s = 1.0, 0.5, 0.1     # 1 mm shift
+    ref = np.broadcast_to((a + b * z)[:, None, None], (nz, ny, nx)).copy()
+    ev = np.broadcast_to((a + b * (z - s))[:, None, None], (nz, ny, nx)).copy()
+    frac, dta, R, step = 0.02, 0.2, 0.6, 0.05
+    g, _, _ = D.gamma_index(ref, ev, (0.2, 0.2, dz), dose_frac=frac, dta_cm=dta, cutoff_frac=0.0,
+                            search_cm=R, step_cm=step)
+    c = frac * ref.max()
+    t = np.arange(-12, 13) * step
+    expect = np.sqrt(np.min(t ** 2 / dta ** 2 + (b * (t - s) / c) ** 2))
+    interior = g[5:-5, :, :]
+    np.testing.assert_allclose(interior, expect, rtol=1e-9)
+    # and the continuous minimum s / sqrt(dta^2 + c^2/b^2) bounds it from below
+    assert expect >= s / np.sqrt(dta ** 2 + (c / b) ** 2) - 1e-12
+
+
+def test_gamma_against_python_brute_force():
+    rng = np.random.default_rng(11)
+    ref = rng.gamma(3.0, 1.0, (4, 5, 6))
+    ev = ref * rng.uniform(0.95, 1.05, ref.shape)
+    vox = (0.2, 0.25, 0.3)
+    frac, dta, cut, R, step = 0.03, 0.3, 0.2, 0.4, 0.1
+    g, rate, n = D.gamma_index(ref, ev, vox, frac, dta, cut, R, step)
+    nz, ny, nx = ref.shape
+    dmax = ref.max()
+
+    def interp(pz, py, px):
+        # trilinear interpolation written as a sum of hat functions
+        tot = 0.0
+        for zc in range(nz):
+            for yc in range(ny):
+                for xc in range(nx):
+                    w = (max(0.0, 1 - abs(pz - zc)) * max(0.0, 1 - abs(py - yc))
+                         * max(0.0, 1 - abs(px - xc)))
+                    if w:
+                        tot += ev[zc, yc, xc] * w
+        return tot
+
+    m = int(R / step + 1e-4)
+    count = passed = 0
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                if ref[k, j, i] < cut * dmax:
+                    assert g[k, j, i] == -1.0
+                    continue
+                best = np.inf
+                for a in range(-m, m + 1):
+                    for bb in range(-m, m + 1):
+                        for c in range(-m, m + 1):
+                            oz, oy, ox = a * step, bb * step, c * step
+                            if oz * oz + oy * oy + ox * ox > R * R * (1 + 1e-6):
+                                continue
+                            pz, py, px = k + oz / vox[2], j + oy / vox[1], i + ox / vox[0]
+                            if not (0 <= pz <= nz - 1 and 0 <= py <= ny - 1 and 0 <= px <= nx - 1):
+                                continue
+                            val = interp(pz, py, px)
+                            best = min(best, (oz * oz + oy * oy + ox * ox) / dta ** 2
+                                       + ((val - ref[k, j, i]) / (frac * dmax)) ** 2)
+                assert abs(g[k, j, i] - np.sqrt(best)) <= 1e-12 * max(1.0, np.sqrt(best)), (k, j, i)
+                count += 1
+                passed += np.sqrt(best) <= 1.0
+    assert n == count and rate == passed / count
+
+
+def test_bf16_inputs_are_exact():
+    rng = np.random.default_rng(12)
+    bits, vals = synth.bf16_normal(rng, (1000,))
+    assert np.all(synth.bf16_bits(vals.astype(np.float32)) == bits)
+    # 8 significant bits: the value times 2^k is an integer below 256
+    m, e = np.frexp(vals[vals != 0])
+    assert np.all(np.abs(m * 256 - np.round(m * 256)) == 0)
