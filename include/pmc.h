@@ -71,6 +71,12 @@ typedef struct {
     int32_t blocks_per_cu;   /* resident workgroups per CU for the persistent grid; 0 = occupancy */
     int32_t refill_lanes;    /* a wave refills when at least this many of its 64 lanes are idle; 0 = tuned */
     int32_t batch_events;    /* a wave handles pending nuclear events once this many lanes wait; 0 = tuned */
+    int32_t tally_cache;     /* LDS deposit cache per workgroup (single-geometry runs): slots, a
+                                power of two 512..16384; 0 = automatic (the tuner may turn it off,
+                                else sized from the LDS left by the tables); -1 = off (every
+                                deposit is a global FP64 atomic) */
+    int32_t epoch_steps;     /* loop iterations between cache flushes; 0 = 64 */
+    int32_t cache_probes;    /* cache slots tried per deposit (linear probing), 1..16; 0 = 4 */
 } pmc_params;
 /* Autotuning: when any of block_threads, refill_lanes, batch_events is 0 and
  * a run has at least 1e6 histories, the first run of each workload signature
@@ -128,12 +134,14 @@ typedef struct {
     double incident, deposited, escaped, neutral, overflow;
     uint64_t histories, steps, secondaries, n_elastic, n_nonelastic, n_overflow;
     uint64_t n_short_steps; /* steps lengthened to s_min (sub-micron boundary approaches) */
-    uint64_t tally_atomics; /* FP64 atomic adds issued into the dose tally */
+    uint64_t tally_atomics; /* energy deposits scored (one per step, event or termination) */
     double total_weight;   /* sum of primary weights (dose normalisation) */
     double device_ms;      /* device time of the run, HIP events */
     double transport_ms;   /* sum over transport launches of their HIP-event durations */
     int32_t generations;   /* transport launches (primaries + secondary generations) */
     int32_t reserved;
+    uint64_t global_atomics; /* FP64 atomic adds that reached the tally in device memory
+                                (deposits that missed the LDS cache plus cache flushes) */
 } pmc_summary;
 
 typedef struct pmc_ctx pmc_ctx;
@@ -234,6 +242,13 @@ pmc_status pmc_inspect_tables(const pmc_ctx* c, float* out_lnr_water, float* out
  * unchanged.  Errors: PMC_ERR_ARG, PMC_ERR_STATE (no geometry),
  * PMC_ERR_DEVICE. */
 pmc_status pmc_atomic_probe(pmc_ctx* c, uint64_t n_atomics, void* hip_stream, double* ms_out);
+
+/* Mass density (g/cm^3, float32) of every voxel of geometry geometry_id
+ * (0 = pmc_load_geometry's) as the transport uses it (the HU calibration of
+ * Sec. II.A.1), written to the device array d_rho ([nz][ny][nx]) on
+ * hip_stream.  Errors: PMC_ERR_ARG (NULL, unknown id), PMC_ERR_STATE (no
+ * geometry), PMC_ERR_DEVICE. */
+pmc_status pmc_geometry_density(pmc_ctx* c, int32_t geometry_id, float* d_rho, void* hip_stream);
 
 /* Library version string, e.g. "pmc 0.1 gfx950". */
 const char* pmc_version(void);

@@ -104,6 +104,18 @@ pmc_status pmc_gamma_index(const double* d_ref, const double* d_eval, int nx, in
                            float cutoff_frac, float search_cm, float step_cm, float* d_gamma,
                            double* pass_rate, int64_t* n_eval, void* hip_stream);
 
+/* Fallback rule of the denoiser: among voxels with d_mc >= cutoff_frac *
+ * max(d_mc), the fraction where |d_den - d_mc| > k_sigma * sqrt(d_var_mc),
+ * i.e. where the denoised dose departs from the noisy Monte Carlo dose it
+ * was computed from by more than k_sigma of that dose's own standard error
+ * (Eq. 5).  A caller falls back to plain Monte Carlo when the fraction
+ * exceeds its threshold.  d_den float32, d_mc and d_var_mc float64, n
+ * elements each (device).  *frac_out and *n_out (host) receive the fraction
+ * and the number of voxels above the cutoff.  Synchronous. */
+pmc_status pmc_denoise_disagreement(const float* d_den, const double* d_mc, const double* d_var_mc,
+                                   int64_t n, float cutoff_frac, float k_sigma, double* frac_out,
+                                   int64_t* n_out, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -74,6 +74,13 @@ struct KernelArgs {
     unsigned long long* counters;   // [plan][8]: steps, elastic, non-elastic, short steps, tally atomics
     int refill_lanes;
     int batch_events;
+    // workgroup deposit cache in LDS (single-plan launches): 2^cache_log2
+    // slots of {uint32 tally index, double sum} at LDS word offset cache_off,
+    // flushed to the tally every epoch_iters loop iterations; 0 = off
+    int cache_log2;
+    int cache_off;
+    int epoch_iters;
+    int cache_probes;   // slots tried (linear probing) before a deposit goes to the tally
 };
 
 }  // namespace pmc

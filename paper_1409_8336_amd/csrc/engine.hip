@@ -29,6 +29,7 @@ hipError_t transport_max_block(bool multi, int* max_threads);
 hipError_t launch_stats(const double* tally, const uint2* vox, unsigned long long nvox, int K,
                         double conv0, double* dose, double* var, double* dep_sum, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_density(const uint2* vox, unsigned long long nvox, float* rho, hipStream_t s);
 hipError_t launch_atomic_probe(double* tally, int nx, int ny, int nz, int K, int grid,
                                unsigned long long per_lane, hipStream_t st);
 }  // namespace pmc
@@ -73,6 +74,7 @@ struct Geometry {
 // launch shape chosen by the autotuner (or fixed by the caller)
 struct Shape {
     int block = 256, blocks_per_cu = 0, refill = 16, batch = 4;
+    int cache = 0;   // deposit cache when the caller leaves it automatic: 0 sized from LDS, -1 off
 };
 
 // one plan of a run, host side
@@ -200,6 +202,11 @@ bool params_ok(const pmc_params& p, std::string& why)
     if (p.blocks_per_cu < 0 || p.blocks_per_cu > 64) { why = "blocks_per_cu out of range"; return false; }
     if (p.refill_lanes < 0 || p.refill_lanes > 64) { why = "refill_lanes out of range"; return false; }
     if (p.batch_events < 0 || p.batch_events > 64) { why = "batch_events out of range"; return false; }
+    if (p.tally_cache != 0 && p.tally_cache != -1 &&
+        (p.tally_cache < 512 || p.tally_cache > 16384 || (p.tally_cache & (p.tally_cache - 1))))
+    { why = "tally_cache must be -1, 0 or a power of two in [512, 16384]"; return false; }
+    if (p.epoch_steps < 0 || p.epoch_steps > 4096) { why = "epoch_steps must be in [0, 4096]"; return false; }
+    if (p.cache_probes < 0 || p.cache_probes > 16) { why = "cache_probes must be in [0, 16]"; return false; }
     return true;
 }
 
@@ -432,7 +439,29 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
     a.batch_events = shape.batch;
 
     const int block = shape.block;
-    const size_t lds = (size_t)(multi ? a.pd_offset + 16 * np : a.blob_words) * 4;
+    const size_t lds_words = (size_t)(multi ? a.pd_offset + 16 * np : a.blob_words);
+    // deposit cache of a single-geometry run: 12 bytes per slot, sized from
+    // what the tables leave of the CU's 160 KiB LDS at 16 waves per CU
+    int slots = 0;
+    const int want = c->p.tally_cache != 0 ? c->p.tally_cache : shape.cache;
+    if (!multi && want >= 0 && plans[0].g->nvox() * (unsigned long long)K < 0xFFFFFFFFull) {
+        slots = want;
+        if (slots == 0) {
+            const long wgs = std::max(1, 1024 / block);
+            const long avail = 163840L / wgs - (long)lds_words * 4 - 64;
+            for (int s2 = 16384; s2 >= 512; s2 >>= 1)
+                if ((long)s2 * 12 <= avail) {
+                    slots = s2;
+                    break;
+                }
+        }
+    }
+    a.cache_log2 = 0;
+    while (slots > 0 && (1 << a.cache_log2) < slots) ++a.cache_log2;
+    a.cache_off = (int)((lds_words + 1) & ~(size_t)1);
+    a.epoch_iters = c->p.epoch_steps ? c->p.epoch_steps : 64;
+    a.cache_probes = c->p.cache_probes ? c->p.cache_probes : 4;
+    const size_t lds = slots ? (size_t)(a.cache_off + 3 * slots + 1) * 4 : lds_words * 4;
     int max_block = 0;
     HIPCHK(transport_max_block(multi, &max_block), "kernel attributes");
     if (block > max_block) return fail(c, PMC_ERR_ARG, "block_threads exceeds the transport kernel's limit");
@@ -507,6 +536,7 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
             sm->n_nonelastic = cnt[8 * p + 2];
             sm->n_short_steps = cnt[8 * p + 3];
             sm->tally_atomics = cnt[8 * p + 4];
+            sm->global_atomics = cnt[8 * p + 5];
             sm->secondaries = produced_total;
             sm->n_overflow = overflow_n;
             sm->total_weight = wtot[p];
@@ -546,26 +576,49 @@ pmc_status choose_shape(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, hipS
         *out = it->second;
         return PMC_OK;
     }
+    // calibration work of about 2e5 histories.  One geometry: the first
+    // spots of the list with their own history counts, which keeps the
+    // spatial coherence of the work (what the deposit cache relies on);
+    // several plans: every plan scaled down.
     std::vector<PlanIn> cal = plans;
-    const double f = 200000.0 / (double)total;
-    for (PlanIn& p : cal) {
-        p.n_hist = (unsigned long long)std::ceil(p.n_hist * f);
+    if (!multi) {
+        PlanIn& p = cal[0];
+        double wsum = 0.0;
+        for (int i = 0; i < p.n_spots; ++i) wsum += p.spots[i].weight;
+        double acc = 0.0;
+        int m = 0;
+        while (m < p.n_spots && acc < 200000.0) {
+            acc += wsum > 0.0 ? (double)p.n_hist * p.spots[m].weight / wsum : 0.0;
+            ++m;
+        }
+        p.n_spots = m > 0 ? m : 1;
+        p.n_hist = std::max<unsigned long long>(1ull, (unsigned long long)std::llround(acc));
         p.summary = nullptr;
+    } else {
+        const double f = 200000.0 / (double)total;
+        for (PlanIn& p : cal) {
+            p.n_hist = (unsigned long long)std::ceil(p.n_hist * f);
+            p.summary = nullptr;
+        }
     }
     std::vector<Shape> cands;
     for (int b : {256, 512, 1024})
         for (int r : {16, 32})
-            for (int e : {2, 4}) {
-                Shape x;
-                x.block = c->p.block_threads ? c->p.block_threads : b;
-                x.blocks_per_cu = c->p.blocks_per_cu;
-                x.refill = c->p.refill_lanes ? c->p.refill_lanes : r;
-                x.batch = c->p.batch_events ? c->p.batch_events : e;
-                bool dup = false;
-                for (const Shape& y : cands)
-                    dup |= (y.block == x.block && y.refill == x.refill && y.batch == x.batch);
-                if (!dup) cands.push_back(x);
-            }
+            for (int e : {2, 4})
+                for (int ch : {0, -1}) {
+                    Shape x;
+                    x.block = c->p.block_threads ? c->p.block_threads : b;
+                    x.blocks_per_cu = c->p.blocks_per_cu;
+                    x.refill = c->p.refill_lanes ? c->p.refill_lanes : r;
+                    x.batch = c->p.batch_events ? c->p.batch_events : e;
+                    // the cache is only worth a choice where it fits next to the tables
+                    x.cache = (multi || c->p.tally_cache != 0 || x.block < 512) ? 0 : ch;
+                    bool dup = false;
+                    for (const Shape& y : cands)
+                        dup |= (y.block == x.block && y.refill == x.refill && y.batch == x.batch &&
+                                y.cache == x.cache);
+                    if (!dup) cands.push_back(x);
+                }
     double best = 1e300;
     Shape best_s = s;
     for (const Shape& x : cands) {
@@ -610,7 +663,7 @@ pmc_status pmc_default_params(pmc_params* p)
     return PMC_OK;
 }
 
-const char* pmc_version(void) { return "pmc 0.2 gfx950"; }
+const char* pmc_version(void) { return "pmc 0.3 gfx950"; }
 
 const char* pmc_last_error(const pmc_ctx* c)
 {
@@ -787,6 +840,19 @@ pmc_status pmc_inspect_tables(const pmc_ctx* c, float* lnr_w, float* lnr_o, floa
             material[4 * m + 2] = c->mats[m].za;
             material[4 * m + 3] = c->mats[m].own ? 1.0 : 0.0;
         }
+    return PMC_OK;
+}
+
+pmc_status pmc_geometry_density(pmc_ctx* c, int32_t geometry_id, float* d_rho, void* stream)
+{
+    if (!c) return PMC_ERR_ARG;
+    if (!have_geometry(c)) return fail(c, PMC_ERR_STATE, "density: no geometry loaded");
+    if (!d_rho || geometry_id < 0 || geometry_id >= (int32_t)c->geoms.size() || !c->geoms[geometry_id] ||
+        c->geoms[geometry_id]->nx <= 0)
+        return fail(c, PMC_ERR_ARG, "density: bad geometry id or NULL output");
+    HIPCHK(hipSetDevice(c->device), "set device");
+    const Geometry& g = *c->geoms[geometry_id];
+    HIPCHK(launch_density((const uint2*)g.vox.p, g.nvox(), d_rho, (hipStream_t)stream), "density");
     return PMC_OK;
 }
 

@@ -91,9 +91,60 @@ __global__ void gamma_kernel(const double* __restrict__ ref, const double* __res
     }
 }
 
+__global__ void disagreement_kernel(const float* __restrict__ den, const double* __restrict__ mc,
+                                    const double* __restrict__ var, size_t n,
+                                    const unsigned long long* __restrict__ maxbits, float cutoff, float k,
+                                    unsigned long long* __restrict__ counts)
+{
+    const double thr = cutoff * __longlong_as_double((long long)maxbits[0]);
+    unsigned long long above = 0, off = 0;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const double m = mc[i];
+        if (!(m >= thr) || m <= 0.0) continue;
+        ++above;
+        off += fabs((double)den[i] - m) > k * sqrt(fmax(var[i], 0.0));
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        above += __shfl_xor(above, o);
+        off += __shfl_xor(off, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&counts[0], above);
+        atomicAdd(&counts[1], off);
+    }
+}
+
 }  // namespace
 
 }  // namespace pmc
+
+extern "C" pmc_status pmc_denoise_disagreement(const float* den, const double* mc, const double* var, int64_t n,
+                                              float cutoff, float k, double* frac_out, int64_t* n_out, void* stream)
+{
+    if (!den || !mc || !var || !frac_out || n <= 0 || !(cutoff >= 0) || !(k > 0)) return PMC_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long* buf = nullptr;
+    if (hipMalloc((void**)&buf, 3 * sizeof(unsigned long long)) != hipSuccess) return PMC_ERR_NOMEM;
+    hipError_t e = hipMemsetAsync(buf, 0, 3 * sizeof(unsigned long long), s);
+    const unsigned blocks = (unsigned)std::min<size_t>(((size_t)n + 255) / 256, 4096);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(pmc::max_abs_kernel, dim3(blocks), dim3(256), 0, s, mc, (size_t)n, buf);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(pmc::disagreement_kernel, dim3(blocks), dim3(256), 0, s, den, mc, var, (size_t)n, buf,
+                           cutoff, k, buf + 1);
+        e = hipGetLastError();
+    }
+    unsigned long long h[3] = {0, 0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(h, buf, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(buf);
+    if (e != hipSuccess) return PMC_ERR_DEVICE;
+    *frac_out = h[1] ? (double)h[2] / (double)h[1] : 0.0;
+    if (n_out) *n_out = (int64_t)h[1];
+    return PMC_OK;
+}
 
 extern "C" pmc_status pmc_gamma_index(const double* ref, const double* ev, int nx, int ny, int nz, float dx,
                                       float dy, float dz, float dose_frac, float dta, float cutoff, float search,

@@ -27,6 +27,7 @@ constexpr float kInvH = 999.0f / 7.824046011f;    // 1 / (ln(2500)/999)
 constexpr float kH = 7.824046011f / 999.0f;
 constexpr float kStraggleK = 0.156914976f;        // K m_e c^2, MeV^2 cm^2 / g
 constexpr float kInf = 3.0e38f;
+constexpr uint32_t kEmptySlot = 0xFFFFFFFFu;   // free deposit-cache slot
 constexpr uint32_t kMaxSteps = 1u << 20;
 constexpr uint32_t kNoStraggle = 1u, kNoMcs = 2u, kNoNuclear = 4u;
 
@@ -172,6 +173,8 @@ struct Plans<true> {
 template <bool kMulti>
 __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
 {
+    // all LDS is the dynamic allocation (no static __shared__ variables, so
+    // that it starts at byte 0 and the cache's doubles are 8-byte aligned)
     extern __shared__ float lds[];
     for (int i = threadIdx.x; i < a.blob_words; i += blockDim.x) lds[i] = a.blob[i];
     if constexpr (kMulti) {
@@ -179,6 +182,19 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
         const uint32_t* src = reinterpret_cast<const uint32_t*>(a.plans);
         for (int i = threadIdx.x; i < a.n_plans * 16; i += blockDim.x) dst[i] = src[i];
     }
+    // deposit cache at an even word offset: slot values (double), slot keys
+    // (tally index), then the count of waves that have finished
+    const bool use_cache = !kMulti && a.cache_log2 > 0;
+    const int n_slots = use_cache ? 1 << a.cache_log2 : 0;
+    const uint32_t slot_shift = 32u - (uint32_t)a.cache_log2;
+    double* const cval = reinterpret_cast<double*>(lds + a.cache_off);
+    uint32_t* const ckey = reinterpret_cast<uint32_t*>(lds + a.cache_off + 2 * n_slots);
+    uint32_t* const waves_done = ckey + n_slots;
+    for (int i = threadIdx.x; i < n_slots; i += blockDim.x) {
+        cval[i] = 0.0;
+        ckey[i] = kEmptySlot;
+    }
+    if (use_cache && threadIdx.x == 0) *waves_done = 0;
     __syncthreads();
     const PlanDesc* pds = reinterpret_cast<const PlanDesc*>(lds + a.pd_offset);
     const Plans<kMulti> P{a, pds};
@@ -210,7 +226,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
 
     // per-lane ledger and counters of the lane's current plan
     double acc_esc = 0.0, acc_neu = 0.0, acc_ovf = 0.0;
-    uint32_t n_steps = 0, n_el = 0, n_ne = 0, n_short = 0, n_dep = 0;
+    uint32_t n_steps = 0, n_el = 0, n_ne = 0, n_short = 0, n_dep = 0, n_glob = 0;
     auto flush = [&](uint32_t pl) {
         double* L = a.ledger + 4 * pl;
         unsigned long long* C = a.counters + 8 * pl;
@@ -222,12 +238,39 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
         if (n_ne) atomicAdd(&C[2], (unsigned long long)n_ne);
         if (n_short) atomicAdd(&C[3], (unsigned long long)n_short);
         if (n_dep) atomicAdd(&C[4], (unsigned long long)n_dep);
+        if (n_glob) atomicAdd(&C[5], (unsigned long long)n_glob);
         acc_esc = acc_neu = acc_ovf = 0.0;
-        n_steps = n_el = n_ne = n_short = n_dep = 0;
+        n_steps = n_el = n_ne = n_short = n_dep = n_glob = 0;
+    };
+    // one deposit into tally element idx of the current plan: through the
+    // workgroup's LDS cache when the slot is free or already holds idx,
+    // else straight to the FP64 tally
+    auto deposit = [&](unsigned long long idx, double v) {
+        ++n_dep;
+        if (use_cache) {
+            const uint32_t key = (uint32_t)idx;
+            uint32_t slot = (key * 0x9E3779B1u) >> slot_shift;
+            for (int probe = 0; probe < a.cache_probes; ++probe) {
+                uint32_t held = ckey[slot];
+                if (held == kEmptySlot) {
+                    held = atomicCAS(&ckey[slot], kEmptySlot, key);
+                    if (held == kEmptySlot) held = key;
+                }
+                if (held == key) {
+                    unsafeAtomicAdd(&cval[slot], v);
+                    return;
+                }
+                slot = (slot + 1u) & (uint32_t)(n_slots - 1);
+            }
+        }
+        unsafeAtomicAdd(&P.tally(plan)[idx], v);
+        ++n_glob;
     };
     bool exhausted = false;
+    bool wave_done = false, counted = false;
 
-    for (;;) {
+    for (;;) {   // epochs: the cache is flushed between them
+    for (int it = 0; !wave_done && (!use_cache || it < a.epoch_iters); ++it) {
         // ---------------------------------------------------------- refill
         const unsigned long long idle = __ballot(!alive);
         const int n_idle = __popcll(idle);
@@ -307,7 +350,10 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
         }
         const unsigned long long busy = __ballot(alive);
         if (busy == 0) {
-            if (exhausted) break;
+            if (exhausted) {
+                wave_done = true;
+                break;
+            }
             continue;
         }
 
@@ -368,8 +414,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
             if (s >= s_range) stop_here = true;
             if (stop_here) {
                 // range-limited: the proton stops in this voxel
-                unsafeAtomicAdd(&P.tally(plan)[vi * K + batch], (double)w * (double)E);
-                ++n_dep;
+                deposit(vi * K + batch, (double)w * (double)E);
                 alive = false;
             } else {
                 // mean loss from the range table (Eq. 2 water-equivalent path)
@@ -447,8 +492,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                     else pz = face;
                 }
                 const float e_new = E - de;
-                unsafeAtomicAdd(&P.tally(plan)[vi * K + batch], (double)w * ((double)E - (double)e_new));
-                ++n_dep;
+                deposit(vi * K + batch, (double)w * ((double)E - (double)e_new));
                 mfp = nuc ? 0.f : fmaxf(mfp - sigma * s, 0.f);
                 E = e_new;
                 ++k;
@@ -456,8 +500,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                 if (E <= kECut || k >= kMaxSteps) {
                     // below the cut-off (or past the step cap that guards
                     // against non-terminating histories): deposit the rest
-                    unsafeAtomicAdd(&P.tally(plan)[vi * K + batch], (double)w * (double)E);
-                    ++n_dep;
+                    deposit(vi * K + batch, (double)w * (double)E);
                     alive = false;
                 } else if (!(locate_axis(px, ux, P.nx(plan), vx) && locate_axis(py, uy, P.ny(plan), vy) &&
                              locate_axis(pz, uz, P.nz(plan), vz))) {
@@ -581,18 +624,15 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                         rotate(rdx, rdy, rdz, cr, sr, phi + 0.5f);
                         const double resid = (double)T - (double)tn_f - (double)tr_f;
                         if (resid != 0.0) {
-                            unsafeAtomicAdd(&P.tally(plan)[vi2], (double)w * resid);
-                            ++n_dep;
+                            deposit(vi2, (double)w * resid);
                         }
                     } else {
-                        unsafeAtomicAdd(&P.tally(plan)[vi2], (double)w * ((double)T - (double)tn_f));
-                        ++n_dep;
+                        deposit(vi2, (double)w * ((double)T - (double)tn_f));
                     }
                     rotate(ux, uy, uz, ct, st, phi);
                     E = tn_f;
                     if (E <= kECut) {
-                        unsafeAtomicAdd(&P.tally(plan)[vi2], (double)w * (double)E);
-                        ++n_dep;
+                        deposit(vi2, (double)w * (double)E);
                         alive = false;
                     } else {
                         mfp = -fln(u01(r3.w));
@@ -640,8 +680,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                     if (n > 2 && ce2 <= kECut) { local += ce2; ce2 = 0.f; }
                     if (n > 3 && ce3 <= kECut) { local += ce3; ce3 = 0.f; }
                     n_out = (ce0 > 0.f) + (ce1 > 0.f) + (ce2 > 0.f) + (ce3 > 0.f);
-                    unsafeAtomicAdd(&P.tally(plan)[vi * K + batch], (double)w * local);
-                    ++n_dep;
+                    deposit(vi * K + batch, (double)w * local);
                     acc_neu += (double)w * ((double)T - loc - carried);
                     alive = false;
                 }
@@ -700,7 +739,27 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                 }
             }
         }
+    }   // iterations of one epoch
+    if (!use_cache) break;
+    if (wave_done && !counted) {
+        counted = true;
+        if (lane == 0) atomicAdd(waves_done, 1u);
     }
+    __syncthreads();
+    // write the epoch's cached sums to the tally and clear the cache
+    for (int i = threadIdx.x; i < n_slots; i += blockDim.x) {
+        const uint32_t key = ckey[i];
+        if (key != kEmptySlot) {
+            unsafeAtomicAdd(&a.single.tally[key], cval[i]);
+            ++n_glob;
+            ckey[i] = kEmptySlot;
+            cval[i] = 0.0;
+        }
+    }
+    const bool all_done = *waves_done == blockDim.x / kWave;
+    __syncthreads();
+    if (all_done) break;
+    }   // epochs
 
     // -------------------------------------------------- flush the ledger
     if constexpr (kMulti) {
@@ -715,6 +774,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
             n_ne += __shfl_xor(n_ne, o);
             n_short += __shfl_xor(n_short, o);
             n_dep += __shfl_xor(n_dep, o);
+            n_glob += __shfl_xor(n_glob, o);
         }
         if (lane == 0) flush(0);
     }
@@ -784,6 +844,13 @@ __global__ void __launch_bounds__(256) stats_kernel(const double* __restrict__ t
     if ((threadIdx.x & 63) == 0 && part != 0.0) unsafeAtomicAdd(dep_sum, part);
 }
 
+__global__ void density_kernel(const uint2* __restrict__ vox, unsigned long long nvox, float* __restrict__ rho)
+{
+    for (unsigned long long v = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; v < nvox;
+         v += (unsigned long long)gridDim.x * blockDim.x)
+        rho[v] = __uint_as_float(vox[v].x);
+}
+
 __global__ void zero_kernel(unsigned long long* __restrict__ p, unsigned long long n)
 {
     for (unsigned long long i = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; i < n;
@@ -806,8 +873,11 @@ hipError_t transport_max_block(bool multi, int* max_threads)
     hipFuncAttributes attr;
     const void* f = multi ? (const void*)transport_kernel<true> : (const void*)transport_kernel<false>;
     hipError_t e = hipFuncGetAttributes(&attr, f);
-    if (e == hipSuccess) *max_threads = attr.maxThreadsPerBlock;
-    return e;
+    if (e != hipSuccess) return e;
+    // the LDS layout assumes the dynamic allocation starts at byte 0
+    if (attr.sharedSizeBytes != 0) return hipErrorInvalidConfiguration;
+    *max_threads = attr.maxThreadsPerBlock;
+    return hipSuccess;
 }
 
 hipError_t transport_occupancy(bool multi, int block, size_t lds_bytes, int* blocks_per_cu)
@@ -832,6 +902,15 @@ hipError_t launch_stats(const double* tally, const uint2* vox, unsigned long lon
     if (blocks == 0) blocks = 1;
     hipLaunchKernelGGL(stats_kernel, dim3((unsigned)blocks), dim3(256), 0, s, tally, vox, nvox, K,
                        conv0, dose, var, dep_sum);
+    return hipGetLastError();
+}
+
+hipError_t launch_density(const uint2* vox, unsigned long long nvox, float* rho, hipStream_t s)
+{
+    unsigned long long blocks = (nvox + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(density_kernel, dim3((unsigned)blocks), dim3(256), 0, s, vox, nvox, rho);
     return hipGetLastError();
 }
 

@@ -206,17 +206,26 @@ __global__ void relu_bwd_kernel(uint16_t* __restrict__ dy, const uint16_t* __res
         if (!(bf2f(y[i]) > 0.f)) dy[i] = 0;
 }
 
-// db[c] += sum_v dy[v][c]
-__global__ void bias_grad_kernel(const uint16_t* __restrict__ dy, float* __restrict__ db, size_t nvox, int C)
+// db[c] += sum_v dy[v][c]: lanes stride over voxels for a fixed channel,
+// the block's partial sums meet in LDS, one atomic per (block, channel)
+__global__ void __launch_bounds__(256) bias_grad_kernel(const uint16_t* __restrict__ dy, float* __restrict__ db,
+                                                        size_t nvox, int C)
 {
+    __shared__ float part[256];
     const int c = threadIdx.x % C;
     const int lanes_per_c = blockDim.x / C;
     const int sub = threadIdx.x / C;
-    if (sub >= lanes_per_c) return;
     float s = 0.f;
-    for (size_t v = (size_t)blockIdx.x * lanes_per_c + sub; v < nvox; v += (size_t)gridDim.x * lanes_per_c)
-        s += bf2f(dy[v * C + c]);
-    atomicAdd(&db[c], s);
+    if (sub < lanes_per_c)
+        for (size_t v = (size_t)blockIdx.x * lanes_per_c + sub; v < nvox; v += (size_t)gridDim.x * lanes_per_c)
+            s += bf2f(dy[v * C + c]);
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x < C) {
+        float t = 0.f;
+        for (int j = 0; j < lanes_per_c; ++j) t += part[j * C + threadIdx.x];
+        atomicAdd(&db[threadIdx.x], t);
+    }
 }
 
 // 2x2x2 average pooling, channels-last
@@ -261,25 +270,32 @@ __global__ void pool_bwd_kernel(const uint16_t* __restrict__ dout, const uint16_
     }
 }
 
-// cat[v] = (coarse[parent(v)][0..Cc), skip[v][0..Cs))  -- nearest 2x upsampling + concat
+// cat[v] = (coarse[parent(v)][0..Cc), skip[v][0..Cs))  -- nearest 2x upsampling + concat;
+// 8 channels (16 bytes) per lane, Cc and Cs multiples of 8
 __global__ void up_concat_kernel(const uint16_t* __restrict__ coarse, const uint16_t* __restrict__ skip,
                                  uint16_t* __restrict__ cat, int N, int D, int H, int W, int Cc, int Cs)
 {
-    const int C = Cc + Cs;
-    const size_t total = (size_t)N * D * H * W * C;
+    const int C8 = (Cc + Cs) >> 3, Cc8 = Cc >> 3, Cs8 = Cs >> 3;
+    const size_t total = (size_t)N * D * H * W * C8;
     const int Ho = H / 2, Wo = W / 2, Do = D / 2;
+    const uint4* cs = reinterpret_cast<const uint4*>(coarse);
+    const uint4* ss = reinterpret_cast<const uint4*>(skip);
+    uint4* dst = reinterpret_cast<uint4*>(cat);
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
-        const int c = (int)(i % C);
-        const size_t v = i / C;
-        size_t r = v;
-        const int x = (int)(r % W); r /= W;
-        const int y = (int)(r % H); r /= H;
-        const int z = (int)(r % D);
-        const int n = (int)(r / D);
-        uint16_t val;
-        if (c < Cc) val = coarse[((((size_t)n * Do + z / 2) * Ho + y / 2) * Wo + x / 2) * Cc + c];
-        else val = skip[v * Cs + (c - Cc)];
-        cat[i] = val;
+        const int c = (int)(i % C8);
+        const size_t v = i / C8;
+        uint4 val;
+        if (c < Cc8) {
+            size_t r = v;
+            const int x = (int)(r % W); r /= W;
+            const int y = (int)(r % H); r /= H;
+            const int z = (int)(r % D);
+            const int n = (int)(r / D);
+            val = cs[((((size_t)n * Do + z / 2) * Ho + y / 2) * Wo + x / 2) * Cc8 + c];
+        } else {
+            val = ss[v * Cs8 + (c - Cc8)];
+        }
+        dst[i] = val;
     }
 }
 
@@ -310,12 +326,14 @@ __global__ void up_concat_bwd_coarse_kernel(const uint16_t* __restrict__ dcat, u
 __global__ void up_concat_bwd_skip_kernel(const uint16_t* __restrict__ dcat, uint16_t* __restrict__ dskip,
                                           size_t nvox, int Cc, int Cs)
 {
-    const int C = Cc + Cs;
-    const size_t total = nvox * Cs;
+    const int C8 = (Cc + Cs) >> 3, Cc8 = Cc >> 3, Cs8 = Cs >> 3;
+    const size_t total = nvox * Cs8;
+    const uint4* src = reinterpret_cast<const uint4*>(dcat);
+    uint4* dst = reinterpret_cast<uint4*>(dskip);
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
-        const size_t v = i / Cs;
-        const int c = (int)(i % Cs);
-        dskip[i] = dcat[v * C + Cc + c];
+        const size_t v = i / Cs8;
+        const int c = (int)(i % Cs8);
+        dst[i] = src[v * C8 + Cc8 + c];
     }
 }
 
@@ -333,14 +351,21 @@ __global__ void make_input_kernel(const float* __restrict__ dose, const float* _
     }
 }
 
-// scale[0] = max_v dose[v]  (non-negative input; scale must start at 0)
-__global__ void max_kernel(const float* __restrict__ a, size_t n, float* __restrict__ scale)
+// scale[0] = max_v dose[v]  (non-negative input; scale must start at 0);
+// one atomic per block
+__global__ void __launch_bounds__(256) max_kernel(const float* __restrict__ a, size_t n, float* __restrict__ scale)
 {
+    __shared__ float part[4];
     float m = 0.f;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         m = fmaxf(m, a[i]);
     for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
-    if ((threadIdx.x & 63) == 0) atomicMax(reinterpret_cast<unsigned int*>(scale), __float_as_uint(m));
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        m = fmaxf(fmaxf(part[0], part[1]), fmaxf(part[2], part[3]));
+        atomicMax(reinterpret_cast<unsigned int*>(scale), __float_as_uint(m));
+    }
 }
 
 // head: out[v] = scale * (dose[v]/scale + sum_c w[c] d1[v][c] + b)  (1x1x1, 16 -> 1, residual)
@@ -356,20 +381,30 @@ __global__ void head_fwd_kernel(const uint16_t* __restrict__ d1, const float* __
     }
 }
 
-// MSE loss in normalised units over voxels with weight mask (all ones when
-// mask is NULL): L = sum_v m_v (out_v - t_v)^2 / scale^2 / sum m_v.  Writes
-// g[v] = dL/d(head pre-activation) = 2 m_v (out_v - t_v) / scale / sum m_v,
-// accumulates the head gradients and the loss.
-__global__ void loss_head_bwd_kernel(const float* __restrict__ out, const float* __restrict__ target,
-                                     const float* __restrict__ scale, const uint16_t* __restrict__ d1,
-                                     const float* __restrict__ w, uint16_t* __restrict__ dd1,
-                                     float* __restrict__ dw, float* __restrict__ db, double* __restrict__ loss,
-                                     size_t nvox, int C, float inv_count)
+// MSE loss in normalised units, L = mean_v ((out_v - t_v) / scale)^2, and
+// the head backward: g_v = dL/d(head pre-activation) = 2 (out_v - t_v) /
+// scale / nvox; dd1[v][c] = g_v w[c]; dw[c] += sum_v g_v d1[v][c];
+// db += sum_v g_v; loss += L.  C = 16 channels: one 32-byte row per voxel.
+// Block partial sums meet in LDS; one atomic per block and quantity.
+__global__ void __launch_bounds__(256) loss_head_bwd_kernel(const float* __restrict__ out,
+                                                            const float* __restrict__ target,
+                                                            const float* __restrict__ scale,
+                                                            const uint16_t* __restrict__ d1,
+                                                            const float* __restrict__ w,
+                                                            uint16_t* __restrict__ dd1, float* __restrict__ dw,
+                                                            float* __restrict__ db, double* __restrict__ loss,
+                                                            size_t nvox, float inv_count)
 {
+    __shared__ float sg[4][17];
+    __shared__ double sl[4];
     const float sc = fmaxf(scale[0], 1e-30f);
     const float isc = 1.0f / sc;
-    float gw[16];
-    for (int c = 0; c < 16; ++c) gw[c] = 0.f;
+    float wv[16], gw[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        wv[c] = w[c];
+        gw[c] = 0.f;
+    }
     float gb = 0.f;
     double l = 0.0;
     for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < nvox; v += (size_t)gridDim.x * blockDim.x) {
@@ -377,20 +412,42 @@ __global__ void loss_head_bwd_kernel(const float* __restrict__ out, const float*
         l += (double)e * e;
         const float g = 2.f * e * inv_count;
         gb += g;
-        for (int c = 0; c < C; ++c) {
-            gw[c] += g * bf2f(d1[v * C + c]);
-            dd1[v * C + c] = f2bf(g * w[c]);
+        const uint4* src = reinterpret_cast<const uint4*>(d1 + v * 16);
+        uint4* dst = reinterpret_cast<uint4*>(dd1 + v * 16);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint4 q = src[h];
+            const uint32_t in[4] = {q.x, q.y, q.z, q.w};
+            uint32_t o[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int c = 8 * h + 2 * k;
+                gw[c] += g * __uint_as_float(in[k] << 16);
+                gw[c + 1] += g * __uint_as_float(in[k] & 0xFFFF0000u);
+                o[k] = (uint32_t)f2bf(g * wv[c]) | ((uint32_t)f2bf(g * wv[c + 1]) << 16);
+            }
+            dst[h] = make_uint4(o[0], o[1], o[2], o[3]);
         }
     }
     for (int o = 32; o > 0; o >>= 1) {
         gb += __shfl_xor(gb, o);
         l += __shfl_xor(l, o);
+#pragma unroll
         for (int c = 0; c < 16; ++c) gw[c] += __shfl_xor(gw[c], o);
     }
+    const int wave = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
-        atomicAdd(db, gb);
-        for (int c = 0; c < C; ++c) atomicAdd(&dw[c], gw[c]);
-        atomicAdd(loss, l * inv_count);
+#pragma unroll
+        for (int c = 0; c < 16; ++c) sg[wave][c] = gw[c];
+        sg[wave][16] = gb;
+        sl[wave] = l;
+    }
+    __syncthreads();
+    if (threadIdx.x < 17) {
+        const float t = sg[0][threadIdx.x] + sg[1][threadIdx.x] + sg[2][threadIdx.x] + sg[3][threadIdx.x];
+        atomicAdd(threadIdx.x < 16 ? &dw[threadIdx.x] : db, t);
+    } else if (threadIdx.x == 32) {
+        atomicAdd(loss, (sl[0] + sl[1] + sl[2] + sl[3]) * inv_count);
     }
 }
 
@@ -478,7 +535,8 @@ hipError_t nn_relu_bwd(uint16_t* dy, const uint16_t* y, size_t n, hipStream_t s)
 
 hipError_t nn_bias_grad(const uint16_t* dy, float* db, size_t nvox, int C, hipStream_t s)
 {
-    hipLaunchKernelGGL(bias_grad_kernel, dim3(1024), dim3(256), 0, s, dy, db, nvox, C);
+    if (C < 1 || C > 256) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(bias_grad_kernel, dim3(grid_for(nvox, 256, 512)), dim3(256), 0, s, dy, db, nvox, C);
     return hipGetLastError();
 }
 
@@ -498,24 +556,26 @@ hipError_t nn_pool_bwd(const uint16_t* dout, const uint16_t* add, uint16_t* din,
 hipError_t nn_up_concat(const uint16_t* coarse, const uint16_t* skip, uint16_t* cat, int N, int D, int H, int W,
                         int Cc, int Cs, hipStream_t s)
 {
-    hipLaunchKernelGGL(up_concat_kernel, dim3(grid_for((size_t)N * D * H * W * (Cc + Cs))), dim3(256), 0, s, coarse, skip,
-                       cat, N, D, H, W, Cc, Cs);
+    if ((Cc | Cs) & 7) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(up_concat_kernel, dim3(grid_for((size_t)N * D * H * W * (Cc + Cs) / 8)), dim3(256), 0, s, coarse,
+                       skip, cat, N, D, H, W, Cc, Cs);
     return hipGetLastError();
 }
 
 hipError_t nn_up_concat_bwd(const uint16_t* dcat, uint16_t* dcoarse, uint16_t* dskip, int N, int D, int H, int W,
                             int Cc, int Cs, hipStream_t s)
 {
+    if ((Cc | Cs) & 7) return hipErrorInvalidValue;
     hipLaunchKernelGGL(up_concat_bwd_coarse_kernel, dim3(grid_for((size_t)N * D * H * W * Cc / 8)), dim3(256), 0, s, dcat,
                        dcoarse, N, D, H, W, Cc, Cs);
-    hipLaunchKernelGGL(up_concat_bwd_skip_kernel, dim3(grid_for((size_t)N * D * H * W * Cs)), dim3(256), 0, s, dcat, dskip,
-                       (size_t)N * D * H * W, Cc, Cs);
+    hipLaunchKernelGGL(up_concat_bwd_skip_kernel, dim3(grid_for((size_t)N * D * H * W * Cs / 8)), dim3(256), 0, s, dcat,
+                       dskip, (size_t)N * D * H * W, Cc, Cs);
     return hipGetLastError();
 }
 
 hipError_t nn_make_input(const float* dose, const float* rho, float* scale, uint16_t* x, size_t nvox, hipStream_t s)
 {
-    hipLaunchKernelGGL(max_kernel, dim3(grid_for(nvox, 256, 4096)), dim3(256), 0, s, dose, nvox, scale);
+    hipLaunchKernelGGL(max_kernel, dim3(grid_for(nvox, 256, 1024)), dim3(256), 0, s, dose, nvox, scale);
     hipLaunchKernelGGL(make_input_kernel, dim3(grid_for(nvox)), dim3(256), 0, s, dose, rho, scale, x, nvox);
     return hipGetLastError();
 }
@@ -531,8 +591,9 @@ hipError_t nn_loss_head_bwd(const float* out, const float* target, const float* 
                             const float* w, uint16_t* dd1, float* dw, float* db, double* loss, size_t nvox, int C,
                             hipStream_t s)
 {
-    hipLaunchKernelGGL(loss_head_bwd_kernel, dim3(grid_for(nvox, 256, 2048)), dim3(256), 0, s, out, target, scale, d1, w,
-                       dd1, dw, db, loss, nvox, C, 1.0f / (float)nvox);
+    if (C != 16) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(loss_head_bwd_kernel, dim3(grid_for(nvox, 256, 1024)), dim3(256), 0, s, out, target, scale, d1, w,
+                       dd1, dw, db, loss, nvox, 1.0f / (float)nvox);
     return hipGetLastError();
 }
 

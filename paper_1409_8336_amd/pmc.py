@@ -23,7 +23,7 @@ PMC_NO_STRAGGLE, PMC_NO_MCS, PMC_NO_NUCLEAR = 1, 2, 4
 EXPORTS = ("pmc_default_params", "pmc_create", "pmc_destroy", "pmc_last_error",
            "pmc_load_physics", "pmc_load_geometry", "pmc_run_spots", "pmc_run_spots_dev",
            "pmc_inspect_tables", "pmc_atomic_probe", "pmc_load_geometry_slot", "pmc_run_plans",
-           "pmc_version")
+           "pmc_geometry_density", "pmc_version")
 
 
 class PMCError(RuntimeError):
@@ -36,7 +36,9 @@ class pmc_params(C.Structure):
     _fields_ = [("f_mcs", C.c_double), ("s_min_cm", C.c_double), ("k_batches", C.c_int32),
                 ("flags", C.c_uint32), ("queue_capacity", C.c_uint32),
                 ("block_threads", C.c_int32), ("blocks_per_cu", C.c_int32),
-                ("refill_lanes", C.c_int32), ("batch_events", C.c_int32)]
+                ("refill_lanes", C.c_int32), ("batch_events", C.c_int32),
+                ("tally_cache", C.c_int32), ("epoch_steps", C.c_int32),
+                ("cache_probes", C.c_int32)]
 
 
 class pmc_spot(C.Structure):
@@ -64,7 +66,7 @@ class pmc_summary(C.Structure):
                 ("n_short_steps", C.c_uint64), ("tally_atomics", C.c_uint64),
                 ("total_weight", C.c_double), ("device_ms", C.c_double),
                 ("transport_ms", C.c_double), ("generations", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("reserved", C.c_int32), ("global_atomics", C.c_uint64)]
 
 
 class pmc_plan(C.Structure):
@@ -105,6 +107,7 @@ def lib():
         L.pmc_load_geometry_slot.argtypes = [vp, C.POINTER(C.c_int), vp, i32, i32, i32, C.c_float,
                                              C.c_float, C.c_float, C.POINTER(pmc_material_table)]
         L.pmc_run_plans.argtypes = [vp, C.POINTER(pmc_plan), i32, u64, vp]
+        L.pmc_geometry_density.argtypes = [vp, i32, vp, vp]
         L.pmc_version.restype = C.c_char_p
         for name in EXPORTS:
             if name not in ("pmc_last_error", "pmc_version"):
@@ -133,7 +136,10 @@ def pmc_last_error(ctx=None) -> str:
 def pmc_default_params(**overrides) -> pmc_params:
     p = pmc_params()
     lib().pmc_default_params(C.byref(p))
+    names = {f[0] for f in pmc_params._fields_}
     for k, v in overrides.items():
+        if k not in names:
+            raise ValueError("unknown engine parameter %r" % k)
         setattr(p, k, v)
     return p
 
@@ -277,6 +283,19 @@ def pmc_atomic_probe(ctx, n_atomics, stream=None):
     _check(ctx, lib().pmc_atomic_probe(ctx, int(n_atomics), C.c_void_p(handle) if handle else None,
                                        C.byref(ms)))
     return ms.value
+
+
+def pmc_geometry_density(ctx, geometry_id, d_rho, stream=None):
+    """Voxel densities (g/cm^3) of a loaded geometry into a float32 device
+    tensor of nz*ny*nx elements."""
+    import torch
+    if d_rho.dtype != torch.float32 or not d_rho.is_cuda or not d_rho.is_contiguous():
+        raise ValueError("d_rho must be a contiguous float32 device tensor")
+    if stream is None:
+        stream = torch.cuda.current_stream(d_rho.device)
+    handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+    _check(ctx, lib().pmc_geometry_density(ctx, int(geometry_id), C.c_void_p(d_rho.data_ptr()),
+                                           C.c_void_p(handle)))
 
 
 class Engine:

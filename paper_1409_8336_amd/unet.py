@@ -15,9 +15,12 @@ EXPORTS = ("pmc_unet_create", "pmc_unet_destroy", "pmc_unet_last_error", "pmc_un
            "pmc_unet_get_params", "pmc_unet_set_params", "pmc_unet_forward", "pmc_unet_backward",
            "pmc_unet_get_grads", "pmc_unet_zero_grads", "pmc_unet_adam_step",
            "pmc_nn_conv3d_forward", "pmc_nn_conv3d_backward_data", "pmc_nn_conv3d_backward_weight",
-           "pmc_gamma_index")
+           "pmc_gamma_index", "pmc_denoise_disagreement")
 
 _ready = False
+# element count of one network input, per handle (the C calls take bare
+# pointers sized at creation)
+_numel = {}
 
 
 def lib():
@@ -42,6 +45,8 @@ def lib():
         L.pmc_nn_conv3d_backward_weight.argtypes = [vp, vp, vp, i32, i32, i32, i32, i32, i32, vp]
         L.pmc_gamma_index.argtypes = [vp, vp, i32, i32, i32, f32, f32, f32, f32, f32, f32, f32, f32,
                                       vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), vp]
+        L.pmc_denoise_disagreement.argtypes = [vp, vp, vp, C.c_int64, f32, f32, C.POINTER(C.c_double),
+                                               C.POINTER(C.c_int64), vp]
         for name in EXPORTS:
             if name != "pmc_unet_last_error":
                 getattr(L, name).restype = C.c_int
@@ -72,11 +77,20 @@ def _stream(stream, device=0):
 def pmc_unet_create(device, n, d, h, w, seed):
     u = C.c_void_p()
     _check(None, lib().pmc_unet_create(C.byref(u), int(device), n, d, h, w, int(seed)))
+    _numel[u.value] = n * d * h * w
     return u
 
 
 def pmc_unet_destroy(u):
+    _numel.pop(u.value, None)
     _check(None, lib().pmc_unet_destroy(u))
+
+
+def _sized(u, *tensors):
+    want = _numel.get(u.value)
+    for t in tensors:
+        if want is None or t.numel() != want:
+            raise ValueError("tensor has %d elements, the network takes %s" % (t.numel(), want))
 
 
 def pmc_unet_param_count(u) -> int:
@@ -110,6 +124,7 @@ def pmc_unet_zero_grads(u, stream=None):
 
 def pmc_unet_forward(u, dose, density, out, stream=None):
     import torch
+    _sized(u, dose, density, out)
     f = torch.float32
     _check(u, lib().pmc_unet_forward(u, _dev(dose, f, "dose"), _dev(density, f, "density"),
                                      _dev(out, f, "out"), _stream(stream, dose.device)))
@@ -117,6 +132,7 @@ def pmc_unet_forward(u, dose, density, out, stream=None):
 
 def pmc_unet_backward(u, dose, density, target, stream=None) -> float:
     import torch
+    _sized(u, dose, density, target)
     f = torch.float32
     loss = C.c_double()
     _check(u, lib().pmc_unet_backward(u, _dev(dose, f, "dose"), _dev(density, f, "density"),
@@ -186,6 +202,22 @@ def pmc_gamma_index(ref, ev, voxel_cm, dose_frac=0.02, dta_cm=0.2, cutoff_frac=0
                                        dta_cm, cutoff_frac, search_cm, step_cm, g, C.byref(rate),
                                        C.byref(n), _stream(stream, ref.device)))
     return rate.value, n.value
+
+
+def pmc_denoise_disagreement(den, mc, var_mc, cutoff_frac=0.1, k_sigma=4.0, stream=None):
+    """Fraction of voxels above cutoff_frac * max(mc) where the denoised
+    dose (float32 tensor) departs from the Monte Carlo dose (float64) by more
+    than k_sigma standard errors; returns (fraction, count above cutoff)."""
+    import torch
+    if den.numel() != mc.numel() or var_mc.numel() != mc.numel():
+        raise ValueError("tensors must have the same number of elements")
+    frac = C.c_double()
+    n = C.c_int64()
+    _check(None, lib().pmc_denoise_disagreement(_dev(den, torch.float32, "den"), _dev(mc, torch.float64, "mc"),
+                                                _dev(var_mc, torch.float64, "var_mc"), mc.numel(),
+                                                cutoff_frac, k_sigma, C.byref(frac), C.byref(n),
+                                                _stream(stream, mc.device)))
+    return frac.value, n.value
 
 
 class UNet:

@@ -253,6 +253,33 @@ def test_launch_shape_does_not_change_results(nd, mt):
             assert s[k] == ref[1][k], (k, params)
 
 
+def test_deposit_cache_preserves_results(nd, mt):
+    """The workgroup LDS deposit cache only regroups FP64 additions: dose,
+    step and event counts equal the uncached run; with the cache on fewer
+    atomics reach device memory, and a tiny cache flushed every 7 iterations
+    (many misses and evictions) gives the same results."""
+    _say("case: deposit cache")
+    cfg = synth.config_ct_spots(150.0, 30_000)
+    runs = []
+    for params in (dict(block_threads=1024, tally_cache=-1), dict(block_threads=1024),
+                   dict(block_threads=1024, tally_cache=512, epoch_steps=7),
+                   dict(block_threads=512, tally_cache=2048, epoch_steps=300)):
+        e = _engine(nd, mt, cfg["hu"], **params)
+        d, v, s = e.run_spots(cfg["spots"], cfg["n_histories"], 6)
+        e.close()
+        runs.append((params, d, v, s))
+    p0, d0, v0, s0 = runs[0]
+    assert s0["global_atomics"] == s0["tally_atomics"]
+    for params, d, v, s in runs[1:]:
+        np.testing.assert_allclose(d, d0, rtol=1e-9, atol=1e-9 * d0.max())
+        np.testing.assert_allclose(v, v0, rtol=1e-6, atol=1e-9 * v0.max())
+        for k in ("steps", "n_elastic", "n_nonelastic", "secondaries", "tally_atomics"):
+            assert s[k] == s0[k], (k, params)
+        assert abs(s["deposited"] - s0["deposited"]) <= 1e-12 * s0["deposited"]
+        assert s["global_atomics"] < s0["global_atomics"], params
+        _say("%s: global atomics %d of %d deposits" % (params, s["global_atomics"], s["tally_atomics"]))
+
+
 def test_device_buffers_match_host_buffers(nd, mt):
     import torch
     _say("case: device buffers")
