@@ -32,8 +32,8 @@ HBM_PEAK = 8.0e12
 # HBM bytes per transport launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
 # scaled by a plain-copy calibration, valid only for the kernel source whose
 # sha256 is recorded (see profiles/); None once the kernel has changed.
-TRAFFIC = {"transport_sha256": "982298d949ac98de847e6aba75853773348c2078c5314f6695063606a3004e1b",
-           "bytes_per_launch": 5.386e9}
+TRAFFIC = {"transport_sha256": "1b16c75b950b37798d0e0b395d11d2515572aafabc43c265e9da9dcabf20a747",
+           "bytes_per_launch": 3.057e9}
 
 
 def _kernel_sha():
@@ -205,6 +205,8 @@ def main():
         "steps_per_s": steps_tot / elapsed,
         "steps_per_history": steps_tot / n_tot,
         "transport_launches_per_step": launches / args.steps,
+        "launch_shape": {k: sums[-1][k] for k in ("block_threads", "grid_blocks", "cache_slots",
+                                                   "epoch_steps")},
         "transport_ms_per_step": 1e3 * transport_s / args.steps,
         "ledger_residual_max": worst_res,
         "roofline": {

@@ -75,7 +75,7 @@ typedef struct {
                                 power of two 512..16384; 0 = automatic (the tuner may turn it off,
                                 else sized from the LDS left by the tables); -1 = off (every
                                 deposit is a global FP64 atomic) */
-    int32_t epoch_steps;     /* loop iterations between cache flushes; 0 = 64 */
+    int32_t epoch_steps;     /* loop iterations between cache flushes; 0 = 32 */
     int32_t cache_probes;    /* cache slots tried per deposit (linear probing), 1..16; 0 = 4 */
 } pmc_params;
 /* Autotuning: when any of block_threads, refill_lanes, batch_events is 0 and
@@ -142,6 +142,10 @@ typedef struct {
     int32_t reserved;
     uint64_t global_atomics; /* FP64 atomic adds that reached the tally in device memory
                                 (deposits that missed the LDS cache plus cache flushes) */
+    int32_t block_threads;   /* launch shape used: workgroup size, */
+    int32_t grid_blocks;     /* workgroups in the persistent grid, */
+    int32_t cache_slots;     /* deposit-cache slots per workgroup (0 = off), */
+    int32_t epoch_steps;     /* loop iterations between cache flushes */
 } pmc_summary;
 
 typedef struct pmc_ctx pmc_ctx;

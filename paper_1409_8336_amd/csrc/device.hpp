@@ -81,6 +81,12 @@ struct KernelArgs {
     int cache_off;
     int epoch_iters;
     int cache_probes;   // slots tried (linear probing) before a deposit goes to the tally
+    // work claims: workgroup b of a launch of G workgroups takes its j-th
+    // index from its own counter wg_claims[gen * G + b] and maps it to
+    // ((j >> claim_log2) * G + b) << claim_log2 | (j & (2^claim_log2 - 1)),
+    // i.e. chunks of 2^claim_log2 consecutive indices dealt round-robin
+    unsigned long long* wg_claims;
+    int claim_log2;
 };
 
 }  // namespace pmc

@@ -111,7 +111,7 @@ struct pmc_ctx {
     // run buffers
     DevBuf<double> d_dose, d_var, d_ledger;
     DevBuf<uint32_t> d_q[2];
-    DevBuf<unsigned long long> d_gc, d_counters, d_spot_start;
+    DevBuf<unsigned long long> d_gc, d_counters, d_spot_start, d_wgc;
     DevBuf<float> d_spots;
     DevBuf<PlanDesc> d_plans;
     unsigned long long* h_pinned = nullptr;   // pinned read-back area
@@ -459,7 +459,7 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
     a.cache_log2 = 0;
     while (slots > 0 && (1 << a.cache_log2) < slots) ++a.cache_log2;
     a.cache_off = (int)((lds_words + 1) & ~(size_t)1);
-    a.epoch_iters = c->p.epoch_steps ? c->p.epoch_steps : 64;
+    a.epoch_iters = c->p.epoch_steps ? c->p.epoch_steps : 32;
     a.cache_probes = c->p.cache_probes ? c->p.cache_probes : 4;
     const size_t lds = slots ? (size_t)(a.cache_off + 3 * slots + 1) * 4 : lds_words * 4;
     int max_block = 0;
@@ -470,12 +470,19 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
     if (fit < 1) return fail(c, PMC_ERR_DEVICE, "transport kernel does not fit on a CU");
     if (bpc == 0 || bpc > fit) bpc = fit;
     const int grid = c->num_cu * bpc;
+    // per-workgroup claim counters of every generation
+    HIPCHK(c->d_wgc.ensure((size_t)kMaxGenerations * grid), "alloc claim counters");
+    HIPCHK(launch_zero(c->d_wgc.p, (size_t)kMaxGenerations * grid * 8, st), "zero claim counters");
+    a.wg_claims = c->d_wgc.p;
     int gens = 0;
     unsigned long long produced_total = 0, overflow_n = 0;
     if (total > 0) {
         for (int gidx = 0;; ++gidx) {
             if (gidx >= kMaxGenerations) return fail(c, PMC_ERR_DEVICE, "secondary generations exceed limit");
             a.gen = gidx;
+            // primaries in runs of 1024 consecutive histories (one spot's
+            // worth, for the deposit cache), secondaries in runs of 64
+            a.claim_log2 = gidx == 0 ? 10 : 6;
             a.q_in = c->d_q[gidx & 1].p;
             a.q_out = c->d_q[(gidx + 1) & 1].p;
             HIPCHK(hipEventRecord(c->ev_gen[2 * gidx], st), "event");
@@ -537,6 +544,10 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
             sm->n_short_steps = cnt[8 * p + 3];
             sm->tally_atomics = cnt[8 * p + 4];
             sm->global_atomics = cnt[8 * p + 5];
+            sm->block_threads = block;
+            sm->grid_blocks = grid;
+            sm->cache_slots = slots;
+            sm->epoch_steps = slots ? a.epoch_iters : 0;
             sm->secondaries = produced_total;
             sm->n_overflow = overflow_n;
             sm->total_weight = wtot[p];
@@ -576,10 +587,12 @@ pmc_status choose_shape(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, hipS
         *out = it->second;
         return PMC_OK;
     }
-    // calibration work of about 2e5 histories.  One geometry: the first
-    // spots of the list with their own history counts, which keeps the
-    // spatial coherence of the work (what the deposit cache relies on);
-    // several plans: every plan scaled down.
+    // calibration work: a fifth of the run, 2e5 to 2e6 histories, enough to
+    // reach the steady state of a full grid of 1024-lane workgroups.  One
+    // geometry: the first spots of the list with their own history counts,
+    // which keeps the spatial coherence of the work (what the deposit cache
+    // relies on); several plans: every plan scaled down.
+    const double cal_hist = std::min(2.0e6, std::max(2.0e5, 0.2 * (double)total));
     std::vector<PlanIn> cal = plans;
     if (!multi) {
         PlanIn& p = cal[0];
@@ -587,7 +600,7 @@ pmc_status choose_shape(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, hipS
         for (int i = 0; i < p.n_spots; ++i) wsum += p.spots[i].weight;
         double acc = 0.0;
         int m = 0;
-        while (m < p.n_spots && acc < 200000.0) {
+        while (m < p.n_spots && acc < cal_hist) {
             acc += wsum > 0.0 ? (double)p.n_hist * p.spots[m].weight / wsum : 0.0;
             ++m;
         }
@@ -595,7 +608,7 @@ pmc_status choose_shape(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, hipS
         p.n_hist = std::max<unsigned long long>(1ull, (unsigned long long)std::llround(acc));
         p.summary = nullptr;
     } else {
-        const double f = 200000.0 / (double)total;
+        const double f = cal_hist / (double)total;
         for (PlanIn& p : cal) {
             p.n_hist = (unsigned long long)std::ceil(p.n_hist * f);
             p.summary = nullptr;

@@ -208,7 +208,13 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
 
     const int lane = threadIdx.x & (kWave - 1);
     const int gen = a.gen;
-    unsigned long long* const claim = &a.gen_counters[2 * gen + 1];
+    unsigned long long* const claim = &a.wg_claims[(size_t)gen * gridDim.x + blockIdx.x];
+    const uint32_t cl2 = (uint32_t)a.claim_log2;
+    const unsigned long long cmask = (1ull << cl2) - 1ull;
+    // the workgroup's j-th claim -> index into the generation's work list
+    auto claim_index = [&](unsigned long long j) {
+        return ((((j >> cl2) * gridDim.x) + blockIdx.x) << cl2) | (j & cmask);
+    };
     unsigned long long* const out_reserve = &a.gen_counters[2 * (gen + 1)];
     unsigned long long limit = a.n_primary;
     if (gen > 0) {
@@ -278,9 +284,9 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
             unsigned long long base = 0;
             if (lane == 0) base = atomicAdd(claim, (unsigned long long)n_idle);
             base = bcast0(base);
-            if (base + (unsigned long long)n_idle >= limit) exhausted = true;
+            if (claim_index(base + (unsigned long long)n_idle) >= limit) exhausted = true;
             if (!alive) {
-                const unsigned long long idx = base + (unsigned long long)mbcnt(idle);
+                const unsigned long long idx = claim_index(base + (unsigned long long)mbcnt(idle));
                 if (idx < limit) {
                     if (gen == 0) {
                         // source: Gaussian spot on the z = 0 face (K1 role)

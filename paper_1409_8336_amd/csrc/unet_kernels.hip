@@ -108,21 +108,27 @@ __global__ void flip_weights_kernel(const uint16_t* __restrict__ w, uint16_t* __
     }
 }
 
-// Weight gradient.  Workgroup = (a chunk of rows) x (kz) x (32-channel input
-// block) x (64-channel output block).  For each 32-voxel x segment the
-// output-gradient tile and the 3 input rows of kz (ky = 0..2) are staged in
-// LDS transposed (channel-major), then each wave accumulates 16x16 tiles of
-// dW[co][(kz*9+ky*3+kx)*Cin + ci] with K = 32 voxels per MFMA, and adds its
-// partial sums to the FP32 gradient with atomics at the end.
-constexpr int kWgTiles = 18;   // (4 co tiles x 9 (ky,kx) x 2 ci tiles) / 4 waves
+// Weight gradient.  Workgroup = (a run of rows) x kz x (32-channel input
+// block) x (64-channel output block).  For tap (kz, ky, kx):
+//   dW[co][ci] += sum_x dout[x][co] in[x + kx - 1][ci]
+//               = sum_x' dout[x' - kx + 1][co] in[x'][ci],
+// so per 64-voxel segment of a row the input rows are staged once (aligned,
+// no halo) and the output gradient three times, shifted by kx, both
+// transposed in LDS (voxel index fastest): every MFMA operand is one aligned
+// 16-byte LDS read, A = output-gradient rows (16 channels x 32 voxels), B =
+// input columns (32 voxels x 16 channels).  The waves split the 16-channel
+// output tiles of the block; where the block has fewer than four of them,
+// they also split the two 32-voxel K-steps and the two input tiles.
+constexpr int kWgSeg = 64;              // voxels per staged segment (two MFMA K-steps)
+constexpr int kWgPitch = kWgSeg + 8;    // LDS row pitch in elements (16-byte multiple)
 __global__ void __launch_bounds__(256) conv3d_wgrad_kernel(const uint16_t* __restrict__ in,
                                                            const uint16_t* __restrict__ dout,
                                                            float* __restrict__ dw, int N, int D,
                                                            int H, int W, int Cin, int Cout, int Kp,
                                                            int rows_per_block)
 {
-    __shared__ uint16_t sdo[64][40];        // [co][x] (32 used, padded)
-    __shared__ uint16_t sin[3][32][40];     // [ky][ci][x+1] (34 used, padded)
+    __shared__ __attribute__((aligned(16))) uint16_t sdo[3][64][kWgPitch];
+    __shared__ __attribute__((aligned(16))) uint16_t sin[3][32][kWgPitch];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int m = lane & 15, g = lane >> 4;
     const int n_ci_blk = (Cin + 31) / 32;
@@ -130,62 +136,100 @@ __global__ void __launch_bounds__(256) conv3d_wgrad_kernel(const uint16_t* __res
     const int cib = (blockIdx.y / 3) % n_ci_blk;
     const int cob = blockIdx.y / (3 * n_ci_blk);
     const int ci0 = cib * 32, co0 = cob * 64;
+    // this wave's share: output tile ct, K-steps and input tiles
+    const int n_cot = min(4, (Cout - co0 + 15) / 16);
+    int ct, ks_sel = -1, cit_sel = -1;
+    if (n_cot >= 3) {
+        ct = wave;
+    } else if (n_cot == 2) {
+        ct = wave & 1;
+        ks_sel = wave >> 1;
+    } else {
+        ct = 0;
+        ks_sel = wave & 1;
+        cit_sel = wave >> 1;
+    }
+    const bool active = ct < n_cot;
     const int total_rows = N * D * H;
     const int row0 = blockIdx.x * rows_per_block;
-    f32x4 acc[kWgTiles];
+    const size_t plane = (size_t)H * W;
+    f32x4 acc[18];
 #pragma unroll
-    for (int t = 0; t < kWgTiles; ++t) acc[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
-    // tile t of this wave: global tile id q = wave * 18 + t over (co tile 0..3) x (ky,kx 0..8) x (ci tile 0..1)
+    for (int t = 0; t < 18; ++t) acc[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
     for (int r = row0; r < row0 + rows_per_block && r < total_rows; ++r) {
         const int y = r % H, nz = r / H, z = nz % D;
-        const size_t plane = (size_t)H * W;
         const size_t nbase = (size_t)(nz - z) * plane;
         const int zz = z + kz - 1;
-        for (int xb = 0; xb < W; xb += 32) {
+        const bool zin = zz >= 0 && zz < D;
+        for (int xb = 0; xb < W; xb += kWgSeg) {
             __syncthreads();
-            // stage dout[v][co0..co0+63] for x in [xb, xb+32)
-            for (int i = threadIdx.x; i < 64 * 32; i += 256) {
-                const int co = i & 63, x = i >> 6;
-                uint16_t v = 0;
-                if (co0 + co < Cout && xb + x < W)
-                    v = dout[(nbase + (size_t)z * plane + (size_t)y * W + xb + x) * Cout + co0 + co];
-                sdo[co][x] = v;
-            }
-            // stage in rows (zz, y+ky-1) at x in [xb-1, xb+33), channels ci0..ci0+31
-            for (int i = threadIdx.x; i < 3 * 32 * 34; i += 256) {
-                const int ci = i & 31, rest = i >> 5;
-                const int xo = rest % 34, ky = rest / 34;
-                const int yy = y + ky - 1, xx = xb + xo - 1;
-                uint16_t v = 0;
-                if (ci0 + ci < Cin && zz >= 0 && zz < D && yy >= 0 && yy < H && xx >= 0 && xx < W)
-                    v = in[(nbase + (size_t)zz * plane + (size_t)yy * W + xx) * Cin + ci0 + ci];
-                sin[ky][ci][xo] = v;
-            }
-            __syncthreads();
-            // A operand: dout^T rows = co, K = x  (lane: co = m, x = 8g..8g+7)
+            // output gradient at x = xb - 1 .. xb + 64 (slot xs = x - xb + 1),
+            // 8 channels per task, into the copy of each kx where it is used
+            for (int i = threadIdx.x; i < (kWgSeg + 2) * 8; i += 256) {
+                const int cg = i & 7, xs = i >> 3;
+                const int x = xb + xs - 1;
+                uint4 v = make_uint4(0u, 0u, 0u, 0u);
+                if (x >= 0 && x < W && co0 + 8 * cg < Cout)
+                    v = *reinterpret_cast<const uint4*>(
+                        dout + (nbase + (size_t)z * plane + (size_t)y * W + x) * Cout + co0 + 8 * cg);
+                const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-            for (int t = 0; t < kWgTiles; ++t) {
-                const int q = wave * kWgTiles + t;
-                const int ct = q / 18, rem = q % 18;
-                const int kyx = rem >> 1, cit = rem & 1;
-                const int ky = kyx / 3, kx = kyx % 3;
-                bf16x8 a, b;
+                for (int kx = 0; kx < 3; ++kx) {
+                    const int xp = xs + kx - 2;     // x' - xb with x' = x + kx - 1
+                    if (xp < 0 || xp >= kWgSeg) continue;
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const uint16_t av = sdo[ct * 16 + m][8 * g + e];
-                    const uint16_t bv = sin[ky][cit * 16 + m][8 * g + e + kx];
-                    a[e] = __builtin_bit_cast(__bf16, av);
-                    b[e] = __builtin_bit_cast(__bf16, bv);
+                    for (int j = 0; j < 4; ++j) {
+                        sdo[kx][8 * cg + 2 * j][xp] = (uint16_t)(wv[j] & 0xFFFFu);
+                        sdo[kx][8 * cg + 2 * j + 1][xp] = (uint16_t)(wv[j] >> 16);
+                    }
                 }
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
+            }
+            // input rows (zz, y + ky - 1) at x = xb .. xb + 63
+            for (int i = threadIdx.x; i < 3 * kWgSeg * 4; i += 256) {
+                const int cg = i & 3, rest = i >> 2;
+                const int xo = rest % kWgSeg, ky = rest / kWgSeg;
+                const int yy = y + ky - 1, x = xb + xo;
+                uint4 v = make_uint4(0u, 0u, 0u, 0u);
+                if (zin && yy >= 0 && yy < H && x < W && ci0 + 8 * cg < Cin)
+                    v = *reinterpret_cast<const uint4*>(
+                        in + (nbase + (size_t)zz * plane + (size_t)yy * W + x) * Cin + ci0 + 8 * cg);
+                const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    sin[ky][8 * cg + 2 * j][xo] = (uint16_t)(wv[j] & 0xFFFFu);
+                    sin[ky][8 * cg + 2 * j + 1][xo] = (uint16_t)(wv[j] >> 16);
+                }
+            }
+            __syncthreads();
+            if (!active) continue;
+#pragma unroll
+            for (int kh = 0; kh < kWgSeg / 32; ++kh) {
+                if (ks_sel >= 0 && kh != ks_sel) continue;
+                const int ks = 32 * kh;
+                bf16x8 av[3];
+#pragma unroll
+                for (int kx = 0; kx < 3; ++kx)
+                    av[kx] = *reinterpret_cast<const bf16x8*>(&sdo[kx][ct * 16 + m][ks + 8 * g]);
+#pragma unroll
+                for (int cit = 0; cit < 2; ++cit) {
+                    if (cit_sel >= 0 && cit != cit_sel) continue;
+#pragma unroll
+                    for (int ky = 0; ky < 3; ++ky) {
+                        const bf16x8 bv = *reinterpret_cast<const bf16x8*>(&sin[ky][cit * 16 + m][ks + 8 * g]);
+#pragma unroll
+                        for (int kx = 0; kx < 3; ++kx) {
+                            const int t = (ky * 3 + kx) * 2 + cit;
+                            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[kx], bv, acc[t], 0, 0, 0);
+                        }
+                    }
+                }
             }
         }
     }
+    if (!active) return;
 #pragma unroll
-    for (int t = 0; t < kWgTiles; ++t) {
-        const int q = wave * kWgTiles + t;
-        const int ct = q / 18, rem = q % 18;
-        const int kyx = rem >> 1, cit = rem & 1;
+    for (int t = 0; t < 18; ++t) {
+        const int kyx = t >> 1, cit = t & 1;
         const int tap = kz * 9 + kyx;
         const int ci = ci0 + cit * 16 + m;
         if (ci >= Cin) continue;

@@ -66,7 +66,9 @@ class pmc_summary(C.Structure):
                 ("n_short_steps", C.c_uint64), ("tally_atomics", C.c_uint64),
                 ("total_weight", C.c_double), ("device_ms", C.c_double),
                 ("transport_ms", C.c_double), ("generations", C.c_int32),
-                ("reserved", C.c_int32), ("global_atomics", C.c_uint64)]
+                ("reserved", C.c_int32), ("global_atomics", C.c_uint64),
+                ("block_threads", C.c_int32), ("grid_blocks", C.c_int32),
+                ("cache_slots", C.c_int32), ("epoch_steps", C.c_int32)]
 
 
 class pmc_plan(C.Structure):
