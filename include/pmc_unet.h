@@ -59,9 +59,11 @@ pmc_status pmc_unet_set_params(pmc_unet* u, const float* host_in);
 pmc_status pmc_unet_forward(pmc_unet* u, const float* d_dose, const float* d_density, float* d_out,
                             void* hip_stream);
 
-/* Forward, mean-squared error against d_target in units of max(d_dose), and
- * backward; gradients are added to the gradient buffer, *loss_out (host,
- * may be NULL) receives the loss.  Synchronous when loss_out != NULL. */
+/* Forward, squared error against d_target in units of max(d_dose) summed
+ * over all voxels and divided by the number of voxels of the dose region
+ * (d_dose >= 1% of its maximum), and backward; gradients are added to the
+ * gradient buffer, *loss_out (host, may be NULL) receives the loss.
+ * Synchronous when loss_out != NULL. */
 pmc_status pmc_unet_backward(pmc_unet* u, const float* d_dose, const float* d_density,
                              const float* d_target, double* loss_out, void* hip_stream);
 

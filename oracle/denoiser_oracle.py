@@ -14,8 +14,10 @@ Sec. II.D, defined by Low et al.):
   library's [cout][tap*cin + ci] order, tap = (kz*3 + ky)*3 + kx).
 * ``UNetOracle``: the 4-level network (16/32/64/128 channels, one conv+ReLU
   per level, 2x2x2 average pooling, nearest upsampling and concatenation
-  [coarse, skip], 1x1x1 residual head scaled by max(dose)), its MSE loss in
-  units of max(dose), the gradient by reverse-mode differentiation in FP64
+  [coarse, skip], 1x1x1 residual head scaled by max(dose)), its loss (the
+  squared error in units of max(dose) summed over all voxels, divided by the
+  number of voxels with dose >= 1% of max(dose)), the gradient by
+  reverse-mode differentiation in FP64
   (PyTorch CPU autograd used as the differentiation primitive), and one Adam
   step (Kingma and Ba, beta1 0.9, beta2 0.999, eps 1e-8).
 * ``gamma_index``: for each reference voxel at or above cutoff * max(ref),
@@ -195,7 +197,8 @@ class UNetOracle:
         loss = None
         if target is not None:
             t = torch.tensor(np.asarray(target, np.float64))
-            loss = (((out - t) / scale) ** 2).mean()
+            n_region = max(1, int((dose_t >= 0.01 * scale).sum()))
+            loss = (((out - t) / scale) ** 2).sum() / n_region
         return p, out, loss
 
     def forward(self, dose, rho):

@@ -30,9 +30,9 @@ hipError_t nn_up_concat_bwd(const uint16_t* dcat, uint16_t* dcoarse, uint16_t* d
 hipError_t nn_make_input(const float* dose, const float* rho, float* scale, uint16_t* x, size_t nvox, hipStream_t s);
 hipError_t nn_head_fwd(const uint16_t* d1, const float* w, const float* b, const float* dose, const float* scale,
                        float* out, size_t nvox, int C, hipStream_t s);
-hipError_t nn_loss_head_bwd(const float* out, const float* target, const float* scale, const uint16_t* d1,
-                            const float* w, uint16_t* dd1, float* dw, float* db, double* loss, size_t nvox, int C,
-                            hipStream_t s);
+hipError_t nn_loss_head_bwd(const float* out, const float* target, const float* dose, const float* scale,
+                            unsigned int* region, const uint16_t* d1, const float* w, uint16_t* dd1, float* dw,
+                            float* db, double* loss, size_t nvox, int C, hipStream_t s);
 hipError_t nn_adam(float* p, float* g, float* m1, float* m2, uint16_t* p_bf, size_t n, float lr, float b1, float b2,
                    float eps, float c1, float c2, hipStream_t s);
 hipError_t nn_f32_to_bf16(const float* a, uint16_t* b, size_t n, hipStream_t s);
@@ -75,6 +75,7 @@ struct pmc_unet {
     Act g_d1, g_c1, g_d2, g_e1s, g_c2, g_d3, g_e2s, g_c3, g_e4, g_e3s, g_p3, g_e3, g_p2, g_e2, g_p1, g_e1;
     float* out = nullptr;     // FP32 network output (denoised dose)
     float* scale = nullptr;
+    unsigned int* region = nullptr;   // voxels in the dose region (loss normalisation)
     double* loss = nullptr;
     std::vector<void*> allocs;
 };
@@ -167,9 +168,9 @@ hipError_t backward(pmc_unet* u, const float* dose, const float* target, hipStre
     const int N = u->N, D = u->D, H = u->H, W = u->W;
     const size_t nv = u->x.nvox;
     if ((e = hipMemsetAsync(u->loss, 0, sizeof(double), s)) != hipSuccess) return e;
-    (void)dose;
-    if ((e = nn_loss_head_bwd(u->out, target, u->scale, u->d1.p, u->p + u->off_hw, u->g_d1.p, u->g + u->off_hw,
-                              u->g + u->off_hb, u->loss, nv, 16, s)) != hipSuccess)
+    if ((e = hipMemsetAsync(u->region, 0, sizeof(unsigned int), s)) != hipSuccess) return e;
+    if ((e = nn_loss_head_bwd(u->out, target, dose, u->scale, u->region, u->d1.p, u->p + u->off_hw, u->g_d1.p,
+                              u->g + u->off_hw, u->g + u->off_hb, u->loss, nv, 16, s)) != hipSuccess)
         return e;
     // dec1: c1 (48) -> d1 (16)
     if ((e = conv_bwd(u, u->conv[6], u->c1, u->d1, u->g_d1, &u->g_c1, 0, s)) != hipSuccess) return e;
@@ -290,6 +291,7 @@ pmc_status pmc_unet_create(pmc_unet** out, int device, int n, int d, int h, int 
     A(act(u, u->g_e1, 0, 16));
     A(ualloc(u, &u->out, u->x.nvox));
     A(ualloc(u, &u->scale, 1));
+    A(ualloc(u, &u->region, 1));
     A(ualloc(u, &u->loss, 1));
     // initial parameters
     std::vector<float> hp(u->n_params, 0.f);

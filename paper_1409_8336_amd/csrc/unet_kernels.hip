@@ -31,8 +31,15 @@ DEV uint16_t f2bf(float f)
 
 // ------------------------------------------------------------ convolution
 
-// One workgroup: 64 consecutive x positions of one (n, z, y) row (16 per
-// wave) and 16*NB output channels starting at blockIdx.y*16*NB.
+// Forward convolution, LDS-staged.  A workgroup computes a 64 (x) x 2 (y) x
+// 2 (z) block of output voxels for 16*NB output channels; wave w owns the
+// 64-voxel row (y0 + (w & 1), z0 + (w >> 1)) as four 16-voxel M tiles.
+// The input is consumed 8 channels at a time: the block's halo (66 x 4 x 4
+// voxels x 8 channels, 16 bytes per voxel) is staged in LDS once and read
+// by all 27 taps.  K order inside a chunk: 4 taps x 8 channels per MFMA
+// K-step (lane group g takes tap 4*s + g), i.e. weight column
+// tap*Cin + 8*c + e; tap 27 (the padding to 28 = 7 x 4) contributes zero.
+constexpr int kCfX = 64, kCfHx = kCfX + 2;          // block width, halo width
 template <int NB>
 __global__ void __launch_bounds__(256) conv3d_fwd_kernel(const uint16_t* __restrict__ in,
                                                          const uint16_t* __restrict__ wt,
@@ -40,55 +47,79 @@ __global__ void __launch_bounds__(256) conv3d_fwd_kernel(const uint16_t* __restr
                                                          uint16_t* __restrict__ out, int D, int H,
                                                          int W, int Cin, int Cout, int Kp, int relu)
 {
+    __shared__ __attribute__((aligned(16))) uint4 halo[4][4][kCfHx];   // [z][y][x], 8 channels
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int nz = blockIdx.z;               // n * D + z
-    const int z = nz % D;
-    const int y = blockIdx.y % H;
-    const int cg = blockIdx.y / H;
-    const int x0 = blockIdx.x * 64 + wave * 16;
-    const int co0 = cg * 16 * NB;
-    const int K = 27 * Cin;
     const int m = lane & 15, g = lane >> 4;
-    const int xa = x0 + m;                   // voxel of this lane's A row
+    const int n_yb = (H + 1) / 2;
+    const int yb = blockIdx.y % n_yb, cg = blockIdx.y / n_yb;
+    const int n_zb = (D + 1) / 2;
+    const int zb = blockIdx.z % n_zb, n = blockIdx.z / n_zb;
+    const int x0 = blockIdx.x * kCfX, y0 = 2 * yb, z0 = 2 * zb;
+    const int co0 = cg * 16 * NB;
+    const int wy = wave & 1, wz = wave >> 1;
     const size_t plane = (size_t)H * W;
-    const size_t nbase = (size_t)(nz - z) * plane;   // n * D * H * W
-    f32x4 acc[NB];
+    const size_t nbase = (size_t)n * D * plane;
+    f32x4 acc[4][NB];
 #pragma unroll
-    for (int j = 0; j < NB; ++j) acc[j] = (f32x4){0.f, 0.f, 0.f, 0.f};
-    for (int kc = 0; kc < Kp; kc += 32) {
-        const int kk = kc + 8 * g;
-        bf16x8 a = (bf16x8){};
-        if (kk < K && xa < W) {
-            const int tap = kk / Cin, ci = kk - tap * Cin;
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) acc[t][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    const int n_chunks = Cin / 8;
+    for (int c = 0; c < n_chunks; ++c) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < 4 * 4 * kCfHx; i += 256) {
+            const int hx = i % kCfHx, r = i / kCfHx;
+            const int hy = r & 3, hz = r >> 2;
+            const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (x >= 0 && x < W && y >= 0 && y < H && z >= 0 && z < D)
+                v = *reinterpret_cast<const uint4*>(in + (nbase + (size_t)z * plane + (size_t)y * W + x) * Cin + 8 * c);
+            halo[hz][hy][hx] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < 7; ++s) {
+            const int tap = 4 * s + g;
+            const bool real = tap < 27;
             const int kz = tap / 9, ky = (tap / 3) % 3, kx = tap % 3;
-            const int zz = z + kz - 1, yy = y + ky - 1, xx = xa + kx - 1;
-            if (zz >= 0 && zz < D && yy >= 0 && yy < H && xx >= 0 && xx < W) {
-                const size_t v = nbase + (size_t)zz * plane + (size_t)yy * W + xx;
-                a = *reinterpret_cast<const bf16x8*>(in + v * Cin + ci);
+            bf16x8 b[NB];
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const int co = co0 + 16 * j + m;
+                b[j] = (bf16x8){};
+                if (real && co < Cout)
+                    b[j] = *reinterpret_cast<const bf16x8*>(wt + (size_t)co * Kp + tap * Cin + 8 * c);
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                bf16x8 a = (bf16x8){};
+                if (real) {
+                    const uint4 q = halo[wz + kz][wy + ky][16 * t + m + kx];
+                    a = __builtin_bit_cast(bf16x8, q);
+                }
+#pragma unroll
+                for (int j = 0; j < NB; ++j)
+                    acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], acc[t][j], 0, 0, 0);
             }
         }
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-            const int co = co0 + 16 * j + m;
-            bf16x8 b = (bf16x8){};
-            if (co < Cout) b = *reinterpret_cast<const bf16x8*>(wt + (size_t)co * Kp + kk);
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
-        }
     }
+    const int y = y0 + wy, z = z0 + wz;
+    if (y >= H || z >= D) return;
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
         const int co = co0 + 16 * j + m;
         if (co >= Cout) continue;
         const float bv = bias ? bias[co] : 0.f;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int x = x0 + 4 * g + i;
-            if (x >= W) continue;
-            float v = acc[j][i] + bv;
-            if (relu) v = v > 0.f ? v : 0.f;
-            const size_t vox = nbase + (size_t)z * plane + (size_t)y * W + x;
-            out[vox * Cout + co] = f2bf(v);
-        }
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int x = x0 + 16 * t + 4 * g + i;
+                if (x >= W) continue;
+                float v = acc[t][j][i] + bv;
+                if (relu) v = v > 0.f ? v : 0.f;
+                out[(nbase + (size_t)z * plane + (size_t)y * W + x) * Cout + co] = f2bf(v);
+            }
     }
 }
 
@@ -412,6 +443,23 @@ __global__ void __launch_bounds__(256) max_kernel(const float* __restrict__ a, s
     }
 }
 
+// region[0] += number of voxels with dose >= frac * scale (the dose region
+// that normalises the loss); one atomic per block
+__global__ void __launch_bounds__(256) region_count_kernel(const float* __restrict__ dose, size_t n,
+                                                           const float* __restrict__ scale, float frac,
+                                                           unsigned int* __restrict__ region)
+{
+    __shared__ unsigned int part[4];
+    const float thr = frac * scale[0];
+    unsigned int c = 0;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        c += dose[i] >= thr;
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(region, part[0] + part[1] + part[2] + part[3]);
+}
+
 // head: out[v] = scale * (dose[v]/scale + sum_c w[c] d1[v][c] + b)  (1x1x1, 16 -> 1, residual)
 __global__ void head_fwd_kernel(const uint16_t* __restrict__ d1, const float* __restrict__ w,
                                 const float* __restrict__ b, const float* __restrict__ dose,
@@ -425,11 +473,14 @@ __global__ void head_fwd_kernel(const uint16_t* __restrict__ d1, const float* __
     }
 }
 
-// MSE loss in normalised units, L = mean_v ((out_v - t_v) / scale)^2, and
-// the head backward: g_v = dL/d(head pre-activation) = 2 (out_v - t_v) /
-// scale / nvox; dd1[v][c] = g_v w[c]; dw[c] += sum_v g_v d1[v][c];
-// db += sum_v g_v; loss += L.  C = 16 channels: one 32-byte row per voxel.
-// Block partial sums meet in LDS; one atomic per block and quantity.
+// Squared error in normalised units over the dose region,
+// L = sum_v ((out_v - t_v) / scale)^2 / n_region (every voxel contributes;
+// n_region, the count of voxels with dose >= 1% of scale, sets the scale of
+// the gradients), and the head backward: g_v = dL/d(head pre-activation) =
+// 2 (out_v - t_v) / scale / n_region; dd1[v][c] = g_v w[c];
+// dw[c] += sum_v g_v d1[v][c]; db += sum_v g_v; loss += L.  C = 16
+// channels: one 32-byte row per voxel.  Block partial sums meet in LDS; one
+// atomic per block and quantity.
 __global__ void __launch_bounds__(256) loss_head_bwd_kernel(const float* __restrict__ out,
                                                             const float* __restrict__ target,
                                                             const float* __restrict__ scale,
@@ -437,8 +488,9 @@ __global__ void __launch_bounds__(256) loss_head_bwd_kernel(const float* __restr
                                                             const float* __restrict__ w,
                                                             uint16_t* __restrict__ dd1, float* __restrict__ dw,
                                                             float* __restrict__ db, double* __restrict__ loss,
-                                                            size_t nvox, float inv_count)
+                                                            size_t nvox, const unsigned int* __restrict__ region)
 {
+    const float inv_count = 1.0f / (float)max(1u, region[0]);
     __shared__ float sg[4][17];
     __shared__ double sl[4];
     const float sc = fmaxf(scale[0], 1e-30f);
@@ -541,7 +593,8 @@ hipError_t nn_conv3d_fwd(const uint16_t* in, const uint16_t* wt, const float* bi
 {
     const int nb = Cout >= 64 ? 4 : (Cout >= 32 ? 2 : 1);
     const int cgroups = (Cout + 16 * nb - 1) / (16 * nb);
-    dim3 grid((W + 63) / 64, H * cgroups, N * D);
+    if (Cin % 8 || Cin < 8 || Kp < 27 * Cin) return hipErrorInvalidValue;
+    dim3 grid((W + kCfX - 1) / kCfX, ((H + 1) / 2) * cgroups, N * ((D + 1) / 2));
     if (nb == 4) hipLaunchKernelGGL(conv3d_fwd_kernel<4>, grid, dim3(256), 0, s, in, wt, bias, out, D, H, W, Cin, Cout, Kp, relu);
     else if (nb == 2) hipLaunchKernelGGL(conv3d_fwd_kernel<2>, grid, dim3(256), 0, s, in, wt, bias, out, D, H, W, Cin, Cout, Kp, relu);
     else hipLaunchKernelGGL(conv3d_fwd_kernel<1>, grid, dim3(256), 0, s, in, wt, bias, out, D, H, W, Cin, Cout, Kp, relu);
@@ -631,13 +684,15 @@ hipError_t nn_head_fwd(const uint16_t* d1, const float* w, const float* b, const
     return hipGetLastError();
 }
 
-hipError_t nn_loss_head_bwd(const float* out, const float* target, const float* scale, const uint16_t* d1,
-                            const float* w, uint16_t* dd1, float* dw, float* db, double* loss, size_t nvox, int C,
-                            hipStream_t s)
+hipError_t nn_loss_head_bwd(const float* out, const float* target, const float* dose, const float* scale,
+                            unsigned int* region, const uint16_t* d1, const float* w, uint16_t* dd1, float* dw,
+                            float* db, double* loss, size_t nvox, int C, hipStream_t s)
 {
     if (C != 16) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(region_count_kernel, dim3(grid_for(nvox, 256, 1024)), dim3(256), 0, s, dose, nvox, scale, 0.01f,
+                       region);
     hipLaunchKernelGGL(loss_head_bwd_kernel, dim3(grid_for(nvox, 256, 1024)), dim3(256), 0, s, out, target, scale, d1, w,
-                       dd1, dw, db, loss, nvox, 1.0f / (float)nvox);
+                       dd1, dw, db, loss, nvox, (const unsigned int*)region);
     return hipGetLastError();
 }
 

@@ -121,10 +121,21 @@ def test_param_layout_matches_documented_sizes():
 
 
 def test_residual_head_with_zero_head_returns_dose():
-    p, dose, rho, _ = _net_case(5)
+    """With the head zeroed the output is the input dose, and the loss is
+    the squared error of the dose itself, summed and divided by the number
+    of voxels at or above 1% of the maximum dose."""
+    p, dose, rho, target = _net_case(5)
     _, ohw, ohb, _ = D.param_layout()
     p[ohw:ohb + 1] = 0.0
-    np.testing.assert_array_equal(D.UNetOracle(p).forward(dose, rho), dose)
+    net = D.UNetOracle(p)
+    np.testing.assert_array_equal(net.forward(dose, rho), dose)
+    dose = dose.copy()
+    dose[0, :4] = 0.0            # a region of zero dose outside the normalisation
+    scale = dose.max()
+    n_region = int((dose >= 0.01 * scale).sum())
+    assert n_region < dose.size
+    expect = (((dose - target) / scale) ** 2).sum() / n_region
+    assert abs(net.loss(dose, rho, target) - expect) <= 1e-12 * expect
 
 
 def test_network_forward_matches_composition_of_definitions():
