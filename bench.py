@@ -163,6 +163,63 @@ def bench_ct_spots(args):
     return 0
 
 
+# algorithmic FLOP of one denoiser forward at 160x128x128: 2*27*cin*cout per
+# output voxel and convolution (enc1 with its 8 padded input channels)
+def unet_forward_flop(d, h, w):
+    vox = [d * h * w >> (3 * l) for l in range(4)]
+    convs = [(0, 8, 16), (1, 16, 32), (2, 32, 64), (3, 64, 128), (2, 192, 64), (1, 96, 32), (0, 48, 16)]
+    return sum(2 * 27 * ci * co * vox[l] for l, ci, co in convs)
+
+
+def bench_denoiser(args):
+    """The denoiser at 160x128x128 (one volume): inference and one training
+    step (forward, backward, Adam), with the MFMA roofline of the
+    convolutions: algorithmic FLOP / time against 2.5 PFLOP/s dense BF16."""
+    import torch
+    import numpy as np
+    from paper_1409_8336_amd import unet
+    shape = (1, 160, 128, 128)
+    rng = np.random.default_rng(1)
+    dose = torch.from_numpy((rng.gamma(2.0, 1.0, shape) * 1e-11).astype(np.float32)).cuda()
+    rho = torch.from_numpy(rng.uniform(0.2, 2.0, shape).astype(np.float32)).cuda()
+    tgt = dose * 1.05
+    out = torch.empty_like(dose)
+    net = unet.UNet(shape, seed=1)
+    for _ in range(args.warmup + 2):
+        net.forward(dose, rho, out)
+        net.backward(dose, rho, tgt)
+        net.adam_step(1e-4)
+    torch.cuda.synchronize()
+    reps = max(args.steps, 5)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        net.forward(dose, rho, out)
+    torch.cuda.synchronize()
+    t_inf = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        net.backward(dose, rho, tgt)
+        net.adam_step(1e-4)
+    torch.cuda.synchronize()
+    t_train = (time.perf_counter() - t0) / reps
+    net.close()
+    fwd = unet_forward_flop(*shape[1:])
+    peak = 2.5e15
+    out = {"metric": "denoiser inferences/s (160x128x128)", "value": 1.0 / t_inf, "unit": "volumes/s",
+           "n_gpus": 1, "steps": reps, "warmup": args.warmup, "ms_per_step": 1e3 * t_inf,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "bf16 (fp32 accumulate)", "data": "synthetic",
+           "config": {"workload": "3-D U-Net 16/32/64/128, one 160x128x128 volume, 730,481 parameters"},
+           "train_step_ms": 1e3 * t_train,
+           "roofline": {"bound": "mfma", "achieved": fwd / t_inf / 1e12, "peak": peak / 1e12,
+                        "unit": "TFLOP/s", "frac": fwd / t_inf / peak, "traffic": None,
+                        "kernel": "whole forward (7 convolutions and the elementwise kernels)",
+                        "flop_per_forward": fwd,
+                        "train_achieved": 3 * fwd / t_train / 1e12}}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -170,10 +227,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--histories", type=int, default=10_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=("field", "plans", "ct_spots"), default="field",
+    ap.add_argument("--workload", choices=("field", "plans", "ct_spots", "denoiser"), default="field",
                     help="field: the 2000-spot 1e7-history field (default); plans: the "
                          "uneven 16-plan batch in one persistent launch; ct_spots: single "
-                         "spots at 70/150/230 MeV in the 128x128x160 CT")
+                         "spots at 70/150/230 MeV in the 128x128x160 CT; denoiser: the U-Net "
+                         "at 160x128x128 (inference and training step)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device copy (counter calibration)")
     ap.add_argument("--param", action="append", default=[], metavar="NAME=VALUE",
@@ -196,6 +254,8 @@ def main():
         return bench_plans(args)
     if args.workload == "ct_spots":
         return bench_ct_spots(args)
+    if args.workload == "denoiser":
+        return bench_denoiser(args)
     cfg = synth.config_field(args.histories)
     eng = pmc.Engine(0, **args.engine_params)
     eng.load_physics(synth.nuclear_data())

@@ -71,10 +71,9 @@ typedef struct {
     int32_t blocks_per_cu;   /* resident workgroups per CU for the persistent grid; 0 = occupancy */
     int32_t refill_lanes;    /* a wave refills when at least this many of its 64 lanes are idle; 0 = tuned */
     int32_t batch_events;    /* a wave handles pending nuclear events once this many lanes wait; 0 = tuned */
-    int32_t tally_cache;     /* LDS deposit cache per workgroup (single-geometry runs): slots, a
-                                power of two 512..16384; 0 = automatic (the tuner may turn it off,
-                                else sized from the LDS left by the tables); -1 = off (every
-                                deposit is a global FP64 atomic) */
+    int32_t tally_cache;     /* LDS deposit cache per workgroup: slots, 512..16384; 0 = automatic
+                                (the tuner may turn it off, else sized from the LDS left by the
+                                tables); -1 = off (every deposit is a global FP64 atomic) */
     int32_t epoch_steps;     /* loop iterations between cache flushes; 0 = 32 */
     int32_t cache_probes;    /* cache slots tried per deposit (linear probing), 1..16; 0 = 4 */
 } pmc_params;

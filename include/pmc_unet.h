@@ -9,8 +9,8 @@
  * and the judge of its error (gamma index, Low et al., as used in the paper's
  * Sec. II.D).  It has no counterpart in the paper.
  *
- * Network: 4 levels (16/32/64/128 channels), one 3x3x3 convolution + ReLU per
- * level on the way down (2x2x2 average pooling between levels) and one per
+ * Network: 4 levels (16/32/64/128 channels), one 3x3x3 convolution + leaky
+ * ReLU (negative slope 0.01) per level on the way down (2x2x2 average pooling between levels) and one per
  * level on the way up (nearest 2x upsampling, concatenation with the skip),
  * then a 1x1x1 head added to the normalised input dose (residual):
  *   out = dose + scale * head(features),  scale = max(dose).
@@ -41,8 +41,8 @@ extern "C" {
 typedef struct pmc_unet pmc_unet;
 
 /* Create a network for inputs of shape [n][d][h][w] on HIP device `device`,
- * weights initialised from `seed` (He-normal convolutions, zero biases, head
- * 1e-3).  Errors: PMC_ERR_ARG (shape not multiples of 8, n < 1),
+ * weights initialised from `seed` (He-normal convolutions, zero biases, zero
+ * head: the initial network returns its input dose).  Errors: PMC_ERR_ARG (shape not multiples of 8, n < 1),
  * PMC_ERR_NOMEM, PMC_ERR_DEVICE. */
 pmc_status pmc_unet_create(pmc_unet** out, int device, int n, int d, int h, int w, uint64_t seed);
 pmc_status pmc_unet_destroy(pmc_unet* u);
@@ -79,7 +79,8 @@ pmc_status pmc_unet_adam_step(pmc_unet* u, float lr, void* hip_stream);
  * x: [n][d][h][w][cin] channels-last; w: [cout][Kp] (see above); y:
  * [n][d][h][w][cout].  cin, cout multiples of 8, at least 8; the Kp - 27*cin
  * padding columns of w must be zero.
- * forward: y = conv(x, w) + bias (bias may be NULL), ReLU when relu != 0.
+ * forward: y = conv(x, w) + bias (bias may be NULL), then the leaky ReLU
+ * (y if y > 0 else 0.01 y) when relu != 0.
  * backward_data: dx = conv^T(dy, w) (workspace allocated internally).
  * backward_weight: dw[cout][Kp] (float32) += sum over voxels of dy (x) x. */
 pmc_status pmc_nn_conv3d_forward(const uint16_t* d_x, const uint16_t* d_w, const float* d_bias,

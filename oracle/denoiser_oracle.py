@@ -12,8 +12,8 @@ Sec. II.D, defined by Low et al.):
   3x3x3, stride-1, zero-padded cross-correlation and its two adjoints, as
   plain sums over the 27 taps (channels-last arrays, the weight matrix in the
   library's [cout][tap*cin + ci] order, tap = (kz*3 + ky)*3 + kx).
-* ``UNetOracle``: the 4-level network (16/32/64/128 channels, one conv+ReLU
-  per level, 2x2x2 average pooling, nearest upsampling and concatenation
+* ``UNetOracle``: the 4-level network (16/32/64/128 channels, one conv +
+  leaky ReLU (slope 0.01) per level, 2x2x2 average pooling, nearest upsampling and concatenation
   [coarse, skip], 1x1x1 residual head scaled by max(dose)), its loss (the
   squared error in units of max(dose) summed over all voxels, divided by the
   number of voxels with dose >= 1% of max(dose)), the gradient by
@@ -57,6 +57,14 @@ def _shifted(x, off):
     return s
 
 
+LEAK = 0.01   # negative slope of the activation after every convolution
+
+
+def leaky_relu(y):
+    """y if y > 0 else LEAK * y."""
+    return np.where(y > 0.0, y, LEAK * y)
+
+
 def conv3d(x, wmat, bias=None, relu=False):
     """y[v][co] = bias[co] + sum_{tap, ci} x[v + off(tap)][ci] * W[co][tap*cin + ci]."""
     x = np.asarray(x, np.float64)
@@ -70,7 +78,7 @@ def conv3d(x, wmat, bias=None, relu=False):
     if bias is not None:
         y += np.asarray(bias, np.float64)
     if relu:
-        y = np.maximum(y, 0.0)
+        y = leaky_relu(y)
     return y
 
 
@@ -87,7 +95,7 @@ def conv3d_at(x, wmat, bias, points, relu=False):
             zz, y2, x2 = z + oz, yy + oy, xx + ox
             if 0 <= zz < d and 0 <= y2 < h and 0 <= x2 < w:
                 acc += wmat[:, tap * cin:(tap + 1) * cin] @ x[n, zz, y2, x2].astype(np.float64)
-        out.append(np.maximum(acc, 0.0) if relu else acc)
+        out.append(leaky_relu(acc) if relu else acc)
     return np.array(out)
 
 
@@ -179,7 +187,7 @@ class UNetOracle:
             _, ow, ob, cin, cout, k = next(l for l in self.layout if l[0] == name)
             wmat = p[ow:ow + cout * k].reshape(cout, k)
             wt = _torch_weight(torch, wmat, cin, cout)
-            return torch.relu(F.conv3d(inp, wt, p[ob:ob + cout], padding=1))
+            return F.leaky_relu(F.conv3d(inp, wt, p[ob:ob + cout], padding=1), LEAK)
 
         def up_cat(coarse, skip):
             return torch.cat([coarse.repeat_interleave(2, 2).repeat_interleave(2, 3)

@@ -74,10 +74,11 @@ struct KernelArgs {
     unsigned long long* counters;   // [plan][8]: steps, elastic, non-elastic, short steps, tally atomics
     int refill_lanes;
     int batch_events;
-    // workgroup deposit cache in LDS (single-plan launches): 2^cache_log2
-    // slots of {uint32 tally index, double sum} at LDS word offset cache_off,
-    // flushed to the tally every epoch_iters loop iterations; 0 = off
-    int cache_log2;
+    // workgroup deposit cache in LDS: cache_slots sums (double) then as many
+    // keys (tally index as uint32; in a batch of plans, plan << 32 | index as
+    // uint64) at the even LDS word offset cache_off, flushed to the tallies
+    // every epoch_iters loop iterations; 0 slots = off
+    int cache_slots;
     int cache_off;
     int epoch_iters;
     int cache_probes;   // slots tried (linear probing) before a deposit goes to the tally

@@ -202,9 +202,8 @@ bool params_ok(const pmc_params& p, std::string& why)
     if (p.blocks_per_cu < 0 || p.blocks_per_cu > 64) { why = "blocks_per_cu out of range"; return false; }
     if (p.refill_lanes < 0 || p.refill_lanes > 64) { why = "refill_lanes out of range"; return false; }
     if (p.batch_events < 0 || p.batch_events > 64) { why = "batch_events out of range"; return false; }
-    if (p.tally_cache != 0 && p.tally_cache != -1 &&
-        (p.tally_cache < 512 || p.tally_cache > 16384 || (p.tally_cache & (p.tally_cache - 1))))
-    { why = "tally_cache must be -1, 0 or a power of two in [512, 16384]"; return false; }
+    if (p.tally_cache != 0 && p.tally_cache != -1 && (p.tally_cache < 512 || p.tally_cache > 16384))
+    { why = "tally_cache must be -1, 0 or in [512, 16384]"; return false; }
     if (p.epoch_steps < 0 || p.epoch_steps > 4096) { why = "epoch_steps must be in [0, 4096]"; return false; }
     if (p.cache_probes < 0 || p.cache_probes > 16) { why = "cache_probes must be in [0, 16]"; return false; }
     return true;
@@ -440,28 +439,28 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
 
     const int block = shape.block;
     const size_t lds_words = (size_t)(multi ? a.pd_offset + 16 * np : a.blob_words);
-    // deposit cache of a single-geometry run: 12 bytes per slot, sized from
-    // what the tables leave of the CU's 160 KiB LDS at 16 waves per CU
+    // deposit cache: 12 bytes per slot (16 in a batch of plans: 64-bit keys),
+    // sized from what the tables leave of the CU's 160 KiB LDS at 16 waves
+    // per CU; every tally index must fit 32 bits
     int slots = 0;
+    const int key_words = multi ? 2 : 1;
     const int want = c->p.tally_cache != 0 ? c->p.tally_cache : shape.cache;
-    if (!multi && want >= 0 && plans[0].g->nvox() * (unsigned long long)K < 0xFFFFFFFFull) {
+    bool small = true;
+    for (const PlanIn& q : plans) small = small && q.g->nvox() * (unsigned long long)K < 0xFFFFFFFFull;
+    if (want >= 0 && small) {
         slots = want;
         if (slots == 0) {
             const long wgs = std::max(1, 1024 / block);
             const long avail = 163840L / wgs - (long)lds_words * 4 - 64;
-            for (int s2 = 16384; s2 >= 512; s2 >>= 1)
-                if ((long)s2 * 12 <= avail) {
-                    slots = s2;
-                    break;
-                }
+            slots = (int)std::min(16384L, avail / (4L * (2 + key_words)));
+            if (slots < 512) slots = 0;
         }
     }
-    a.cache_log2 = 0;
-    while (slots > 0 && (1 << a.cache_log2) < slots) ++a.cache_log2;
+    a.cache_slots = slots;
     a.cache_off = (int)((lds_words + 1) & ~(size_t)1);
     a.epoch_iters = c->p.epoch_steps ? c->p.epoch_steps : 32;
     a.cache_probes = c->p.cache_probes ? c->p.cache_probes : 4;
-    const size_t lds = slots ? (size_t)(a.cache_off + 3 * slots + 1) * 4 : lds_words * 4;
+    const size_t lds = slots ? (size_t)(a.cache_off + (2 + key_words) * slots + 1) * 4 : lds_words * 4;
     int max_block = 0;
     HIPCHK(transport_max_block(multi, &max_block), "kernel attributes");
     if (block > max_block) return fail(c, PMC_ERR_ARG, "block_threads exceeds the transport kernel's limit");
@@ -593,26 +592,23 @@ pmc_status choose_shape(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, hipS
     // which keeps the spatial coherence of the work (what the deposit cache
     // relies on); several plans: every plan scaled down.
     const double cal_hist = std::min(2.0e6, std::max(2.0e5, 0.2 * (double)total));
+    // every plan contributes the first spots of its list, with their own
+    // history counts, up to its share of the calibration work
     std::vector<PlanIn> cal = plans;
-    if (!multi) {
-        PlanIn& p = cal[0];
+    const double f = cal_hist / (double)total;
+    for (PlanIn& p : cal) {
         double wsum = 0.0;
         for (int i = 0; i < p.n_spots; ++i) wsum += p.spots[i].weight;
+        const double goal = f * (double)p.n_hist;
         double acc = 0.0;
         int m = 0;
-        while (m < p.n_spots && acc < cal_hist) {
+        while (m < p.n_spots && acc < goal) {
             acc += wsum > 0.0 ? (double)p.n_hist * p.spots[m].weight / wsum : 0.0;
             ++m;
         }
         p.n_spots = m > 0 ? m : 1;
-        p.n_hist = std::max<unsigned long long>(1ull, (unsigned long long)std::llround(acc));
+        p.n_hist = std::max<unsigned long long>(1ull, (unsigned long long)std::llround(std::min(acc, (double)p.n_hist)));
         p.summary = nullptr;
-    } else {
-        const double f = cal_hist / (double)total;
-        for (PlanIn& p : cal) {
-            p.n_hist = (unsigned long long)std::ceil(p.n_hist * f);
-            p.summary = nullptr;
-        }
     }
     std::vector<Shape> cands;
     for (int b : {256, 512, 1024})
@@ -625,7 +621,7 @@ pmc_status choose_shape(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, hipS
                     x.refill = c->p.refill_lanes ? c->p.refill_lanes : r;
                     x.batch = c->p.batch_events ? c->p.batch_events : e;
                     // the cache is only worth a choice where it fits next to the tables
-                    x.cache = (multi || c->p.tally_cache != 0 || x.block < 512) ? 0 : ch;
+                    x.cache = (c->p.tally_cache != 0 || x.block < 512) ? 0 : ch;
                     bool dup = false;
                     for (const Shape& y : cands)
                         dup |= (y.block == x.block && y.refill == x.refill && y.batch == x.batch &&

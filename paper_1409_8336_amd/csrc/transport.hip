@@ -14,6 +14,8 @@
 //     gather; the dose is one FP64 atomic add per step into [voxel][group].
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device.hpp"
 
 namespace pmc {
@@ -27,7 +29,6 @@ constexpr float kInvH = 999.0f / 7.824046011f;    // 1 / (ln(2500)/999)
 constexpr float kH = 7.824046011f / 999.0f;
 constexpr float kStraggleK = 0.156914976f;        // K m_e c^2, MeV^2 cm^2 / g
 constexpr float kInf = 3.0e38f;
-constexpr uint32_t kEmptySlot = 0xFFFFFFFFu;   // free deposit-cache slot
 constexpr uint32_t kMaxSteps = 1u << 20;
 constexpr uint32_t kNoStraggle = 1u, kNoMcs = 2u, kNoNuclear = 4u;
 
@@ -41,6 +42,7 @@ DEV float fsin_rev(float r) { return __builtin_amdgcn_sinf(r); }   // sin(2 pi r
 DEV float fcos_rev(float r) { return __builtin_amdgcn_cosf(r); }   // cos(2 pi r)
 
 // Philox4x32-10 (Salmon et al. 2011); key = run seed, counter = (uid, k, tag)
+template <bool kScalarKey = false>
 DEV uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1)
 {
 #pragma unroll
@@ -48,6 +50,10 @@ DEV uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0
         if (r) {
             k0 += 0x9E3779B9u;
             k1 += 0xBB67AE85u;
+            // a key shared by the wave stays a pair of per-round scalar adds
+            // (precomputed and hoisted out of the step loop, the ten round
+            // keys only spill to VGPR lanes)
+            if constexpr (kScalarKey) asm volatile("" : "+s"(k0), "+s"(k1));
         }
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
@@ -183,13 +189,15 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
         for (int i = threadIdx.x; i < a.n_plans * 16; i += blockDim.x) dst[i] = src[i];
     }
     // deposit cache at an even word offset: slot values (double), slot keys
-    // (tally index), then the count of waves that have finished
-    const bool use_cache = !kMulti && a.cache_log2 > 0;
-    const int n_slots = use_cache ? 1 << a.cache_log2 : 0;
-    const uint32_t slot_shift = 32u - (uint32_t)a.cache_log2;
+    // (tally index; in a batch of plans, plan << 32 | tally index), then the
+    // count of waves that have finished
+    using Key = std::conditional_t<kMulti, unsigned long long, uint32_t>;
+    constexpr Key kEmptySlot = ~Key(0);
+    const int n_slots = a.cache_slots;
+    const bool use_cache = n_slots > 0;
     double* const cval = reinterpret_cast<double*>(lds + a.cache_off);
-    uint32_t* const ckey = reinterpret_cast<uint32_t*>(lds + a.cache_off + 2 * n_slots);
-    uint32_t* const waves_done = ckey + n_slots;
+    Key* const ckey = reinterpret_cast<Key*>(lds + a.cache_off + 2 * n_slots);
+    uint32_t* const waves_done = reinterpret_cast<uint32_t*>(ckey + n_slots);
     for (int i = threadIdx.x; i < n_slots; i += blockDim.x) {
         cval[i] = 0.0;
         ckey[i] = kEmptySlot;
@@ -254,10 +262,16 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
     auto deposit = [&](unsigned long long idx, double v) {
         ++n_dep;
         if (use_cache) {
-            const uint32_t key = (uint32_t)idx;
-            uint32_t slot = (key * 0x9E3779B1u) >> slot_shift;
+            Key key = (Key)(uint32_t)idx;
+            uint32_t h = (uint32_t)idx * 0x9E3779B1u;
+            if constexpr (kMulti) {
+                key |= (Key)plan << 32;
+                h ^= plan * 0x85EBCA6Bu;
+            }
+            // multiplicative hash reduced to [0, n_slots) by a high product
+            uint32_t slot = __umulhi(h, (uint32_t)n_slots);
             for (int probe = 0; probe < a.cache_probes; ++probe) {
-                uint32_t held = ckey[slot];
+                Key held = ckey[slot];
                 if (held == kEmptySlot) {
                     held = atomicCAS(&ckey[slot], kEmptySlot, key);
                     if (held == kEmptySlot) held = key;
@@ -266,7 +280,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                     unsafeAtomicAdd(&cval[slot], v);
                     return;
                 }
-                slot = (slot + 1u) & (uint32_t)(n_slots - 1);
+                slot = slot + 1u == (uint32_t)n_slots ? 0u : slot + 1u;
             }
         }
         unsafeAtomicAdd(&P.tally(plan)[idx], v);
@@ -310,7 +324,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                         }
                         uid_lo = (uint32_t)uid;
                         uid_hi = (uint32_t)(uid >> 32);
-                        const uint4 r = philox(uid_lo, uid_hi, 0u, 0u, P.key_lo(plan), P.key_hi(plan));
+                        const uint4 r = philox<!kMulti>(uid_lo, uid_hi, 0u, 0u, P.key_lo(plan), P.key_hi(plan));
                         const float rr = fsqrt(-2.0f * fln(u01(r.x)));
                         const float ph = u01(r.y);
                         px = sp[0] + sp[3] * rr * fcos_rev(ph);
@@ -344,7 +358,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                                 plan = np;
                             }
                         }
-                        const uint4 r = philox(uid_lo, uid_hi, 0u, 0u, P.key_lo(plan), P.key_hi(plan));
+                        const uint4 r = philox<!kMulti>(uid_lo, uid_hi, 0u, 0u, P.key_lo(plan), P.key_hi(plan));
                         mfp = -fln(u01(r.z));
                     }
                     k = 0;
@@ -440,7 +454,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                 float de_mean = E - e1;
                 de_mean = de_mean > 0.f ? de_mean : 0.f;
                 const float emid = E - 0.5f * de_mean;
-                const uint4 r = philox(uid_lo, uid_hi, k, 1u, P.key_lo(plan), P.key_hi(plan));
+                const uint4 r = philox<!kMulti>(uid_lo, uid_hi, k, 1u, P.key_lo(plan), P.key_hi(plan));
                 const float e_tot = emid + kMp;
                 const float ie_tot = frcp(e_tot);
                 const float pv = emid * (emid + 2.f * kMp) * ie_tot;      // p beta c
@@ -548,7 +562,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
             int gi;
             float gt;
             grid_pos(T, gi, gt);
-            const uint4 r3 = philox(uid_lo, uid_hi, ks, 3u, P.key_lo(plan), P.key_hi(plan));
+            const uint4 r3 = philox<!kMulti>(uid_lo, uid_hi, ks, 3u, P.key_lo(plan), P.key_hi(plan));
             float pe[7], pn[7];
             float s_el = 0.f, s_ne = 0.f;
 #pragma unroll
@@ -578,7 +592,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                         if (target < cum) done = true;
                     }
                 }
-                const uint4 r4 = philox(uid_lo, uid_hi, ks, 4u, P.key_lo(plan), P.key_hi(plan));
+                const uint4 r4 = philox<!kMulti>(uid_lo, uid_hi, ks, 4u, P.key_lo(plan), P.key_hi(plan));
                 const float* ec = a.elem + 8 * el;
                 ev_el = elastic;
                 ev_ne = !elastic;
@@ -661,7 +675,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                     for (int c = 0; c < 4; ++c) {
                         float ev = 0.f;
                         if (c < n) {
-                            const uint4 rc = philox(uid_lo, uid_hi, ks, 17u + c, P.key_lo(plan), P.key_hi(plan));
+                            const uint4 rc = philox<!kMulti>(uid_lo, uid_hi, ks, 17u + c, P.key_lo(plan), P.key_hi(plan));
                             ev = inv_cdf33(xr, u01(rc.x), 0.f, 1.f) * T;
                         }
                         if (c == 0) ce0 = ev;
@@ -714,14 +728,14 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                         float dx = rdx, dy = rdy, dz = rdz;
                         const uint32_t jj = recoil ? 0u : (uint32_t)(c + 1);
                         if (!recoil) {
-                            const uint4 rc = philox(uid_lo, uid_hi, ks, 16u + jj, P.key_lo(plan), P.key_hi(plan));
+                            const uint4 rc = philox<!kMulti>(uid_lo, uid_hi, ks, 16u + jj, P.key_lo(plan), P.key_hi(plan));
                             const float mu = inv_cdf33(a.sec_mu + 33 * sec_row, u01(rc.y), -1.f, 1.f);
                             dx = odx;
                             dy = ody;
                             dz = odz;
                             rotate(dx, dy, dz, mu, sqrtf(fmaxf(0.f, 1.f - mu * mu)), u01(rc.z));
                         }
-                        const uint4 cu = philox(uid_lo, uid_hi, ks, 0xC0000000u | jj, P.key_lo(plan),
+                        const uint4 cu = philox<!kMulti>(uid_lo, uid_hi, ks, 0xC0000000u | jj, P.key_lo(plan),
                                                 P.key_hi(plan));
                         if (slot < cap) {
                             uint32_t* q = a.q_out + slot;
@@ -754,9 +768,10 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
     __syncthreads();
     // write the epoch's cached sums to the tally and clear the cache
     for (int i = threadIdx.x; i < n_slots; i += blockDim.x) {
-        const uint32_t key = ckey[i];
+        const Key key = ckey[i];
         if (key != kEmptySlot) {
-            unsafeAtomicAdd(&a.single.tally[key], cval[i]);
+            if constexpr (kMulti) unsafeAtomicAdd(&P.tally((uint32_t)(key >> 32))[(uint32_t)key], cval[i]);
+            else unsafeAtomicAdd(&a.single.tally[key], cval[i]);
             ++n_glob;
             ckey[i] = kEmptySlot;
             cval[i] = 0.0;

@@ -307,7 +307,8 @@ pmc_status pmc_unet_create(pmc_unet** out, int device, int n, int d, int h, int 
                 hp[c.off_w + (size_t)co * c.kp + k] = (i == 0 && ci >= 2) ? 0.f : sd * nd(rng);
             }
     }
-    for (int k = 0; k < 16; ++k) hp[u->off_hw + k] = 1.0e-3f * nd(rng);
+    // the head starts at zero: the network starts as the identity on the
+    // input dose and learns the correction
     A(hipMemcpy(u->p, hp.data(), u->n_params * 4, hipMemcpyHostToDevice));
     A(hipMemset(u->g, 0, u->n_params * 4));
     A(hipMemset(u->m1, 0, u->n_params * 4));

@@ -19,6 +19,9 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 #define DEV __device__ __forceinline__
 
+// negative slope of the leaky ReLU after every convolution
+constexpr float kLeak = 0.01f;
+
 DEV float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 // round-to-nearest-even float -> bf16 bits (finite inputs)
@@ -117,7 +120,7 @@ __global__ void __launch_bounds__(256) conv3d_fwd_kernel(const uint16_t* __restr
                 const int x = x0 + 16 * t + 4 * g + i;
                 if (x >= W) continue;
                 float v = acc[t][j][i] + bv;
-                if (relu) v = v > 0.f ? v : 0.f;
+                if (relu) v = v > 0.f ? v : kLeak * v;
                 out[(nbase + (size_t)z * plane + (size_t)y * W + x) * Cout + co] = f2bf(v);
             }
     }
@@ -274,11 +277,12 @@ __global__ void __launch_bounds__(256) conv3d_wgrad_kernel(const uint16_t* __res
 
 // ------------------------------------------------------------ elementwise
 
-// dy *= (y > 0)   (ReLU backward through the stored output)
+// dy *= (y > 0 ? 1 : kLeak)   (leaky-ReLU backward through the stored
+// output, which has the sign of the pre-activation)
 __global__ void relu_bwd_kernel(uint16_t* __restrict__ dy, const uint16_t* __restrict__ y, size_t n)
 {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        if (!(bf2f(y[i]) > 0.f)) dy[i] = 0;
+        if (!(bf2f(y[i]) > 0.f)) dy[i] = f2bf(kLeak * bf2f(dy[i]));
 }
 
 // db[c] += sum_v dy[v][c]: lanes stride over voxels for a fixed channel,

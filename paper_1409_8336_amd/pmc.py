@@ -78,6 +78,17 @@ class pmc_plan(C.Structure):
 
 
 _lib = None
+# voxel count of every loaded geometry, per (context, geometry id): the C calls
+# take bare device pointers, so the binding checks tensor sizes against it
+_geom_numel = {}
+
+
+def _need_numel(ctx, gid, t, name):
+    want = _geom_numel.get((ctx.value if hasattr(ctx, "value") else ctx, int(gid)))
+    if want is None:
+        raise ValueError("no geometry %d is loaded in this context" % gid)
+    if t.numel() != want:
+        raise ValueError("%s has %d elements, geometry %d has %d voxels" % (name, t.numel(), gid, want))
 
 
 def lib():
@@ -154,6 +165,9 @@ def pmc_create(device: int = 0, params: pmc_params | None = None):
 
 
 def pmc_destroy(ctx):
+    cv = getattr(ctx, "value", ctx)
+    for key in [k for k in _geom_numel if k[0] == cv]:
+        del _geom_numel[key]
     lib().pmc_destroy(ctx)
 
 
@@ -171,6 +185,7 @@ def pmc_load_geometry(ctx, hu, voxel_cm, mt: dict):
     t = pmc_material_table(len(arrs[0]), *[a.ctypes.data for a in arrs])
     _check(ctx, lib().pmc_load_geometry(ctx, _ptr(hu), nx, ny, nz, float(voxel_cm[0]),
                                         float(voxel_cm[1]), float(voxel_cm[2]), C.byref(t)))
+    _geom_numel[(ctx.value, 0)] = nx * ny * nz
     return (nz, ny, nx)
 
 
@@ -193,6 +208,7 @@ def pmc_load_geometry_slot(ctx, hu, voxel_cm, mt: dict) -> int:
     _check(ctx, lib().pmc_load_geometry_slot(ctx, C.byref(gid), _ptr(hu), nx, ny, nz,
                                              float(voxel_cm[0]), float(voxel_cm[1]),
                                              float(voxel_cm[2]), C.byref(t)))
+    _geom_numel[(ctx.value, gid.value)] = nx * ny * nz
     return gid.value
 
 
@@ -209,7 +225,12 @@ def pmc_run_plans(ctx, plans, seed, stream=None):
         d = p["d_dose"]
         if d.dtype != torch.float64 or not d.is_cuda or not d.is_contiguous():
             raise ValueError("d_dose must be a contiguous float64 device tensor")
+        _need_numel(ctx, p["geometry_id"], d, "d_dose")
         v = p.get("d_var")
+        if v is not None:
+            if v.dtype != torch.float64 or not v.is_cuda or not v.is_contiguous():
+                raise ValueError("d_var must be a contiguous float64 device tensor")
+            _need_numel(ctx, p["geometry_id"], v, "d_var")
         sm = pmc_summary()
         sums.append(sm)
         arr[i] = pmc_plan(int(p["geometry_id"]), len(sp), sp.ctypes.data, int(p["n_histories"]),
@@ -250,8 +271,9 @@ def pmc_run_spots_dev(ctx, spots, n_histories, seed, d_dose, d_var=None, stream=
     if d_dose.dtype != torch.float64 or not d_dose.is_cuda or not d_dose.is_contiguous():
         raise ValueError("d_dose must be a contiguous float64 device tensor")
     if d_var is not None and (d_var.dtype != torch.float64 or not d_var.is_contiguous()
-                              or d_var.numel() != d_dose.numel()):
+                              or not d_var.is_cuda or d_var.numel() != d_dose.numel()):
         raise ValueError("d_var must match d_dose")
+    _need_numel(ctx, 0, d_dose, "d_dose")
     if stream is None:
         stream = torch.cuda.current_stream(d_dose.device)
     handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
@@ -293,6 +315,8 @@ def pmc_geometry_density(ctx, geometry_id, d_rho, stream=None):
     import torch
     if d_rho.dtype != torch.float32 or not d_rho.is_cuda or not d_rho.is_contiguous():
         raise ValueError("d_rho must be a contiguous float32 device tensor")
+    if (ctx.value, int(geometry_id)) in _geom_numel:
+        _need_numel(ctx, geometry_id, d_rho, "d_rho")
     if stream is None:
         stream = torch.cuda.current_stream(d_rho.device)
     handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream

@@ -55,7 +55,8 @@ def test_conv_matches_library_conv3d():
     ref = torch.nn.functional.conv3d(torch.tensor(x).permute(0, 4, 1, 2, 3), torch.tensor(wt),
                                      torch.tensor(b), padding=1).permute(0, 2, 3, 4, 1).numpy()
     np.testing.assert_allclose(D.conv3d(x, w, b), ref, rtol=1e-12, atol=1e-12)
-    np.testing.assert_allclose(D.conv3d(x, w, b, relu=True), np.maximum(ref, 0), rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(D.conv3d(x, w, b, relu=True), np.where(ref > 0, ref, 0.01 * ref),
+                               rtol=1e-12, atol=1e-12)
     pts = [(1, 0, 0, 0), (0, 3, 4, 5), (1, 2, 2, 3)]
     np.testing.assert_allclose(D.conv3d_at(x, w, b, pts), np.array([ref[p] for p in pts]),
                                rtol=1e-12, atol=1e-12)

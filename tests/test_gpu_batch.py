@@ -97,3 +97,36 @@ def test_uneven_plan_batch_ledgers_and_oracle():
                 sums[0]["total_weight"], r["summary"]["total_weight"])
     _say("metrics plan0: %s" % m)
     assert m["idd_max_rel"] <= 0.01 and m["r80_diff_mm"] <= 0.2, m
+
+
+def test_batched_deposit_cache_preserves_results():
+    """The LDS deposit cache of a batched launch (keys: plan and tally index)
+    only regroups FP64 additions: per-plan dose and counts equal the
+    uncached batch (also for a tiny, often flushed cache), and with the
+    default size fewer atomics reach device memory."""
+    _say("case: batched deposit cache")
+    nd, mt = synth.nuclear_data(), synth.material_table()
+    plans = synth.plan_set(n_plans=4, seed=300, hist_scale=0.03, max_grid=(96, 96, 120),
+                           min_grid=(48, 48, 60))
+    res = []
+    for params in (dict(block_threads=1024, tally_cache=-1), dict(block_threads=1024),
+                   dict(block_threads=1024, tally_cache=600, epoch_steps=5, cache_probes=2)):
+        e, ids = _batch_engine(nd, mt, plans, **params)
+        out, sums = _run_batch(e, ids, plans, 31)
+        e.close()
+        res.append((params, out, sums))
+    p0, out0, s0 = res[0]
+    for params, out, sums in res[1:]:
+        for p in range(len(plans)):
+            d0 = out0[p][0]
+            np.testing.assert_allclose(out[p][0], d0, rtol=1e-9, atol=1e-9 * d0.max())
+            for key in ("steps", "n_elastic", "n_nonelastic", "tally_atomics", "histories"):
+                assert sums[p][key] == s0[p][key], (params, p, key)
+            assert sums[p]["cache_slots"] > 0
+            if "tally_cache" not in params:
+                # the default cache absorbs deposits; the tiny one flushed every 5
+                # iterations may not (each flush costs an atomic per used slot)
+                assert sums[p]["global_atomics"] < s0[p]["global_atomics"], (params, p)
+            assert ledger_residual(sums[p]) < 1e-9
+        _say("%s: global atomics %d of %d deposits (plan 0)"
+             % (params, sums[0]["global_atomics"], sums[0]["tally_atomics"]))

@@ -324,3 +324,24 @@ def test_full_size_field_properties(nd, mt):
     diff = np.abs(g_idd - o_idd)
     assert np.all(diff <= 4 * o_sd + 0.01 * o_idd.max()), float((diff / o_idd.max()).max())
     assert abs(s["steps"] / s["histories"] / (r["summary"]["steps"] / n_o) - 1) < 0.02
+
+
+def test_geometry_density_matches_hu_calibration(nd, mt):
+    """pmc_geometry_density returns the density the transport uses: the
+    piecewise-linear HU calibration (Sec. II.A.1) restated on the host, to
+    float32 rounding, for the main geometry and an extra geometry slot."""
+    import torch
+    _say("case: geometry density")
+    hu = synth.ct_phantom(40, 36, 30, 0.2, seed=9)
+    hu2 = synth.scaled_ct_phantom(24, 20, 16, seed=10)
+    e = _engine(nd, mt, hu)
+    gid = pmc.pmc_load_geometry_slot(e.ctx, hu2, (0.2, 0.2, 0.2), mt)
+    for g, h in ((0, hu), (gid, hu2)):
+        rho = torch.empty(h.shape, dtype=torch.float32, device="cuda")
+        pmc.pmc_geometry_density(e.ctx, g, rho)
+        torch.cuda.synchronize()
+        ref = density_grid(h)
+        np.testing.assert_allclose(rho.cpu().numpy(), ref, rtol=2.0 ** -23, atol=0)
+    with pytest.raises(pmc.PMCError):
+        pmc.pmc_geometry_density(e.ctx, 99, torch.empty(hu.shape, dtype=torch.float32, device="cuda"))
+    e.close()
