@@ -32,8 +32,8 @@ HBM_PEAK = 8.0e12
 # HBM bytes per transport launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
 # scaled by a plain-copy calibration, valid only for the kernel source whose
 # sha256 is recorded (see profiles/); None once the kernel has changed.
-TRAFFIC = {"transport_sha256": "1b16c75b950b37798d0e0b395d11d2515572aafabc43c265e9da9dcabf20a747",
-           "bytes_per_launch": 3.057e9}
+TRAFFIC = {"transport_sha256": "e09ad140a048ac7bf25c8adb15c2a833d116b2eebb36bd1feb8091a7cb9485d7",
+           "bytes_per_launch": 2.907e9}
 
 
 def _kernel_sha():
