@@ -277,7 +277,7 @@ def main():
     n_tot = args.steps * cfg["n_histories"]
     steps_tot = sum(s["steps"] for s in sums)
     transport_s = sum(s["transport_ms"] for s in sums) * 1e-3
-    launches = sum(s["generations"] for s in sums)
+    launches = sum(s["launches"] for s in sums)
     achieved = ALG_BYTES_PER_STEP * steps_tot / transport_s
     deposits_tot = sum(s["tally_atomics"] for s in sums)
     atomics_tot = sum(s["global_atomics"] for s in sums)

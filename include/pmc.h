@@ -78,10 +78,12 @@ typedef struct {
     int32_t cache_probes;    /* cache slots tried per deposit (linear probing), 1..16; 0 = 4 */
 } pmc_params;
 /* Autotuning: when any of block_threads, refill_lanes, batch_events is 0 and
- * a run has at least 1e6 histories, the first run of each workload signature
- * (single/batched, plan count, log2 of histories and voxels) times a few
- * candidate launch shapes on a 2e5-history copy of the workload and keeps the
- * fastest for that signature.  Results do not depend on the shape. */
+ * a run has at least 2e5 histories, the first run of each workload signature
+ * (single/batched, plan count, log2 of histories and voxels) times the
+ * candidate launch shapes (workgroup size, refill and event thresholds, LDS
+ * deposit cache on or off) on the first spots of every plan, a fifth of the
+ * run (2e5 to 2e6 histories), and keeps the fastest for that signature.
+ * Results do not depend on the shape. */
 
 /* Fill *p with the defaults above.  Never fails for a non-NULL p. */
 pmc_status pmc_default_params(pmc_params* p);
@@ -137,8 +139,10 @@ typedef struct {
     double total_weight;   /* sum of primary weights (dose normalisation) */
     double device_ms;      /* device time of the run, HIP events */
     double transport_ms;   /* sum over transport launches of their HIP-event durations */
-    int32_t generations;   /* transport launches (primaries + secondary generations) */
-    int32_t reserved;
+    int32_t generations;   /* generations run: primaries, secondary generations, and the
+                              empty one that ends the run */
+    int32_t launches;      /* transport launches issued (generations are launched in groups;
+                              launches past the empty generation exit at once) */
     uint64_t global_atomics; /* FP64 atomic adds that reached the tally in device memory
                                 (deposits that missed the LDS cache plus cache flushes) */
     int32_t block_threads;   /* launch shape used: workgroup size, */

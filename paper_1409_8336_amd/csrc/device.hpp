@@ -33,6 +33,28 @@ struct PlanDesc {
 };
 static_assert(sizeof(PlanDesc) == 64, "PlanDesc is 16 words");
 
+// Arguments the step loop does not read every step: staged in LDS at the
+// start of the transport kernel and read there at their use sites, so that
+// they do not hold scalar registers across the loop.
+struct alignas(8) LdsArgs {
+    const float* el_sig;
+    const float* mat_npg;
+    const float* elem;
+    const float* sec_mult;
+    const float* sec_floc;
+    const float* sec_x;
+    const float* sec_mu;
+    const float* spots;
+    const unsigned long long* spot_start;
+    const uint32_t* q_in;
+    uint32_t* q_out;
+    unsigned long long q_cap;
+    double* ledger;
+    unsigned long long* counters;
+    int n_spots;
+    int pad;
+};
+
 struct KernelArgs {
     PlanDesc single;            // the plan of a single-plan launch
     const PlanDesc* plans;      // batched launch: n_plans descriptors, staged into LDS
@@ -84,10 +106,12 @@ struct KernelArgs {
     int cache_probes;   // slots tried (linear probing) before a deposit goes to the tally
     // work claims: workgroup b of a launch of G workgroups takes its j-th
     // index from its own counter wg_claims[gen * G + b] and maps it to
-    // ((j >> claim_log2) * G + b) << claim_log2 | (j & (2^claim_log2 - 1)),
-    // i.e. chunks of 2^claim_log2 consecutive indices dealt round-robin
+    // ((j >> c) * G + b) << c | (j & (2^c - 1)), i.e. runs of 2^c consecutive
+    // indices dealt round-robin; c is at most claim_log2 and small enough
+    // that every workgroup gets about four runs of the generation's work
     unsigned long long* wg_claims;
     int claim_log2;
+    int args_off;   // LDS word offset (even) of the staged LdsArgs
 };
 
 }  // namespace pmc

@@ -123,6 +123,7 @@ struct pmc_ctx {
 namespace {
 
 constexpr size_t kPinnedBytes = 65536;
+constexpr int kGenGroup = 6;   // generations launched per host synchronisation
 
 pmc_status fail(pmc_ctx* c, pmc_status s, const std::string& msg)
 {
@@ -451,7 +452,7 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
         slots = want;
         if (slots == 0) {
             const long wgs = std::max(1, 1024 / block);
-            const long avail = 163840L / wgs - (long)lds_words * 4 - 64;
+            const long avail = 163840L / wgs - (long)lds_words * 4 - 16 - (long)sizeof(LdsArgs) - 16;
             slots = (int)std::min(16384L, avail / (4L * (2 + key_words)));
             if (slots < 512) slots = 0;
         }
@@ -460,7 +461,9 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
     a.cache_off = (int)((lds_words + 1) & ~(size_t)1);
     a.epoch_iters = c->p.epoch_steps ? c->p.epoch_steps : 32;
     a.cache_probes = c->p.cache_probes ? c->p.cache_probes : 4;
-    const size_t lds = slots ? (size_t)(a.cache_off + (2 + key_words) * slots + 1) * 4 : lds_words * 4;
+    const size_t used = slots ? (size_t)a.cache_off + (size_t)(2 + key_words) * slots + 1 : lds_words;
+    a.args_off = (int)((used + 1) & ~(size_t)1);
+    const size_t lds = (size_t)a.args_off * 4 + sizeof(LdsArgs);
     int max_block = 0;
     HIPCHK(transport_max_block(multi, &max_block), "kernel attributes");
     if (block > max_block) return fail(c, PMC_ERR_ARG, "block_threads exceeds the transport kernel's limit");
@@ -475,25 +478,42 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
     a.wg_claims = c->d_wgc.p;
     int gens = 0;
     unsigned long long produced_total = 0, overflow_n = 0;
+    // generations are launched in groups without waiting: each launch reads
+    // its own work count on the device (an empty generation exits at once),
+    // and the host reads the produced counts once per group
+    int launched = 0;
     if (total > 0) {
-        for (int gidx = 0;; ++gidx) {
-            if (gidx >= kMaxGenerations) return fail(c, PMC_ERR_DEVICE, "secondary generations exceed limit");
-            a.gen = gidx;
-            // primaries in runs of 1024 consecutive histories (one spot's
-            // worth, for the deposit cache), secondaries in runs of 64
-            a.claim_log2 = gidx == 0 ? 10 : 6;
-            a.q_in = c->d_q[gidx & 1].p;
-            a.q_out = c->d_q[(gidx + 1) & 1].p;
-            HIPCHK(hipEventRecord(c->ev_gen[2 * gidx], st), "event");
-            HIPCHK(launch_transport(a, multi, grid, block, lds, st), "transport launch");
-            HIPCHK(hipEventRecord(c->ev_gen[2 * gidx + 1], st), "event");
-            ++gens;
-            HIPCHK(hipMemcpyAsync(c->h_pinned, c->d_gc.p + 2 * (gidx + 1), 8, hipMemcpyDeviceToHost, st), "read counters");
+        bool done = false;
+        while (!done) {
+            const int g0 = launched;
+            const int g1 = std::min(g0 + kGenGroup, kMaxGenerations);
+            if (g0 >= kMaxGenerations) return fail(c, PMC_ERR_DEVICE, "secondary generations exceed limit");
+            for (int gidx = g0; gidx < g1; ++gidx) {
+                a.gen = gidx;
+                // primaries in runs of 1024 consecutive histories (one spot's
+                // worth, for the deposit cache), secondaries in runs of 64
+                a.claim_log2 = gidx == 0 ? 10 : 6;
+                a.q_in = c->d_q[gidx & 1].p;
+                a.q_out = c->d_q[(gidx + 1) & 1].p;
+                HIPCHK(hipEventRecord(c->ev_gen[2 * gidx], st), "event");
+                HIPCHK(launch_transport(a, multi, grid, block, lds, st), "transport launch");
+                HIPCHK(hipEventRecord(c->ev_gen[2 * gidx + 1], st), "event");
+            }
+            launched = g1;
+            // produced counts of generations g0+1 .. g1: words 2(g0+1) .. 2 g1
+            HIPCHK(hipMemcpyAsync(c->h_pinned, c->d_gc.p + 2 * (g0 + 1), 8 * (2 * (g1 - g0) - 1),
+                                  hipMemcpyDeviceToHost, st), "read counters");
             HIPCHK(hipStreamSynchronize(st), "transport");
-            const unsigned long long prod = c->h_pinned[0];
-            produced_total += prod;
-            if (prod > cap) overflow_n += prod - cap;
-            if (prod == 0) break;
+            for (int gidx = g0; gidx < g1; ++gidx) {
+                const unsigned long long prod = c->h_pinned[2 * (gidx - g0)];
+                ++gens;
+                produced_total += prod;
+                if (prod > cap) overflow_n += prod - cap;
+                if (prod == 0) {
+                    done = true;
+                    break;
+                }
+            }
         }
     }
     if (!tuning) {
@@ -514,7 +534,7 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1), "event time");
     double transport_ms = 0.0;
-    for (int gidx = 0; gidx < gens; ++gidx) {
+    for (int gidx = 0; gidx < launched; ++gidx) {
         float t = 0.f;
         HIPCHK(hipEventElapsedTime(&t, c->ev_gen[2 * gidx], c->ev_gen[2 * gidx + 1]), "event time");
         transport_ms += t;
@@ -553,6 +573,7 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
             sm->device_ms = ms;
             sm->transport_ms = transport_ms;
             sm->generations = gens;
+            sm->launches = launched;
         }
     }
     if (overflow_n) return fail(c, PMC_ERR_QUEUE_OVERFLOW, "secondary queue overflow: raise queue_capacity");
@@ -575,7 +596,7 @@ pmc_status choose_shape(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, hipS
         total += p.n_hist;
         vox += p.g->nvox();
     }
-    if (!tune || total < 1000000ull) {
+    if (!tune || total < 200000ull) {
         *out = s;
         return PMC_OK;
     }

@@ -203,6 +203,24 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
         ckey[i] = kEmptySlot;
     }
     if (use_cache && threadIdx.x == 0) *waves_done = 0;
+    LdsArgs* const L = reinterpret_cast<LdsArgs*>(lds + a.args_off);
+    if (threadIdx.x == 0) {
+        L->el_sig = a.el_sig;
+        L->mat_npg = a.mat_npg;
+        L->elem = a.elem;
+        L->sec_mult = a.sec_mult;
+        L->sec_floc = a.sec_floc;
+        L->sec_x = a.sec_x;
+        L->sec_mu = a.sec_mu;
+        L->spots = a.spots;
+        L->spot_start = a.spot_start;
+        L->q_in = a.q_in;
+        L->q_out = a.q_out;
+        L->q_cap = a.q_cap;
+        L->ledger = a.ledger;
+        L->counters = a.counters;
+        L->n_spots = a.n_spots;
+    }
     __syncthreads();
     const PlanDesc* pds = reinterpret_cast<const PlanDesc*>(lds + a.pd_offset);
     const Plans<kMulti> P{a, pds};
@@ -216,19 +234,23 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
 
     const int lane = threadIdx.x & (kWave - 1);
     const int gen = a.gen;
-    unsigned long long* const claim = &a.wg_claims[(size_t)gen * gridDim.x + blockIdx.x];
-    const uint32_t cl2 = (uint32_t)a.claim_log2;
-    const unsigned long long cmask = (1ull << cl2) - 1ull;
-    // the workgroup's j-th claim -> index into the generation's work list
-    auto claim_index = [&](unsigned long long j) {
-        return ((((j >> cl2) * gridDim.x) + blockIdx.x) << cl2) | (j & cmask);
-    };
     unsigned long long* const out_reserve = &a.gen_counters[2 * (gen + 1)];
     unsigned long long limit = a.n_primary;
     if (gen > 0) {
         const unsigned long long produced = a.gen_counters[2 * gen];
         limit = produced < a.q_cap ? produced : a.q_cap;
     }
+    unsigned long long* const claim = &a.wg_claims[(size_t)gen * gridDim.x + blockIdx.x];
+    // run length: the largest power of two up to 2^claim_log2 that still
+    // gives every workgroup about four runs of this generation's work
+    const unsigned long long per_wg = limit / (4ull * gridDim.x);
+    uint32_t cl2 = 0;
+    while (cl2 < (uint32_t)a.claim_log2 && (2ull << cl2) <= per_wg) ++cl2;
+    const unsigned long long cmask = (1ull << cl2) - 1ull;
+    // the workgroup's j-th claim -> index into the generation's work list
+    auto claim_index = [&](unsigned long long j) {
+        return ((((j >> cl2) * gridDim.x) + blockIdx.x) << cl2) | (j & cmask);
+    };
     const int K = a.k_batches;
     const uint32_t flags = a.flags;
 
@@ -242,11 +264,11 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
     double acc_esc = 0.0, acc_neu = 0.0, acc_ovf = 0.0;
     uint32_t n_steps = 0, n_el = 0, n_ne = 0, n_short = 0, n_dep = 0, n_glob = 0;
     auto flush = [&](uint32_t pl) {
-        double* L = a.ledger + 4 * pl;
-        unsigned long long* C = a.counters + 8 * pl;
-        if (acc_esc != 0.0) unsafeAtomicAdd(&L[0], acc_esc);
-        if (acc_neu != 0.0) unsafeAtomicAdd(&L[1], acc_neu);
-        if (acc_ovf != 0.0) unsafeAtomicAdd(&L[2], acc_ovf);
+        double* LG = L->ledger + 4 * pl;
+        unsigned long long* C = L->counters + 8 * pl;
+        if (acc_esc != 0.0) unsafeAtomicAdd(&LG[0], acc_esc);
+        if (acc_neu != 0.0) unsafeAtomicAdd(&LG[1], acc_neu);
+        if (acc_ovf != 0.0) unsafeAtomicAdd(&LG[2], acc_ovf);
         if (n_steps) atomicAdd(&C[0], (unsigned long long)n_steps);
         if (n_el) atomicAdd(&C[1], (unsigned long long)n_el);
         if (n_ne) atomicAdd(&C[2], (unsigned long long)n_ne);
@@ -304,14 +326,14 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                 if (idx < limit) {
                     if (gen == 0) {
                         // source: Gaussian spot on the z = 0 face (K1 role)
-                        int lo = 0, hi = a.n_spots;
+                        int lo = 0, hi = L->n_spots;
                         while (hi - lo > 1) {
                             const int mid = (lo + hi) >> 1;
-                            if (a.spot_start[mid] <= idx) lo = mid;
+                            if (L->spot_start[mid] <= idx) lo = mid;
                             else hi = mid;
                         }
-                        const float* sp = a.spots + 8 * lo;
-                        const unsigned long long s0 = a.spot_start[lo], s1 = a.spot_start[lo + 1];
+                        const float* sp = L->spots + 8 * lo;
+                        const unsigned long long s0 = L->spot_start[lo], s1 = L->spot_start[lo + 1];
                         unsigned long long uid = idx;
                         if constexpr (kMulti) {
                             // uid within the plan: the spot's first index in its plan
@@ -338,8 +360,8 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                         mfp = -fln(u01(r.z));
                         batch = (uint32_t)(((idx - s0) * (unsigned long long)K) / (s1 - s0));
                     } else {
-                        const uint32_t* q = a.q_in + idx;
-                        const unsigned long long c = a.q_cap;
+                        const uint32_t* q = L->q_in + idx;
+                        const unsigned long long c = L->q_cap;
                         px = __uint_as_float(q[0]);
                         py = __uint_as_float(q[c]);
                         pz = __uint_as_float(q[2 * c]);
@@ -567,9 +589,9 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
             float s_el = 0.f, s_ne = 0.f;
 #pragma unroll
             for (int e = 0; e < 7; ++e) {
-                const float npg = a.mat_npg[7 * m + e];
-                const float* te = a.el_sig + e * 1000;
-                const float* tn = a.el_sig + (7 + e) * 1000;
+                const float npg = L->mat_npg[7 * m + e];
+                const float* te = L->el_sig + e * 1000;
+                const float* tn = L->el_sig + (7 + e) * 1000;
                 pe[e] = npg > 0.f ? npg * (te[gi] + gt * (te[gi + 1] - te[gi])) : 0.f;
                 pn[e] = npg > 0.f ? npg * (tn[gi] + gt * (tn[gi + 1] - tn[gi])) : 0.f;
                 s_el += pe[e];
@@ -593,7 +615,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                     }
                 }
                 const uint4 r4 = philox<!kMulti>(uid_lo, uid_hi, ks, 4u, P.key_lo(plan), P.key_hi(plan));
-                const float* ec = a.elem + 8 * el;
+                const float* ec = L->elem + 8 * el;
                 ev_el = elastic;
                 ev_ne = !elastic;
                 if (elastic) {
@@ -664,12 +686,12 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                     j = j > 24 ? 24 : j;
                     const int row = nu * 25 + j;
                     sec_row = row;
-                    const float* mc5 = a.sec_mult + 5 * row;
+                    const float* mc5 = L->sec_mult + 5 * row;
                     const float um = u01(r4.x);
                     int n = 0;
                     while (n < 4 && !(um < mc5[n])) ++n;
-                    const float fl = a.sec_floc[row];
-                    const float* xr = a.sec_x + 33 * row;
+                    const float fl = L->sec_floc[row];
+                    const float* xr = L->sec_x + 33 * row;
                     float sum = 0.f;
 #pragma unroll
                     for (int c = 0; c < 4; ++c) {
@@ -720,7 +742,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
             base = bcast0(base);
             if (n_out > 0) {
                 unsigned long long slot = base + off;
-                const unsigned long long cap = a.q_cap;
+                const unsigned long long cap = L->q_cap;
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     const float ev = c == 0 ? ce0 : (c == 1 ? ce1 : (c == 2 ? ce2 : ce3));
@@ -729,7 +751,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                         const uint32_t jj = recoil ? 0u : (uint32_t)(c + 1);
                         if (!recoil) {
                             const uint4 rc = philox<!kMulti>(uid_lo, uid_hi, ks, 16u + jj, P.key_lo(plan), P.key_hi(plan));
-                            const float mu = inv_cdf33(a.sec_mu + 33 * sec_row, u01(rc.y), -1.f, 1.f);
+                            const float mu = inv_cdf33(L->sec_mu + 33 * sec_row, u01(rc.y), -1.f, 1.f);
                             dx = odx;
                             dy = ody;
                             dz = odz;
@@ -738,7 +760,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                         const uint4 cu = philox<!kMulti>(uid_lo, uid_hi, ks, 0xC0000000u | jj, P.key_lo(plan),
                                                 P.key_hi(plan));
                         if (slot < cap) {
-                            uint32_t* q = a.q_out + slot;
+                            uint32_t* q = L->q_out + slot;
                             q[0] = __float_as_uint(ox);
                             q[cap] = __float_as_uint(oy);
                             q[2 * cap] = __float_as_uint(oz);
@@ -838,16 +860,29 @@ hipError_t launch_atomic_probe(double* tally, int nx, int ny, int nz, int K, int
 
 // dose statistics over the K groups: total, variance of the total, and the
 // deposited-energy sum (Sec. II.B.2)
-__global__ void __launch_bounds__(256) stats_kernel(const double* __restrict__ tally,
-                                                    const uint2* __restrict__ vox,
-                                                    unsigned long long nvox, int K, double conv0,
-                                                    double* __restrict__ dose,
-                                                    double* __restrict__ var, double* dep_sum)
+// A block takes kStatsVox consecutive voxels at a time: their [voxel][K]
+// tally rows form one contiguous run, read with unit stride into LDS, then
+// each lane reduces its voxel's K groups from LDS.
+constexpr int kStatsVox = 128;
+__global__ void __launch_bounds__(kStatsVox) stats_kernel(const double* __restrict__ tally,
+                                                          const uint2* __restrict__ vox,
+                                                          unsigned long long nvox, int K, double conv0,
+                                                          double* __restrict__ dose,
+                                                          double* __restrict__ var, double* dep_sum)
 {
+    extern __shared__ double rows[];   // kStatsVox * K
     double part = 0.0;
-    for (unsigned long long v = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; v < nvox;
-         v += (unsigned long long)gridDim.x * blockDim.x) {
-        const double* t = tally + v * K;
+    for (unsigned long long v0 = blockIdx.x * (unsigned long long)kStatsVox; v0 < nvox;
+         v0 += (unsigned long long)gridDim.x * kStatsVox) {
+        const unsigned long long left = nvox - v0;
+        const int nv = left < (unsigned long long)kStatsVox ? (int)left : kStatsVox;
+        __syncthreads();
+        const double* src = tally + v0 * K;
+        for (int i = threadIdx.x; i < nv * K; i += kStatsVox) rows[i] = src[i];
+        __syncthreads();
+        if ((int)threadIdx.x >= nv) continue;
+        const unsigned long long v = v0 + threadIdx.x;
+        const double* t = rows + threadIdx.x * K;
         double tot = 0.0;
         for (int b = 0; b < K; ++b) tot += t[b];
         const double mean = tot / K;
@@ -918,11 +953,13 @@ hipError_t transport_occupancy(bool multi, int block, size_t lds_bytes, int* blo
 hipError_t launch_stats(const double* tally, const uint2* vox, unsigned long long nvox, int K,
                         double conv0, double* dose, double* var, double* dep_sum, hipStream_t s)
 {
-    unsigned long long blocks = (nvox + 255) / 256;
+    if (K < 2 || K > 64) return hipErrorInvalidValue;
+    unsigned long long blocks = (nvox + kStatsVox - 1) / kStatsVox;
     if (blocks > 65536) blocks = 65536;
     if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(stats_kernel, dim3((unsigned)blocks), dim3(256), 0, s, tally, vox, nvox, K,
-                       conv0, dose, var, dep_sum);
+    hipLaunchKernelGGL(stats_kernel, dim3((unsigned)blocks), dim3(kStatsVox),
+                       (size_t)kStatsVox * K * sizeof(double), s, tally, vox, nvox, K, conv0, dose, var,
+                       dep_sum);
     return hipGetLastError();
 }
 

@@ -66,7 +66,7 @@ class pmc_summary(C.Structure):
                 ("n_short_steps", C.c_uint64), ("tally_atomics", C.c_uint64),
                 ("total_weight", C.c_double), ("device_ms", C.c_double),
                 ("transport_ms", C.c_double), ("generations", C.c_int32),
-                ("reserved", C.c_int32), ("global_atomics", C.c_uint64),
+                ("launches", C.c_int32), ("global_atomics", C.c_uint64),
                 ("block_threads", C.c_int32), ("grid_blocks", C.c_int32),
                 ("cache_slots", C.c_int32), ("epoch_steps", C.c_int32)]
 
@@ -244,7 +244,7 @@ def pmc_run_plans(ctx, plans, seed, stream=None):
 
 
 def summary_dict(s: pmc_summary) -> dict:
-    return {f[0]: getattr(s, f[0]) for f in pmc_summary._fields_ if f[0] != "reserved"}
+    return {f[0]: getattr(s, f[0]) for f in pmc_summary._fields_}
 
 
 def _spots(spots):

@@ -261,9 +261,10 @@ def test_deposit_cache_preserves_results(nd, mt):
     _say("case: deposit cache")
     cfg = synth.config_ct_spots(150.0, 30_000)
     runs = []
-    for params in (dict(block_threads=1024, tally_cache=-1), dict(block_threads=1024),
-                   dict(block_threads=1024, tally_cache=512, epoch_steps=7),
-                   dict(block_threads=512, tally_cache=2048, epoch_steps=300)):
+    fixed = dict(refill_lanes=16, batch_events=4)   # no autotuning
+    for params in (dict(fixed, block_threads=1024, tally_cache=-1), dict(fixed, block_threads=1024),
+                   dict(fixed, block_threads=1024, tally_cache=512, epoch_steps=7),
+                   dict(fixed, block_threads=512, tally_cache=2048, epoch_steps=300)):
         e = _engine(nd, mt, cfg["hu"], **params)
         d, v, s = e.run_spots(cfg["spots"], cfg["n_histories"], 6)
         e.close()
