@@ -452,7 +452,8 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
         slots = want;
         if (slots == 0) {
             const long wgs = std::max(1, 1024 / block);
-            const long avail = 163840L / wgs - (long)lds_words * 4 - 16 - (long)sizeof(LdsArgs) - 16;
+            const long avail = 163840L / wgs - (long)lds_words * 4 - 16 - (long)sizeof(LdsArgs) -
+                               (multi ? 72L * np : 0L) - 16;
             slots = (int)std::min(16384L, avail / (4L * (2 + key_words)));
             if (slots < 512) slots = 0;
         }
@@ -463,7 +464,8 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
     a.cache_probes = c->p.cache_probes ? c->p.cache_probes : 4;
     const size_t used = slots ? (size_t)a.cache_off + (size_t)(2 + key_words) * slots + 1 : lds_words;
     a.args_off = (int)((used + 1) & ~(size_t)1);
-    const size_t lds = (size_t)a.args_off * 4 + sizeof(LdsArgs);
+    // batched launches: per-plan ledger (3 doubles) and counters (6 u64) after the arguments
+    const size_t lds = (size_t)a.args_off * 4 + sizeof(LdsArgs) + (multi ? 72 * (size_t)np : 0);
     int max_block = 0;
     HIPCHK(transport_max_block(multi, &max_block), "kernel attributes");
     if (block > max_block) return fail(c, PMC_ERR_ARG, "block_threads exceeds the transport kernel's limit");

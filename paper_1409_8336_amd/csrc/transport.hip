@@ -29,6 +29,7 @@ constexpr float kInvH = 999.0f / 7.824046011f;    // 1 / (ln(2500)/999)
 constexpr float kH = 7.824046011f / 999.0f;
 constexpr float kStraggleK = 0.156914976f;        // K m_e c^2, MeV^2 cm^2 / g
 constexpr float kInf = 3.0e38f;
+constexpr int kWgCounters = 6;   // steps, elastic, non-elastic, short steps, deposits, tally atomics
 constexpr uint32_t kMaxSteps = 1u << 20;
 constexpr uint32_t kNoStraggle = 1u, kNoMcs = 2u, kNoNuclear = 4u;
 
@@ -204,6 +205,17 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
     }
     if (use_cache && threadIdx.x == 0) *waves_done = 0;
     LdsArgs* const L = reinterpret_cast<LdsArgs*>(lds + a.args_off);
+    // batched launches: per-plan ledger (escaped, neutral, overflow) and
+    // counters of the workgroup, accumulated in LDS and written out once at
+    // the end (lanes change plan at nearly every refill of a secondary
+    // generation; flushing to the same few device addresses each time
+    // serialised on the memory-side atomics)
+    double* const wg_led = reinterpret_cast<double*>(lds + a.args_off + (int)(sizeof(LdsArgs) / 4));
+    unsigned long long* const wg_cnt = reinterpret_cast<unsigned long long*>(wg_led + 3 * a.n_plans);
+    if constexpr (kMulti) {
+        for (int i = threadIdx.x; i < 3 * a.n_plans; i += blockDim.x) wg_led[i] = 0.0;
+        for (int i = threadIdx.x; i < kWgCounters * a.n_plans; i += blockDim.x) wg_cnt[i] = 0ull;
+    }
     if (threadIdx.x == 0) {
         L->el_sig = a.el_sig;
         L->mat_npg = a.mat_npg;
@@ -264,6 +276,22 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
     double acc_esc = 0.0, acc_neu = 0.0, acc_ovf = 0.0;
     uint32_t n_steps = 0, n_el = 0, n_ne = 0, n_short = 0, n_dep = 0, n_glob = 0;
     auto flush = [&](uint32_t pl) {
+        if constexpr (kMulti) {
+            double* LG = wg_led + 3 * pl;
+            unsigned long long* C = wg_cnt + kWgCounters * pl;
+            if (acc_esc != 0.0) unsafeAtomicAdd(&LG[0], acc_esc);
+            if (acc_neu != 0.0) unsafeAtomicAdd(&LG[1], acc_neu);
+            if (acc_ovf != 0.0) unsafeAtomicAdd(&LG[2], acc_ovf);
+            if (n_steps) atomicAdd(&C[0], (unsigned long long)n_steps);
+            if (n_el) atomicAdd(&C[1], (unsigned long long)n_el);
+            if (n_ne) atomicAdd(&C[2], (unsigned long long)n_ne);
+            if (n_short) atomicAdd(&C[3], (unsigned long long)n_short);
+            if (n_dep) atomicAdd(&C[4], (unsigned long long)n_dep);
+            if (n_glob) atomicAdd(&C[5], (unsigned long long)n_glob);
+            acc_esc = acc_neu = acc_ovf = 0.0;
+            n_steps = n_el = n_ne = n_short = n_dep = n_glob = 0;
+            return;
+        }
         double* LG = L->ledger + 4 * pl;
         unsigned long long* C = L->counters + 8 * pl;
         if (acc_esc != 0.0) unsafeAtomicAdd(&LG[0], acc_esc);
@@ -807,6 +835,15 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
     // -------------------------------------------------- flush the ledger
     if constexpr (kMulti) {
         flush(plan);
+        __syncthreads();
+        for (int i = threadIdx.x; i < 3 * a.n_plans; i += blockDim.x) {
+            const int pl = i / 3, f = i - 3 * pl;
+            if (wg_led[i] != 0.0) unsafeAtomicAdd(&L->ledger[4 * pl + f], wg_led[i]);
+        }
+        for (int i = threadIdx.x; i < kWgCounters * a.n_plans; i += blockDim.x) {
+            const int pl = i / kWgCounters, f = i - kWgCounters * pl;
+            if (wg_cnt[i] != 0ull) atomicAdd(&L->counters[8 * pl + f], wg_cnt[i]);
+        }
     } else {
         for (int o = 32; o > 0; o >>= 1) {
             acc_esc += __shfl_xor(acc_esc, o);
