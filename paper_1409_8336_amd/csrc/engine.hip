@@ -635,7 +635,7 @@ pmc_status choose_shape(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, hipS
     }
     std::vector<Shape> cands;
     for (int b : {256, 512, 1024})
-        for (int r : {16, 32})
+        for (int r : {8, 16})
             for (int e : {2, 4})
                 for (int ch : {0, -1}) {
                     Shape x;

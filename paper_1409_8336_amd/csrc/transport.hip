@@ -898,8 +898,9 @@ hipError_t launch_atomic_probe(double* tally, int nx, int ny, int nz, int K, int
 // dose statistics over the K groups: total, variance of the total, and the
 // deposited-energy sum (Sec. II.B.2)
 // A block takes kStatsVox consecutive voxels at a time: their [voxel][K]
-// tally rows form one contiguous run, read with unit stride into LDS, then
-// each lane reduces its voxel's K groups from LDS.
+// tally rows form one contiguous run, read with 16-byte unit-stride loads
+// into LDS rows padded to an odd number of doubles (fewer bank conflicts),
+// then each lane reduces its voxel's K groups from LDS.
 constexpr int kStatsVox = 128;
 __global__ void __launch_bounds__(kStatsVox) stats_kernel(const double* __restrict__ tally,
                                                           const uint2* __restrict__ vox,
@@ -907,19 +908,28 @@ __global__ void __launch_bounds__(kStatsVox) stats_kernel(const double* __restri
                                                           double* __restrict__ dose,
                                                           double* __restrict__ var, double* dep_sum)
 {
-    extern __shared__ double rows[];   // kStatsVox * K
+    extern __shared__ double rows[];   // kStatsVox * (K | 1)
+    const int pitch = K | 1;
     double part = 0.0;
     for (unsigned long long v0 = blockIdx.x * (unsigned long long)kStatsVox; v0 < nvox;
          v0 += (unsigned long long)gridDim.x * kStatsVox) {
         const unsigned long long left = nvox - v0;
         const int nv = left < (unsigned long long)kStatsVox ? (int)left : kStatsVox;
+        const int n = nv * K;                      // doubles in this run
         __syncthreads();
-        const double* src = tally + v0 * K;
-        for (int i = threadIdx.x; i < nv * K; i += kStatsVox) rows[i] = src[i];
+        // the run starts at v0 * K doubles, a multiple of 2: 16-byte aligned
+        const double2* src2 = reinterpret_cast<const double2*>(tally + v0 * K);
+        for (int i = threadIdx.x; i < (n >> 1); i += kStatsVox) {
+            const double2 q = src2[i];
+            const int e0 = 2 * i, e1 = 2 * i + 1;
+            rows[(e0 / K) * pitch + e0 % K] = q.x;
+            rows[(e1 / K) * pitch + e1 % K] = q.y;
+        }
+        if ((n & 1) && threadIdx.x == 0) rows[((n - 1) / K) * pitch + (n - 1) % K] = tally[v0 * K + n - 1];
         __syncthreads();
         if ((int)threadIdx.x >= nv) continue;
         const unsigned long long v = v0 + threadIdx.x;
-        const double* t = rows + threadIdx.x * K;
+        const double* t = rows + threadIdx.x * pitch;
         double tot = 0.0;
         for (int b = 0; b < K; ++b) tot += t[b];
         const double mean = tot / K;
@@ -991,12 +1001,17 @@ hipError_t launch_stats(const double* tally, const uint2* vox, unsigned long lon
                         double conv0, double* dose, double* var, double* dep_sum, hipStream_t s)
 {
     if (K < 2 || K > 64) return hipErrorInvalidValue;
+    const size_t bytes = (size_t)kStatsVox * (K | 1) * sizeof(double);
+    if (bytes > 65536) {
+        const hipError_t e = hipFuncSetAttribute((const void*)stats_kernel,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+    }
     unsigned long long blocks = (nvox + kStatsVox - 1) / kStatsVox;
     if (blocks > 65536) blocks = 65536;
     if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(stats_kernel, dim3((unsigned)blocks), dim3(kStatsVox),
-                       (size_t)kStatsVox * K * sizeof(double), s, tally, vox, nvox, K, conv0, dose, var,
-                       dep_sum);
+    hipLaunchKernelGGL(stats_kernel, dim3((unsigned)blocks), dim3(kStatsVox), bytes, s, tally, vox, nvox, K,
+                       conv0, dose, var, dep_sum);
     return hipGetLastError();
 }
 

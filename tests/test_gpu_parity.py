@@ -346,3 +346,26 @@ def test_geometry_density_matches_hu_calibration(nd, mt):
     with pytest.raises(pmc.PMCError):
         pmc.pmc_geometry_density(e.ctx, 99, torch.empty(hu.shape, dtype=torch.float32, device="cuda"))
     e.close()
+
+
+def test_group_count_leaves_the_dose_unchanged(nd, mt):
+    """K only splits the histories into groups for the variance: the total
+    dose is the same realisation for K = 3, 10 and 64 (FP64 summation order
+    aside), the variance is non-negative and its mean over the dose region
+    agrees between K = 10 and K = 64 within their sampling spread."""
+    _say("case: group counts")
+    cfg = synth.config_ct_spots(150.0, 40_000)
+    res = {}
+    for k in (3, 10, 64):
+        e = _engine(nd, mt, cfg["hu"], k_batches=k)
+        d, v, s = e.run_spots(cfg["spots"], cfg["n_histories"], 4)
+        e.close()
+        res[k] = (d, v, s)
+        assert (v >= 0).all()
+    d10, v10, _ = res[10]
+    for k in (3, 64):
+        np.testing.assert_allclose(res[k][0], d10, rtol=1e-9, atol=1e-12 * d10.max())
+    m = d10 > 0.1 * d10.max()
+    r = res[64][1][m].mean() / v10[m].mean()
+    # the mean of many voxel variances: each has relative spread sqrt(2/(K-1))
+    assert 0.8 < r < 1.25, r
