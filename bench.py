@@ -112,6 +112,8 @@ def bench_plans(args):
                                   "1e6-1e7 histories each, one persistent launch",
                       "histories_per_step": n_tot // args.steps},
            "steps_per_s": steps_tot / elapsed,
+           "launch_shape": {k: all_sums[-1][0][k] for k in ("block_threads", "grid_blocks",
+                                                            "cache_slots", "epoch_steps")},
            "transport_ms_per_step": sum(s[0]["transport_ms"] for s in all_sums) / args.steps,
            "ledger_residual_max": max(abs(s["incident"] - s["deposited"] - s["escaped"] - s["neutral"]
                                           - s["overflow"]) / s["incident"]
