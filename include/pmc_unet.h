@@ -6,8 +6,8 @@
  * part trains and runs a 3-D U-Net that maps a low-history dose (plus the
  * density map) to an estimate of the high-history dose, so that a plan can be
  * evaluated from far fewer histories; plain Monte Carlo remains the fallback
- * and the judge of its error (gamma index, Low et al., as used in the paper's
- * Sec. II.D).  It has no counterpart in the paper.
+ * and the reference for its error (gamma index, Low et al., as used in the
+ * paper's Sec. II.D).  It has no counterpart in the paper.
  *
  * Network: 4 levels (16/32/64/128 channels), one 3x3x3 convolution + leaky
  * ReLU (negative slope 0.01) per level on the way down (2x2x2 average pooling between levels) and one per

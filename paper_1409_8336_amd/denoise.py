@@ -109,9 +109,11 @@ def build_dataset(sim, indices, n_low, n_high, log=_log):
     return {"low": low, "high": high, "rho": rho, "spots": spots, "indices": list(indices)}
 
 
-def train(net, data, rows, seconds, lr_max=1e-3, lr_min=1e-5, seed=0, max_steps=None, log=_log):
-    """Adam on one full volume per step, cosine learning-rate decay over the
-    time budget; returns [(step, elapsed_s, loss)]."""
+def train(net, data, rows, seconds, lr_max=5e-4, lr_min=1e-5, seed=0, max_steps=None, batch=4,
+          log=_log):
+    """Adam on the gradient summed over `batch` full volumes per step (the
+    backward call adds into the gradient buffer), cosine learning-rate decay
+    over the time budget; returns [(step, elapsed_s, mean loss of the step)]."""
     import torch
     rng = np.random.default_rng(seed)
     hist = []
@@ -123,12 +125,14 @@ def train(net, data, rows, seconds, lr_max=1e-3, lr_min=1e-5, seed=0, max_steps=
         el = time.perf_counter() - t0
         if el >= seconds or (max_steps is not None and step >= max_steps):
             break
-        if not order:
-            order = list(rng.permutation(rows))
-        r = order.pop()
         frac = min(1.0, el / seconds)
         lr = lr_min + 0.5 * (lr_max - lr_min) * (1 + math.cos(math.pi * frac))
-        loss = net.backward(data["low"][r], data["rho"][r], data["high"][r])
+        loss = 0.0
+        for _ in range(batch):
+            if not order:
+                order = list(rng.permutation(rows))
+            r = order.pop()
+            loss += net.backward(data["low"][r], data["rho"][r], data["high"][r]) / batch
         net.adam_step(lr)
         step += 1
         hist.append((step, el, loss))
@@ -237,7 +241,8 @@ def main(argv=None):
     ap.add_argument("--n-low", type=int, default=100_000)
     ap.add_argument("--n-high", type=int, default=100_000_000)
     ap.add_argument("--train-seconds", type=float, default=300.0)
-    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr", type=float, default=5e-4)
+    ap.add_argument("--batch", type=int, default=4)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", default=None)
     ap.add_argument("--save-params", default=None)
@@ -250,7 +255,8 @@ def main(argv=None):
     n_train = a.cases - a.held_out
     # one volume [1, d, h, w] per call
     net = unet.UNet((1,) + tuple(data["low"].shape[1:]), seed=a.seed)
-    hist = train(net, data, list(range(n_train)), a.train_seconds, lr_max=a.lr, seed=a.seed)
+    hist = train(net, data, list(range(n_train)), a.train_seconds, lr_max=a.lr, seed=a.seed,
+                 batch=a.batch)
     _log("trained %d steps in %.0f s, final loss(avg 100) %.4e"
          % (len(hist), hist[-1][1], np.mean([h[2] for h in hist[-100:]])))
     if a.save_params:
@@ -259,7 +265,8 @@ def main(argv=None):
     summ = summarize(recs)
     summ.update({"data_s": t_data, "train_steps": len(hist), "train_s": hist[-1][1],
                  "final_loss": float(np.mean([h[2] for h in hist[-100:]])), "n_low": a.n_low,
-                 "n_high": a.n_high, "cases_total": a.cases, "train_cases": n_train})
+                 "n_high": a.n_high, "cases_total": a.cases, "train_cases": n_train, "batch": a.batch,
+                 "lr_max": a.lr})
     _log("summary %s" % json.dumps(summ))
     if a.out:
         with open(a.out, "w") as f:
