@@ -283,6 +283,7 @@ def main():
     achieved = ALG_BYTES_PER_STEP * steps_tot / transport_s
     deposits_tot = sum(s["tally_atomics"] for s in sums)
     atomics_tot = sum(s["global_atomics"] for s in sums)
+    flush_tot = sum(s["cache_flush_atomics"] for s in sums)
     probe_ms = pmc.pmc_atomic_probe(eng.ctx, max(1, atomics_tot // args.steps), stream)
     probe_rate = (atomics_tot / args.steps) / (probe_ms * 1e-3)
     atomic_rate = atomics_tot / transport_s
@@ -330,6 +331,7 @@ def main():
         "atomic_roofline": {
             "deposits_per_step": deposits_tot / args.steps,
             "tally_atomics_per_step": atomics_tot / args.steps,
+            "flush_atomics_per_step": flush_tot / args.steps,
             "achieved_atomics_per_s": atomic_rate,
             "probe_atomics_per_s": probe_rate,
             "frac": atomic_rate / probe_rate,

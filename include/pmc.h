@@ -76,6 +76,9 @@ typedef struct {
                                 tables); -1 = off (every deposit is a global FP64 atomic) */
     int32_t epoch_steps;     /* loop iterations between cache flushes; 0 = 32 */
     int32_t cache_probes;    /* cache slots tried per deposit (linear probing), 1..16; 0 = 4 */
+    int32_t claim_run_log2;  /* a workgroup claims primaries in runs of up to 2^claim_run_log2
+                                consecutive histories (a pencil's worth for the cache), 4..16;
+                                0 = 10 */
 } pmc_params;
 /* Autotuning: when any of block_threads, refill_lanes, batch_events is 0 and
  * a run has at least 2e5 histories, the first run of each workload signature
@@ -149,6 +152,8 @@ typedef struct {
     int32_t grid_blocks;     /* workgroups in the persistent grid, */
     int32_t cache_slots;     /* deposit-cache slots per workgroup (0 = off), */
     int32_t epoch_steps;     /* loop iterations between cache flushes */
+    uint64_t cache_flush_atomics; /* of global_atomics, those the epoch flushes issued (the rest
+                                     are deposits that found no cache slot) */
 } pmc_summary;
 
 typedef struct pmc_ctx pmc_ctx;

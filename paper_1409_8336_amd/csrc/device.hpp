@@ -12,6 +12,12 @@ constexpr int kWave = 64;
 constexpr int kQueuePlanes = 12;   // px py pz ux uy uz E w uid_lo uid_hi batch plan
 constexpr int kMaxPlans = 64;
 constexpr int kMaxGenerations = 64;
+// counters a workgroup accumulates per plan: steps, elastic, non-elastic,
+// short steps, deposits, tally atomics, of which cache-flush atomics; with
+// the ledger (escaped, neutral, overflow: 3 doubles) the per-plan LDS block
+// of a batched launch
+constexpr int kWgCounters = 7;
+constexpr int kPlanLdsBytes = 8 * (3 + kWgCounters);
 
 // LDS blob layout, in 32-bit words
 constexpr int kOffLnrWater = 0;
@@ -45,7 +51,7 @@ struct alignas(8) LdsArgs {
     const float* sec_x;
     const float* sec_mu;
     const float* spots;
-    const unsigned long long* spot_start;
+    const unsigned long long* order;
     const uint32_t* q_in;
     uint32_t* q_out;
     unsigned long long q_cap;
@@ -80,9 +86,14 @@ struct KernelArgs {
     uint32_t flags;
     float f_mcs, s_min;
     // primaries (generation 0): spots[s*8 + {x/dx, y/dy, E, sx/dx, sy/dy, weight,
-    // plan (bits), first index of the spot within its plan (bits)}]
+    // plan (bits), first index of the spot within its plan (bits)}].  They are
+    // worked in batch-major order: all of statistical group 0 of every spot,
+    // then group 1, ...  order[b * (n_spots + 1) + s] is the work index where
+    // group b of spot s starts (entry n_spots: where group b ends), and
+    // order[K * (n_spots + 1) + b * n_spots + s] the history index within its
+    // plan (the random-number stream) of that part's first history
     const float* spots;
-    const unsigned long long* spot_start;   // [n_spots + 1]
+    const unsigned long long* order;
     int n_spots;
     unsigned long long n_primary;
     // secondary queues: plane p of entry i at q[p * q_cap + i]
@@ -93,7 +104,7 @@ struct KernelArgs {
     int gen;
     // outputs, per plan
     double* ledger;                 // [plan][4]: escaped, neutral, overflow, deposited
-    unsigned long long* counters;   // [plan][8]: steps, elastic, non-elastic, short steps, tally atomics
+    unsigned long long* counters;   // [plan][8]: the kWgCounters counters above
     int refill_lanes;
     int batch_events;
     // workgroup deposit cache in LDS: cache_slots sums (double) then as many

@@ -111,7 +111,7 @@ struct pmc_ctx {
     // run buffers
     DevBuf<double> d_dose, d_var, d_ledger;
     DevBuf<uint32_t> d_q[2];
-    DevBuf<unsigned long long> d_gc, d_counters, d_spot_start, d_wgc;
+    DevBuf<unsigned long long> d_gc, d_counters, d_order, d_wgc;
     DevBuf<float> d_spots;
     DevBuf<PlanDesc> d_plans;
     unsigned long long* h_pinned = nullptr;   // pinned read-back area
@@ -207,6 +207,8 @@ bool params_ok(const pmc_params& p, std::string& why)
     { why = "tally_cache must be -1, 0 or in [512, 16384]"; return false; }
     if (p.epoch_steps < 0 || p.epoch_steps > 4096) { why = "epoch_steps must be in [0, 4096]"; return false; }
     if (p.cache_probes < 0 || p.cache_probes > 16) { why = "cache_probes must be in [0, 16]"; return false; }
+    if (p.claim_run_log2 != 0 && (p.claim_run_log2 < 4 || p.claim_run_log2 > 16))
+    { why = "claim_run_log2 must be 0 or in [4, 16]"; return false; }
     return true;
 }
 
@@ -348,7 +350,7 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
     // spots of every plan, flattened, each tagged with its plan and its first
     // history index within the plan
     std::vector<float> sp;
-    std::vector<unsigned long long> start(1, 0);
+    std::vector<unsigned long long> start(1, 0), first;
     std::vector<double> incident(np, 0.0), wtot(np, 0.0);
     unsigned long long total = 0;
     for (int p = 0; p < np; ++p) {
@@ -368,6 +370,7 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
                                   u2f((uint32_t)p), u2f((uint32_t)local)};
             sp.insert(sp.end(), rec, rec + 8);
             start.push_back(start.back() + ns[s2]);
+            first.push_back(local);
             local += ns[s2];
             incident[p] += (double)ns[s2] * (double)omf * (double)q.e_mev;
             wtot[p] += (double)ns[s2] * (double)omf;
@@ -376,6 +379,30 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
     }
     const int n_spots = (int)start.size() - 1;
     if (sp.empty()) sp.assign(8, 0.f);
+    // batch-major work order of the primaries (Sec. II.B.2 groups): statistical
+    // group b of a spot with n histories holds its histories at positions
+    // [ceil(b n / K), ceil((b + 1) n / K)); the primaries are worked group by
+    // group, so that a workgroup's run of consecutive work indices stays in
+    // one group (one tally column) while it moves across neighbouring spots.
+    // The history index (random-number stream) and the group of every
+    // primary are those of the spot-major numbering.
+    const size_t ns1 = (size_t)n_spots + 1;
+    std::vector<unsigned long long> order((size_t)K * ns1 + (size_t)K * n_spots + 1, 0ull);
+    {
+        unsigned long long at = 0;
+        for (int b = 0; b < K; ++b) {
+            for (int s2 = 0; s2 < n_spots; ++s2) {
+                const unsigned long long n = start[s2 + 1] - start[s2];
+                const unsigned long long p0 = ((unsigned long long)b * n + K - 1) / K;
+                const unsigned long long p1 = ((unsigned long long)(b + 1) * n + K - 1) / K;
+                order[b * ns1 + s2] = at;
+                order[(size_t)K * ns1 + (size_t)b * n_spots + s2] = first[s2] + p0;
+                at += p1 - p0;
+            }
+            order[b * ns1 + n_spots] = at;
+        }
+        if (at != total) return fail(c, PMC_ERR_ARG, "internal: work order does not cover the histories");
+    }
     HIPCHK(hipSetDevice(c->device), "set device");
     const unsigned long long cap = c->p.queue_capacity ? c->p.queue_capacity
                                                        : std::max<unsigned long long>(65536ull, total);
@@ -398,10 +425,10 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
     HIPCHK(c->d_counters.ensure(8 * np), "alloc counters");
     HIPCHK(c->d_ledger.ensure(4 * np), "alloc ledger");
     HIPCHK(c->d_spots.ensure(sp.size()), "alloc spots");
-    HIPCHK(c->d_spot_start.ensure(start.size()), "alloc spots");
+    HIPCHK(c->d_order.ensure(order.size()), "alloc spots");
     HIPCHK(c->d_plans.ensure(np), "alloc plans");
     HIPCHK(hipMemcpyAsync(c->d_spots.p, sp.data(), sp.size() * 4, hipMemcpyHostToDevice, st), "upload spots");
-    HIPCHK(hipMemcpyAsync(c->d_spot_start.p, start.data(), start.size() * 8, hipMemcpyHostToDevice, st), "upload spots");
+    HIPCHK(hipMemcpyAsync(c->d_order.p, order.data(), order.size() * 8, hipMemcpyHostToDevice, st), "upload spots");
     HIPCHK(hipMemcpyAsync(c->d_plans.p, pd.data(), np * sizeof(PlanDesc), hipMemcpyHostToDevice, st), "upload plans");
     HIPCHK(hipEventRecord(c->ev0, st), "event");
     for (int p = 0; p < np; ++p) HIPCHK(launch_zero(pd[p].tally, plans[p].g->nvox() * K * 8, st), "zero tally");
@@ -428,7 +455,7 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
     a.f_mcs = (float)c->p.f_mcs;
     a.s_min = (float)c->p.s_min_cm;
     a.spots = c->d_spots.p;
-    a.spot_start = c->d_spot_start.p;
+    a.order = c->d_order.p;
     a.n_spots = n_spots;
     a.n_primary = total;
     a.q_cap = cap;
@@ -453,7 +480,7 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
         if (slots == 0) {
             const long wgs = std::max(1, 1024 / block);
             const long avail = 163840L / wgs - (long)lds_words * 4 - 16 - (long)sizeof(LdsArgs) -
-                               (multi ? 72L * np : 0L) - 16;
+                               (multi ? (long)kPlanLdsBytes * np : 0L) - 16;
             slots = (int)std::min(16384L, avail / (4L * (2 + key_words)));
             if (slots < 512) slots = 0;
         }
@@ -464,8 +491,8 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
     a.cache_probes = c->p.cache_probes ? c->p.cache_probes : 4;
     const size_t used = slots ? (size_t)a.cache_off + (size_t)(2 + key_words) * slots + 1 : lds_words;
     a.args_off = (int)((used + 1) & ~(size_t)1);
-    // batched launches: per-plan ledger (3 doubles) and counters (6 u64) after the arguments
-    const size_t lds = (size_t)a.args_off * 4 + sizeof(LdsArgs) + (multi ? 72 * (size_t)np : 0);
+    // batched launches: per-plan ledger and counters after the arguments
+    const size_t lds = (size_t)a.args_off * 4 + sizeof(LdsArgs) + (multi ? kPlanLdsBytes * (size_t)np : 0);
     int max_block = 0;
     HIPCHK(transport_max_block(multi, &max_block), "kernel attributes");
     if (block > max_block) return fail(c, PMC_ERR_ARG, "block_threads exceeds the transport kernel's limit");
@@ -492,9 +519,9 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
             if (g0 >= kMaxGenerations) return fail(c, PMC_ERR_DEVICE, "secondary generations exceed limit");
             for (int gidx = g0; gidx < g1; ++gidx) {
                 a.gen = gidx;
-                // primaries in runs of 1024 consecutive histories (one spot's
-                // worth, for the deposit cache), secondaries in runs of 64
-                a.claim_log2 = gidx == 0 ? 10 : 6;
+                // primaries in runs of up to 1024 consecutive histories (a
+                // pencil's worth, for the deposit cache), secondaries in runs of 64
+                a.claim_log2 = gidx == 0 ? (c->p.claim_run_log2 ? c->p.claim_run_log2 : 10) : 6;
                 a.q_in = c->d_q[gidx & 1].p;
                 a.q_out = c->d_q[(gidx + 1) & 1].p;
                 HIPCHK(hipEventRecord(c->ev_gen[2 * gidx], st), "event");
@@ -565,6 +592,7 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
             sm->n_short_steps = cnt[8 * p + 3];
             sm->tally_atomics = cnt[8 * p + 4];
             sm->global_atomics = cnt[8 * p + 5];
+            sm->cache_flush_atomics = cnt[8 * p + 6];
             sm->block_threads = block;
             sm->grid_blocks = grid;
             sm->cache_slots = slots;

@@ -21,6 +21,16 @@
 namespace pmc {
 
 #define DEV __device__ __forceinline__
+// Pointers the kernel reads from LDS (a batch's plan table, the staged
+// arguments) are generic to the compiler; casting them to the global address
+// space gives global instead of flat memory instructions, which do not make
+// the wave wait for its LDS operations as well.
+#define GLOBAL __attribute__((address_space(1)))
+template <typename T>
+DEV GLOBAL T* gbl(T* p)
+{
+    return (GLOBAL T*)p;
+}
 
 constexpr float kMp = 938.272088f;
 constexpr float kECut = 0.1f;
@@ -29,7 +39,6 @@ constexpr float kInvH = 999.0f / 7.824046011f;    // 1 / (ln(2500)/999)
 constexpr float kH = 7.824046011f / 999.0f;
 constexpr float kStraggleK = 0.156914976f;        // K m_e c^2, MeV^2 cm^2 / g
 constexpr float kInf = 3.0e38f;
-constexpr int kWgCounters = 6;   // steps, elastic, non-elastic, short steps, deposits, tally atomics
 constexpr uint32_t kMaxSteps = 1u << 20;
 constexpr uint32_t kNoStraggle = 1u, kNoMcs = 2u, kNoNuclear = 4u;
 
@@ -41,6 +50,42 @@ DEV float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 DEV float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 DEV float fsin_rev(float r) { return __builtin_amdgcn_sinf(r); }   // sin(2 pi r)
 DEV float fcos_rev(float r) { return __builtin_amdgcn_cosf(r); }   // cos(2 pi r)
+
+// Inverse error function for |x| < 1 in the two-region form of Giles (2010,
+// "Approximating the erfinv function"): with w = -ln(1 - x^2), erfinv(x) / x
+// is a degree-8 polynomial in w - 2.5 for w < 5 and in sqrt(w) - 3 beyond.
+// The coefficients are this project's least-squares fits in relative error
+// (csrc/erfinv_fit.py); evaluated in FP32 the result stays within 5e-7 of
+// erfinv(x) for every x = 2u - 1 that u01 can produce (4e-7 measured).
+DEV float inv_erf(float x)
+{
+    const float w = -fln((1.f - x) * (1.f + x));
+    float p;
+    if (w < 5.f) {
+        const float t = w - 2.5f;
+        p = 2.771113862e-08f;
+        p = fmaf(p, t, 3.502618917e-07f);
+        p = fmaf(p, t, -3.515215773e-06f);
+        p = fmaf(p, t, -4.458842729e-06f);
+        p = fmaf(p, t, 2.185349323e-04f);
+        p = fmaf(p, t, -1.253544576e-03f);
+        p = fmaf(p, t, -4.177604915e-03f);
+        p = fmaf(p, t, 2.466406246e-01f);
+        p = fmaf(p, t, 1.501409398e+00f);
+    } else {
+        const float t = fsqrt(w) - 3.f;
+        p = -1.968507892e-04f;
+        p = fmaf(p, t, 8.508432244e-05f);
+        p = fmaf(p, t, 1.354683624e-03f);
+        p = fmaf(p, t, -3.657624243e-03f);
+        p = fmaf(p, t, 5.733725080e-03f);
+        p = fmaf(p, t, -7.627108717e-03f);
+        p = fmaf(p, t, 9.440027455e-03f);
+        p = fmaf(p, t, 1.001674451e+00f);
+        p = fmaf(p, t, 2.832976890e+00f);
+    }
+    return p * x;
+}
 
 // Philox4x32-10 (Salmon et al. 2011); key = run seed, counter = (uid, k, tag)
 template <bool kScalarKey = false>
@@ -83,24 +128,21 @@ DEV unsigned long long bcast0(unsigned long long v)
     return ((unsigned long long)hi << 32) | lo;
 }
 
-// rotate direction by polar cos/sin and azimuth phi (revolutions)
+// rotate direction by polar cos/sin and azimuth phi (revolutions); a
+// direction along the z axis (every primary's first step) takes the frame of
+// the axes, without a branch
 DEV void rotate(float& ux, float& uy, float& uz, float ct, float st, float phi)
 {
     const float cp = fcos_rev(phi), sp = fsin_rev(phi);
     const float perp = fsqrt(ux * ux + uy * uy);
-    if (perp < 1.0e-6f) {
-        ux = st * cp;
-        uy = st * sp;
-        uz = uz >= 0.f ? ct : -ct;
-        return;
-    }
-    const float ip = frcp(perp);
+    const bool axial = perp < 1.0e-6f;
+    const float ip = frcp(axial ? 1.f : perp);
     const float nx = ux * ct + st * (ux * uz * cp - uy * sp) * ip;
     const float ny = uy * ct + st * (uy * uz * cp + ux * sp) * ip;
     const float nz = uz * ct - st * cp * perp;
-    ux = nx;
-    uy = ny;
-    uz = nz;
+    ux = axial ? st * cp : nx;
+    uy = axial ? st * sp : ny;
+    uz = axial ? (uz >= 0.f ? ct : -ct) : nz;
 }
 
 // voxel containing p (voxel units); on a face, the voxel being entered
@@ -125,7 +167,7 @@ DEV void grid_pos(float e, int& i, float& t)
     t = f;
 }
 
-DEV float inv_cdf33(const float* __restrict__ cdf, float u, float lo, float hi)
+DEV float inv_cdf33(const GLOBAL float* __restrict__ cdf, float u, float lo, float hi)
 {
     int l = 0, h = 32;
     while (h - l > 1) {
@@ -225,7 +267,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
         L->sec_x = a.sec_x;
         L->sec_mu = a.sec_mu;
         L->spots = a.spots;
-        L->spot_start = a.spot_start;
+        L->order = a.order;
         L->q_in = a.q_in;
         L->q_out = a.q_out;
         L->q_cap = a.q_cap;
@@ -274,7 +316,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
 
     // per-lane ledger and counters of the lane's current plan
     double acc_esc = 0.0, acc_neu = 0.0, acc_ovf = 0.0;
-    uint32_t n_steps = 0, n_el = 0, n_ne = 0, n_short = 0, n_dep = 0, n_glob = 0;
+    uint32_t n_steps = 0, n_el = 0, n_ne = 0, n_short = 0, n_dep = 0, n_glob = 0, n_flush = 0;
     auto flush = [&](uint32_t pl) {
         if constexpr (kMulti) {
             double* LG = wg_led + 3 * pl;
@@ -288,8 +330,9 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
             if (n_short) atomicAdd(&C[3], (unsigned long long)n_short);
             if (n_dep) atomicAdd(&C[4], (unsigned long long)n_dep);
             if (n_glob) atomicAdd(&C[5], (unsigned long long)n_glob);
+            if (n_flush) atomicAdd(&C[6], (unsigned long long)n_flush);
             acc_esc = acc_neu = acc_ovf = 0.0;
-            n_steps = n_el = n_ne = n_short = n_dep = n_glob = 0;
+            n_steps = n_el = n_ne = n_short = n_dep = n_glob = n_flush = 0;
             return;
         }
         double* LG = L->ledger + 4 * pl;
@@ -303,8 +346,9 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
         if (n_short) atomicAdd(&C[3], (unsigned long long)n_short);
         if (n_dep) atomicAdd(&C[4], (unsigned long long)n_dep);
         if (n_glob) atomicAdd(&C[5], (unsigned long long)n_glob);
+        if (n_flush) atomicAdd(&C[6], (unsigned long long)n_flush);
         acc_esc = acc_neu = acc_ovf = 0.0;
-        n_steps = n_el = n_ne = n_short = n_dep = n_glob = 0;
+        n_steps = n_el = n_ne = n_short = n_dep = n_glob = n_flush = 0;
     };
     // one deposit into tally element idx of the current plan: through the
     // workgroup's LDS cache when the slot is free or already holds idx,
@@ -333,7 +377,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                 slot = slot + 1u == (uint32_t)n_slots ? 0u : slot + 1u;
             }
         }
-        unsafeAtomicAdd(&P.tally(plan)[idx], v);
+        __hip_atomic_fetch_add(gbl(P.tally(plan)) + idx, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         ++n_glob;
     };
     bool exhausted = false;
@@ -353,24 +397,35 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                 const unsigned long long idx = claim_index(base + (unsigned long long)mbcnt(idle));
                 if (idx < limit) {
                     if (gen == 0) {
-                        // source: Gaussian spot on the z = 0 face (K1 role)
+                        // source: Gaussian spot on the z = 0 face (K1 role).
+                        // Work index -> statistical group b, then spot s within
+                        // the group's part of the list, then the history.
+                        const int ns1 = L->n_spots + 1;
+                        const GLOBAL unsigned long long* ord = gbl(L->order);
+                        int bg = 0;
+                        {
+                            int hi = K;
+                            while (hi - bg > 1) {
+                                const int mid = (bg + hi) >> 1;
+                                if (ord[mid * ns1] <= idx) bg = mid;
+                                else hi = mid;
+                            }
+                        }
+                        const GLOBAL unsigned long long* row = ord + bg * ns1;
                         int lo = 0, hi = L->n_spots;
                         while (hi - lo > 1) {
                             const int mid = (lo + hi) >> 1;
-                            if (L->spot_start[mid] <= idx) lo = mid;
+                            if (row[mid] <= idx) lo = mid;
                             else hi = mid;
                         }
-                        const float* sp = L->spots + 8 * lo;
-                        const unsigned long long s0 = L->spot_start[lo], s1 = L->spot_start[lo + 1];
-                        unsigned long long uid = idx;
+                        const GLOBAL float* sp = gbl(L->spots) + 8 * lo;
+                        const unsigned long long uid = ord[K * ns1 + bg * L->n_spots + lo] + (idx - row[lo]);
                         if constexpr (kMulti) {
-                            // uid within the plan: the spot's first index in its plan
                             const uint32_t np = __float_as_uint(sp[6]);
                             if (np != plan) {
                                 flush(plan);
                                 plan = np;
                             }
-                            uid = (unsigned long long)__float_as_uint(sp[7]) + (idx - s0);
                         }
                         uid_lo = (uint32_t)uid;
                         uid_hi = (uint32_t)(uid >> 32);
@@ -386,9 +441,9 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                         E = sp[2];
                         w = sp[5];
                         mfp = -fln(u01(r.z));
-                        batch = (uint32_t)(((idx - s0) * (unsigned long long)K) / (s1 - s0));
+                        batch = (uint32_t)bg;
                     } else {
-                        const uint32_t* q = L->q_in + idx;
+                        const GLOBAL uint32_t* q = gbl(L->q_in) + idx;
                         const unsigned long long c = L->q_cap;
                         px = __uint_as_float(q[0]);
                         py = __uint_as_float(q[c]);
@@ -431,9 +486,37 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
         bool stepped = false, short_step = false;
         if (alive && !pend) {
             const unsigned long long vi = ((unsigned long long)vz * P.ny(plan) + vy) * P.nx(plan) + vx;
-            const uint2 rec = P.vox(plan)[vi];
-            const float rho = __uint_as_float(rec.x);
-            const int m = (int)rec.y;
+            const unsigned long long rec = gbl(reinterpret_cast<const unsigned long long*>(P.vox(plan)))[vi];
+            // what does not depend on the voxel record is computed while its
+            // gather is in flight: the step's random numbers, the energy's
+            // grid position and the distance to the voxel boundary
+            const uint4 r = philox<!kMulti>(uid_lo, uid_hi, k, 1u, P.key_lo(plan), P.key_hi(plan));
+            int gi;
+            float gt;
+            grid_pos(E, gi, gt);
+            float d = kInf;
+            int axis = 2;
+            {
+                // (evaluated for every axis; one with no direction component
+                // is then excluded by the selects)
+                const float tx = ((float)(ux > 0.f ? vx + 1 : vx) - px) * P.vs(plan, 0) * frcp(ux);
+                const float ty = ((float)(uy > 0.f ? vy + 1 : vy) - py) * P.vs(plan, 1) * frcp(uy);
+                const float tz = ((float)(uz > 0.f ? vz + 1 : vz) - pz) * P.vs(plan, 2) * frcp(uz);
+                const float dx = ux != 0.f ? tx : kInf;
+                const float dy = uy != 0.f ? ty : kInf;
+                const float dz = uz != 0.f ? tz : kInf;
+                d = dx;
+                axis = 0;
+                if (dy < d) { d = dy; axis = 1; }
+                if (dz < d) { d = dz; axis = 2; }
+            }
+            // an empty asm that takes the record only after those values
+            // exist: it keeps the compiler from moving their arithmetic behind
+            // the wait for the gather
+            uint32_t rec_x = (uint32_t)rec, rec_y = (uint32_t)(rec >> 32);
+            asm volatile("" : "+v"(rec_x), "+v"(rec_y) : "v"(r.x), "v"(r.y), "v"(r.z), "v"(r.w), "v"(d), "v"(gt));
+            const float rho = __uint_as_float(rec_x);
+            const int m = (int)rec_y;
             const float mf = mc[4 * m + 0];
             const float mx0 = mc[4 * m + 1];
             const float mza = mc[4 * m + 2];
@@ -445,12 +528,8 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
             const float ln_r1 = own ? a.ln_r1[1] : a.ln_r1[0];
             const float inv_step = own ? a.inv_step[1] : a.inv_step[0];
 
-            int gi;
-            float gt;
-            grid_pos(E, gi, gt);
-            float range;
-            if (gi == 0) range = gt * r_first;
-            else range = fexp(lnr[gi] + gt * (lnr[gi + 1] - lnr[gi]));
+            const float range_tab = fexp(lnr[gi] + gt * (lnr[gi + 1] - lnr[gi]));
+            const float range = gi == 0 ? gt * r_first : range_tab;
             const float s_range = range * frcp(scale);
             float sigma = 0.f;
             if (!(flags & kNoNuclear)) {
@@ -458,122 +537,106 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                 sigma = rho * (sm[gi] + gt * (sm[gi + 1] - sm[gi]));
             }
             const float s_nuc = sigma > 0.f ? mfp * frcp(sigma) : kInf;
-            // distance to the voxel boundary
-            float d = kInf;
-            int axis = 2;
-            {
-                float da;
-                if (ux != 0.f) {
-                    da = ((float)(ux > 0.f ? vx + 1 : vx) - px) * P.vs(plan, 0) * frcp(ux);
-                    if (da < d) { d = da; axis = 0; }
-                }
-                if (uy != 0.f) {
-                    da = ((float)(uy > 0.f ? vy + 1 : vy) - py) * P.vs(plan, 1) * frcp(uy);
-                    if (da < d) { d = da; axis = 1; }
-                }
-                if (uz != 0.f) {
-                    da = ((float)(uz > 0.f ? vz + 1 : vz) - pz) * P.vs(plan, 2) * frcp(uz);
-                    if (da < d) { d = da; axis = 2; }
-                }
-            }
             bool stop_here = (s_range <= d && s_range <= s_nuc);
             const bool nuc = s_nuc < d;
             float s = nuc ? s_nuc : d;
             short_step = s < a.s_min;
             s = short_step ? a.s_min : s;
-            if (s >= s_range) stop_here = true;
+            stop_here = stop_here || s >= s_range;
+            // The step is evaluated also when the range ends it (the proton
+            // then deposits all of E here and its new state is discarded):
+            // one path without branches around it.
+            // mean loss from the range table (Eq. 2 water-equivalent path)
+            const float r1 = range - s * scale;
+            float e1;
+            {
+                const float lr = fln(fmaxf(r1, r_first));
+                int c = (int)((lr - ln_r1) * inv_step);
+                c = c < 0 ? 0 : (c > 1023 ? 1023 : c);
+                int j = inv[c];
+                j += (j < 998 && lnr[j + 1] <= lr);
+                j += (j < 998 && lnr[j + 1] <= lr);
+                while (j < 998 && lnr[j + 1] <= lr) ++j;
+                const float tt = (lr - lnr[j]) * frcp(lnr[j + 1] - lnr[j]);
+                const float e_tab = fexp(kLnE0 + ((float)j + tt) * kH);
+                const float e_low = fexp(kLnE0 + (r1 > 0.f ? r1 : 0.f) * frcp(r_first) * kH);
+                e1 = r1 <= r_first ? e_low : e_tab;
+            }
+            float de_mean = E - e1;
+            de_mean = de_mean > 0.f ? de_mean : 0.f;
+            const float emid = E - 0.5f * de_mean;
+            const float e_tot = emid + kMp;
+            const float ie_tot = frcp(e_tot);
+            const float pv = emid * (emid + 2.f * kMp) * ie_tot;      // p beta c
+            const float b2 = pv * ie_tot;
+            float de = de_mean;
+            if (!(flags & kNoStraggle)) {
+                const float g = e_tot * (1.0f / kMp);
+                const float var = kStraggleK * rho * mza * s * g * g * (1.f - 0.5f * b2);
+                const float z = 1.414213562f * inv_erf(2.f * u01(r.w) - 1.f);
+                de = de_mean + fsqrt(var) * z;
+                de = de < 0.f ? 0.f : (de > E ? E : de);
+            }
+            float theta = 0.f;
+            if (!(flags & kNoMcs)) {
+                const float x0 = mx0 * frcp(rho);
+                float br = 1.f + 0.038f * fln(s * frcp(x0 * b2));
+                br = br > 0.f ? br : 0.f;
+                const float th0 = a.f_mcs * 13.6f * frcp(pv) * fsqrt(s * frcp(x0)) * br;
+                theta = th0 * fsqrt(-2.f * fln(u01(r.y)));
+            }
+            // random hinge at a uniform fraction of the step; on a
+            // boundary-limited step the second segment runs along the new
+            // direction to the crossed face plane and ends on it
+            const float h1 = u01(r.x) * s;
+            float h2 = s - h1;
+            px += h1 * ux * P.ivs(plan, 0);
+            py += h1 * uy * P.ivs(plan, 1);
+            pz += h1 * uz * P.ivs(plan, 2);
+            const float da_before = axis == 0 ? ux : (axis == 1 ? uy : uz);
+            const int va = axis == 0 ? vx : (axis == 1 ? vy : vz);
+            const float face = (float)(da_before > 0.f ? va + 1 : va);
+            {
+                // theta = 0 (no scattering) leaves the direction as it is
+                const float tr = theta * 0.159154943f;
+                float nx = ux, ny = uy, nz = uz;
+                rotate(nx, ny, nz, fcos_rev(tr), fsin_rev(tr), u01(r.z));
+                const bool turn = theta != 0.f;
+                ux = turn ? nx : ux;
+                uy = turn ? ny : uy;
+                uz = turn ? nz : uz;
+            }
+            const float da = axis == 0 ? ux : (axis == 1 ? uy : uz);
+            const float pa = axis == 0 ? px : (axis == 1 ? py : pz);
+            const float vsa = axis == 0 ? P.vs(plan, 0) : (axis == 1 ? P.vs(plan, 1) : P.vs(plan, 2));
+            const float l2 = (face - pa) * vsa * frcp(da);
+            const bool on_face = !nuc && da * da_before > 0.f && l2 >= 0.f && l2 <= 2.f * h2;
+            h2 = on_face ? l2 : h2;
+            px += h2 * ux * P.ivs(plan, 0);
+            py += h2 * uy * P.ivs(plan, 1);
+            pz += h2 * uz * P.ivs(plan, 2);
+            px = on_face && axis == 0 ? face : px;
+            py = on_face && axis == 1 ? face : py;
+            pz = on_face && axis == 2 ? face : pz;
+            const float e_new = E - de;
+            // range-limited: the proton stops in this voxel with all of E
+            deposit(vi * K + batch,
+                    stop_here ? (double)w * (double)E : (double)w * ((double)E - (double)e_new));
             if (stop_here) {
-                // range-limited: the proton stops in this voxel
-                deposit(vi * K + batch, (double)w * (double)E);
                 alive = false;
             } else {
-                // mean loss from the range table (Eq. 2 water-equivalent path)
-                const float r1 = range - s * scale;
-                float e1;
-                if (r1 <= r_first) {
-                    e1 = fexp(kLnE0 + (r1 > 0.f ? r1 : 0.f) * frcp(r_first) * kH);
-                } else {
-                    const float lr = fln(r1);
-                    int c = (int)((lr - ln_r1) * inv_step);
-                    c = c < 0 ? 0 : (c > 1023 ? 1023 : c);
-                    int j = inv[c];
-                    while (j < 998 && lnr[j + 1] <= lr) ++j;
-                    const float tt = (lr - lnr[j]) / (lnr[j + 1] - lnr[j]);
-                    e1 = fexp(kLnE0 + ((float)j + tt) * kH);
-                }
-                float de_mean = E - e1;
-                de_mean = de_mean > 0.f ? de_mean : 0.f;
-                const float emid = E - 0.5f * de_mean;
-                const uint4 r = philox<!kMulti>(uid_lo, uid_hi, k, 1u, P.key_lo(plan), P.key_hi(plan));
-                const float e_tot = emid + kMp;
-                const float ie_tot = frcp(e_tot);
-                const float pv = emid * (emid + 2.f * kMp) * ie_tot;      // p beta c
-                const float b2 = pv * ie_tot;
-                float de = de_mean;
-                if (!(flags & kNoStraggle)) {
-                    const float g = e_tot * (1.0f / kMp);
-                    const float var = kStraggleK * rho * mza * s * g * g * (1.f - 0.5f * b2);
-                    const float z = 1.414213562f * erfinvf(2.f * u01(r.w) - 1.f);
-                    de = de_mean + fsqrt(var) * z;
-                    de = de < 0.f ? 0.f : (de > E ? E : de);
-                }
-                float theta = 0.f;
-                if (!(flags & kNoMcs)) {
-                    const float x0 = mx0 * frcp(rho);
-                    float br = 1.f + 0.038f * fln(s * frcp(x0 * b2));
-                    br = br > 0.f ? br : 0.f;
-                    const float th0 = a.f_mcs * 13.6f * frcp(pv) * fsqrt(s * frcp(x0)) * br;
-                    theta = th0 * fsqrt(-2.f * fln(u01(r.y)));
-                }
-                // random hinge at a uniform fraction of the step; on a
-                // boundary-limited step the second segment runs along the new
-                // direction to the crossed face plane and ends on it
-                const float h1 = u01(r.x) * s;
-                float h2 = s - h1;
-                px += h1 * ux * P.ivs(plan, 0);
-                py += h1 * uy * P.ivs(plan, 1);
-                pz += h1 * uz * P.ivs(plan, 2);
-                const float da_before = axis == 0 ? ux : (axis == 1 ? uy : uz);
-                const int va = axis == 0 ? vx : (axis == 1 ? vy : vz);
-                const float face = (float)(da_before > 0.f ? va + 1 : va);
-                if (theta != 0.f) {
-                    const float tr = theta * 0.159154943f;
-                    rotate(ux, uy, uz, fcos_rev(tr), fsin_rev(tr), u01(r.z));
-                }
-                bool on_face = false;
-                if (!nuc) {
-                    const float da = axis == 0 ? ux : (axis == 1 ? uy : uz);
-                    const float pa = axis == 0 ? px : (axis == 1 ? py : pz);
-                    if (da * da_before > 0.f) {
-                        const float vsa = axis == 0 ? P.vs(plan, 0) : (axis == 1 ? P.vs(plan, 1) : P.vs(plan, 2));
-                        const float l2 = (face - pa) * vsa / da;
-                        if (l2 >= 0.f && l2 <= 2.f * h2) {
-                            h2 = l2;
-                            on_face = true;
-                        }
-                    }
-                }
-                px += h2 * ux * P.ivs(plan, 0);
-                py += h2 * uy * P.ivs(plan, 1);
-                pz += h2 * uz * P.ivs(plan, 2);
-                if (on_face) {
-                    if (axis == 0) px = face;
-                    else if (axis == 1) py = face;
-                    else pz = face;
-                }
-                const float e_new = E - de;
-                deposit(vi * K + batch, (double)w * ((double)E - (double)e_new));
                 mfp = nuc ? 0.f : fmaxf(mfp - sigma * s, 0.f);
                 E = e_new;
                 ++k;
                 stepped = true;
+                const bool inside = locate_axis(px, ux, P.nx(plan), vx) & locate_axis(py, uy, P.ny(plan), vy) &
+                                    locate_axis(pz, uz, P.nz(plan), vz);
                 if (E <= kECut || k >= kMaxSteps) {
                     // below the cut-off (or past the step cap that guards
                     // against non-terminating histories): deposit the rest
                     deposit(vi * K + batch, (double)w * (double)E);
                     alive = false;
-                } else if (!(locate_axis(px, ux, P.nx(plan), vx) && locate_axis(py, uy, P.ny(plan), vy) &&
-                             locate_axis(pz, uz, P.nz(plan), vz))) {
+                } else if (!inside) {
                     acc_esc += (double)w * (double)E;
                     alive = false;
                 } else if (nuc) {
@@ -606,8 +669,8 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
         if (pend) {
             pend = false;
             const unsigned long long vi = ((unsigned long long)vz * P.ny(plan) + vy) * P.nx(plan) + vx;
-            const uint2 rec = P.vox(plan)[vi];
-            const int m = (int)rec.y;
+            const unsigned long long rec = gbl(reinterpret_cast<const unsigned long long*>(P.vox(plan)))[vi];
+            const int m = (int)(uint32_t)(rec >> 32);
             const float T = E;
             int gi;
             float gt;
@@ -617,9 +680,9 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
             float s_el = 0.f, s_ne = 0.f;
 #pragma unroll
             for (int e = 0; e < 7; ++e) {
-                const float npg = L->mat_npg[7 * m + e];
-                const float* te = L->el_sig + e * 1000;
-                const float* tn = L->el_sig + (7 + e) * 1000;
+                const float npg = gbl(L->mat_npg)[7 * m + e];
+                const GLOBAL float* te = gbl(L->el_sig) + e * 1000;
+                const GLOBAL float* tn = gbl(L->el_sig) + (7 + e) * 1000;
                 pe[e] = npg > 0.f ? npg * (te[gi] + gt * (te[gi + 1] - te[gi])) : 0.f;
                 pn[e] = npg > 0.f ? npg * (tn[gi] + gt * (tn[gi + 1] - tn[gi])) : 0.f;
                 s_el += pe[e];
@@ -643,7 +706,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                     }
                 }
                 const uint4 r4 = philox<!kMulti>(uid_lo, uid_hi, ks, 4u, P.key_lo(plan), P.key_hi(plan));
-                const float* ec = L->elem + 8 * el;
+                const GLOBAL float* ec = gbl(L->elem) + 8 * el;
                 ev_el = elastic;
                 ev_ne = !elastic;
                 if (elastic) {
@@ -714,12 +777,12 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                     j = j > 24 ? 24 : j;
                     const int row = nu * 25 + j;
                     sec_row = row;
-                    const float* mc5 = L->sec_mult + 5 * row;
+                    const GLOBAL float* mc5 = gbl(L->sec_mult) + 5 * row;
                     const float um = u01(r4.x);
                     int n = 0;
                     while (n < 4 && !(um < mc5[n])) ++n;
-                    const float fl = L->sec_floc[row];
-                    const float* xr = L->sec_x + 33 * row;
+                    const float fl = gbl(L->sec_floc)[row];
+                    const GLOBAL float* xr = gbl(L->sec_x) + 33 * row;
                     float sum = 0.f;
 #pragma unroll
                     for (int c = 0; c < 4; ++c) {
@@ -779,7 +842,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                         const uint32_t jj = recoil ? 0u : (uint32_t)(c + 1);
                         if (!recoil) {
                             const uint4 rc = philox<!kMulti>(uid_lo, uid_hi, ks, 16u + jj, P.key_lo(plan), P.key_hi(plan));
-                            const float mu = inv_cdf33(L->sec_mu + 33 * sec_row, u01(rc.y), -1.f, 1.f);
+                            const float mu = inv_cdf33(gbl(L->sec_mu) + 33 * sec_row, u01(rc.y), -1.f, 1.f);
                             dx = odx;
                             dy = ody;
                             dz = odz;
@@ -788,7 +851,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                         const uint4 cu = philox<!kMulti>(uid_lo, uid_hi, ks, 0xC0000000u | jj, P.key_lo(plan),
                                                 P.key_hi(plan));
                         if (slot < cap) {
-                            uint32_t* q = L->q_out + slot;
+                            GLOBAL uint32_t* q = gbl(L->q_out) + slot;
                             q[0] = __float_as_uint(ox);
                             q[cap] = __float_as_uint(oy);
                             q[2 * cap] = __float_as_uint(oz);
@@ -820,9 +883,12 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
     for (int i = threadIdx.x; i < n_slots; i += blockDim.x) {
         const Key key = ckey[i];
         if (key != kEmptySlot) {
-            if constexpr (kMulti) unsafeAtomicAdd(&P.tally((uint32_t)(key >> 32))[(uint32_t)key], cval[i]);
+            if constexpr (kMulti)
+                __hip_atomic_fetch_add(gbl(P.tally((uint32_t)(key >> 32))) + (uint32_t)key, cval[i], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
             else unsafeAtomicAdd(&a.single.tally[key], cval[i]);
             ++n_glob;
+            ++n_flush;
             ckey[i] = kEmptySlot;
             cval[i] = 0.0;
         }
@@ -855,6 +921,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
             n_short += __shfl_xor(n_short, o);
             n_dep += __shfl_xor(n_dep, o);
             n_glob += __shfl_xor(n_glob, o);
+            n_flush += __shfl_xor(n_flush, o);
         }
         if (lane == 0) flush(0);
     }

@@ -38,7 +38,7 @@ class pmc_params(C.Structure):
                 ("block_threads", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("refill_lanes", C.c_int32), ("batch_events", C.c_int32),
                 ("tally_cache", C.c_int32), ("epoch_steps", C.c_int32),
-                ("cache_probes", C.c_int32)]
+                ("cache_probes", C.c_int32), ("claim_run_log2", C.c_int32)]
 
 
 class pmc_spot(C.Structure):
@@ -68,7 +68,8 @@ class pmc_summary(C.Structure):
                 ("transport_ms", C.c_double), ("generations", C.c_int32),
                 ("launches", C.c_int32), ("global_atomics", C.c_uint64),
                 ("block_threads", C.c_int32), ("grid_blocks", C.c_int32),
-                ("cache_slots", C.c_int32), ("epoch_steps", C.c_int32)]
+                ("cache_slots", C.c_int32), ("epoch_steps", C.c_int32),
+                ("cache_flush_atomics", C.c_uint64)]
 
 
 class pmc_plan(C.Structure):
