@@ -75,7 +75,7 @@ typedef struct {
                                 (the tuner may turn it off, else sized from the LDS left by the
                                 tables); -1 = off (every deposit is a global FP64 atomic) */
     int32_t epoch_steps;     /* loop iterations between cache flushes; 0 = 32 */
-    int32_t cache_probes;    /* cache slots tried per deposit (linear probing), 1..16; 0 = 4 */
+    int32_t cache_probes;    /* cache slots tried per deposit (linear probing), 1..16; 0 = 3 */
     int32_t claim_run_log2;  /* a workgroup claims primaries in runs of up to 2^claim_run_log2
                                 consecutive histories (a pencil's worth for the cache), 4..16;
                                 0 = 10 */
@@ -85,8 +85,9 @@ typedef struct {
  * (single/batched, plan count, log2 of histories and voxels) times the
  * candidate launch shapes (workgroup size, refill and event thresholds, LDS
  * deposit cache on or off) on the first spots of every plan, a fifth of the
- * run (2e5 to 2e6 histories), and keeps the fastest for that signature.
- * Results do not depend on the shape. */
+ * run (2e5 to 2e6 histories), times the three fastest twice more, and keeps
+ * the one with the best of its times for that signature.  Results do not
+ * depend on the shape. */
 
 /* Fill *p with the defaults above.  Never fails for a non-NULL p. */
 pmc_status pmc_default_params(pmc_params* p);

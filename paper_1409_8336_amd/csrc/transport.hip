@@ -279,10 +279,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
     const PlanDesc* pds = reinterpret_cast<const PlanDesc*>(lds + a.pd_offset);
     const Plans<kMulti> P{a, pds};
 
-    const float* lnr_w = lds + kOffLnrWater;
-    const float* lnr_o = lds + kOffLnrOwn;
-    const uint16_t* inv_w = reinterpret_cast<const uint16_t*>(lds + kOffInvWater);
-    const uint16_t* inv_o = reinterpret_cast<const uint16_t*>(lds + kOffInvOwn);
+    const uint16_t* lds16 = reinterpret_cast<const uint16_t*>(lds);
     const float* sig = lds + kOffSigma;
     const float* mc = lds + kOffSigma + 1000 * a.n_mat;
 
@@ -362,19 +359,27 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                 key |= (Key)plan << 32;
                 h ^= plan * 0x85EBCA6Bu;
             }
-            // multiplicative hash reduced to [0, n_slots) by a high product
+            // multiplicative hash reduced to [0, n_slots) by a high product;
+            // a slot is ours if it holds the key or we claim it empty
             uint32_t slot = __umulhi(h, (uint32_t)n_slots);
-            for (int probe = 0; probe < a.cache_probes; ++probe) {
-                Key held = ckey[slot];
+            auto take = [&](uint32_t sl) {
+                Key held = ckey[sl];
                 if (held == kEmptySlot) {
-                    held = atomicCAS(&ckey[slot], kEmptySlot, key);
+                    held = atomicCAS(&ckey[sl], kEmptySlot, key);
                     if (held == kEmptySlot) held = key;
                 }
-                if (held == key) {
-                    unsafeAtomicAdd(&cval[slot], v);
-                    return;
-                }
+                return held == key;
+            };
+            bool hit = take(slot);
+            // further slots by linear probing (written out for the second,
+            // a loop beyond it)
+            for (int probe = 1; !hit && probe < a.cache_probes; ++probe) {
                 slot = slot + 1u == (uint32_t)n_slots ? 0u : slot + 1u;
+                hit = take(slot);
+            }
+            if (hit) {
+                unsafeAtomicAdd(&cval[slot], v);
+                return;
             }
         }
         __hip_atomic_fetch_add(gbl(P.tally(plan)) + idx, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -494,6 +499,11 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
             int gi;
             float gt;
             grid_pos(E, gi, gt);
+            // range-table entries of both stopping tables (water-scaled and
+            // the material's own): which one applies is known only from the
+            // record, and reading both keeps them off the dependent chain
+            const float lw0 = lds[kOffLnrWater + gi], lw1 = lds[kOffLnrWater + gi + 1];
+            const float lo0 = lds[kOffLnrOwn + gi], lo1 = lds[kOffLnrOwn + gi + 1];
             float d = kInf;
             int axis = 2;
             {
@@ -514,7 +524,8 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
             // exist: it keeps the compiler from moving their arithmetic behind
             // the wait for the gather
             uint32_t rec_x = (uint32_t)rec, rec_y = (uint32_t)(rec >> 32);
-            asm volatile("" : "+v"(rec_x), "+v"(rec_y) : "v"(r.x), "v"(r.y), "v"(r.z), "v"(r.w), "v"(d), "v"(gt));
+            asm volatile("" : "+v"(rec_x), "+v"(rec_y) : "v"(r.x), "v"(r.y), "v"(r.z), "v"(r.w), "v"(d), "v"(gt),
+                         "v"(lw0), "v"(lw1), "v"(lo0), "v"(lo1));
             const float rho = __uint_as_float(rec_x);
             const int m = (int)rec_y;
             const float mf = mc[4 * m + 0];
@@ -522,13 +533,15 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
             const float mza = mc[4 * m + 2];
             const bool own = mc[4 * m + 3] != 0.f;
             const float scale = rho * mf;                          // Eq. 1-2
-            const float* lnr = own ? lnr_o : lnr_w;
-            const uint16_t* inv = own ? inv_o : inv_w;
+            // (table offsets selected, not pointers: the addresses stay LDS ones)
+            const float* lnr = lds + (own ? kOffLnrOwn : kOffLnrWater);
+            const uint16_t* inv = lds16 + 2 * (own ? kOffInvOwn : kOffInvWater);
             const float r_first = own ? a.r_first[1] : a.r_first[0];
             const float ln_r1 = own ? a.ln_r1[1] : a.ln_r1[0];
             const float inv_step = own ? a.inv_step[1] : a.inv_step[0];
 
-            const float range_tab = fexp(lnr[gi] + gt * (lnr[gi + 1] - lnr[gi]));
+            const float l_a = own ? lo0 : lw0, l_b = own ? lo1 : lw1;
+            const float range_tab = fexp(l_a + gt * (l_b - l_a));
             const float range = gi == 0 ? gt * r_first : range_tab;
             const float s_range = range * frcp(scale);
             float sigma = 0.f;
@@ -553,11 +566,27 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                 const float lr = fln(fmaxf(r1, r_first));
                 int c = (int)((lr - ln_r1) * inv_step);
                 c = c < 0 ? 0 : (c > 1023 ? 1023 : c);
+                // a coarse cell spans at most about one grid interval: two
+                // unconditional advances (reads clamped into the table), then
+                // a loop that practically never runs
+                // j = inv[c] <= 998: the four entries j..j+3 are read at once
+                // (j+2, j+3 may lie past this table's end inside the LDS
+                // blob; they are used only where j + 1 < 998)
                 int j = inv[c];
-                j += (j < 998 && lnr[j + 1] <= lr);
-                j += (j < 998 && lnr[j + 1] <= lr);
-                while (j < 998 && lnr[j + 1] <= lr) ++j;
-                const float tt = (lr - lnr[j]) * frcp(lnr[j + 1] - lnr[j]);
+                const float q0 = lnr[j], q1 = lnr[j + 1], q2 = lnr[j + 2], q3 = lnr[j + 3];
+                const bool adv1 = j < 998 && q1 <= lr;
+                const bool adv2 = adv1 && j + 1 < 998 && q2 <= lr;
+                float lo_l = adv2 ? q2 : (adv1 ? q1 : q0);
+                float hi_l = adv2 ? q3 : (adv1 ? q2 : q1);
+                j += (int)adv1 + (int)adv2;
+                if (j < 998 && hi_l <= lr) {
+                    // more than two grid intervals in one coarse cell (not
+                    // the case for these tables; kept for safety)
+                    while (j < 998 && lnr[j + 1] <= lr) ++j;
+                    lo_l = lnr[j];
+                    hi_l = lnr[j + 1];
+                }
+                const float tt = (lr - lo_l) * frcp(hi_l - lo_l);
                 const float e_tab = fexp(kLnE0 + ((float)j + tt) * kH);
                 const float e_low = fexp(kLnE0 + (r1 > 0.f ? r1 : 0.f) * frcp(r_first) * kH);
                 e1 = r1 <= r_first ? e_low : e_tab;
