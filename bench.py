@@ -113,7 +113,8 @@ def bench_plans(args):
                       "histories_per_step": n_tot // args.steps},
            "steps_per_s": steps_tot / elapsed,
            "launch_shape": {k: all_sums[-1][0][k] for k in ("block_threads", "grid_blocks",
-                                                            "cache_slots", "epoch_steps")},
+                                                            "cache_slots", "epoch_steps", "refill_lanes",
+                                                            "batch_events")},
            "transport_ms_per_step": sum(s[0]["transport_ms"] for s in all_sums) / args.steps,
            "ledger_residual_max": max(abs(s["incident"] - s["deposited"] - s["escaped"] - s["neutral"]
                                           - s["overflow"]) / s["incident"]
@@ -314,7 +315,7 @@ def main():
         "steps_per_history": steps_tot / n_tot,
         "transport_launches_per_step": launches / args.steps,
         "launch_shape": {k: sums[-1][k] for k in ("block_threads", "grid_blocks", "cache_slots",
-                                                   "epoch_steps")},
+                                                   "epoch_steps", "refill_lanes", "batch_events")},
         "transport_ms_per_step": 1e3 * transport_s / args.steps,
         "ledger_residual_max": worst_res,
         "roofline": {

@@ -155,6 +155,8 @@ typedef struct {
     int32_t epoch_steps;     /* loop iterations between cache flushes */
     uint64_t cache_flush_atomics; /* of global_atomics, those the epoch flushes issued (the rest
                                      are deposits that found no cache slot) */
+    int32_t refill_lanes;    /* launch shape used (continued): refill and event thresholds */
+    int32_t batch_events;
 } pmc_summary;
 
 typedef struct pmc_ctx pmc_ctx;

@@ -593,6 +593,8 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
             sm->tally_atomics = cnt[8 * p + 4];
             sm->global_atomics = cnt[8 * p + 5];
             sm->cache_flush_atomics = cnt[8 * p + 6];
+            sm->refill_lanes = shape.refill;
+            sm->batch_events = shape.batch;
             sm->block_threads = block;
             sm->grid_blocks = grid;
             sm->cache_slots = slots;
@@ -638,33 +640,41 @@ pmc_status choose_shape(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, hipS
         return PMC_OK;
     }
     // calibration work: a fifth of the run, 2e5 to 2e6 histories, enough to
-    // reach the steady state of a full grid of 1024-lane workgroups.  One
-    // geometry: the first spots of the list with their own history counts,
-    // which keeps the spatial coherence of the work (what the deposit cache
-    // relies on); several plans: every plan scaled down.
+    // reach the steady state of a full grid of 1024-lane workgroups.  Every
+    // plan contributes eight runs of consecutive spots spread evenly over its
+    // list (every energy layer of a field is represented), with their own
+    // history counts, up to its share of the work: consecutive spots keep the
+    // spatial coherence the deposit cache relies on.
     const double cal_hist = std::min(2.0e6, std::max(2.0e5, 0.2 * (double)total));
-    // every plan contributes the first spots of its list, with their own
-    // history counts, up to its share of the calibration work
-    std::vector<PlanIn> cal = plans;
     const double f = cal_hist / (double)total;
-    for (PlanIn& p : cal) {
+    constexpr int kCalBlocks = 8;
+    std::vector<PlanIn> cal = plans;
+    std::vector<std::vector<pmc_spot>> cal_spots(cal.size());
+    for (size_t pi = 0; pi < cal.size(); ++pi) {
+        PlanIn& p = cal[pi];
         double wsum = 0.0;
         for (int i = 0; i < p.n_spots; ++i) wsum += p.spots[i].weight;
         const double goal = f * (double)p.n_hist;
+        std::vector<pmc_spot>& sel = cal_spots[pi];
         double acc = 0.0;
-        int m = 0;
-        while (m < p.n_spots && acc < goal) {
-            acc += wsum > 0.0 ? (double)p.n_hist * p.spots[m].weight / wsum : 0.0;
-            ++m;
+        for (int blk = 0; blk < kCalBlocks; ++blk) {
+            int m = (int)(((long long)blk * p.n_spots) / kCalBlocks);
+            const double blk_goal = goal * (blk + 1) / kCalBlocks;
+            while (m < p.n_spots && (acc < blk_goal || sel.empty())) {
+                acc += wsum > 0.0 ? (double)p.n_hist * p.spots[m].weight / wsum : 0.0;
+                sel.push_back(p.spots[m]);
+                ++m;
+            }
         }
-        p.n_spots = m > 0 ? m : 1;
+        p.spots = sel.data();
+        p.n_spots = (int)sel.size();
         p.n_hist = std::max<unsigned long long>(1ull, (unsigned long long)std::llround(std::min(acc, (double)p.n_hist)));
         p.summary = nullptr;
     }
     std::vector<Shape> cands;
     for (int b : {256, 512, 1024})
         for (int r : {8, 16})
-            for (int e : {2, 4})
+            for (int e : {4, 8})
                 for (int ch : {0, -1}) {
                     Shape x;
                     x.block = c->p.block_threads ? c->p.block_threads : b;

@@ -167,15 +167,26 @@ DEV void grid_pos(float e, int& i, float& t)
     t = f;
 }
 
+// x at CDF value u of a 33-point table (CDF at lo + (hi - lo) i / 32, linear
+// between the points): the largest i in [0, 31] with cdf[i] <= u, found in two
+// rounds of independent loads (every fourth point, then the three inside the
+// bracket) instead of a chain of dependent ones; the CDF is non-decreasing,
+// so counting the points <= u gives the same index a bisection would
 DEV float inv_cdf33(const GLOBAL float* __restrict__ cdf, float u, float lo, float hi)
 {
-    int l = 0, h = 32;
-    while (h - l > 1) {
-        const int mid = (l + h) >> 1;
-        if (cdf[mid] <= u) l = mid;
-        else h = mid;
-    }
-    const float c0 = cdf[l], c1 = cdf[l + 1];
+    float c4[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) c4[i] = cdf[4 * i];
+    int l = 0;
+#pragma unroll
+    for (int i = 1; i < 8; ++i) l += (int)(c4[i] <= u);
+    l *= 4;
+    const float f1 = cdf[l + 1], f2 = cdf[l + 2], f3 = cdf[l + 3];
+    int k = (int)(f1 <= u) + (int)(f2 <= u) + (int)(f3 <= u);
+    float c_hi = c4[l / 4 + 1];
+    const float c0 = k == 0 ? c4[l / 4] : (k == 1 ? f1 : (k == 2 ? f2 : f3));
+    const float c1 = k == 0 ? f1 : (k == 1 ? f2 : (k == 2 ? f3 : c_hi));
+    l += k;
     const float frac = (u - c0) / (c1 - c0);
     return lo + (hi - lo) * ((float)l + frac) * (1.0f / 32.0f);
 }
@@ -405,24 +416,44 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                         // source: Gaussian spot on the z = 0 face (K1 role).
                         // Work index -> statistical group b, then spot s within
                         // the group's part of the list, then the history.
-                        const int ns1 = L->n_spots + 1;
+                        // The refilled lanes of a wave take consecutive work
+                        // indices (within a claim run): the first one's place
+                        // is searched once for the wave (uniform, scalar
+                        // code), the others step forward from it, and a lane
+                        // that lands past a run boundary searches on its own.
+                        const int nsp = L->n_spots;
+                        const int ns1 = nsp + 1;
                         const GLOBAL unsigned long long* ord = gbl(L->order);
-                        int bg = 0;
-                        {
-                            int hi = K;
-                            while (hi - bg > 1) {
-                                const int mid = (bg + hi) >> 1;
-                                if (ord[mid * ns1] <= idx) bg = mid;
-                                else hi = mid;
+                        auto locate_work = [&](unsigned long long x, int& b_out, int& s_out) {
+                            int b0 = 0, hb = K;
+                            while (hb - b0 > 1) {
+                                const int mid = (b0 + hb) >> 1;
+                                if (ord[mid * ns1] <= x) b0 = mid;
+                                else hb = mid;
+                            }
+                            const GLOBAL unsigned long long* rw = ord + b0 * ns1;
+                            int s0 = 0, hs = nsp;
+                            while (hs - s0 > 1) {
+                                const int mid = (s0 + hs) >> 1;
+                                if (rw[mid] <= x) s0 = mid;
+                                else hs = mid;
+                            }
+                            b_out = b0;
+                            s_out = s0;
+                        };
+                        int bg, lo;
+                        locate_work(claim_index(base), bg, lo);
+                        // (a run holds consecutive indices; idx < n_primary
+                        // keeps the walk inside the table: the last group's
+                        // row ends at n_primary)
+                        for (int walk = 0; walk < 4 && idx >= ord[bg * ns1 + lo + 1]; ++walk) {
+                            if (++lo == nsp) {
+                                lo = 0;
+                                ++bg;
                             }
                         }
+                        if (idx < ord[bg * ns1 + lo] || idx >= ord[bg * ns1 + lo + 1]) locate_work(idx, bg, lo);
                         const GLOBAL unsigned long long* row = ord + bg * ns1;
-                        int lo = 0, hi = L->n_spots;
-                        while (hi - lo > 1) {
-                            const int mid = (lo + hi) >> 1;
-                            if (row[mid] <= idx) lo = mid;
-                            else hi = mid;
-                        }
                         const GLOBAL float* sp = gbl(L->spots) + 8 * lo;
                         const unsigned long long uid = ord[K * ns1 + bg * L->n_spots + lo] + (idx - row[lo]);
                         if constexpr (kMulti) {

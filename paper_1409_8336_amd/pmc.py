@@ -69,7 +69,8 @@ class pmc_summary(C.Structure):
                 ("launches", C.c_int32), ("global_atomics", C.c_uint64),
                 ("block_threads", C.c_int32), ("grid_blocks", C.c_int32),
                 ("cache_slots", C.c_int32), ("epoch_steps", C.c_int32),
-                ("cache_flush_atomics", C.c_uint64)]
+                ("cache_flush_atomics", C.c_uint64), ("refill_lanes", C.c_int32),
+                ("batch_events", C.c_int32)]
 
 
 class pmc_plan(C.Structure):
