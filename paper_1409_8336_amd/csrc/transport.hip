@@ -1031,7 +1031,8 @@ hipError_t launch_atomic_probe(double* tally, int nx, int ny, int nz, int K, int
 constexpr int kStatsVox = 128;
 __global__ void __launch_bounds__(kStatsVox) stats_kernel(const double* __restrict__ tally,
                                                           const uint2* __restrict__ vox,
-                                                          unsigned long long nvox, int K, double conv0,
+                                                          unsigned long long nvox, int K, uint32_t k_magic,
+                                                          double inv_k, double k_ratio, double conv0,
                                                           double* __restrict__ dose,
                                                           double* __restrict__ var, double* dep_sum)
 {
@@ -1043,35 +1044,55 @@ __global__ void __launch_bounds__(kStatsVox) stats_kernel(const double* __restri
         const unsigned long long left = nvox - v0;
         const int nv = left < (unsigned long long)kStatsVox ? (int)left : kStatsVox;
         const int n = nv * K;                      // doubles in this run
+        // the voxel's record is read before the barrier, off the dependent path
+        const unsigned long long v = v0 + threadIdx.x;
+        const float rho = (int)threadIdx.x < nv ? __uint_as_float(vox[v].x) : 1.f;
         __syncthreads();
-        // the run starts at v0 * K doubles, a multiple of 2: 16-byte aligned
+        // the run starts at v0 * K doubles, a multiple of 2: 16-byte aligned.
+        // Element e lies in row e / K, computed as a high product with
+        // k_magic = ceil(2^32 / K) (exact for e < 2^32 / K^2, here e < 8192)
         const double2* src2 = reinterpret_cast<const double2*>(tally + v0 * K);
         for (int i = threadIdx.x; i < (n >> 1); i += kStatsVox) {
             const double2 q = src2[i];
-            const int e0 = 2 * i, e1 = 2 * i + 1;
-            rows[(e0 / K) * pitch + e0 % K] = q.x;
-            rows[(e1 / K) * pitch + e1 % K] = q.y;
+            const uint32_t e0 = 2u * (uint32_t)i, e1 = e0 + 1u;
+            const uint32_t r0 = __umulhi(e0, k_magic), r1 = __umulhi(e1, k_magic);
+            rows[r0 * pitch + (e0 - r0 * K)] = q.x;
+            rows[r1 * pitch + (e1 - r1 * K)] = q.y;
         }
         if ((n & 1) && threadIdx.x == 0) rows[((n - 1) / K) * pitch + (n - 1) % K] = tally[v0 * K + n - 1];
         __syncthreads();
         if ((int)threadIdx.x >= nv) continue;
-        const unsigned long long v = v0 + threadIdx.x;
         const double* t = rows + threadIdx.x * pitch;
         double tot = 0.0;
         for (int b = 0; b < K; ++b) tot += t[b];
-        const double mean = tot / K;
+        const double mean = tot * inv_k;
         double ss = 0.0;
         for (int b = 0; b < K; ++b) {
             const double dd = t[b] - mean;
             ss += dd * dd;
         }
-        const double conv = conv0 / (double)__uint_as_float(vox[v].x);
+        // conv0 / rho: an FP32 reciprocal refined by two Newton steps in FP64
+        const double rd = (double)rho;
+        double ir = (double)frcp(rho);
+        ir = ir * (2.0 - rd * ir);
+        ir = ir * (2.0 - rd * ir);
+        const double conv = conv0 * ir;
         dose[v] = tot * conv;
-        if (var) var[v] = (double)K / (K - 1) * ss * conv * conv;
+        if (var) var[v] = k_ratio * ss * conv * conv;
         part += tot;
     }
+    // one atomic per workgroup: the workgroups' partial sums all go to one
+    // address, where memory-side atomics serialise (one per wave of 65536
+    // workgroups took most of the kernel's time)
     for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
-    if ((threadIdx.x & 63) == 0 && part != 0.0) unsafeAtomicAdd(dep_sum, part);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) rows[threadIdx.x >> 6] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sum = 0.0;
+        for (int w = 0; w < kStatsVox / 64; ++w) sum += rows[w];
+        if (sum != 0.0) unsafeAtomicAdd(dep_sum, sum);
+    }
 }
 
 __global__ void density_kernel(const uint2* __restrict__ vox, unsigned long long nvox, float* __restrict__ rho)
@@ -1134,11 +1155,14 @@ hipError_t launch_stats(const double* tally, const uint2* vox, unsigned long lon
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (e != hipSuccess) return e;
     }
+    // enough workgroups to fill the chip several times over, each looping over
+    // runs of voxels (fewer workgroups, fewer atomics on the deposited sum)
     unsigned long long blocks = (nvox + kStatsVox - 1) / kStatsVox;
-    if (blocks > 65536) blocks = 65536;
+    if (blocks > 4096) blocks = 4096;
     if (blocks == 0) blocks = 1;
+    const uint32_t k_magic = (uint32_t)((0x100000000ull + (unsigned)K - 1) / (unsigned)K);
     hipLaunchKernelGGL(stats_kernel, dim3((unsigned)blocks), dim3(kStatsVox), bytes, s, tally, vox, nvox, K,
-                       conv0, dose, var, dep_sum);
+                       k_magic, 1.0 / K, (double)K / (K - 1), conv0, dose, var, dep_sum);
     return hipGetLastError();
 }
 
