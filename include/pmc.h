@@ -74,11 +74,16 @@ typedef struct {
     int32_t tally_cache;     /* LDS deposit cache per workgroup: slots, 512..16384; 0 = automatic
                                 (the tuner may turn it off, else sized from the LDS left by the
                                 tables); -1 = off (every deposit is a global FP64 atomic) */
-    int32_t epoch_steps;     /* loop iterations between cache flushes; 0 = 32 */
+    int32_t epoch_steps;     /* loop iterations between epoch ends (cache flush, own-queue
+                                publication); 0 = 32 */
     int32_t cache_probes;    /* cache slots tried per deposit (linear probing), 1..16; 0 = 3 */
     int32_t claim_run_log2;  /* a workgroup claims primaries in runs of up to 2^claim_run_log2
                                 consecutive histories (a pencil's worth for the cache), 4..16;
                                 0 = 10 */
+    int32_t local_queue;     /* secondary protons a workgroup queues for its own lanes within a
+                                launch (entries of 48 B per workgroup), 1..65536; 0 = up to
+                                16384 within 256 MiB for the grid;
+                                -1 = off (every secondary waits for the next generation launch) */
 } pmc_params;
 /* Autotuning: when any of block_threads, refill_lanes, batch_events is 0 and
  * a run has at least 2e5 histories, the first run of each workload signature
@@ -138,6 +143,9 @@ typedef struct {
 typedef struct {
     double incident, deposited, escaped, neutral, overflow;
     uint64_t histories, steps, secondaries, n_elastic, n_nonelastic, n_overflow;
+                           /* secondaries: protons emitted by nuclear events (taken by the
+                              emitting workgroup, this plan, plus those that went through the
+                              generation queues, whole run) */
     uint64_t n_short_steps; /* steps lengthened to s_min (sub-micron boundary approaches) */
     uint64_t tally_atomics; /* energy deposits scored (one per step, event or termination) */
     double total_weight;   /* sum of primary weights (dose normalisation) */
@@ -152,7 +160,8 @@ typedef struct {
     int32_t block_threads;   /* launch shape used: workgroup size, */
     int32_t grid_blocks;     /* workgroups in the persistent grid, */
     int32_t cache_slots;     /* deposit-cache slots per workgroup (0 = off), */
-    int32_t epoch_steps;     /* loop iterations between cache flushes */
+    int32_t epoch_steps;     /* loop iterations between epoch ends (cache flush, own-queue
+                                publication) */
     uint64_t cache_flush_atomics; /* of global_atomics, those the epoch flushes issued (the rest
                                      are deposits that found no cache slot) */
     int32_t refill_lanes;    /* launch shape used (continued): refill and event thresholds */

@@ -13,11 +13,25 @@ constexpr int kQueuePlanes = 12;   // px py pz ux uy uz E w uid_lo uid_hi batch 
 constexpr int kMaxPlans = 64;
 constexpr int kMaxGenerations = 64;
 // counters a workgroup accumulates per plan: steps, elastic, non-elastic,
-// short steps, deposits, tally atomics, of which cache-flush atomics; with
-// the ledger (escaped, neutral, overflow: 3 doubles) the per-plan LDS block
-// of a batched launch
-constexpr int kWgCounters = 7;
+// short steps, deposits, tally atomics, of which cache-flush atomics,
+// secondaries queued in the workgroup's own queue; with the ledger (escaped,
+// neutral, overflow: 3 doubles) the per-plan LDS block of a batched launch
+constexpr int kWgCounters = 8;
 constexpr int kPlanLdsBytes = 8 * (3 + kWgCounters);
+// device counters per plan (u64): the kWgCounters above, then at index 8 the
+// count of workgroups that stopped at the epoch limit (plan 0 only)
+constexpr int kPlanCounters = 16;
+constexpr int kCtrAborted = 8;
+// LDS control words of a workgroup (u32), after the deposit cache: own
+// secondary queue produced / claimed / published, alive lanes at the epoch
+// end, primaries exhausted, workgroup done
+constexpr int kWgCtlWords = 8;
+// a workgroup's own secondary queue entry: 12 u32 (px py pz ux uy uz E w
+// uid_lo uid_hi group plan), 48 bytes
+constexpr int kLocEntryWords = 12;
+// epochs after which a workgroup stops (a guard against a non-terminating
+// launch; reported as an error)
+constexpr uint32_t kMaxEpochs = 1u << 21;
 
 // LDS blob layout, in 32-bit words
 constexpr int kOffLnrWater = 0;
@@ -57,8 +71,9 @@ struct alignas(8) LdsArgs {
     unsigned long long q_cap;
     double* ledger;
     unsigned long long* counters;
+    uint32_t* q_loc;   // this launch's per-workgroup queues (loc_cap entries each)
     int n_spots;
-    int pad;
+    int loc_cap;
 };
 
 struct KernelArgs {
@@ -104,7 +119,7 @@ struct KernelArgs {
     int gen;
     // outputs, per plan
     double* ledger;                 // [plan][4]: escaped, neutral, overflow, deposited
-    unsigned long long* counters;   // [plan][8]: the kWgCounters counters above
+    unsigned long long* counters;   // [plan][kPlanCounters]: the counters above
     int refill_lanes;
     int batch_events;
     // workgroup deposit cache in LDS: cache_slots sums (double) then as many
@@ -123,6 +138,12 @@ struct KernelArgs {
     unsigned long long* wg_claims;
     int claim_log2;
     int args_off;   // LDS word offset (even) of the staged LdsArgs
+    // secondaries a workgroup emits go first to its own queue (loc_cap AoS
+    // entries of kLocEntryWords at q_loc + b * loc_cap * kLocEntryWords),
+    // published at the next epoch boundary and taken by its own idle lanes;
+    // what does not fit goes to the next generation's queue; 0 = off
+    uint32_t* q_loc;
+    int loc_cap;
 };
 
 }  // namespace pmc

@@ -112,6 +112,7 @@ struct pmc_ctx {
     DevBuf<double> d_dose, d_var, d_ledger;
     DevBuf<uint32_t> d_q[2];
     DevBuf<unsigned long long> d_gc, d_counters, d_order, d_wgc;
+    DevBuf<uint32_t> d_qloc;   // per-workgroup secondary queues
     DevBuf<float> d_spots;
     DevBuf<PlanDesc> d_plans;
     unsigned long long* h_pinned = nullptr;   // pinned read-back area
@@ -209,6 +210,7 @@ bool params_ok(const pmc_params& p, std::string& why)
     if (p.cache_probes < 0 || p.cache_probes > 16) { why = "cache_probes must be in [0, 16]"; return false; }
     if (p.claim_run_log2 != 0 && (p.claim_run_log2 < 4 || p.claim_run_log2 > 16))
     { why = "claim_run_log2 must be 0 or in [4, 16]"; return false; }
+    if (p.local_queue < -1 || p.local_queue > 65536) { why = "local_queue must be -1, 0 or in [1, 65536]"; return false; }
     return true;
 }
 
@@ -422,7 +424,7 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
     HIPCHK(c->d_q[0].ensure(cap * kQueuePlanes), "alloc queue");
     HIPCHK(c->d_q[1].ensure(cap * kQueuePlanes), "alloc queue");
     HIPCHK(c->d_gc.ensure(2 * (kMaxGenerations + 2)), "alloc counters");
-    HIPCHK(c->d_counters.ensure(8 * np), "alloc counters");
+    HIPCHK(c->d_counters.ensure((size_t)kPlanCounters * np), "alloc counters");
     HIPCHK(c->d_ledger.ensure(4 * np), "alloc ledger");
     HIPCHK(c->d_spots.ensure(sp.size()), "alloc spots");
     HIPCHK(c->d_order.ensure(order.size()), "alloc spots");
@@ -433,7 +435,7 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
     HIPCHK(hipEventRecord(c->ev0, st), "event");
     for (int p = 0; p < np; ++p) HIPCHK(launch_zero(pd[p].tally, plans[p].g->nvox() * K * 8, st), "zero tally");
     HIPCHK(launch_zero(c->d_gc.p, c->d_gc.n * 8, st), "zero counters");
-    HIPCHK(launch_zero(c->d_counters.p, 64 * (size_t)np, st), "zero counters");
+    HIPCHK(launch_zero(c->d_counters.p, 8 * (size_t)kPlanCounters * np, st), "zero counters");
     HIPCHK(launch_zero(c->d_ledger.p, 32 * (size_t)np, st), "zero ledger");
 
     KernelArgs a{};
@@ -479,8 +481,12 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
         slots = want;
         if (slots == 0) {
             const long wgs = std::max(1, 1024 / block);
-            const long avail = 163840L / wgs - (long)lds_words * 4 - 16 - (long)sizeof(LdsArgs) -
-                               (multi ? (long)kPlanLdsBytes * np : 0L) - 16;
+            // what the tables, the control words, the staged arguments (with
+            // their alignment) and a batch's per-plan block leave of the CU's
+            // 160 KiB
+            const long cache_off_bytes = 4L * (long)((lds_words + 1) & ~(size_t)1);
+            const long avail = 163840L / wgs - cache_off_bytes - 4L * kWgCtlWords - 8 - (long)sizeof(LdsArgs) -
+                               (multi ? (long)kPlanLdsBytes * np : 0L);
             slots = (int)std::min(16384L, avail / (4L * (2 + key_words)));
             if (slots < 512) slots = 0;
         }
@@ -489,7 +495,8 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
     a.cache_off = (int)((lds_words + 1) & ~(size_t)1);
     a.epoch_iters = c->p.epoch_steps ? c->p.epoch_steps : 32;
     a.cache_probes = c->p.cache_probes ? c->p.cache_probes : 3;
-    const size_t used = slots ? (size_t)a.cache_off + (size_t)(2 + key_words) * slots + 1 : lds_words;
+    // (the workgroup's control words follow the cache, also without one)
+    const size_t used = (size_t)a.cache_off + (size_t)(2 + key_words) * slots + kWgCtlWords;
     a.args_off = (int)((used + 1) & ~(size_t)1);
     // batched launches: per-plan ledger and counters after the arguments
     const size_t lds = (size_t)a.args_off * 4 + sizeof(LdsArgs) + (multi ? kPlanLdsBytes * (size_t)np : 0);
@@ -505,17 +512,30 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
     HIPCHK(c->d_wgc.ensure((size_t)kMaxGenerations * grid), "alloc claim counters");
     HIPCHK(launch_zero(c->d_wgc.p, (size_t)kMaxGenerations * grid * 8, st), "zero claim counters");
     a.wg_claims = c->d_wgc.p;
+    // per-workgroup secondary queues (48-byte entries); automatic: up to
+    // 16384 entries per workgroup within 256 MiB for the whole grid
+    a.loc_cap = c->p.local_queue < 0
+                    ? 0
+                    : (c->p.local_queue ? c->p.local_queue
+                                        : (int)std::min<long>(16384L, (256L << 20) / (48L * grid)));
+    if (a.loc_cap > 0) {
+        HIPCHK(c->d_qloc.ensure((size_t)grid * (size_t)a.loc_cap * kLocEntryWords), "alloc workgroup queues");
+        a.q_loc = c->d_qloc.p;
+    }
     int gens = 0;
     unsigned long long produced_total = 0, overflow_n = 0;
     // generations are launched in groups without waiting: each launch reads
     // its own work count on the device (an empty generation exits at once),
     // and the host reads the produced counts once per group
     int launched = 0;
+    // with the workgroups' own queues the next generation only holds what
+    // overflowed them: launch two at a time (the second is mostly empty)
+    const int group = a.loc_cap > 0 ? 2 : kGenGroup;
     if (total > 0) {
         bool done = false;
         while (!done) {
             const int g0 = launched;
-            const int g1 = std::min(g0 + kGenGroup, kMaxGenerations);
+            const int g1 = std::min(g0 + group, kMaxGenerations);
             if (g0 >= kMaxGenerations) return fail(c, PMC_ERR_DEVICE, "secondary generations exceed limit");
             for (int gidx = g0; gidx < g1; ++gidx) {
                 a.gen = gidx;
@@ -555,7 +575,7 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
         }
     }
     HIPCHK(hipEventRecord(c->ev1, st), "event");
-    const size_t led_words = 4 * (size_t)np, cnt_words = 8 * (size_t)np;
+    const size_t led_words = 4 * (size_t)np, cnt_words = (size_t)kPlanCounters * np;
     if ((led_words + cnt_words) * 8 > kPinnedBytes) return fail(c, PMC_ERR_ARG, "too many plans");
     HIPCHK(hipMemcpyAsync(c->h_pinned, c->d_ledger.p, led_words * 8, hipMemcpyDeviceToHost, st), "read ledger");
     HIPCHK(hipMemcpyAsync(c->h_pinned + led_words, c->d_counters.p, cnt_words * 8, hipMemcpyDeviceToHost, st), "read counters");
@@ -586,20 +606,23 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
             sm->overflow = led[4 * p + 2];
             sm->deposited = led[4 * p + 3];
             sm->histories = plans[p].n_hist;
-            sm->steps = cnt[8 * p + 0];
-            sm->n_elastic = cnt[8 * p + 1];
-            sm->n_nonelastic = cnt[8 * p + 2];
-            sm->n_short_steps = cnt[8 * p + 3];
-            sm->tally_atomics = cnt[8 * p + 4];
-            sm->global_atomics = cnt[8 * p + 5];
-            sm->cache_flush_atomics = cnt[8 * p + 6];
+            const unsigned long long* cp = cnt + (size_t)kPlanCounters * p;
+            sm->steps = cp[0];
+            sm->n_elastic = cp[1];
+            sm->n_nonelastic = cp[2];
+            sm->n_short_steps = cp[3];
+            sm->tally_atomics = cp[4];
+            sm->global_atomics = cp[5];
+            sm->cache_flush_atomics = cp[6];
             sm->refill_lanes = shape.refill;
             sm->batch_events = shape.batch;
             sm->block_threads = block;
             sm->grid_blocks = grid;
             sm->cache_slots = slots;
-            sm->epoch_steps = slots ? a.epoch_iters : 0;
-            sm->secondaries = produced_total;
+            sm->epoch_steps = a.epoch_iters;
+            // taken by the emitting workgroup (this plan), plus those that
+            // went through the generation queues (the whole run)
+            sm->secondaries = cp[7] + produced_total;
             sm->n_overflow = overflow_n;
             sm->total_weight = wtot[p];
             sm->device_ms = ms;
@@ -608,6 +631,8 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
             sm->launches = launched;
         }
     }
+    if (c->h_pinned[led_words + kCtrAborted] != 0)
+        return fail(c, PMC_ERR_DEVICE, "transport workgroups stopped at the epoch limit: dose incomplete");
     if (overflow_n) return fail(c, PMC_ERR_QUEUE_OVERFLOW, "secondary queue overflow: raise queue_capacity");
     return PMC_OK;
 }

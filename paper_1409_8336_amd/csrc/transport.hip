@@ -18,6 +18,12 @@
 
 #include "device.hpp"
 
+// Multiply-adds are fused only where one source expression holds both
+// (not across statements after inlining): the single-plan and batched
+// instantiations then round every step identically, so a batch reproduces
+// single-plan runs history by history.
+#pragma clang fp contract(on)
+
 namespace pmc {
 
 #define DEV __device__ __forceinline__
@@ -26,6 +32,9 @@ namespace pmc {
 // space gives global instead of flat memory instructions, which do not make
 // the wave wait for its LDS operations as well.
 #define GLOBAL __attribute__((address_space(1)))
+// 16-byte vector for global-space loads and stores (the HIP vector types do
+// not bind to address-space-qualified references)
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 template <typename T>
 DEV GLOBAL T* gbl(T* p)
 {
@@ -244,19 +253,25 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
     }
     // deposit cache at an even word offset: slot values (double), slot keys
     // (tally index; in a batch of plans, plan << 32 | tally index), then the
-    // count of waves that have finished
+    // workgroup's control words
     using Key = std::conditional_t<kMulti, unsigned long long, uint32_t>;
     constexpr Key kEmptySlot = ~Key(0);
     const int n_slots = a.cache_slots;
     const bool use_cache = n_slots > 0;
     double* const cval = reinterpret_cast<double*>(lds + a.cache_off);
     Key* const ckey = reinterpret_cast<Key*>(lds + a.cache_off + 2 * n_slots);
-    uint32_t* const waves_done = reinterpret_cast<uint32_t*>(ckey + n_slots);
+    uint32_t* const ctl = reinterpret_cast<uint32_t*>(ckey + n_slots);
+    uint32_t* const loc_produced = ctl + 0;   // entries reserved in the own queue
+    uint32_t* const loc_claimed = ctl + 1;    // entries taken by lanes
+    uint32_t* const loc_avail = ctl + 2;      // entries published (written before the last epoch end)
+    uint32_t* const wg_busy = ctl + 3;        // alive lanes counted at the epoch end
+    uint32_t* const prim_done = ctl + 4;      // some wave found the work list exhausted
+    uint32_t* const wg_done = ctl + 5;
     for (int i = threadIdx.x; i < n_slots; i += blockDim.x) {
         cval[i] = 0.0;
         ckey[i] = kEmptySlot;
     }
-    if (use_cache && threadIdx.x == 0) *waves_done = 0;
+    if (threadIdx.x < kWgCtlWords) ctl[threadIdx.x] = 0u;
     LdsArgs* const L = reinterpret_cast<LdsArgs*>(lds + a.args_off);
     // batched launches: per-plan ledger (escaped, neutral, overflow) and
     // counters of the workgroup, accumulated in LDS and written out once at
@@ -285,6 +300,8 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
         L->ledger = a.ledger;
         L->counters = a.counters;
         L->n_spots = a.n_spots;
+        L->loc_cap = a.loc_cap;
+        L->q_loc = a.q_loc + (size_t)blockIdx.x * (size_t)a.loc_cap * kLocEntryWords;
     }
     __syncthreads();
     const PlanDesc* pds = reinterpret_cast<const PlanDesc*>(lds + a.pd_offset);
@@ -324,7 +341,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
 
     // per-lane ledger and counters of the lane's current plan
     double acc_esc = 0.0, acc_neu = 0.0, acc_ovf = 0.0;
-    uint32_t n_steps = 0, n_el = 0, n_ne = 0, n_short = 0, n_dep = 0, n_glob = 0, n_flush = 0;
+    uint32_t n_steps = 0, n_el = 0, n_ne = 0, n_short = 0, n_dep = 0, n_glob = 0, n_flush = 0, n_locq = 0;
     auto flush = [&](uint32_t pl) {
         if constexpr (kMulti) {
             double* LG = wg_led + 3 * pl;
@@ -339,12 +356,13 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
             if (n_dep) atomicAdd(&C[4], (unsigned long long)n_dep);
             if (n_glob) atomicAdd(&C[5], (unsigned long long)n_glob);
             if (n_flush) atomicAdd(&C[6], (unsigned long long)n_flush);
+            if (n_locq) atomicAdd(&C[7], (unsigned long long)n_locq);
             acc_esc = acc_neu = acc_ovf = 0.0;
-            n_steps = n_el = n_ne = n_short = n_dep = n_glob = n_flush = 0;
+            n_steps = n_el = n_ne = n_short = n_dep = n_glob = n_flush = n_locq = 0;
             return;
         }
         double* LG = L->ledger + 4 * pl;
-        unsigned long long* C = L->counters + 8 * pl;
+        unsigned long long* C = L->counters + kPlanCounters * pl;
         if (acc_esc != 0.0) unsafeAtomicAdd(&LG[0], acc_esc);
         if (acc_neu != 0.0) unsafeAtomicAdd(&LG[1], acc_neu);
         if (acc_ovf != 0.0) unsafeAtomicAdd(&LG[2], acc_ovf);
@@ -355,8 +373,9 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
         if (n_dep) atomicAdd(&C[4], (unsigned long long)n_dep);
         if (n_glob) atomicAdd(&C[5], (unsigned long long)n_glob);
         if (n_flush) atomicAdd(&C[6], (unsigned long long)n_flush);
+        if (n_locq) atomicAdd(&C[7], (unsigned long long)n_locq);
         acc_esc = acc_neu = acc_ovf = 0.0;
-        n_steps = n_el = n_ne = n_short = n_dep = n_glob = n_flush = 0;
+        n_steps = n_el = n_ne = n_short = n_dep = n_glob = n_flush = n_locq = 0;
     };
     // one deposit into tally element idx of the current plan: through the
     // workgroup's LDS cache when the slot is free or already holds idx,
@@ -397,21 +416,79 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
         ++n_glob;
     };
     bool exhausted = false;
-    bool wave_done = false, counted = false;
+    uint32_t epoch = 0;
 
-    for (;;) {   // epochs: the cache is flushed between them
-    for (int it = 0; !wave_done && (!use_cache || it < a.epoch_iters); ++it) {
+    // epochs: between them the workgroup flushes its deposit cache, publishes
+    // the secondaries its lanes queued in its own queue and decides whether
+    // it is done
+    for (;;) {
+    for (int it = 0; it < a.epoch_iters; ++it) {
         // ---------------------------------------------------------- refill
+        // idle lanes take first the published entries of the workgroup's own
+        // queue, then indices of the generation's work list
         const unsigned long long idle = __ballot(!alive);
         const int n_idle = __popcll(idle);
-        if (!exhausted && n_idle > 0 && (n_idle == kWave || n_idle >= a.refill_lanes)) {
+        if (n_idle > 0 && (n_idle == kWave || n_idle >= a.refill_lanes || exhausted)) {
+            const int rank = mbcnt(idle);
+            uint32_t n_sec = 0, sec_base = 0;
+            if (lane == 0 && L->loc_cap > 0) {
+                // claim up to n_idle published entries: compare-and-swap on the
+                // LDS counter (a failed swap means another wave claimed)
+                const uint32_t av = *loc_avail;
+                uint32_t c = *loc_claimed;
+                while (c < av) {
+                    const uint32_t take = min(av - c, (uint32_t)n_idle);
+                    const uint32_t prev = atomicCAS(loc_claimed, c, c + take);
+                    if (prev == c) {
+                        sec_base = c;
+                        n_sec = take;
+                        break;
+                    }
+                    c = prev;
+                }
+            }
+            n_sec = __builtin_amdgcn_readfirstlane(n_sec);
+            sec_base = __builtin_amdgcn_readfirstlane(sec_base);
+            const int n_rest = n_idle - (int)n_sec;
+            const bool take_prim = !exhausted && n_rest > 0;
             unsigned long long base = 0;
-            if (lane == 0) base = atomicAdd(claim, (unsigned long long)n_idle);
-            base = bcast0(base);
-            if (claim_index(base + (unsigned long long)n_idle) >= limit) exhausted = true;
+            if (take_prim) {
+                if (lane == 0) base = atomicAdd(claim, (unsigned long long)n_rest);
+                base = bcast0(base);
+                if (claim_index(base + (unsigned long long)n_rest) >= limit) exhausted = true;
+            }
             if (!alive) {
-                const unsigned long long idx = claim_index(base + (unsigned long long)mbcnt(idle));
-                if (idx < limit) {
+                bool got = false;
+                if (rank < (int)n_sec) {
+                    // a secondary of this workgroup (48-byte entry)
+                    const GLOBAL u32x4* q4 = reinterpret_cast<const GLOBAL u32x4*>(
+                        gbl(L->q_loc) + (size_t)(sec_base + (uint32_t)rank) * kLocEntryWords);
+                    const u32x4 e0 = q4[0], e1 = q4[1], e2 = q4[2];
+                    px = __uint_as_float(e0.x);
+                    py = __uint_as_float(e0.y);
+                    pz = __uint_as_float(e0.z);
+                    ux = __uint_as_float(e0.w);
+                    uy = __uint_as_float(e1.x);
+                    uz = __uint_as_float(e1.y);
+                    E = __uint_as_float(e1.z);
+                    w = __uint_as_float(e1.w);
+                    uid_lo = e2.x;
+                    uid_hi = e2.y;
+                    batch = e2.z;
+                    if constexpr (kMulti) {
+                        if (e2.w != plan) {
+                            flush(plan);
+                            plan = e2.w;
+                        }
+                    }
+                    const uint4 r = philox<!kMulti>(uid_lo, uid_hi, 0u, 0u, P.key_lo(plan), P.key_hi(plan));
+                    mfp = -fln(u01(r.z));
+                    got = true;
+                }
+                const unsigned long long idx =
+                    claim_index(base + (unsigned long long)(rank - (int)n_sec));
+                if (!got && take_prim && idx < limit) {
+                    got = true;
                     if (gen == 0) {
                         // source: Gaussian spot on the z = 0 face (K1 role).
                         // Work index -> statistical group b, then spot s within
@@ -502,6 +579,8 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                         const uint4 r = philox<!kMulti>(uid_lo, uid_hi, 0u, 0u, P.key_lo(plan), P.key_hi(plan));
                         mfp = -fln(u01(r.z));
                     }
+                }
+                if (got) {
                     k = 0;
                     alive = locate_axis(px, ux, P.nx(plan), vx) && locate_axis(py, uy, P.ny(plan), vy) &&
                             locate_axis(pz, uz, P.nz(plan), vz);
@@ -511,10 +590,9 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
         }
         const unsigned long long busy = __ballot(alive);
         if (busy == 0) {
-            if (exhausted) {
-                wave_done = true;
-                break;
-            }
+            // nothing to run: with the work list exhausted and nothing
+            // published in the own queue, wait for the epoch end
+            if (exhausted) break;
             continue;
         }
 
@@ -881,18 +959,29 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
         }
         n_el += ev_el;
         n_ne += ev_ne;
-        // append emitted protons to the next generation's queue
+        // append emitted protons: to the workgroup's own queue (entries
+        // lbase + i while below its capacity), what does not fit to the next
+        // generation's queue
         {
             const unsigned long long b0 = __ballot(n_out & 1), b1 = __ballot(n_out & 2),
                                      b2 = __ballot(n_out & 4);
             const int total = __popcll(b0) + 2 * __popcll(b1) + 4 * __popcll(b2);
             if (total == 0) continue;
             const int off = mbcnt(b0) + 2 * mbcnt(b1) + 4 * mbcnt(b2);
-            unsigned long long base = 0;
-            if (lane == 0) base = atomicAdd(out_reserve, (unsigned long long)total);
-            base = bcast0(base);
+            const uint32_t lcap = (uint32_t)L->loc_cap;
+            uint32_t lbase = 0;
+            if (lane == 0 && lcap > 0) lbase = atomicAdd(loc_produced, (uint32_t)total);
+            lbase = __builtin_amdgcn_readfirstlane(lbase);
+            const uint32_t first_over = lcap > lbase ? lcap : lbase;
+            const uint32_t end = lbase + (uint32_t)total;
+            const uint32_t n_over = end > first_over ? end - first_over : 0u;
+            unsigned long long gbase = 0;
+            if (n_over > 0) {
+                if (lane == 0) gbase = atomicAdd(out_reserve, (unsigned long long)n_over);
+                gbase = bcast0(gbase);
+            }
             if (n_out > 0) {
-                unsigned long long slot = base + off;
+                uint32_t li = lbase + (uint32_t)off;
                 const unsigned long long cap = L->q_cap;
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
@@ -910,7 +999,17 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                         }
                         const uint4 cu = philox<!kMulti>(uid_lo, uid_hi, ks, 0xC0000000u | jj, P.key_lo(plan),
                                                 P.key_hi(plan));
-                        if (slot < cap) {
+                        const unsigned long long slot = gbase + (unsigned long long)(li - first_over);
+                        if (li < lcap) {
+                            GLOBAL u32x4* q4 = reinterpret_cast<GLOBAL u32x4*>(gbl(L->q_loc) +
+                                                                               (size_t)li * kLocEntryWords);
+                            q4[0] = u32x4{__float_as_uint(ox), __float_as_uint(oy), __float_as_uint(oz),
+                                          __float_as_uint(dx)};
+                            q4[1] = u32x4{__float_as_uint(dy), __float_as_uint(dz), __float_as_uint(ev),
+                                          __float_as_uint(w)};
+                            q4[2] = u32x4{cu.x, cu.y, batch, plan};
+                            ++n_locq;
+                        } else if (slot < cap) {
                             GLOBAL uint32_t* q = gbl(L->q_out) + slot;
                             q[0] = __float_as_uint(ox);
                             q[cap] = __float_as_uint(oy);
@@ -927,17 +1026,22 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                         } else {
                             acc_ovf += (double)w * (double)ev;
                         }
-                        ++slot;
+                        ++li;
                     }
                 }
             }
         }
     }   // iterations of one epoch
-    if (!use_cache) break;
-    if (wave_done && !counted) {
-        counted = true;
-        if (lane == 0) atomicAdd(waves_done, 1u);
+    // epoch end: every wave reports its alive lanes (pending events
+    // included) and whether it found the work list exhausted
+    {
+        const int n_alive = __popcll(__ballot(alive));
+        if (lane == 0) {
+            if (n_alive > 0) atomicAdd(wg_busy, (uint32_t)n_alive);
+            if (exhausted) *prim_done = 1u;
+        }
     }
+    ++epoch;
     __syncthreads();
     // write the epoch's cached sums to the tally and clear the cache
     for (int i = threadIdx.x; i < n_slots; i += blockDim.x) {
@@ -953,9 +1057,21 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
             cval[i] = 0.0;
         }
     }
-    const bool all_done = *waves_done == blockDim.x / kWave;
+    // publish what the lanes queued this epoch (written before the barrier
+    // above); the workgroup is done when the work list is exhausted, no lane
+    // is alive and every published entry has been taken
+    if (threadIdx.x == 0) {
+        const uint32_t lcap = (uint32_t)L->loc_cap;
+        const uint32_t prod = min(*loc_produced, lcap);
+        *loc_avail = prod;
+        const bool done = *prim_done != 0u && *wg_busy == 0u && *loc_claimed >= prod;
+        const bool stop = !done && epoch >= kMaxEpochs;
+        if (stop) atomicAdd(&L->counters[kCtrAborted], 1ull);
+        *wg_done = (done || stop) ? 1u : 0u;
+        *wg_busy = 0u;
+    }
     __syncthreads();
-    if (all_done) break;
+    if (*wg_done) break;
     }   // epochs
 
     // -------------------------------------------------- flush the ledger
@@ -968,7 +1084,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
         }
         for (int i = threadIdx.x; i < kWgCounters * a.n_plans; i += blockDim.x) {
             const int pl = i / kWgCounters, f = i - kWgCounters * pl;
-            if (wg_cnt[i] != 0ull) atomicAdd(&L->counters[8 * pl + f], wg_cnt[i]);
+            if (wg_cnt[i] != 0ull) atomicAdd(&L->counters[kPlanCounters * pl + f], wg_cnt[i]);
         }
     } else {
         for (int o = 32; o > 0; o >>= 1) {
@@ -982,6 +1098,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
             n_dep += __shfl_xor(n_dep, o);
             n_glob += __shfl_xor(n_glob, o);
             n_flush += __shfl_xor(n_flush, o);
+            n_locq += __shfl_xor(n_locq, o);
         }
         if (lane == 0) flush(0);
     }

@@ -38,7 +38,8 @@ class pmc_params(C.Structure):
                 ("block_threads", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("refill_lanes", C.c_int32), ("batch_events", C.c_int32),
                 ("tally_cache", C.c_int32), ("epoch_steps", C.c_int32),
-                ("cache_probes", C.c_int32), ("claim_run_log2", C.c_int32)]
+                ("cache_probes", C.c_int32), ("claim_run_log2", C.c_int32),
+                ("local_queue", C.c_int32)]
 
 
 class pmc_spot(C.Structure):

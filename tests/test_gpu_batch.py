@@ -71,6 +71,30 @@ def test_batched_equals_unbatched():
         assert ledger_residual(sums[p]) < 1e-9
 
 
+def test_batched_workgroup_queues_preserve_results():
+    """In a batch, secondaries carry their plan through the workgroups' own
+    queues: per-plan doses and counts equal the run with the queues off."""
+    _say("case: batched workgroup queues")
+    nd, mt = synth.nuclear_data(), synth.material_table()
+    plans = synth.plan_set(n_plans=3, seed=201, hist_scale=0.02, max_grid=(80, 80, 120),
+                           min_grid=(40, 40, 60))
+    fixed = dict(block_threads=1024, refill_lanes=8, batch_events=4)
+    res = []
+    for params in (dict(fixed, local_queue=-1), dict(fixed), dict(fixed, local_queue=8)):
+        e, ids = _batch_engine(nd, mt, plans, **params)
+        res.append(_run_batch(e, ids, plans, 21))
+        e.close()
+    (out0, sums0) = res[0]
+    for out, sums in res[1:]:
+        for p in range(len(plans)):
+            d0 = out0[p][0]
+            np.testing.assert_allclose(out[p][0], d0, rtol=1e-9, atol=1e-9 * d0.max())
+            np.testing.assert_allclose(out[p][1], out0[p][1], rtol=1e-6, atol=1e-9 * out0[p][1].max())
+            for key in ("steps", "n_elastic", "n_nonelastic", "tally_atomics"):
+                assert sums[p][key] == sums0[p][key], (p, key)
+            assert ledger_residual(sums[p]) < 1e-9
+
+
 def test_uneven_plan_batch_ledgers_and_oracle():
     """Sixteen plans of uneven size (grids 96^3..256x256x200, 200-3000 spots),
     histories scaled down; every ledger closes and plan 0 matches the oracle

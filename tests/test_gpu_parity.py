@@ -216,13 +216,15 @@ def test_argument_errors(nd, mt):
 def test_queue_overflow_is_reported_and_ledger_closes(nd, mt):
     _say("case: overflow")
     hu = synth.water_phantom(32, 32, 170)
-    e = _engine(nd, mt, hu, queue_capacity=8)
+    # the generation queue's overflow: workgroup queues off, so that every
+    # secondary goes through it
+    e = _engine(nd, mt, hu, queue_capacity=8, local_queue=-1)
     with pytest.raises(pmc.PMCError) as ei:
         e.run_spots(synth.pencil_spot(3.2, 3.2, 230.0, 0.3), 20000, 1)
     assert ei.value.status == pmc.PMC_ERR_QUEUE_OVERFLOW
     s = pmc.summary_dict(pmc.pmc_summary())
     e.close()
-    e = _engine(nd, mt, hu, queue_capacity=8)
+    e = _engine(nd, mt, hu, queue_capacity=8, local_queue=4)
     dose = np.zeros(hu.shape)
     var = np.zeros(hu.shape)
     summ = pmc.pmc_summary()
@@ -251,6 +253,34 @@ def test_launch_shape_does_not_change_results(nd, mt):
         np.testing.assert_allclose(d, ref[0], rtol=1e-9, atol=1e-9 * ref[0].max())
         for k in ("steps", "n_elastic", "n_nonelastic", "secondaries"):
             assert s[k] == ref[1][k], (k, params)
+
+
+def test_workgroup_queues_preserve_results(nd, mt):
+    """Secondaries a workgroup takes from its own queue within the launch give
+    the dose, variance and counts of the generation-by-generation schedule
+    (queues off); a 4-entry queue sends most of them on to the generation
+    queue, mixing both paths; the ledger closes in every case."""
+    _say("case: workgroup queues")
+    cfg = synth.config_ct_spots(150.0, 30_000)
+    runs = []
+    fixed = dict(refill_lanes=8, batch_events=4)   # no autotuning
+    for params in (dict(fixed, block_threads=1024, local_queue=-1), dict(fixed, block_threads=1024),
+                   dict(fixed, block_threads=1024, local_queue=4),
+                   dict(fixed, block_threads=256, local_queue=64, epoch_steps=5)):
+        e = _engine(nd, mt, cfg["hu"], **params)
+        d, v, s = e.run_spots(cfg["spots"], cfg["n_histories"], 8)
+        e.close()
+        _say("  %s: generations %d secondaries %d" % (params, s["generations"], s["secondaries"]))
+        runs.append((params, d, v, s))
+    p0, d0, v0, s0 = runs[0]
+    assert s0["secondaries"] > 100 and s0["generations"] >= 3
+    assert runs[1][3]["generations"] <= 2        # everything inside the first launch
+    for params, d, v, s in runs[1:]:
+        np.testing.assert_allclose(d, d0, rtol=1e-9, atol=1e-9 * d0.max())
+        np.testing.assert_allclose(v, v0, rtol=1e-6, atol=1e-9 * v0.max())
+        for k in ("steps", "n_elastic", "n_nonelastic", "secondaries", "tally_atomics", "n_overflow"):
+            assert s[k] == s0[k], (k, params)
+        assert ledger_residual(s) < 1e-9
 
 
 def test_deposit_cache_preserves_results(nd, mt):
