@@ -32,8 +32,8 @@ HBM_PEAK = 8.0e12
 # HBM bytes per transport launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
 # scaled by a plain-copy calibration, valid only for the kernel source whose
 # sha256 is recorded (see profiles/); None once the kernel has changed.
-TRAFFIC = {"transport_sha256": "7dcb5cd450d8ace6bb0ff62f8771c62e620ca12f18c53d104ede64a68d13c636",
-           "bytes_per_launch": 2.113e9}
+TRAFFIC = {"transport_sha256": "0cbdaef28efb6050215f0942ca589e7ab936ca52eb5825b252cb34ed3c9b1183",
+           "bytes_per_launch": 6.379e9}
 
 
 def _kernel_sha():

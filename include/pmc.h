@@ -82,7 +82,7 @@ typedef struct {
                                 0 = 10 */
     int32_t local_queue;     /* secondary protons a workgroup queues for its own lanes within a
                                 launch (entries of 48 B per workgroup), 1..65536; 0 = up to
-                                16384 within 256 MiB for the grid;
+                                65536 within 1 GiB for the grid;
                                 -1 = off (every secondary waits for the next generation launch) */
 } pmc_params;
 /* Autotuning: when any of block_threads, refill_lanes, batch_events is 0 and

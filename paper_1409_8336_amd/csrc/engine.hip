@@ -513,11 +513,12 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
     HIPCHK(launch_zero(c->d_wgc.p, (size_t)kMaxGenerations * grid * 8, st), "zero claim counters");
     a.wg_claims = c->d_wgc.p;
     // per-workgroup secondary queues (48-byte entries); automatic: up to
-    // 16384 entries per workgroup within 256 MiB for the whole grid
+    // 65536 entries per workgroup within 1 GiB for the whole grid (a
+    // workgroup of the 16-plan batch emits about 40000 secondaries)
     a.loc_cap = c->p.local_queue < 0
                     ? 0
                     : (c->p.local_queue ? c->p.local_queue
-                                        : (int)std::min<long>(16384L, (256L << 20) / (48L * grid)));
+                                        : (int)std::min<long>(65536L, (1L << 30) / (48L * grid)));
     if (a.loc_cap > 0) {
         HIPCHK(c->d_qloc.ensure((size_t)grid * (size_t)a.loc_cap * kLocEntryWords), "alloc workgroup queues");
         a.q_loc = c->d_qloc.p;
