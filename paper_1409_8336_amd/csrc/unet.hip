@@ -15,6 +15,9 @@
 namespace pmc {
 hipError_t nn_conv3d_fwd(const uint16_t* in, const uint16_t* wt, const float* bias, uint16_t* out, int N,
                          int D, int H, int W, int Cin, int Cout, int Kp, int relu, hipStream_t s);
+hipError_t nn_conv3d_fwd_cat(const uint16_t* in, const uint16_t* coarse, int Cc, const uint16_t* wt,
+                             const float* bias, uint16_t* out, int N, int D, int H, int W, int Cin, int Cout,
+                             int Kp, int relu, hipStream_t s);
 hipError_t nn_flip_weights(const uint16_t* w, uint16_t* wf, int Cin, int Cout, int Kp, int Kpf, hipStream_t s);
 hipError_t nn_conv3d_wgrad(const uint16_t* in, const uint16_t* dout, float* dw, int N, int D, int H, int W,
                            int Cin, int Cout, int Kp, hipStream_t s);
@@ -122,6 +125,22 @@ hipError_t conv_fwd(pmc_unet* u, const Conv& c, const Act& in, Act& out, int lev
                          u->W >> level, c.cin, c.cout, c.kp, 1, s);
 }
 
+// a decoder convolution whose input is [upsampled coarse, skip]: either from
+// the concatenation, formed first (training keeps it for the weight
+// gradient), or read from both sources by the convolution itself
+hipError_t dec_fwd(pmc_unet* u, const Conv& c, const Act& coarse, const Act& skip, Act& cat, Act& out, int level,
+                   bool keep_cat, hipStream_t s)
+{
+    const int d = u->D >> level, h = u->H >> level, w = u->W >> level;
+    if (keep_cat) {
+        hipError_t e = nn_up_concat(coarse.p, skip.p, cat.p, u->N, d, h, w, coarse.c, skip.c, s);
+        if (e != hipSuccess) return e;
+        return conv_fwd(u, c, cat, out, level, s);
+    }
+    return nn_conv3d_fwd_cat(skip.p, coarse.p, coarse.c, u->wbf + c.off_wbf, u->p + c.off_b, out.p, u->N, d, h, w,
+                             c.cin, c.cout, c.kp, 1, s);
+}
+
 // backward of one conv + ReLU layer: dy (gradient at the ReLU output, made
 // the pre-activation gradient in place), its input x and output y; writes
 // the input gradient dx unless dx is NULL
@@ -139,7 +158,8 @@ hipError_t conv_bwd(pmc_unet* u, const Conv& c, const Act& x, const Act& y, Act&
     return nn_conv3d_fwd(dy.p, u->wf + c.off_wf, nullptr, dx->p, u->N, d, h, w, c.cout, c.cin, c.kpf, 0, s);
 }
 
-hipError_t forward(pmc_unet* u, const float* dose, const float* rho, hipStream_t s)
+// train: keep what the backward pass reads; out: the head's output
+hipError_t forward(pmc_unet* u, const float* dose, const float* rho, bool train, float* out, hipStream_t s)
 {
     hipError_t e;
     const size_t nv = u->x.nvox;
@@ -153,13 +173,10 @@ hipError_t forward(pmc_unet* u, const float* dose, const float* rho, hipStream_t
     if ((e = conv_fwd(u, u->conv[2], u->p2, u->e3, 2, s)) != hipSuccess) return e;
     if ((e = nn_pool_fwd(u->e3.p, u->p3.p, N, D >> 2, H >> 2, W >> 2, 64, s)) != hipSuccess) return e;
     if ((e = conv_fwd(u, u->conv[3], u->p3, u->e4, 3, s)) != hipSuccess) return e;
-    if ((e = nn_up_concat(u->e4.p, u->e3.p, u->c3.p, N, D >> 2, H >> 2, W >> 2, 128, 64, s)) != hipSuccess) return e;
-    if ((e = conv_fwd(u, u->conv[4], u->c3, u->d3, 2, s)) != hipSuccess) return e;
-    if ((e = nn_up_concat(u->d3.p, u->e2.p, u->c2.p, N, D >> 1, H >> 1, W >> 1, 64, 32, s)) != hipSuccess) return e;
-    if ((e = conv_fwd(u, u->conv[5], u->c2, u->d2, 1, s)) != hipSuccess) return e;
-    if ((e = nn_up_concat(u->d2.p, u->e1.p, u->c1.p, N, D, H, W, 32, 16, s)) != hipSuccess) return e;
-    if ((e = conv_fwd(u, u->conv[6], u->c1, u->d1, 0, s)) != hipSuccess) return e;
-    return nn_head_fwd(u->d1.p, u->p + u->off_hw, u->p + u->off_hb, dose, u->scale, u->out, nv, 16, s);
+    if ((e = dec_fwd(u, u->conv[4], u->e4, u->e3, u->c3, u->d3, 2, train, s)) != hipSuccess) return e;
+    if ((e = dec_fwd(u, u->conv[5], u->d3, u->e2, u->c2, u->d2, 1, train, s)) != hipSuccess) return e;
+    if ((e = dec_fwd(u, u->conv[6], u->d2, u->e1, u->c1, u->d1, 0, train, s)) != hipSuccess) return e;
+    return nn_head_fwd(u->d1.p, u->p + u->off_hw, u->p + u->off_hb, dose, u->scale, out, nv, 16, s);
 }
 
 hipError_t backward(pmc_unet* u, const float* dose, const float* target, hipStream_t s)
@@ -378,8 +395,7 @@ pmc_status pmc_unet_forward(pmc_unet* u, const float* dose, const float* rho, fl
     if (!dose || !rho || !d_out) return ufail(u, PMC_ERR_ARG, "NULL tensor");
     UCHK(hipSetDevice(u->device), "set device");
     hipStream_t s = (hipStream_t)stream;
-    UCHK(forward(u, dose, rho, s), "forward");
-    UCHK(hipMemcpyAsync(d_out, u->out, u->x.nvox * 4, hipMemcpyDeviceToDevice, s), "copy output");
+    UCHK(forward(u, dose, rho, false, d_out, s), "forward");
     return PMC_OK;
 }
 
@@ -390,7 +406,7 @@ pmc_status pmc_unet_backward(pmc_unet* u, const float* dose, const float* rho, c
     if (!dose || !rho || !target) return ufail(u, PMC_ERR_ARG, "NULL tensor");
     UCHK(hipSetDevice(u->device), "set device");
     hipStream_t s = (hipStream_t)stream;
-    UCHK(forward(u, dose, rho, s), "forward");
+    UCHK(forward(u, dose, rho, true, u->out, s), "forward");
     UCHK(backward(u, dose, target, s), "backward");
     if (loss_out) {
         UCHK(hipMemcpyAsync(loss_out, u->loss, 8, hipMemcpyDeviceToHost, s), "read loss");

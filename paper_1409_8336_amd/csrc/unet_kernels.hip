@@ -16,6 +16,9 @@ namespace pmc {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+#define GLOBAL __attribute__((address_space(1)))
+#define LOCAL __attribute__((address_space(3)))
 
 #define DEV __device__ __forceinline__
 
@@ -34,52 +37,93 @@ DEV uint16_t f2bf(float f)
 
 // ------------------------------------------------------------ convolution
 
-// Forward convolution, LDS-staged.  A workgroup computes a 64 (x) x 2 (y) x
-// 2 (z) block of output voxels for 16*NB output channels; wave w owns the
-// 64-voxel row (y0 + (w & 1), z0 + (w >> 1)) as four 16-voxel M tiles.
-// The input is consumed 8 channels at a time: the block's halo (66 x 4 x 4
-// voxels x 8 channels, 16 bytes per voxel) is staged in LDS once and read
-// by all 27 taps.  K order inside a chunk: 4 taps x 8 channels per MFMA
-// K-step (lane group g takes tap 4*s + g), i.e. weight column
-// tap*Cin + 8*c + e; tap 27 (the padding to 28 = 7 x 4) contributes zero.
-constexpr int kCfX = 64, kCfHx = kCfX + 2;          // block width, halo width
-template <int NB>
+// Forward convolution, pipelined through LDS.  A workgroup computes a
+// 64 (x) x TY (y) x TZ (z) block of output voxels (TY x TZ = 4R rows; wave w
+// owns rows wR .. wR+R-1, each as four 16-voxel M tiles) for 16*NB output
+// channels.  The input is consumed 8 channels (one 16-byte voxel entry) at a
+// time: the block's halo (66 x (TY+2) x (TZ+2) entries) and the chunk's
+// weights (28 taps x 16*NB output channels, tap 27 the zero padding of K to
+// 7 x 32) are copied straight from global memory into LDS
+// (global_load_lds_dwordx4, out-of-range voxels from a zero page), into one of
+// two buffers while the MFMAs read the other, so every operand comes from
+// LDS and the copies of chunk c+1 overlap the arithmetic of chunk c (kPipe;
+// a one-chunk input uses a single buffer).  K order inside a chunk: 4 taps x
+// 8 channels per MFMA K-step (lane group g takes tap 4*s + g), i.e. weight
+// column tap*Cin + 8*c + e.  With a coarse source (Cc > 0) the input is the
+// decoder's concatenation [nearest upsampling of coarse (Cc channels, half
+// resolution), in (Cin - Cc channels)], read from both without forming it.
+__device__ const u32x4 kZero16[4] = {};
+
+template <int NB, int R>
+struct FwdTile {
+    static constexpr int TY = R >= 2 ? 4 : 2, TZ = R >= 4 ? 4 : 2;
+    static constexpr int HX = 66, HY = TY + 2, HZ = TZ + 2;
+    static constexpr int NHALO = HX * HY * HZ;
+    static constexpr int NWT = 28 * 16 * NB;
+    static constexpr int NENT = (NHALO + NWT + 63) / 64 * 64;   // whole 64-entry blocks
+};
+
+template <int NB, int R, bool kPipe>
 __global__ void __launch_bounds__(256) conv3d_fwd_kernel(const uint16_t* __restrict__ in,
+                                                         const uint16_t* __restrict__ coarse, int Cc,
                                                          const uint16_t* __restrict__ wt,
                                                          const float* __restrict__ bias,
                                                          uint16_t* __restrict__ out, int D, int H,
                                                          int W, int Cin, int Cout, int Kp, int relu)
 {
-    __shared__ __attribute__((aligned(16))) uint4 halo[4][4][kCfHx];   // [z][y][x], 8 channels
+    using T = FwdTile<NB, R>;
+    // two distinct LDS objects, so that the compiler's wait for the copies
+    // into one is not placed before reads of the other
+    __shared__ __attribute__((aligned(16))) u32x4 buf0[T::NENT];
+    __shared__ __attribute__((aligned(16))) u32x4 buf1[kPipe ? T::NENT : 4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int m = lane & 15, g = lane >> 4;
-    const int n_yb = (H + 1) / 2;
+    const int n_yb = (H + T::TY - 1) / T::TY;
     const int yb = blockIdx.y % n_yb, cg = blockIdx.y / n_yb;
-    const int n_zb = (D + 1) / 2;
+    const int n_zb = (D + T::TZ - 1) / T::TZ;
     const int zb = blockIdx.z % n_zb, n = blockIdx.z / n_zb;
-    const int x0 = blockIdx.x * kCfX, y0 = 2 * yb, z0 = 2 * zb;
+    const int x0 = blockIdx.x * 64, y0 = T::TY * yb, z0 = T::TZ * zb;
     const int co0 = cg * 16 * NB;
-    const int wy = wave & 1, wz = wave >> 1;
     const size_t plane = (size_t)H * W;
     const size_t nbase = (size_t)n * D * plane;
-    f32x4 acc[4][NB];
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int j = 0; j < NB; ++j) acc[t][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
     const int n_chunks = Cin / 8;
-    for (int c = 0; c < n_chunks; ++c) {
-        __syncthreads();
-        for (int i = threadIdx.x; i < 4 * 4 * kCfHx; i += 256) {
-            const int hx = i % kCfHx, r = i / kCfHx;
-            const int hy = r & 3, hz = r >> 2;
-            const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
-            uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (x >= 0 && x < W && y >= 0 && y < H && z >= 0 && z < D)
-                v = *reinterpret_cast<const uint4*>(in + (nbase + (size_t)z * plane + (size_t)y * W + x) * Cin + 8 * c);
-            halo[hz][hy][hx] = v;
+    const int Cs = Cin - Cc;   // channels of `in`
+    const int Hc = H >> 1, Wc = W >> 1;
+    const size_t nbase_c = (size_t)n * (D >> 1) * Hc * Wc;
+    // copy chunk c (halo, then weights) into dst: 64-entry blocks dealt to
+    // the waves in turn, lane l of a block writing entry 64 * blk + l
+    auto issue = [&](int c, u32x4* dst) {
+        const bool from_coarse = 8 * c < Cc;
+        for (int blk = wave; blk < T::NENT / 64; blk += 4) {
+            const int e = blk * 64 + lane;
+            const GLOBAL void* src = (const GLOBAL void*)&kZero16[0];
+            if (e < T::NHALO) {
+                const int hx = e % T::HX, r2 = e / T::HX;
+                const int hy = r2 % T::HY, hz = r2 / T::HY;
+                const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
+                if (x >= 0 && x < W && y >= 0 && y < H && z >= 0 && z < D) {
+                    if (from_coarse)
+                        src = (const GLOBAL void*)(coarse + (nbase_c + ((size_t)(z >> 1) * Hc + (y >> 1)) * Wc +
+                                                             (x >> 1)) * Cc + 8 * c);
+                    else
+                        src = (const GLOBAL void*)(in + (nbase + (size_t)z * plane + (size_t)y * W + x) * Cs +
+                                                   (8 * c - Cc));
+                }
+            } else if (e < T::NHALO + T::NWT) {
+                const int q = e - T::NHALO, tap = q / (16 * NB), co = co0 + q % (16 * NB);
+                if (tap < 27 && co < Cout) src = (const GLOBAL void*)(wt + (size_t)co * Kp + tap * Cin + 8 * c);
+            }
+            __builtin_amdgcn_global_load_lds(src, (LOCAL void*)(dst + blk * 64), 16, 0, 0);
         }
-        __syncthreads();
+    };
+    f32x4 acc[R][4][NB];
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int j = 0; j < NB; ++j) acc[i][t][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    auto compute = [&](const u32x4* bf) {
 #pragma unroll
         for (int s = 0; s < 7; ++s) {
             const int tap = 4 * s + g;
@@ -87,42 +131,67 @@ __global__ void __launch_bounds__(256) conv3d_fwd_kernel(const uint16_t* __restr
             const int kz = tap / 9, ky = (tap / 3) % 3, kx = tap % 3;
             bf16x8 b[NB];
 #pragma unroll
-            for (int j = 0; j < NB; ++j) {
-                const int co = co0 + 16 * j + m;
-                b[j] = (bf16x8){};
-                if (real && co < Cout)
-                    b[j] = *reinterpret_cast<const bf16x8*>(wt + (size_t)co * Kp + tap * Cin + 8 * c);
-            }
+            for (int j = 0; j < NB; ++j) b[j] = __builtin_bit_cast(bf16x8, bf[T::NHALO + tap * 16 * NB + 16 * j + m]);
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                bf16x8 a = (bf16x8){};
-                if (real) {
-                    const uint4 q = halo[wz + kz][wy + ky][16 * t + m + kx];
-                    a = __builtin_bit_cast(bf16x8, q);
+            for (int i = 0; i < R; ++i) {
+                const int r = wave * R + i, ry = r % T::TY, rz = r / T::TY;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    // (for the padding tap the index stays inside the buffer;
+                    // the entry read is discarded)
+                    const u32x4 q = bf[((rz + kz) * T::HY + (ry + ky)) * T::HX + 16 * t + m + kx];
+                    const bf16x8 a = real ? __builtin_bit_cast(bf16x8, q) : (bf16x8){};
+#pragma unroll
+                    for (int j = 0; j < NB; ++j)
+                        acc[i][t][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], acc[i][t][j], 0, 0, 0);
                 }
-#pragma unroll
-                for (int j = 0; j < NB; ++j)
-                    acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], acc[t][j], 0, 0, 0);
             }
         }
+    };
+    // vmcnt(0), other counters untouched: this wave's copies have landed
+    constexpr int kWaitCopies = 0x0F70;
+    if constexpr (kPipe) {
+        issue(0, buf0);
+        for (int c = 0; c < n_chunks; c += 2) {
+            __builtin_amdgcn_s_waitcnt(kWaitCopies);
+            __syncthreads();   // chunk c in buf0 complete; buf1 no longer read
+            if (c + 1 < n_chunks) issue(c + 1, buf1);
+            compute(buf0);
+            if (c + 1 >= n_chunks) break;
+            __builtin_amdgcn_s_waitcnt(kWaitCopies);
+            __syncthreads();   // chunk c+1 in buf1 complete; buf0 no longer read
+            if (c + 2 < n_chunks) issue(c + 2, buf0);
+            compute(buf1);
+        }
+    } else {
+        for (int c = 0; c < n_chunks; ++c) {
+            if (c) __syncthreads();   // buf0 no longer read
+            issue(c, buf0);
+            __builtin_amdgcn_s_waitcnt(kWaitCopies);
+            __syncthreads();
+            compute(buf0);
+        }
     }
-    const int y = y0 + wy, z = z0 + wz;
-    if (y >= H || z >= D) return;
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
-        const int co = co0 + 16 * j + m;
-        if (co >= Cout) continue;
-        const float bv = bias ? bias[co] : 0.f;
+    for (int i = 0; i < R; ++i) {
+        const int r = wave * R + i, y = y0 + r % T::TY, z = z0 + r / T::TY;
+        if (y >= H || z >= D) continue;
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
+        for (int j = 0; j < NB; ++j) {
+            const int co = co0 + 16 * j + m;
+            if (co >= Cout) continue;
+            const float bv = bias ? bias[co] : 0.f;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int x = x0 + 16 * t + 4 * g + i;
-                if (x >= W) continue;
-                float v = acc[t][j][i] + bv;
-                if (relu) v = v > 0.f ? v : kLeak * v;
-                out[(nbase + (size_t)z * plane + (size_t)y * W + x) * Cout + co] = f2bf(v);
-            }
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int x = x0 + 16 * t + 4 * g + q;
+                    if (x >= W) continue;
+                    float v = acc[i][t][j][q] + bv;
+                    if (relu) v = v > 0.f ? v : kLeak * v;
+                    out[(nbase + (size_t)z * plane + (size_t)y * W + x) * Cout + co] = f2bf(v);
+                }
+        }
     }
 }
 
@@ -472,7 +541,19 @@ __global__ void head_fwd_kernel(const uint16_t* __restrict__ d1, const float* __
     const float sc = fmaxf(scale[0], 1e-30f);
     for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < nvox; v += (size_t)gridDim.x * blockDim.x) {
         float s = b[0];
-        for (int c = 0; c < C; ++c) s += w[c] * bf2f(d1[v * C + c]);
+        if (C == 16) {
+            // the voxel's 32-byte row in two 16-byte loads (same sum order)
+            const uint4* r = reinterpret_cast<const uint4*>(d1 + v * 16);
+            const uint4 q0 = r[0], q1 = r[1];
+            const uint32_t u[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                s += w[2 * k] * __uint_as_float(u[k] << 16);
+                s += w[2 * k + 1] * __uint_as_float(u[k] & 0xFFFF0000u);
+            }
+        } else {
+            for (int c = 0; c < C; ++c) s += w[c] * bf2f(d1[v * C + c]);
+        }
         out[v] = dose[v] + sc * s;
     }
 }
@@ -592,17 +673,41 @@ static unsigned grid_for(size_t n, unsigned block = 256, unsigned cap = 65536)
     return (unsigned)g;
 }
 
+hipError_t nn_conv3d_fwd_cat(const uint16_t* in, const uint16_t* coarse, int Cc, const uint16_t* wt,
+                             const float* bias, uint16_t* out, int N, int D, int H, int W, int Cin, int Cout,
+                             int Kp, int relu, hipStream_t s)
+{
+    // 16 output channels: tiles of 64 x 4 x 2 voxels (R = 2); more: 32
+    // channels per workgroup on 64 x 2 x 2 tiles (two double buffers leave
+    // room for two workgroups per CU); a one-chunk input (Cin = 8) single-
+    // buffered, three workgroups per CU
+    if (Cin % 8 || Cin < 8 || Kp < 27 * Cin || Cc % 8 || Cc < 0 || Cc >= Cin || (Cc && !coarse) ||
+        (Cc && (D % 2 || H % 2 || W % 2)))
+        return hipErrorInvalidValue;
+    const int n_zb1 = N * ((D + FwdTile<1, 2>::TZ - 1) / FwdTile<1, 2>::TZ);
+    if (Cout <= 16) {
+        using T = FwdTile<1, 2>;
+        dim3 grid((W + 63) / 64, (H + T::TY - 1) / T::TY, n_zb1);
+        if (Cin == 8)
+            hipLaunchKernelGGL((conv3d_fwd_kernel<1, 2, false>), grid, dim3(256), 0, s, in, coarse, Cc, wt, bias, out, D,
+                               H, W, Cin, Cout, Kp, relu);
+        else
+            hipLaunchKernelGGL((conv3d_fwd_kernel<1, 2, true>), grid, dim3(256), 0, s, in, coarse, Cc, wt, bias, out, D,
+                               H, W, Cin, Cout, Kp, relu);
+    } else {
+        using T = FwdTile<2, 1>;
+        const int cgroups = (Cout + 31) / 32;
+        dim3 grid((W + 63) / 64, ((H + T::TY - 1) / T::TY) * cgroups, N * ((D + T::TZ - 1) / T::TZ));
+        hipLaunchKernelGGL((conv3d_fwd_kernel<2, 1, true>), grid, dim3(256), 0, s, in, coarse, Cc, wt, bias, out, D, H,
+                           W, Cin, Cout, Kp, relu);
+    }
+    return hipGetLastError();
+}
+
 hipError_t nn_conv3d_fwd(const uint16_t* in, const uint16_t* wt, const float* bias, uint16_t* out, int N,
                          int D, int H, int W, int Cin, int Cout, int Kp, int relu, hipStream_t s)
 {
-    const int nb = Cout >= 64 ? 4 : (Cout >= 32 ? 2 : 1);
-    const int cgroups = (Cout + 16 * nb - 1) / (16 * nb);
-    if (Cin % 8 || Cin < 8 || Kp < 27 * Cin) return hipErrorInvalidValue;
-    dim3 grid((W + kCfX - 1) / kCfX, ((H + 1) / 2) * cgroups, N * ((D + 1) / 2));
-    if (nb == 4) hipLaunchKernelGGL(conv3d_fwd_kernel<4>, grid, dim3(256), 0, s, in, wt, bias, out, D, H, W, Cin, Cout, Kp, relu);
-    else if (nb == 2) hipLaunchKernelGGL(conv3d_fwd_kernel<2>, grid, dim3(256), 0, s, in, wt, bias, out, D, H, W, Cin, Cout, Kp, relu);
-    else hipLaunchKernelGGL(conv3d_fwd_kernel<1>, grid, dim3(256), 0, s, in, wt, bias, out, D, H, W, Cin, Cout, Kp, relu);
-    return hipGetLastError();
+    return nn_conv3d_fwd_cat(in, nullptr, 0, wt, bias, out, N, D, H, W, Cin, Cout, Kp, relu, s);
 }
 
 hipError_t nn_flip_weights(const uint16_t* w, uint16_t* wf, int Cin, int Cout, int Kp, int Kpf, hipStream_t s)
