@@ -71,9 +71,15 @@ pmc_status pmc_unet_backward(pmc_unet* u, const float* d_dose, const float* d_de
 pmc_status pmc_unet_get_grads(pmc_unet* u, float* host_out);
 pmc_status pmc_unet_zero_grads(pmc_unet* u, void* hip_stream);
 
+/* L2 norm of the accumulated gradient (all parameters), computed on the
+ * device in FP64 and returned to *norm_out (synchronises the stream). */
+pmc_status pmc_unet_grad_norm(pmc_unet* u, double* norm_out, void* hip_stream);
+
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with learning rate lr on
- * the accumulated gradients, which it then resets to zero. */
-pmc_status pmc_unet_adam_step(pmc_unet* u, float lr, void* hip_stream);
+ * grad_scale times the accumulated gradients (grad_scale in (0, 1]: the
+ * caller's gradient-norm clipping, 1 = plain Adam), which it then resets to
+ * zero. */
+pmc_status pmc_unet_adam_step(pmc_unet* u, float lr, float grad_scale, void* hip_stream);
 
 /* ---- single layers, for kernel tests (device pointers, BF16 as uint16) ----
  * x: [n][d][h][w][cin] channels-last; w: [cout][Kp] (see above); y:

@@ -222,8 +222,10 @@ class UNetOracle:
         l.backward()
         return float(l.detach()), p.grad.numpy().copy(), out.detach().numpy()
 
-    def adam_step(self, grad, m1, m2, step, lr, b1=0.9, b2=0.999, eps=1e-8):
-        """One Adam step on the held parameters; returns the new moments."""
+    def adam_step(self, grad, m1, m2, step, lr, b1=0.9, b2=0.999, eps=1e-8, grad_scale=1.0):
+        """One Adam step on grad_scale * grad (the caller's clipping factor)
+        for the held parameters; returns the new moments."""
+        grad = grad_scale * grad
         m1 = b1 * m1 + (1 - b1) * grad
         m2 = b2 * m2 + (1 - b2) * grad * grad
         mh = m1 / (1 - b1 ** step)

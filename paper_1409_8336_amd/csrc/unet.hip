@@ -37,7 +37,8 @@ hipError_t nn_loss_head_bwd(const float* out, const float* target, const float* 
                             unsigned int* region, const uint16_t* d1, const float* w, uint16_t* dd1, float* dw,
                             float* db, double* loss, size_t nvox, int C, hipStream_t s);
 hipError_t nn_adam(float* p, float* g, float* m1, float* m2, uint16_t* p_bf, size_t n, float lr, float b1, float b2,
-                   float eps, float c1, float c2, hipStream_t s);
+                   float eps, float c1, float c2, float gs, hipStream_t s);
+hipError_t nn_sqnorm(const float* g, size_t n, double* out, hipStream_t s);
 hipError_t nn_f32_to_bf16(const float* a, uint16_t* b, size_t n, hipStream_t s);
 }  // namespace pmc
 
@@ -80,6 +81,7 @@ struct pmc_unet {
     float* scale = nullptr;
     unsigned int* region = nullptr;   // voxels in the dose region (loss normalisation)
     double* loss = nullptr;
+    double* gnorm2 = nullptr;   // squared gradient norm (pmc_unet_grad_norm)
     std::vector<void*> allocs;
 };
 
@@ -310,6 +312,7 @@ pmc_status pmc_unet_create(pmc_unet** out, int device, int n, int d, int h, int 
     A(ualloc(u, &u->scale, 1));
     A(ualloc(u, &u->region, 1));
     A(ualloc(u, &u->loss, 1));
+    A(ualloc(u, &u->gnorm2, 1));
     // initial parameters
     std::vector<float> hp(u->n_params, 0.f);
     std::mt19937_64 rng(seed);
@@ -415,10 +418,26 @@ pmc_status pmc_unet_backward(pmc_unet* u, const float* dose, const float* rho, c
     return PMC_OK;
 }
 
-pmc_status pmc_unet_adam_step(pmc_unet* u, float lr, void* stream)
+pmc_status pmc_unet_grad_norm(pmc_unet* u, double* norm_out, void* stream)
+{
+    if (!u) return PMC_ERR_ARG;
+    if (!norm_out) return ufail(u, PMC_ERR_ARG, "NULL output");
+    UCHK(hipSetDevice(u->device), "set device");
+    hipStream_t s = (hipStream_t)stream;
+    UCHK(hipMemsetAsync(u->gnorm2, 0, sizeof(double), s), "zero norm");
+    UCHK(nn_sqnorm(u->g, u->n_params, u->gnorm2, s), "gradient norm");
+    double n2 = 0.0;
+    UCHK(hipMemcpyAsync(&n2, u->gnorm2, sizeof(double), hipMemcpyDeviceToHost, s), "read norm");
+    UCHK(hipStreamSynchronize(s), "gradient norm");
+    *norm_out = std::sqrt(n2);
+    return PMC_OK;
+}
+
+pmc_status pmc_unet_adam_step(pmc_unet* u, float lr, float grad_scale, void* stream)
 {
     if (!u) return PMC_ERR_ARG;
     if (!(lr > 0.f)) return ufail(u, PMC_ERR_ARG, "lr must be > 0");
+    if (!(grad_scale > 0.f) || !(grad_scale <= 1.f)) return ufail(u, PMC_ERR_ARG, "grad_scale must be in (0, 1]");
     UCHK(hipSetDevice(u->device), "set device");
     hipStream_t s = (hipStream_t)stream;
     u->step += 1;
@@ -428,12 +447,12 @@ pmc_status pmc_unet_adam_step(pmc_unet* u, float lr, void* stream)
         const Conv& c = u->conv[i];
         const size_t nw = (size_t)c.cout * c.kp;
         UCHK(nn_adam(u->p + c.off_w, u->g + c.off_w, u->m1 + c.off_w, u->m2 + c.off_w, u->wbf + c.off_wbf, nw, lr,
-                     b1, b2, eps, c1, c2, s), "adam");
+                     b1, b2, eps, c1, c2, grad_scale, s), "adam");
         UCHK(nn_adam(u->p + c.off_b, u->g + c.off_b, u->m1 + c.off_b, u->m2 + c.off_b, nullptr, c.cout, lr, b1, b2,
-                     eps, c1, c2, s), "adam");
+                     eps, c1, c2, grad_scale, s), "adam");
     }
     UCHK(nn_adam(u->p + u->off_hw, u->g + u->off_hw, u->m1 + u->off_hw, u->m2 + u->off_hw, nullptr, 17, lr, b1, b2,
-                 eps, c1, c2, s), "adam");
+                 eps, c1, c2, grad_scale, s), "adam");
     return PMC_OK;
 }
 

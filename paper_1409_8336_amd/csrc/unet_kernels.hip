@@ -634,12 +634,31 @@ __global__ void __launch_bounds__(256) loss_head_bwd_kernel(const float* __restr
 
 // Adam on FP32 master parameters; refreshes the BF16 copies of the
 // convolution weights (p_bf == NULL for parameters kept in FP32)
+// sum of squares of a float vector into *out (FP64; one atomic per block)
+__global__ void __launch_bounds__(256) sqnorm_kernel(const float* __restrict__ g, size_t n, double* out)
+{
+    __shared__ double part[4];
+    double acc = 0.0;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const double v = (double)g[i];
+        acc += v * v;
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double t = part[0] + part[1] + part[2] + part[3];
+        if (t != 0.0) unsafeAtomicAdd(out, t);
+    }
+}
+
+// Adam on gradient gs * g (gs: the caller's clipping factor, 1 = plain)
 __global__ void adam_kernel(float* __restrict__ p, float* __restrict__ g, float* __restrict__ m1,
                             float* __restrict__ m2, uint16_t* __restrict__ p_bf, size_t n, float lr,
-                            float b1, float b2, float eps, float c1, float c2)
+                            float b1, float b2, float eps, float c1, float c2, float gs)
 {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const float gi = g[i];
+        const float gi = gs * g[i];
         const float a = b1 * m1[i] + (1.f - b1) * gi;
         const float s = b2 * m2[i] + (1.f - b2) * gi * gi;
         m1[i] = a;
@@ -677,22 +696,23 @@ hipError_t nn_conv3d_fwd_cat(const uint16_t* in, const uint16_t* coarse, int Cc,
                              const float* bias, uint16_t* out, int N, int D, int H, int W, int Cin, int Cout,
                              int Kp, int relu, hipStream_t s)
 {
-    // 16 output channels: tiles of 64 x 4 x 2 voxels (R = 2); more: 32
-    // channels per workgroup on 64 x 2 x 2 tiles (two double buffers leave
-    // room for two workgroups per CU); a one-chunk input (Cin = 8) single-
-    // buffered, three workgroups per CU
+    // 64 x 2 x 2-voxel tiles; 16 output channels per workgroup (three
+    // workgroups per CU) or 32 (two per CU).  The copies in flight per CU set
+    // the pace (a 64 x 4 x 2 tile, fewer halo bytes per voxel but two
+    // workgroups per CU, was 4% slower at 160 x 128 x 128; 64 x 4 x 4, one
+    // workgroup per CU, 19% slower).  A one-chunk input (Cin = 8) is
+    // single-buffered.
     if (Cin % 8 || Cin < 8 || Kp < 27 * Cin || Cc % 8 || Cc < 0 || Cc >= Cin || (Cc && !coarse) ||
         (Cc && (D % 2 || H % 2 || W % 2)))
         return hipErrorInvalidValue;
-    const int n_zb1 = N * ((D + FwdTile<1, 2>::TZ - 1) / FwdTile<1, 2>::TZ);
     if (Cout <= 16) {
-        using T = FwdTile<1, 2>;
-        dim3 grid((W + 63) / 64, (H + T::TY - 1) / T::TY, n_zb1);
+        using T = FwdTile<1, 1>;
+        dim3 grid((W + 63) / 64, (H + T::TY - 1) / T::TY, N * ((D + T::TZ - 1) / T::TZ));
         if (Cin == 8)
-            hipLaunchKernelGGL((conv3d_fwd_kernel<1, 2, false>), grid, dim3(256), 0, s, in, coarse, Cc, wt, bias, out, D,
+            hipLaunchKernelGGL((conv3d_fwd_kernel<1, 1, false>), grid, dim3(256), 0, s, in, coarse, Cc, wt, bias, out, D,
                                H, W, Cin, Cout, Kp, relu);
         else
-            hipLaunchKernelGGL((conv3d_fwd_kernel<1, 2, true>), grid, dim3(256), 0, s, in, coarse, Cc, wt, bias, out, D,
+            hipLaunchKernelGGL((conv3d_fwd_kernel<1, 1, true>), grid, dim3(256), 0, s, in, coarse, Cc, wt, bias, out, D,
                                H, W, Cin, Cout, Kp, relu);
     } else {
         using T = FwdTile<2, 1>;
@@ -806,9 +826,16 @@ hipError_t nn_loss_head_bwd(const float* out, const float* target, const float* 
 }
 
 hipError_t nn_adam(float* p, float* g, float* m1, float* m2, uint16_t* p_bf, size_t n, float lr, float b1, float b2,
-                   float eps, float c1, float c2, hipStream_t s)
+                   float eps, float c1, float c2, float gs, hipStream_t s)
 {
-    hipLaunchKernelGGL(adam_kernel, dim3(grid_for(n)), dim3(256), 0, s, p, g, m1, m2, p_bf, n, lr, b1, b2, eps, c1, c2);
+    hipLaunchKernelGGL(adam_kernel, dim3(grid_for(n)), dim3(256), 0, s, p, g, m1, m2, p_bf, n, lr, b1, b2, eps, c1, c2,
+                       gs);
+    return hipGetLastError();
+}
+
+hipError_t nn_sqnorm(const float* g, size_t n, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(sqnorm_kernel, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, g, n, out);
     return hipGetLastError();
 }
 

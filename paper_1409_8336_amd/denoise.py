@@ -110,10 +110,13 @@ def build_dataset(sim, indices, n_low, n_high, log=_log):
 
 
 def train(net, data, rows, seconds, lr_max=5e-4, lr_min=1e-5, seed=0, max_steps=None, batch=4,
-          log=_log):
+          clip=3.0, log=_log):
     """Adam on the gradient summed over `batch` full volumes per step (the
     backward call adds into the gradient buffer), cosine learning-rate decay
-    over the time budget; returns [(step, elapsed_s, mean loss of the step)]."""
+    over the time budget; a step whose gradient norm exceeds `clip` times the
+    running mean of the norms (after 20 steps) is scaled down to that bound.
+    Returns [(step, elapsed_s, mean loss of the step)]; net.n_clipped counts
+    the clipped steps."""
     import torch
     rng = np.random.default_rng(seed)
     hist = []
@@ -121,6 +124,7 @@ def train(net, data, rows, seconds, lr_max=5e-4, lr_min=1e-5, seed=0, max_steps=
     step = 0
     last_log = t0
     order = []
+    ema, n_clipped = None, 0
     while True:
         el = time.perf_counter() - t0
         if el >= seconds or (max_steps is not None and step >= max_steps):
@@ -133,14 +137,22 @@ def train(net, data, rows, seconds, lr_max=5e-4, lr_min=1e-5, seed=0, max_steps=
                 order = list(rng.permutation(rows))
             r = order.pop()
             loss += net.backward(data["low"][r], data["rho"][r], data["high"][r]) / batch
-        net.adam_step(lr)
+        norm = net.grad_norm()
+        scale = 1.0
+        if clip and ema is not None and step >= 20 and norm > clip * ema:
+            scale = clip * ema / norm
+            n_clipped += 1
+        ema = norm if ema is None else 0.95 * ema + 0.05 * norm * scale
+        net.adam_step(lr, grad_scale=scale)
         step += 1
         hist.append((step, el, loss))
         if time.perf_counter() - last_log > 30:
             recent = np.mean([h[2] for h in hist[-100:]])
-            log("train step %d  %.0f s  lr %.2e  loss(avg 100) %.4e" % (step, el, lr, recent))
+            log("train step %d  %.0f s  lr %.2e  loss(avg 100) %.4e  grad norm (mean) %.3e  clipped %d"
+                % (step, el, lr, recent, ema, n_clipped))
             last_log = time.perf_counter()
     torch.cuda.synchronize()
+    net.n_clipped = n_clipped
     return hist
 
 
@@ -266,7 +278,7 @@ def main(argv=None):
     summ.update({"data_s": t_data, "train_steps": len(hist), "train_s": hist[-1][1],
                  "final_loss": float(np.mean([h[2] for h in hist[-100:]])), "n_low": a.n_low,
                  "n_high": a.n_high, "cases_total": a.cases, "train_cases": n_train, "batch": a.batch,
-                 "lr_max": a.lr})
+                 "lr_max": a.lr, "clipped_steps": net.n_clipped})
     _log("summary %s" % json.dumps(summ))
     if a.out:
         with open(a.out, "w") as f:

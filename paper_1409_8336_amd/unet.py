@@ -13,7 +13,7 @@ from . import pmc
 # every symbol include/pmc_unet.h declares
 EXPORTS = ("pmc_unet_create", "pmc_unet_destroy", "pmc_unet_last_error", "pmc_unet_param_count",
            "pmc_unet_get_params", "pmc_unet_set_params", "pmc_unet_forward", "pmc_unet_backward",
-           "pmc_unet_get_grads", "pmc_unet_zero_grads", "pmc_unet_adam_step",
+           "pmc_unet_get_grads", "pmc_unet_zero_grads", "pmc_unet_adam_step", "pmc_unet_grad_norm",
            "pmc_nn_conv3d_forward", "pmc_nn_conv3d_backward_data", "pmc_nn_conv3d_backward_weight",
            "pmc_gamma_index", "pmc_denoise_disagreement")
 
@@ -39,7 +39,8 @@ def lib():
         L.pmc_unet_backward.argtypes = [vp, vp, vp, vp, C.POINTER(C.c_double), vp]
         L.pmc_unet_get_grads.argtypes = [vp, vp]
         L.pmc_unet_zero_grads.argtypes = [vp, vp]
-        L.pmc_unet_adam_step.argtypes = [vp, f32, vp]
+        L.pmc_unet_adam_step.argtypes = [vp, f32, f32, vp]
+        L.pmc_unet_grad_norm.argtypes = [vp, C.POINTER(C.c_double), vp]
         L.pmc_nn_conv3d_forward.argtypes = [vp, vp, vp, vp, i32, i32, i32, i32, i32, i32, i32, vp]
         L.pmc_nn_conv3d_backward_data.argtypes = [vp, vp, vp, i32, i32, i32, i32, i32, i32, vp]
         L.pmc_nn_conv3d_backward_weight.argtypes = [vp, vp, vp, i32, i32, i32, i32, i32, i32, vp]
@@ -141,8 +142,14 @@ def pmc_unet_backward(u, dose, density, target, stream=None) -> float:
     return loss.value
 
 
-def pmc_unet_adam_step(u, lr, stream=None):
-    _check(u, lib().pmc_unet_adam_step(u, float(lr), _stream(stream)))
+def pmc_unet_adam_step(u, lr, grad_scale=1.0, stream=None):
+    _check(u, lib().pmc_unet_adam_step(u, float(lr), float(grad_scale), _stream(stream)))
+
+
+def pmc_unet_grad_norm(u, stream=None):
+    out = C.c_double(0.0)
+    _check(u, lib().pmc_unet_grad_norm(u, C.byref(out), _stream(stream)))
+    return out.value
 
 
 def _bf16(t, name):
@@ -257,5 +264,8 @@ class UNet:
     def backward(self, dose, density, target, stream=None):
         return pmc_unet_backward(self.u, dose, density, target, stream)
 
-    def adam_step(self, lr, stream=None):
-        pmc_unet_adam_step(self.u, lr, stream)
+    def adam_step(self, lr, grad_scale=1.0, stream=None):
+        pmc_unet_adam_step(self.u, lr, grad_scale, stream)
+
+    def grad_norm(self, stream=None):
+        return pmc_unet_grad_norm(self.u, stream)

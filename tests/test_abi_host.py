@@ -67,7 +67,8 @@ def test_denoiser_and_gamma_reject_bad_arguments(lib):
         assert L.pmc_unet_create(C.byref(u), 0, *shape, 0) == pmc.PMC_ERR_ARG
     assert L.pmc_unet_destroy(None) == pmc.PMC_OK
     assert L.pmc_unet_forward(None, None, None, None, None) == pmc.PMC_ERR_ARG
-    assert L.pmc_unet_adam_step(None, 1e-3, None) == pmc.PMC_ERR_ARG
+    assert L.pmc_unet_adam_step(None, 1e-3, 1.0, None) == pmc.PMC_ERR_ARG
+    assert L.pmc_unet_grad_norm(None, None, None) == pmc.PMC_ERR_ARG
     # channel counts must be multiples of 8
     assert L.pmc_nn_conv3d_forward(None, None, None, None, 1, 8, 8, 8, 8, 16, 0, None) == pmc.PMC_ERR_ARG
     one = C.c_void_p(1)

@@ -257,6 +257,41 @@ def test_adam_step_and_bf16_refresh():
     fresh.close()
 
 
+def test_grad_norm_and_scaled_adam():
+    """The device gradient norm equals the norm of the gradient read back,
+    and two Adam steps on scaled gradients (the clipping factor) match the
+    oracle's two steps on the same gradients and factors."""
+    import torch
+    _say("case: gradient norm and scaled adam")
+    U = _unet()
+    shape = (1, 8, 8, 16)
+    rng = np.random.default_rng(37)
+    net = U.UNet(shape, seed=5)
+    p0 = _net_params(net.u, 6)
+    net.set_params(p0)
+    dose, rho, target = _net_inputs(rng, shape)
+    td, tr, tt = (torch.from_numpy(a).cuda() for a in (dose, rho, target))
+    orc = D.UNetOracle(p0.astype(np.float64))
+    m1 = m2 = None
+    lr = 1e-3
+    for step, scale in ((1, 0.25), (2, 1.0)):
+        net.backward(td, tr, tt)
+        g = net.grads().astype(np.float64)
+        norm = net.grad_norm()
+        assert abs(norm - np.linalg.norm(g)) <= 1e-6 * np.linalg.norm(g)
+        net.adam_step(lr, grad_scale=scale)
+        if m1 is None:
+            m1, m2 = np.zeros_like(g), np.zeros_like(g)
+        m1, m2 = orc.adam_step(g, m1, m2, step, lr, grad_scale=scale)
+    torch.cuda.synchronize()
+    p2 = net.params().astype(np.float64)
+    # the second step's gradients come from the GPU's own (FP32) first-step
+    # parameters, which the oracle shares through g: compare the update
+    dev = np.abs(p2 - orc.params)
+    assert np.all(dev <= 1e-5 * lr + 2.0 ** -22 * np.abs(orc.params)), float(dev.max())
+    net.close()
+
+
 def test_training_reduces_loss():
     import torch
     _say("case: training loop")
