@@ -91,27 +91,45 @@ __global__ void __launch_bounds__(256) conv3d_fwd_kernel(const uint16_t* __restr
     const int Hc = H >> 1, Wc = W >> 1;
     const size_t nbase_c = (size_t)n * (D >> 1) * Hc * Wc;
     // copy chunk c (halo, then weights) into dst: 64-entry blocks dealt to
-    // the waves in turn, lane l of a block writing entry 64 * blk + l
+    // the waves in turn, lane l of a block writing entry 64 * blk + l.  The
+    // element offsets of a lane's entries do not depend on the chunk (which
+    // only adds 8 c): computed once, -1 for the zero page.
+    constexpr int kBlk = T::NENT / 64, kPer = (kBlk + 3) / 4;
+    int off_in[kPer], off_co[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int e = (wave + 4 * q) * 64 + lane;
+        off_in[q] = -1;
+        off_co[q] = -1;
+        if (e < T::NHALO) {
+            const int hx = e % T::HX, r2 = e / T::HX;
+            const int hy = r2 % T::HY, hz = r2 / T::HY;
+            const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
+            if (x >= 0 && x < W && y >= 0 && y < H && z >= 0 && z < D) {
+                off_in[q] = (int)((nbase + (size_t)z * plane + (size_t)y * W + x) * Cs);
+                if (Cc) off_co[q] = (int)((nbase_c + ((size_t)(z >> 1) * Hc + (y >> 1)) * Wc + (x >> 1)) * Cc);
+            }
+        } else if (e < T::NHALO + T::NWT) {
+            const int qq = e - T::NHALO, tap = qq / (16 * NB), co = co0 + qq % (16 * NB);
+            if (tap < 27 && co < Cout) off_in[q] = co * Kp + tap * Cin;
+        }
+    }
     auto issue = [&](int c, u32x4* dst) {
         const bool from_coarse = 8 * c < Cc;
-        for (int blk = wave; blk < T::NENT / 64; blk += 4) {
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int blk = wave + 4 * q;
+            if (kBlk % 4 != 0 && blk >= kBlk) break;
             const int e = blk * 64 + lane;
             const GLOBAL void* src = (const GLOBAL void*)&kZero16[0];
             if (e < T::NHALO) {
-                const int hx = e % T::HX, r2 = e / T::HX;
-                const int hy = r2 % T::HY, hz = r2 / T::HY;
-                const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
-                if (x >= 0 && x < W && y >= 0 && y < H && z >= 0 && z < D) {
-                    if (from_coarse)
-                        src = (const GLOBAL void*)(coarse + (nbase_c + ((size_t)(z >> 1) * Hc + (y >> 1)) * Wc +
-                                                             (x >> 1)) * Cc + 8 * c);
-                    else
-                        src = (const GLOBAL void*)(in + (nbase + (size_t)z * plane + (size_t)y * W + x) * Cs +
-                                                   (8 * c - Cc));
+                if (from_coarse) {
+                    if (off_co[q] >= 0) src = (const GLOBAL void*)(coarse + off_co[q] + 8 * c);
+                } else if (off_in[q] >= 0) {
+                    src = (const GLOBAL void*)(in + off_in[q] + (8 * c - Cc));
                 }
-            } else if (e < T::NHALO + T::NWT) {
-                const int q = e - T::NHALO, tap = q / (16 * NB), co = co0 + q % (16 * NB);
-                if (tap < 27 && co < Cout) src = (const GLOBAL void*)(wt + (size_t)co * Kp + tap * Cin + 8 * c);
+            } else if (off_in[q] >= 0) {
+                src = (const GLOBAL void*)(wt + off_in[q] + 8 * c);
             }
             __builtin_amdgcn_global_load_lds(src, (LOCAL void*)(dst + blk * 64), 16, 0, 0);
         }
@@ -704,6 +722,9 @@ hipError_t nn_conv3d_fwd_cat(const uint16_t* in, const uint16_t* coarse, int Cc,
     // single-buffered.
     if (Cin % 8 || Cin < 8 || Kp < 27 * Cin || Cc % 8 || Cc < 0 || Cc >= Cin || (Cc && !coarse) ||
         (Cc && (D % 2 || H % 2 || W % 2)))
+        return hipErrorInvalidValue;
+    // the kernel keeps element offsets in 32 bits
+    if ((size_t)N * D * H * W * (size_t)Cin >= (size_t)0x7FFFFFFF || (size_t)Cout * Kp >= (size_t)0x7FFFFFFF)
         return hipErrorInvalidValue;
     if (Cout <= 16) {
         using T = FwdTile<1, 1>;
