@@ -54,16 +54,20 @@ DEV uint16_t f2bf(float f)
 // resolution), in (Cin - Cc channels)], read from both without forming it.
 __device__ const u32x4 kZero16[4] = {};
 
-template <int NB, int R>
+// TX: tile width in x (64, 32 or 16; a 64-voxel row of a wave covers TX
+// voxels in x and 64 / TX in y, so narrow levels waste no lanes)
+template <int NB, int R, int TX>
 struct FwdTile {
-    static constexpr int TY = R >= 2 ? 4 : 2, TZ = R >= 4 ? 4 : 2;
-    static constexpr int HX = 66, HY = TY + 2, HZ = TZ + 2;
+    static constexpr int XT = TX / 16, YR = 4 / XT;          // M tiles per row in x; y values per row
+    static constexpr int RY = R >= 2 ? 4 : 2, RZ = R >= 4 ? 4 : 2;   // rows in y, in z
+    static constexpr int TY = RY * YR, TZ = RZ;
+    static constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
     static constexpr int NHALO = HX * HY * HZ;
     static constexpr int NWT = 28 * 16 * NB;
     static constexpr int NENT = (NHALO + NWT + 63) / 64 * 64;   // whole 64-entry blocks
 };
 
-template <int NB, int R, bool kPipe>
+template <int NB, int R, int TX, bool kPipe>
 __global__ void __launch_bounds__(256) conv3d_fwd_kernel(const uint16_t* __restrict__ in,
                                                          const uint16_t* __restrict__ coarse, int Cc,
                                                          const uint16_t* __restrict__ wt,
@@ -71,7 +75,7 @@ __global__ void __launch_bounds__(256) conv3d_fwd_kernel(const uint16_t* __restr
                                                          uint16_t* __restrict__ out, int D, int H,
                                                          int W, int Cin, int Cout, int Kp, int relu)
 {
-    using T = FwdTile<NB, R>;
+    using T = FwdTile<NB, R, TX>;
     // two distinct LDS objects, so that the compiler's wait for the copies
     // into one is not placed before reads of the other
     __shared__ __attribute__((aligned(16))) u32x4 buf0[T::NENT];
@@ -82,7 +86,7 @@ __global__ void __launch_bounds__(256) conv3d_fwd_kernel(const uint16_t* __restr
     const int yb = blockIdx.y % n_yb, cg = blockIdx.y / n_yb;
     const int n_zb = (D + T::TZ - 1) / T::TZ;
     const int zb = blockIdx.z % n_zb, n = blockIdx.z / n_zb;
-    const int x0 = blockIdx.x * 64, y0 = T::TY * yb, z0 = T::TZ * zb;
+    const int x0 = blockIdx.x * TX, y0 = T::TY * yb, z0 = T::TZ * zb;
     const int co0 = cg * 16 * NB;
     const size_t plane = (size_t)H * W;
     const size_t nbase = (size_t)n * D * plane;
@@ -152,12 +156,13 @@ __global__ void __launch_bounds__(256) conv3d_fwd_kernel(const uint16_t* __restr
             for (int j = 0; j < NB; ++j) b[j] = __builtin_bit_cast(bf16x8, bf[T::NHALO + tap * 16 * NB + 16 * j + m]);
 #pragma unroll
             for (int i = 0; i < R; ++i) {
-                const int r = wave * R + i, ry = r % T::TY, rz = r / T::TY;
+                const int r = wave * R + i, ry = r % T::RY, rz = r / T::RY;
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
+                    const int xl = 16 * (t % T::XT), yl = ry * T::YR + t / T::XT;
                     // (for the padding tap the index stays inside the buffer;
                     // the entry read is discarded)
-                    const u32x4 q = bf[((rz + kz) * T::HY + (ry + ky)) * T::HX + 16 * t + m + kx];
+                    const u32x4 q = bf[((rz + kz) * T::HY + (yl + ky)) * T::HX + xl + m + kx];
                     const bf16x8 a = real ? __builtin_bit_cast(bf16x8, q) : (bf16x8){};
 #pragma unroll
                     for (int j = 0; j < NB; ++j)
@@ -192,23 +197,26 @@ __global__ void __launch_bounds__(256) conv3d_fwd_kernel(const uint16_t* __restr
     }
 #pragma unroll
     for (int i = 0; i < R; ++i) {
-        const int r = wave * R + i, y = y0 + r % T::TY, z = z0 + r / T::TY;
-        if (y >= H || z >= D) continue;
+        const int r = wave * R + i, ry = r % T::RY, z = z0 + r / T::RY;
+        if (z >= D) continue;
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
             const int co = co0 + 16 * j + m;
             if (co >= Cout) continue;
             const float bv = bias ? bias[co] : 0.f;
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
+            for (int t = 0; t < 4; ++t) {
+                const int y = y0 + ry * T::YR + t / T::XT;
+                if (y >= H) continue;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const int x = x0 + 16 * t + 4 * g + q;
+                    const int x = x0 + 16 * (t % T::XT) + 4 * g + q;
                     if (x >= W) continue;
                     float v = acc[i][t][j][q] + bv;
                     if (relu) v = v > 0.f ? v : kLeak * v;
                     out[(nbase + (size_t)z * plane + (size_t)y * W + x) * Cout + co] = f2bf(v);
                 }
+            }
         }
     }
 }
@@ -710,39 +718,49 @@ static unsigned grid_for(size_t n, unsigned block = 256, unsigned cap = 65536)
     return (unsigned)g;
 }
 
+template <int NB, int TX, bool kPipe>
+static hipError_t launch_fwd(const uint16_t* in, const uint16_t* coarse, int Cc, const uint16_t* wt, const float* bias,
+                             uint16_t* out, int N, int D, int H, int W, int Cin, int Cout, int Kp, int relu,
+                             hipStream_t s)
+{
+    using T = FwdTile<NB, 1, TX>;
+    const int cgroups = (Cout + 16 * NB - 1) / (16 * NB);
+    dim3 grid((W + TX - 1) / TX, ((H + T::TY - 1) / T::TY) * cgroups, N * ((D + T::TZ - 1) / T::TZ));
+    hipLaunchKernelGGL((conv3d_fwd_kernel<NB, 1, TX, kPipe>), grid, dim3(256), 0, s, in, coarse, Cc, wt, bias, out, D,
+                       H, W, Cin, Cout, Kp, relu);
+    return hipGetLastError();
+}
+
 hipError_t nn_conv3d_fwd_cat(const uint16_t* in, const uint16_t* coarse, int Cc, const uint16_t* wt,
                              const float* bias, uint16_t* out, int N, int D, int H, int W, int Cin, int Cout,
                              int Kp, int relu, hipStream_t s)
 {
-    // 64 x 2 x 2-voxel tiles; 16 output channels per workgroup (three
-    // workgroups per CU) or 32 (two per CU).  The copies in flight per CU set
-    // the pace (a 64 x 4 x 2 tile, fewer halo bytes per voxel but two
-    // workgroups per CU, was 4% slower at 160 x 128 x 128; 64 x 4 x 4, one
-    // workgroup per CU, 19% slower).  A one-chunk input (Cin = 8) is
-    // single-buffered.
+    // Tiles of 4 rows of 64 voxels (TX in x by 64 / TX in y; two rows in y,
+    // two in z); 16 output channels per workgroup (three workgroups per CU)
+    // or 32 (two per CU).  The copies in flight per CU set the pace (a
+    // 64 x 4 x 2 tile, fewer halo bytes per voxel but two workgroups per CU,
+    // was 4% slower at 160 x 128 x 128; 64 x 4 x 4, one workgroup per CU, 19%
+    // slower).  A one-chunk input (Cin = 8) is single-buffered.
     if (Cin % 8 || Cin < 8 || Kp < 27 * Cin || Cc % 8 || Cc < 0 || Cc >= Cin || (Cc && !coarse) ||
         (Cc && (D % 2 || H % 2 || W % 2)))
         return hipErrorInvalidValue;
     // the kernel keeps element offsets in 32 bits
     if ((size_t)N * D * H * W * (size_t)Cin >= (size_t)0x7FFFFFFF || (size_t)Cout * Kp >= (size_t)0x7FFFFFFF)
         return hipErrorInvalidValue;
+    // tile width: the grid's x extent up to 64
+    const int tx = W >= 64 ? 64 : (W >= 32 ? 32 : 16);
+#define PMC_FWD(NB, TX, PIPE) \
+    launch_fwd<NB, TX, PIPE>(in, coarse, Cc, wt, bias, out, N, D, H, W, Cin, Cout, Kp, relu, s)
     if (Cout <= 16) {
-        using T = FwdTile<1, 1>;
-        dim3 grid((W + 63) / 64, (H + T::TY - 1) / T::TY, N * ((D + T::TZ - 1) / T::TZ));
-        if (Cin == 8)
-            hipLaunchKernelGGL((conv3d_fwd_kernel<1, 1, false>), grid, dim3(256), 0, s, in, coarse, Cc, wt, bias, out, D,
-                               H, W, Cin, Cout, Kp, relu);
-        else
-            hipLaunchKernelGGL((conv3d_fwd_kernel<1, 1, true>), grid, dim3(256), 0, s, in, coarse, Cc, wt, bias, out, D,
-                               H, W, Cin, Cout, Kp, relu);
-    } else {
-        using T = FwdTile<2, 1>;
-        const int cgroups = (Cout + 31) / 32;
-        dim3 grid((W + 63) / 64, ((H + T::TY - 1) / T::TY) * cgroups, N * ((D + T::TZ - 1) / T::TZ));
-        hipLaunchKernelGGL((conv3d_fwd_kernel<2, 1, true>), grid, dim3(256), 0, s, in, coarse, Cc, wt, bias, out, D, H,
-                           W, Cin, Cout, Kp, relu);
+        if (Cin == 8 && tx == 64) return PMC_FWD(1, 64, false);
+        if (tx == 64) return PMC_FWD(1, 64, true);
+        if (tx == 32) return PMC_FWD(1, 32, true);
+        return PMC_FWD(1, 16, true);
     }
-    return hipGetLastError();
+    if (tx == 64) return PMC_FWD(2, 64, true);
+    if (tx == 32) return PMC_FWD(2, 32, true);
+    return PMC_FWD(2, 16, true);
+#undef PMC_FWD
 }
 
 hipError_t nn_conv3d_fwd(const uint16_t* in, const uint16_t* wt, const float* bias, uint16_t* out, int N,
