@@ -116,12 +116,40 @@ def bench_plans(args):
                                                             "cache_slots", "epoch_steps", "refill_lanes",
                                                             "batch_events")},
            "transport_ms_per_step": sum(s[0]["transport_ms"] for s in all_sums) / args.steps,
+           "denoiser_per_plan": _plans_denoiser(plans, spec),
            "ledger_residual_max": max(abs(s["incident"] - s["deposited"] - s["escaped"] - s["neutral"]
                                           - s["overflow"]) / s["incident"]
                                       for sums in all_sums for s in sums)}
     eng.close()
     print(json.dumps(out), flush=True)
     return 0
+
+
+def _plans_denoiser(plans, spec):
+    """Denoiser inference on every plan's dose after the batch: one network
+    per plan, its sides rounded up to multiples of 8 (the plan's grid sits at
+    the origin, zero outside). Times with the library's initial weights
+    (the arithmetic does not depend on them)."""
+    import torch
+    from paper_1409_8336_amd import unet
+    ms = []
+    for p, sp in zip(plans, spec):
+        d, h, w = (int(v) for v in p["hu"].shape)
+        shape = (1,) + tuple(-(-v // 8) * 8 for v in (d, h, w))
+        net = unet.UNet(shape, seed=1)
+        rho = torch.ones((d, h, w), dtype=torch.float32, device="cuda:0")
+        dose = sp["d_dose"].float()
+        out = torch.empty_like(dose)
+        net.forward_region(dose, rho, out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            net.forward_region(dose, rho, out)
+        torch.cuda.synchronize()
+        ms.append(1e3 * (time.perf_counter() - t0) / 3)
+        net.close()
+    return {"ms": ms, "total_ms": sum(ms),
+            "note": "one inference per plan on its own dose, networks sized to the plan's grid rounded up to 8"}
 
 
 def bench_ct_spots(args):

@@ -59,6 +59,14 @@ pmc_status pmc_unet_set_params(pmc_unet* u, const float* host_in);
 pmc_status pmc_unet_forward(pmc_unet* u, const float* d_dose, const float* d_density, float* d_out,
                             void* hip_stream);
 
+/* Denoise a grid smaller than the network's shape (the network needs sides
+ * divisible by 8; a treatment plan's CT need not): d_dose, d_density and
+ * d_out are [n][d][h][w] (each side at most the one given to pmc_unet_create), placed
+ * at the origin of the network's grid, which is zero outside them (no dose,
+ * density 0).  PMC_ERR_ARG if the grid does not fit. */
+pmc_status pmc_unet_forward_region(pmc_unet* u, const float* d_dose, const float* d_density, int d, int h, int w,
+                                   float* d_out, void* hip_stream);
+
 /* Forward, squared error against d_target in units of max(d_dose) summed
  * over all voxels and divided by the number of voxels of the dose region
  * (d_dose >= 1% of its maximum), and backward; gradients are added to the

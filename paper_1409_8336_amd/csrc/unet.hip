@@ -30,9 +30,10 @@ hipError_t nn_up_concat(const uint16_t* coarse, const uint16_t* skip, uint16_t* 
                         int Cc, int Cs, hipStream_t s);
 hipError_t nn_up_concat_bwd(const uint16_t* dcat, uint16_t* dcoarse, uint16_t* dskip, int N, int D, int H, int W,
                             int Cc, int Cs, hipStream_t s);
-hipError_t nn_make_input(const float* dose, const float* rho, float* scale, uint16_t* x, size_t nvox, hipStream_t s);
+hipError_t nn_make_input(const float* dose, const float* rho, float* scale, uint16_t* x, size_t nvox, int N, int D,
+                         int H, int W, int d, int h, int w, hipStream_t s);
 hipError_t nn_head_fwd(const uint16_t* d1, const float* w, const float* b, const float* dose, const float* scale,
-                       float* out, size_t nvox, int C, hipStream_t s);
+                       float* out, size_t nvox, int C, int D, int H, int W, int d, int h, int wd, hipStream_t s);
 hipError_t nn_loss_head_bwd(const float* out, const float* target, const float* dose, const float* scale,
                             unsigned int* region, const uint16_t* d1, const float* w, uint16_t* dd1, float* dw,
                             float* db, double* loss, size_t nvox, int C, hipStream_t s);
@@ -160,13 +161,17 @@ hipError_t conv_bwd(pmc_unet* u, const Conv& c, const Act& x, const Act& y, Act&
     return nn_conv3d_fwd(dy.p, u->wf + c.off_wf, nullptr, dx->p, u->N, d, h, w, c.cout, c.cin, c.kpf, 0, s);
 }
 
-// train: keep what the backward pass reads; out: the head's output
-hipError_t forward(pmc_unet* u, const float* dose, const float* rho, bool train, float* out, hipStream_t s)
+// train: keep what the backward pass reads; out: the head's output; the
+// caller's grid is d x h x w inside the network's (the whole of it in
+// training)
+hipError_t forward(pmc_unet* u, const float* dose, const float* rho, bool train, float* out, int d, int h, int w,
+                   hipStream_t s)
 {
     hipError_t e;
     const size_t nv = u->x.nvox;
     if ((e = hipMemsetAsync(u->scale, 0, sizeof(float), s)) != hipSuccess) return e;
-    if ((e = nn_make_input(dose, rho, u->scale, u->x.p, nv, s)) != hipSuccess) return e;
+    if ((e = nn_make_input(dose, rho, u->scale, u->x.p, nv, u->N, u->D, u->H, u->W, d, h, w, s)) != hipSuccess)
+        return e;
     const int N = u->N, D = u->D, H = u->H, W = u->W;
     if ((e = conv_fwd(u, u->conv[0], u->x, u->e1, 0, s)) != hipSuccess) return e;
     if ((e = nn_pool_fwd(u->e1.p, u->p1.p, N, D, H, W, 16, s)) != hipSuccess) return e;
@@ -178,7 +183,7 @@ hipError_t forward(pmc_unet* u, const float* dose, const float* rho, bool train,
     if ((e = dec_fwd(u, u->conv[4], u->e4, u->e3, u->c3, u->d3, 2, train, s)) != hipSuccess) return e;
     if ((e = dec_fwd(u, u->conv[5], u->d3, u->e2, u->c2, u->d2, 1, train, s)) != hipSuccess) return e;
     if ((e = dec_fwd(u, u->conv[6], u->d2, u->e1, u->c1, u->d1, 0, train, s)) != hipSuccess) return e;
-    return nn_head_fwd(u->d1.p, u->p + u->off_hw, u->p + u->off_hb, dose, u->scale, out, nv, 16, s);
+    return nn_head_fwd(u->d1.p, u->p + u->off_hw, u->p + u->off_hb, dose, u->scale, out, nv, 16, D, H, W, d, h, w, s);
 }
 
 hipError_t backward(pmc_unet* u, const float* dose, const float* target, hipStream_t s)
@@ -395,10 +400,19 @@ pmc_status pmc_unet_zero_grads(pmc_unet* u, void* stream)
 pmc_status pmc_unet_forward(pmc_unet* u, const float* dose, const float* rho, float* d_out, void* stream)
 {
     if (!u) return PMC_ERR_ARG;
+    return pmc_unet_forward_region(u, dose, rho, u->D, u->H, u->W, d_out, stream);
+}
+
+pmc_status pmc_unet_forward_region(pmc_unet* u, const float* dose, const float* rho, int d, int h, int w,
+                                   float* d_out, void* stream)
+{
+    if (!u) return PMC_ERR_ARG;
     if (!dose || !rho || !d_out) return ufail(u, PMC_ERR_ARG, "NULL tensor");
+    if (d < 1 || h < 1 || w < 1 || d > u->D || h > u->H || w > u->W)
+        return ufail(u, PMC_ERR_ARG, "the grid must fit inside the network's shape");
     UCHK(hipSetDevice(u->device), "set device");
     hipStream_t s = (hipStream_t)stream;
-    UCHK(forward(u, dose, rho, false, d_out, s), "forward");
+    UCHK(forward(u, dose, rho, false, d_out, d, h, w, s), "forward");
     return PMC_OK;
 }
 
@@ -409,7 +423,7 @@ pmc_status pmc_unet_backward(pmc_unet* u, const float* dose, const float* rho, c
     if (!dose || !rho || !target) return ufail(u, PMC_ERR_ARG, "NULL tensor");
     UCHK(hipSetDevice(u->device), "set device");
     hipStream_t s = (hipStream_t)stream;
-    UCHK(forward(u, dose, rho, true, u->out, s), "forward");
+    UCHK(forward(u, dose, rho, true, u->out, u->D, u->H, u->W, s), "forward");
     UCHK(backward(u, dose, target, s), "backward");
     if (loss_out) {
         UCHK(hipMemcpyAsync(loss_out, u->loss, 8, hipMemcpyDeviceToHost, s), "read loss");

@@ -512,14 +512,34 @@ __global__ void up_concat_bwd_skip_kernel(const uint16_t* __restrict__ dcat, uin
 }
 
 // network input: x[v] = (dose[v] * inv_scale, density[v] * 0.5, 0 x 6)
+// Grids: the network's [n][D][H][W] and the caller's compact [n][d][h][w]
+// (d <= D, h <= H, w <= W) placed at its origin; outside it the input is
+// zero (no dose, density 0) and no output is written.
+struct Region {
+    int D, H, W, d, h, w;
+    // compact index of network voxel v, or -1 outside the caller's grid
+    DEV long long compact(size_t v) const
+    {
+        const int x = (int)(v % W);
+        size_t r = v / W;
+        const int y = (int)(r % H);
+        r /= H;
+        const int z = (int)(r % D);
+        const size_t n = r / D;
+        if (x >= w || y >= h || z >= d) return -1;
+        return (long long)(((n * d + z) * h + y) * w + x);
+    }
+};
+
 __global__ void make_input_kernel(const float* __restrict__ dose, const float* __restrict__ rho,
-                                  const float* __restrict__ scale, uint16_t* __restrict__ x, size_t nvox)
+                                  const float* __restrict__ scale, uint16_t* __restrict__ x, size_t nvox, Region rg)
 {
     const float inv = 1.0f / fmaxf(scale[0], 1e-30f);
     for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < nvox; v += (size_t)gridDim.x * blockDim.x) {
+        const long long vc = rg.compact(v);
         uint16_t* o = x + 8 * v;
-        o[0] = f2bf(dose[v] * inv);
-        o[1] = f2bf(rho[v] * 0.5f);
+        o[0] = vc >= 0 ? f2bf(dose[vc] * inv) : (uint16_t)0;
+        o[1] = vc >= 0 ? f2bf(rho[vc] * 0.5f) : (uint16_t)0;
 #pragma unroll
         for (int c = 2; c < 8; ++c) o[c] = 0;
     }
@@ -562,10 +582,13 @@ __global__ void __launch_bounds__(256) region_count_kernel(const float* __restri
 // head: out[v] = scale * (dose[v]/scale + sum_c w[c] d1[v][c] + b)  (1x1x1, 16 -> 1, residual)
 __global__ void head_fwd_kernel(const uint16_t* __restrict__ d1, const float* __restrict__ w,
                                 const float* __restrict__ b, const float* __restrict__ dose,
-                                const float* __restrict__ scale, float* __restrict__ out, size_t nvox, int C)
+                                const float* __restrict__ scale, float* __restrict__ out, size_t nvox, int C,
+                                Region rg)
 {
     const float sc = fmaxf(scale[0], 1e-30f);
     for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < nvox; v += (size_t)gridDim.x * blockDim.x) {
+        const long long vc = rg.compact(v);
+        if (vc < 0) continue;
         float s = b[0];
         if (C == 16) {
             // the voxel's 32-byte row in two 16-byte loads (same sum order)
@@ -580,7 +603,7 @@ __global__ void head_fwd_kernel(const uint16_t* __restrict__ d1, const float* __
         } else {
             for (int c = 0; c < C; ++c) s += w[c] * bf2f(d1[v * C + c]);
         }
-        out[v] = dose[v] + sc * s;
+        out[vc] = dose[vc] + sc * s;
     }
 }
 
@@ -838,17 +861,23 @@ hipError_t nn_up_concat_bwd(const uint16_t* dcat, uint16_t* dcoarse, uint16_t* d
     return hipGetLastError();
 }
 
-hipError_t nn_make_input(const float* dose, const float* rho, float* scale, uint16_t* x, size_t nvox, hipStream_t s)
+// nvox: voxels of the network grid; the region gives the caller's (compact)
+// grid inside it, whose ncomp = n d h w voxels hold dose and density
+hipError_t nn_make_input(const float* dose, const float* rho, float* scale, uint16_t* x, size_t nvox, int N, int D,
+                         int H, int W, int d, int h, int w, hipStream_t s)
 {
-    hipLaunchKernelGGL(max_kernel, dim3(grid_for(nvox, 256, 1024)), dim3(256), 0, s, dose, nvox, scale);
-    hipLaunchKernelGGL(make_input_kernel, dim3(grid_for(nvox)), dim3(256), 0, s, dose, rho, scale, x, nvox);
+    const Region rg{D, H, W, d, h, w};
+    const size_t ncomp = (size_t)N * d * h * w;
+    hipLaunchKernelGGL(max_kernel, dim3(grid_for(ncomp, 256, 1024)), dim3(256), 0, s, dose, ncomp, scale);
+    hipLaunchKernelGGL(make_input_kernel, dim3(grid_for(nvox)), dim3(256), 0, s, dose, rho, scale, x, nvox, rg);
     return hipGetLastError();
 }
 
 hipError_t nn_head_fwd(const uint16_t* d1, const float* w, const float* b, const float* dose, const float* scale,
-                       float* out, size_t nvox, int C, hipStream_t s)
+                       float* out, size_t nvox, int C, int D, int H, int W, int d, int h, int wd, hipStream_t s)
 {
-    hipLaunchKernelGGL(head_fwd_kernel, dim3(grid_for(nvox)), dim3(256), 0, s, d1, w, b, dose, scale, out, nvox, C);
+    const Region rg{D, H, W, d, h, wd};
+    hipLaunchKernelGGL(head_fwd_kernel, dim3(grid_for(nvox)), dim3(256), 0, s, d1, w, b, dose, scale, out, nvox, C, rg);
     return hipGetLastError();
 }
 

@@ -13,6 +13,7 @@ from . import pmc
 # every symbol include/pmc_unet.h declares
 EXPORTS = ("pmc_unet_create", "pmc_unet_destroy", "pmc_unet_last_error", "pmc_unet_param_count",
            "pmc_unet_get_params", "pmc_unet_set_params", "pmc_unet_forward", "pmc_unet_backward",
+           "pmc_unet_forward_region",
            "pmc_unet_get_grads", "pmc_unet_zero_grads", "pmc_unet_adam_step", "pmc_unet_grad_norm",
            "pmc_nn_conv3d_forward", "pmc_nn_conv3d_backward_data", "pmc_nn_conv3d_backward_weight",
            "pmc_gamma_index", "pmc_denoise_disagreement")
@@ -20,6 +21,7 @@ EXPORTS = ("pmc_unet_create", "pmc_unet_destroy", "pmc_unet_last_error", "pmc_un
 _ready = False
 # element count of one network input, per handle (the C calls take bare
 # pointers sized at creation)
+_shape = {}
 _numel = {}
 
 
@@ -36,6 +38,7 @@ def lib():
         L.pmc_unet_get_params.argtypes = [vp, vp]
         L.pmc_unet_set_params.argtypes = [vp, vp]
         L.pmc_unet_forward.argtypes = [vp, vp, vp, vp, vp]
+        L.pmc_unet_forward_region.argtypes = [vp, vp, vp, C.c_int, C.c_int, C.c_int, vp, vp]
         L.pmc_unet_backward.argtypes = [vp, vp, vp, vp, C.POINTER(C.c_double), vp]
         L.pmc_unet_get_grads.argtypes = [vp, vp]
         L.pmc_unet_zero_grads.argtypes = [vp, vp]
@@ -79,11 +82,13 @@ def pmc_unet_create(device, n, d, h, w, seed):
     u = C.c_void_p()
     _check(None, lib().pmc_unet_create(C.byref(u), int(device), n, d, h, w, int(seed)))
     _numel[u.value] = n * d * h * w
+    _shape[u.value] = (n, d, h, w)
     return u
 
 
 def pmc_unet_destroy(u):
     _numel.pop(u.value, None)
+    _shape.pop(u.value, None)
     _check(None, lib().pmc_unet_destroy(u))
 
 
@@ -129,6 +134,22 @@ def pmc_unet_forward(u, dose, density, out, stream=None):
     f = torch.float32
     _check(u, lib().pmc_unet_forward(u, _dev(dose, f, "dose"), _dev(density, f, "density"),
                                      _dev(out, f, "out"), _stream(stream, dose.device)))
+
+
+def pmc_unet_forward_region(u, dose, density, out, stream=None):
+    """Denoise a [d][h][w] grid no larger than the network's shape (zero
+    outside it); dose, density and out are tensors of that shape."""
+    import torch
+    shp = _shape.get(u.value)
+    if shp is None or dose.dim() != 3 or tuple(density.shape) != tuple(dose.shape) or \
+            tuple(out.shape) != tuple(dose.shape):
+        raise ValueError("dose, density and out must be [d][h][w] tensors of one shape")
+    d, h, w = (int(v) for v in dose.shape)
+    if shp[0] != 1 or d > shp[1] or h > shp[2] or w > shp[3]:
+        raise ValueError("grid %s does not fit the network's shape %s" % ((d, h, w), shp))
+    f = torch.float32
+    _check(u, lib().pmc_unet_forward_region(u, _dev(dose, f, "dose"), _dev(density, f, "density"), d, h, w,
+                                            _dev(out, f, "out"), _stream(stream, dose.device)))
 
 
 def pmc_unet_backward(u, dose, density, target, stream=None) -> float:
@@ -260,6 +281,9 @@ class UNet:
 
     def forward(self, dose, density, out, stream=None):
         pmc_unet_forward(self.u, dose, density, out, stream)
+
+    def forward_region(self, dose, density, out, stream=None):
+        pmc_unet_forward_region(self.u, dose, density, out, stream)
 
     def backward(self, dose, density, target, stream=None):
         return pmc_unet_backward(self.u, dose, density, target, stream)

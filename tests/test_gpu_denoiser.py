@@ -257,6 +257,36 @@ def test_adam_step_and_bf16_refresh():
     fresh.close()
 
 
+def test_forward_region_equals_zero_padded_forward():
+    """A grid smaller than the network's shape (the sides of a plan's CT need
+    not divide by 8) gives, voxel for voxel, the output of the full-shape
+    forward on the same grid zero-padded to the network's shape."""
+    import torch
+    _say("case: forward on a sub-grid")
+    U = _unet()
+    shape = (1, 16, 16, 24)
+    rng = np.random.default_rng(53)
+    net = U.UNet(shape, seed=4)
+    net.set_params(_net_params(net.u, 8))
+    d, h, w = 13, 11, 20
+    dose, rho, _ = _net_inputs(rng, (d, h, w))
+    td, tr = torch.from_numpy(dose).cuda(), torch.from_numpy(rho).cuda()
+    out_r = torch.zeros((d, h, w), dtype=torch.float32, device="cuda")
+    net.forward_region(td, tr, out_r)
+    pd_ = torch.zeros(shape, dtype=torch.float32, device="cuda")
+    pr = torch.zeros_like(pd_)
+    pd_[0, :d, :h, :w] = td
+    pr[0, :d, :h, :w] = tr
+    out_f = torch.zeros_like(pd_)
+    net.forward(pd_, pr, out_f)
+    torch.cuda.synchronize()
+    assert torch.equal(out_r, out_f[0, :d, :h, :w])
+    with pytest.raises(ValueError):
+        net.forward_region(torch.zeros((17, 4, 4), device="cuda"), torch.zeros((17, 4, 4), device="cuda"),
+                           torch.zeros((17, 4, 4), device="cuda"))
+    net.close()
+
+
 def test_grad_norm_and_scaled_adam():
     """The device gradient norm equals the norm of the gradient read back,
     and two Adam steps on scaled gradients (the clipping factor) match the
