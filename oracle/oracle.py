@@ -80,6 +80,9 @@ def lib():
             L.oracle_run_spots.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_uint64, C.c_uint64,
                                            C.c_void_p, C.c_void_p, C.POINTER(Summary),
                                            C.POINTER(Diag)]
+            L.oracle_run_spots_let.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_uint64,
+                                               C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                               C.POINTER(Summary), C.POINTER(Diag)]
             L.oracle_philox4x32_10.argtypes = [u32p, u32p, u32p]
             L.oracle_philox4x32_10.restype = None
             L.oracle_u01.argtypes = [C.c_uint32]
@@ -192,7 +195,9 @@ class Oracle:
         self.shape = (nz, ny, nx)
 
     def run_spots(self, spots, n_histories, seed, batch_tally=False, first_nuclear=False,
-                  escape_cap=0, uid_range=None):
+                  escape_cap=0, uid_range=None, let=False):
+        """Dose, variance and summary; with let=True also the dose-averaged
+        LET per voxel in keV/um (key "let")."""
         spots = np.ascontiguousarray(spots, dtype=np.float32).reshape(-1, 6)
         dose = np.zeros(self.shape, dtype=np.float64)
         var = np.zeros(self.shape, dtype=np.float64)
@@ -213,8 +218,15 @@ class Oracle:
             el = np.zeros((int(escape_cap), 8), dtype=np.float64)
             dg.escape_log = _ptr(el)
             dg.escape_cap = int(escape_cap)
-        rc = lib().oracle_run_spots(self.h, _ptr(spots), len(spots), int(n_histories), int(seed),
-                                    _ptr(dose), _ptr(var), C.byref(s), C.byref(dg))
+        if let:
+            lt = np.zeros(self.shape, dtype=np.float64)
+            out["let"] = lt
+            rc = lib().oracle_run_spots_let(self.h, _ptr(spots), len(spots), int(n_histories),
+                                            int(seed), _ptr(dose), _ptr(var), _ptr(lt),
+                                            C.byref(s), C.byref(dg))
+        else:
+            rc = lib().oracle_run_spots(self.h, _ptr(spots), len(spots), int(n_histories),
+                                        int(seed), _ptr(dose), _ptr(var), C.byref(s), C.byref(dg))
         if rc:
             raise ValueError("oracle_run_spots failed: %d" % rc)
         if escape_cap:

@@ -684,6 +684,8 @@ typedef struct {
     uint64_t seed;
     double* tally;   /* nvox x K */
     ora_diag* diag;
+    double* let_num; /* nvox: sum of w * eps * L over proton steps (NULL = not scored) */
+    double* let_den; /* nvox: sum of w * eps over the same steps */
 } orun;
 
 static void push(ostack* s, const opart* q)
@@ -700,6 +702,22 @@ static void deposit(const ora_ctx* c, const orun* r, size_t v, int batch, double
     double* slot = &r->tally[v * (size_t)c->p.k_batches + batch];
 #pragma omp atomic
     *slot += amount;
+}
+
+/* Dose-averaged LET (Sec. III, LET_d maps): a proton step that starts in
+ * voxel v and deposits eps there adds w * eps * L to the numerator and
+ * w * eps to the denominator, L being the stopping power of v's medium
+ * averaged over the step's mean (CSDA) energy loss, in MeV/cm.  Deposits
+ * that belong to no step (recoil nuclei, the local share of a non-elastic
+ * event, secondaries below the cut-off, the sub-cut-off rest of a track) are
+ * not scored. */
+static void score_let(const orun* r, size_t v, double amount, double l_mev_cm)
+{
+    if (!r->let_num) return;
+#pragma omp atomic
+    r->let_num[v] += amount * l_mev_cm;
+#pragma omp atomic
+    r->let_den[v] += amount;
 }
 
 static int locate(const ora_ctx* c, const double p[3], const double d[3], int v[3])
@@ -852,9 +870,11 @@ static void transport(const ora_ctx* c, const orun* r, opart* q, ostack* st, oac
             else continue;
             if (da < d) { d = da; axis = a; }
         }
-        /* range-limited step: the proton stops in this voxel */
+        /* range-limited step: the proton stops in this voxel; its stopping
+         * power averaged over the residual range (R(E_CUT) = 0) */
         if (s_range <= d && s_range <= s_nuc) {
             deposit(c, r, vi, q->batch, q->w * q->e);
+            score_let(r, vi, q->w * q->e, (q->e - E_CUT) / s_range);
             return;
         }
         const int lim = (s_nuc < d) ? LIM_NUC : LIM_BND;
@@ -863,6 +883,7 @@ static void transport(const ora_ctx* c, const orun* r, opart* q, ostack* st, oac
         if (short_step) s = c->p.s_min_cm;
         if (s >= s_range) {
             deposit(c, r, vi, q->batch, q->w * q->e);
+            score_let(r, vi, q->w * q->e, (q->e - E_CUT) / s_range);
             return;
         }
         /* mean loss from the range table, Eq. 2 water-equivalent path */
@@ -904,6 +925,7 @@ static void transport(const ora_ctx* c, const orun* r, opart* q, ostack* st, oac
         if (on_face) q->p[axis] = face;
         const double e_new = q->e - de;
         deposit(c, r, vi, q->batch, q->w * (q->e - e_new));
+        score_let(r, vi, q->w * (q->e - e_new), de_mean / s);
         q->mfp = (lim == LIM_NUC) ? 0.0 : fmax(q->mfp - sig * s, 0.0);
         q->e = e_new;
         q->k = ks + 1;
@@ -937,8 +959,9 @@ static int cmp_rem(const void* a, const void* b)
     return x->idx - y->idx;
 }
 
-int oracle_run_spots(ora_ctx* c, const ora_spot* spots, int n_spots, uint64_t n_hist,
-                     uint64_t seed, double* dose, double* var, ora_summary* sum, ora_diag* diag)
+static int run_impl(ora_ctx* c, const ora_spot* spots, int n_spots, uint64_t n_hist,
+                    uint64_t seed, double* dose, double* var, double* let, ora_summary* sum,
+                    ora_diag* diag)
 {
     if (!c || !dose || !var || !sum) return -1;
     if (!c->have_physics || !c->have_geometry) return -6;
@@ -962,8 +985,9 @@ int oracle_run_spots(ora_ctx* c, const ora_spot* spots, int n_spots, uint64_t n_
     double* omega = (double*)calloc(n_spots > 0 ? n_spots : 1, sizeof(double));
     remk* rk = (remk*)calloc(n_spots > 0 ? n_spots : 1, sizeof(remk));
     double* tally = (double*)calloc(c->nvox * (size_t)K, sizeof(double));
-    if (!ns || !start || !omega || !rk || !tally) {
-        free(ns); free(start); free(omega); free(rk); free(tally);
+    double* let_nd = let ? (double*)calloc(2 * c->nvox, sizeof(double)) : NULL;
+    if (!ns || !start || !omega || !rk || !tally || (let && !let_nd)) {
+        free(ns); free(start); free(omega); free(rk); free(tally); free(let_nd);
         return -3;
     }
     if (n_hist > 0) {
@@ -992,7 +1016,7 @@ int oracle_run_spots(ora_ctx* c, const ora_spot* spots, int n_spots, uint64_t n_
     if (diag) diag->escape_count = 0;
     if (diag && diag->first_nuclear_z_cm)
         for (uint64_t h = 0; h < n_hist; ++h) diag->first_nuclear_z_cm[h] = NAN;
-    orun run = {seed, tally, diag};
+    orun run = {seed, tally, diag, let_nd, let_nd ? let_nd + c->nvox : NULL};
     double incident = 0.0, escaped = 0.0, neutral = 0.0;
     uint64_t steps = 0, secs = 0, nel = 0, nne = 0, nshort = 0, inter[2][ORA_NEL];
     memset(inter, 0, sizeof(inter));
@@ -1070,6 +1094,12 @@ int oracle_run_spots(ora_ctx* c, const ora_spot* spots, int n_spots, uint64_t n_
         var[v] = (double)K / (K - 1) * ss * conv * conv;
         deposited += tot;
     }
+    /* LET_d in keV/um (1 MeV/cm = 0.1 keV/um); 0 where no step deposited */
+    if (let)
+        for (size_t v = 0; v < c->nvox; ++v) {
+            const double num = let_nd[v], den = let_nd[c->nvox + v];
+            let[v] = (den > 0.0) ? 0.1 * num / den : 0.0;
+        }
     if (diag && diag->batch_tally) memcpy(diag->batch_tally, tally, sizeof(double) * c->nvox * K);
     sum->incident = incident;
     sum->deposited = deposited;
@@ -1087,6 +1117,20 @@ int oracle_run_spots(ora_ctx* c, const ora_spot* spots, int n_spots, uint64_t n_
 #ifdef _OPENMP
     sum->wall_s = omp_get_wtime() - t0;
 #endif
-    free(ns); free(start); free(omega); free(rk); free(tally);
+    free(ns); free(start); free(omega); free(rk); free(tally); free(let_nd);
     return 0;
+}
+
+int oracle_run_spots(ora_ctx* c, const ora_spot* spots, int n_spots, uint64_t n_hist,
+                     uint64_t seed, double* dose, double* var, ora_summary* sum, ora_diag* diag)
+{
+    return run_impl(c, spots, n_spots, n_hist, seed, dose, var, NULL, sum, diag);
+}
+
+int oracle_run_spots_let(ora_ctx* c, const ora_spot* spots, int n_spots, uint64_t n_hist,
+                         uint64_t seed, double* dose, double* var, double* let_kev_um,
+                         ora_summary* sum, ora_diag* diag)
+{
+    if (!let_kev_um) return -1;
+    return run_impl(c, spots, n_spots, n_hist, seed, dose, var, let_kev_um, sum, diag);
 }

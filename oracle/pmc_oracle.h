@@ -95,6 +95,16 @@ int oracle_load_geometry(ora_ctx* c, const int16_t* hu, int nx, int ny, int nz,
 int oracle_run_spots(ora_ctx* c, const ora_spot* spots, int n_spots, uint64_t n_histories,
                      uint64_t seed, double* dose_gy, double* var_gy2, ora_summary* s,
                      ora_diag* diag);
+/* As oracle_run_spots, and the dose-averaged LET of every voxel (Sec. III,
+ * LET_d maps) in keV/um into let_kev_um (nx*ny*nz doubles):
+ * sum(w eps L) / sum(w eps) over the proton steps that start in the voxel,
+ * eps the step's deposit and L the stopping power of the voxel's medium
+ * averaged over the step's mean energy loss (a range-limited step: over the
+ * residual range).  Local deposits of nuclear events and the sub-cut-off rest
+ * of a track are not scored.  0 where no step deposited. */
+int oracle_run_spots_let(ora_ctx* c, const ora_spot* spots, int n_spots, uint64_t n_histories,
+                         uint64_t seed, double* dose_gy, double* var_gy2, double* let_kev_um,
+                         ora_summary* s, ora_diag* diag);
 
 /* ---- individual pieces, exported for the closed-form pins ---- */
 void oracle_philox4x32_10(const uint32_t key[2], const uint32_t ctr[4], uint32_t out[4]);

@@ -519,3 +519,124 @@ def test_spot_allocation_largest_remainder():
     expect = 2 * 50.0 * (1 / 6 * 10 / 2) + 3 * 60.0 * (2 / 6 * 10 / 3) + 5 * 70.0 * (3 / 6 * 10 / 5)
     assert abs(out["summary"]["incident"] - expect) < 1e-9
     assert abs(out["summary"]["total_weight"] - 10.0) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Dose-averaged LET (Sec. III, LET_d maps): sum(w eps L) / sum(w eps) over
+# proton steps, L the stopping power of the voxel's medium averaged over the
+# step's mean energy loss (keV/um)
+# ---------------------------------------------------------------------------
+
+DETERMINISTIC = O.NO_STRAGGLE | O.NO_MCS | O.NO_NUCLEAR
+
+
+def _bin_scale(o, lib, water_za, hu):
+    """Density, stopping-power table (Z/A, I) and water-equivalent scale of
+    the material bin holding hu (Sec. II.A.1-2)."""
+    mt = synth.material_table()
+    b = int(np.searchsorted(mt["hu_lo"].astype(int), hu, side="right") - 1)
+    lo = int(mt["hu_lo"][b])
+    hi = int(mt["hu_lo"][b + 1]) if b + 1 < len(mt["hu_lo"]) else 3000
+    rho = float(mt["rho_lo"][b])
+    if hi > lo:
+        rho += (float(mt["rho_hi"][b]) - float(mt["rho_lo"][b])) * (hu - lo) / (hi - lo)
+    info = o.material_info(b)
+    if info["own"]:
+        return info["z_over_a"], info["i_ev"], rho
+    return water_za, 75.0, rho * info["f"]
+
+
+@pytest.mark.parametrize("hu,e0", [(0, 100.0), (1000, 150.0), (3000, 70.0)])
+def test_let_of_a_deterministic_pencil_is_loss_per_path(lib, water_za, hu, e0):
+    """Straight zero-width pencil, mean loss only: every step crosses one
+    voxel, so LET_d is the energy lost across the voxel per unit length (from
+    an independent quadrature of the stopping power), and in the voxel where
+    the range ends it is the residual energy over the residual path."""
+    nz = 100 if hu != 3000 else 40
+    o = _oracle(flags=DETERMINISTIC, hu=synth.uniform_phantom(hu, 3, 3, nz))
+    za, i_ev, scale = _bin_scale(o, lib, water_za, hu)
+    out = o.run_spots(synth.pencil_spot(0.3, 0.3, e0, sigma_cm=0.0), 20, 1, let=True)
+    let = out["let"][:, 1, 1]
+    r0, e_at = _energy_at_depth_fn(lib, za, i_ev, e0, scale)
+    depth = r0 / scale
+    last = int(math.floor(depth / 0.2))
+    assert np.all(let[last + 1:] == 0) and np.all(out["let"][:, 0, :] == 0)
+    for i in list(range(0, last, max(1, last // 10))) + [last - 1]:
+        want = 0.1 * (e_at(0.2 * i) - e_at(0.2 * (i + 1))) / 0.2
+        assert abs(let[i] / want - 1) < 2e-6, (i, let[i], want)
+    e_last = e_at(0.2 * last)
+    want = 0.1 * (e_last - 0.1) / (depth - 0.2 * last)
+    assert abs(let[last] / want - 1) < 1e-5, (let[last], want)
+
+
+def test_let_entrance_matches_pstar_stopping_power(water_za, lib):
+    """Units (keV/um) and medium: at the entrance LET_d equals the tabulated
+    electronic stopping power of water at the voxel's mid energy."""
+    pstar = {float(r[0]): float(r[1]) for r in _golden("water_stopping_pstar.txt")}
+    o = _oracle(flags=DETERMINISTIC, hu=synth.uniform_phantom(0, 3, 3, 10))
+    for e0 in (70.0, 100.0, 150.0, 200.0):
+        let0 = o.run_spots(synth.pencil_spot(0.3, 0.3, e0, 0.0), 4, 1, let=True)["let"][0, 1, 1]
+        e_mid = e0 - 0.5 * 0.2 * 10.0 * let0              # half the loss in the first voxel
+        slope = (lib.oracle_stopping_power(e_mid, water_za, 75.0) /
+                 lib.oracle_stopping_power(e0, water_za, 75.0))
+        assert abs(let0 / (0.1 * pstar[e0] * slope) - 1) < 0.003, (e0, let0)
+
+
+def test_let_is_dose_averaged_not_track_averaged(lib, water_za):
+    """Two energies through one voxel column: each proton loses eps_i = L_i dz,
+    so the dose average is (L1^2 + L2^2) / (L1 + L2), not the track average
+    (L1 + L2) / 2."""
+    o = _oracle(flags=DETERMINISTIC, hu=synth.uniform_phantom(0, 3, 3, 40))
+    r_lo = o.run_spots(synth.pencil_spot(0.3, 0.3, 70.0, 0.0), 6, 1, let=True)
+    r_hi = o.run_spots(synth.pencil_spot(0.3, 0.3, 200.0, 0.0), 6, 1, let=True)
+    lo, hi = r_lo["let"][:, 1, 1], r_hi["let"][:, 1, 1]
+    d_lo, d_hi = r_lo["dose"][:, 1, 1], r_hi["dose"][:, 1, 1]
+    both = np.concatenate([synth.pencil_spot(0.3, 0.3, 70.0, 0.0),
+                           synth.pencil_spot(0.3, 0.3, 200.0, 0.0)])
+    mix = o.run_spots(both, 12, 1, let=True)["let"][:, 1, 1]
+    # everywhere (also where the 70 MeV protons stop): weights = the doses
+    any_ = d_lo + d_hi > 0
+    want = (d_lo * lo + d_hi * hi)[any_] / (d_lo + d_hi)[any_]
+    np.testing.assert_allclose(mix[any_], want, rtol=1e-12)
+    # where both cross the whole voxel, eps_i = L_i dz
+    full = (lo > 0) & (hi > 0)
+    full[np.nonzero(lo)[0][-1]] = False
+    assert full.sum() >= 20
+    want = (lo[full] ** 2 + hi[full] ** 2) / (lo[full] + hi[full])
+    np.testing.assert_allclose(mix[full], want, rtol=1e-9)
+    track = 0.5 * (lo[full] + hi[full])
+    assert np.max(np.abs(want / track - 1)) > 0.2
+
+
+def test_let_scoring_leaves_dose_unchanged_and_rises_to_the_distal_edge():
+    """Full physics, 100 MeV pencil in water: scoring LET_d does not change
+    the dose; LET_d at the entrance lies between the primary's stopping power
+    and a few per cent above it (slow secondary protons add to it), and it
+    rises through the Bragg peak to several keV/um where protons range out."""
+    spots = synth.pencil_spot(3.1, 3.1, 100.0, 0.3)
+    slabs = {}
+    for flags in (0, O.NO_NUCLEAR):
+        o = O.Oracle(n_threads=1, flags=flags)
+        o.load_physics(synth.nuclear_data())
+        o.load_geometry(synth.water_phantom(31, 31, 60), (0.2, 0.2, 0.2), synth.material_table())
+        a = o.run_spots(spots, 4000, 3, let=True)
+        b = o.run_spots(spots, 4000, 3)
+        np.testing.assert_allclose(a["dose"], b["dose"], rtol=1e-12, atol=0)
+        let, dose = a["let"], a["dose"]
+        assert np.all(let[dose == 0] == 0)
+        e_dep = dose.sum(axis=(1, 2))
+        # dose-weighted mean over each depth slab
+        slabs[flags] = ((let * dose).sum(axis=(1, 2)) / np.maximum(e_dep, 1e-300), e_dep)
+    det = _oracle(flags=DETERMINISTIC, hu=synth.uniform_phantom(0, 3, 3, 60))
+    l0 = det.run_spots(synth.pencil_spot(0.3, 0.3, 100.0, 0.0), 4, 1, let=True)["let"][0, 1, 1]
+    # straggling and scattering leave the entrance value at the primary's
+    # stopping power; slow secondary protons (elastic recoils, non-elastic
+    # emission) raise it
+    no_nuc = slabs[O.NO_NUCLEAR][0]
+    assert abs(no_nuc[0] / l0 - 1) < 0.01, (no_nuc[0], l0)
+    slab, e_dep = slabs[0]
+    assert 1.02 < slab[0] / l0 < 1.3, (slab[0], l0)
+    peak = int(np.argmax(e_dep))
+    distal = peak + int(np.argmax(e_dep[peak:] < 0.8 * e_dep[peak]))
+    assert slab[distal] > 3.0 * slab[0], (slab[distal], slab[0])
+    assert np.all(np.diff(no_nuc[:peak - 2]) > -0.02 * no_nuc[:peak - 3]), no_nuc[:peak]
