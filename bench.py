@@ -32,8 +32,8 @@ HBM_PEAK = 8.0e12
 # HBM bytes per transport launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
 # scaled by a plain-copy calibration, valid only for the kernel source whose
 # sha256 is recorded (see profiles/); None once the kernel has changed.
-TRAFFIC = {"transport_sha256": "0cbdaef28efb6050215f0942ca589e7ab936ca52eb5825b252cb34ed3c9b1183",
-           "bytes_per_launch": 6.379e9}
+TRAFFIC = {"transport_sha256": "ed5a113cfa378bdadf63ce061a2b3b403d81c0b75d2cd892403e0a8136c72c28",
+           "bytes_per_launch": 6.211e9, "let_bytes_per_launch": 1.2964e10}
 
 
 def _kernel_sha():
@@ -42,16 +42,17 @@ def _kernel_sha():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def cpu_baseline(cfg, target_s=10.0):
+def cpu_baseline(cfg, target_s=12.0):
     from oracle import oracle as O
     from paper_1409_8336_amd import synth
     o = O.Oracle()
     o.load_physics(synth.nuclear_data())
     o.load_geometry(cfg["hu"], cfg["voxel_cm"], synth.material_table())
-    probe = 20000
+    # a probe long enough that thread start-up does not dominate its rate
+    probe = 100_000
     r = o.run_spots(cfg["spots"], probe, 2)
     rate = probe / max(r["summary"]["wall_s"], 1e-6)
-    n = int(min(2_000_000, max(probe, rate * target_s)))
+    n = int(min(5_000_000, max(probe, rate * target_s)))
     r = o.run_spots(cfg["spots"], n, 3)
     s = r["summary"]
     o.close()
@@ -263,6 +264,8 @@ def main():
                          "uneven 16-plan batch in one persistent launch; ct_spots: single "
                          "spots at 70/150/230 MeV in the 128x128x160 CT; denoiser: the U-Net "
                          "at 160x128x128 (inference and training step)")
+    ap.add_argument("--let-steps", type=int, default=3,
+                    help="field workload: also time this many runs with LET_d scored (0 = skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device copy (counter calibration)")
     ap.add_argument("--param", action="append", default=[], metavar="NAME=VALUE",
@@ -370,6 +373,39 @@ def main():
                     "FP64 adds that reach device memory (cache misses and flushes)",
         },
     }
+    # the same workload with dose-averaged LET scored in the same transport
+    # (Sec. III): its rate beside the dose-only one
+    if args.let_steps > 0:
+        d_let = torch.empty_like(d_dose)
+        eng.run_spots_let_dev(cfg["spots"], cfg["n_histories"], cfg["seed"], d_dose, d_let, d_var, stream)
+        torch.cuda.synchronize()
+        lsums = []
+        t0 = time.perf_counter()
+        for i in range(args.let_steps):
+            lsums.append(eng.run_spots_let_dev(cfg["spots"], cfg["n_histories"], cfg["seed"] + i, d_dose,
+                                               d_let, d_var, stream))
+        torch.cuda.synchronize()
+        let_elapsed = time.perf_counter() - t0
+        dose_rate = n_tot / elapsed
+        let_rate = args.let_steps * cfg["n_histories"] / let_elapsed
+        let_transport_s = sum(s["transport_ms"] for s in lsums) * 1e-3
+        let_atomics = sum(s["global_atomics"] for s in lsums)
+        out["let_d"] = {
+            "histories_per_s": let_rate,
+            "achieved_atomics_per_s": let_atomics / let_transport_s,
+            "atomic_frac": (let_atomics / let_transport_s) / probe_rate,
+            "traffic_bytes_per_launch": (TRAFFIC["let_bytes_per_launch"]
+                                         if TRAFFIC["transport_sha256"] == _kernel_sha() else None),
+            "ms_per_step": 1e3 * let_elapsed / args.let_steps,
+            "transport_ms_per_step": sum(s["transport_ms"] for s in lsums) / args.let_steps,
+            "rate_vs_dose_only": let_rate / dose_rate,
+            "deposits_per_step": sum(s["tally_atomics"] for s in lsums) / args.let_steps,
+            "tally_atomics_per_step": sum(s["global_atomics"] for s in lsums) / args.let_steps,
+            "launch_shape": {k: lsums[-1][k] for k in ("block_threads", "grid_blocks", "cache_slots",
+                                                        "refill_lanes", "batch_events")},
+            "steps": args.let_steps,
+        }
+        del d_let
     # the same run through host buffers: spots in, dose and variance copied
     # back over PCIe (context only; not the headline value)
     t0 = time.perf_counter()

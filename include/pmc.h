@@ -147,7 +147,8 @@ typedef struct {
                               emitting workgroup, this plan, plus those that went through the
                               generation queues, whole run) */
     uint64_t n_short_steps; /* steps lengthened to s_min (sub-micron boundary approaches) */
-    uint64_t tally_atomics; /* energy deposits scored (one per step, event or termination) */
+    uint64_t tally_atomics; /* energy deposits scored (one per step, event or termination;
+                               with LET_d scoring also its own deposits) */
     double total_weight;   /* sum of primary weights (dose normalisation) */
     double device_ms;      /* device time of the run, HIP events */
     double transport_ms;   /* sum over transport launches of their HIP-event durations */
@@ -214,6 +215,29 @@ pmc_status pmc_run_spots_dev(pmc_ctx* c, const pmc_spot* spots, int n_spots, uin
                              uint64_t seed, double* d_dose, double* d_var, void* hip_stream,
                              pmc_summary* summary);
 
+/* As pmc_run_spots_dev, and the dose-averaged LET (LET_d, Sec. III and its
+ * LET_d maps) of every voxel in keV/um into the caller-owned device buffer
+ * d_let (nx*ny*nz doubles, [nz][ny][nx]), computed in the same transport:
+ *   LET_d(v) = sum(w eps L) / sum(w eps)
+ * over the proton steps (primaries and secondary protons) that start in v,
+ * eps the step's deposit (with straggling; the whole energy on a step the
+ * range ends) and L the stopping power of v's medium averaged over the
+ * step's mean energy loss (over the residual range when the range ends the
+ * step).  Energy deposited outside any step (recoil nuclei and the local
+ * share of nuclear events, sub-cut-off secondaries and track rests) is not
+ * scored, as the paper's LET_d leaves out heavy recoils.  0 where no step
+ * deposited.  Dose and variance are those pmc_run_spots_dev gives.  The
+ * tally holds two extra FP64 planes (16 bytes per voxel).  Errors: as
+ * pmc_run_spots_dev; PMC_ERR_ARG also for d_let NULL. */
+pmc_status pmc_run_spots_let_dev(pmc_ctx* c, const pmc_spot* spots, int n_spots, uint64_t n_histories,
+                                 uint64_t seed, double* d_dose, double* d_var, double* d_let,
+                                 void* hip_stream, pmc_summary* summary);
+
+/* As pmc_run_spots with LET_d (keV/um) into the host array let_out as well. */
+pmc_status pmc_run_spots_let(pmc_ctx* c, const pmc_spot* spots, int n_spots, uint64_t n_histories,
+                             uint64_t seed, double* dose_out, double* var_out, double* let_out,
+                             pmc_summary* summary);
+
 /* Load a further geometry for batched runs (configurations with many CTs).
  * Same arguments as pmc_load_geometry, which must have been called first; the
  * material table must equal the one already loaded.  *geometry_id_out
@@ -226,7 +250,9 @@ pmc_status pmc_load_geometry_slot(pmc_ctx* c, int* geometry_id_out, const int16_
 
 /* One plan of a batched run: n_histories over its spots on geometry slot
  * geometry_id, dose and variance into caller-owned device buffers of that
- * geometry's voxel count (d_var may be NULL), optional host summary. */
+ * geometry's voxel count (d_var may be NULL), optional host summary, and
+ * optionally LET_d as pmc_run_spots_let_dev gives it (d_let NULL = not
+ * wanted; when any plan of a batch asks for it, the whole launch scores it). */
 typedef struct {
     int32_t geometry_id;
     int32_t n_spots;
@@ -235,6 +261,7 @@ typedef struct {
     double* d_dose;
     double* d_var;
     pmc_summary* summary;      /* host, may be NULL */
+    double* d_let;             /* LET_d, keV/um, or NULL */
 } pmc_plan;
 
 /* Transport every plan in one persistent launch per secondary generation:

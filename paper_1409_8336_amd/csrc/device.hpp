@@ -41,6 +41,13 @@ constexpr int kOffInvOwn = 2512;
 constexpr int kOffSigma = 3024;      // n_mat x 1000 total cross section per gram
 // then n_mat x 4 words: f (Eq. 1; 1 for own-table bins), X0 (g/cm^2), Z/A, own flag
 
+// Run flag set by the engine (beside the public PMC_NO_* switches, bits 0-2)
+// when LET_d is scored: the tally of a plan then holds, after its
+// [nvox][k_batches] dose groups, two planes of nvox doubles: the LET
+// numerator (sum of w eps L over proton steps) and the energy deposited
+// outside any step (nuclear-event local deposits, sub-cut-off rests).
+constexpr uint32_t kScoreLet = 1u << 8;
+
 // One plan: its geometry (voxel record = {density as float bits, material
 // bin}), its dose tally and its random-number key.  64 bytes.
 struct PlanDesc {
@@ -48,7 +55,7 @@ struct PlanDesc {
     float vs[3];        // voxel size, cm
     float ivs[3];       // 1 / voxel size
     const uint2* vox;
-    double* tally;      // [nvox][k_batches] weighted MeV
+    double* tally;      // [nvox][k_batches] weighted MeV (+ 2 x [nvox] with LET_d scoring)
     uint32_t key_lo, key_hi;
 };
 static_assert(sizeof(PlanDesc) == 64, "PlanDesc is 16 words");

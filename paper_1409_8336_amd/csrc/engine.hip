@@ -27,7 +27,8 @@ hipError_t launch_transport(const KernelArgs& a, bool multi, int grid, int block
 hipError_t transport_occupancy(bool multi, int block, size_t lds_bytes, int* blocks_per_cu);
 hipError_t transport_max_block(bool multi, int* max_threads);
 hipError_t launch_stats(const double* tally, const uint2* vox, unsigned long long nvox, int K,
-                        double conv0, double* dose, double* var, double* dep_sum, hipStream_t s);
+                        double conv0, double* dose, double* var, double* dep_sum, double* let,
+                        hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_density(const uint2* vox, unsigned long long nvox, float* rho, hipStream_t s);
 hipError_t launch_atomic_probe(double* tally, int nx, int ny, int nz, int K, int grid,
@@ -87,6 +88,7 @@ struct PlanIn {
     double* d_dose;
     double* d_var;
     pmc_summary* summary;
+    double* d_let;   // LET_d output (nvox doubles) or NULL
 };
 
 }  // namespace
@@ -109,7 +111,7 @@ struct pmc_ctx {
     // device tables
     DevBuf<float> d_blob, d_el_sig, d_npg, d_elem, d_mult, d_floc, d_xcdf, d_mucdf;
     // run buffers
-    DevBuf<double> d_dose, d_var, d_ledger;
+    DevBuf<double> d_dose, d_var, d_let, d_ledger;
     DevBuf<uint32_t> d_q[2];
     DevBuf<unsigned long long> d_gc, d_counters, d_order, d_wgc;
     DevBuf<uint32_t> d_qloc;   // per-workgroup secondary queues
@@ -346,6 +348,11 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
 {
     const int K = c->p.k_batches;
     const int np = (int)plans.size();
+    // LET_d is scored for the whole launch when any plan asks for it: every
+    // plan's tally then carries the two LET planes after its dose groups
+    bool let = false;
+    for (const PlanIn& q : plans) let = let || q.d_let != nullptr;
+    const int planes = K + (let ? 2 : 0);
     for (int p = 0; p < np; ++p)
         for (int q = 0; q < p; ++q)
             if (plans[p].g == plans[q].g) return fail(c, PMC_ERR_ARG, "two plans of one run share a geometry");
@@ -411,7 +418,7 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
     std::vector<PlanDesc> pd(np);
     for (int p = 0; p < np; ++p) {
         Geometry& g = *plans[p].g;
-        HIPCHK(g.tally.ensure(g.nvox() * K), "alloc tally");
+        HIPCHK(g.tally.ensure(g.nvox() * planes), "alloc tally");
         PlanDesc& d = pd[p];
         std::memset(&d, 0, sizeof(d));
         d.nx = g.nx; d.ny = g.ny; d.nz = g.nz;
@@ -433,7 +440,8 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
     HIPCHK(hipMemcpyAsync(c->d_order.p, order.data(), order.size() * 8, hipMemcpyHostToDevice, st), "upload spots");
     HIPCHK(hipMemcpyAsync(c->d_plans.p, pd.data(), np * sizeof(PlanDesc), hipMemcpyHostToDevice, st), "upload plans");
     HIPCHK(hipEventRecord(c->ev0, st), "event");
-    for (int p = 0; p < np; ++p) HIPCHK(launch_zero(pd[p].tally, plans[p].g->nvox() * K * 8, st), "zero tally");
+    for (int p = 0; p < np; ++p)
+        HIPCHK(launch_zero(pd[p].tally, plans[p].g->nvox() * planes * 8, st), "zero tally");
     HIPCHK(launch_zero(c->d_gc.p, c->d_gc.n * 8, st), "zero counters");
     HIPCHK(launch_zero(c->d_counters.p, 8 * (size_t)kPlanCounters * np, st), "zero counters");
     HIPCHK(launch_zero(c->d_ledger.p, 32 * (size_t)np, st), "zero ledger");
@@ -453,7 +461,7 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
     a.el_sig = c->d_el_sig.p; a.mat_npg = c->d_npg.p; a.elem = c->d_elem.p;
     a.sec_mult = c->d_mult.p; a.sec_floc = c->d_floc.p; a.sec_x = c->d_xcdf.p; a.sec_mu = c->d_mucdf.p;
     a.k_batches = K;
-    a.flags = c->p.flags;
+    a.flags = c->p.flags | (let ? kScoreLet : 0u);
     a.f_mcs = (float)c->p.f_mcs;
     a.s_min = (float)c->p.s_min_cm;
     a.spots = c->d_spots.p;
@@ -469,14 +477,15 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
 
     const int block = shape.block;
     const size_t lds_words = (size_t)(multi ? a.pd_offset + 16 * np : a.blob_words);
-    // deposit cache: 12 bytes per slot (16 in a batch of plans: 64-bit keys),
-    // sized from what the tables leave of the CU's 160 KiB LDS at 16 waves
-    // per CU; every tally index must fit 32 bits
+    // deposit cache: 12 bytes per slot (16 in a batch of plans: 64-bit keys;
+    // 4 more with LET_d scoring: the slot's float LET numerator), sized from
+    // what the tables leave of the CU's 160 KiB LDS at 16 waves per CU; every
+    // tally index must fit 32 bits
     int slots = 0;
-    const int key_words = multi ? 2 : 1;
+    const int key_num_words = (multi ? 2 : 1) + (let ? 1 : 0);
     const int want = c->p.tally_cache != 0 ? c->p.tally_cache : shape.cache;
     bool small = true;
-    for (const PlanIn& q : plans) small = small && q.g->nvox() * (unsigned long long)K < 0xFFFFFFFFull;
+    for (const PlanIn& q : plans) small = small && q.g->nvox() * (unsigned long long)planes < 0xFFFFFFFFull;
     if (want >= 0 && small) {
         slots = want;
         if (slots == 0) {
@@ -487,7 +496,7 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
             const long cache_off_bytes = 4L * (long)((lds_words + 1) & ~(size_t)1);
             const long avail = 163840L / wgs - cache_off_bytes - 4L * kWgCtlWords - 8 - (long)sizeof(LdsArgs) -
                                (multi ? (long)kPlanLdsBytes * np : 0L);
-            slots = (int)std::min(16384L, avail / (4L * (2 + key_words)));
+            slots = (int)std::min(16384L, avail / (4L * (2 + key_num_words)));
             if (slots < 512) slots = 0;
         }
     }
@@ -496,7 +505,7 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
     a.epoch_iters = c->p.epoch_steps ? c->p.epoch_steps : 32;
     a.cache_probes = c->p.cache_probes ? c->p.cache_probes : 3;
     // (the workgroup's control words follow the cache, also without one)
-    const size_t used = (size_t)a.cache_off + (size_t)(2 + key_words) * slots + kWgCtlWords;
+    const size_t used = (size_t)a.cache_off + (size_t)(2 + key_num_words) * slots + kWgCtlWords;
     a.args_off = (int)((used + 1) & ~(size_t)1);
     // batched launches: per-plan ledger and counters after the arguments
     const size_t lds = (size_t)a.args_off * 4 + sizeof(LdsArgs) + (multi ? kPlanLdsBytes * (size_t)np : 0);
@@ -572,7 +581,7 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
             const double vol = (double)g.vs[0] * g.vs[1] * g.vs[2];
             const double conv0 = wtot[p] > 0.0 ? 1.602176634e-10 / (vol * wtot[p]) : 0.0;
             HIPCHK(launch_stats(g.tally.p, g.vox.p, g.nvox(), K, conv0, plans[p].d_dose, plans[p].d_var,
-                                c->d_ledger.p + 4 * p + 3, st), "stats launch");
+                                c->d_ledger.p + 4 * p + 3, plans[p].d_let, st), "stats launch");
         }
     }
     HIPCHK(hipEventRecord(c->ev1, st), "event");
@@ -659,7 +668,9 @@ pmc_status choose_shape(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, hipS
         return PMC_OK;
     }
     auto log2i = [](unsigned long long v) { int l = 0; while (v >>= 1) ++l; return l; };
-    const auto key = std::make_tuple((int)multi, (int)plans.size(), log2i(total), log2i(vox));
+    bool let = false;
+    for (const PlanIn& p : plans) let = let || p.d_let != nullptr;
+    const auto key = std::make_tuple((int)multi + 2 * (int)let, (int)plans.size(), log2i(total), log2i(vox));
     auto it = c->tuned.find(key);
     if (it != c->tuned.end()) {
         *out = it->second;
@@ -972,7 +983,20 @@ pmc_status pmc_run_spots_dev(pmc_ctx* c, const pmc_spot* spots, int n_spots, uin
     if (!c) return PMC_ERR_ARG;
     if (!d_dose) return fail(c, PMC_ERR_ARG, "d_dose is NULL");
     if (!c->have_phys || !have_geometry(c)) return fail(c, PMC_ERR_STATE, "load physics and geometry first");
-    std::vector<PlanIn> plans{{c->geoms[0].get(), spots, n_spots, n_histories, seed, d_dose, d_var, summary}};
+    std::vector<PlanIn> plans{{c->geoms[0].get(), spots, n_spots, n_histories, seed, d_dose, d_var, summary,
+                               nullptr}};
+    return run_plans_impl(c, plans, false, (hipStream_t)hip_stream);
+}
+
+pmc_status pmc_run_spots_let_dev(pmc_ctx* c, const pmc_spot* spots, int n_spots, uint64_t n_histories,
+                                 uint64_t seed, double* d_dose, double* d_var, double* d_let,
+                                 void* hip_stream, pmc_summary* summary)
+{
+    if (!c) return PMC_ERR_ARG;
+    if (!d_dose || !d_let) return fail(c, PMC_ERR_ARG, "d_dose or d_let is NULL");
+    if (!c->have_phys || !have_geometry(c)) return fail(c, PMC_ERR_STATE, "load physics and geometry first");
+    std::vector<PlanIn> plans{{c->geoms[0].get(), spots, n_spots, n_histories, seed, d_dose, d_var, summary,
+                               d_let}};
     return run_plans_impl(c, plans, false, (hipStream_t)hip_stream);
 }
 
@@ -986,11 +1010,34 @@ pmc_status pmc_run_spots(pmc_ctx* c, const pmc_spot* spots, int n_spots, uint64_
     const size_t nv = c->geoms[0]->nvox();
     HIPCHK(c->d_dose.ensure(nv), "alloc dose");
     HIPCHK(c->d_var.ensure(nv), "alloc var");
-    std::vector<PlanIn> plans{{c->geoms[0].get(), spots, n_spots, n_histories, seed, c->d_dose.p, c->d_var.p, summary}};
+    std::vector<PlanIn> plans{{c->geoms[0].get(), spots, n_spots, n_histories, seed, c->d_dose.p, c->d_var.p, summary,
+                               nullptr}};
     pmc_status s = run_plans_impl(c, plans, false, nullptr);
     if (s != PMC_OK && s != PMC_ERR_QUEUE_OVERFLOW) return s;
     HIPCHK(hipMemcpy(dose_out, c->d_dose.p, nv * 8, hipMemcpyDeviceToHost), "read dose");
     HIPCHK(hipMemcpy(var_out, c->d_var.p, nv * 8, hipMemcpyDeviceToHost), "read variance");
+    return s;
+}
+
+pmc_status pmc_run_spots_let(pmc_ctx* c, const pmc_spot* spots, int n_spots, uint64_t n_histories,
+                             uint64_t seed, double* dose_out, double* var_out, double* let_out,
+                             pmc_summary* summary)
+{
+    if (!c) return PMC_ERR_ARG;
+    if (!dose_out || !var_out || !let_out) return fail(c, PMC_ERR_ARG, "dose/var/let output is NULL");
+    if (!c->have_phys || !have_geometry(c)) return fail(c, PMC_ERR_STATE, "load physics and geometry first");
+    HIPCHK(hipSetDevice(c->device), "set device");
+    const size_t nv = c->geoms[0]->nvox();
+    HIPCHK(c->d_dose.ensure(nv), "alloc dose");
+    HIPCHK(c->d_var.ensure(nv), "alloc var");
+    HIPCHK(c->d_let.ensure(nv), "alloc let");
+    std::vector<PlanIn> plans{{c->geoms[0].get(), spots, n_spots, n_histories, seed, c->d_dose.p, c->d_var.p, summary,
+                               c->d_let.p}};
+    pmc_status s = run_plans_impl(c, plans, false, nullptr);
+    if (s != PMC_OK && s != PMC_ERR_QUEUE_OVERFLOW) return s;
+    HIPCHK(hipMemcpy(dose_out, c->d_dose.p, nv * 8, hipMemcpyDeviceToHost), "read dose");
+    HIPCHK(hipMemcpy(var_out, c->d_var.p, nv * 8, hipMemcpyDeviceToHost), "read variance");
+    HIPCHK(hipMemcpy(let_out, c->d_let.p, nv * 8, hipMemcpyDeviceToHost), "read LET");
     return s;
 }
 
@@ -1006,7 +1053,7 @@ pmc_status pmc_run_plans(pmc_ctx* c, const pmc_plan* plans, int n_plans, uint64_
             return fail(c, PMC_ERR_ARG, "unknown geometry_id");
         if (!q.d_dose) return fail(c, PMC_ERR_ARG, "plan d_dose is NULL");
         v.push_back({c->geoms[q.geometry_id].get(), q.spots, q.n_spots, q.n_histories, seed + (uint64_t)p,
-                     q.d_dose, q.d_var, q.summary});
+                     q.d_dose, q.d_var, q.summary, q.d_let});
     }
     return run_plans_impl(c, v, true, (hipStream_t)hip_stream);
 }

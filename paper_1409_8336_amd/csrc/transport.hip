@@ -252,15 +252,18 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
         for (int i = threadIdx.x; i < a.n_plans * 16; i += blockDim.x) dst[i] = src[i];
     }
     // deposit cache at an even word offset: slot values (double), slot keys
-    // (tally index; in a batch of plans, plan << 32 | tally index), then the
-    // workgroup's control words
+    // (tally index; in a batch of plans, plan << 32 | tally index), with
+    // LET_d scoring the slots' LET numerators (float partial sums, flushed to
+    // the FP64 numerator plane), then the workgroup's control words
     using Key = std::conditional_t<kMulti, unsigned long long, uint32_t>;
     constexpr Key kEmptySlot = ~Key(0);
     const int n_slots = a.cache_slots;
     const bool use_cache = n_slots > 0;
+    const bool score_let = (a.flags & kScoreLet) != 0u;
     double* const cval = reinterpret_cast<double*>(lds + a.cache_off);
     Key* const ckey = reinterpret_cast<Key*>(lds + a.cache_off + 2 * n_slots);
-    uint32_t* const ctl = reinterpret_cast<uint32_t*>(ckey + n_slots);
+    float* const cnum = reinterpret_cast<float*>(ckey + n_slots);
+    uint32_t* const ctl = reinterpret_cast<uint32_t*>(cnum + (score_let ? n_slots : 0));
     uint32_t* const loc_produced = ctl + 0;   // entries reserved in the own queue
     uint32_t* const loc_claimed = ctl + 1;    // entries taken by lanes
     uint32_t* const loc_avail = ctl + 2;      // entries published (written before the last epoch end)
@@ -270,6 +273,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
     for (int i = threadIdx.x; i < n_slots; i += blockDim.x) {
         cval[i] = 0.0;
         ckey[i] = kEmptySlot;
+        if (score_let) cnum[i] = 0.f;
     }
     if (threadIdx.x < kWgCtlWords) ctl[threadIdx.x] = 0u;
     LdsArgs* const L = reinterpret_cast<LdsArgs*>(lds + a.args_off);
@@ -379,8 +383,11 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
     };
     // one deposit into tally element idx of the current plan: through the
     // workgroup's LDS cache when the slot is free or already holds idx,
-    // else straight to the FP64 tally
-    auto deposit = [&](unsigned long long idx, double v) {
+    // else straight to the FP64 tally.  With a LET_d numerator (a step's
+    // deposit, idx = voxel * K + group) the numerator shares the dose's slot,
+    // or goes to the numerator plane element num_idx beside it.
+    auto deposit = [&](unsigned long long idx, double v, bool with_num = false, double num = 0.0,
+                       unsigned long long num_idx = 0ull) {
         ++n_dep;
         if (use_cache) {
             Key key = (Key)(uint32_t)idx;
@@ -409,11 +416,26 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
             }
             if (hit) {
                 unsafeAtomicAdd(&cval[slot], v);
+                if (with_num) atomicAdd(&cnum[slot], (float)num);
                 return;
             }
         }
         __hip_atomic_fetch_add(gbl(P.tally(plan)) + idx, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         ++n_glob;
+        if (with_num) {
+            __hip_atomic_fetch_add(gbl(P.tally(plan)) + num_idx, num, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ++n_glob;
+        }
+    };
+    // a deposit that belongs to no proton step (Sec. III LET_d leaves out
+    // such local deposits): into the dose, and with LET_d scoring also into
+    // the plane that the LET denominator subtracts from the dose
+    auto deposit_local = [&](unsigned long long vi, double v) {
+        deposit(vi * K + batch, v);
+        if (flags & kScoreLet) {
+            const unsigned long long nv = (unsigned long long)P.nx(plan) * P.ny(plan) * P.nz(plan);
+            deposit(nv * (K + 1) + vi, v);
+        }
     };
     bool exhausted = false;
     uint32_t epoch = 0;
@@ -758,8 +780,17 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
             pz = on_face && axis == 2 ? face : pz;
             const float e_new = E - de;
             // range-limited: the proton stops in this voxel with all of E
-            deposit(vi * K + batch,
-                    stop_here ? (double)w * (double)E : (double)w * ((double)E - (double)e_new));
+            const double dep = stop_here ? (double)w * (double)E : (double)w * ((double)E - (double)e_new);
+            if (flags & kScoreLet) {
+                // LET_d numerator: the deposit times the medium's stopping
+                // power averaged over the step's mean loss (over the residual
+                // range when the range ends the step), MeV/cm
+                const float l = stop_here ? (E - kECut) * frcp(s_range) : de_mean * frcp(s);
+                const unsigned long long nv = (unsigned long long)P.nx(plan) * P.ny(plan) * P.nz(plan);
+                deposit(vi * K + batch, dep, true, dep * (double)l, nv * K + vi);
+            } else {
+                deposit(vi * K + batch, dep);
+            }
             if (stop_here) {
                 alive = false;
             } else {
@@ -772,7 +803,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                 if (E <= kECut || k >= kMaxSteps) {
                     // below the cut-off (or past the step cap that guards
                     // against non-terminating histories): deposit the rest
-                    deposit(vi * K + batch, (double)w * (double)E);
+                    deposit_local(vi, (double)w * (double)E);
                     alive = false;
                 } else if (!inside) {
                     acc_esc += (double)w * (double)E;
@@ -884,7 +915,6 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                     const float phi = u01(r4.y);
                     const float tn_f = tn;
                     const float tr_f = T - tn_f;
-                    const unsigned long long vi2 = vi * K + batch;
                     if (el == 0 && tr_f > kECut) {
                         recoil = true;
                         ce0 = tr_f;
@@ -895,15 +925,15 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                         rotate(rdx, rdy, rdz, cr, sr, phi + 0.5f);
                         const double resid = (double)T - (double)tn_f - (double)tr_f;
                         if (resid != 0.0) {
-                            deposit(vi2, (double)w * resid);
+                            deposit_local(vi, (double)w * resid);
                         }
                     } else {
-                        deposit(vi2, (double)w * ((double)T - (double)tn_f));
+                        deposit_local(vi, (double)w * ((double)T - (double)tn_f));
                     }
                     rotate(ux, uy, uz, ct, st, phi);
                     E = tn_f;
                     if (E <= kECut) {
-                        deposit(vi2, (double)w * (double)E);
+                        deposit_local(vi, (double)w * (double)E);
                         alive = false;
                     } else {
                         mfp = -fln(u01(r3.w));
@@ -951,7 +981,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                     if (n > 2 && ce2 <= kECut) { local += ce2; ce2 = 0.f; }
                     if (n > 3 && ce3 <= kECut) { local += ce3; ce3 = 0.f; }
                     n_out = (ce0 > 0.f) + (ce1 > 0.f) + (ce2 > 0.f) + (ce3 > 0.f);
-                    deposit(vi * K + batch, (double)w * local);
+                    deposit_local(vi, (double)w * local);
                     acc_neu += (double)w * ((double)T - loc - carried);
                     alive = false;
                 }
@@ -1053,6 +1083,21 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
             else unsafeAtomicAdd(&a.single.tally[key], cval[i]);
             ++n_glob;
             ++n_flush;
+            if (score_let) {
+                // the slot's LET numerator, if it held step deposits (key =
+                // voxel * K + group), to element voxel of the numerator plane
+                const float nm = cnum[i];
+                if (nm != 0.f) {
+                    const uint32_t pk = kMulti ? (uint32_t)(key >> 32) : 0u;
+                    const uint32_t t = (uint32_t)key;
+                    const unsigned long long nv = (unsigned long long)P.nx(pk) * P.ny(pk) * P.nz(pk);
+                    __hip_atomic_fetch_add(gbl(P.tally(pk)) + nv * K + t / (uint32_t)K, (double)nm,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ++n_glob;
+                    ++n_flush;
+                }
+                cnum[i] = 0.f;
+            }
             ckey[i] = kEmptySlot;
             cval[i] = 0.0;
         }
@@ -1140,7 +1185,8 @@ hipError_t launch_atomic_probe(double* tally, int nx, int ny, int nz, int K, int
 }
 
 // dose statistics over the K groups: total, variance of the total, and the
-// deposited-energy sum (Sec. II.B.2)
+// deposited-energy sum (Sec. II.B.2); with LET_d scoring also the LET_d of
+// every voxel from the two planes after the groups
 // A block takes kStatsVox consecutive voxels at a time: their [voxel][K]
 // tally rows form one contiguous run, read with 16-byte unit-stride loads
 // into LDS rows padded to an odd number of doubles (fewer bank conflicts),
@@ -1151,7 +1197,9 @@ __global__ void __launch_bounds__(kStatsVox) stats_kernel(const double* __restri
                                                           unsigned long long nvox, int K, uint32_t k_magic,
                                                           double inv_k, double k_ratio, double conv0,
                                                           double* __restrict__ dose,
-                                                          double* __restrict__ var, double* dep_sum)
+                                                          double* __restrict__ var, double* dep_sum,
+                                                          const double* __restrict__ let_nd,
+                                                          double* __restrict__ let)
 {
     extern __shared__ double rows[];   // kStatsVox * (K | 1)
     const int pitch = K | 1;
@@ -1197,6 +1245,13 @@ __global__ void __launch_bounds__(kStatsVox) stats_kernel(const double* __restri
         dose[v] = tot * conv;
         if (var) var[v] = k_ratio * ss * conv * conv;
         part += tot;
+        if (let) {
+            // LET_d (keV/um; 1 MeV/cm = 0.1 keV/um): numerator over the
+            // energy of the proton steps, i.e. the dose minus what was
+            // deposited outside any step
+            const double num = let_nd[v], den = tot - let_nd[nvox + v];
+            let[v] = (num > 0.0 && den > 0.0) ? 0.1 * num / den : 0.0;
+        }
     }
     // one atomic per workgroup: the workgroups' partial sums all go to one
     // address, where memory-side atomics serialise (one per wave of 65536
@@ -1263,7 +1318,8 @@ hipError_t transport_occupancy(bool multi, int block, size_t lds_bytes, int* blo
 }
 
 hipError_t launch_stats(const double* tally, const uint2* vox, unsigned long long nvox, int K,
-                        double conv0, double* dose, double* var, double* dep_sum, hipStream_t s)
+                        double conv0, double* dose, double* var, double* dep_sum, double* let,
+                        hipStream_t s)
 {
     if (K < 2 || K > 64) return hipErrorInvalidValue;
     const size_t bytes = (size_t)kStatsVox * (K | 1) * sizeof(double);
@@ -1279,7 +1335,8 @@ hipError_t launch_stats(const double* tally, const uint2* vox, unsigned long lon
     if (blocks == 0) blocks = 1;
     const uint32_t k_magic = (uint32_t)((0x100000000ull + (unsigned)K - 1) / (unsigned)K);
     hipLaunchKernelGGL(stats_kernel, dim3((unsigned)blocks), dim3(kStatsVox), bytes, s, tally, vox, nvox, K,
-                       k_magic, 1.0 / K, (double)K / (K - 1), conv0, dose, var, dep_sum);
+                       k_magic, 1.0 / K, (double)K / (K - 1), conv0, dose, var, dep_sum,
+                       let ? tally + nvox * (unsigned long long)K : nullptr, let);
     return hipGetLastError();
 }
 

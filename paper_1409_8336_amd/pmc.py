@@ -23,7 +23,7 @@ PMC_NO_STRAGGLE, PMC_NO_MCS, PMC_NO_NUCLEAR = 1, 2, 4
 EXPORTS = ("pmc_default_params", "pmc_create", "pmc_destroy", "pmc_last_error",
            "pmc_load_physics", "pmc_load_geometry", "pmc_run_spots", "pmc_run_spots_dev",
            "pmc_inspect_tables", "pmc_atomic_probe", "pmc_load_geometry_slot", "pmc_run_plans",
-           "pmc_geometry_density", "pmc_version")
+           "pmc_geometry_density", "pmc_version", "pmc_run_spots_let", "pmc_run_spots_let_dev")
 
 
 class PMCError(RuntimeError):
@@ -77,7 +77,7 @@ class pmc_summary(C.Structure):
 class pmc_plan(C.Structure):
     _fields_ = [("geometry_id", C.c_int32), ("n_spots", C.c_int32), ("spots", C.c_void_p),
                 ("n_histories", C.c_uint64), ("d_dose", C.c_void_p), ("d_var", C.c_void_p),
-                ("summary", C.c_void_p)]
+                ("summary", C.c_void_p), ("d_let", C.c_void_p)]
 
 
 _lib = None
@@ -118,6 +118,9 @@ def lib():
                                         C.POINTER(pmc_material_table)]
         L.pmc_run_spots.argtypes = [vp, vp, i32, u64, u64, vp, vp, C.POINTER(pmc_summary)]
         L.pmc_run_spots_dev.argtypes = [vp, vp, i32, u64, u64, vp, vp, vp, C.POINTER(pmc_summary)]
+        L.pmc_run_spots_let.argtypes = [vp, vp, i32, u64, u64, vp, vp, vp, C.POINTER(pmc_summary)]
+        L.pmc_run_spots_let_dev.argtypes = [vp, vp, i32, u64, u64, vp, vp, vp, vp,
+                                            C.POINTER(pmc_summary)]
         L.pmc_inspect_tables.argtypes = [vp, vp, vp, vp, vp, vp]
         L.pmc_atomic_probe.argtypes = [vp, u64, vp, C.POINTER(C.c_double)]
         L.pmc_load_geometry_slot.argtypes = [vp, C.POINTER(C.c_int), vp, i32, i32, i32, C.c_float,
@@ -217,8 +220,8 @@ def pmc_load_geometry_slot(ctx, hu, voxel_cm, mt: dict) -> int:
 
 def pmc_run_plans(ctx, plans, seed, stream=None):
     """Batched run.  plans: list of dicts with geometry_id, spots, n_histories,
-    d_dose (and optional d_var) torch float64 device tensors.  Returns the
-    per-plan summaries."""
+    d_dose (and optional d_var, d_let) torch float64 device tensors.  Returns
+    the per-plan summaries."""
     import torch
     arr = (pmc_plan * len(plans))()
     keep, sums = [], []
@@ -229,16 +232,18 @@ def pmc_run_plans(ctx, plans, seed, stream=None):
         if d.dtype != torch.float64 or not d.is_cuda or not d.is_contiguous():
             raise ValueError("d_dose must be a contiguous float64 device tensor")
         _need_numel(ctx, p["geometry_id"], d, "d_dose")
-        v = p.get("d_var")
-        if v is not None:
-            if v.dtype != torch.float64 or not v.is_cuda or not v.is_contiguous():
-                raise ValueError("d_var must be a contiguous float64 device tensor")
-            _need_numel(ctx, p["geometry_id"], v, "d_var")
+        opt = {}
+        for name in ("d_var", "d_let"):
+            v = p.get(name)
+            if v is not None:
+                if v.dtype != torch.float64 or not v.is_cuda or not v.is_contiguous():
+                    raise ValueError("%s must be a contiguous float64 device tensor" % name)
+                _need_numel(ctx, p["geometry_id"], v, name)
+                opt[name] = v.data_ptr()
         sm = pmc_summary()
         sums.append(sm)
         arr[i] = pmc_plan(int(p["geometry_id"]), len(sp), sp.ctypes.data, int(p["n_histories"]),
-                          d.data_ptr(), v.data_ptr() if v is not None else None,
-                          C.addressof(sm))
+                          d.data_ptr(), opt.get("d_var"), C.addressof(sm), opt.get("d_let"))
     if stream is None:
         stream = torch.cuda.current_stream()
     handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
@@ -264,6 +269,43 @@ def pmc_run_spots(ctx, spots, n_histories, seed, shape):
                              _ptr(var), C.byref(s))
     _check(ctx, st)
     return dose, var, summary_dict(s)
+
+
+def pmc_run_spots_let(ctx, spots, n_histories, seed, shape):
+    """Host-buffer run with dose-averaged LET: returns (dose, var, let in
+    keV/um, summary)."""
+    sp = _spots(spots)
+    dose = np.zeros(shape, np.float64)
+    var = np.zeros(shape, np.float64)
+    let = np.zeros(shape, np.float64)
+    s = pmc_summary()
+    st = lib().pmc_run_spots_let(ctx, _ptr(sp), len(sp), int(n_histories), int(seed), _ptr(dose),
+                                 _ptr(var), _ptr(let), C.byref(s))
+    _check(ctx, st)
+    return dose, var, let, summary_dict(s)
+
+
+def pmc_run_spots_let_dev(ctx, spots, n_histories, seed, d_dose, d_let, d_var=None, stream=None):
+    """As pmc_run_spots_dev, with LET_d (keV/um) into the float64 device
+    tensor d_let of the geometry's voxel count."""
+    import torch
+    sp = _spots(spots)
+    for name, t in (("d_dose", d_dose), ("d_let", d_let), ("d_var", d_var)):
+        if t is None and name == "d_var":
+            continue
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("%s must be a contiguous float64 device tensor" % name)
+        _need_numel(ctx, 0, t, name)
+    if stream is None:
+        stream = torch.cuda.current_stream(d_dose.device)
+    handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+    s = pmc_summary()
+    st = lib().pmc_run_spots_let_dev(ctx, _ptr(sp), len(sp), int(n_histories), int(seed),
+                                     C.c_void_p(d_dose.data_ptr()),
+                                     C.c_void_p(d_var.data_ptr()) if d_var is not None else None,
+                                     C.c_void_p(d_let.data_ptr()), C.c_void_p(handle), C.byref(s))
+    _check(ctx, st)
+    return summary_dict(s)
 
 
 def pmc_run_spots_dev(ctx, spots, n_histories, seed, d_dose, d_var=None, stream=None):
@@ -357,3 +399,10 @@ class Engine:
 
     def run_spots_dev(self, spots, n_histories, seed, d_dose, d_var=None, stream=None):
         return pmc_run_spots_dev(self.ctx, spots, n_histories, seed, d_dose, d_var, stream)
+
+    def run_spots_let(self, spots, n_histories, seed):
+        return pmc_run_spots_let(self.ctx, spots, n_histories, seed, self.shape)
+
+    def run_spots_let_dev(self, spots, n_histories, seed, d_dose, d_let, d_var=None, stream=None):
+        return pmc_run_spots_let_dev(self.ctx, spots, n_histories, seed, d_dose, d_let, d_var,
+                                     stream)
