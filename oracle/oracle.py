@@ -17,7 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "pmc_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
-NO_STRAGGLE, NO_MCS, NO_NUCLEAR = 1, 2, 4
+NO_STRAGGLE, NO_MCS, NO_NUCLEAR, VAVILOV = 1, 2, 4, 8
+VAV_SHAPE = (5, 31, 97)   # [beta^2 = k/10][log10 kappa = -2 + j/10][z = -6 + i/8]
 _lock = threading.Lock()
 _lib = None
 
@@ -101,6 +102,13 @@ def lib():
                 f = getattr(L, name)
                 f.argtypes = args
                 f.restype = d
+            for name, args in [("oracle_vavilov_cdf", [d, d, d]),
+                               ("oracle_vavilov_kappa", [d, d, d, d]),
+                               ("oracle_vavilov_quantile", [C.c_void_p, d, d, d])]:
+                f = getattr(L, name)
+                f.argtypes = args
+                f.restype = d
+            L.oracle_vavilov_table.argtypes = [C.c_void_p]
             L.oracle_material_info.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_double)]
             L.oracle_elastic_sample.argtypes = [C.c_int, d, d, d, C.POINTER(C.c_double)]
             L.oracle_secondary_sample.argtypes = [C.c_void_p, C.c_int, d, C.c_uint64, C.c_uint32,
@@ -130,6 +138,24 @@ def elastic_sample(mass_number, t_mev, u_comp, u_t):
     out = (C.c_double * 7)()
     lib().oracle_elastic_sample(int(mass_number), t_mev, u_comp, u_t, out)
     return list(out)
+
+
+def vavilov_cdf(kappa, beta2, x):
+    """P(X <= x), X = (energy loss - mean) / T_max in Vavilov's model."""
+    return lib().oracle_vavilov_cdf(float(kappa), float(beta2), float(x))
+
+
+def vavilov_table():
+    """Quantile nodes G of the standardised Vavilov variable, VAV_SHAPE."""
+    out = np.zeros(VAV_SHAPE, dtype=np.float64)
+    rc = lib().oracle_vavilov_table(_ptr(out))
+    if rc:
+        raise ValueError("oracle_vavilov_table failed: %d" % rc)
+    return out
+
+
+def vavilov_kappa(t_mev, s_cm, rho, za):
+    return lib().oracle_vavilov_kappa(float(t_mev), float(s_cm), float(rho), float(za))
 
 
 def rotate(d, ct, st, phi_rev):
@@ -238,6 +264,10 @@ class Oracle:
         return out
 
     # ---- pieces for pins ----
+    def vavilov_quantile(self, kappa, beta2, z):
+        """The transport's Vavilov draw for normal score z (flags VAVILOV)."""
+        return lib().oracle_vavilov_quantile(self.h, float(kappa), float(beta2), float(z))
+
     def range(self, t_mev, table=0):
         return lib().oracle_range(self.h, table, float(t_mev))
 

@@ -65,6 +65,8 @@ static const int EL_MASS_NUMBER[ORA_NEL] = {1, 12, 14, 16, 31, 40, 48};
 
 enum { LIM_NUC = 0, LIM_BND = 1 };
 
+static double vav_quantile(const double* t, double kappa, double beta2, double z);
+
 /* ======================================================================
  * Random numbers: Philox4x32-10 (Salmon et al., SC'11), keyed by the run
  * seed, counter = (uid lo, uid hi, step index k, tag).  Tags: 0 birth,
@@ -338,6 +340,7 @@ struct ora_ctx {
     double xcdf[ORA_SEC_NUCLEI][ORA_SEC_EBINS][ORA_SEC_NCDF + 1];
     double mucdf[ORA_SEC_NUCLEI][ORA_SEC_EBINS][ORA_SEC_NCDF + 1];
     rtable water;
+    double* vav;                         /* Vavilov quantile nodes (ORA_VAVILOV) */
     int nmat;
     omat mat[16];
     int n[3];
@@ -355,8 +358,23 @@ int oracle_create(ora_ctx** out, const ora_params* p)
     if (!c) return -3;
     c->p = *p;
     if (rt_build(&c->water, oracle_water_z_over_a(), WATER_I_EV)) { free(c); return -3; }
+    if (p->flags & ORA_VAVILOV) {
+        c->vav = (double*)malloc(sizeof(double) * ORA_VAV_NB * ORA_VAV_NK * ORA_VAV_NZ);
+        if (!c->vav || oracle_vavilov_table(c->vav)) {
+            free(c->vav);
+            rt_free(&c->water);
+            free(c);
+            return -3;
+        }
+    }
     *out = c;
     return 0;
+}
+
+double oracle_vavilov_quantile(const ora_ctx* c, double kappa, double beta2, double z)
+{
+    if (!c || !c->vav) return NAN;
+    return vav_quantile(c->vav, kappa, beta2, z);
 }
 
 static void free_geometry(ora_ctx* c)
@@ -372,6 +390,7 @@ int oracle_destroy(ora_ctx* c)
     if (!c) return 0;
     free_geometry(c);
     rt_free(&c->water);
+    free(c->vav);
     free(c);
     return 0;
 }
@@ -546,6 +565,250 @@ double oracle_straggling_variance(double t, double s, double rho, double za)
     double e_tot = t + M_PROTON;
     double beta2 = t * (t + 2.0 * M_PROTON) / (e_tot * e_tot);
     return K_BETHE * M_ELECTRON * rho * za * s * gamma * gamma * (1.0 - 0.5 * beta2);
+}
+
+/* ======================================================================
+ * Vavilov straggling (Sec. II.A.2: a Vavilov-Gaussian model of the energy
+ * loss fluctuations)
+ *
+ * The loss of a step is <Delta> + sigma W, sigma^2 the Bohr variance above
+ * and W standardised (mean 0, variance 1).  With the Vavilov parameter
+ * kappa = xi / T_max in [0.01, 10), W follows Vavilov's distribution for
+ * (kappa, beta^2); outside that range W is standard normal.  Vavilov's
+ * model: free-electron collisions with energy transfers v T_max, v in
+ * (0, 1], occurring with density kappa (1 - beta^2 v) / v^2.  Then
+ * X = (Delta - <Delta>) / T_max has
+ *   ln E[exp(i t X)] = kappa (A(t) + i B(t)),
+ *   A(t) = Int_0^1 (1 - beta^2 v)(cos tv - 1) / v^2 dv,
+ *   B(t) = Int_0^1 (1 - beta^2 v)(sin tv - tv) / v^2 dv,
+ * and W = X / sqrt(kappa (1 - beta^2 / 2)).  Here A and B come from running
+ * integrals of the integrands after substituting x = t v:
+ *   A = t J2(t) - beta^2 J1(t),  B = t K2(t) - beta^2 K1(t),
+ *   J2 = Int_0^t (cos x - 1)/x^2, J1 = Int_0^t (cos x - 1)/x,
+ *   K2 = Int_0^t (sin x - x)/x^2, K1 = Int_0^t (sin x - x)/x,
+ * accumulated by Simpson's rule, and the distribution function from the
+ * Gil-Pelaez inversion
+ *   F(x) = 1/2 - (1/pi) Int_0^inf exp(kappa A) sin(kappa B - t x) / t dt.
+ * The sampler maps z = Phi^-1(u) through the quantile function
+ * W = G(z) = F_W^-1(Phi(z)), tabulated at z = -6 + i/8 (97 nodes),
+ * log10 kappa = -2 + j/10 (31 nodes) and beta^2 = k/10 (k = 0..4), and
+ * interpolated trilinearly (beta^2 clamped to [0, 0.4]).
+ * ====================================================================== */
+#define VAV_DU 0.01              /* running-integral step */
+#define VAV_UMAX 12000.0         /* supports kappa >= 0.0025 */
+static double* vav_run = NULL;   /* [n][4]: J2, J1, K2, K1 at u = k VAV_DU */
+static long vav_n = 0;
+
+static void vav_integrands(double x, double f[4])
+{
+    if (x < 0.02) {              /* series: the closed forms cancel badly near 0 */
+        double x2 = x * x;
+        f[0] = -0.5 + x2 / 24.0 - x2 * x2 / 720.0;
+        f[1] = x * (-0.5 + x2 / 24.0 - x2 * x2 / 720.0);
+        f[2] = x * (-1.0 / 6.0 + x2 / 120.0 - x2 * x2 / 5040.0);
+        f[3] = x2 * (-1.0 / 6.0 + x2 / 120.0 - x2 * x2 / 5040.0);
+        return;
+    }
+    double c = cos(x) - 1.0, sn = sin(x) - x;
+    f[0] = c / (x * x);
+    f[1] = c / x;
+    f[2] = sn / (x * x);
+    f[3] = sn / x;
+}
+
+static int vav_build_running(void)
+{
+    int ok = 1;
+#pragma omp critical(vav_running)
+    {
+        if (!vav_run) {
+            long n = (long)(VAV_UMAX / VAV_DU) + 2;
+            double* r = (double*)malloc(sizeof(double) * 4 * (size_t)n);
+            if (!r) ok = 0;
+            else {
+                double acc[4] = {0, 0, 0, 0}, f0[4], fm[4], f1[4];
+                vav_integrands(0.0, f0);
+                for (int q = 0; q < 4; ++q) r[q] = 0.0;
+                for (long k = 1; k < n; ++k) {
+                    double a = (k - 1) * VAV_DU, b = k * VAV_DU;
+                    vav_integrands(0.5 * (a + b), fm);
+                    vav_integrands(b, f1);
+                    for (int q = 0; q < 4; ++q) {
+                        acc[q] += VAV_DU / 6.0 * (f0[q] + 4.0 * fm[q] + f1[q]);
+                        r[4 * k + q] = acc[q];
+                        f0[q] = f1[q];
+                    }
+                }
+                vav_n = n;
+                vav_run = r;
+            }
+        }
+    }
+    return ok && vav_run != NULL;
+}
+
+/* kappa A and kappa B at t = k VAV_DU */
+static void vav_ab(long k, double kappa, double beta2, double* ka, double* kb)
+{
+    const double t = k * VAV_DU;
+    const double* r = vav_run + 4 * k;
+    *ka = kappa * (t * r[0] - beta2 * r[1]);
+    *kb = kappa * (t * r[2] - beta2 * r[3]);
+}
+
+/* support window of X used for the inversion step: the distribution has
+ * negligible mass (far below 1e-9) outside it */
+static void vav_window(double kappa, double* lo, double* hi)
+{
+    *lo = -8.0 * sqrt(kappa) - 0.1;
+    *hi = 4.0 + 8.0 * sqrt(kappa);
+}
+
+/* Gil-Pelaez sums for the points x[0..nx): F[i] = P(X <= x[i]) */
+static int vav_cdf_points(double kappa, double beta2, const double* x, int nx, double* F)
+{
+    if (!(kappa > 0.0) || beta2 < 0.0 || beta2 >= 1.0 || !vav_build_running()) return -1;
+    double lo, hi;
+    vav_window(kappa, &lo, &hi);
+    /* midpoint rule, step dt = 2 m VAV_DU with 2 pi / dt at least twice the window */
+    long m = (long)floor(M_PI / (hi - lo) / (2.0 * VAV_DU));
+    if (m < 1) m = 1;
+    const double dt = 2.0 * m * VAV_DU;
+    /* nodes t_j = (j + 1/2) dt = (2j + 1) m VAV_DU while exp(kappa A) > e^-45 */
+    long nt = 0;
+    while (1) {
+        long k = (2 * nt + 1) * m;
+        if (k >= vav_n) return -2;
+        double ka, kb;
+        vav_ab(k, kappa, beta2, &ka, &kb);
+        if (ka < -45.0) break;
+        ++nt;
+    }
+    double* amp = (double*)malloc(sizeof(double) * 3 * (size_t)(nt > 0 ? nt : 1));
+    if (!amp) return -3;
+    for (long j = 0; j < nt; ++j) {
+        long k = (2 * j + 1) * m;
+        double ka, kb;
+        vav_ab(k, kappa, beta2, &ka, &kb);
+        double t = k * VAV_DU;
+        amp[3 * j] = exp(ka) / t;
+        amp[3 * j + 1] = kb;
+        amp[3 * j + 2] = t;
+    }
+    for (int i = 0; i < nx; ++i) {
+        double sum = 0.0;
+        for (long j = 0; j < nt; ++j) sum += amp[3 * j] * sin(amp[3 * j + 1] - amp[3 * j + 2] * x[i]);
+        F[i] = 0.5 - sum * dt / M_PI;
+    }
+    free(amp);
+    return 0;
+}
+
+double oracle_vavilov_cdf(double kappa, double beta2, double x)
+{
+    double f;
+    if (vav_cdf_points(kappa, beta2, &x, 1, &f)) return NAN;
+    return f;
+}
+
+static double std_normal_cdf_z(double z) { return 0.5 * erfc(-z / sqrt(2.0)); }
+
+/* quantile nodes of W for one (kappa, beta^2): G[i] at z = -6 + i/8 */
+static int vav_nodes(double kappa, double beta2, double* G)
+{
+    const double euler = 0.57721566490153286;
+    double lo, hi;
+    vav_window(kappa, &lo, &hi);
+    /* points: uniform in lambda = X/kappa - (1 - euler) - ln kappa (step
+     * 1/40) over the Landau-like core, then uniform in X to the window end */
+    const double l0 = fmax(-8.0, lo / kappa - (1.0 - euler) - log(kappa));
+    const double l_hi = hi / kappa - (1.0 - euler) - log(kappa);
+    const double l1 = fmin(25.0, l_hi);
+    int n1 = (int)ceil((l1 - l0) * 40.0) + 1, n2 = l_hi > l1 ? 400 : 0;
+    int nx = n1 + n2;
+    double* x = (double*)malloc(sizeof(double) * 2 * (size_t)nx);
+    if (!x) return -3;
+    double* F = x + nx;
+    for (int i = 0; i < n1; ++i) {
+        double l = l0 + (l1 - l0) * i / (n1 - 1);
+        x[i] = kappa * (l + (1.0 - euler) + log(kappa));
+    }
+    for (int i = 0; i < n2; ++i) x[n1 + i] = x[n1 - 1] + (hi - x[n1 - 1]) * (i + 1) / n2;
+    int rc = vav_cdf_points(kappa, beta2, x, nx, F);
+    if (rc) { free(x); return rc; }
+    for (int i = 0; i < nx; ++i) {          /* a distribution function: in [0, 1], non-decreasing */
+        if (F[i] < 0.0) F[i] = 0.0;
+        if (F[i] > 1.0) F[i] = 1.0;
+        if (i > 0 && F[i] < F[i - 1]) F[i] = F[i - 1];
+    }
+    const double c = sqrt(kappa * (1.0 - 0.5 * beta2));
+    int at = 0;
+    for (int q = 0; q < ORA_VAV_NZ; ++q) {
+        double u = std_normal_cdf_z(-6.0 + q / 8.0);
+        while (at < nx - 1 && F[at] < u) ++at;
+        double xq;
+        if (at == 0) xq = x[0];
+        else if (F[at] < u) xq = x[nx - 1];
+        else {
+            double fa = F[at - 1], fb = F[at];
+            xq = fb > fa ? x[at - 1] + (x[at] - x[at - 1]) * (u - fa) / (fb - fa) : x[at];
+        }
+        G[q] = xq / c;
+    }
+    free(x);
+    return 0;
+}
+
+int oracle_vavilov_table(double* out)
+{
+    if (!out) return -1;
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : bad)
+    for (int jb = 0; jb < ORA_VAV_NB * ORA_VAV_NK; ++jb) {
+        const int b = jb / ORA_VAV_NK, j = jb % ORA_VAV_NK;
+        const double kappa = pow(10.0, -2.0 + j / 10.0);
+        if (vav_nodes(kappa, 0.1 * b, out + (size_t)jb * ORA_VAV_NZ)) bad = 1;
+    }
+    return bad ? -2 : 0;
+}
+
+/* W for normal score z at (kappa, beta^2) from the table t (trilinear) */
+static double vav_quantile(const double* t, double kappa, double beta2, double z)
+{
+    if (!(kappa >= 0.01 && kappa < 10.0)) return z;
+    double fk = (log10(kappa) + 2.0) * 10.0;
+    int j = (int)floor(fk);
+    if (j > ORA_VAV_NK - 2) j = ORA_VAV_NK - 2;
+    fk -= j;
+    double fb = fmin(fmax(beta2, 0.0), 0.4) * 10.0;
+    int b = (int)floor(fb);
+    if (b > ORA_VAV_NB - 2) b = ORA_VAV_NB - 2;
+    fb -= b;
+    double fz = (z + 6.0) * 8.0;
+    int q = (int)floor(fz);
+    if (q < 0) q = 0;
+    if (q > ORA_VAV_NZ - 2) q = ORA_VAV_NZ - 2;
+    fz -= q;                      /* beyond the end nodes: linear extrapolation */
+    double acc = 0.0;
+    for (int db = 0; db < 2; ++db)
+        for (int dj = 0; dj < 2; ++dj) {
+            const double* row = t + ((size_t)(b + db) * ORA_VAV_NK + (j + dj)) * ORA_VAV_NZ;
+            double g = row[q] + fz * (row[q + 1] - row[q]);
+            acc += (db ? fb : 1.0 - fb) * (dj ? fk : 1.0 - fk) * g;
+        }
+    return acc;
+}
+
+/* Vavilov parameter of a step: xi / T_max */
+double oracle_vavilov_kappa(double t, double s, double rho, double za)
+{
+    const double gamma = 1.0 + t / M_PROTON;
+    const double e_tot = t + M_PROTON;
+    const double beta2 = t * (t + 2.0 * M_PROTON) / (e_tot * e_tot);
+    const double xi = 0.5 * K_BETHE * za * rho * s / beta2;
+    const double r = M_ELECTRON / M_PROTON;
+    const double tmax = 2.0 * M_ELECTRON * beta2 * gamma * gamma / (1.0 + 2.0 * gamma * r + r * r);
+    return xi / tmax;
 }
 
 void oracle_rotate(double d[3], double ct, double st, double phi_rev)
@@ -896,7 +1159,15 @@ static void transport(const ora_ctx* c, const orun* r, opart* q, ostack* st, oac
         double de = de_mean;
         if (!(flags & ORA_NO_STRAGGLE)) {
             double var = oracle_straggling_variance(e_mid, s, rho, m->za);
-            de = de_mean + sqrt(var) * oracle_normal_quantile(u[3]);
+            double z = oracle_normal_quantile(u[3]);
+            if (flags & ORA_VAVILOV) {
+                /* Vavilov-Gaussian: the normal score mapped through the
+                 * Vavilov quantile function of the step's (kappa, beta^2) */
+                const double e_tot = e_mid + M_PROTON;
+                const double b2 = e_mid * (e_mid + 2.0 * M_PROTON) / (e_tot * e_tot);
+                z = vav_quantile(c->vav, oracle_vavilov_kappa(e_mid, s, rho, m->za), b2, z);
+            }
+            de = de_mean + sqrt(var) * z;
             if (de < 0.0) de = 0.0;
             if (de > q->e) de = q->e;
         }

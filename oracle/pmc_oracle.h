@@ -32,7 +32,14 @@ extern "C" {
 #define ORA_SEC_MULT 5
 #define ORA_SEC_NCDF 32
 
-enum { ORA_NO_STRAGGLE = 1, ORA_NO_MCS = 2, ORA_NO_NUCLEAR = 4 };
+/* ORA_VAVILOV: Vavilov-Gaussian straggling instead of Gaussian (Sec. II.A.2) */
+enum { ORA_NO_STRAGGLE = 1, ORA_NO_MCS = 2, ORA_NO_NUCLEAR = 4, ORA_VAVILOV = 8 };
+
+/* Vavilov quantile table: [beta^2 = k/10, k < 5][log10 kappa = -2 + j/10, j < 31]
+   [z = -6 + i/8, i < 97] */
+#define ORA_VAV_NB 5
+#define ORA_VAV_NK 31
+#define ORA_VAV_NZ 97
 
 typedef struct {
     double f_mcs;        /* Highland multiplier (1.07, Sec. II.A.2) */
@@ -132,6 +139,15 @@ int oracle_secondary_sample(const ora_ctx* c, int element, double t_mev, uint64_
                             uint32_t k, uint64_t seed, double u_mult, int* n_out,
                             double e_out[4], double mu_out[4], double* f_local);
 void oracle_rotate(double dir[3], double cos_t, double sin_t, double phi_rev);
+/* Vavilov straggling: distribution function of X = (Delta - <Delta>)/T_max
+   (Gil-Pelaez inversion of the characteristic function), the quantile
+   nodes of W = X / sqrt(kappa (1 - beta^2/2)) at the table's grid
+   (out: 5 x 31 x 97), the step's kappa = xi / T_max, and the trilinear
+   quantile the transport draws with (context created with ORA_VAVILOV). */
+double oracle_vavilov_cdf(double kappa, double beta2, double x);
+int oracle_vavilov_table(double* out);
+double oracle_vavilov_kappa(double t_mev, double s_cm, double rho, double za);
+double oracle_vavilov_quantile(const ora_ctx* c, double kappa, double beta2, double z);
 
 #ifdef __cplusplus
 }

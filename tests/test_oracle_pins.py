@@ -640,3 +640,139 @@ def test_let_scoring_leaves_dose_unchanged_and_rises_to_the_distal_edge():
     distal = peak + int(np.argmax(e_dep[peak:] < 0.8 * e_dep[peak]))
     assert slab[distal] > 3.0 * slab[0], (slab[distal], slab[0])
     assert np.all(np.diff(no_nuc[:peak - 2]) > -0.02 * no_nuc[:peak - 3]), no_nuc[:peak]
+
+
+# ---------------------------------------------------------------------------
+# Vavilov straggling (Sec. II.A.2, Vavilov-Gaussian model): the quantile
+# table of the standardised loss W = (Delta - <Delta>) / sigma
+# ---------------------------------------------------------------------------
+
+EULER = 0.5772156649015329
+Z_NODES = np.arange(97) / 8.0 - 6.0
+
+
+@pytest.fixture(scope="module")
+def vav_table():
+    return O.vavilov_table()
+
+
+def _kappa_node(j):
+    return 10.0 ** (-2.0 + j / 10.0)
+
+
+def test_vavilov_table_moments_match_cumulants(vav_table):
+    """Vavilov's collision spectrum kappa (1 - beta^2 v) / v^2 gives the
+    cumulants of X = (Delta - <Delta>)/T_max in closed form: kappa_n =
+    kappa (1/(n-1) - beta^2/n).  The table's quantile function integrated
+    against the normal density must give mean 0, variance 1 and the
+    skewness kappa_3 / kappa_2^1.5 at every node."""
+    w = stats.norm.pdf(Z_NODES)
+    for b in range(5):
+        beta2 = 0.1 * b
+        for j in range(31):
+            g = vav_table[b, j]
+            k = _kappa_node(j)
+            m1 = np.trapezoid(g * w, Z_NODES)
+            m2 = np.trapezoid(g * g * w, Z_NODES)
+            m3 = np.trapezoid(g ** 3 * w, Z_NODES)
+            skew = k * (0.5 - beta2 / 3.0) / (k * (1.0 - beta2 / 2.0)) ** 1.5
+            assert abs(m1) < 2e-3 and abs(m2 - 1.0) < 3e-3, (b, j, m1, m2)
+            assert abs(m3 / skew - 1.0) < 0.01, (b, j, m3, skew)
+            assert np.all(np.diff(g) > 0), (b, j)
+
+
+def test_vavilov_tends_to_landau_for_small_kappa():
+    """kappa -> 0 with beta^2 = 0: X/kappa - (1 - Euler) - ln kappa tends to
+    the Landau variable L with E[exp(-u L)] = u^u; scipy's standard Landau
+    is (2/pi)(L + ln(2/pi)).  At kappa = 0.0025 the core agrees to 0.005."""
+    k = 0.0025
+    for lam in np.linspace(-2.0, 2.0, 9):
+        got = O.vavilov_cdf(k, 0.0, k * (lam + 1.0 - EULER + math.log(k)))
+        want = stats.landau.cdf(2.0 / math.pi * (lam + math.log(2.0 / math.pi)))
+        assert abs(got - want) < 0.005, (lam, got, want)
+
+
+def test_vavilov_tends_to_gauss_for_large_kappa():
+    """Large kappa: the distribution of W follows its Edgeworth expansion
+    (skewness and excess kurtosis from the closed-form cumulants)."""
+    k, beta2 = 200.0, 0.2
+    c = math.sqrt(k * (1.0 - beta2 / 2.0))
+    g1 = k * (0.5 - beta2 / 3.0) / c ** 3
+    g2 = k * (1.0 / 3.0 - beta2 / 4.0) / c ** 4
+    for w in np.linspace(-3.0, 3.0, 13):
+        he2, he3, he5 = w * w - 1, w ** 3 - 3 * w, w ** 5 - 10 * w ** 3 + 15 * w
+        want = stats.norm.cdf(w) - stats.norm.pdf(w) * (g1 / 6 * he2 + g2 / 24 * he3 + g1 * g1 / 72 * he5)
+        got = O.vavilov_cdf(k, beta2, w * c)
+        assert abs(got - want) < 3e-4, (w, got, want)
+
+
+@pytest.mark.parametrize("j,b", [(7, 2), (17, 3)])
+def test_vavilov_nodes_match_brute_force_collisions(vav_table, j, b):
+    """Brute force: the loss as a sum of individual collisions (a thinned
+    Poisson process with intensity kappa (1 - beta^2 v)/v^2 above v0 = 1e-3,
+    the rest as its mean plus a normal term of its variance), 4e5 samples;
+    empirical quantiles within 5 standard errors of the table nodes."""
+    k, beta2 = _kappa_node(j), 0.1 * b
+    rng = np.random.default_rng(1234 + j)
+    v0, n, chunk = 1e-3, 400_000, 20_000
+    lam = k * (1.0 / v0 - 1.0)
+    mean = k * (math.log(1.0 / v0) - beta2 * (1.0 - v0))
+    sub_sd = math.sqrt(k * (v0 - beta2 * v0 * v0 / 2.0))
+    xs = []
+    for _ in range(n // chunk):
+        cnt = rng.poisson(lam, chunk)
+        u = rng.random(cnt.sum())
+        v = 1.0 / (1.0 / v0 - u * (1.0 / v0 - 1.0))
+        keep = rng.random(v.size) < 1.0 - beta2 * v
+        sums = np.bincount(np.repeat(np.arange(chunk), cnt), weights=v * keep, minlength=chunk)
+        xs.append(sums - mean + sub_sd * rng.standard_normal(chunk))
+    w = np.sort(np.concatenate(xs)) / math.sqrt(k * (1.0 - beta2 / 2.0))
+    g = vav_table[b, j]
+    for q in (16, 32, 40, 48, 56, 64, 72):        # z = -4, -2, -1, 0, 1, 2, 3
+        z = Z_NODES[q]
+        p = stats.norm.cdf(z)
+        emp = w[int(p * n)]
+        dens = stats.norm.pdf(z) / ((g[q + 1] - g[q - 1]) * 4.0)   # f_W = phi(z) / G'(z)
+        se = math.sqrt(p * (1 - p) / n) / dens
+        assert abs(emp - g[q]) < 5 * se + 2e-3, (z, emp, g[q], se)
+
+
+def test_vavilov_interpolation_error_off_the_nodes():
+    """The trilinear draw against the exact quantile (root of the Gil-Pelaez
+    distribution function) at points between the nodes: within 0.015 sigma."""
+    o = O.Oracle(flags=O.VAVILOV)
+    for k in (0.013, 0.12, 1.7, 6.3):
+        for beta2 in (0.05, 0.25, 0.38):
+            c = math.sqrt(k * (1.0 - beta2 / 2.0))
+            for z in (-2.5, -0.2, 1.9, 3.1):
+                p = stats.norm.cdf(z)
+                x = optimize.brentq(lambda x: O.vavilov_cdf(k, beta2, x) - p,
+                                    -8 * math.sqrt(k) - 0.1, 4 + 8 * math.sqrt(k), xtol=1e-12)
+                assert abs(o.vavilov_quantile(k, beta2, z) - x / c) < 0.015, (k, beta2, z)
+    # outside [0.01, 10) the draw is the normal score itself
+    assert o.vavilov_quantile(0.005, 0.2, 1.3) == 1.3 and o.vavilov_quantile(12.0, 0.2, -0.7) == -0.7
+
+
+def test_vavilov_straggling_in_one_step():
+    """One 2 mm water step at 100 MeV with Vavilov straggling: the mean loss
+    is unchanged, the variance is Bohr's and the skewness that of the step's
+    kappa (0.4: Vavilov regime)."""
+    n = 40_000
+    flags = O.NO_MCS | O.NO_NUCLEAR
+    o, esc = _slab_run(flags | O.VAVILOV, n)
+    _, esc_g = _slab_run(flags, n)
+    loss, loss_g = 100.0 - esc[:, 6], 100.0 - esc_g[:, 6]
+    za = O.lib().oracle_water_z_over_a()
+    e_mid = 100.0 - 0.5 * loss_g.mean()
+    var = O.lib().oracle_straggling_variance(e_mid, 0.2, 1.0, za)
+    k = O.vavilov_kappa(e_mid, 0.2, 1.0, za)
+    et = e_mid + 938.272088
+    beta2 = e_mid * (e_mid + 2 * 938.272088) / et ** 2
+    skew = k * (0.5 - beta2 / 3.0) / (k * (1.0 - beta2 / 2.0)) ** 1.5
+    assert 0.1 < k < 1.0
+    sd = math.sqrt(var)
+    assert abs(loss.mean() - loss_g.mean()) < 4 * sd / math.sqrt(n)
+    assert abs(loss.var() / var - 1.0) < 0.05
+    got_skew = stats.skew(loss)
+    assert abs(got_skew - skew) < 0.15 * skew, (got_skew, skew)
+    assert abs(stats.skew(loss_g)) < 0.1
