@@ -54,11 +54,19 @@ typedef enum {
     PMC_ERR_STATE = -6           /* call order: physics and geometry must be loaded first */
 } pmc_status;
 
-/* Test switches: the closed-form special cases of the method. */
+/* Test switches: the closed-form special cases of the method; and the
+ * straggling model. */
 enum {
     PMC_NO_STRAGGLE = 1u,  /* mean energy loss only */
     PMC_NO_MCS = 2u,       /* no angular deflection */
-    PMC_NO_NUCLEAR = 4u    /* no elastic or non-elastic nuclear events */
+    PMC_NO_NUCLEAR = 4u,   /* no elastic or non-elastic nuclear events */
+    PMC_VAVILOV = 8u       /* Vavilov-Gaussian straggling (Sec. II.A.2): the loss of a step
+                              is <Delta> + sigma W, sigma^2 Bohr's variance, W the
+                              standardised Vavilov variable of the step's kappa = xi/T_max
+                              and beta^2 when kappa is in [0.01, 10), else standard normal;
+                              W drawn by mapping the step's normal score through the
+                              quantile table pmc_vavilov_table returns (trilinear).
+                              Default (flag clear): W standard normal */
 };
 
 typedef struct {
@@ -300,6 +308,16 @@ pmc_status pmc_atomic_probe(pmc_ctx* c, uint64_t n_atomics, void* hip_stream, do
  * hip_stream.  Errors: PMC_ERR_ARG (NULL, unknown id), PMC_ERR_STATE (no
  * geometry), PMC_ERR_DEVICE. */
 pmc_status pmc_geometry_density(pmc_ctx* c, int32_t geometry_id, float* d_rho, void* hip_stream);
+
+/* The Vavilov straggling table used with PMC_VAVILOV (host only, no device
+ * work): 5 x 31 x 97 floats into out, [beta^2 = k/10, k < 5][log10 kappa =
+ * -2 + j/10, j < 31][z = -6 + i/8, i < 97], the quantile G(z) = F_W^-1(Phi(z))
+ * of the standardised loss W = (Delta - <Delta>) / sqrt(xi T_max (1 -
+ * beta^2/2)) in Vavilov's model (free-electron collisions with transfer
+ * density kappa (1 - beta^2 v)/v^2, v = eps/T_max in (0, 1]), from the
+ * inversion of its characteristic function.  Built once per process (about
+ * a second).  Errors: PMC_ERR_ARG (out NULL or n_floats < 15035). */
+pmc_status pmc_vavilov_table(float* out, int32_t n_floats);
 
 /* Library version string, e.g. "pmc 0.1 gfx950". */
 const char* pmc_version(void);

@@ -73,6 +73,7 @@ struct alignas(8) LdsArgs {
     const float* sec_mu;
     const float* spots;
     const unsigned long long* order;
+    const float* vav;  // Vavilov straggling quantile table (flag PMC_VAVILOV), or NULL
     const uint32_t* q_in;
     uint32_t* q_out;
     unsigned long long q_cap;
@@ -103,6 +104,7 @@ struct KernelArgs {
     const float* sec_floc;  // [6][25]
     const float* sec_x;     // [6][25][33]
     const float* sec_mu;    // [6][25][33]
+    const float* vav;       // [5][31][97] Vavilov quantiles (flag PMC_VAVILOV), or NULL
     // run
     int k_batches;
     uint32_t flags;

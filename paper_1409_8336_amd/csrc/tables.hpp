@@ -60,6 +60,11 @@ struct Material {
     bool own = false;
 };
 
+// Vavilov straggling quantile table (built once per process):
+// [beta^2 = k/10][log10 kappa = -2 + j/10][z = -6 + i/8], standardised loss W.
+constexpr int kVavNB = 5, kVavNK = 31, kVavNZ = 97;
+const std::vector<float>& vavilov_table();
+
 // Validates and derives the per-bin materials; returns "" or an error text.
 std::string build_materials(int n_bins, const int16_t* hu_lo, const float* rho_lo,
                             const float* rho_hi, const float* mass_frac, const float* i_ev,

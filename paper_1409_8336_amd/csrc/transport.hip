@@ -47,9 +47,14 @@ constexpr float kLnE0 = -2.302585093f;            // ln 0.1
 constexpr float kInvH = 999.0f / 7.824046011f;    // 1 / (ln(2500)/999)
 constexpr float kH = 7.824046011f / 999.0f;
 constexpr float kStraggleK = 0.156914976f;        // K m_e c^2, MeV^2 cm^2 / g
+// Vavilov kappa = xi / T_max = (K/2)(Z/A) rho s / beta^2 over
+// 2 m_e beta^2 gamma^2 / (1 + 2 gamma m_e/M + (m_e/M)^2); the (m_e/M)^2 term
+// (3e-7) is dropped
+constexpr float kVavXi = 0.150233246f;             // (K/2) / (2 m_e c^2), cm^2 / g
+constexpr float kMeOverMp = 5.44617021e-4f;
 constexpr float kInf = 3.0e38f;
 constexpr uint32_t kMaxSteps = 1u << 20;
-constexpr uint32_t kNoStraggle = 1u, kNoMcs = 2u, kNoNuclear = 4u;
+constexpr uint32_t kNoStraggle = 1u, kNoMcs = 2u, kNoNuclear = 4u, kVavilov = 8u;
 
 // ---------------------------------------------------------------- helpers
 
@@ -296,6 +301,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
         L->sec_floc = a.sec_floc;
         L->sec_x = a.sec_x;
         L->sec_mu = a.sec_mu;
+        L->vav = a.vav;
         L->spots = a.spots;
         L->order = a.order;
         L->q_in = a.q_in;
@@ -733,7 +739,35 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
             if (!(flags & kNoStraggle)) {
                 const float g = e_tot * (1.0f / kMp);
                 const float var = kStraggleK * rho * mza * s * g * g * (1.f - 0.5f * b2);
-                const float z = 1.414213562f * inv_erf(2.f * u01(r.w) - 1.f);
+                float z = 1.414213562f * inv_erf(2.f * u01(r.w) - 1.f);
+                if (flags & kVavilov) {
+                    // Vavilov-Gaussian (Sec. II.A.2): the normal score through
+                    // the Vavilov quantile function of the step's kappa =
+                    // xi / T_max and beta^2, tabulated at log10 kappa = -2 +
+                    // j/10, beta^2 = k/10, z = -6 + i/8 (trilinear); outside
+                    // kappa in [0.01, 10) the loss stays Gaussian
+                    const float kappa = kVavXi * mza * rho * s * (1.f + 2.f * g * kMeOverMp) * frcp(b2 * b2 * g * g);
+                    const float lk = fln(kappa) * 0.4342944819f;
+                    if (lk >= -2.f && lk < 1.f) {
+                        float fk = (lk + 2.f) * 10.f;
+                        const int j = min((int)fk, 29);
+                        fk -= (float)j;
+                        float fb = fminf(fmaxf(b2, 0.f), 0.4f) * 10.f;
+                        const int kb = min((int)fb, 3);
+                        fb -= (float)kb;
+                        float fz = (z + 6.f) * 8.f;
+                        const int q = min(max((int)floorf(fz), 0), 95);
+                        fz -= (float)q;
+                        const GLOBAL float* t0 = gbl(L->vav) + (kb * 31 + j) * 97 + q;
+                        const GLOBAL float* t1 = t0 + 31 * 97;
+                        const float g00 = t0[0] + fz * (t0[1] - t0[0]);
+                        const float g01 = t0[97] + fz * (t0[98] - t0[97]);
+                        const float g10 = t1[0] + fz * (t1[1] - t1[0]);
+                        const float g11 = t1[97] + fz * (t1[98] - t1[97]);
+                        const float ga = g00 + fk * (g01 - g00), gb = g10 + fk * (g11 - g10);
+                        z = ga + fb * (gb - ga);
+                    }
+                }
                 de = de_mean + fsqrt(var) * z;
                 de = de < 0.f ? 0.f : (de > E ? E : de);
             }
