@@ -17,7 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "pmc_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
-NO_STRAGGLE, NO_MCS, NO_NUCLEAR, VAVILOV = 1, 2, 4, 8
+NO_STRAGGLE, NO_MCS, NO_NUCLEAR, VAVILOV, MOLIERE = 1, 2, 4, 8, 16
+MOL_SHAPE = (13, 161)     # [1/B = 1/20 + j (2/9 - 1/20)/12][q = k/8]
 VAV_SHAPE = (5, 31, 97)   # [beta^2 = k/10][log10 kappa = -2 + j/10][z = -6 + i/8]
 _lock = threading.Lock()
 _lib = None
@@ -109,6 +110,13 @@ def lib():
                 f.argtypes = args
                 f.restype = d
             L.oracle_vavilov_table.argtypes = [C.c_void_p]
+            L.oracle_moliere_f.argtypes = [C.c_int, d]
+            L.oracle_moliere_f.restype = d
+            L.oracle_moliere_survival.argtypes = [d, d]
+            L.oracle_moliere_survival.restype = d
+            L.oracle_moliere_table.argtypes = [C.c_void_p]
+            L.oracle_moliere_theta.argtypes = [C.c_void_p, C.c_int, d, d, d, d, C.POINTER(d)]
+            L.oracle_moliere_theta.restype = d
             L.oracle_material_info.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_double)]
             L.oracle_elastic_sample.argtypes = [C.c_int, d, d, d, C.POINTER(C.c_double)]
             L.oracle_secondary_sample.argtypes = [C.c_void_p, C.c_int, d, C.c_uint64, C.c_uint32,
@@ -151,6 +159,23 @@ def vavilov_table():
     rc = lib().oracle_vavilov_table(_ptr(out))
     if rc:
         raise ValueError("oracle_vavilov_table failed: %d" % rc)
+    return out
+
+
+def moliere_f(n, v):
+    """Bethe's f0, f1, f2 of the Molière expansion at reduced angle v."""
+    return lib().oracle_moliere_f(int(n), float(v))
+
+
+def moliere_survival(x, v):
+    """P(V > v) of the reduced angle for 1/B = x."""
+    return lib().oracle_moliere_survival(float(x), float(v))
+
+
+def moliere_table():
+    out = np.zeros(MOL_SHAPE, dtype=np.float64)
+    if lib().oracle_moliere_table(_ptr(out)):
+        raise ValueError("oracle_moliere_table failed")
     return out
 
 
@@ -264,6 +289,14 @@ class Oracle:
         return out
 
     # ---- pieces for pins ----
+    def moliere_theta(self, material, t_mev, rho, s_cm, u):
+        """(polar angle, B) of the transport's Molière draw (flags MOLIERE);
+        angle NaN and B 0 where the step keeps Highland."""
+        b = C.c_double()
+        th = lib().oracle_moliere_theta(self.h, int(material), float(t_mev), float(rho), float(s_cm),
+                                        float(u), C.byref(b))
+        return th, b.value
+
     def vavilov_quantile(self, kappa, beta2, z):
         """The transport's Vavilov draw for normal score z (flags VAVILOV)."""
         return lib().oracle_vavilov_quantile(self.h, float(kappa), float(beta2), float(z))

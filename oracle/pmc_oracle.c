@@ -341,6 +341,7 @@ struct ora_ctx {
     double mucdf[ORA_SEC_NUCLEI][ORA_SEC_EBINS][ORA_SEC_NCDF + 1];
     rtable water;
     double* vav;                         /* Vavilov quantile nodes (ORA_VAVILOV) */
+    double* mol;                         /* Molière ln R table (ORA_MOLIERE) */
     int nmat;
     omat mat[16];
     int n[3];
@@ -361,6 +362,16 @@ int oracle_create(ora_ctx** out, const ora_params* p)
     if (p->flags & ORA_VAVILOV) {
         c->vav = (double*)malloc(sizeof(double) * ORA_VAV_NB * ORA_VAV_NK * ORA_VAV_NZ);
         if (!c->vav || oracle_vavilov_table(c->vav)) {
+            free(c->vav);
+            rt_free(&c->water);
+            free(c);
+            return -3;
+        }
+    }
+    if (p->flags & ORA_MOLIERE) {
+        c->mol = (double*)malloc(sizeof(double) * ORA_MOL_NX * ORA_MOL_NQ);
+        if (!c->mol || oracle_moliere_table(c->mol)) {
+            free(c->mol);
             free(c->vav);
             rt_free(&c->water);
             free(c);
@@ -391,6 +402,7 @@ int oracle_destroy(ora_ctx* c)
     free_geometry(c);
     rt_free(&c->water);
     free(c->vav);
+    free(c->mol);
     free(c);
     return 0;
 }
@@ -811,6 +823,212 @@ double oracle_vavilov_kappa(double t, double s, double rho, double za)
     return xi / tmax;
 }
 
+/* ======================================================================
+ * Molière multiple scattering (Sec. II.A.2 names a full Molière option
+ * beside the scaled Highland formula), in Bethe's form:
+ *   f(theta) theta dtheta = v dv [f0(v) + f1(v)/B + f2(v)/B^2],
+ *   v = theta / (chi_c sqrt B), f0 = 2 exp(-v^2),
+ *   fn(v) = (1/n!) Int_0^inf u J0(v u) exp(-u^2/4) [(u^2/4) ln(u^2/4)]^n du,
+ * chi_c^2 = 4 pi N_A e^4 (rho s) sum_i w_i Z_i (Z_i + 1) / A_i / (p beta)^2,
+ * the screening angle of element i chi_a,i^2 = chi_0,i^2 (1.13 + 3.76
+ * (Z_i alpha / beta)^2), chi_0,i = hbar c Z_i^(1/3) / (0.885 a_0 p c),
+ * combined as ln chi_a^2 = sum_i w_i Z_i (Z_i + 1)/A_i ln chi_a,i^2 / sum of
+ * the same weights, and B from B - ln B = ln(chi_c^2 / (1.167 chi_a^2)).
+ * The expansion needs B >= 4.5; a step with fewer collisions keeps the
+ * scaled Highland Gaussian.
+ * Sampling: with q = -ln u, v^2 = q R(q, 1/B), the function ln R tabulated
+ * at q = k/8 (k <= 160) and 1/B = 1/20 + j (2/9 - 1/20)/12 (j <= 12; 1/B
+ * clamped to that range), interpolated bilinearly (linear extrapolation in
+ * q beyond 20); theta = min(pi, chi_c sqrt(B) v), azimuth uniform.
+ * The distribution functions Fn(v) = Int_0^v fn v' dv' =
+ * (v/n!) Int_0^inf J1(v u) exp(-u^2/4) [(u^2/4) ln(u^2/4)]^n du are
+ * integrated by Simpson's rule on v <= 20 and continued beyond by their
+ * asymptotic forms F1 = -(v^-2 + 2 v^-4), F2 proportional to ln v / v^4.
+ * ====================================================================== */
+#define MOL_VMAX 20.0
+#define MOL_DV 0.02
+#define MOL_NV 1001                  /* v grid 0 .. 20 */
+static double* mol_F = NULL;         /* [MOL_NV][2]: F1, F2 */
+
+static double mol_g(double u, int n)
+{
+    const double y = 0.25 * u * u;
+    if (y <= 0.0) return 0.0;
+    const double t = y * log(y);
+    return exp(-y) * (n == 1 ? t : 0.5 * t * t);
+}
+
+double oracle_moliere_f(int n, double v)
+{
+    if (n == 0) return 2.0 * exp(-v * v);
+    if (n != 1 && n != 2) return NAN;
+    const int N = 28000;                /* u in [0, 14], step 5e-4 */
+    const double h = 14.0 / N;
+    double s = 0.0;
+    for (int k = 0; k <= N; ++k) {
+        const double u = k * h;
+        const double w = (k == 0 || k == N) ? 1.0 : (k & 1 ? 4.0 : 2.0);
+        s += w * u * j0(v * u) * mol_g(u, n);
+    }
+    return s * h / 3.0;
+}
+
+static double mol_F_direct(int n, double v)
+{
+    const int N = 14000;                /* u in [0, 14], step 1e-3 */
+    const double h = 14.0 / N;
+    double s = 0.0;
+    for (int k = 0; k <= N; ++k) {
+        const double u = k * h;
+        const double w = (k == 0 || k == N) ? 1.0 : (k & 1 ? 4.0 : 2.0);
+        s += w * j1(v * u) * mol_g(u, n);
+    }
+    return v * s * h / 3.0;
+}
+
+static int mol_build_F(void)
+{
+    int ok = 1;
+#pragma omp critical(mol_F)
+    {
+        if (!mol_F) {
+            double* t = (double*)malloc(sizeof(double) * 2 * MOL_NV);
+            if (!t) ok = 0;
+            else {
+#pragma omp parallel for schedule(dynamic, 8)
+                for (int i = 0; i < MOL_NV; ++i) {
+                    t[2 * i] = mol_F_direct(1, i * MOL_DV);
+                    t[2 * i + 1] = mol_F_direct(2, i * MOL_DV);
+                }
+                mol_F = t;
+            }
+        }
+    }
+    return ok && mol_F;
+}
+
+/* F1 and F2 at v */
+static void mol_F12(double v, double* f1, double* f2)
+{
+    if (v >= MOL_VMAX) {
+        const double r = MOL_VMAX / v;
+        *f1 = -(1.0 / (v * v) + 2.0 / (v * v * v * v));
+        *f2 = mol_F[2 * (MOL_NV - 1) + 1] * r * r * r * r * log(v) / log(MOL_VMAX);
+        return;
+    }
+    const double x = v / MOL_DV;
+    int i = (int)x;
+    if (i > MOL_NV - 2) i = MOL_NV - 2;
+    const double fr = x - i;
+    *f1 = mol_F[2 * i] + fr * (mol_F[2 * i + 2] - mol_F[2 * i]);
+    *f2 = mol_F[2 * i + 1] + fr * (mol_F[2 * i + 3] - mol_F[2 * i + 1]);
+}
+
+/* P(V > v) for 1/B = x */
+double oracle_moliere_survival(double x, double v)
+{
+    if (!mol_build_F()) return NAN;
+    double f1, f2;
+    mol_F12(v, &f1, &f2);
+    return exp(-v * v) - x * f1 - x * x * f2;
+}
+
+static double mol_x_node(int j) { return 0.05 + j * (2.0 / 9.0 - 0.05) / (ORA_MOL_NX - 1); }
+
+int oracle_moliere_table(double* out)
+{
+    if (!out || !mol_build_F()) return -1;
+    const double euler = 0.57721566490153286;
+    const double f1_0 = 2.0 * (1.0 - euler);
+    const double f2_0 = 2.0 * ((1.5 - euler) * (1.5 - euler) + M_PI * M_PI / 6.0 - 1.25);
+#pragma omp parallel for
+    for (int j = 0; j < ORA_MOL_NX; ++j) {
+        const double x = mol_x_node(j);
+        for (int k = 0; k < ORA_MOL_NQ; ++k) {
+            const double q = k / 8.0;
+            if (k == 0) {                       /* small v: F = f(0) v^2 / 2 */
+                out[j * ORA_MOL_NQ] = log(2.0 / (2.0 + x * f1_0 + x * x * f2_0));
+                continue;
+            }
+            const double target = exp(-q);     /* P(V > v) = 1 - u = e^-q */
+            double lo = 0.0, hi = 1.0e5;
+            for (int it = 0; it < 200; ++it) {
+                const double mid = 0.5 * (lo + hi);
+                if (oracle_moliere_survival(x, mid) > target) lo = mid;
+                else hi = mid;
+            }
+            const double v = 0.5 * (lo + hi);
+            out[j * ORA_MOL_NQ + k] = log(v * v / q);
+        }
+    }
+    return 0;
+}
+
+/* ln chi_c^2, ln chi_a^2 and B of a step; returns 0 when B < 4.5 */
+static int mol_step(const omat* m, double t, double rho, double s, double* chi_c2, double* bB)
+{
+    const double e_tot = t + M_PROTON;
+    const double pc = sqrt(t * (t + 2.0 * M_PROTON));
+    const double beta2 = pc * pc / (e_tot * e_tot);
+    const double pbeta = pc * pc / e_tot;
+    double s1 = 0.0, la = 0.0;
+    for (int e = 0; e < ORA_NEL; ++e) {
+        if (m->w[e] <= 0.0) continue;
+        const double z = EL_Z[e];
+        const double wt = m->w[e] * z * (z + 1.0) / EL_A[e];
+        const double chi0 = 0.0042134917 * cbrt(z) / pc;
+        const double za = z * ALPHA_FS;
+        s1 += wt;
+        la += wt * log(chi0 * chi0 * (1.13 + 3.76 * za * za / beta2));
+    }
+    la /= s1;
+    const double lc = log(K_BETHE * M_ELECTRON * s1 * rho * s / (pbeta * pbeta));
+    const double b = lc - log(1.167) - la;
+    if (b < 4.5 - log(4.5)) return 0;
+    double B = b + log(b);
+    for (int it = 0; it < 30; ++it) B -= (B - log(B) - b) / (1.0 - 1.0 / B);
+    *chi_c2 = exp(lc);
+    *bB = B;
+    return 1;
+}
+
+/* polar angle for uniform u (q = -ln u) from the table */
+static double mol_theta(const double* tab, double chi_c2, double B, double u)
+{
+    double x = 1.0 / B;
+    if (x < 0.05) x = 0.05;
+    if (x > 2.0 / 9.0) x = 2.0 / 9.0;
+    double fx = (x - 0.05) / ((2.0 / 9.0 - 0.05) / (ORA_MOL_NX - 1));
+    int j = (int)fx;
+    if (j > ORA_MOL_NX - 2) j = ORA_MOL_NX - 2;
+    fx -= j;
+    const double q = -log(u);
+    double fq = q * 8.0;
+    int k = (int)fq;
+    if (k > ORA_MOL_NQ - 2) k = ORA_MOL_NQ - 2;
+    fq -= k;
+    const double* r0 = tab + j * ORA_MOL_NQ;
+    const double* r1 = r0 + ORA_MOL_NQ;
+    const double a = r0[k] + fq * (r0[k + 1] - r0[k]);
+    const double c = r1[k] + fq * (r1[k + 1] - r1[k]);
+    const double v2 = q * exp(a + fx * (c - a));
+    const double th = sqrt(chi_c2 * B * v2);
+    return th < M_PI ? th : M_PI;
+}
+
+double oracle_moliere_theta(const ora_ctx* c, int material, double t_mev, double rho, double s_cm,
+                            double u, double* b_out)
+{
+    if (!c || !c->mol || material < 0 || material >= c->nmat) return NAN;
+    double chi_c2, B;
+    if (!mol_step(&c->mat[material], t_mev, rho, s_cm, &chi_c2, &B)) {
+        if (b_out) *b_out = 0.0;
+        return NAN;
+    }
+    if (b_out) *b_out = B;
+    return mol_theta(c->mol, chi_c2, B, u);
+}
+
 void oracle_rotate(double d[3], double ct, double st, double phi_rev)
 {
     double cp = cos(2.0 * M_PI * phi_rev), sp = sin(2.0 * M_PI * phi_rev);
@@ -1173,7 +1391,13 @@ static void transport(const ora_ctx* c, const orun* r, opart* q, ostack* st, oac
         }
         double theta = 0.0;
         if (!(flags & ORA_NO_MCS))
-            theta = oracle_highland_theta0(e_mid, s, m->x0 / rho, c->p.f_mcs) * sqrt(-2.0 * log(u[1]));
+        {
+            double chi_c2, B;
+            if ((flags & ORA_MOLIERE) && mol_step(m, e_mid, rho, s, &chi_c2, &B))
+                theta = mol_theta(c->mol, chi_c2, B, u[1]);
+            else
+                theta = oracle_highland_theta0(e_mid, s, m->x0 / rho, c->p.f_mcs) * sqrt(-2.0 * log(u[1]));
+        }
         /* random hinge: deflect at a uniform fraction u0 of the step.  On a
          * boundary-limited step the remaining segment runs along the new
          * direction to the crossed face plane and ends exactly on it, unless

@@ -33,7 +33,14 @@ extern "C" {
 #define ORA_SEC_NCDF 32
 
 /* ORA_VAVILOV: Vavilov-Gaussian straggling instead of Gaussian (Sec. II.A.2) */
-enum { ORA_NO_STRAGGLE = 1, ORA_NO_MCS = 2, ORA_NO_NUCLEAR = 4, ORA_VAVILOV = 8 };
+/* ORA_MOLIERE: Molière multiple scattering instead of the scaled Highland
+   Gaussian where B >= 4.5 (Sec. II.A.2) */
+enum { ORA_NO_STRAGGLE = 1, ORA_NO_MCS = 2, ORA_NO_NUCLEAR = 4, ORA_VAVILOV = 8, ORA_MOLIERE = 16 };
+
+/* Molière sampling table: [1/B = 1/20 + j (2/9 - 1/20)/12, j < 13][q = k/8, k < 161]
+   of ln(v^2 / q), v the reduced angle, q = -ln u */
+#define ORA_MOL_NX 13
+#define ORA_MOL_NQ 161
 
 /* Vavilov quantile table: [beta^2 = k/10, k < 5][log10 kappa = -2 + j/10, j < 31]
    [z = -6 + i/8, i < 97] */
@@ -148,6 +155,16 @@ double oracle_vavilov_cdf(double kappa, double beta2, double x);
 int oracle_vavilov_table(double* out);
 double oracle_vavilov_kappa(double t_mev, double s_cm, double rho, double za);
 double oracle_vavilov_quantile(const ora_ctx* c, double kappa, double beta2, double z);
+/* Molière: Bethe's f0, f1, f2 at reduced angle v (n = 0, 1, 2), the
+   survival P(V > v) at 1/B = x, the sampling table (out: 13 x 161), and the
+   transport's polar angle for material bin m at kinetic energy t, density
+   rho, step s and uniform u (context created with ORA_MOLIERE; NaN and
+   *b_out = 0 where B < 4.5, i.e. the step keeps Highland) */
+double oracle_moliere_f(int n, double v);
+double oracle_moliere_survival(double x, double v);
+int oracle_moliere_table(double* out);
+double oracle_moliere_theta(const ora_ctx* c, int material, double t_mev, double rho, double s_cm,
+                            double u, double* b_out);
 
 #ifdef __cplusplus
 }

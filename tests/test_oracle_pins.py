@@ -776,3 +776,92 @@ def test_vavilov_straggling_in_one_step():
     got_skew = stats.skew(loss)
     assert abs(got_skew - skew) < 0.15 * skew, (got_skew, skew)
     assert abs(stats.skew(loss_g)) < 0.1
+
+
+# ---------------------------------------------------------------------------
+# Molière multiple scattering (Sec. II.A.2 option), Bethe's expansion
+# ---------------------------------------------------------------------------
+
+def test_moliere_functions_at_zero_have_closed_forms():
+    """fn(0) = (1/n!) Int u e^{-u^2/4} [(u^2/4) ln(u^2/4)]^n du = (2/n!) Gamma^(n)(n+1):
+    f1(0) = 2 (1 - Euler), f2(0) = Gamma''(3) = 2[(3/2 - Euler)^2 + pi^2/6 - 5/4]."""
+    assert abs(O.moliere_f(0, 0.0) - 2.0) < 1e-15
+    assert abs(O.moliere_f(1, 0.0) - 2.0 * (1.0 - EULER)) < 1e-9
+    want2 = 2.0 * ((1.5 - EULER) ** 2 + math.pi ** 2 / 6.0 - 1.25)
+    assert abs(O.moliere_f(2, 0.0) - want2) < 1e-9
+
+
+def test_moliere_tail_is_rutherford():
+    """Single scattering: f1 -> 2 v^-4 (1 + 4 v^-2) for large v, and the
+    survival of the reduced angle tends to (1/B) v^-2."""
+    for v in (8.0, 12.0, 20.0):
+        ratio = O.moliere_f(1, v) * v ** 4 / 2.0
+        assert abs(ratio / (1.0 + 4.0 / v ** 2) - 1.0) < 0.01, (v, ratio)
+    x = 0.1
+    for v in (25.0, 60.0, 200.0):
+        s = O.moliere_survival(x, v)
+        assert abs(s / (x / v ** 2) - 1.0) < 0.02, (v, s)
+
+
+def test_moliere_distribution_function_is_consistent():
+    """The survival function (J1 form of the running integral) and the
+    densities (J0 form) agree: -dS/dv / v = f0 + x f1 + x^2 f2; S(0) = 1,
+    S decreasing, and the numerical and asymptotic pieces join at v = 20."""
+    x = 1.0 / 8.0
+    assert abs(O.moliere_survival(x, 0.0) - 1.0) < 1e-12
+    vs = np.linspace(0.2, 19.0, 40)
+    for v in vs:
+        h = 1e-2
+        dens = -(O.moliere_survival(x, v + h) - O.moliere_survival(x, v - h)) / (2 * h) / v
+        want = O.moliere_f(0, v) + x * O.moliere_f(1, v) + x * x * O.moliere_f(2, v)
+        assert abs(dens - want) < 2e-4 * max(1.0, abs(want) * 1e3) + 1e-6, (v, dens, want)
+    grid = np.linspace(0.0, 100.0, 2001)
+    s = np.array([O.moliere_survival(x, v) for v in grid])
+    assert np.all(np.diff(s) < 0)
+    a, b = O.moliere_survival(x, 20.0 - 1e-9), O.moliere_survival(x, 20.0 + 1e-9)
+    assert abs(a - b) < 2e-6, (a, b)
+
+
+def _moliere_angles(e0, s_cm, n=200_000):
+    o = _oracle(flags=O.MOLIERE, hu=synth.water_phantom(4, 4, 4))
+    u = (np.arange(n) + 0.5) / n
+    out = [o.moliere_theta(2, e0, 1.0, s_cm, ui) for ui in u]
+    return np.array([t for t, _ in out]), out[0][1]
+
+
+@pytest.mark.parametrize("e0,s_cm", [(100.0, 1.0), (200.0, 5.0), (70.0, 0.5)])
+def test_moliere_core_agrees_with_highland_within_its_accuracy(lib, e0, s_cm):
+    """The RPP states that Highland's theta0 describes the central 98% of the
+    projected Molière distribution to 11% for 1e-3 < x/X0 < 100: the RMS of
+    the central 98% of the projected angle from the Molière draw (quantiles
+    of u, uniform azimuth) against Highland (F = 1)."""
+    th, B = _moliere_angles(e0, s_cm)
+    assert 4.5 <= B < 20
+    rng = np.random.default_rng(0)
+    proj = np.sort(th * np.cos(2 * np.pi * rng.random(th.size)))
+    n = proj.size
+    core = proj[int(0.01 * n):int(0.99 * n)]
+    x0 = 36.08                                       # water, g/cm^2
+    hl = lib.oracle_highland_theta0(e0, s_cm, x0, 1.0)
+    # a Gaussian of width w has RMS 0.9346 w over its central 98%
+    w = np.sqrt(np.mean(core ** 2)) / 0.9346
+    assert abs(w / hl - 1.0) < 0.11, (w, hl)
+
+
+def test_moliere_single_scattering_fraction(lib):
+    """Far outside the core the Molière draw follows Rutherford single
+    scattering: P(theta > t) = chi_c^2 / t^2 (1 + 2 (chi_c^2 B / t^2))."""
+    n = 400_000
+    th, B = _moliere_angles(100.0, 0.2, n)
+    za = {1: (1.0, 1.00794), 8: (8.0, 15.9994)}
+    w = {1: 0.111894, 8: 0.888106}
+    s1 = sum(w[k] * za[k][0] * (za[k][0] + 1) / za[k][1] for k in za)
+    pc = math.sqrt(100.0 * (100.0 + 2 * 938.272088))
+    pbeta = pc * pc / (100.0 + 938.272088)
+    chi_c2 = 0.307075 * 0.51099895 * s1 * 0.2 / pbeta ** 2
+    for t_over in (8.0, 15.0):
+        t = t_over * math.sqrt(chi_c2 * B)
+        frac = np.mean(th > t)
+        want = chi_c2 / t ** 2 * (1.0 + 2.0 * chi_c2 * B / t ** 2)
+        se = math.sqrt(want / n)
+        assert abs(frac - want) < 4 * se + 0.03 * want, (t_over, frac, want)
