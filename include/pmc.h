@@ -55,18 +55,28 @@ typedef enum {
 } pmc_status;
 
 /* Test switches: the closed-form special cases of the method; and the
- * straggling model. */
+ * straggling and multiple-scattering models. */
 enum {
     PMC_NO_STRAGGLE = 1u,  /* mean energy loss only */
     PMC_NO_MCS = 2u,       /* no angular deflection */
     PMC_NO_NUCLEAR = 4u,   /* no elastic or non-elastic nuclear events */
-    PMC_VAVILOV = 8u       /* Vavilov-Gaussian straggling (Sec. II.A.2): the loss of a step
+    PMC_VAVILOV = 8u,      /* Vavilov-Gaussian straggling (Sec. II.A.2): the loss of a step
                               is <Delta> + sigma W, sigma^2 Bohr's variance, W the
                               standardised Vavilov variable of the step's kappa = xi/T_max
                               and beta^2 when kappa is in [0.01, 10), else standard normal;
                               W drawn by mapping the step's normal score through the
                               quantile table pmc_vavilov_table returns (trilinear).
                               Default (flag clear): W standard normal */
+    PMC_MOLIERE = 16u      /* Molière multiple scattering (Sec. II.A.2's full Molière option)
+                              instead of the scaled Highland Gaussian, on steps where
+                              Bethe's B (B - ln B = ln(chi_c^2 / 1.167 chi_a^2)) is at
+                              least 4.5; chi_c^2 = K m_e c^2 rho s sum w Z(Z+1)/A / (p beta)^2,
+                              the screening angle from the Z(Z+1)/A-weighted logs of the
+                              elements' chi_0^2 (1.13 + 3.76 (Z alpha / beta)^2); polar
+                              angle chi_c sqrt(B) v with v^2 = q R(q, 1/B), q = -ln u, from
+                              the table pmc_moliere_table returns (bilinear), at most pi.
+                              Steps with B < 4.5 keep the Highland Gaussian (f_mcs applies
+                              there only) */
 };
 
 typedef struct {
@@ -318,6 +328,14 @@ pmc_status pmc_geometry_density(pmc_ctx* c, int32_t geometry_id, float* d_rho, v
  * inversion of its characteristic function.  Built once per process (about
  * a second).  Errors: PMC_ERR_ARG (out NULL or n_floats < 15035). */
 pmc_status pmc_vavilov_table(float* out, int32_t n_floats);
+
+/* The Molière sampling table used with PMC_MOLIERE (host only, no device
+ * work): 13 x 161 floats into out, [1/B = 1/20 + j (2/9 - 1/20)/12, j < 13]
+ * [q = k/8, k < 161], ln(v^2 / q) where P(V > v) = e^-q for the reduced angle
+ * V of Bethe's expansion f0 + f1/B + f2/B^2 (1/B clamped to the table's
+ * range by the transport).  Built once per process.  Errors: PMC_ERR_ARG
+ * (out NULL or n_floats < 2093). */
+pmc_status pmc_moliere_table(float* out, int32_t n_floats);
 
 /* Library version string, e.g. "pmc 0.1 gfx950". */
 const char* pmc_version(void);

@@ -9,8 +9,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpmc.so")
-SOURCES = ["engine.hip", "transport.hip", "tables.cpp", "vavilov.cpp", "unet.hip", "unet_kernels.hip",
-           "gamma.hip"]
+SOURCES = ["engine.hip", "transport.hip", "tables.cpp", "vavilov.cpp", "moliere.cpp", "unet.hip",
+           "unet_kernels.hip", "gamma.hip"]
 HEADERS = ["device.hpp", "tables.hpp"]
 
 HIP_FLAGS = [

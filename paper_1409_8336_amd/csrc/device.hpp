@@ -74,6 +74,8 @@ struct alignas(8) LdsArgs {
     const float* spots;
     const unsigned long long* order;
     const float* vav;  // Vavilov straggling quantile table (flag PMC_VAVILOV), or NULL
+    const float* mol;     // Molière sampling table (flag PMC_MOLIERE), or NULL
+    const float* molmat;  // [n_mat][16] Molière material constants, or NULL
     const uint32_t* q_in;
     uint32_t* q_out;
     unsigned long long q_cap;
@@ -105,6 +107,8 @@ struct KernelArgs {
     const float* sec_x;     // [6][25][33]
     const float* sec_mu;    // [6][25][33]
     const float* vav;       // [5][31][97] Vavilov quantiles (flag PMC_VAVILOV), or NULL
+    const float* mol;       // [13][161] Molière ln R (flag PMC_MOLIERE), or NULL
+    const float* molmat;    // [n_mat][16] Molière material constants
     // run
     int k_batches;
     uint32_t flags;

@@ -113,6 +113,7 @@ struct pmc_ctx {
     // run buffers
     DevBuf<double> d_dose, d_var, d_let, d_ledger;
     DevBuf<float> d_vav;       // Vavilov quantile table (PMC_VAVILOV)
+    DevBuf<float> d_mol, d_molmat;  // Molière table and material constants (PMC_MOLIERE)
     DevBuf<uint32_t> d_q[2];
     DevBuf<unsigned long long> d_gc, d_counters, d_order, d_wgc;
     DevBuf<uint32_t> d_qloc;   // per-workgroup secondary queues
@@ -193,7 +194,12 @@ pmc_status upload_tables(pmc_ctx* c)
     std::vector<float> npg(nm * kNEl);
     for (int m = 0; m < nm; ++m)
         for (int e = 0; e < kNEl; ++e) npg[m * kNEl + e] = (float)c->mats[m].nuclei_per_g_barn[e];
-    return upload(c, c->d_npg, npg, "upload nuclei per gram");
+    s = upload(c, c->d_npg, npg, "upload nuclei per gram");
+    if (s != PMC_OK) return s;
+    static_assert(kMolMatFloats == 16, "the transport kernel reads 16 Moliere floats per material");
+    std::vector<float> mol((size_t)nm * kMolMatFloats);
+    for (int m = 0; m < nm; ++m) moliere_material(c->mats[m].w, &mol[(size_t)m * kMolMatFloats]);
+    return upload(c, c->d_molmat, mol, "upload Moliere material constants");
 }
 
 bool params_ok(const pmc_params& p, std::string& why)
@@ -201,7 +207,7 @@ bool params_ok(const pmc_params& p, std::string& why)
     if (!(p.f_mcs >= 0.0 && p.f_mcs < 10.0)) { why = "f_mcs out of range"; return false; }
     if (!(p.s_min_cm > 0.0 && p.s_min_cm < 1.0)) { why = "s_min_cm out of range"; return false; }
     if (p.k_batches < 2 || p.k_batches > 64) { why = "k_batches must be in [2, 64]"; return false; }
-    if (p.flags & ~15u) { why = "unknown flags"; return false; }
+    if (p.flags & ~31u) { why = "unknown flags"; return false; }
     if (p.block_threads != 0 && (p.block_threads < 64 || p.block_threads > 1024 || p.block_threads % 64))
     { why = "block_threads must be 0 or a multiple of 64 in [64, 1024]"; return false; }
     if (p.blocks_per_cu < 0 || p.blocks_per_cu > 64) { why = "blocks_per_cu out of range"; return false; }
@@ -462,6 +468,8 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
     a.el_sig = c->d_el_sig.p; a.mat_npg = c->d_npg.p; a.elem = c->d_elem.p;
     a.sec_mult = c->d_mult.p; a.sec_floc = c->d_floc.p; a.sec_x = c->d_xcdf.p; a.sec_mu = c->d_mucdf.p;
     a.vav = c->d_vav.p;
+    a.mol = c->d_mol.p;
+    a.molmat = c->d_molmat.p;
     a.k_batches = K;
     a.flags = c->p.flags | (let ? kScoreLet : 0u);
     a.f_mcs = (float)c->p.f_mcs;
@@ -828,6 +836,15 @@ pmc_status pmc_create(pmc_ctx** out, int device, const pmc_params* p)
             return PMC_ERR_DEVICE;
         }
     c->num_cu = prop.multiProcessorCount;
+    if (prm.flags & PMC_MOLIERE) {
+        const std::vector<float>& t = moliere_table();
+        if ((e = c->d_mol.ensure(t.size())) != hipSuccess ||
+            (e = hipMemcpy(c->d_mol.p, t.data(), t.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) {
+            g_create_error = std::string("Moliere table upload: ") + hipGetErrorString(e);
+            pmc_destroy(c);
+            return PMC_ERR_DEVICE;
+        }
+    }
     if (prm.flags & PMC_VAVILOV) {
         const std::vector<float>& t = vavilov_table();
         if ((e = c->d_vav.ensure(t.size())) != hipSuccess ||
@@ -838,6 +855,14 @@ pmc_status pmc_create(pmc_ctx** out, int device, const pmc_params* p)
         }
     }
     *out = c;
+    return PMC_OK;
+}
+
+pmc_status pmc_moliere_table(float* out, int32_t n_floats)
+{
+    const std::vector<float>& t = moliere_table();
+    if (!out || n_floats < (int32_t)t.size()) return PMC_ERR_ARG;
+    std::copy(t.begin(), t.end(), out);
     return PMC_OK;
 }
 

@@ -65,6 +65,14 @@ struct Material {
 constexpr int kVavNB = 5, kVavNK = 31, kVavNZ = 97;
 const std::vector<float>& vavilov_table();
 
+// Molière sampling table (built once per process): ln(v^2 / q) at
+// [1/B = 1/20 + j (2/9 - 1/20)/12][q = k/8]; and the per-material constants
+// the kernel's step needs: {sum w Z(Z+1)/A, sum_i omega_i ln chi_0,i^2 (pc)^2,
+// omega_i (i < 7), 3.76 (Z_i alpha)^2 (i < 7)}, omega_i the Z(Z+1)/A weights.
+constexpr int kMolNX = 13, kMolNQ = 161, kMolMatFloats = 16;
+const std::vector<float>& moliere_table();
+void moliere_material(const double w[kNEl], float out[kMolMatFloats]);
+
 // Validates and derives the per-bin materials; returns "" or an error text.
 std::string build_materials(int n_bins, const int16_t* hu_lo, const float* rho_lo,
                             const float* rho_hi, const float* mass_frac, const float* i_ev,

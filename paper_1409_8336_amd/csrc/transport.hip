@@ -54,7 +54,7 @@ constexpr float kVavXi = 0.150233246f;             // (K/2) / (2 m_e c^2), cm^2 
 constexpr float kMeOverMp = 5.44617021e-4f;
 constexpr float kInf = 3.0e38f;
 constexpr uint32_t kMaxSteps = 1u << 20;
-constexpr uint32_t kNoStraggle = 1u, kNoMcs = 2u, kNoNuclear = 4u, kVavilov = 8u;
+constexpr uint32_t kNoStraggle = 1u, kNoMcs = 2u, kNoNuclear = 4u, kVavilov = 8u, kMoliere = 16u;
 
 // ---------------------------------------------------------------- helpers
 
@@ -302,6 +302,8 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
         L->sec_x = a.sec_x;
         L->sec_mu = a.sec_mu;
         L->vav = a.vav;
+        L->mol = a.mol;
+        L->molmat = a.molmat;
         L->spots = a.spots;
         L->order = a.order;
         L->q_in = a.q_in;
@@ -773,11 +775,52 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
             }
             float theta = 0.f;
             if (!(flags & kNoMcs)) {
-                const float x0 = mx0 * frcp(rho);
-                float br = 1.f + 0.038f * fln(s * frcp(x0 * b2));
-                br = br > 0.f ? br : 0.f;
-                const float th0 = a.f_mcs * 13.6f * frcp(pv) * fsqrt(s * frcp(x0)) * br;
-                theta = th0 * fsqrt(-2.f * fln(u01(r.y)));
+                bool moliere = false;
+                if (flags & kMoliere) {
+                    // Molière (Sec. II.A.2 option), Bethe's form: chi_c^2 =
+                    // K m_e c^2 sum w Z(Z+1)/A rho s / (p beta)^2; the
+                    // screening angle from the Z(Z+1)/A-weighted logs of the
+                    // elements' chi_a^2 = chi_0^2 (1.13 + 3.76 (Z alpha/beta)^2);
+                    // B - ln B = ln(chi_c^2 / 1.167 chi_a^2); B >= 4.5 only
+                    const GLOBAL float* mm = gbl(L->molmat) + 16 * m;   // 16 floats per material
+                    const float lc = fln(kStraggleK * mm[0] * rho * s) - 2.f * fln(pv);
+                    const float ib2 = frcp(b2);
+                    float la = mm[1] - fln(pv * e_tot);
+#pragma unroll
+                    for (int el = 0; el < 7; ++el) {
+                        const float om = mm[2 + el];
+                        if (om > 0.f) la += om * fln(1.13f + mm[9 + el] * ib2);
+                    }
+                    const float bb = lc - 0.154436f - la;          // ln 1.167
+                    if (bb >= 2.9959226f) {                         // 4.5 - ln 4.5
+                        float B = bb + fln(bb);
+#pragma unroll
+                        for (int it = 0; it < 4; ++it) B -= (B - fln(B) - bb) * frcp(1.f - frcp(B));
+                        // reduced angle v^2 = q R(q, 1/B), q = -ln u; ln R
+                        // bilinear in (1/B, q) on [1/20, 2/9] x [0, 20]
+                        const float x = fminf(fmaxf(frcp(B), 0.05f), 0.2222222f);
+                        float fx = (x - 0.05f) * (12.f / (0.2222222f - 0.05f));
+                        const int jx = min((int)fx, 11);
+                        fx -= (float)jx;
+                        const float q = -fln(u01(r.y));
+                        float fq = q * 8.f;
+                        const int kq = min((int)fq, 159);
+                        fq -= (float)kq;
+                        const GLOBAL float* t0 = gbl(L->mol) + jx * 161 + kq;
+                        const float ra = t0[0] + fq * (t0[1] - t0[0]);
+                        const float rb = t0[161] + fq * (t0[162] - t0[161]);
+                        const float v2 = q * fexp(ra + fx * (rb - ra));
+                        theta = fminf(fsqrt(fexp(lc) * B * v2), 3.14159265f);
+                        moliere = true;
+                    }
+                }
+                if (!moliere) {
+                    const float x0 = mx0 * frcp(rho);
+                    float br = 1.f + 0.038f * fln(s * frcp(x0 * b2));
+                    br = br > 0.f ? br : 0.f;
+                    const float th0 = a.f_mcs * 13.6f * frcp(pv) * fsqrt(s * frcp(x0)) * br;
+                    theta = th0 * fsqrt(-2.f * fln(u01(r.y)));
+                }
             }
             // random hinge at a uniform fraction of the step; on a
             // boundary-limited step the second segment runs along the new

@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libpmc.so")
 
 PMC_OK, PMC_ERR_ARG, PMC_ERR_RANGE, PMC_ERR_NOMEM = 0, -1, -2, -3
 PMC_ERR_DEVICE, PMC_ERR_QUEUE_OVERFLOW, PMC_ERR_STATE = -4, -5, -6
-PMC_NO_STRAGGLE, PMC_NO_MCS, PMC_NO_NUCLEAR, PMC_VAVILOV = 1, 2, 4, 8
+PMC_NO_STRAGGLE, PMC_NO_MCS, PMC_NO_NUCLEAR, PMC_VAVILOV, PMC_MOLIERE = 1, 2, 4, 8, 16
+MOL_SHAPE = (13, 161)     # [1/B = 1/20 + j (2/9 - 1/20)/12][q = k/8]
 VAV_SHAPE = (5, 31, 97)   # [beta^2 = k/10][log10 kappa = -2 + j/10][z = -6 + i/8]
 
 # every symbol include/pmc.h declares
@@ -25,7 +26,7 @@ EXPORTS = ("pmc_default_params", "pmc_create", "pmc_destroy", "pmc_last_error",
            "pmc_load_physics", "pmc_load_geometry", "pmc_run_spots", "pmc_run_spots_dev",
            "pmc_inspect_tables", "pmc_atomic_probe", "pmc_load_geometry_slot", "pmc_run_plans",
            "pmc_geometry_density", "pmc_version", "pmc_run_spots_let", "pmc_run_spots_let_dev",
-           "pmc_vavilov_table")
+           "pmc_vavilov_table", "pmc_moliere_table")
 
 
 class PMCError(RuntimeError):
@@ -130,6 +131,7 @@ def lib():
         L.pmc_run_plans.argtypes = [vp, C.POINTER(pmc_plan), i32, u64, vp]
         L.pmc_geometry_density.argtypes = [vp, i32, vp, vp]
         L.pmc_vavilov_table.argtypes = [vp, C.c_int32]
+        L.pmc_moliere_table.argtypes = [vp, C.c_int32]
         L.pmc_version.restype = C.c_char_p
         for name in EXPORTS:
             if name not in ("pmc_last_error", "pmc_version"):
@@ -338,6 +340,13 @@ def pmc_vavilov_table():
     """The engine's Vavilov straggling quantile table, VAV_SHAPE (host only)."""
     out = np.zeros(VAV_SHAPE, np.float32)
     _check(None, lib().pmc_vavilov_table(_ptr(out), out.size))
+    return out
+
+
+def pmc_moliere_table():
+    """The engine's Molière sampling table, MOL_SHAPE (host only)."""
+    out = np.zeros(MOL_SHAPE, np.float32)
+    _check(None, lib().pmc_moliere_table(_ptr(out), out.size))
     return out
 
 

@@ -46,7 +46,7 @@ def test_create_rejects_bad_params_before_device(lib):
     h = C.c_void_p()
     assert lib.pmc_create(None, 0, None) == pmc.PMC_ERR_ARG
     for bad in (dict(k_batches=1), dict(k_batches=65), dict(block_threads=100),
-                dict(s_min_cm=0.0), dict(flags=16), dict(flags=64)):
+                dict(s_min_cm=0.0), dict(flags=32), dict(flags=64)):
         p = pmc.pmc_default_params(**bad)
         assert lib.pmc_create(C.byref(h), 0, C.byref(p)) == pmc.PMC_ERR_ARG
         assert pmc.pmc_last_error(None) != ""
@@ -101,3 +101,18 @@ def test_denoiser_and_gamma_reject_bad_arguments(lib):
                              C.byref(rate), C.byref(n), None) == pmc.PMC_ERR_ARG
     assert L.pmc_gamma_index(one, one, 4, 4, 4, 0.2, 0.2, 0.2, 0.02, 0.2, 0.1, 10.0, 0.05, None,
                              C.byref(rate), C.byref(n), None) == pmc.PMC_ERR_ARG
+
+
+def test_engine_moliere_table_matches_oracle():
+    """The engine's Molière table (J0 densities on a v grid, running Simpson
+    integrals) against the oracle's (J1 running integrals in closed form,
+    Simpson in u): ln(v^2/q) within 5e-4 everywhere, i.e. the sampled angles
+    within 0.025%."""
+    import numpy as np
+    from oracle import oracle as O
+    eng = pmc.pmc_moliere_table().astype(np.float64)
+    ora = O.moliere_table()
+    assert np.all(np.isfinite(eng))
+    assert np.max(np.abs(eng - ora)) < 5e-4
+    buf = (C.c_float * 16)()
+    assert pmc.lib().pmc_moliere_table(buf, 16) == pmc.PMC_ERR_ARG
