@@ -32,8 +32,8 @@ HBM_PEAK = 8.0e12
 # HBM bytes per transport launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
 # scaled by a plain-copy calibration, valid only for the kernel source whose
 # sha256 is recorded (see profiles/); None once the kernel has changed.
-TRAFFIC = {"transport_sha256": "ed5a113cfa378bdadf63ce061a2b3b403d81c0b75d2cd892403e0a8136c72c28",
-           "bytes_per_launch": 6.211e9, "let_bytes_per_launch": 1.2964e10}
+TRAFFIC = {"transport_sha256": "55475cc482b334d826b2d62152e6568297e1fde022617ac3553ed0fdc0821664",
+           "bytes_per_launch": 6.2164e9, "let_bytes_per_launch": 1.29626e10}
 
 
 def _kernel_sha():
