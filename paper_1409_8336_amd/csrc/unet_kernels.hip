@@ -248,6 +248,9 @@ __global__ void flip_weights_kernel(const uint16_t* __restrict__ w, uint16_t* __
 // input columns (32 voxels x 16 channels).  The waves split the 16-channel
 // output tiles of the block; where the block has fewer than four of them,
 // they also split the two 32-voxel K-steps and the two input tiles.
+// Staging: a thread takes an 8-voxel x 8-channel block (eight 16-byte
+// loads, one per voxel), transposes it in registers and writes eight
+// 16-byte rows (8 voxels of one channel) to LDS.
 constexpr int kWgSeg = 64;              // voxels per staged segment (two MFMA K-steps)
 constexpr int kWgPitch = kWgSeg + 8;    // LDS row pitch in elements (16-byte multiple)
 __global__ void __launch_bounds__(256) conv3d_wgrad_kernel(const uint16_t* __restrict__ in,
@@ -292,41 +295,53 @@ __global__ void __launch_bounds__(256) conv3d_wgrad_kernel(const uint16_t* __res
         const bool zin = zz >= 0 && zz < D;
         for (int xb = 0; xb < W; xb += kWgSeg) {
             __syncthreads();
-            // output gradient at x = xb - 1 .. xb + 64 (slot xs = x - xb + 1),
-            // 8 channels per task, into the copy of each kx where it is used
-            for (int i = threadIdx.x; i < (kWgSeg + 2) * 8; i += 256) {
-                const int cg = i & 7, xs = i >> 3;
-                const int x = xb + xs - 1;
-                uint4 v = make_uint4(0u, 0u, 0u, 0u);
-                if (x >= 0 && x < W && co0 + 8 * cg < Cout)
-                    v = *reinterpret_cast<const uint4*>(
-                        dout + (nbase + (size_t)z * plane + (size_t)y * W + x) * Cout + co0 + 8 * cg);
-                const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+            // tasks 0..191: output gradient, copy kx, channels co0 + 8 cg ..,
+            // slots xp = 8 vg .. 8 vg + 7 holding x = xb + xp + 1 - kx;
+            // tasks 192..287: input rows (zz, y + ky - 1), channels
+            // ci0 + 8 cg .., x = xb + 8 vg ..
+            for (int i = threadIdx.x; i < 288; i += 256) {
+                const bool is_do = i < 192;
+                const int t = is_do ? i : i - 192;
+                const int cg = is_do ? (t & 7) : (t & 3);
+                const int vg = is_do ? ((t >> 3) & 7) : ((t >> 2) & 7);
+                const int cpy = is_do ? (t >> 6) : (t >> 5);        // kx or ky
+                const int C = is_do ? Cout : Cin;
+                const int c0 = (is_do ? co0 : ci0) + 8 * cg;
+                // output-gradient rows past Cout are never read (Cout is a
+                // multiple of 16); input rows past Cin are read by the MFMAs
+                // of discarded columns and are written as zeros
+                if (is_do && c0 >= C) continue;
+                const int yy = is_do ? y : y + cpy - 1;
+                const int zp = is_do ? z : zz;
+                const bool row_ok = c0 < C && (is_do || (zin && yy >= 0 && yy < H));
+                const int x0 = is_do ? xb + 8 * vg + 1 - cpy : xb + 8 * vg;
+                const uint16_t* src = (is_do ? dout : in) + (nbase + (size_t)zp * plane + (size_t)yy * W) * C + c0;
+                uint4 v[8];
 #pragma unroll
-                for (int kx = 0; kx < 3; ++kx) {
-                    const int xp = xs + kx - 2;     // x' - xb with x' = x + kx - 1
-                    if (xp < 0 || xp >= kWgSeg) continue;
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        sdo[kx][8 * cg + 2 * j][xp] = (uint16_t)(wv[j] & 0xFFFFu);
-                        sdo[kx][8 * cg + 2 * j + 1][xp] = (uint16_t)(wv[j] >> 16);
-                    }
+                for (int j = 0; j < 8; ++j) {
+                    const int x = x0 + j;
+                    v[j] = make_uint4(0u, 0u, 0u, 0u);
+                    if (row_ok && x >= 0 && x < W) v[j] = *reinterpret_cast<const uint4*>(src + (size_t)x * C);
                 }
-            }
-            // input rows (zz, y + ky - 1) at x = xb .. xb + 63
-            for (int i = threadIdx.x; i < 3 * kWgSeg * 4; i += 256) {
-                const int cg = i & 3, rest = i >> 2;
-                const int xo = rest % kWgSeg, ky = rest / kWgSeg;
-                const int yy = y + ky - 1, x = xb + xo;
-                uint4 v = make_uint4(0u, 0u, 0u, 0u);
-                if (zin && yy >= 0 && yy < H && x < W && ci0 + 8 * cg < Cin)
-                    v = *reinterpret_cast<const uint4*>(
-                        in + (nbase + (size_t)zz * plane + (size_t)yy * W + x) * Cin + ci0 + 8 * cg);
-                const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+                // channel c = 2 q + h of voxel j is half h of word q of v[j];
+                // row c = the 8 voxels' halves, packed in pairs of voxels
+                uint16_t* dst = is_do ? &sdo[cpy][8 * cg][8 * vg] : &sin[cpy][8 * cg][8 * vg];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    sin[ky][8 * cg + 2 * j][xo] = (uint16_t)(wv[j] & 0xFFFFu);
-                    sin[ky][8 * cg + 2 * j + 1][xo] = (uint16_t)(wv[j] >> 16);
+                for (int q = 0; q < 4; ++q) {
+                    uint32_t w[8];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) w[j] = q == 0 ? v[j].x : (q == 1 ? v[j].y : (q == 2 ? v[j].z : v[j].w));
+                    uint4 lo, hi;
+                    lo.x = (w[0] & 0xFFFFu) | (w[1] << 16);
+                    lo.y = (w[2] & 0xFFFFu) | (w[3] << 16);
+                    lo.z = (w[4] & 0xFFFFu) | (w[5] << 16);
+                    lo.w = (w[6] & 0xFFFFu) | (w[7] << 16);
+                    hi.x = (w[0] >> 16) | (w[1] & 0xFFFF0000u);
+                    hi.y = (w[2] >> 16) | (w[3] & 0xFFFF0000u);
+                    hi.z = (w[4] >> 16) | (w[5] & 0xFFFF0000u);
+                    hi.w = (w[6] >> 16) | (w[7] & 0xFFFF0000u);
+                    *reinterpret_cast<uint4*>(dst + (2 * q) * kWgPitch) = lo;
+                    *reinterpret_cast<uint4*>(dst + (2 * q + 1) * kWgPitch) = hi;
                 }
             }
             __syncthreads();
