@@ -248,9 +248,11 @@ __global__ void flip_weights_kernel(const uint16_t* __restrict__ w, uint16_t* __
 // input columns (32 voxels x 16 channels).  The waves split the 16-channel
 // output tiles of the block; where the block has fewer than four of them,
 // they also split the two 32-voxel K-steps and the two input tiles.
-// Staging: a thread takes an 8-voxel x 8-channel block (eight 16-byte
-// loads, one per voxel), transposes it in registers and writes eight
-// 16-byte rows (8 voxels of one channel) to LDS.
+// Staging: a thread takes an 8-voxel x 8-channel block (one 16-byte load per
+// voxel), transposes it in registers and writes eight 16-byte rows (8 voxels
+// of one channel) to LDS; the three x-shifted output-gradient copies come
+// from one load of 10 voxels, and the block walks its rows with the input
+// rows in a three-slot ring (one new row per row where the plane continues).
 constexpr int kWgSeg = 64;              // voxels per staged segment (two MFMA K-steps)
 constexpr int kWgPitch = kWgSeg + 8;    // LDS row pitch in elements (16-byte multiple)
 __global__ void __launch_bounds__(256) conv3d_wgrad_kernel(const uint16_t* __restrict__ in,
@@ -268,8 +270,11 @@ __global__ void __launch_bounds__(256) conv3d_wgrad_kernel(const uint16_t* __res
     const int cib = (blockIdx.y / 3) % n_ci_blk;
     const int cob = blockIdx.y / (3 * n_ci_blk);
     const int ci0 = cib * 32, co0 = cob * 64;
-    // this wave's share: output tile ct, K-steps and input tiles
+    // this wave's share: output tile ct, K-steps and input tiles (an input
+    // block with 16 channels or fewer has one input tile: the second is
+    // neither staged nor multiplied)
     const int n_cot = min(4, (Cout - co0 + 15) / 16);
+    const int n_cit = min(2, (Cin - ci0 + 15) / 16);
     int ct, ks_sel = -1, cit_sel = -1;
     if (n_cot >= 3) {
         ct = wave;
@@ -281,67 +286,88 @@ __global__ void __launch_bounds__(256) conv3d_wgrad_kernel(const uint16_t* __res
         ks_sel = wave & 1;
         cit_sel = wave >> 1;
     }
-    const bool active = ct < n_cot;
+    const bool active = ct < n_cot && (cit_sel < 0 || cit_sel < n_cit);
     const int total_rows = N * D * H;
     const int row0 = blockIdx.x * rows_per_block;
+    const int r_end = min(row0 + rows_per_block, total_rows);
     const size_t plane = (size_t)H * W;
     f32x4 acc[18];
 #pragma unroll
     for (int t = 0; t < 18; ++t) acc[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
-    for (int r = row0; r < row0 + rows_per_block && r < total_rows; ++r) {
-        const int y = r % H, nz = r / H, z = nz % D;
-        const size_t nbase = (size_t)(nz - z) * plane;
-        const int zz = z + kz - 1;
-        const bool zin = zz >= 0 && zz < D;
-        for (int xb = 0; xb < W; xb += kWgSeg) {
+    // 8 voxels of one channel group -> 8 LDS rows (channel c = 2 q + h of
+    // voxel j is half h of word q of v[j]; a row packs the voxels in pairs)
+    auto put = [](uint16_t* dst, const uint4* v) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            uint32_t w[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) w[j] = q == 0 ? v[j].x : (q == 1 ? v[j].y : (q == 2 ? v[j].z : v[j].w));
+            uint4 lo, hi;
+            lo.x = (w[0] & 0xFFFFu) | (w[1] << 16);
+            lo.y = (w[2] & 0xFFFFu) | (w[3] << 16);
+            lo.z = (w[4] & 0xFFFFu) | (w[5] << 16);
+            lo.w = (w[6] & 0xFFFFu) | (w[7] << 16);
+            hi.x = (w[0] >> 16) | (w[1] & 0xFFFF0000u);
+            hi.y = (w[2] >> 16) | (w[3] & 0xFFFF0000u);
+            hi.z = (w[4] >> 16) | (w[5] & 0xFFFF0000u);
+            hi.w = (w[6] >> 16) | (w[7] & 0xFFFF0000u);
+            *reinterpret_cast<uint4*>(dst + (2 * q) * kWgPitch) = lo;
+            *reinterpret_cast<uint4*>(dst + (2 * q + 1) * kWgPitch) = hi;
+        }
+    };
+    // x segments outside, the block's rows inside: the input rows of row r
+    // (y + ky - 1, ky < 3) sit in the ring slot (y + ky - 1 + 3) % 3, and the
+    // next row of the same plane stages only its new row y + 2
+    for (int xb = 0; xb < W; xb += kWgSeg) {
+        int prev_nz = -1, prev_y = -2;
+        for (int r = row0; r < r_end; ++r) {
+            const int y = r % H, nz = r / H, z = nz % D;
+            const size_t nbase = (size_t)(nz - z) * plane;
+            const int zz = z + kz - 1;
+            const bool zin = zz >= 0 && zz < D;
+            const bool slide = nz == prev_nz && y == prev_y + 1;
+            prev_nz = nz;
+            prev_y = y;
+            const int n_new = slide ? 1 : 3;            // input rows to stage
             __syncthreads();
-            // tasks 0..191: output gradient, copy kx, channels co0 + 8 cg ..,
-            // slots xp = 8 vg .. 8 vg + 7 holding x = xb + xp + 1 - kx;
-            // tasks 192..287: input rows (zz, y + ky - 1), channels
-            // ci0 + 8 cg .., x = xb + 8 vg ..
-            for (int i = threadIdx.x; i < 288; i += 256) {
-                const bool is_do = i < 192;
-                const int t = is_do ? i : i - 192;
-                const int cg = is_do ? (t & 7) : (t & 3);
-                const int vg = is_do ? ((t >> 3) & 7) : ((t >> 2) & 7);
-                const int cpy = is_do ? (t >> 6) : (t >> 5);        // kx or ky
-                const int C = is_do ? Cout : Cin;
-                const int c0 = (is_do ? co0 : ci0) + 8 * cg;
-                // output-gradient rows past Cout are never read (Cout is a
-                // multiple of 16); input rows past Cin are read by the MFMAs
-                // of discarded columns and are written as zeros
-                if (is_do && c0 >= C) continue;
-                const int yy = is_do ? y : y + cpy - 1;
-                const int zp = is_do ? z : zz;
-                const bool row_ok = c0 < C && (is_do || (zin && yy >= 0 && yy < H));
-                const int x0 = is_do ? xb + 8 * vg + 1 - cpy : xb + 8 * vg;
-                const uint16_t* src = (is_do ? dout : in) + (nbase + (size_t)zp * plane + (size_t)yy * W) * C + c0;
-                uint4 v[8];
+            const int i = threadIdx.x;
+            if (i < 64) {
+                // output gradient of row r, channels co0 + 8 cg .., voxels
+                // x = xb + 8 vg - 1 .. + 8 loaded once; copy kx holds slot
+                // xp = x - xb + kx - 1 (the voxel x = xb + xp + 1 - kx)
+                const int cg = i & 7, vg = i >> 3;
+                const int c0 = co0 + 8 * cg;
+                if (c0 < Cout) {
+                    const uint16_t* src = dout + (nbase + (size_t)z * plane + (size_t)y * W) * Cout + c0;
+                    uint4 u[10];
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const int x = x0 + j;
-                    v[j] = make_uint4(0u, 0u, 0u, 0u);
-                    if (row_ok && x >= 0 && x < W) v[j] = *reinterpret_cast<const uint4*>(src + (size_t)x * C);
+                    for (int k = 0; k < 10; ++k) {
+                        const int x = xb + 8 * vg - 1 + k;
+                        u[k] = make_uint4(0u, 0u, 0u, 0u);
+                        if (x >= 0 && x < W) u[k] = *reinterpret_cast<const uint4*>(src + (size_t)x * Cout);
+                    }
+#pragma unroll
+                    for (int kx = 0; kx < 3; ++kx) put(&sdo[kx][8 * cg][8 * vg], u + 2 - kx);
                 }
-                // channel c = 2 q + h of voxel j is half h of word q of v[j];
-                // row c = the 8 voxels' halves, packed in pairs of voxels
-                uint16_t* dst = is_do ? &sdo[cpy][8 * cg][8 * vg] : &sin[cpy][8 * cg][8 * vg];
+            } else if (i < 64 + 32 * n_new) {
+                // input row yy = y + 1 (slide) or y - 1 + k, channels
+                // ci0 + 8 cg .., x = xb + 8 vg ..; input rows past Cin
+                // inside a used tile are staged as zeros
+                const int t = i - 64;
+                const int cg = t & 3, vg = (t >> 2) & 7, k = t >> 5;
+                if (cg < 2 * n_cit) {
+                    const int yy = slide ? y + 1 : y - 1 + k;
+                    const int c0 = ci0 + 8 * cg;
+                    const bool ok = zin && yy >= 0 && yy < H && c0 < Cin;
+                    const uint16_t* src = in + (nbase + (size_t)zz * plane + (size_t)yy * W) * Cin + c0;
+                    uint4 v[8];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    uint32_t w[8];
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) w[j] = q == 0 ? v[j].x : (q == 1 ? v[j].y : (q == 2 ? v[j].z : v[j].w));
-                    uint4 lo, hi;
-                    lo.x = (w[0] & 0xFFFFu) | (w[1] << 16);
-                    lo.y = (w[2] & 0xFFFFu) | (w[3] << 16);
-                    lo.z = (w[4] & 0xFFFFu) | (w[5] << 16);
-                    lo.w = (w[6] & 0xFFFFu) | (w[7] << 16);
-                    hi.x = (w[0] >> 16) | (w[1] & 0xFFFF0000u);
-                    hi.y = (w[2] >> 16) | (w[3] & 0xFFFF0000u);
-                    hi.z = (w[4] >> 16) | (w[5] & 0xFFFF0000u);
-                    hi.w = (w[6] >> 16) | (w[7] & 0xFFFF0000u);
-                    *reinterpret_cast<uint4*>(dst + (2 * q) * kWgPitch) = lo;
-                    *reinterpret_cast<uint4*>(dst + (2 * q + 1) * kWgPitch) = hi;
+                    for (int j = 0; j < 8; ++j) {
+                        const int x = xb + 8 * vg + j;
+                        v[j] = make_uint4(0u, 0u, 0u, 0u);
+                        if (ok && x < W) v[j] = *reinterpret_cast<const uint4*>(src + (size_t)x * Cin);
+                    }
+                    put(&sin[(yy + 3) % 3][8 * cg][8 * vg], v);
                 }
             }
             __syncthreads();
@@ -356,10 +382,11 @@ __global__ void __launch_bounds__(256) conv3d_wgrad_kernel(const uint16_t* __res
                     av[kx] = *reinterpret_cast<const bf16x8*>(&sdo[kx][ct * 16 + m][ks + 8 * g]);
 #pragma unroll
                 for (int cit = 0; cit < 2; ++cit) {
-                    if (cit_sel >= 0 && cit != cit_sel) continue;
+                    if ((cit_sel >= 0 && cit != cit_sel) || cit >= n_cit) continue;
 #pragma unroll
                     for (int ky = 0; ky < 3; ++ky) {
-                        const bf16x8 bv = *reinterpret_cast<const bf16x8*>(&sin[ky][cit * 16 + m][ks + 8 * g]);
+                        const int sl = (y + ky - 1 + 3) % 3;
+                        const bf16x8 bv = *reinterpret_cast<const bf16x8*>(&sin[sl][cit * 16 + m][ks + 8 * g]);
 #pragma unroll
                         for (int kx = 0; kx < 3; ++kx) {
                             const int t = (ky * 3 + kx) * 2 + cit;
