@@ -236,3 +236,29 @@ def test_let_at_the_field_size(nd, mt):
     mean = float((let[hi] * b[hi]).sum() / b[hi].sum())
     _say("dose-weighted mean LET_d above 10%% of max: %.3f keV/um" % mean)
     assert 0.4 < mean < 4.0, mean
+
+
+def test_let_with_vavilov_and_moliere(nd, mt):
+    """All three options in one run (LET_d scored, Vavilov straggling,
+    Molière scattering) against the oracle with the same options: the dose
+    bars of the parity tests and the LET_d bars above."""
+    from parity_tools import compare, density_grid
+    _say("case: LET + Vavilov + Moliere")
+    cfg = synth.config_ct_spots(150.0, 60_000)
+    e = _engine(nd, mt, cfg["hu"], flags=pmc.PMC_VAVILOV | pmc.PMC_MOLIERE)
+    gd, gv, gl, gs = e.run_spots_let(cfg["spots"], cfg["n_histories"], 1)
+    e.close()
+    o = O.Oracle(flags=O.VAVILOV | O.MOLIERE)
+    o.load_physics(nd)
+    o.load_geometry(cfg["hu"], (0.2, 0.2, 0.2), mt)
+    r1 = o.run_spots(cfg["spots"], cfg["n_histories"], 1, let=True)
+    r2 = o.run_spots(cfg["spots"], cfg["n_histories"], 2, let=True)
+    m = compare(gd, gv, r1["dose"], r1["var"], density_grid(cfg["hu"]), (0.2, 0.2, 0.2),
+                gs["total_weight"], r1["summary"]["total_weight"])
+    same = _let_metrics(gl, r1["let"], r1["dose"])
+    indep = _let_metrics(r2["let"], r1["let"], r1["dose"])
+    _say("dose %s; LET same seed %s, oracle seeds %s" % (m, same, indep))
+    assert m["idd_max_rel"] <= 0.01 and m["r80_diff_mm"] <= 0.2, m
+    assert m["all_within_3sigma"] or m["frac_z_gt3"] <= 0.01, m
+    assert ledger_residual(gs) < 1e-5
+    assert same["slab_max"] <= 0.01 and same["rms"] <= indep["rms"], (same, indep)
