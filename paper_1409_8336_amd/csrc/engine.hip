@@ -24,8 +24,8 @@
 namespace pmc {
 hipError_t launch_transport(const KernelArgs& a, bool multi, int grid, int block, size_t lds_bytes,
                             hipStream_t s);
-hipError_t transport_occupancy(bool multi, int block, size_t lds_bytes, int* blocks_per_cu);
-hipError_t transport_max_block(bool multi, int* max_threads);
+hipError_t transport_occupancy(bool multi, uint32_t flags, int block, size_t lds_bytes, int* blocks_per_cu);
+hipError_t transport_max_block(bool multi, uint32_t flags, int* max_threads);
 hipError_t launch_stats(const double* tally, const uint2* vox, unsigned long long nvox, int K,
                         double conv0, double* dose, double* var, double* dep_sum, double* let,
                         hipStream_t s);
@@ -520,10 +520,10 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
     // batched launches: per-plan ledger and counters after the arguments
     const size_t lds = (size_t)a.args_off * 4 + sizeof(LdsArgs) + (multi ? kPlanLdsBytes * (size_t)np : 0);
     int max_block = 0;
-    HIPCHK(transport_max_block(multi, &max_block), "kernel attributes");
+    HIPCHK(transport_max_block(multi, a.flags, &max_block), "kernel attributes");
     if (block > max_block) return fail(c, PMC_ERR_ARG, "block_threads exceeds the transport kernel's limit");
     int bpc = shape.blocks_per_cu, fit = 0;
-    HIPCHK(transport_occupancy(multi, block, lds, &fit), "occupancy");
+    HIPCHK(transport_occupancy(multi, a.flags, block, lds, &fit), "occupancy");
     if (fit < 1) return fail(c, PMC_ERR_DEVICE, "transport kernel does not fit on a CU");
     if (bpc == 0 || bpc > fit) bpc = fit;
     const int grid = c->num_cu * bpc;

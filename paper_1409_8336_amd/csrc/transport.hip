@@ -244,7 +244,10 @@ struct Plans<true> {
 
 // -------------------------------------------------------------- the kernel
 
-template <bool kMulti>
+// kOpt: the instantiation with the optional paths (LET_d scoring, Vavilov
+// straggling, Molière scattering; each still selected by its run flag); the
+// other one carries none of their code
+template <bool kMulti, bool kOpt>
 __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
 {
     // all LDS is the dynamic allocation (no static __shared__ variables, so
@@ -264,7 +267,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
     constexpr Key kEmptySlot = ~Key(0);
     const int n_slots = a.cache_slots;
     const bool use_cache = n_slots > 0;
-    const bool score_let = (a.flags & kScoreLet) != 0u;
+    const bool score_let = kOpt && (a.flags & kScoreLet) != 0u;
     double* const cval = reinterpret_cast<double*>(lds + a.cache_off);
     Key* const ckey = reinterpret_cast<Key*>(lds + a.cache_off + 2 * n_slots);
     float* const cnum = reinterpret_cast<float*>(ckey + n_slots);
@@ -440,7 +443,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
     // the plane that the LET denominator subtracts from the dose
     auto deposit_local = [&](unsigned long long vi, double v) {
         deposit(vi * K + batch, v);
-        if (flags & kScoreLet) {
+        if (kOpt && (flags & kScoreLet)) {
             const unsigned long long nv = (unsigned long long)P.nx(plan) * P.ny(plan) * P.nz(plan);
             deposit(nv * (K + 1) + vi, v);
         }
@@ -742,7 +745,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                 const float g = e_tot * (1.0f / kMp);
                 const float var = kStraggleK * rho * mza * s * g * g * (1.f - 0.5f * b2);
                 float z = 1.414213562f * inv_erf(2.f * u01(r.w) - 1.f);
-                if (flags & kVavilov) {
+                if (kOpt && (flags & kVavilov)) {
                     // Vavilov-Gaussian (Sec. II.A.2): the normal score through
                     // the Vavilov quantile function of the step's kappa =
                     // xi / T_max and beta^2, tabulated at log10 kappa = -2 +
@@ -776,7 +779,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
             float theta = 0.f;
             if (!(flags & kNoMcs)) {
                 bool moliere = false;
-                if (flags & kMoliere) {
+                if (kOpt && (flags & kMoliere)) {
                     // Molière (Sec. II.A.2 option), Bethe's form: chi_c^2 =
                     // K m_e c^2 sum w Z(Z+1)/A rho s / (p beta)^2; the
                     // screening angle from the Z(Z+1)/A-weighted logs of the
@@ -858,7 +861,7 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
             const float e_new = E - de;
             // range-limited: the proton stops in this voxel with all of E
             const double dep = stop_here ? (double)w * (double)E : (double)w * ((double)E - (double)e_new);
-            if (flags & kScoreLet) {
+            if (kOpt && (flags & kScoreLet)) {
                 // LET_d numerator: the deposit times the medium's stopping
                 // power averaged over the step's mean loss (over the residual
                 // range when the range ends the step), MeV/cm
@@ -1360,18 +1363,36 @@ __global__ void zero_kernel(unsigned long long* __restrict__ p, unsigned long lo
 
 // ------------------------------------------------------------- launchers
 
+namespace {
+// the instantiation for a launch: batched or not, with the optional paths if
+// any of their flags is set
+const void* kernel_for(bool multi, bool opt)
+{
+    if (multi) return opt ? (const void*)transport_kernel<true, true> : (const void*)transport_kernel<true, false>;
+    return opt ? (const void*)transport_kernel<false, true> : (const void*)transport_kernel<false, false>;
+}
+}  // namespace
+
+bool transport_needs_options(uint32_t flags) { return (flags & (kScoreLet | kVavilov | kMoliere)) != 0u; }
+
 hipError_t launch_transport(const KernelArgs& a, bool multi, int grid, int block, size_t lds_bytes,
                             hipStream_t s)
 {
-    if (multi) hipLaunchKernelGGL(transport_kernel<true>, dim3(grid), dim3(block), lds_bytes, s, a);
-    else hipLaunchKernelGGL(transport_kernel<false>, dim3(grid), dim3(block), lds_bytes, s, a);
+    const bool opt = transport_needs_options(a.flags);
+    if (multi) {
+        if (opt) hipLaunchKernelGGL((transport_kernel<true, true>), dim3(grid), dim3(block), lds_bytes, s, a);
+        else hipLaunchKernelGGL((transport_kernel<true, false>), dim3(grid), dim3(block), lds_bytes, s, a);
+    } else {
+        if (opt) hipLaunchKernelGGL((transport_kernel<false, true>), dim3(grid), dim3(block), lds_bytes, s, a);
+        else hipLaunchKernelGGL((transport_kernel<false, false>), dim3(grid), dim3(block), lds_bytes, s, a);
+    }
     return hipGetLastError();
 }
 
-hipError_t transport_max_block(bool multi, int* max_threads)
+hipError_t transport_max_block(bool multi, uint32_t flags, int* max_threads)
 {
     hipFuncAttributes attr;
-    const void* f = multi ? (const void*)transport_kernel<true> : (const void*)transport_kernel<false>;
+    const void* f = kernel_for(multi, transport_needs_options(flags));
     hipError_t e = hipFuncGetAttributes(&attr, f);
     if (e != hipSuccess) return e;
     // the LDS layout assumes the dynamic allocation starts at byte 0
@@ -1380,18 +1401,14 @@ hipError_t transport_max_block(bool multi, int* max_threads)
     return hipSuccess;
 }
 
-hipError_t transport_occupancy(bool multi, int block, size_t lds_bytes, int* blocks_per_cu)
+hipError_t transport_occupancy(bool multi, uint32_t flags, int block, size_t lds_bytes, int* blocks_per_cu)
 {
-    const void* f = multi ? (const void*)transport_kernel<true> : (const void*)transport_kernel<false>;
+    const void* f = kernel_for(multi, transport_needs_options(flags));
     if (lds_bytes > 65536) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
         if (e != hipSuccess) return e;
     }
-    if (multi)
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<true>, block,
-                                                            lds_bytes);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel<false>, block,
-                                                        lds_bytes);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, block, lds_bytes);
 }
 
 hipError_t launch_stats(const double* tally, const uint2* vox, unsigned long long nvox, int K,

@@ -157,3 +157,37 @@ def test_batched_deposit_cache_preserves_results():
             assert tot <= 1.2 * tot0, (tot, tot0)
         _say("%s: global atomics %d of %d deposits (plan 0)"
              % (params, sums[0]["global_atomics"], sums[0]["tally_atomics"]))
+
+
+def test_batched_options_equal_single_plans():
+    """The batched kernel with every option on (LET_d scored, Vavilov
+    straggling, Molière scattering): each plan equals its single-plan run
+    (same random keys) to summation order."""
+    import torch
+    _say("case: batched options")
+    nd, mt = synth.nuclear_data(), synth.material_table()
+    plans = synth.plan_set(n_plans=3, seed=220, hist_scale=0.02, max_grid=(80, 80, 120),
+                           min_grid=(40, 40, 60))
+    flags = pmc.PMC_VAVILOV | pmc.PMC_MOLIERE
+    e, ids = _batch_engine(nd, mt, plans, flags=flags)
+    bufs, spec = [], []
+    for gid, p in zip(ids, plans):
+        d = torch.zeros(p["hu"].shape, dtype=torch.float64, device="cuda")
+        lt = torch.zeros_like(d)
+        bufs.append((d, lt))
+        spec.append(dict(geometry_id=gid, spots=p["spots"], n_histories=p["n_histories"], d_dose=d,
+                         d_let=lt))
+    sums = pmc.pmc_run_plans(e.ctx, spec, 41)
+    torch.cuda.synchronize()
+    e.close()
+    for p, plan in enumerate(plans):
+        single = pmc.Engine(0, flags=flags)
+        single.load_physics(nd)
+        single.load_geometry(plan["hu"], plan["voxel_cm"], mt)
+        d, v, lt, s = single.run_spots_let(plan["spots"], plan["n_histories"], 41 + p)
+        single.close()
+        np.testing.assert_allclose(bufs[p][0].cpu().numpy(), d, rtol=1e-9, atol=1e-9 * d.max())
+        np.testing.assert_allclose(bufs[p][1].cpu().numpy(), lt, rtol=1e-5, atol=1e-12)
+        for key in ("steps", "n_elastic", "n_nonelastic", "histories"):
+            assert sums[p][key] == s[key], (p, key)
+        assert ledger_residual(sums[p]) < 1e-9
