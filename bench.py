@@ -42,7 +42,7 @@ def _kernel_sha():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def cpu_baseline(cfg, target_s=12.0):
+def cpu_baseline(cfg, target_s=18.0):
     from oracle import oracle as O
     from paper_1409_8336_amd import synth
     o = O.Oracle()
@@ -52,7 +52,7 @@ def cpu_baseline(cfg, target_s=12.0):
     probe = 100_000
     r = o.run_spots(cfg["spots"], probe, 2)
     rate = probe / max(r["summary"]["wall_s"], 1e-6)
-    n = int(min(5_000_000, max(probe, rate * target_s)))
+    n = int(min(8_000_000, max(probe, rate * target_s)))
     r = o.run_spots(cfg["spots"], n, 3)
     s = r["summary"]
     o.close()
