@@ -737,7 +737,7 @@ pmc_status choose_shape(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, hipS
                     if (!dup) cands.push_back(x);
                 }
     // every candidate once, then the three fastest twice more: a shape is
-    // judged by the best of its three times, which keeps one noisy
+    // rated by the best of its three times, which keeps one noisy
     // calibration launch from deciding (neighbouring shapes differ by a few
     // per cent)
     std::vector<std::pair<double, int>> times;
