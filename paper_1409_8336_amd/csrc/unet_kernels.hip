@@ -255,6 +255,10 @@ __global__ void flip_weights_kernel(const uint16_t* __restrict__ w, uint16_t* __
 // rows in a three-slot ring (one new row per row where the plane continues).
 constexpr int kWgSeg = 64;              // voxels per staged segment (two MFMA K-steps)
 constexpr int kWgPitch = kWgSeg + 8;    // LDS row pitch in elements (16-byte multiple)
+// kOneCt (Cout <= 16): every wave owns one input tile and one K-step half,
+// so it accumulates 9 tiles (the taps) instead of 18: half the accumulator
+// registers, three workgroups per CU instead of two
+template <bool kOneCt>
 __global__ void __launch_bounds__(256) conv3d_wgrad_kernel(const uint16_t* __restrict__ in,
                                                            const uint16_t* __restrict__ dout,
                                                            float* __restrict__ dw, int N, int D,
@@ -291,9 +295,10 @@ __global__ void __launch_bounds__(256) conv3d_wgrad_kernel(const uint16_t* __res
     const int row0 = blockIdx.x * rows_per_block;
     const int r_end = min(row0 + rows_per_block, total_rows);
     const size_t plane = (size_t)H * W;
-    f32x4 acc[18];
+    constexpr int kTiles = kOneCt ? 9 : 18;
+    f32x4 acc[kTiles];
 #pragma unroll
-    for (int t = 0; t < 18; ++t) acc[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < kTiles; ++t) acc[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
     // 8 voxels of one channel group -> 8 LDS rows (channel c = 2 q + h of
     // voxel j is half h of word q of v[j]; a row packs the voxels in pairs)
     auto put = [](uint16_t* dst, const uint4* v) {
@@ -389,7 +394,7 @@ __global__ void __launch_bounds__(256) conv3d_wgrad_kernel(const uint16_t* __res
                         const bf16x8 bv = *reinterpret_cast<const bf16x8*>(&sin[sl][cit * 16 + m][ks + 8 * g]);
 #pragma unroll
                         for (int kx = 0; kx < 3; ++kx) {
-                            const int t = (ky * 3 + kx) * 2 + cit;
+                            const int t = kOneCt ? ky * 3 + kx : (ky * 3 + kx) * 2 + cit;
                             acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[kx], bv, acc[t], 0, 0, 0);
                         }
                     }
@@ -399,8 +404,8 @@ __global__ void __launch_bounds__(256) conv3d_wgrad_kernel(const uint16_t* __res
     }
     if (!active) return;
 #pragma unroll
-    for (int t = 0; t < 18; ++t) {
-        const int kyx = t >> 1, cit = t & 1;
+    for (int t = 0; t < kTiles; ++t) {
+        const int kyx = kOneCt ? t : t >> 1, cit = kOneCt ? cit_sel : t & 1;
         const int tap = kz * 9 + kyx;
         const int ci = ci0 + cit * 16 + m;
         if (ci >= Cin) continue;
@@ -852,8 +857,12 @@ hipError_t nn_conv3d_wgrad(const uint16_t* in, const uint16_t* dout, float* dw, 
     if (blocks_x < 1) blocks_x = 1;
     const int rows = (total_rows + blocks_x - 1) / blocks_x;
     blocks_x = (total_rows + rows - 1) / rows;
-    hipLaunchKernelGGL(conv3d_wgrad_kernel, dim3(blocks_x, others), dim3(256), 0, s, in, dout, dw, N, D, H, W, Cin,
-                       Cout, Kp, rows);
+    if (Cout <= 16)
+        hipLaunchKernelGGL(conv3d_wgrad_kernel<true>, dim3(blocks_x, others), dim3(256), 0, s, in, dout, dw, N, D, H,
+                           W, Cin, Cout, Kp, rows);
+    else
+        hipLaunchKernelGGL(conv3d_wgrad_kernel<false>, dim3(blocks_x, others), dim3(256), 0, s, in, dout, dw, N, D,
+                           H, W, Cin, Cout, Kp, rows);
     return hipGetLastError();
 }
 
