@@ -21,8 +21,7 @@ hipError_t nn_conv3d_fwd_cat(const uint16_t* in, const uint16_t* coarse, int Cc,
 hipError_t nn_flip_weights(const uint16_t* w, uint16_t* wf, int Cin, int Cout, int Kp, int Kpf, hipStream_t s);
 hipError_t nn_conv3d_wgrad(const uint16_t* in, const uint16_t* dout, float* dw, int N, int D, int H, int W,
                            int Cin, int Cout, int Kp, hipStream_t s);
-hipError_t nn_relu_bwd(uint16_t* dy, const uint16_t* y, size_t n, hipStream_t s);
-hipError_t nn_bias_grad(const uint16_t* dy, float* db, size_t nvox, int C, hipStream_t s);
+hipError_t nn_relu_bias_bwd(uint16_t* dy, const uint16_t* y, float* db, size_t nvox, int C, hipStream_t s);
 hipError_t nn_pool_fwd(const uint16_t* in, uint16_t* out, int N, int D, int H, int W, int C, hipStream_t s);
 hipError_t nn_pool_bwd(const uint16_t* dout, const uint16_t* add, uint16_t* din, int N, int D, int H, int W, int C,
                        hipStream_t s);
@@ -152,8 +151,7 @@ hipError_t conv_bwd(pmc_unet* u, const Conv& c, const Act& x, const Act& y, Act&
 {
     const int d = u->D >> level, h = u->H >> level, w = u->W >> level;
     hipError_t e;
-    if ((e = nn_relu_bwd(dy.p, y.p, dy.nvox * dy.c, s)) != hipSuccess) return e;
-    if ((e = nn_bias_grad(dy.p, u->g + c.off_b, dy.nvox, c.cout, s)) != hipSuccess) return e;
+    if ((e = nn_relu_bias_bwd(dy.p, y.p, u->g + c.off_b, dy.nvox, c.cout, s)) != hipSuccess) return e;
     if ((e = nn_conv3d_wgrad(x.p, dy.p, u->g + c.off_w, u->N, d, h, w, c.cin, c.cout, c.kp, s)) != hipSuccess) return e;
     if (!dx) return hipSuccess;
     if ((e = nn_flip_weights(u->wbf + c.off_wbf, u->wf + c.off_wf, c.cin, c.cout, c.kp, c.kpf, s)) != hipSuccess)

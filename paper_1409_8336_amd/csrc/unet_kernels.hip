@@ -419,32 +419,50 @@ __global__ void __launch_bounds__(256) conv3d_wgrad_kernel(const uint16_t* __res
 
 // ------------------------------------------------------------ elementwise
 
-// dy *= (y > 0 ? 1 : kLeak)   (leaky-ReLU backward through the stored
-// output, which has the sign of the pre-activation)
-__global__ void relu_bwd_kernel(uint16_t* __restrict__ dy, const uint16_t* __restrict__ y, size_t n)
+// Leaky-ReLU backward through the stored output (which has the sign of the
+// pre-activation) and the bias gradient in one pass: dy *= (y > 0 ? 1 :
+// kLeak), rounded to BF16 in place, and db[c] += sum_v dy[v][c] of the
+// rounded values.  A lane takes 8 channels (16 bytes) of a voxel; the
+// block's partial sums meet in LDS, one atomic per (block, channel).
+// C is a multiple of 8 with C / 8 dividing 256.
+__global__ void __launch_bounds__(256) relu_bias_bwd_kernel(uint16_t* __restrict__ dy,
+                                                            const uint16_t* __restrict__ y,
+                                                            float* __restrict__ db, size_t nvox, int C)
 {
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        if (!(bf2f(y[i]) > 0.f)) dy[i] = f2bf(kLeak * bf2f(dy[i]));
-}
-
-// db[c] += sum_v dy[v][c]: lanes stride over voxels for a fixed channel,
-// the block's partial sums meet in LDS, one atomic per (block, channel)
-__global__ void __launch_bounds__(256) bias_grad_kernel(const uint16_t* __restrict__ dy, float* __restrict__ db,
-                                                        size_t nvox, int C)
-{
-    __shared__ float part[256];
-    const int c = threadIdx.x % C;
-    const int lanes_per_c = blockDim.x / C;
-    const int sub = threadIdx.x / C;
-    float s = 0.f;
-    if (sub < lanes_per_c)
-        for (size_t v = (size_t)blockIdx.x * lanes_per_c + sub; v < nvox; v += (size_t)gridDim.x * lanes_per_c)
-            s += bf2f(dy[v * C + c]);
-    part[threadIdx.x] = s;
+    __shared__ float part[256 * 8];
+    const int G = C / 8;                       // channel groups per voxel
+    const int g = threadIdx.x % G;
+    const int lanes_per_g = blockDim.x / G;
+    const int sub = threadIdx.x / G;
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (size_t v = (size_t)blockIdx.x * lanes_per_g + sub; v < nvox; v += (size_t)gridDim.x * lanes_per_g) {
+        uint4* pd = reinterpret_cast<uint4*>(dy + v * C + 8 * g);
+        const uint4 yv = *reinterpret_cast<const uint4*>(y + v * C + 8 * g);
+        uint4 dv = *pd;
+        uint32_t dw[4] = {dv.x, dv.y, dv.z, dv.w};
+        const uint32_t yw[4] = {yv.x, yv.y, yv.z, yv.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            uint32_t out = 0;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                uint16_t d = (uint16_t)(dw[q] >> (16 * h));
+                const uint16_t yy = (uint16_t)(yw[q] >> (16 * h));
+                if (!(bf2f(yy) > 0.f)) d = f2bf(kLeak * bf2f(d));
+                acc[2 * q + h] += bf2f(d);
+                out |= (uint32_t)d << (16 * h);
+            }
+            dw[q] = out;
+        }
+        *pd = make_uint4(dw[0], dw[1], dw[2], dw[3]);
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) part[threadIdx.x * 8 + k] = acc[k];
     __syncthreads();
-    if (threadIdx.x < C) {
+    if ((int)threadIdx.x < C) {
+        const int cg = threadIdx.x / 8, k = threadIdx.x % 8;
         float t = 0.f;
-        for (int j = 0; j < lanes_per_c; ++j) t += part[j * C + threadIdx.x];
+        for (int j = 0; j < lanes_per_g; ++j) t += part[(j * G + cg) * 8 + k];
         atomicAdd(&db[threadIdx.x], t);
     }
 }
@@ -866,16 +884,13 @@ hipError_t nn_conv3d_wgrad(const uint16_t* in, const uint16_t* dout, float* dw, 
     return hipGetLastError();
 }
 
-hipError_t nn_relu_bwd(uint16_t* dy, const uint16_t* y, size_t n, hipStream_t s)
-{
-    hipLaunchKernelGGL(relu_bwd_kernel, dim3(grid_for(n)), dim3(256), 0, s, dy, y, n);
-    return hipGetLastError();
-}
 
-hipError_t nn_bias_grad(const uint16_t* dy, float* db, size_t nvox, int C, hipStream_t s)
+hipError_t nn_relu_bias_bwd(uint16_t* dy, const uint16_t* y, float* db, size_t nvox, int C, hipStream_t s)
 {
-    if (C < 1 || C > 256) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(bias_grad_kernel, dim3(grid_for(nvox, 256, 512)), dim3(256), 0, s, dy, db, nvox, C);
+    if (C < 8 || C > 256 || C % 8 || 256 % (C / 8)) return hipErrorInvalidValue;
+    // a few hundred workgroups: each adds C partial sums to the same C addresses
+    hipLaunchKernelGGL(relu_bias_bwd_kernel, dim3(grid_for(nvox, 256 / (C / 8), 512)), dim3(256), 0, s, dy, y, db,
+                       nvox, C);
     return hipGetLastError();
 }
 
