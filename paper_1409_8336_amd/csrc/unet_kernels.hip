@@ -493,19 +493,34 @@ __global__ void pool_fwd_kernel(const uint16_t* __restrict__ in, uint16_t* __res
 __global__ void pool_bwd_kernel(const uint16_t* __restrict__ dout, const uint16_t* __restrict__ add,
                                 uint16_t* __restrict__ din, int N, int D, int H, int W, int C)
 {
-    const size_t total = (size_t)N * D * H * W * C;
+    // 8 channels (16 bytes) per lane; C a multiple of 8
+    const int C8 = C >> 3;
+    const size_t total = (size_t)N * D * H * W * C8;
     const int Ho = H / 2, Wo = W / 2, Do = D / 2;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
-        const int c = (int)(i % C);
-        size_t r = i / C;
+        const int c8 = (int)(i % C8);
+        size_t r = i / C8;
         const int x = (int)(r % W); r /= W;
         const int y = (int)(r % H); r /= H;
         const int z = (int)(r % D);
         const int n = (int)(r / D);
-        const size_t p = ((((size_t)n * Do + z / 2) * Ho + y / 2) * Wo + x / 2) * C + c;
-        float v = 0.125f * bf2f(dout[p]);
-        if (add) v += bf2f(add[i]);
-        din[i] = f2bf(v);
+        const size_t p = ((((size_t)n * Do + z / 2) * Ho + y / 2) * Wo + x / 2) * C + 8 * c8;
+        const uint4 dv = *reinterpret_cast<const uint4*>(dout + p);
+        const uint4 av = add ? *reinterpret_cast<const uint4*>(add + 8 * i) : make_uint4(0u, 0u, 0u, 0u);
+        const uint32_t dw[4] = {dv.x, dv.y, dv.z, dv.w}, aw[4] = {av.x, av.y, av.z, av.w};
+        uint32_t ow[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            uint32_t o = 0;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                float v = 0.125f * bf2f((uint16_t)(dw[q] >> (16 * h)));
+                if (add) v += bf2f((uint16_t)(aw[q] >> (16 * h)));
+                o |= (uint32_t)f2bf(v) << (16 * h);
+            }
+            ow[q] = o;
+        }
+        *reinterpret_cast<uint4*>(din + 8 * i) = make_uint4(ow[0], ow[1], ow[2], ow[3]);
     }
 }
 
@@ -543,22 +558,31 @@ __global__ void up_concat_kernel(const uint16_t* __restrict__ coarse, const uint
 __global__ void up_concat_bwd_coarse_kernel(const uint16_t* __restrict__ dcat, uint16_t* __restrict__ dcoarse,
                                             int N, int D, int H, int W, int Cc, int Cs)
 {
-    const int C = Cc + Cs;
+    // 8 channels (16 bytes) per lane; Cc and Cs multiples of 8
+    const int C = Cc + Cs, Cc8 = Cc >> 3;
     const int Do = D / 2, Ho = H / 2, Wo = W / 2;
-    const size_t total = (size_t)N * Do * Ho * Wo * Cc;
+    const size_t total = (size_t)N * Do * Ho * Wo * Cc8;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
-        const int c = (int)(i % Cc);
-        size_t r = i / Cc;
+        const int c8 = (int)(i % Cc8);
+        size_t r = i / Cc8;
         const int x = (int)(r % Wo); r /= Wo;
         const int y = (int)(r % Ho); r /= Ho;
         const int z = (int)(r % Do);
         const int n = (int)(r / Do);
-        float s = 0.f;
+        float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         for (int dz = 0; dz < 2; ++dz)
             for (int dy = 0; dy < 2; ++dy)
-                for (int dx = 0; dx < 2; ++dx)
-                    s += bf2f(dcat[((((size_t)n * D + 2 * z + dz) * H + 2 * y + dy) * W + 2 * x + dx) * C + c]);
-        dcoarse[i] = f2bf(s);
+                for (int dx = 0; dx < 2; ++dx) {
+                    const uint4 v = *reinterpret_cast<const uint4*>(
+                        dcat + ((((size_t)n * D + 2 * z + dz) * H + 2 * y + dy) * W + 2 * x + dx) * C + 8 * c8);
+                    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) acc[k] += bf2f((uint16_t)(w[k >> 1] >> (16 * (k & 1))));
+                }
+        uint32_t o[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) o[q] = (uint32_t)f2bf(acc[2 * q]) | ((uint32_t)f2bf(acc[2 * q + 1]) << 16);
+        *reinterpret_cast<uint4*>(dcoarse + 8 * i) = make_uint4(o[0], o[1], o[2], o[3]);
     }
 }
 
@@ -903,7 +927,9 @@ hipError_t nn_pool_fwd(const uint16_t* in, uint16_t* out, int N, int D, int H, i
 hipError_t nn_pool_bwd(const uint16_t* dout, const uint16_t* add, uint16_t* din, int N, int D, int H, int W, int C,
                        hipStream_t s)
 {
-    hipLaunchKernelGGL(pool_bwd_kernel, dim3(grid_for((size_t)N * D * H * W * C)), dim3(256), 0, s, dout, add, din, N, D, H, W, C);
+    if (C % 8) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(pool_bwd_kernel, dim3(grid_for((size_t)N * D * H * W * (C / 8))), dim3(256), 0, s, dout, add,
+                       din, N, D, H, W, C);
     return hipGetLastError();
 }
 
@@ -920,8 +946,8 @@ hipError_t nn_up_concat_bwd(const uint16_t* dcat, uint16_t* dcoarse, uint16_t* d
                             int Cc, int Cs, hipStream_t s)
 {
     if ((Cc | Cs) & 7) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(up_concat_bwd_coarse_kernel, dim3(grid_for((size_t)N * D * H * W * Cc / 8)), dim3(256), 0, s, dcat,
-                       dcoarse, N, D, H, W, Cc, Cs);
+    hipLaunchKernelGGL(up_concat_bwd_coarse_kernel, dim3(grid_for((size_t)N * (D / 2) * (H / 2) * (W / 2) * (Cc / 8))),
+                       dim3(256), 0, s, dcat, dcoarse, N, D, H, W, Cc, Cs);
     hipLaunchKernelGGL(up_concat_bwd_skip_kernel, dim3(grid_for((size_t)N * D * H * W * Cs / 8)), dim3(256), 0, s, dcat,
                        dskip, (size_t)N * D * H * W, Cc, Cs);
     return hipGetLastError();
