@@ -471,21 +471,32 @@ __global__ void __launch_bounds__(256) relu_bias_bwd_kernel(uint16_t* __restrict
 __global__ void pool_fwd_kernel(const uint16_t* __restrict__ in, uint16_t* __restrict__ out, int N, int D,
                                 int H, int W, int C)
 {
-    const int Do = D / 2, Ho = H / 2, Wo = W / 2;
-    const size_t total = (size_t)N * Do * Ho * Wo * C;
+    // 8 channels (16 bytes) per lane; C a multiple of 8; the eight children
+    // summed in the same order as element by element
+    const int Do = D / 2, Ho = H / 2, Wo = W / 2, C8 = C >> 3;
+    const size_t total = (size_t)N * Do * Ho * Wo * C8;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
-        const int c = (int)(i % C);
-        size_t r = i / C;
+        const int c8 = (int)(i % C8);
+        size_t r = i / C8;
         const int x = (int)(r % Wo); r /= Wo;
         const int y = (int)(r % Ho); r /= Ho;
         const int z = (int)(r % Do);
         const int n = (int)(r / Do);
-        float s = 0.f;
+        float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         for (int dz = 0; dz < 2; ++dz)
             for (int dy = 0; dy < 2; ++dy)
-                for (int dx = 0; dx < 2; ++dx)
-                    s += bf2f(in[((((size_t)n * D + 2 * z + dz) * H + 2 * y + dy) * W + 2 * x + dx) * C + c]);
-        out[i] = f2bf(0.125f * s);
+                for (int dx = 0; dx < 2; ++dx) {
+                    const uint4 v = *reinterpret_cast<const uint4*>(
+                        in + ((((size_t)n * D + 2 * z + dz) * H + 2 * y + dy) * W + 2 * x + dx) * C + 8 * c8);
+                    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) acc[k] += bf2f((uint16_t)(w[k >> 1] >> (16 * (k & 1))));
+                }
+        uint32_t o[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            o[q] = (uint32_t)f2bf(0.125f * acc[2 * q]) | ((uint32_t)f2bf(0.125f * acc[2 * q + 1]) << 16);
+        *reinterpret_cast<uint4*>(out + 8 * i) = make_uint4(o[0], o[1], o[2], o[3]);
     }
 }
 
@@ -920,7 +931,9 @@ hipError_t nn_relu_bias_bwd(uint16_t* dy, const uint16_t* y, float* db, size_t n
 
 hipError_t nn_pool_fwd(const uint16_t* in, uint16_t* out, int N, int D, int H, int W, int C, hipStream_t s)
 {
-    hipLaunchKernelGGL(pool_fwd_kernel, dim3(grid_for((size_t)N * D * H * W * C / 8)), dim3(256), 0, s, in, out, N, D, H, W, C);
+    if (C % 8) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(pool_fwd_kernel, dim3(grid_for((size_t)N * (D / 2) * (H / 2) * (W / 2) * (C / 8))), dim3(256), 0,
+                       s, in, out, N, D, H, W, C);
     return hipGetLastError();
 }
 
