@@ -278,7 +278,7 @@ def main():
     if args.copy_probe:
         return copy_probe()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs on a single MI355X and has no "
+        print("bench.py measures one GPU: the engine runs on a single MI355X and has no "
               "multi-GPU path (--gpus %d requested)" % args.gpus, file=sys.stderr)
         return 2
     import torch

@@ -2,7 +2,7 @@
 oracle on the same seeded inputs (arXiv:1409.8336 Sec. II.A transport,
 Sec. II.B.2 statistics).
 
-Tolerances (the acceptance bar of this build):
+Tolerances (the acceptance bar):
   integrated depth-dose within 1% of its maximum, R80 within 0.2 mm,
   voxels above 10% of the maximum dose consistent within 3 sigma of the two
   10-group variance estimates, energy-ledger residual below 1e-5.
