@@ -32,8 +32,8 @@ HBM_PEAK = 8.0e12
 # HBM bytes per transport launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
 # scaled by a plain-copy calibration, valid only for the kernel source whose
 # sha256 is recorded (see profiles/); None once the kernel has changed.
-TRAFFIC = {"transport_sha256": "c4825828bd6e38044237f5ba716d22866d53f1f16b2c8225ba3b4ec442c8aa65",
-           "bytes_per_launch": 6.2121e9, "let_bytes_per_launch": 1.29667e10}
+TRAFFIC = {"transport_sha256": "00e279ca51a38dab47f5f00a83e51605defd374927561f0c7adfb045afcd305e",
+           "bytes_per_launch": 6.1906e9, "let_bytes_per_launch": 1.29461e10}
 
 
 def _kernel_sha():

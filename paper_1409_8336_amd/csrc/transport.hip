@@ -1270,8 +1270,13 @@ hipError_t launch_atomic_probe(double* tally, int nx, int ny, int nz, int K, int
 // A block takes kStatsVox consecutive voxels at a time: their [voxel][K]
 // tally rows form one contiguous run, read with 16-byte unit-stride loads
 // into LDS rows padded to an odd number of doubles (fewer bank conflicts),
-// then each lane reduces its voxel's K groups from LDS.
+// then each lane reduces its voxel's K groups from LDS.  With kPre (K <= 16:
+// a run is at most kStatsPre 16-byte loads per lane) the next run's loads are
+// issued into registers before the current run is reduced, so that they are
+// in flight during the reduction.
 constexpr int kStatsVox = 128;
+constexpr int kStatsPre = 8;
+template <bool kPre>
 __global__ void __launch_bounds__(kStatsVox) stats_kernel(const double* __restrict__ tally,
                                                           const uint2* __restrict__ vox,
                                                           unsigned long long nvox, int K, uint32_t k_magic,
@@ -1283,9 +1288,34 @@ __global__ void __launch_bounds__(kStatsVox) stats_kernel(const double* __restri
 {
     extern __shared__ double rows[];   // kStatsVox * (K | 1)
     const int pitch = K | 1;
+    const unsigned long long stride = (unsigned long long)gridDim.x * kStatsVox;
     double part = 0.0;
-    for (unsigned long long v0 = blockIdx.x * (unsigned long long)kStatsVox; v0 < nvox;
-         v0 += (unsigned long long)gridDim.x * kStatsVox) {
+    // element e of a run lies in row e / K, computed as a high product with
+    // k_magic = ceil(2^32 / K) (exact for e < 2^32 / K^2, here e < 8192)
+    auto put = [&](int i, const double2& q) {
+        const uint32_t e0 = 2u * (uint32_t)i, e1 = e0 + 1u;
+        const uint32_t r0 = __umulhi(e0, k_magic), r1 = __umulhi(e1, k_magic);
+        rows[r0 * pitch + (e0 - r0 * K)] = q.x;
+        rows[r1 * pitch + (e1 - r1 * K)] = q.y;
+    };
+    // pairs of doubles of the run that starts at voxel w (16-byte aligned:
+    // it starts at w * K doubles, w a multiple of kStatsVox)
+    auto pairs = [&](unsigned long long w) {
+        const unsigned long long left = nvox - w;
+        return ((left < (unsigned long long)kStatsVox ? (int)left : kStatsVox) * K) >> 1;
+    };
+    double2 pre[kPre ? kStatsPre : 1];
+    if (kPre && blockIdx.x * (unsigned long long)kStatsVox < nvox) {
+        const unsigned long long w = blockIdx.x * (unsigned long long)kStatsVox;
+        const double2* src2 = reinterpret_cast<const double2*>(tally + w * K);
+        const int np = pairs(w);
+#pragma unroll
+        for (int j = 0; j < (kPre ? kStatsPre : 1); ++j) {
+            const int i = (int)threadIdx.x + j * kStatsVox;
+            if (i < np) pre[j] = src2[i];
+        }
+    }
+    for (unsigned long long v0 = blockIdx.x * (unsigned long long)kStatsVox; v0 < nvox; v0 += stride) {
         const unsigned long long left = nvox - v0;
         const int nv = left < (unsigned long long)kStatsVox ? (int)left : kStatsVox;
         const int n = nv * K;                      // doubles in this run
@@ -1293,19 +1323,29 @@ __global__ void __launch_bounds__(kStatsVox) stats_kernel(const double* __restri
         const unsigned long long v = v0 + threadIdx.x;
         const float rho = (int)threadIdx.x < nv ? __uint_as_float(vox[v].x) : 1.f;
         __syncthreads();
-        // the run starts at v0 * K doubles, a multiple of 2: 16-byte aligned.
-        // Element e lies in row e / K, computed as a high product with
-        // k_magic = ceil(2^32 / K) (exact for e < 2^32 / K^2, here e < 8192)
-        const double2* src2 = reinterpret_cast<const double2*>(tally + v0 * K);
-        for (int i = threadIdx.x; i < (n >> 1); i += kStatsVox) {
-            const double2 q = src2[i];
-            const uint32_t e0 = 2u * (uint32_t)i, e1 = e0 + 1u;
-            const uint32_t r0 = __umulhi(e0, k_magic), r1 = __umulhi(e1, k_magic);
-            rows[r0 * pitch + (e0 - r0 * K)] = q.x;
-            rows[r1 * pitch + (e1 - r1 * K)] = q.y;
+        if (kPre) {
+#pragma unroll
+            for (int j = 0; j < (kPre ? kStatsPre : 1); ++j) {
+                const int i = (int)threadIdx.x + j * kStatsVox;
+                if (i < (n >> 1)) put(i, pre[j]);
+            }
+        } else {
+            const double2* src2 = reinterpret_cast<const double2*>(tally + v0 * K);
+            for (int i = threadIdx.x; i < (n >> 1); i += kStatsVox) put(i, src2[i]);
         }
         if ((n & 1) && threadIdx.x == 0) rows[((n - 1) / K) * pitch + (n - 1) % K] = tally[v0 * K + n - 1];
         __syncthreads();
+        if (kPre && v0 + stride < nvox) {
+            // the next run's loads, in flight while this run is reduced
+            const unsigned long long w = v0 + stride;
+            const double2* src2 = reinterpret_cast<const double2*>(tally + w * K);
+            const int np = pairs(w);
+#pragma unroll
+            for (int j = 0; j < (kPre ? kStatsPre : 1); ++j) {
+                const int i = (int)threadIdx.x + j * kStatsVox;
+                if (i < np) pre[j] = src2[i];
+            }
+        }
         if ((int)threadIdx.x >= nv) continue;
         const double* t = rows + threadIdx.x * pitch;
         double tot = 0.0;
@@ -1417,20 +1457,33 @@ hipError_t launch_stats(const double* tally, const uint2* vox, unsigned long lon
 {
     if (K < 2 || K > 64) return hipErrorInvalidValue;
     const size_t bytes = (size_t)kStatsVox * (K | 1) * sizeof(double);
+    // registers hold a whole run when it is at most kStatsPre loads per lane
+    const bool pre = (size_t)kStatsVox * K / 2 <= (size_t)kStatsPre * kStatsVox;
     if (bytes > 65536) {
-        const hipError_t e = hipFuncSetAttribute((const void*)stats_kernel,
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-        if (e != hipSuccess) return e;
+        const hipError_t ea = hipFuncSetAttribute(pre ? (const void*)stats_kernel<true> : (const void*)stats_kernel<false>,
+                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (ea != hipSuccess) return ea;
     }
-    // enough workgroups to fill the chip several times over, each looping over
-    // runs of voxels (fewer workgroups, fewer atomics on the deposited sum)
+    // as many workgroups as are resident at once (a second, partial wave of
+    // workgroups would run after the first), each looping over runs of voxels
+    const void* kfn = pre ? (const void*)stats_kernel<true> : (const void*)stats_kernel<false>;
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, kStatsVox, bytes);
+    if (e != hipSuccess) return e;
+    const unsigned long long resident = (unsigned long long)std::max(1, cus) * (unsigned long long)std::max(1, per_cu);
     unsigned long long blocks = (nvox + kStatsVox - 1) / kStatsVox;
-    if (blocks > 4096) blocks = 4096;
+    if (blocks > resident) blocks = resident;
     if (blocks == 0) blocks = 1;
     const uint32_t k_magic = (uint32_t)((0x100000000ull + (unsigned)K - 1) / (unsigned)K);
-    hipLaunchKernelGGL(stats_kernel, dim3((unsigned)blocks), dim3(kStatsVox), bytes, s, tally, vox, nvox, K,
-                       k_magic, 1.0 / K, (double)K / (K - 1), conv0, dose, var, dep_sum,
-                       let ? tally + nvox * (unsigned long long)K : nullptr, let);
+    const double* let_nd = let ? tally + nvox * (unsigned long long)K : nullptr;
+    if (pre)
+        hipLaunchKernelGGL(stats_kernel<true>, dim3((unsigned)blocks), dim3(kStatsVox), bytes, s, tally, vox, nvox, K,
+                           k_magic, 1.0 / K, (double)K / (K - 1), conv0, dose, var, dep_sum, let_nd, let);
+    else
+        hipLaunchKernelGGL(stats_kernel<false>, dim3((unsigned)blocks), dim3(kStatsVox), bytes, s, tally, vox, nvox, K,
+                           k_magic, 1.0 / K, (double)K / (K - 1), conv0, dose, var, dep_sum, let_nd, let);
     return hipGetLastError();
 }
 
