@@ -18,6 +18,7 @@ SRC = os.path.join(HERE, "pmc_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 NO_STRAGGLE, NO_MCS, NO_NUCLEAR, VAVILOV, MOLIERE = 1, 2, 4, 8, 16
+PLAIN_HINGE = 32   # test only: no landing of the second hinge segment on the face
 MOL_SHAPE = (13, 161)     # [1/B = 1/20 + j (2/9 - 1/20)/12][q = k/8]
 VAV_SHAPE = (5, 31, 97)   # [beta^2 = k/10][log10 kappa = -2 + j/10][z = -6 + i/8]
 _lock = threading.Lock()

@@ -20,8 +20,15 @@
  *   CSDA range / inverse ..... pinned (independent scipy quadrature)
  *   Eq. 1/2 scaling .......... pinned (deterministic stopping depths)
  *   radiation lengths ........ pinned (published X0 values)
- *   Highland MCS + hinge ..... pinned (thin-slab exit-angle width)
- *   straggling ............... pinned (Bohr variance of one step)
+ *   Highland MCS ............. pinned (hand-evaluated worked value; thin-slab
+ *                              exit-angle width; Moliere core within 11%)
+ *   random hinge ............. pinned (thin-slab exit displacement: the
+ *                              thin-layer moments <x^2> = s^2<theta^2>/3,
+ *                              <x theta> = s<theta^2>/2; face landing against
+ *                              the plain hinge)
+ *   source lateral profile ... pinned (per-axis SD = the spot's sigma_x,
+ *                              sigma_y on an anisotropic grid; KS normality)
+ *   straggling ............... pinned (Bohr variance of one step; worked value)
  *   attenuation .............. pinned (exp(-n sigma L), constant sigma)
  *   elastic (Eq. 3) .......... pinned (KS against the integrated Eq. 3, and
  *                              four-momentum conservation)
@@ -1409,7 +1416,7 @@ static void transport(const ora_ctx* c, const orun* r, opart* q, ostack* st, oac
         double rest = (1.0 - u[0]) * s;
         int on_face = 0;
         const double face = (d_axis_before > 0.0) ? (double)(v[axis] + 1) : (double)v[axis];
-        if (lim == LIM_BND && q->d[axis] * d_axis_before > 0.0) {
+        if (lim == LIM_BND && !(flags & ORA_PLAIN_HINGE) && q->d[axis] * d_axis_before > 0.0) {
             const double l2 = (face - q->p[axis]) * c->vs[axis] / q->d[axis];
             if (l2 >= 0.0 && l2 <= 2.0 * rest) {
                 rest = l2;

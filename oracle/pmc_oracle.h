@@ -35,7 +35,11 @@ extern "C" {
 /* ORA_VAVILOV: Vavilov-Gaussian straggling instead of Gaussian (Sec. II.A.2) */
 /* ORA_MOLIERE: Molière multiple scattering instead of the scaled Highland
    Gaussian where B >= 4.5 (Sec. II.A.2) */
-enum { ORA_NO_STRAGGLE = 1, ORA_NO_MCS = 2, ORA_NO_NUCLEAR = 4, ORA_VAVILOV = 8, ORA_MOLIERE = 16 };
+/* ORA_PLAIN_HINGE (test only): the second hinge segment always keeps its
+   nominal length (1 - u) s, without the landing on the crossed face plane;
+   used to measure what that landing changes */
+enum { ORA_NO_STRAGGLE = 1, ORA_NO_MCS = 2, ORA_NO_NUCLEAR = 4, ORA_VAVILOV = 8, ORA_MOLIERE = 16,
+       ORA_PLAIN_HINGE = 32 };
 
 /* Molière sampling table: [1/B = 1/20 + j (2/9 - 1/20)/12, j < 13][q = k/8, k < 161]
    of ln(v^2 / q), v the reduced angle, q = -ln u */

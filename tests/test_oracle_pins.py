@@ -298,6 +298,142 @@ def test_thin_slab_highland_width():
     assert abs(math.sqrt(np.mean(ang_y ** 2)) / rms - 1) < 0.02
 
 
+def test_highland_and_bohr_worked_values(lib, water_za):
+    """The oracle's two width formulas against hand-evaluated worked values
+    of the published formulas (tests/golden/highland_bohr_worked_values.txt)."""
+    g = {r[0]: float(r[1]) for r in _golden("highland_bohr_worked_values.txt")}
+    th1 = lib.oracle_highland_theta0(100.0, 0.2, 36.08, 1.0)
+    th107 = lib.oracle_highland_theta0(100.0, 0.2, 36.08, 1.07)
+    assert abs(th1 * 1e3 / g["theta0_mrad_f1"] - 1) < 2e-5, th1
+    assert abs(th107 * 1e3 / g["theta0_mrad_f107"] - 1) < 2e-5, th107
+    var = lib.oracle_straggling_variance(100.0, 0.2, 1.0, water_za)
+    ref = g["bohr_sigma_mev"] ** 2 * g["bohr_relativistic_factor"]
+    assert abs(var / ref - 1) < 1e-4, (var, ref)
+
+
+def _ratio_se(a, b):
+    """mean(a)/mean(b) and its standard error (delta method)."""
+    r = a.mean() / b.mean()
+    return r, float(np.std(a - r * b, ddof=1) / (math.sqrt(len(a)) * abs(b.mean())))
+
+
+def test_hinge_exit_displacement_matches_thin_layer_moments():
+    """Random hinge (Sec. II.A.3), one step through a thin slab: a deflection
+    at a uniform fraction u of the step leaves the lateral displacement
+    x = (1 - u) s tan(theta_x), so <x^2> = s^2 <theta_x^2> / 3 and
+    <x theta_x> = s <theta_x^2> / 2 -- the thin-layer moments of continuous
+    multiple scattering (Fermi-Eyges A2 and A1 over A0).  With the Highland
+    width, the RMS displacement is theta0 s / sqrt(3)."""
+    n = 100000
+    o, esc = _slab_run(O.NO_STRAGGLE | O.NO_NUCLEAR, n)
+    s = 0.2
+    assert np.allclose(esc[:, 2], s)        # one step, ending on the exit face
+    for axis in (0, 1):
+        x = esc[:, axis] - 100.0
+        tx = esc[:, 3 + axis] / esc[:, 5]
+        r2, se2 = _ratio_se(x * x, s * s * tx * tx / 3.0)
+        assert abs(r2 - 1) < 4 * se2 + 1e-3, (axis, r2, se2)
+        r1, se1 = _ratio_se(x * tx, s * tx * tx / 2.0)
+        assert abs(r1 - 1) < 4 * se1 + 1e-3, (axis, r1, se1)
+    # absolute width: theta0 of the step's mid energy, PDG water X0
+    e0 = 100.0
+    e1 = o.energy_at_range(o.range(e0) - s)
+    emid = e0 - 0.5 * (e0 - e1)
+    pv = emid * (emid + 2 * 938.272088) / (emid + 938.272088)
+    b2 = emid * (emid + 2 * 938.272088) / (emid + 938.272088) ** 2
+    x0 = 36.08
+    theta0 = 1.07 * 13.6 / pv * math.sqrt(s / x0) * (1 + 0.038 * math.log(s / (x0 * b2)))
+    x = esc[:, 0] - 100.0
+    rms = math.sqrt(np.mean(x * x))
+    # E[x^4] / E[x^2]^2 = 5.4 for x = (1 - u) N(0, 1): SE of the RMS sqrt(4.4 / n) / 2
+    se = 0.5 * math.sqrt(4.4 / n)
+    assert abs(rms / (theta0 * s / math.sqrt(3)) - 1) < 4 * se + 0.002, (rms, theta0 * s / math.sqrt(3))
+
+
+def test_source_lateral_profile_matches_spot_sigmas():
+    """Source (Gaussian spots on the entrance face, standing in for the phase
+    space of Sec. II.A.6): with scattering, straggling and nuclear events off
+    every proton leaves the back face where it entered, so the exit positions
+    show the source's lateral profile -- per-axis normal with the spot's own
+    sigma_x and sigma_y (in cm, on a grid with unequal voxel sizes), centred on
+    the spot, uncorrelated."""
+    hu = synth.water_phantom(60, 48, 2)
+    o = _oracle(flags=O.NO_MCS | O.NO_STRAGGLE | O.NO_NUCLEAR, hu=hu, voxel=(0.3, 0.25, 0.2))
+    n = 40000
+    xs, ys, sx, sy = 9.0, 6.0, 0.3, 0.6
+    spot = np.array([[xs, ys, 100.0, sx, sy, 1.0]], np.float32)
+    esc = o.run_spots(spot, n, 11, escape_cap=n)["escapes"]
+    assert len(esc) == n
+    assert np.allclose(esc[:, 2], 0.4) and np.all(esc[:, 5] == 1.0)
+    x, y = esc[:, 0] - xs, esc[:, 1] - ys
+    for v, sig in ((x, sx), (y, sy)):
+        assert abs(v.mean()) < 4 * sig / math.sqrt(n)
+        assert abs(v.std(ddof=1) / sig - 1) < 4 / math.sqrt(2 * n), (v.std(ddof=1), sig)
+        assert stats.kstest(v / sig, "norm").pvalue > 1e-3
+    assert abs(np.corrcoef(x, y)[0, 1]) < 4 / math.sqrt(n)
+    # a pencil of zero width enters exactly at the spot position
+    z0 = o.run_spots(np.array([[xs, ys, 100.0, 0.0, 0.0, 1.0]], np.float32), 100, 11,
+                     escape_cap=100)["escapes"]
+    assert np.allclose(z0[:, 0], xs, atol=1e-9) and np.allclose(z0[:, 1], ys, atol=1e-9)
+
+
+def _hinge_ab(hu, spot, n, flags, seed=1):
+    """IDD, R80 and central lateral RMS per slice of the oracle with the face
+    landing of the second hinge segment (the default reading) and without it."""
+    from tests import parity_tools as PT
+    res = {}
+    rho = PT.density_grid(hu)
+    for name, fl in (("landing", flags), ("plain", flags | O.PLAIN_HINGE)):
+        o = _oracle(flags=fl, hu=hu)
+        out = o.run_spots(spot, n, seed)
+        s = out["summary"]
+        e = PT.energy_grid(out["dose"], rho, (0.2, 0.2, 0.2), s["total_weight"])
+        ez = PT.idd(e)
+        nz, ny, nx = hu.shape
+        xc = (np.arange(nx) + 0.5) * 0.2
+        core = np.abs(xc - float(spot[0, 0])) < 2.0        # the beam core, without the halo
+        ex = e.sum(axis=1)[:, core]                        # [z][x]
+        w = np.maximum(ex.sum(axis=1), 1e-300)
+        mx = (ex * xc[core]).sum(axis=1) / w
+        rms = np.sqrt(np.maximum((ex * xc[core] ** 2).sum(axis=1) / w - mx ** 2, 0))
+        res[name] = dict(idd=ez, r80=PT.r80(ez, 0.2), rms=rms, steps=s["steps"] / s["histories"],
+                         short=s["n_short_steps"] / s["histories"])
+    return res
+
+
+@pytest.mark.parametrize("case", ["water100", "ct150"])
+def test_face_landing_of_the_hinge_changes_no_dose_measure(case):
+    """Random hinge (Sec. II.A.3) on boundary steps.  The reading that lands
+    the second segment on the crossed face (it may stretch up to twice its
+    nominal length, or shrink, without a change of the step's energy loss)
+    against the plain hinge, whose proton ends up to a micrometre short of
+    the face and then takes a minimum-length step.  With straggling off the
+    two are the same transport up to that geometry: IDD within 1% of its
+    maximum, R80 within 0.05 mm, beam-core lateral RMS within 0.5% on average
+    (4% per slice) where the IDD is above 10% of its maximum.  With straggling on the landing removes
+    nearly all minimum-length steps (the plain hinge takes 0.5 of them per
+    regular step; their Gaussian loss, whose width far exceeds its mean at
+    1 um, is clamped at zero and shortens the range)."""
+    if case == "water100":
+        hu = synth.water_phantom(64, 64, 128)
+        spot = synth.pencil_spot(6.4, 6.4, 100.0, 0.3)
+        n = 60000
+    else:
+        hu = synth.ct_phantom()
+        spot = synth.pencil_spot(12.8, 12.8, 150.0, 0.3)
+        n = 20000
+    r = _hinge_ab(hu, spot, n, O.NO_STRAGGLE)
+    a, b = r["landing"], r["plain"]
+    assert np.max(np.abs(a["idd"] - b["idd"])) < 0.01 * b["idd"].max()
+    assert abs(a["r80"] - b["r80"]) < 0.005, (a["r80"], b["r80"])
+    sel = b["idd"] > 0.1 * b["idd"].max()
+    ratio = a["rms"][sel] / b["rms"][sel]
+    assert abs(ratio.mean() - 1) < 0.005 and np.max(np.abs(ratio - 1)) < 0.04, ratio
+    assert a["short"] < 0.002 * a["steps"] and b["short"] > 0.3 * (b["steps"] - b["short"])
+    f = _hinge_ab(hu, spot, n // 4, 0)
+    assert f["landing"]["short"] < 0.01 * f["plain"]["short"]
+
+
 def test_rotation_preserves_norm_and_angle():
     rng = np.random.default_rng(5)
     for _ in range(200):
