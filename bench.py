@@ -42,12 +42,28 @@ def _kernel_sha():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def cpu_baseline(cfg, target_s=18.0):
+def _cpu_model():
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return None
+
+
+def cpu_baseline(cfg, target_s=15.0, single_s=8.0):
+    """The FP64 oracle on this host: all threads (OpenMP over histories) on a
+    sample sized for about target_s, then one thread on a sample sized for
+    about single_s; the same field, CT and seeds."""
     from oracle import oracle as O
     from paper_1409_8336_amd import synth
+    nd, mt = synth.nuclear_data(), synth.material_table()
     o = O.Oracle()
-    o.load_physics(synth.nuclear_data())
-    o.load_geometry(cfg["hu"], cfg["voxel_cm"], synth.material_table())
+    o.load_physics(nd)
+    o.load_geometry(cfg["hu"], cfg["voxel_cm"], mt)
     # a probe long enough that thread start-up does not dominate its rate
     probe = 100_000
     r = o.run_spots(cfg["spots"], probe, 2)
@@ -56,24 +72,36 @@ def cpu_baseline(cfg, target_s=18.0):
     r = o.run_spots(cfg["spots"], n, 3)
     s = r["summary"]
     o.close()
+    o1 = O.Oracle(n_threads=1)
+    o1.load_physics(nd)
+    o1.load_geometry(cfg["hu"], cfg["voxel_cm"], mt)
+    rate1 = (n / s["wall_s"]) / max(int(s["threads"]), 1)
+    n1 = int(max(2_000, rate1 * single_s))
+    r1 = o1.run_spots(cfg["spots"], n1, 4)
+    s1 = r1["summary"]
+    o1.close()
     return {"value": n / s["wall_s"], "unit": "histories/s", "cores": int(s["threads"]),
             "kind": "oracle",
             "sample": "%d histories of the same 2000-spot field on the same CT (weights-"
                       "proportional allocation), wall %.2f s, %.1f steps/history"
-                      % (n, s["wall_s"], s["steps"] / n)}
+                      % (n, s["wall_s"], s["steps"] / n),
+            "single_thread": {"value": n1 / s1["wall_s"], "unit": "histories/s", "cores": 1,
+                              "sample": "%d histories of the same field, wall %.2f s" % (n1, s1["wall_s"])},
+            "cpu_model": _cpu_model()}
 
 
 def copy_probe():
-    """A plain copy of known size (256 MiB read + 256 MiB written per launch):
-    the reference that scales FETCH_SIZE / WRITE_SIZE counter readings."""
-    import torch
-    x = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
-    y = torch.empty_like(x)
-    torch.cuda.synchronize()
-    for _ in range(3):
-        y.copy_(x)
-    torch.cuda.synchronize()
-    print(json.dumps({"copy_probe_bytes": x.numel() * 4, "launches": 3}))
+    """The library's plain read and plain copy kernels on 256 MiB (four
+    launches each): the copy, of known size (256 MiB read + 256 MiB written
+    per launch), is the reference that scales FETCH_SIZE / WRITE_SIZE
+    counter readings."""
+    from paper_1409_8336_amd import pmc
+    eng = pmc.Engine(0)
+    n = 256 * 1024 * 1024
+    read_ms, copy_ms = pmc.pmc_stream_probe(eng.ctx, n)
+    eng.close()
+    print(json.dumps({"copy_probe_bytes": n, "launches": 4, "kernel": "copy_kernel",
+                      "read_gbs": n / read_ms / 1e6, "copy_gbs": 2 * n / copy_ms / 1e6}))
     return 0
 
 
@@ -313,6 +341,15 @@ def main():
     transport_s = sum(s["transport_ms"] for s in sums) * 1e-3
     launches = sum(s["launches"] for s in sums)
     achieved = ALG_BYTES_PER_STEP * steps_tot / transport_s
+    # the transport's own address stream replayed without the physics, and
+    # the plain-read bandwidth of this device
+    rep = pmc.pmc_roofline_replay(eng.ctx, cfg["spots"], cfg["n_histories"], cfg["seed"], stream)
+    read_ms, _ = pmc.pmc_stream_probe(eng.ctx, 4 << 30, stream)
+    stream_read_gbs = (4 << 30) / read_ms / 1e6
+    t_tr = rep["trace_only_ms"]
+    t_gather = rep["gather_ms"] - t_tr
+    t_atom = min(rep["atomic_ms"], rep["cached_atomic_ms"]) - t_tr
+    t_mem = max(t_gather, t_atom)
     deposits_tot = sum(s["tally_atomics"] for s in sums)
     atomics_tot = sum(s["global_atomics"] for s in sums)
     flush_tot = sum(s["cache_flush_atomics"] for s in sums)
@@ -358,7 +395,29 @@ def main():
             "traffic": traffic,
             "kernel": "transport_kernel",
             "avg_launch_ms": 1e3 * transport_s / launches,
+            "launches_per_step": launches / args.steps,
             "bytes_per_step": ALG_BYTES_PER_STEP,
+            "stream_read_gbs": stream_read_gbs,
+            # the memory/atomic roofline of the transport's own address stream:
+            # every step's 8-B voxel gather and 8-B FP64 tally add replayed in
+            # the traced run's order, grid, workgroups, lanes and epochs
+            "replay": {
+                "frac": t_mem / rep["transport_ms"],
+                "binding": "tally atomics" if t_atom >= t_gather else "voxel gathers",
+                "frac_with_trace_stream": max(rep["gather_ms"], min(rep["atomic_ms"], rep["cached_atomic_ms"]))
+                                          / rep["transport_ms"],
+                "combined_frac": (rep["combined_ms"] - t_tr) / rep["transport_ms"],
+                "transport_ms": rep["transport_ms"],
+                "gather_ms": t_gather,
+                "atomic_ms": rep["atomic_ms"] - t_tr,
+                "cached_atomic_ms": rep["cached_atomic_ms"] - t_tr,
+                "combined_ms": rep["combined_ms"] - t_tr,
+                "trace_stream_ms": t_tr,
+                "steps_traced_frac": rep["steps_traced"] / rep["steps"],
+                "note": "replay times net of streaming the 4-byte-per-lane-iteration trace "
+                        "(trace_stream_ms); frac = max(gathers, faster of direct or cached "
+                        "atomics) / transport launch",
+            },
         },
         "atomic_roofline": {
             "deposits_per_step": deposits_tot / args.steps,

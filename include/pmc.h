@@ -170,8 +170,8 @@ typedef struct {
     double total_weight;   /* sum of primary weights (dose normalisation) */
     double device_ms;      /* device time of the run, HIP events */
     double transport_ms;   /* sum over transport launches of their HIP-event durations */
-    int32_t generations;   /* generations run: primaries, secondary generations, and the
-                              empty one that ends the run */
+    int32_t generations;   /* generations run: the primaries' and each secondary generation
+                              that had work (with the workgroup queues on, usually 1) */
     int32_t launches;      /* transport launches issued (generations are launched in groups;
                               launches past the empty generation exit at once) */
     uint64_t global_atomics; /* FP64 atomic adds that reached the tally in device memory
@@ -185,6 +185,9 @@ typedef struct {
                                      are deposits that found no cache slot) */
     int32_t refill_lanes;    /* launch shape used (continued): refill and event thresholds */
     int32_t batch_events;
+    double first_launch_ms;  /* HIP-event duration of the first transport launch (generation 0;
+                                with the workgroup queues on it holds the whole transport, the
+                                following launch only confirms that nothing overflowed) */
 } pmc_summary;
 
 typedef struct pmc_ctx pmc_ctx;
@@ -312,6 +315,52 @@ pmc_status pmc_inspect_tables(const pmc_ctx* c, float* out_lnr_water, float* out
  * PMC_ERR_DEVICE. */
 pmc_status pmc_atomic_probe(pmc_ctx* c, uint64_t n_atomics, void* hip_stream, double* ms_out);
 
+/* Roofline measurement of the transport on the loaded geometry (single
+ * plan, same spots, histories and seed as pmc_run_spots_dev).  The
+ * transport's memory work per condensed-history step is one voxel-record
+ * gather and one FP64 dose-tally add (Sec. II.A.3 steps, Sec. II.B.2
+ * tallies).  This call runs the workload once as a normal run (autotuned
+ * shape; transport_ms = its first transport launch), once more with an
+ * address trace (the same launch shape; every loop iteration each lane
+ * records the tally element its step deposited into), then replays that
+ * address stream with the same grid, workgroups, lanes and epochs and none
+ * of the physics: the trace alone, the gathers, the deposits as
+ * device-memory FP64 atomics, the deposits through the workgroup LDS cache
+ * as the transport issues them, and gathers plus cached deposits.  Each
+ * replay time includes streaming the trace (4 bytes per lane and
+ * iteration; trace_only_ms).  Deposits outside a step (nuclear events,
+ * terminations below the cut-off) are not traced: steps_traced of the
+ * run's deposits.  Results are written to the context's dose and variance
+ * buffers and discarded; the tally is left as the run made it (replays add
+ * zero).  Needs about 4 B x lanes x iterations of device memory (8 GB for
+ * the 1e7-history field), released on return.  Errors: PMC_ERR_ARG,
+ * PMC_ERR_RANGE, PMC_ERR_STATE, PMC_ERR_NOMEM, PMC_ERR_DEVICE. */
+typedef struct {
+    double transport_ms;      /* the untraced run's first transport launch */
+    double trace_only_ms;     /* replay streaming the trace only */
+    double gather_ms;         /* + every step's voxel-record gather (8 B) */
+    double atomic_ms;         /* + every step's deposit as a device-memory FP64 atomic */
+    double cached_atomic_ms;  /* + every step's deposit through the LDS cache, epoch flushes */
+    double combined_ms;       /* + gathers and cached deposits together */
+    uint64_t steps;           /* steps of the untraced run */
+    uint64_t steps_traced;    /* trace entries holding a step (generation 0) */
+    uint64_t deposits;        /* deposits of the untraced run (steps and local deposits) */
+    uint64_t trace_iters;     /* loop iterations recorded per lane */
+    int32_t grid_blocks, block_threads, cache_slots, epoch_steps;
+} pmc_replay_result;
+
+pmc_status pmc_roofline_replay(pmc_ctx* c, const pmc_spot* spots, int n_spots, uint64_t n_histories,
+                               uint64_t seed, void* hip_stream, pmc_replay_result* out);
+
+/* Memory-bandwidth references on hip_stream: a plain read of `bytes` of
+ * device memory (16-byte loads over a grid of 8 workgroups of 256 lanes per
+ * CU) and a plain copy of `bytes` to another buffer (`bytes` read and
+ * `bytes` written), each the best of three launches; the copy is the
+ * reference of known size for HBM byte counters.  Allocates 2 x bytes and
+ * frees them on return.  Errors: PMC_ERR_ARG (bytes < 1 MiB or not a
+ * multiple of 16, NULL outputs), PMC_ERR_NOMEM, PMC_ERR_DEVICE. */
+pmc_status pmc_stream_probe(pmc_ctx* c, uint64_t bytes, void* hip_stream, double* read_ms, double* copy_ms);
+
 /* Mass density (g/cm^3, float32) of every voxel of geometry geometry_id
  * (0 = pmc_load_geometry's) as the transport uses it (the HU calibration of
  * Sec. II.A.1), written to the device array d_rho ([nz][ny][nx]) on
@@ -336,6 +385,52 @@ pmc_status pmc_vavilov_table(float* out, int32_t n_floats);
  * range by the transport).  Built once per process.  Errors: PMC_ERR_ARG
  * (out NULL or n_floats < 2093). */
 pmc_status pmc_moliere_table(float* out, int32_t n_floats);
+
+/* Launch layout of the transport kernel, host only (no device work, usable
+ * without a GPU).  The run driver lays out and checks every launch with the
+ * same code: the workgroup's LDS (Sec. II.B.3 keeps the hot tables in fast
+ * on-chip memory; here the table blob, a batch's plan descriptors, the
+ * deposit cache's sums, keys and LET numerators, the control words, the
+ * staged arguments and a batch's per-plan ledgers and counters) and the
+ * sizes of the device buffers the kernel indexes (tally planes, generation
+ * and workgroup queues, claim counters, the primary work list). */
+typedef struct {
+    int32_t block_threads;      /* workgroup size, multiple of 64 in [64, 1024] */
+    int32_t grid_blocks;        /* workgroups of the launch; 0 = not yet known
+                                   (then the grid-dependent sizes stay 0) */
+    int32_t n_plans;            /* [1, 64]; 1 for a single-plan launch */
+    int32_t batched;            /* nonzero: the batched-plan kernel */
+    int32_t score_let;          /* nonzero: LET_d planes and numerators */
+    int32_t k_batches;          /* statistical groups, [2, 64] */
+    int32_t n_mat;              /* material bins, [1, 16] */
+    int32_t tally_cache;        /* as pmc_params.tally_cache: -1 off, 0 sized from the LDS left */
+    int32_t local_queue;        /* as pmc_params.local_queue */
+    int32_t n_spots;            /* all plans */
+    uint64_t queue_capacity;    /* as pmc_params.queue_capacity (0 = max(65536, N)) */
+    uint64_t n_histories;       /* all plans */
+    uint64_t max_plan_histories;
+    uint64_t max_nvox;          /* largest plan grid, voxels */
+} pmc_launch_query;
+
+typedef struct {
+    uint64_t lds_bytes;         /* dynamic LDS per workgroup */
+    /* LDS regions, 32-bit word offsets from the start of the allocation */
+    int32_t blob_words, plan_desc_off, cache_off, key_off, num_off, ctl_off, args_off,
+        ledger_off, counter_off, end_words;
+    int32_t cache_slots, key_words, tally_planes, local_queue_cap, args_bytes, reserved;
+    uint64_t queue_cap;         /* generation queue entries (12 u32 planes each) */
+    uint64_t local_queue_words; /* all workgroup queues (12 u32 per entry) */
+    uint64_t claim_words;       /* per-generation claim counters (u64) */
+    uint64_t order_words;       /* primary work list (u64) */
+} pmc_launch_layout;
+
+/* Fills *out for *q and checks it: every LDS region aligned, disjoint and
+ * inside the allocation, the allocation within a CU's 160 KiB, every cache
+ * key below the free-slot marker, every queue, claim and work-list index
+ * inside its buffer.  Returns PMC_OK, or PMC_ERR_ARG with the reason in why
+ * (why_len bytes, NUL-terminated; may be NULL) and *out as far as computed.
+ * Errors: PMC_ERR_ARG (NULL q/out, or the launch does not fit). */
+pmc_status pmc_plan_launch(const pmc_launch_query* q, pmc_launch_layout* out, char* why, int32_t why_len);
 
 /* Library version string, e.g. "pmc 0.1 gfx950". */
 const char* pmc_version(void);

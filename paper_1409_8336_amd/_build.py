@@ -9,9 +9,9 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpmc.so")
-SOURCES = ["engine.hip", "transport.hip", "tables.cpp", "vavilov.cpp", "moliere.cpp", "unet.hip",
-           "unet_kernels.hip", "gamma.hip"]
-HEADERS = ["device.hpp", "tables.hpp"]
+SOURCES = ["engine.hip", "layout.hip", "transport.hip", "tables.cpp", "vavilov.cpp", "moliere.cpp", "unet.hip",
+           "unet_kernels.hip", "gamma.hip", "replay.hip"]
+HEADERS = ["cache.hpp", "device.hpp", "layout.hpp", "tables.hpp"]
 
 HIP_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

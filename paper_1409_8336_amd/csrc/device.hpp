@@ -47,6 +47,14 @@ constexpr int kOffSigma = 3024;      // n_mat x 1000 total cross section per gra
 // numerator (sum of w eps L over proton steps) and the energy deposited
 // outside any step (nuclear-event local deposits, sub-cut-off rests).
 constexpr uint32_t kScoreLet = 1u << 8;
+// Run flag of a measurement run (single plan, optional-path instantiation):
+// every loop iteration each lane records the tally element its step deposited
+// into, voxel * K + group (its voxel-record gather is element / K;
+// 0xFFFFFFFF for no step) at trace[(epoch * epoch_iters + iteration) *
+// trace_lanes + global lane], and each workgroup its epoch count; the
+// roofline replay re-issues that stream.
+constexpr uint32_t kTrace = 1u << 9;
+constexpr uint32_t kTraceNone = 0xFFFFFFFFu;
 
 // One plan: its geometry (voxel record = {density as float bits, material
 // bin}), its dose tally and its random-number key.  64 bytes.
@@ -141,6 +149,10 @@ struct KernelArgs {
     // every epoch_iters loop iterations; 0 slots = off
     int cache_slots;
     int cache_off;
+    // LDS word offsets of the cache keys, their LET numerators, the control
+    // words and a batch's per-plan ledgers and counters (computed and checked
+    // on the host with the rest of the launch layout)
+    int key_off, num_off, ctl_off, led_off, cnt_off;
     int epoch_iters;
     int cache_probes;   // slots tried (linear probing) before a deposit goes to the tally
     // work claims: workgroup b of a launch of G workgroups takes its j-th
@@ -157,6 +169,12 @@ struct KernelArgs {
     // what does not fit goes to the next generation's queue; 0 = off
     uint32_t* q_loc;
     int loc_cap;
+    // flag kTrace: the address trace (see kTrace), iterations it holds per
+    // lane, lanes of the launch, and each workgroup's epoch count
+    uint32_t* trace;
+    unsigned long long trace_iters;
+    unsigned long long trace_lanes;
+    uint32_t* trace_epochs;
 };
 
 }  // namespace pmc

@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "device.hpp"
+#include "layout.hpp"
 #include "pmc.h"
 #include "tables.hpp"
 
@@ -33,6 +34,13 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_density(const uint2* vox, unsigned long long nvox, float* rho, hipStream_t s);
 hipError_t launch_atomic_probe(double* tally, int nx, int ny, int nz, int K, int grid,
                                unsigned long long per_lane, hipStream_t st);
+hipError_t launch_replay(int mode, const uint32_t* trace, unsigned long long trace_iters, unsigned long long lanes,
+                         const uint32_t* epochs, int epoch_iters, int K, const uint2* vox, double* tally,
+                         int n_slots, int probes, int grid, int block, unsigned long long* sink, hipStream_t st);
+hipError_t launch_stream_read(const void* p, size_t bytes, unsigned long long* sink, int grid, hipStream_t st);
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, int grid, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t* p, unsigned long long n, uint32_t v, hipStream_t st);
+hipError_t launch_count_steps(const uint32_t* trace, unsigned long long n, unsigned long long* out, hipStream_t st);
 }  // namespace pmc
 
 using namespace pmc;
@@ -119,6 +127,8 @@ struct pmc_ctx {
     DevBuf<uint32_t> d_qloc;   // per-workgroup secondary queues
     DevBuf<float> d_spots;
     DevBuf<PlanDesc> d_plans;
+    DevBuf<uint32_t> d_trace, d_trace_epochs;   // roofline replay: address trace (kTrace)
+    DevBuf<unsigned long long> d_sink;
     unsigned long long* h_pinned = nullptr;   // pinned read-back area
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t ev_gen[2 * kMaxGenerations] = {};
@@ -345,14 +355,23 @@ float u2f(uint32_t u)
 }
 
 struct RunResult {
-    double transport_ms = 0, device_ms = 0;
+    double transport_ms = 0, device_ms = 0, first_ms = 0;
     int generations = 0;
+};
+
+// a traced run (kTrace, first generation only): iterations to hold per lane
+// in, the launch shape and trace extent out
+struct TraceReq {
+    unsigned long long iters = 0;
+    int grid = 0, block = 0, slots = 0, epoch_iters = 0, probes = 0;
+    unsigned long long lanes = 0;
 };
 
 // The driver.  tuning = a calibration run: no statistics, no outputs.
 pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const Shape& shape,
-                      hipStream_t st, bool tuning, RunResult* rr)
+                      hipStream_t st, bool tuning, RunResult* rr, TraceReq* trace = nullptr)
 {
+    if (trace && (multi || plans.size() != 1)) return fail(c, PMC_ERR_ARG, "a traced run has one plan");
     const int K = c->p.k_batches;
     const int np = (int)plans.size();
     // LET_d is scored for the whole launch when any plan asks for it: every
@@ -486,39 +505,43 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
     a.batch_events = shape.batch;
 
     const int block = shape.block;
-    const size_t lds_words = (size_t)(multi ? a.pd_offset + 16 * np : a.blob_words);
-    // deposit cache: 12 bytes per slot (16 in a batch of plans: 64-bit keys;
-    // 4 more with LET_d scoring: the slot's float LET numerator), sized from
-    // what the tables leave of the CU's 160 KiB LDS at 16 waves per CU; every
-    // tally index must fit 32 bits
-    int slots = 0;
-    const int key_num_words = (multi ? 2 : 1) + (let ? 1 : 0);
-    const int want = c->p.tally_cache != 0 ? c->p.tally_cache : shape.cache;
-    bool small = true;
-    for (const PlanIn& q : plans) small = small && q.g->nvox() * (unsigned long long)planes < 0xFFFFFFFFull;
-    if (want >= 0 && small) {
-        slots = want;
-        if (slots == 0) {
-            const long wgs = std::max(1, 1024 / block);
-            // what the tables, the control words, the staged arguments (with
-            // their alignment) and a batch's per-plan block leave of the CU's
-            // 160 KiB
-            const long cache_off_bytes = 4L * (long)((lds_words + 1) & ~(size_t)1);
-            const long avail = 163840L / wgs - cache_off_bytes - 4L * kWgCtlWords - 8 - (long)sizeof(LdsArgs) -
-                               (multi ? (long)kPlanLdsBytes * np : 0L);
-            slots = (int)std::min(16384L, avail / (4L * (2 + key_num_words)));
-            if (slots < 512) slots = 0;
-        }
+    // launch layout (LDS regions, buffer sizes): computed and checked by
+    // plan_layout, which the kernel's offsets come from; the grid-dependent
+    // parts once the occupancy has fixed the grid
+    LayoutQuery lq;
+    lq.block = block;
+    lq.n_plans = np;
+    lq.multi = multi;
+    lq.score_let = let;
+    lq.k_batches = K;
+    lq.n_mat = a.n_mat;
+    lq.cache_request = c->p.tally_cache != 0 ? c->p.tally_cache : shape.cache;
+    lq.local_queue = c->p.local_queue;
+    lq.queue_capacity = c->p.queue_capacity;
+    lq.n_histories = total;
+    lq.n_spots = n_spots;
+    for (const PlanIn& q : plans) {
+        lq.max_nvox = std::max<unsigned long long>(lq.max_nvox, q.g->nvox());
+        lq.max_plan_histories = std::max<unsigned long long>(lq.max_plan_histories, q.n_hist);
     }
+    LaunchLayout lay;
+    std::string why = plan_layout(lq, &lay);
+    if (!why.empty()) return fail(c, PMC_ERR_ARG, "launch layout: " + why);
+    if (lay.blob_words != a.blob_words || lay.pd_off != a.pd_offset || lay.q_cap != cap ||
+        lay.planes != planes || lay.order_words != order.size())
+        return fail(c, PMC_ERR_DEVICE, "internal: launch layout disagrees with the run's buffers");
+    const int slots = lay.cache_slots;
     a.cache_slots = slots;
-    a.cache_off = (int)((lds_words + 1) & ~(size_t)1);
+    a.cache_off = lay.cache_off;
+    a.key_off = lay.key_off;
+    a.num_off = lay.num_off;
+    a.ctl_off = lay.ctl_off;
+    a.args_off = lay.args_off;
+    a.led_off = lay.led_off;
+    a.cnt_off = lay.cnt_off;
     a.epoch_iters = c->p.epoch_steps ? c->p.epoch_steps : 32;
     a.cache_probes = c->p.cache_probes ? c->p.cache_probes : 3;
-    // (the workgroup's control words follow the cache, also without one)
-    const size_t used = (size_t)a.cache_off + (size_t)(2 + key_num_words) * slots + kWgCtlWords;
-    a.args_off = (int)((used + 1) & ~(size_t)1);
-    // batched launches: per-plan ledger and counters after the arguments
-    const size_t lds = (size_t)a.args_off * 4 + sizeof(LdsArgs) + (multi ? kPlanLdsBytes * (size_t)np : 0);
+    const size_t lds = lay.lds_bytes;
     int max_block = 0;
     HIPCHK(transport_max_block(multi, a.flags, &max_block), "kernel attributes");
     if (block > max_block) return fail(c, PMC_ERR_ARG, "block_threads exceeds the transport kernel's limit");
@@ -527,21 +550,42 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
     if (fit < 1) return fail(c, PMC_ERR_DEVICE, "transport kernel does not fit on a CU");
     if (bpc == 0 || bpc > fit) bpc = fit;
     const int grid = c->num_cu * bpc;
+    lq.grid = grid;
+    why = plan_layout(lq, &lay);
+    if (!why.empty()) return fail(c, PMC_ERR_ARG, "launch layout: " + why);
+    if (lay.lds_bytes != lds) return fail(c, PMC_ERR_DEVICE, "internal: launch layout changed with the grid");
     // per-workgroup claim counters of every generation
-    HIPCHK(c->d_wgc.ensure((size_t)kMaxGenerations * grid), "alloc claim counters");
-    HIPCHK(launch_zero(c->d_wgc.p, (size_t)kMaxGenerations * grid * 8, st), "zero claim counters");
+    HIPCHK(c->d_wgc.ensure(lay.claim_words), "alloc claim counters");
+    HIPCHK(launch_zero(c->d_wgc.p, lay.claim_words * 8, st), "zero claim counters");
     a.wg_claims = c->d_wgc.p;
     // per-workgroup secondary queues (48-byte entries); automatic: up to
     // 65536 entries per workgroup within 1 GiB for the whole grid (a
     // workgroup of the 16-plan batch emits about 40000 secondaries)
-    a.loc_cap = c->p.local_queue < 0
-                    ? 0
-                    : (c->p.local_queue ? c->p.local_queue
-                                        : (int)std::min<long>(65536L, (1L << 30) / (48L * grid)));
+    a.loc_cap = lay.loc_cap;
     if (a.loc_cap > 0) {
-        HIPCHK(c->d_qloc.ensure((size_t)grid * (size_t)a.loc_cap * kLocEntryWords), "alloc workgroup queues");
+        HIPCHK(c->d_qloc.ensure(lay.qloc_words), "alloc workgroup queues");
         a.q_loc = c->d_qloc.p;
     }
+    if (trace) {
+        // the address trace of generation 0: trace->iters loop iterations of
+        // every lane, pre-filled with "no step"
+        const unsigned long long lanes = (unsigned long long)grid * block;
+        HIPCHK(c->d_trace.ensure(trace->iters * lanes), "alloc trace");
+        HIPCHK(c->d_trace_epochs.ensure(grid), "alloc trace");
+        HIPCHK(launch_fill_u32(c->d_trace.p, trace->iters * lanes, kTraceNone, st), "clear trace");
+        HIPCHK(launch_fill_u32(c->d_trace_epochs.p, grid, 0u, st), "clear trace");
+        a.trace = c->d_trace.p;
+        a.trace_iters = trace->iters;
+        a.trace_lanes = lanes;
+        a.trace_epochs = c->d_trace_epochs.p;
+        trace->grid = grid;
+        trace->block = block;
+        trace->slots = slots;
+        trace->epoch_iters = a.epoch_iters;
+        trace->probes = a.cache_probes;
+        trace->lanes = lanes;
+    }
+    const uint32_t run_flags = a.flags;
     int gens = 0;
     unsigned long long produced_total = 0, overflow_n = 0;
     // generations are launched in groups without waiting: each launch reads
@@ -549,8 +593,9 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
     // and the host reads the produced counts once per group
     int launched = 0;
     // with the workgroups' own queues the next generation only holds what
-    // overflowed them: launch two at a time (the second is mostly empty)
-    const int group = a.loc_cap > 0 ? 2 : kGenGroup;
+    // overflowed them, almost always nothing: launch one at a time, so that a
+    // run is one launch unless its workgroup queues overflowed
+    const int group = a.loc_cap > 0 ? 1 : kGenGroup;
     if (total > 0) {
         bool done = false;
         while (!done) {
@@ -564,6 +609,7 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
                 a.claim_log2 = gidx == 0 ? (c->p.claim_run_log2 ? c->p.claim_run_log2 : 10) : 6;
                 a.q_in = c->d_q[gidx & 1].p;
                 a.q_out = c->d_q[(gidx + 1) & 1].p;
+                a.flags = run_flags | (trace && gidx == 0 ? kTrace : 0u);
                 HIPCHK(hipEventRecord(c->ev_gen[2 * gidx], st), "event");
                 HIPCHK(launch_transport(a, multi, grid, block, lds, st), "transport launch");
                 HIPCHK(hipEventRecord(c->ev_gen[2 * gidx + 1], st), "event");
@@ -602,14 +648,16 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
     HIPCHK(hipStreamSynchronize(st), "run");
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1), "event time");
-    double transport_ms = 0.0;
+    double transport_ms = 0.0, first_ms = 0.0;
     for (int gidx = 0; gidx < launched; ++gidx) {
         float t = 0.f;
         HIPCHK(hipEventElapsedTime(&t, c->ev_gen[2 * gidx], c->ev_gen[2 * gidx + 1]), "event time");
         transport_ms += t;
+        if (gidx == 0) first_ms = t;
     }
     if (rr) {
         rr->transport_ms = transport_ms;
+        rr->first_ms = first_ms;
         rr->device_ms = ms;
         rr->generations = gens;
     }
@@ -647,6 +695,7 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
             sm->total_weight = wtot[p];
             sm->device_ms = ms;
             sm->transport_ms = transport_ms;
+            sm->first_launch_ms = first_ms;
             sm->generations = gens;
             sm->launches = launched;
         }
@@ -1100,6 +1149,128 @@ pmc_status pmc_run_plans(pmc_ctx* c, const pmc_plan* plans, int n_plans, uint64_
                      q.d_dose, q.d_var, q.summary, q.d_let});
     }
     return run_plans_impl(c, v, true, (hipStream_t)hip_stream);
+}
+
+pmc_status pmc_roofline_replay(pmc_ctx* c, const pmc_spot* spots, int n_spots, uint64_t n_histories,
+                               uint64_t seed, void* hip_stream, pmc_replay_result* out)
+{
+    if (!c) return PMC_ERR_ARG;
+    if (!out) return fail(c, PMC_ERR_ARG, "out is NULL");
+    if (!c->have_phys || !have_geometry(c)) return fail(c, PMC_ERR_STATE, "load physics and geometry first");
+    if (n_histories == 0) return fail(c, PMC_ERR_ARG, "n_histories is 0");
+    HIPCHK(hipSetDevice(c->device), "set device");
+    hipStream_t st = (hipStream_t)hip_stream;
+    Geometry& g = *c->geoms[0];
+    const size_t nv = g.nvox();
+    HIPCHK(c->d_dose.ensure(nv), "alloc dose");
+    HIPCHK(c->d_var.ensure(nv), "alloc var");
+    pmc_summary s0;
+    std::vector<PlanIn> plans{{&g, spots, n_spots, n_histories, seed, c->d_dose.p, c->d_var.p, &s0, nullptr}};
+    pmc_status s = run_plans_impl(c, plans, false, st);
+    if (s != PMC_OK) return s;
+    Shape shape;
+    shape.block = s0.block_threads;
+    shape.blocks_per_cu = s0.grid_blocks / std::max(1, c->num_cu);
+    shape.refill = s0.refill_lanes;
+    shape.batch = s0.batch_events;
+    shape.cache = s0.cache_slots > 0 ? s0.cache_slots : -1;
+    // the traced run, with the same launch shape; iterations per lane from
+    // the untraced run's steps, doubled until the trace holds every epoch
+    TraceReq tr;
+    const unsigned long long lanes = (unsigned long long)s0.grid_blocks * (unsigned long long)s0.block_threads;
+    tr.iters = 2 * s0.steps / std::max<unsigned long long>(lanes, 1) + 4096;
+    std::vector<uint32_t> epochs;
+    for (int attempt = 0;; ++attempt) {
+        pmc_summary s1;
+        plans[0].summary = &s1;
+        RunResult r1;
+        s = run_driver(c, plans, false, shape, st, false, &r1, &tr);
+        if (s != PMC_OK) { c->d_trace.release(); return s; }
+        if (tr.grid != s0.grid_blocks || tr.block != s0.block_threads || s1.steps != s0.steps)
+        { c->d_trace.release(); return fail(c, PMC_ERR_DEVICE, "internal: the traced run differs from the run"); }
+        epochs.assign(tr.grid, 0u);
+        HIPCHK(hipMemcpy(epochs.data(), c->d_trace_epochs.p, tr.grid * 4, hipMemcpyDeviceToHost), "read epochs");
+        const unsigned long long need = (unsigned long long)*std::max_element(epochs.begin(), epochs.end()) *
+                                        (unsigned long long)tr.epoch_iters;
+        if (need <= tr.iters) break;
+        if (attempt == 2) { c->d_trace.release(); return fail(c, PMC_ERR_DEVICE, "trace does not fit"); }
+        tr.iters = need + 4096;
+    }
+    HIPCHK(c->d_sink.ensure(2), "alloc sink");
+    HIPCHK(launch_zero(c->d_sink.p, 16, st), "zero sink");
+    HIPCHK(launch_count_steps(c->d_trace.p, tr.iters * tr.lanes, c->d_sink.p + 1, st), "count trace");
+    unsigned long long traced = 0;
+    HIPCHK(hipMemcpyAsync(&traced, c->d_sink.p + 1, 8, hipMemcpyDeviceToHost, st), "read count");
+    HIPCHK(hipStreamSynchronize(st), "count trace");
+    auto timed = [&](int mode, double* ms) -> pmc_status {
+        double best = 1e300;
+        for (int rep = 0; rep < 3; ++rep) {
+            HIPCHK(hipEventRecord(c->ev0, st), "event");
+            HIPCHK(launch_replay(mode, c->d_trace.p, tr.iters, tr.lanes, c->d_trace_epochs.p, tr.epoch_iters,
+                                 c->p.k_batches, g.vox.p, g.tally.p, tr.slots, tr.probes, tr.grid, tr.block,
+                                 c->d_sink.p, st), "replay launch");
+            HIPCHK(hipEventRecord(c->ev1, st), "event");
+            HIPCHK(hipEventSynchronize(c->ev1), "replay");
+            float t = 0.f;
+            HIPCHK(hipEventElapsedTime(&t, c->ev0, c->ev1), "event time");
+            best = std::min(best, (double)t);
+        }
+        *ms = best;
+        return PMC_OK;
+    };
+    std::memset(out, 0, sizeof(*out));
+    const int modes[5] = {0, 1, 2, 6, 7};
+    double* dst[5] = {&out->trace_only_ms, &out->gather_ms, &out->atomic_ms, &out->cached_atomic_ms,
+                      &out->combined_ms};
+    for (int i = 0; i < 5; ++i) {
+        if (modes[i] >= 6 && tr.slots == 0) {   // no cache in this shape: the direct atomics
+            *dst[i] = modes[i] == 6 ? out->atomic_ms : 0.0;
+            if (modes[i] == 7 && (s = timed(3, dst[i])) != PMC_OK) { c->d_trace.release(); return s; }
+            continue;
+        }
+        if ((s = timed(modes[i], dst[i])) != PMC_OK) { c->d_trace.release(); return s; }
+    }
+    c->d_trace.release();
+    out->transport_ms = s0.first_launch_ms;
+    out->steps = s0.steps;
+    out->steps_traced = traced;
+    out->deposits = s0.tally_atomics;
+    out->trace_iters = tr.iters;
+    out->grid_blocks = tr.grid;
+    out->block_threads = tr.block;
+    out->cache_slots = tr.slots;
+    out->epoch_steps = tr.epoch_iters;
+    return PMC_OK;
+}
+
+pmc_status pmc_stream_probe(pmc_ctx* c, uint64_t bytes, void* hip_stream, double* read_ms, double* copy_ms)
+{
+    if (!c) return PMC_ERR_ARG;
+    if (!read_ms || !copy_ms || bytes < (1ull << 20) || bytes % 16)
+        return fail(c, PMC_ERR_ARG, "bytes must be a multiple of 16 of at least 1 MiB; outputs non-NULL");
+    HIPCHK(hipSetDevice(c->device), "set device");
+    hipStream_t st = (hipStream_t)hip_stream;
+    DevBuf<uint4> a, b;
+    HIPCHK(a.ensure(bytes / 16), "alloc probe");
+    HIPCHK(b.ensure(bytes / 16), "alloc probe");
+    HIPCHK(c->d_sink.ensure(2), "alloc sink");
+    HIPCHK(launch_zero(a.p, bytes, st), "fill probe");
+    const int grid = 8 * c->num_cu;
+    for (int which = 0; which < 2; ++which) {
+        double best = 1e300;
+        for (int rep = 0; rep < 4; ++rep) {   // the first launch warms up
+            HIPCHK(hipEventRecord(c->ev0, st), "event");
+            if (which == 0) HIPCHK(launch_stream_read(a.p, bytes, c->d_sink.p, grid, st), "read probe");
+            else HIPCHK(launch_copy(a.p, b.p, bytes, grid, st), "copy probe");
+            HIPCHK(hipEventRecord(c->ev1, st), "event");
+            HIPCHK(hipEventSynchronize(c->ev1), "probe");
+            float t = 0.f;
+            HIPCHK(hipEventElapsedTime(&t, c->ev0, c->ev1), "event time");
+            if (rep > 0) best = std::min(best, (double)t);
+        }
+        *(which == 0 ? read_ms : copy_ms) = best;
+    }
+    return PMC_OK;
 }
 
 pmc_status pmc_atomic_probe(pmc_ctx* c, uint64_t n_atomics, void* hip_stream, double* ms_out)

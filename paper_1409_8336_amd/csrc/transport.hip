@@ -17,6 +17,7 @@
 #include <type_traits>
 
 #include "device.hpp"
+#include "cache.hpp"
 
 // Multiply-adds are fused only where one source expression holds both
 // (not across statements after inlining): the single-plan and batched
@@ -269,9 +270,9 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
     const bool use_cache = n_slots > 0;
     const bool score_let = kOpt && (a.flags & kScoreLet) != 0u;
     double* const cval = reinterpret_cast<double*>(lds + a.cache_off);
-    Key* const ckey = reinterpret_cast<Key*>(lds + a.cache_off + 2 * n_slots);
-    float* const cnum = reinterpret_cast<float*>(ckey + n_slots);
-    uint32_t* const ctl = reinterpret_cast<uint32_t*>(cnum + (score_let ? n_slots : 0));
+    Key* const ckey = reinterpret_cast<Key*>(lds + a.key_off);
+    float* const cnum = reinterpret_cast<float*>(lds + a.num_off);
+    uint32_t* const ctl = reinterpret_cast<uint32_t*>(lds + a.ctl_off);
     uint32_t* const loc_produced = ctl + 0;   // entries reserved in the own queue
     uint32_t* const loc_claimed = ctl + 1;    // entries taken by lanes
     uint32_t* const loc_avail = ctl + 2;      // entries published (written before the last epoch end)
@@ -290,8 +291,8 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
     // the end (lanes change plan at nearly every refill of a secondary
     // generation; flushing to the same few device addresses each time
     // serialised on the memory-side atomics)
-    double* const wg_led = reinterpret_cast<double*>(lds + a.args_off + (int)(sizeof(LdsArgs) / 4));
-    unsigned long long* const wg_cnt = reinterpret_cast<unsigned long long*>(wg_led + 3 * a.n_plans);
+    double* const wg_led = reinterpret_cast<double*>(lds + a.led_off);
+    unsigned long long* const wg_cnt = reinterpret_cast<unsigned long long*>(lds + a.cnt_off);
     if constexpr (kMulti) {
         for (int i = threadIdx.x; i < 3 * a.n_plans; i += blockDim.x) wg_led[i] = 0.0;
         for (int i = threadIdx.x; i < kWgCounters * a.n_plans; i += blockDim.x) wg_cnt[i] = 0ull;
@@ -407,25 +408,10 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                 key |= (Key)plan << 32;
                 h ^= plan * 0x85EBCA6Bu;
             }
-            // multiplicative hash reduced to [0, n_slots) by a high product;
-            // a slot is ours if it holds the key or we claim it empty
-            uint32_t slot = __umulhi(h, (uint32_t)n_slots);
-            auto take = [&](uint32_t sl) {
-                Key held = ckey[sl];
-                if (held == kEmptySlot) {
-                    held = atomicCAS(&ckey[sl], kEmptySlot, key);
-                    if (held == kEmptySlot) held = key;
-                }
-                return held == key;
-            };
-            bool hit = take(slot);
-            // further slots by linear probing (written out for the second,
-            // a loop beyond it)
-            for (int probe = 1; !hit && probe < a.cache_probes; ++probe) {
-                slot = slot + 1u == (uint32_t)n_slots ? 0u : slot + 1u;
-                hit = take(slot);
-            }
-            if (hit) {
+            // multiplicative hash; a slot is ours if it holds the key or we
+            // claim it empty
+            const int slot = cache_slot(ckey, key, h, (uint32_t)n_slots, a.cache_probes);
+            if (slot >= 0) {
                 unsafeAtomicAdd(&cval[slot], v);
                 if (with_num) atomicAdd(&cnum[slot], (float)num);
                 return;
@@ -631,8 +617,10 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
 
         // ------------------------------------------------------------ step
         bool stepped = false, short_step = false;
+        uint32_t tr_key = kTraceNone;   // measurement trace (flag kTrace)
         if (alive && !pend) {
             const unsigned long long vi = ((unsigned long long)vz * P.ny(plan) + vy) * P.nx(plan) + vx;
+            if constexpr (kOpt && !kMulti) tr_key = (uint32_t)(vi * K + batch);
             const unsigned long long rec = gbl(reinterpret_cast<const unsigned long long*>(P.vox(plan)))[vi];
             // what does not depend on the voxel record is computed while its
             // gather is in flight: the step's random numbers, the energy's
@@ -895,6 +883,14 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
         }
         n_steps += stepped;
         n_short += stepped && short_step;
+        if constexpr (kOpt && !kMulti) {
+            if (flags & kTrace) {
+                const unsigned long long n = (unsigned long long)epoch * (unsigned)a.epoch_iters + (unsigned)it;
+                if (n < a.trace_iters)
+                    a.trace[n * a.trace_lanes + blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x] =
+                        tr_key;
+            }
+        }
 
         // ------------------------------------------- batched nuclear events
         const unsigned long long pm = __ballot(pend);
@@ -1199,6 +1195,9 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
     if (*wg_done) break;
     }   // epochs
 
+    if constexpr (kOpt && !kMulti) {
+        if ((flags & kTrace) && threadIdx.x == 0) a.trace_epochs[blockIdx.x] = epoch;
+    }
     // -------------------------------------------------- flush the ledger
     if constexpr (kMulti) {
         flush(plan);
@@ -1413,7 +1412,7 @@ const void* kernel_for(bool multi, bool opt)
 }
 }  // namespace
 
-bool transport_needs_options(uint32_t flags) { return (flags & (kScoreLet | kVavilov | kMoliere)) != 0u; }
+bool transport_needs_options(uint32_t flags) { return (flags & (kScoreLet | kVavilov | kMoliere | kTrace)) != 0u; }
 
 hipError_t launch_transport(const KernelArgs& a, bool multi, int grid, int block, size_t lds_bytes,
                             hipStream_t s)

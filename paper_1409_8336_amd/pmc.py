@@ -26,7 +26,8 @@ EXPORTS = ("pmc_default_params", "pmc_create", "pmc_destroy", "pmc_last_error",
            "pmc_load_physics", "pmc_load_geometry", "pmc_run_spots", "pmc_run_spots_dev",
            "pmc_inspect_tables", "pmc_atomic_probe", "pmc_load_geometry_slot", "pmc_run_plans",
            "pmc_geometry_density", "pmc_version", "pmc_run_spots_let", "pmc_run_spots_let_dev",
-           "pmc_vavilov_table", "pmc_moliere_table")
+           "pmc_vavilov_table", "pmc_moliere_table", "pmc_plan_launch", "pmc_roofline_replay",
+           "pmc_stream_probe")
 
 
 class PMCError(RuntimeError):
@@ -74,7 +75,31 @@ class pmc_summary(C.Structure):
                 ("block_threads", C.c_int32), ("grid_blocks", C.c_int32),
                 ("cache_slots", C.c_int32), ("epoch_steps", C.c_int32),
                 ("cache_flush_atomics", C.c_uint64), ("refill_lanes", C.c_int32),
-                ("batch_events", C.c_int32)]
+                ("batch_events", C.c_int32), ("first_launch_ms", C.c_double)]
+
+
+class pmc_launch_query(C.Structure):
+    _fields_ = [("block_threads", C.c_int32), ("grid_blocks", C.c_int32), ("n_plans", C.c_int32),
+                ("batched", C.c_int32), ("score_let", C.c_int32), ("k_batches", C.c_int32),
+                ("n_mat", C.c_int32), ("tally_cache", C.c_int32), ("local_queue", C.c_int32),
+                ("n_spots", C.c_int32), ("queue_capacity", C.c_uint64), ("n_histories", C.c_uint64),
+                ("max_plan_histories", C.c_uint64), ("max_nvox", C.c_uint64)]
+
+
+class pmc_launch_layout(C.Structure):
+    _fields_ = [("lds_bytes", C.c_uint64)] + [(n, C.c_int32) for n in (
+        "blob_words", "plan_desc_off", "cache_off", "key_off", "num_off", "ctl_off", "args_off",
+        "ledger_off", "counter_off", "end_words", "cache_slots", "key_words", "tally_planes",
+        "local_queue_cap", "args_bytes", "reserved")] + [
+        ("queue_cap", C.c_uint64), ("local_queue_words", C.c_uint64), ("claim_words", C.c_uint64),
+        ("order_words", C.c_uint64)]
+
+
+class pmc_replay_result(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("transport_ms", "trace_only_ms", "gather_ms", "atomic_ms",
+                                          "cached_atomic_ms", "combined_ms")] + [
+        (n, C.c_uint64) for n in ("steps", "steps_traced", "deposits", "trace_iters")] + [
+        (n, C.c_int32) for n in ("grid_blocks", "block_threads", "cache_slots", "epoch_steps")]
 
 
 class pmc_plan(C.Structure):
@@ -132,6 +157,10 @@ def lib():
         L.pmc_geometry_density.argtypes = [vp, i32, vp, vp]
         L.pmc_vavilov_table.argtypes = [vp, C.c_int32]
         L.pmc_moliere_table.argtypes = [vp, C.c_int32]
+        L.pmc_plan_launch.argtypes = [C.POINTER(pmc_launch_query), C.POINTER(pmc_launch_layout), C.c_char_p,
+                                      C.c_int32]
+        L.pmc_roofline_replay.argtypes = [vp, vp, i32, u64, u64, vp, C.POINTER(pmc_replay_result)]
+        L.pmc_stream_probe.argtypes = [vp, u64, vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.pmc_version.restype = C.c_char_p
         for name in EXPORTS:
             if name not in ("pmc_last_error", "pmc_version"):
@@ -371,6 +400,40 @@ def pmc_atomic_probe(ctx, n_atomics, stream=None):
     _check(ctx, lib().pmc_atomic_probe(ctx, int(n_atomics), C.c_void_p(handle) if handle else None,
                                        C.byref(ms)))
     return ms.value
+
+
+def pmc_plan_launch(**query):
+    """Launch layout for the query fields (pmc_launch_query); host only.
+    Returns (status, layout fields as a dict, reason)."""
+    q = pmc_launch_query(**query)
+    out = pmc_launch_layout()
+    why = C.create_string_buffer(256)
+    rc = lib().pmc_plan_launch(C.byref(q), C.byref(out), why, 256)
+    return rc, {f[0]: getattr(out, f[0]) for f in pmc_launch_layout._fields_}, why.value.decode()
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    h = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+    return C.c_void_p(h) if h else None
+
+
+def pmc_roofline_replay(ctx, spots, n_histories, seed, stream=None):
+    """Replay timings of the transport's own address stream (pmc_replay_result
+    fields as a dict)."""
+    sp = np.ascontiguousarray(spots, dtype=np.float32).reshape(-1, 6)
+    out = pmc_replay_result()
+    _check(ctx, lib().pmc_roofline_replay(ctx, _ptr(sp), len(sp), int(n_histories), int(seed),
+                                          _stream_handle(stream), C.byref(out)))
+    return {f[0]: getattr(out, f[0]) for f in pmc_replay_result._fields_}
+
+
+def pmc_stream_probe(ctx, n_bytes, stream=None):
+    """(read ms, copy ms) of a plain read and a plain copy of n_bytes."""
+    r, cp = C.c_double(), C.c_double()
+    _check(ctx, lib().pmc_stream_probe(ctx, int(n_bytes), _stream_handle(stream), C.byref(r), C.byref(cp)))
+    return r.value, cp.value
 
 
 def pmc_geometry_density(ctx, geometry_id, d_rho, stream=None):

@@ -51,6 +51,11 @@ def compare(a_dose, a_var, b_dose, b_var, rho, voxel_cm, wa, wb):
     sel = b_dose >= 0.1 * b_dose.max()
     sd = np.sqrt(a_var[sel] + b_var[sel])
     z = (a_dose[sel] - b_dose[sel]) / np.where(sd > 0, sd, 1.0)
+    # the two 10-group variance estimates voxel by voxel (Eq. 5): on the same
+    # seed they are estimates from the same group tallies
+    va, vb = a_var[sel], b_var[sel]
+    pos = vb > 0
+    vrel = np.abs(va[pos] - vb[pos]) / vb[pos] if pos.any() else np.zeros(1)
     return {
         "idd_max_rel": float(np.max(np.abs(ia - ib)) / ib.max()),
         "r80_a": r80(ia, voxel_cm[2]), "r80_b": r80(ib, voxel_cm[2]),
@@ -60,7 +65,21 @@ def compare(a_dose, a_var, b_dose, b_var, rho, voxel_cm, wa, wb):
         "z_mean": float(z.mean()) if sel.any() else 0.0,
         "z_std": float(z.std()) if sel.any() else 0.0,
         "all_within_3sigma": bool(np.all(np.abs(z) <= 3.0)),
+        "z_absmax": float(np.abs(z).max()) if sel.any() else 0.0,
+        "var_rel_median": float(np.median(vrel)),
+        "var_rel_p99": float(np.percentile(vrel, 99)),
+        "var_ratio_sum": float(va.sum() / vb.sum()) if vb.sum() > 0 else 1.0,
     }
+
+
+def assert_same_seed(m, var_median=0.02, var_p99=0.25):
+    """Same-seed parity: every voxel at or above 10% of the maximum dose within
+    3 sigma of the two variance estimates, and the GPU's per-voxel variance
+    equal to the oracle's (median and 99th percentile of the relative
+    difference; a missing K/(K-1) factor alone would put every voxel 10% off)."""
+    assert m["all_within_3sigma"], m
+    assert m["var_rel_median"] <= var_median and m["var_rel_p99"] <= var_p99, m
+    assert abs(m["var_ratio_sum"] - 1) <= var_median, m
 
 
 def ledger_residual(s):

@@ -1,6 +1,6 @@
 """Batched persistent launch over many plans (pmc_run_plans): a batch gives
 exactly the per-plan results of single-plan runs (same random keys), every
-plan's ledger closes, and a plan of the batch matches the oracle."""
+plan's ledger closes, and every plan of the batch matches the oracle."""
 import sys
 
 import numpy as np
@@ -9,7 +9,7 @@ import pytest
 from oracle import oracle as O
 from paper_1409_8336_amd import pmc, synth
 
-from parity_tools import compare, density_grid, ledger_residual
+from parity_tools import assert_same_seed, compare, density_grid, ledger_residual
 
 pytestmark = pytest.mark.gpu
 
@@ -95,32 +95,38 @@ def test_batched_workgroup_queues_preserve_results():
             assert ledger_residual(sums[p]) < 1e-9
 
 
-def test_uneven_plan_batch_ledgers_and_oracle():
-    """Sixteen plans of uneven size (grids 96^3..256x256x200, 200-3000 spots),
-    histories scaled down; every ledger closes and plan 0 matches the oracle
-    run with the same key."""
+def test_uneven_plan_batch_every_plan_matches_the_oracle():
+    """Sixteen plans of uneven size (grids 96^3..256x256x200, 200-3000 spots)
+    in one batched launch, at 2% of their configured 1e6-1e7 histories
+    (2e4-2e5 per plan, 8.5e5 in all): every ledger closes, and every plan
+    matches the oracle run with the same key (seed + plan index) -- IDD within
+    1%, R80 within 0.2 mm, every voxel at or above 10% of the plan's maximum
+    dose within 3 sigma, the variance voxel by voxel."""
     _say("case: uneven 16-plan batch")
     nd, mt = synth.nuclear_data(), synth.material_table()
     plans = synth.plan_set(n_plans=16, seed=100, hist_scale=0.02)
     e, ids = _batch_engine(nd, mt, plans)
     out, sums = _run_batch(e, ids, plans, 21)
     e.close()
-    for p in range(16):
-        assert sums[p]["histories"] == plans[p]["n_histories"]
-        assert ledger_residual(sums[p]) < 1e-5, (p, sums[p])
-        assert (out[p][0] >= 0).all() and (out[p][1] >= 0).all()
     _say("batch device ms %.2f transport ms %.2f generations %d"
          % (sums[0]["device_ms"], sums[0]["transport_ms"], sums[0]["generations"]))
-    plan = plans[0]
     o = O.Oracle()
     o.load_physics(nd)
-    o.load_geometry(plan["hu"], plan["voxel_cm"], mt)
-    r = o.run_spots(plan["spots"], plan["n_histories"], 21)
-    rho = density_grid(plan["hu"])
-    m = compare(out[0][0], out[0][1], r["dose"], r["var"], rho, plan["voxel_cm"],
-                sums[0]["total_weight"], r["summary"]["total_weight"])
-    _say("metrics plan0: %s" % m)
-    assert m["idd_max_rel"] <= 0.01 and m["r80_diff_mm"] <= 0.2, m
+    for p, plan in enumerate(plans):
+        assert sums[p]["histories"] == plan["n_histories"]
+        assert ledger_residual(sums[p]) < 1e-5, (p, sums[p])
+        assert (out[p][0] >= 0).all() and (out[p][1] >= 0).all()
+        o.load_geometry(plan["hu"], plan["voxel_cm"], mt)
+        r = o.run_spots(plan["spots"], plan["n_histories"], 21 + p)
+        m = compare(out[p][0], out[p][1], r["dose"], r["var"], density_grid(plan["hu"]), plan["voxel_cm"],
+                    sums[p]["total_weight"], r["summary"]["total_weight"])
+        _say("metrics plan %d (%s, %d spots, %d histories): %s"
+             % (p, plan["hu"].shape, len(plan["spots"]), plan["n_histories"], m))
+        assert m["idd_max_rel"] <= 0.01 and m["r80_diff_mm"] <= 0.2, (p, m)
+        assert_same_seed(m)
+        assert ledger_residual(r["summary"]) < 1e-5
+        assert abs(sums[p]["steps"] / r["summary"]["steps"] - 1) < 0.01, (p, sums[p]["steps"])
+    o.close()
 
 
 def test_batched_deposit_cache_preserves_results():

@@ -259,6 +259,6 @@ def test_let_with_vavilov_and_moliere(nd, mt):
     indep = _let_metrics(r2["let"], r1["let"], r1["dose"])
     _say("dose %s; LET same seed %s, oracle seeds %s" % (m, same, indep))
     assert m["idd_max_rel"] <= 0.01 and m["r80_diff_mm"] <= 0.2, m
-    assert m["all_within_3sigma"] or m["frac_z_gt3"] <= 0.01, m
+    assert m["all_within_3sigma"], m
     assert ledger_residual(gs) < 1e-5
     assert same["slab_max"] <= 0.01 and same["rms"] <= indep["rms"], (same, indep)

@@ -16,7 +16,7 @@ import pytest
 from oracle import oracle as O
 from paper_1409_8336_amd import pmc, synth
 
-from parity_tools import compare, density_grid, ledger_residual
+from parity_tools import assert_same_seed, compare, density_grid, ledger_residual
 
 pytestmark = pytest.mark.gpu
 
@@ -48,18 +48,6 @@ def _oracle(nd, mt, hu, voxel=(0.2, 0.2, 0.2), flags=0):
     o.load_physics(nd)
     o.load_geometry(hu, voxel, mt)
     return o
-
-
-def _voxel_consistency_ok(m):
-    """Every voxel within 3 sigma; where histories have diverged through
-    float32-vs-float64 decision flips the realisations are statistically
-    independent and the t-distributed z-scores (two 10-group estimates) are
-    held to their expected tail fraction instead."""
-    if m["all_within_3sigma"]:
-        return True
-    n = m["n_sel"]
-    tail = 0.008 + 3.0 * math.sqrt(0.008 / max(n, 1))
-    return m["frac_z_gt3"] <= tail and abs(m["z_mean"]) <= 0.1 and 0.85 <= m["z_std"] <= 1.2
 
 
 # ---------------------------------------------------------------- tables
@@ -140,7 +128,7 @@ def _parity(nd, mt, hu, spots, n, seed_gpu=1, seed_ora=1, tag=""):
 def _assert_parity(m):
     assert m["idd_max_rel"] <= 0.01, m
     assert m["r80_diff_mm"] <= 0.2, m
-    assert _voxel_consistency_ok(m), m
+    assert_same_seed(m)
     assert m["gpu_res"] < 1e-5 and m["ora_res"] < 1e-5, m
     assert abs(m["gpu_steps_per_hist"] / m["ora_steps_per_hist"] - 1) < 0.01, m
 
@@ -156,7 +144,9 @@ def test_water_pencil_parity(nd, mt):
 
 @pytest.mark.parametrize("energy", [70.0, 150.0, 230.0])
 def test_ct_spot_parity(nd, mt, energy):
-    cfg = synth.config_ct_spots(energy, 60_000)
+    """The heterogeneous CT with one spot per energy at its configured 1e6
+    histories."""
+    cfg = synth.config_ct_spots(energy, 1_000_000)
     m, gs, os_ = _parity(nd, mt, cfg["hu"], cfg["spots"], cfg["n_histories"], tag="ct%g" % energy)
     _assert_parity(m)
 
@@ -330,31 +320,42 @@ def test_device_buffers_match_host_buffers(nd, mt):
 
 # --------------------------------------------- full-size treatment field
 
-def test_full_size_field_properties(nd, mt):
-    """The 256x256x200 CT with the 2000-spot field at 1e7 histories, in the
-    benchmark's launch configuration: properties that hold at any size, and
-    the depth-dose per unit weight against an oracle run on a bounded
-    subset of the same workload."""
+def test_full_size_field_same_seed_parity(nd, mt):
+    """The 256x256x200 CT with the 2000-spot field at its configured 1e7
+    histories, in the benchmark's launch configuration (device buffers on
+    the current stream, autotuned launch shape), against the oracle on the
+    same seed: IDD within 1%, R80 within 0.2 mm, every voxel at or above 10%
+    of the maximum dose within 3 sigma, the variance voxel by voxel, the
+    ledger, steps per history; and properties that hold at any size."""
+    import torch
     cfg = synth.config_field(10_000_000)
-    _say("case: full field n=%d" % cfg["n_histories"])
+    n = cfg["n_histories"]
+    _say("case: full field same seed n=%d (GPU)" % n)
     e = _engine(nd, mt, cfg["hu"])
-    d, v, s = e.run_spots(cfg["spots"], cfg["n_histories"], 1)
+    dd = torch.empty(cfg["hu"].shape, dtype=torch.float64, device="cuda")
+    dv = torch.empty_like(dd)
+    gs = e.run_spots_dev(cfg["spots"], n, cfg["seed"], dd, dv, torch.cuda.current_stream())
+    torch.cuda.synchronize()
     e.close()
-    _say("full field summary %s" % s)
-    assert ledger_residual(s) < 1e-5
-    assert (d >= 0).all() and (v >= 0).all()
-    assert s["histories"] == cfg["n_histories"]
-    n_o = 100_000
+    gd, gv = dd.cpu().numpy(), dv.cpu().numpy()
+    del dd, dv
+    _say("full field GPU summary %s" % gs)
+    assert gs["histories"] == n and (gd >= 0).all() and (gv >= 0).all()
+    _say("case: full field same seed n=%d (oracle)" % n)
     o = _oracle(nd, mt, cfg["hu"])
-    r = o.run_spots(cfg["spots"], n_o, 2)
-    rho = density_grid(cfg["hu"])
-    g_idd = (d * rho).sum(axis=(1, 2))
-    o_idd = (r["dose"] * rho).sum(axis=(1, 2))
-    # per-slice standard error of the oracle estimate from its group variance
-    o_sd = np.sqrt((r["var"] * rho ** 2).sum(axis=(1, 2)))
-    diff = np.abs(g_idd - o_idd)
-    assert np.all(diff <= 4 * o_sd + 0.01 * o_idd.max()), float((diff / o_idd.max()).max())
-    assert abs(s["steps"] / s["histories"] / (r["summary"]["steps"] / n_o) - 1) < 0.02
+    r = o.run_spots(cfg["spots"], n, cfg["seed"])
+    o.close()
+    os_ = r["summary"]
+    _say("oracle %.1f s on %d threads" % (os_["wall_s"], os_["threads"]))
+    m = compare(gd, gv, r["dose"], r["var"], density_grid(cfg["hu"]), (0.2, 0.2, 0.2),
+                gs["total_weight"], os_["total_weight"])
+    m.update(gpu_steps_per_hist=gs["steps"] / n, ora_steps_per_hist=os_["steps"] / n,
+             gpu_res=ledger_residual(gs), ora_res=ledger_residual(os_))
+    _say("metrics field: %s" % m)
+    _assert_parity(m)
+    for key in ("n_nonelastic", "n_elastic"):
+        a, b = gs[key], os_[key]
+        assert abs(a - b) <= 4 * math.sqrt(a + b) + 2, (key, a, b)
 
 
 def test_geometry_density_matches_hu_calibration(nd, mt):
@@ -399,3 +400,37 @@ def test_group_count_leaves_the_dose_unchanged(nd, mt):
     r = res[64][1][m].mean() / v10[m].mean()
     # the mean of many voxel variances: each has relative spread sqrt(2/(K-1))
     assert 0.8 < r < 1.25, r
+
+
+def test_hundred_million_histories_without_variance(nd, mt):
+    """The launch shape of the one GPU fault on record, run on the fixed
+    code: a denoiser-target run of 1e8 histories on the 128x128x160 CT
+    through pmc_run_spots_dev with no variance output (d_var NULL), 512-lane
+    workgroups two per CU with the deposit cache.  Its ledger closes, the
+    dose is finite and non-negative, and its depth-dose agrees with an
+    independent 1e6-history oracle run within the oracle's noise."""
+    import torch
+    case = synth.denoiser_case(0)
+    n = 100_000_000
+    _say("case: 1e8 histories, d_var NULL, 512-lane workgroups (GPU)")
+    e = _engine(nd, mt, case["hu"], block_threads=512, blocks_per_cu=2, refill_lanes=16,
+                batch_events=4)
+    dd = torch.empty(case["hu"].shape, dtype=torch.float64, device="cuda")
+    s = e.run_spots_dev(case["spots"], n, 20_000, dd, None)
+    torch.cuda.synchronize()
+    e.close()
+    d = dd.cpu().numpy()
+    _say("1e8 summary %s" % s)
+    assert s["histories"] == n and s["block_threads"] == 512 and s["cache_slots"] > 0
+    assert s["grid_blocks"] == 2 * torch.cuda.get_device_properties(0).multi_processor_count
+    assert ledger_residual(s) < 1e-5
+    assert np.isfinite(d).all() and (d >= 0).all() and d.max() > 0
+    o = _oracle(nd, mt, case["hu"])
+    r = o.run_spots(case["spots"], 1_000_000, 3)
+    o.close()
+    rho = density_grid(case["hu"])
+    g_idd = (d * rho).sum(axis=(1, 2))
+    o_idd = (r["dose"] * rho).sum(axis=(1, 2))
+    o_sd = np.sqrt((r["var"] * rho ** 2).sum(axis=(1, 2)))
+    diff = np.abs(g_idd - o_idd)
+    assert np.all(diff <= 4 * o_sd + 0.01 * o_idd.max()), float((diff / o_idd.max()).max())

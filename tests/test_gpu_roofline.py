@@ -1,0 +1,59 @@
+"""Roofline measurement entry points on the GPU (through the C ABI): the
+replay of the transport's own address stream (one voxel-record gather and
+one FP64 tally add per condensed-history step, Sec. II.A.3 / II.B.2) and the
+plain read / copy bandwidth references."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1409_8336_amd import pmc, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def test_replay_reissues_the_transport_address_stream():
+    """The traced run is the run (same steps), its trace holds every step of
+    the first generation, the replays take positive time that grows with the
+    work they re-issue, and the engine's results are unchanged afterwards."""
+    _say("case: roofline replay (CT 150 MeV, 3e5 histories)")
+    nd, mt = synth.nuclear_data(), synth.material_table()
+    cfg = synth.config_ct_spots(150.0, 300_000)
+    e = pmc.Engine(0)
+    e.load_physics(nd)
+    e.load_geometry(cfg["hu"], cfg["voxel_cm"], mt)
+    d0, v0, s0 = e.run_spots(cfg["spots"], cfg["n_histories"], 5)
+    r = pmc.pmc_roofline_replay(e.ctx, cfg["spots"], cfg["n_histories"], 5)
+    _say("replay %s" % r)
+    d1, v1, s1 = e.run_spots(cfg["spots"], cfg["n_histories"], 5)
+    e.close()
+    assert r["steps"] == s0["steps"]
+    # generation 0 holds every step unless a workgroup queue overflowed
+    assert 0.99 * r["steps"] <= r["steps_traced"] <= r["steps"]
+    assert r["deposits"] >= r["steps"]
+    assert r["grid_blocks"] > 0 and r["block_threads"] > 0 and r["trace_iters"] > 0
+    for k in ("transport_ms", "trace_only_ms", "gather_ms", "atomic_ms", "cached_atomic_ms", "combined_ms"):
+        assert r[k] > 0, k
+    assert r["gather_ms"] >= 0.9 * r["trace_only_ms"]
+    assert r["combined_ms"] >= 0.9 * max(r["gather_ms"], r["cached_atomic_ms"])
+    np.testing.assert_allclose(d1, d0, rtol=1e-9, atol=1e-12 * d0.max())
+    assert s1["steps"] == s0["steps"]
+
+
+def test_stream_probe_bandwidth_is_plausible():
+    _say("case: stream probe")
+    e = pmc.Engine(0)
+    n = 1 << 30
+    read_ms, copy_ms = pmc.pmc_stream_probe(e.ctx, n)
+    e.close()
+    read_gbs = n / (read_ms * 1e-3) / 1e9
+    copy_gbs = 2 * n / (copy_ms * 1e-3) / 1e9
+    _say("read %.0f GB/s, copy %.0f GB/s" % (read_gbs, copy_gbs))
+    assert 500 < read_gbs < 8000 and 500 < copy_gbs < 8000
+    with pytest.raises(pmc.PMCError):
+        pmc.pmc_stream_probe(pmc.Engine(0).ctx, 1000)
