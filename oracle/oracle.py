@@ -15,10 +15,31 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "pmc_oracle.c")
+SRC_INC = os.path.join(HERE, "pmc_oracle_inc.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 NO_STRAGGLE, NO_MCS, NO_NUCLEAR, VAVILOV, MOLIERE = 1, 2, 4, 8, 16
 PLAIN_HINGE = 32   # test only: no landing of the second hinge segment on the face
+INC = 64           # non-elastic events by the intranuclear cascade and evaporation
+INC_SHELLS, INC_MAX_OUT = 15, 96
+EJ_NAMES = ("n", "p", "d", "t", "He3", "alpha")
+
+
+class Nucleus(C.Structure):
+    _fields_ = [("z", C.c_int32), ("a", C.c_int32), ("radius_ws", C.c_double), ("diffuseness", C.c_double),
+                ("r_out", C.c_double), ("r", C.c_double * (INC_SHELLS + 1)),
+                ("rho_p", C.c_double * INC_SHELLS), ("rho_n", C.c_double * INC_SHELLS),
+                ("tf_p", C.c_double * INC_SHELLS), ("tf_n", C.c_double * INC_SHELLS)]
+
+
+class IncResult(C.Structure):
+    _fields_ = [("n", C.c_int32), ("kind", C.c_int32 * INC_MAX_OUT), ("stage", C.c_int32 * INC_MAX_OUT),
+                ("id", C.c_uint32 * INC_MAX_OUT), ("t", C.c_double * INC_MAX_OUT),
+                ("dir", (C.c_double * 3) * INC_MAX_OUT), ("z_res", C.c_int32), ("a_res", C.c_int32),
+                ("e_star", C.c_double), ("e_star_sum", C.c_double), ("n_coll", C.c_int32),
+                ("n_blocked", C.c_int32), ("attempts", C.c_int32), ("n_esc", C.c_int32),
+                ("compound", C.c_int32), ("z_fin", C.c_int32), ("a_fin", C.c_int32),
+                ("e_star_fin", C.c_double), ("binding", C.c_double), ("pauli_min", C.c_double)]
 MOL_SHAPE = (13, 161)     # [1/B = 1/20 + j (2/9 - 1/20)/12][q = k/8]
 VAV_SHAPE = (5, 31, 97)   # [beta^2 = k/10][log10 kappa = -2 + j/10][z = -6 + i/8]
 _lock = threading.Lock()
@@ -28,10 +49,10 @@ _lib = None
 def build(force: bool = False) -> str:
     """Compile the oracle (gcc -O2, OpenMP, no fast-math)."""
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < max(
-            os.path.getmtime(SRC), os.path.getmtime(os.path.join(HERE, "pmc_oracle.h"))):
+            os.path.getmtime(SRC), os.path.getmtime(SRC_INC), os.path.getmtime(os.path.join(HERE, "pmc_oracle.h"))):
         tmp = LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fopenmp", "-fPIC",
-                               "-shared", "-Wall", "-Wno-unknown-pragmas", SRC, "-o", tmp, "-lm"])
+                               "-shared", "-Wall", "-Wno-unknown-pragmas", SRC, SRC_INC, "-o", tmp, "-lm"])
         os.replace(tmp, LIB)
     return LIB
 
@@ -126,6 +147,24 @@ def lib():
                                                   C.POINTER(C.c_double)]
             L.oracle_rotate.argtypes = [C.POINTER(C.c_double), d, d, d]
             L.oracle_rotate.restype = None
+            L.oracle_inc_nucleus.argtypes = [C.c_int, C.POINTER(Nucleus)]
+            L.oracle_nn_sigma_mb.argtypes = [C.c_int, d]
+            L.oracle_nn_sigma_mb.restype = d
+            L.oracle_nn_slope.argtypes = [d]
+            L.oracle_nn_slope.restype = d
+            L.oracle_inc_event.argtypes = [C.c_int, d, C.c_uint64, C.c_uint64, C.c_uint32, C.c_int,
+                                           C.POINTER(IncResult)]
+            L.oracle_evaporate.argtypes = [C.c_int, C.c_int, d, C.c_uint64, C.c_uint64, C.c_uint32,
+                                           C.POINTER(IncResult)]
+            L.oracle_binding_energy.argtypes = [C.c_int, C.c_int]
+            L.oracle_binding_energy.restype = d
+            L.oracle_evap_width.argtypes = [C.c_int, C.c_int, d, C.c_int, C.POINTER(d), C.POINTER(d)]
+            L.oracle_evap_width.restype = d
+            L.oracle_fermi_momentum.argtypes = [d, C.POINTER(d), C.POINTER(d)]
+            L.oracle_fermi_momentum.restype = None
+            L.oracle_inc_refract.argtypes = [d, d, d, C.POINTER(d), C.POINTER(d), C.POINTER(d)]
+            L.oracle_nn_collide.argtypes = [C.POINTER(d), C.POINTER(d), d, d, C.POINTER(d), C.POINTER(d)]
+            L.oracle_nn_collide.restype = None
             _lib = L
     return _lib
 
@@ -188,6 +227,73 @@ def rotate(d, ct, st, phi_rev):
     arr = (C.c_double * 3)(*d)
     lib().oracle_rotate(arr, ct, st, phi_rev)
     return list(arr)
+
+
+def inc_nucleus(element):
+    """The cascade's nucleus for element 1..6 (C, N, O, P, Ca, Ti) as a dict."""
+    nu = Nucleus()
+    if lib().oracle_inc_nucleus(int(element), C.byref(nu)):
+        raise ValueError("bad element")
+    out = {"z": nu.z, "a": nu.a, "radius_ws": nu.radius_ws, "diffuseness": nu.diffuseness, "r_out": nu.r_out}
+    for k in ("r", "rho_p", "rho_n", "tf_p", "tf_n"):
+        out[k] = np.array(getattr(nu, k)[:], dtype=np.float64)
+    return out
+
+
+def _inc_dict(r):
+    n = r.n
+    out = {k: getattr(r, k) for k in ("z_res", "a_res", "e_star", "e_star_sum", "n_coll", "n_blocked",
+                                       "attempts", "n_esc", "compound", "z_fin", "a_fin", "e_star_fin",
+                                       "binding", "pauli_min")}
+    out.update(kind=np.array(r.kind[:n]), stage=np.array(r.stage[:n]), id=np.array(r.id[:n]),
+               t=np.array(r.t[:n]), dir=np.array([list(r.dir[i]) for i in range(n)]).reshape(n, 3))
+    return out
+
+
+def inc_event(element, t_mev, seed, uid, ks=0, evaporate=True):
+    """One non-elastic event (cascade, then evaporation) as a dict."""
+    r = IncResult()
+    if lib().oracle_inc_event(int(element), float(t_mev), int(seed), int(uid), int(ks), int(evaporate),
+                              C.byref(r)):
+        raise ValueError("oracle_inc_event failed")
+    return _inc_dict(r)
+
+
+def evaporate(z, a, e_star, seed, uid, ks=0):
+    r = IncResult()
+    lib().oracle_evaporate(int(z), int(a), float(e_star), int(seed), int(uid), int(ks), C.byref(r))
+    return _inc_dict(r)
+
+
+def evap_width(z, a, e_star, kind):
+    """(relative width, separation energy, Coulomb barrier) of ejectile kind."""
+    s, v = C.c_double(), C.c_double()
+    w = lib().oracle_evap_width(int(z), int(a), float(e_star), int(kind), C.byref(s), C.byref(v))
+    return w, s.value, v.value
+
+
+def fermi_momentum(p_fermi, u):
+    uu = (C.c_double * 3)(*u)
+    p = (C.c_double * 3)()
+    lib().oracle_fermi_momentum(float(p_fermi), uu, p)
+    return list(p)
+
+
+def inc_refract(t, v_from, v_to, x, d):
+    """(crossed, new kinetic energy, new direction) at a shell boundary."""
+    xx = (C.c_double * 3)(*x)
+    dd = (C.c_double * 3)(*d)
+    to = C.c_double()
+    crossed = lib().oracle_inc_refract(float(t), float(v_from), float(v_to), xx, dd, C.byref(to))
+    return crossed, to.value, list(dd)
+
+
+def nn_collide(p1, p2, u_t, u_phi):
+    a = (C.c_double * 3)(*p1)
+    b = (C.c_double * 3)(*p2)
+    o1, o2 = (C.c_double * 3)(), (C.c_double * 3)()
+    lib().oracle_nn_collide(a, b, float(u_t), float(u_phi), o1, o2)
+    return list(o1), list(o2)
 
 
 def radiation_length(w):

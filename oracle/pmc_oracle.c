@@ -1304,6 +1304,33 @@ static int interact(const ora_ctx* c, const orun* r, opart* q, const int v[3], u
         return 1;
     }
     acc->n_ne++;
+    if (c->p.flags & ORA_INC) {
+        /* intranuclear cascade and evaporation (Sec. II.A.4): protons above
+         * the cut-off are transported, neutrons dropped (neutral ledger, with
+         * the separation energies and the excitation left for photons), the
+         * kinetic energy of heavier fragments and of sub-cut-off protons
+         * deposited here */
+        ora_inc_result ir;
+        oracle_inc_event(el, t, r->seed, q->uid, ks, 1, &ir);
+        double local = 0.0, neutral = ir.binding + ir.e_star_fin;
+        for (int i = 0; i < ir.n; ++i) {
+            if (ir.kind[i] == ORA_EJ_N) { neutral += ir.t[i]; continue; }
+            if (ir.kind[i] != ORA_EJ_P || ir.t[i] <= E_CUT) { local += ir.t[i]; continue; }
+            opart ch = *q;
+            const double* e = ir.dir[i];
+            oracle_rotate(ch.d, e[2], sqrt(e[0] * e[0] + e[1] * e[1]), atan2(e[1], e[0]) / (2.0 * M_PI));
+            ch.e = ir.t[i];
+            ch.uid = child_uid(r->seed, q->uid, ks, ir.id[i]);
+            ch.k = 0;
+            ch.primary = 0;
+            birth(r, &ch);
+            push(st, &ch);
+            acc->secondaries++;
+        }
+        deposit(c, r, vi, q->batch, q->w * local);
+        acc->neutral += q->w * neutral;
+        return 0;
+    }
     int n;
     double es[4], mus[4], fl;
     oracle_secondary_sample(c, el, t, q->uid, ks, r->seed, u4[0], &n, es, mus, &fl);

@@ -38,8 +38,10 @@ extern "C" {
 /* ORA_PLAIN_HINGE (test only): the second hinge segment always keeps its
    nominal length (1 - u) s, without the landing on the crossed face plane;
    used to measure what that landing changes */
+/* ORA_INC: non-elastic events by the intranuclear cascade and evaporation
+   below (Sec. II.A.4) instead of the synthetic secondary table */
 enum { ORA_NO_STRAGGLE = 1, ORA_NO_MCS = 2, ORA_NO_NUCLEAR = 4, ORA_VAVILOV = 8, ORA_MOLIERE = 16,
-       ORA_PLAIN_HINGE = 32 };
+       ORA_PLAIN_HINGE = 32, ORA_INC = 64 };
 
 /* Molière sampling table: [1/B = 1/20 + j (2/9 - 1/20)/12, j < 13][q = k/8, k < 161]
    of ln(v^2 / q), v the reduced angle, q = -ln u */
@@ -169,6 +171,60 @@ double oracle_moliere_survival(double x, double v);
 int oracle_moliere_table(double* out);
 double oracle_moliere_theta(const ora_ctx* c, int material, double t_mev, double rho, double s_cm,
                             double u, double* b_out);
+
+/* ---- Intranuclear cascade and evaporation (Sec. II.A.4), test pieces ----
+ * Targets: element index 1..6 = C-12, N-14, O-16, P-31, Ca-40, Ti-48. */
+#define ORA_INC_SHELLS 15
+#define ORA_INC_MAX_OUT 96
+enum { ORA_EJ_N = 0, ORA_EJ_P = 1, ORA_EJ_D = 2, ORA_EJ_T = 3, ORA_EJ_HE3 = 4, ORA_EJ_ALPHA = 5 };
+
+typedef struct {
+    int32_t z, a;
+    double radius_ws, diffuseness, r_out;        /* fm */
+    double r[ORA_INC_SHELLS + 1];                /* shell boundaries, fm */
+    double rho_p[ORA_INC_SHELLS], rho_n[ORA_INC_SHELLS];   /* fm^-3 */
+    double tf_p[ORA_INC_SHELLS], tf_n[ORA_INC_SHELLS];     /* Fermi kinetic energies, MeV */
+} ora_nucleus;
+
+typedef struct {
+    int32_t n;                                   /* emitted particles */
+    int32_t kind[ORA_INC_MAX_OUT];               /* ORA_EJ_* */
+    int32_t stage[ORA_INC_MAX_OUT];              /* 0 cascade, 1 evaporation */
+    uint32_t id[ORA_INC_MAX_OUT];                /* child id (uid draw tag 0xC0000000 | id) */
+    double t[ORA_INC_MAX_OUT];                   /* kinetic energy, MeV */
+    double dir[ORA_INC_MAX_OUT][3];              /* direction, incident proton along +z */
+    int32_t z_res, a_res;                        /* residual after the cascade */
+    double e_star;                               /* its excitation (from the energy balance) */
+    double e_star_sum;                           /* the same from the holes and trapped particles */
+    int32_t n_coll, n_blocked, attempts, n_esc;  /* allowed / Pauli-blocked collisions, entries */
+    int32_t compound;                            /* no allowed collision in 64 entries: absorbed */
+    int32_t z_fin, a_fin;                        /* after evaporation */
+    double e_star_fin;                           /* excitation left (photons, not followed) */
+    double binding;                              /* (n_esc - 1) S + sum of evaporation separation energies */
+    double pauli_min;                            /* least (product kinetic energy - its Fermi energy)
+                                                    over the allowed collisions (INFINITY if none) */
+} ora_inc_result;
+
+int oracle_inc_nucleus(int element, ora_nucleus* out);
+double oracle_nn_sigma_mb(int same_species, double t_lab_mev);
+double oracle_nn_slope(double p_lab_gev);
+/* One non-elastic event of a proton of t_mev on element (1..6), random
+   stream (seed, uid, ks); evaporate = 0 stops after the cascade. */
+int oracle_inc_event(int element, double t_mev, uint64_t seed, uint64_t uid, uint32_t ks, int evaporate,
+                     ora_inc_result* out);
+/* Evaporation of a nucleus (z, a, e_star) alone, emissions numbered from 0. */
+int oracle_evaporate(int z, int a, double e_star, uint64_t seed, uint64_t uid, uint32_t ks, ora_inc_result* out);
+double oracle_binding_energy(int z, int a);      /* MeV; -INFINITY where unbound */
+/* the cascade's sub-steps, as it calls them: a Fermi-sea partner momentum
+   (MeV/c) in shell k from uniforms u[0] (magnitude), u[1] (cos theta),
+   u[2] (azimuth); the crossing of a spherical shell boundary (returns 1 if
+   crossed, 0 if reflected; t and d updated); an elastic NN collision */
+void oracle_fermi_momentum(double p_fermi, const double u[3], double p[3]);
+int oracle_inc_refract(double t, double v_from, double v_to, const double x[3], double d[3], double* t_out);
+void oracle_nn_collide(const double p1[3], const double p2[3], double u_t, double u_phi, double o1[3], double o2[3]);
+/* Relative emission width of ejectile kind from (z, a, e_star) by quadrature,
+   and its separation energy and Coulomb barrier. */
+double oracle_evap_width(int z, int a, double e_star, int kind, double* sep, double* barrier);
 
 #ifdef __cplusplus
 }
