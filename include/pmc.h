@@ -67,7 +67,7 @@ enum {
                               W drawn by mapping the step's normal score through the
                               quantile table pmc_vavilov_table returns (trilinear).
                               Default (flag clear): W standard normal */
-    PMC_MOLIERE = 16u      /* Molière multiple scattering (Sec. II.A.2's full Molière option)
+    PMC_MOLIERE = 16u,     /* Molière multiple scattering (Sec. II.A.2's full Molière option)
                               instead of the scaled Highland Gaussian, on steps where
                               Bethe's B (B - ln B = ln(chi_c^2 / 1.167 chi_a^2)) is at
                               least 4.5; chi_c^2 = K m_e c^2 rho s sum w Z(Z+1)/A / (p beta)^2,
@@ -77,6 +77,18 @@ enum {
                               the table pmc_moliere_table returns (bilinear), at most pi.
                               Steps with B < 4.5 keep the Highland Gaussian (f_mcs applies
                               there only) */
+    PMC_INC = 64u          /* non-elastic events by the intranuclear cascade and evaporation
+                              of Sec. II.A.4 (pmc_inc_events describes the model) instead of
+                              the per-nucleus secondary tables of pmc_nuclear_data: the
+                              transport lists each event and stops the proton; after each
+                              transport generation a cascade kernel works the list (FP64),
+                              queues the protons it emits above 0.1 MeV for the next
+                              generation, deposits the kinetic energy of heavier fragments
+                              and sub-cut-off protons in the event's voxel and books
+                              neutrons, separation energies and the residual excitation as
+                              neutral.  The event list holds queue_capacity events per
+                              generation (0: max(65536, N)); beyond it the event's energy is
+                              overflow and the run returns PMC_ERR_QUEUE_OVERFLOW */
 };
 
 typedef struct {
@@ -188,6 +200,10 @@ typedef struct {
     double first_launch_ms;  /* HIP-event duration of the first transport launch (generation 0;
                                 with the workgroup queues on it holds the whole transport, the
                                 following launch only confirms that nothing overflowed) */
+    uint64_t inc_events;     /* PMC_INC: non-elastic events worked by the cascade kernel, */
+    uint64_t inc_secondaries; /* the protons it queued (also counted in secondaries), */
+    uint64_t inc_collisions; /* the allowed nucleon-nucleon collisions of their cascades */
+    double inc_ms;           /* PMC_INC: sum of the cascade launches' HIP-event durations */
 } pmc_summary;
 
 typedef struct pmc_ctx pmc_ctx;
@@ -431,6 +447,86 @@ typedef struct {
  * (why_len bytes, NUL-terminated; may be NULL) and *out as far as computed.
  * Errors: PMC_ERR_ARG (NULL q/out, or the launch does not fit). */
 pmc_status pmc_plan_launch(const pmc_launch_query* q, pmc_launch_layout* out, char* why, int32_t why_len);
+
+/* ---- Intranuclear cascade and evaporation (Sec. II.A.4; flag PMC_INC) ----
+ * Targets: element 1..6 = C-12, N-14, O-16, P-31, Ca-40, Ti-48 (the
+ * material compositions' C, N, O, P, Ca, Ti).  The model, with the readings
+ * taken where the paper is silent or its models' parameters are absent:
+ *   - nucleus: Woods-Saxon density, R = 1.16 A^(1/3) (1 - 1.16 A^(-2/3)) fm,
+ *     diffuseness 0.55 fm, cut at R + 5 a into 15 equal-thickness shells at
+ *     the profile's mean density, normalised to A; protons Z/A of it,
+ *     neutrons N/A; a two-component Fermi gas per shell (Fermi momentum
+ *     (3 pi^2 rho)^(1/3) hbar c), well depth = Fermi energy + 7 MeV;
+ *   - the proton enters at an impact parameter uniform over the outer disc,
+ *     refracted at every shell boundary (energy conserved, tangential
+ *     momentum kept; total reflection where the normal component would be
+ *     imaginary); free paths from free elastic NN cross sections (like
+ *     nucleons 22 + 1000/T mb, unlike 30 + 3000/T mb; stand-ins for
+ *     Cugnon's) on the partners not yet exhausted; partner momentum uniform
+ *     in the shell's Fermi sphere; CM angle from exp(B t), B = 5.5 p^8 /
+ *     (7.7 + p^8) (GeV/c)^-2; Pauli blocking: both products above their
+ *     Fermi energies; the entry is repeated (at most 64 times) until the
+ *     cascade has an allowed collision, else the proton is absorbed;
+ *   - excitation of the residual = incident energy - emitted kinetic energy
+ *     - 7 MeV per emitted nucleon beyond the first; Weisskopf-Ewing
+ *     evaporation of n, p, d, t, 3He, alpha (Weizsaecker binding energies,
+ *     Coulomb barriers at R = 1.5 (A_d^(1/3) + a^(1/3)) fm, level density
+ *     exp(2 sqrt(A_d U / 8))), isotropic, until no channel is open or A <= 4;
+ *   - at most 96 emitted particles per event; FP64 throughout.
+ * Random numbers: Philox4x32-10 keyed by seed, counter (uid, ks, tag):
+ * cascade particle j's m-th block of entry attempt e uses tag 0x40000000 |
+ * e << 20 | j << 12 | m; evaporation step i tag 0x50000000 | i << 8 | r;
+ * the uid of an emitted proton with child id is the first two words of the
+ * block with tag 0xC0000000 | id. */
+typedef struct {
+    int32_t n_out;           /* emitted particles in particles[i * 96 ...] */
+    int32_t n_coll;          /* allowed NN collisions of the final entry attempt */
+    int32_t n_blocked;       /* Pauli-blocked (or no-room) collision candidates, all attempts */
+    int32_t attempts;        /* entry attempts (64 and compound = 1: absorbed) */
+    int32_t n_esc;           /* nucleons that left the nucleus in the cascade */
+    int32_t compound;
+    int32_t z_res, a_res;    /* residual after the cascade */
+    int32_t z_fin, a_fin;    /* after evaporation */
+    int32_t reserved[2];
+    double e_star;           /* residual excitation from the energy balance, MeV */
+    double e_star_sum;       /* the same from the holes and trapped particles (a check) */
+    double e_star_fin;       /* excitation left after evaporation (photons, not followed) */
+    double binding;          /* 7 MeV per extra cascade nucleon + evaporation separation energies */
+} pmc_inc_result;
+
+typedef struct {
+    int32_t kind;            /* 0 n, 1 p, 2 d, 3 t, 4 3He, 5 alpha */
+    int32_t stage;           /* 0 cascade, 1 evaporation */
+    uint32_t id;             /* child id: 0x100 + cascade particle, 0x400 + evaporation step */
+    int32_t reserved;
+    double t_mev;            /* kinetic energy */
+    double dir[3];           /* direction; the incident proton moves along +z */
+} pmc_inc_particle;
+
+/* Runs n non-elastic events on the GPU, event i a proton of t_mev[i] on
+ * element[i] with random stream (uid[i], ks[i]) under key seed; evaporate =
+ * 0 stops after the cascade.  Host buffers: results[n], particles[n * 96]
+ * (entries beyond results[i].n_out unspecified).  Device memory is
+ * allocated and released inside the call (an inspection entry point; the
+ * transport uses the same kernel code on its event lists).  Errors:
+ * PMC_ERR_ARG (NULL arrays with n > 0, n < 0, element outside 1..6),
+ * PMC_ERR_RANGE (t_mev outside (0, 1000]), PMC_ERR_NOMEM, PMC_ERR_DEVICE. */
+pmc_status pmc_inc_events(pmc_ctx* c, const int32_t* element, const double* t_mev, const uint64_t* uid,
+                          const uint32_t* ks, int32_t n, uint64_t seed, int32_t evaporate,
+                          pmc_inc_result* results, pmc_inc_particle* particles);
+
+/* The cascade's target nucleus, host only: out[0..15] shell boundaries (fm),
+ * out[16..30] proton and out[31..45] neutron densities (fm^-3), out[46..60]
+ * proton and out[61..75] neutron Fermi kinetic energies (MeV), out[76] the
+ * Woods-Saxon radius R (fm), out[77] A.  Errors: PMC_ERR_ARG (out NULL,
+ * n_doubles < 78, element outside 1..6). */
+pmc_status pmc_inc_nucleus(int32_t element, double* out, int32_t n_doubles);
+
+/* Relative evaporation width of ejectile kind (0..5) from nucleus (z, a) at
+ * excitation e_star (MeV), host only, in closed form; *sep and *barrier (may
+ * be NULL) get the channel's separation energy and Coulomb barrier.  0 for a
+ * closed channel or a kind outside 0..5. */
+double pmc_inc_width(int32_t z, int32_t a, double e_star, int32_t kind, double* sep, double* barrier);
 
 /* Library version string, e.g. "pmc 0.1 gfx950". */
 const char* pmc_version(void);

@@ -10,8 +10,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpmc.so")
 SOURCES = ["engine.hip", "layout.hip", "transport.hip", "tables.cpp", "vavilov.cpp", "moliere.cpp", "unet.hip",
-           "unet_kernels.hip", "gamma.hip", "replay.hip"]
-HEADERS = ["cache.hpp", "device.hpp", "layout.hpp", "tables.hpp"]
+           "unet_kernels.hip", "gamma.hip", "replay.hip", "inc.hip"]
+HEADERS = ["cache.hpp", "device.hpp", "inc.hpp", "layout.hpp", "rng.hpp", "tables.hpp"]
 
 HIP_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

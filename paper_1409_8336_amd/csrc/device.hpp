@@ -22,6 +22,11 @@ constexpr int kPlanLdsBytes = 8 * (3 + kWgCounters);
 // count of workgroups that stopped at the epoch limit (plan 0 only)
 constexpr int kPlanCounters = 16;
 constexpr int kCtrAborted = 8;
+// non-elastic events worked by the cascade kernel, the protons it queued and
+// the allowed nucleon-nucleon collisions of their cascades (flag PMC_INC)
+constexpr int kCtrIncEvents = 9;
+constexpr int kCtrIncSecondaries = 10;
+constexpr int kCtrIncCollisions = 11;
 // LDS control words of a workgroup (u32), after the deposit cache: own
 // secondary queue produced / claimed / published, alive lanes at the epoch
 // end, primaries exhausted, workgroup done
@@ -54,6 +59,9 @@ constexpr uint32_t kScoreLet = 1u << 8;
 // trace_lanes + global lane], and each workgroup its epoch count; the
 // roofline replay re-issues that stream.
 constexpr uint32_t kTrace = 1u << 9;
+// Public flag PMC_INC: a non-elastic event is written to the generation's
+// event list (IncEvent) for the cascade kernel, and the proton stops.
+constexpr uint32_t kInc = 64u;
 constexpr uint32_t kTraceNone = 0xFFFFFFFFu;
 
 // One plan: its geometry (voxel record = {density as float bits, material
@@ -90,6 +98,9 @@ struct alignas(8) LdsArgs {
     double* ledger;
     unsigned long long* counters;
     uint32_t* q_loc;   // this launch's per-workgroup queues (loc_cap entries each)
+    void* inc_ev;      // flag PMC_INC: this generation's event list (IncEvent entries)
+    unsigned long long* inc_count;   // events recorded in it
+    unsigned long long inc_cap;
     int n_spots;
     int loc_cap;
 };
@@ -175,6 +186,11 @@ struct KernelArgs {
     unsigned long long trace_iters;
     unsigned long long trace_lanes;
     uint32_t* trace_epochs;
+    // flag PMC_INC: the generation's non-elastic event list (IncEvent, 64 B
+    // each), its counter and capacity
+    void* inc_ev;
+    unsigned long long* inc_count;
+    unsigned long long inc_cap;
 };
 
 }  // namespace pmc

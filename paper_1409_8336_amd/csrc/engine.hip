@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "device.hpp"
+#include "inc.hpp"
 #include "layout.hpp"
 #include "pmc.h"
 #include "tables.hpp"
@@ -41,6 +42,11 @@ hipError_t launch_stream_read(const void* p, size_t bytes, unsigned long long* s
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, int grid, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, unsigned long long n, uint32_t v, hipStream_t st);
 hipError_t launch_count_steps(const uint32_t* trace, unsigned long long n, unsigned long long* out, hipStream_t st);
+hipError_t launch_inc_transport(const IncLaunch& a, int grid, hipStream_t st);
+hipError_t inc_transport_occupancy(int* blocks_per_cu);
+hipError_t launch_inc_inspect(const IncNucleus* nuclei, const int32_t* element, const double* t,
+                              const unsigned long long* uid, const uint32_t* ks, int n, uint64_t seed, int evap,
+                              IncResult* res, IncParticle* out, hipStream_t st);
 }  // namespace pmc
 
 using namespace pmc;
@@ -128,6 +134,13 @@ struct pmc_ctx {
     DevBuf<float> d_spots;
     DevBuf<PlanDesc> d_plans;
     DevBuf<uint32_t> d_trace, d_trace_epochs;   // roofline replay: address trace (kTrace)
+    // intranuclear cascade (PMC_INC): the six target nuclei, the event list
+    // of a generation (IncEvent) and each generation's event count
+    DevBuf<IncNucleus> d_inc_nuc;
+    DevBuf<IncEvent> d_inc_ev;
+    DevBuf<unsigned long long> d_inc_count;
+    int inc_grid = 0;
+    hipEvent_t ev_inc[2 * kMaxGenerations] = {};
     DevBuf<unsigned long long> d_sink;
     unsigned long long* h_pinned = nullptr;   // pinned read-back area
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -217,7 +230,7 @@ bool params_ok(const pmc_params& p, std::string& why)
     if (!(p.f_mcs >= 0.0 && p.f_mcs < 10.0)) { why = "f_mcs out of range"; return false; }
     if (!(p.s_min_cm > 0.0 && p.s_min_cm < 1.0)) { why = "s_min_cm out of range"; return false; }
     if (p.k_batches < 2 || p.k_batches > 64) { why = "k_batches must be in [2, 64]"; return false; }
-    if (p.flags & ~31u) { why = "unknown flags"; return false; }
+    if (p.flags & ~(31u | (uint32_t)PMC_INC)) { why = "unknown flags"; return false; }
     if (p.block_threads != 0 && (p.block_threads < 64 || p.block_threads > 1024 || p.block_threads % 64))
     { why = "block_threads must be 0 or a multiple of 64 in [64, 1024]"; return false; }
     if (p.blocks_per_cu < 0 || p.blocks_per_cu > 64) { why = "blocks_per_cu out of range"; return false; }
@@ -352,6 +365,22 @@ float u2f(uint32_t u)
     float f;
     std::memcpy(&f, &u, 4);
     return f;
+}
+
+// The cascade's target nuclei on the device and the event kernel's grid
+// (built once per context, on the first run or inspection that needs them).
+pmc_status ensure_inc(pmc_ctx* c)
+{
+    if (c->d_inc_nuc.p && c->inc_grid > 0) return PMC_OK;
+    std::vector<IncNucleus> nu(kIncTargets);
+    for (int e = 1; e <= kIncTargets; ++e) build_inc_nucleus(e, &nu[e - 1]);
+    HIPCHK(c->d_inc_nuc.ensure(kIncTargets), "alloc nuclei");
+    HIPCHK(hipMemcpy(c->d_inc_nuc.p, nu.data(), kIncTargets * sizeof(IncNucleus), hipMemcpyHostToDevice),
+           "upload nuclei");
+    int per_cu = 0;
+    HIPCHK(inc_transport_occupancy(&per_cu), "cascade kernel occupancy");
+    c->inc_grid = c->num_cu * std::max(1, std::min(per_cu, 4));
+    return PMC_OK;
 }
 
 struct RunResult {
@@ -585,6 +614,18 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
         trace->probes = a.cache_probes;
         trace->lanes = lanes;
     }
+    // non-elastic events by the intranuclear cascade: one event list per
+    // generation, worked by the cascade kernel right after the transport
+    const bool inc = (a.flags & kInc) != 0u;
+    if (inc) {
+        pmc_status si = ensure_inc(c);
+        if (si != PMC_OK) return si;
+        HIPCHK(c->d_inc_ev.ensure(cap), "alloc event list");
+        HIPCHK(c->d_inc_count.ensure(kMaxGenerations), "alloc event counters");
+        HIPCHK(launch_zero(c->d_inc_count.p, kMaxGenerations * 8, st), "zero event counters");
+        a.inc_ev = c->d_inc_ev.p;
+        a.inc_cap = cap;
+    }
     const uint32_t run_flags = a.flags;
     int gens = 0;
     unsigned long long produced_total = 0, overflow_n = 0;
@@ -610,9 +651,20 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
                 a.q_in = c->d_q[gidx & 1].p;
                 a.q_out = c->d_q[(gidx + 1) & 1].p;
                 a.flags = run_flags | (trace && gidx == 0 ? kTrace : 0u);
+                a.inc_count = inc ? c->d_inc_count.p + gidx : nullptr;
                 HIPCHK(hipEventRecord(c->ev_gen[2 * gidx], st), "event");
                 HIPCHK(launch_transport(a, multi, grid, block, lds, st), "transport launch");
                 HIPCHK(hipEventRecord(c->ev_gen[2 * gidx + 1], st), "event");
+                if (inc) {
+                    // this generation's events; their protons join the next
+                    // generation's queue
+                    IncLaunch il{c->d_inc_ev.p, c->d_inc_count.p + gidx, cap, c->d_inc_nuc.p, c->d_plans.p,
+                                 np, K, let ? 1 : 0, a.q_out, cap, &c->d_gc.p[2 * (gidx + 1)],
+                                 c->d_ledger.p, c->d_counters.p};
+                    HIPCHK(hipEventRecord(c->ev_inc[2 * gidx], st), "event");
+                    HIPCHK(launch_inc_transport(il, c->inc_grid, st), "cascade launch");
+                    HIPCHK(hipEventRecord(c->ev_inc[2 * gidx + 1], st), "event");
+                }
             }
             launched = g1;
             // produced counts of generations g0+1 .. g1: words 2(g0+1) .. 2 g1
@@ -648,12 +700,23 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
     HIPCHK(hipStreamSynchronize(st), "run");
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1), "event time");
-    double transport_ms = 0.0, first_ms = 0.0;
+    double transport_ms = 0.0, first_ms = 0.0, inc_ms = 0.0;
     for (int gidx = 0; gidx < launched; ++gidx) {
         float t = 0.f;
         HIPCHK(hipEventElapsedTime(&t, c->ev_gen[2 * gidx], c->ev_gen[2 * gidx + 1]), "event time");
         transport_ms += t;
         if (gidx == 0) first_ms = t;
+        if (inc) {
+            HIPCHK(hipEventElapsedTime(&t, c->ev_inc[2 * gidx], c->ev_inc[2 * gidx + 1]), "event time");
+            inc_ms += t;
+        }
+    }
+    if (inc && launched > 0) {
+        // events beyond the list's capacity were counted as overflow
+        std::vector<unsigned long long> ec(launched);
+        HIPCHK(hipMemcpy(ec.data(), c->d_inc_count.p, 8 * (size_t)launched, hipMemcpyDeviceToHost), "read events");
+        for (int gidx = 0; gidx < launched; ++gidx)
+            if (ec[gidx] > cap) overflow_n += ec[gidx] - cap;
     }
     if (rr) {
         rr->transport_ms = transport_ms;
@@ -698,6 +761,10 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
             sm->first_launch_ms = first_ms;
             sm->generations = gens;
             sm->launches = launched;
+            sm->inc_events = cp[kCtrIncEvents];
+            sm->inc_secondaries = cp[kCtrIncSecondaries];
+            sm->inc_collisions = cp[kCtrIncCollisions];
+            sm->inc_ms = inc_ms;
         }
     }
     if (c->h_pinned[led_words + kCtrAborted] != 0)
@@ -879,7 +946,7 @@ pmc_status pmc_create(pmc_ctx** out, int device, const pmc_params* p)
         return PMC_ERR_DEVICE;
     }
     for (int i = 0; i < 2 * kMaxGenerations; ++i)
-        if ((e = hipEventCreate(&c->ev_gen[i])) != hipSuccess) {
+        if ((e = hipEventCreate(&c->ev_gen[i])) != hipSuccess || (e = hipEventCreate(&c->ev_inc[i])) != hipSuccess) {
             g_create_error = std::string("device setup: ") + hipGetErrorString(e);
             pmc_destroy(c);
             return PMC_ERR_DEVICE;
@@ -931,8 +998,10 @@ pmc_status pmc_destroy(pmc_ctx* c)
     if (c->h_pinned) (void)hipHostFree(c->h_pinned);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
-    for (int i = 0; i < 2 * kMaxGenerations; ++i)
+    for (int i = 0; i < 2 * kMaxGenerations; ++i) {
         if (c->ev_gen[i]) (void)hipEventDestroy(c->ev_gen[i]);
+        if (c->ev_inc[i]) (void)hipEventDestroy(c->ev_inc[i]);
+    }
     delete c;   // the DevBuf destructors release the remaining device buffers
     return PMC_OK;
 }
@@ -1240,6 +1309,49 @@ pmc_status pmc_roofline_replay(pmc_ctx* c, const pmc_spot* spots, int n_spots, u
     out->block_threads = tr.block;
     out->cache_slots = tr.slots;
     out->epoch_steps = tr.epoch_iters;
+    return PMC_OK;
+}
+
+static_assert(sizeof(pmc_inc_result) == sizeof(IncResult), "pmc_inc_result mirrors IncResult");
+static_assert(sizeof(pmc_inc_particle) == sizeof(IncParticle), "pmc_inc_particle mirrors IncParticle");
+
+pmc_status pmc_inc_events(pmc_ctx* c, const int32_t* element, const double* t_mev, const uint64_t* uid,
+                          const uint32_t* ks, int32_t n, uint64_t seed, int32_t evaporate, pmc_inc_result* results,
+                          pmc_inc_particle* particles)
+{
+    if (!c) return PMC_ERR_ARG;
+    if (n < 0 || (n > 0 && (!element || !t_mev || !uid || !ks || !results || !particles)))
+        return fail(c, PMC_ERR_ARG, "NULL event arrays or outputs, or n < 0");
+    for (int i = 0; i < n; ++i) {
+        if (element[i] < 1 || element[i] > kIncTargets) return fail(c, PMC_ERR_ARG, "element outside 1..6");
+        if (!(t_mev[i] > 0.0 && t_mev[i] <= 1000.0)) return fail(c, PMC_ERR_RANGE, "kinetic energy outside (0, 1000] MeV");
+    }
+    if (n == 0) return PMC_OK;
+    HIPCHK(hipSetDevice(c->device), "set device");
+    pmc_status s = ensure_inc(c);
+    if (s != PMC_OK) return s;
+    DevBuf<int32_t> d_el;
+    DevBuf<double> d_t;
+    DevBuf<unsigned long long> d_uid;
+    DevBuf<uint32_t> d_ks;
+    DevBuf<IncResult> d_res;
+    DevBuf<IncParticle> d_out;
+    HIPCHK(d_el.ensure(n), "alloc events");
+    HIPCHK(d_t.ensure(n), "alloc events");
+    HIPCHK(d_uid.ensure(n), "alloc events");
+    HIPCHK(d_ks.ensure(n), "alloc events");
+    HIPCHK(d_res.ensure(n), "alloc results");
+    HIPCHK(d_out.ensure((size_t)n * kIncMaxOut), "alloc particles");
+    HIPCHK(hipMemcpy(d_el.p, element, 4 * (size_t)n, hipMemcpyHostToDevice), "upload events");
+    HIPCHK(hipMemcpy(d_t.p, t_mev, 8 * (size_t)n, hipMemcpyHostToDevice), "upload events");
+    HIPCHK(hipMemcpy(d_uid.p, uid, 8 * (size_t)n, hipMemcpyHostToDevice), "upload events");
+    HIPCHK(hipMemcpy(d_ks.p, ks, 4 * (size_t)n, hipMemcpyHostToDevice), "upload events");
+    HIPCHK(launch_inc_inspect(c->d_inc_nuc.p, d_el.p, d_t.p, d_uid.p, d_ks.p, n, seed, evaporate, d_res.p, d_out.p,
+                              nullptr), "cascade launch");
+    HIPCHK(hipDeviceSynchronize(), "cascade");
+    HIPCHK(hipMemcpy(results, d_res.p, sizeof(IncResult) * (size_t)n, hipMemcpyDeviceToHost), "read results");
+    HIPCHK(hipMemcpy(particles, d_out.p, sizeof(IncParticle) * (size_t)n * kIncMaxOut, hipMemcpyDeviceToHost),
+           "read particles");
     return PMC_OK;
 }
 

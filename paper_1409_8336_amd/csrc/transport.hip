@@ -18,6 +18,7 @@
 
 #include "device.hpp"
 #include "cache.hpp"
+#include "rng.hpp"
 
 // Multiply-adds are fused only where one source expression holds both
 // (not across statements after inlining): the single-plan and batched
@@ -101,35 +102,6 @@ DEV float inv_erf(float x)
     }
     return p * x;
 }
-
-// Philox4x32-10 (Salmon et al. 2011); key = run seed, counter = (uid, k, tag)
-template <bool kScalarKey = false>
-DEV uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1)
-{
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        if (r) {
-            k0 += 0x9E3779B9u;
-            k1 += 0xBB67AE85u;
-            // a key shared by the wave stays a pair of per-round scalar adds
-            // (precomputed and hoisted out of the step loop, the ten round
-            // keys only spill to VGPR lanes)
-            if constexpr (kScalarKey) asm volatile("" : "+s"(k0), "+s"(k1));
-        }
-        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
-        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
-        c1 = (uint32_t)p1;
-        c3 = (uint32_t)p0;
-        c0 = n0;
-        c2 = n2;
-    }
-    return make_uint4(c0, c1, c2, c3);
-}
-
-// strictly inside (0,1), exactly representable in float
-DEV float u01(uint32_t x) { return ((float)(x >> 9) + 0.5f) * (1.0f / 8388608.0f); }
 
 DEV int mbcnt(unsigned long long m)
 {
@@ -318,6 +290,9 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
         L->n_spots = a.n_spots;
         L->loc_cap = a.loc_cap;
         L->q_loc = a.q_loc + (size_t)blockIdx.x * (size_t)a.loc_cap * kLocEntryWords;
+        L->inc_ev = a.inc_ev;
+        L->inc_count = a.inc_count;
+        L->inc_cap = a.inc_cap;
     }
     __syncthreads();
     const PlanDesc* pds = reinterpret_cast<const PlanDesc*>(lds + a.pd_offset);
@@ -911,6 +886,11 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
         bool recoil = false, ev_el = false, ev_ne = false;
         uint32_t ks = k - 1u;
         int sec_row = 0;
+        // flag PMC_INC: the event goes to the cascade kernel's list
+        bool inc_ev = false;
+        int inc_el = 0;
+        float inc_t = 0.f;
+        unsigned long long inc_vi = 0;
         if (pend) {
             pend = false;
             const unsigned long long vi = ((unsigned long long)vz * P.ny(plan) + vy) * P.nx(plan) + vx;
@@ -1014,6 +994,14 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
                     } else {
                         mfp = -fln(u01(r3.w));
                     }
+                } else if (kOpt && (flags & kInc)) {
+                    // non-elastic, intranuclear cascade: the event is listed
+                    // for the cascade kernel, which emits the secondaries
+                    inc_ev = true;
+                    inc_el = el;
+                    inc_t = T;
+                    inc_vi = vi;
+                    alive = false;
                 } else {
                     // non-elastic: secondary protons from the per-nucleus table
                     const int nu = el - 1;
@@ -1065,6 +1053,31 @@ __global__ void __launch_bounds__(1024) transport_kernel(KernelArgs a)
         }
         n_el += ev_el;
         n_ne += ev_ne;
+        if constexpr (kOpt) {
+            // the wave's cascade events to the generation's list, one
+            // reservation per wave
+            const unsigned long long bm = __ballot(inc_ev);
+            if (bm != 0ull) {
+                unsigned long long base = 0;
+                if (lane == 0) base = atomicAdd(L->inc_count, (unsigned long long)__popcll(bm));
+                base = bcast0(base);
+                if (inc_ev) {
+                    const unsigned long long idx = base + (unsigned long long)mbcnt(bm);
+                    if (idx < L->inc_cap) {
+                        GLOBAL u32x4* e4 = reinterpret_cast<GLOBAL u32x4*>(
+                            reinterpret_cast<GLOBAL unsigned char*>(gbl(L->inc_ev)) + idx * 64ull);
+                        e4[0] = u32x4{__float_as_uint(ox), __float_as_uint(oy), __float_as_uint(oz),
+                                      __float_as_uint(odx)};
+                        e4[1] = u32x4{__float_as_uint(ody), __float_as_uint(odz), __float_as_uint(inc_t),
+                                      __float_as_uint(w)};
+                        e4[2] = u32x4{uid_lo, uid_hi, batch, plan};
+                        e4[3] = u32x4{ks, (uint32_t)inc_el, (uint32_t)inc_vi, (uint32_t)(inc_vi >> 32)};
+                    } else {
+                        acc_ovf += (double)w * (double)inc_t;
+                    }
+                }
+            }
+        }
         // append emitted protons: to the workgroup's own queue (entries
         // lbase + i while below its capacity), what does not fit to the next
         // generation's queue
@@ -1412,7 +1425,10 @@ const void* kernel_for(bool multi, bool opt)
 }
 }  // namespace
 
-bool transport_needs_options(uint32_t flags) { return (flags & (kScoreLet | kVavilov | kMoliere | kTrace)) != 0u; }
+bool transport_needs_options(uint32_t flags)
+{
+    return (flags & (kScoreLet | kVavilov | kMoliere | kTrace | kInc)) != 0u;
+}
 
 hipError_t launch_transport(const KernelArgs& a, bool multi, int grid, int block, size_t lds_bytes,
                             hipStream_t s)

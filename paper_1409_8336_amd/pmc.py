@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libpmc.so")
 
 PMC_OK, PMC_ERR_ARG, PMC_ERR_RANGE, PMC_ERR_NOMEM = 0, -1, -2, -3
 PMC_ERR_DEVICE, PMC_ERR_QUEUE_OVERFLOW, PMC_ERR_STATE = -4, -5, -6
-PMC_NO_STRAGGLE, PMC_NO_MCS, PMC_NO_NUCLEAR, PMC_VAVILOV, PMC_MOLIERE = 1, 2, 4, 8, 16
+PMC_NO_STRAGGLE, PMC_NO_MCS, PMC_NO_NUCLEAR, PMC_VAVILOV, PMC_MOLIERE, PMC_INC = 1, 2, 4, 8, 16, 64
+INC_MAX_OUT = 96   # emitted particles per cascade event
 MOL_SHAPE = (13, 161)     # [1/B = 1/20 + j (2/9 - 1/20)/12][q = k/8]
 VAV_SHAPE = (5, 31, 97)   # [beta^2 = k/10][log10 kappa = -2 + j/10][z = -6 + i/8]
 
@@ -27,7 +28,7 @@ EXPORTS = ("pmc_default_params", "pmc_create", "pmc_destroy", "pmc_last_error",
            "pmc_inspect_tables", "pmc_atomic_probe", "pmc_load_geometry_slot", "pmc_run_plans",
            "pmc_geometry_density", "pmc_version", "pmc_run_spots_let", "pmc_run_spots_let_dev",
            "pmc_vavilov_table", "pmc_moliere_table", "pmc_plan_launch", "pmc_roofline_replay",
-           "pmc_stream_probe")
+           "pmc_stream_probe", "pmc_inc_events", "pmc_inc_nucleus", "pmc_inc_width")
 
 
 class PMCError(RuntimeError):
@@ -75,7 +76,20 @@ class pmc_summary(C.Structure):
                 ("block_threads", C.c_int32), ("grid_blocks", C.c_int32),
                 ("cache_slots", C.c_int32), ("epoch_steps", C.c_int32),
                 ("cache_flush_atomics", C.c_uint64), ("refill_lanes", C.c_int32),
-                ("batch_events", C.c_int32), ("first_launch_ms", C.c_double)]
+                ("batch_events", C.c_int32), ("first_launch_ms", C.c_double),
+                ("inc_events", C.c_uint64), ("inc_secondaries", C.c_uint64),
+                ("inc_collisions", C.c_uint64), ("inc_ms", C.c_double)]
+
+
+class pmc_inc_result(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in ("n_out", "n_coll", "n_blocked", "attempts", "n_esc", "compound",
+                                         "z_res", "a_res", "z_fin", "a_fin", "reserved0", "reserved1")] + [
+        (n, C.c_double) for n in ("e_star", "e_star_sum", "e_star_fin", "binding")]
+
+
+class pmc_inc_particle(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("stage", C.c_int32), ("id", C.c_uint32), ("reserved", C.c_int32),
+                ("t_mev", C.c_double), ("dir", C.c_double * 3)]
 
 
 class pmc_launch_query(C.Structure):
@@ -161,10 +175,15 @@ def lib():
                                       C.c_int32]
         L.pmc_roofline_replay.argtypes = [vp, vp, i32, u64, u64, vp, C.POINTER(pmc_replay_result)]
         L.pmc_stream_probe.argtypes = [vp, u64, vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.pmc_inc_events.argtypes = [vp, vp, vp, vp, vp, C.c_int32, u64, C.c_int32, vp, vp]
+        L.pmc_inc_nucleus.argtypes = [C.c_int32, vp, C.c_int32]
+        L.pmc_inc_width.argtypes = [C.c_int32, C.c_int32, C.c_double, C.c_int32, C.POINTER(C.c_double),
+                                    C.POINTER(C.c_double)]
         L.pmc_version.restype = C.c_char_p
         for name in EXPORTS:
-            if name not in ("pmc_last_error", "pmc_version"):
+            if name not in ("pmc_last_error", "pmc_version", "pmc_inc_width"):
                 getattr(L, name).restype = C.c_int
+        L.pmc_inc_width.restype = C.c_double
         _lib = L
     return _lib
 
@@ -434,6 +453,41 @@ def pmc_stream_probe(ctx, n_bytes, stream=None):
     r, cp = C.c_double(), C.c_double()
     _check(ctx, lib().pmc_stream_probe(ctx, int(n_bytes), _stream_handle(stream), C.byref(r), C.byref(cp)))
     return r.value, cp.value
+
+
+def pmc_inc_events(ctx, element, t_mev, uid, ks, seed, evaporate=True):
+    """Cascade and evaporation of n non-elastic events on the GPU.  Returns
+    (results: list of dicts of pmc_inc_result fields, particles: structured
+    array [n][INC_MAX_OUT] with kind, stage, id, t_mev, dir)."""
+    el = np.ascontiguousarray(element, dtype=np.int32).ravel()
+    n = el.size
+    t = np.ascontiguousarray(np.broadcast_to(np.asarray(t_mev, np.float64), (n,)))
+    u = np.ascontiguousarray(np.broadcast_to(np.asarray(uid, np.uint64), (n,)))
+    k = np.ascontiguousarray(np.broadcast_to(np.asarray(ks, np.uint32), (n,)))
+    res = (pmc_inc_result * max(n, 1))()
+    pdt = np.dtype([("kind", np.int32), ("stage", np.int32), ("id", np.uint32), ("reserved", np.int32),
+                    ("t_mev", np.float64), ("dir", np.float64, 3)])
+    parts = np.zeros((max(n, 1), INC_MAX_OUT), pdt)
+    _check(ctx, lib().pmc_inc_events(ctx, _ptr(el), _ptr(t), _ptr(u), _ptr(k), n, int(seed),
+                                     1 if evaporate else 0, C.cast(res, C.c_void_p), _ptr(parts)))
+    out = [{f[0]: getattr(res[i], f[0]) for f in pmc_inc_result._fields_} for i in range(n)]
+    return out, parts[:n]
+
+
+def pmc_inc_nucleus(element):
+    """The cascade's target nucleus (host only): shell radii, densities and
+    Fermi energies of protons and neutrons, the Woods-Saxon radius and A."""
+    out = np.zeros(78, np.float64)
+    _check(None, lib().pmc_inc_nucleus(int(element), _ptr(out), out.size))
+    return {"r": out[:16], "rho_p": out[16:31], "rho_n": out[31:46], "tf_p": out[46:61],
+            "tf_n": out[61:76], "radius_ws": out[76], "a": int(out[77])}
+
+
+def pmc_inc_width(z, a, e_star, kind):
+    """(relative evaporation width, separation energy, barrier), host only."""
+    sep, bar = C.c_double(), C.c_double()
+    w = lib().pmc_inc_width(int(z), int(a), float(e_star), int(kind), C.byref(sep), C.byref(bar))
+    return w, sep.value, bar.value
 
 
 def pmc_geometry_density(ctx, geometry_id, d_rho, stream=None):

@@ -5,6 +5,8 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 from paper_1409_8336_amd import pmc, unet
@@ -14,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared(header="pmc.h"):
     text = open(os.path.join(ROOT, "include", header)).read()
-    return sorted(set(re.findall(r"^\s*(?:pmc_status|const char\*)\s+(pmc_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:pmc_status|const char\*|double)\s+(pmc_\w+)\s*\(", text, re.M)))
 
 
 @pytest.fixture(scope="module")
@@ -46,7 +48,7 @@ def test_create_rejects_bad_params_before_device(lib):
     h = C.c_void_p()
     assert lib.pmc_create(None, 0, None) == pmc.PMC_ERR_ARG
     for bad in (dict(k_batches=1), dict(k_batches=65), dict(block_threads=100),
-                dict(s_min_cm=0.0), dict(flags=32), dict(flags=64)):
+                dict(s_min_cm=0.0), dict(flags=32), dict(flags=128)):
         p = pmc.pmc_default_params(**bad)
         assert lib.pmc_create(C.byref(h), 0, C.byref(p)) == pmc.PMC_ERR_ARG
         assert pmc.pmc_last_error(None) != ""
@@ -116,3 +118,42 @@ def test_engine_moliere_table_matches_oracle():
     assert np.max(np.abs(eng - ora)) < 5e-4
     buf = (C.c_float * 16)()
     assert pmc.lib().pmc_moliere_table(buf, 16) == pmc.PMC_ERR_ARG
+
+
+def test_cascade_nucleus_matches_the_oracle(lib):
+    """The engine's Woods-Saxon shells (Gauss-Legendre) against the oracle's
+    (Simpson): shell radii, densities of both species and Fermi energies."""
+    from oracle import oracle as O
+    for el in range(1, 7):
+        e = pmc.pmc_inc_nucleus(el)
+        o = O.inc_nucleus(el)
+        assert e["a"] == o["a"]
+        np.testing.assert_allclose(e["r"], o["r"], rtol=1e-14, atol=0)
+        assert abs(e["radius_ws"] - o["radius_ws"]) < 1e-13
+        for k in ("rho_p", "rho_n", "tf_p", "tf_n"):
+            np.testing.assert_allclose(e[k], o[k], rtol=1e-9, err_msg="element %d %s" % (el, k))
+    assert lib.pmc_inc_nucleus(0, None, 78) == pmc.PMC_ERR_ARG
+    assert lib.pmc_inc_nucleus(7, None, 78) == pmc.PMC_ERR_ARG
+
+
+def test_evaporation_widths_match_the_oracle(lib):
+    """The engine's closed-form level-density integral against the oracle's
+    quadrature, with separation energies and barriers, over open and closed
+    channels of light and heavy residuals."""
+    from oracle import oracle as O
+    rng = np.random.default_rng(5)
+    cases = [(8, 17, 30.0), (22, 49, 120.0), (6, 13, 9.0), (20, 41, 2.0), (15, 32, 0.3), (3, 6, 40.0)]
+    cases += [(int(z), int(z) + int(rng.integers(0, 8)), float(rng.uniform(0.1, 200.0)))
+              for z in rng.integers(3, 23, size=40)]
+    n_open = 0
+    for z, a, es in cases:
+        for kind in range(6):
+            we, se, be = pmc.pmc_inc_width(z, a, es, kind)
+            wo, so, bo = O.evap_width(z, a, es, kind)
+            if wo == 0.0:
+                assert we == 0.0, (z, a, es, kind)
+                continue
+            n_open += 1
+            assert abs(se - so) < 1e-9 and abs(be - bo) < 1e-12, (z, a, es, kind)
+            assert abs(we / wo - 1.0) < 1e-8, (z, a, es, kind, we, wo)
+    assert n_open > 100
