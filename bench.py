@@ -294,6 +294,9 @@ def main():
                          "at 160x128x128 (inference and training step)")
     ap.add_argument("--let-steps", type=int, default=3,
                     help="field workload: also time this many runs with LET_d scored (0 = skip)")
+    ap.add_argument("--inc-steps", type=int, default=2,
+                    help="field workload: also time this many runs with non-elastic events by the "
+                         "intranuclear cascade (PMC_INC; 0 = skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device copy (counter calibration)")
     ap.add_argument("--param", action="append", default=[], metavar="NAME=VALUE",
@@ -465,6 +468,40 @@ def main():
             "steps": args.let_steps,
         }
         del d_let
+    # the same workload with non-elastic events by the intranuclear cascade
+    # and evaporation (Sec. II.A.4) instead of the secondary tables
+    if args.inc_steps > 0:
+        params = dict(args.engine_params)
+        params["flags"] = int(params.get("flags", 0)) | pmc.PMC_INC
+        ei = pmc.Engine(0, **params)
+        ei.load_physics(synth.nuclear_data())
+        ei.load_geometry(cfg["hu"], cfg["voxel_cm"], synth.material_table())
+        ei.run_spots_dev(cfg["spots"], cfg["n_histories"], cfg["seed"], d_dose, d_var, stream)
+        torch.cuda.synchronize()
+        isums = []
+        t0 = time.perf_counter()
+        for i in range(args.inc_steps):
+            isums.append(ei.run_spots_dev(cfg["spots"], cfg["n_histories"], cfg["seed"] + i, d_dose, d_var,
+                                          stream))
+        torch.cuda.synchronize()
+        inc_elapsed = time.perf_counter() - t0
+        ei.close()
+        k = args.inc_steps
+        out["inc"] = {
+            "histories_per_s": k * cfg["n_histories"] / inc_elapsed,
+            "rate_vs_tables": (k * cfg["n_histories"] / inc_elapsed) / (n_tot / elapsed),
+            "ms_per_step": 1e3 * inc_elapsed / k,
+            "transport_ms_per_step": sum(s["transport_ms"] for s in isums) / k,
+            "cascade_ms_per_step": sum(s["inc_ms"] for s in isums) / k,
+            "events_per_step": sum(s["inc_events"] for s in isums) / k,
+            "cascade_protons_per_step": sum(s["inc_secondaries"] for s in isums) / k,
+            "nn_collisions_per_step": sum(s["inc_collisions"] for s in isums) / k,
+            "generations": isums[-1]["generations"],
+            "launches_per_step": sum(s["launches"] for s in isums) / k,
+            "ledger_residual_max": max(abs(s["incident"] - s["deposited"] - s["escaped"] - s["neutral"]
+                                           - s["overflow"]) / s["incident"] for s in isums),
+            "steps": k,
+        }
     # the same run through host buffers: spots in, dose and variance copied
     # back over PCIe (context only; not the headline value)
     t0 = time.perf_counter()

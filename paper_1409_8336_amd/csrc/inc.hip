@@ -447,11 +447,12 @@ __host__ __device__ int cascade(const IncNucleus& nu, double t_in, const Stream&
 }
 
 // Evaporation of nucleus (z, a) at excitation es until no channel is open,
-// A <= 4 or the event holds kIncMaxOut particles: channel by its width,
-// energy above the barrier y in (0, X] with density ~ (X - y)... of the
-// daughter's level density: y exp(2 sqrt(a (X - y))) sampled by rejection
-// from y = X sqrt(u) (when 2 sqrt(a X) < 2) or from a Gamma(2, sqrt(X/a))
-// proposal (otherwise), both dominating the density; direction isotropic.
+// A <= 4 or the event holds kIncMaxOut particles: the channel by its width;
+// the ejectile's kinetic energy above the barrier, y in (0, X], with density
+// ~ y exp(2 sqrt(a (X - y))) (the width's integrand, the daughter left at
+// X - y), by rejection from y = X sqrt(u) (when 2 sqrt(a X) < 2) or from a
+// Gamma(2, sqrt(X/a)) proposal (otherwise), both dominating the density;
+// direction isotropic.
 template <class Emit>
 __host__ __device__ void evaporate(int z, int a, double es, const Stream& st, IncResult& r, int& n_kept, Emit& emit)
 {
