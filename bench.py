@@ -145,6 +145,7 @@ def bench_plans(args):
                                                             "cache_slots", "epoch_steps", "refill_lanes",
                                                             "batch_events")},
            "transport_ms_per_step": sum(s[0]["transport_ms"] for s in all_sums) / args.steps,
+           "per_plan": _plans_alone(eng, plans, spec, all_sums[-1], elapsed / args.steps),
            "denoiser_per_plan": _plans_denoiser(plans, spec),
            "ledger_residual_max": max(abs(s["incident"] - s["deposited"] - s["escaped"] - s["neutral"]
                                           - s["overflow"]) / s["incident"]
@@ -152,6 +153,34 @@ def bench_plans(args):
     eng.close()
     print(json.dumps(out), flush=True)
     return 0
+
+
+def _plans_alone(eng, plans, spec, sums, batch_s):
+    """Every plan of the batch run on its own (a one-plan launch, after one
+    untimed run that also tunes its shape): its wall time and rate, beside
+    its share of the batch (the batch wall time split by the plans' steps).
+    The sum of the solo times over the batch time is what running the plans
+    together saves."""
+    import torch
+    from paper_1409_8336_amd import pmc
+    steps_all = sum(s["steps"] for s in sums)
+    rows, solo_total = [], 0.0
+    for i, (p, sp) in enumerate(zip(plans, spec)):
+        one = [dict(sp)]
+        pmc.pmc_run_plans(eng.ctx, one, 50 + i)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = pmc.pmc_run_plans(eng.ctx, one, 70 + i)[0]
+        torch.cuda.synchronize()
+        solo = time.perf_counter() - t0
+        solo_total += solo
+        rows.append({"grid": list(p["hu"].shape[::-1]), "spots": int(len(p["spots"])),
+                     "histories": int(p["n_histories"]), "solo_ms": 1e3 * solo,
+                     "solo_histories_per_s": p["n_histories"] / solo,
+                     "batch_share_ms": 1e3 * batch_s * sums[i]["steps"] / steps_all,
+                     "steps_per_history": r["steps"] / p["n_histories"]})
+    return {"plans": rows, "solo_total_ms": 1e3 * solo_total, "batch_ms": 1e3 * batch_s,
+            "batch_speedup_vs_one_by_one": solo_total / batch_s}
 
 
 def _plans_denoiser(plans, spec):
@@ -389,38 +418,41 @@ def main():
                                                    "epoch_steps", "refill_lanes", "batch_events")},
         "transport_ms_per_step": 1e3 * transport_s / args.steps,
         "ledger_residual_max": worst_res,
+        # roofline of the transport (SURVEY's protocol): its own address
+        # stream -- every step's 8-B voxel gather and 8-B FP64 tally add, in
+        # the traced run's order, grid, workgroups, lanes and epochs -- replayed
+        # without the physics; the slower of the gather replay and the faster
+        # of the direct and LDS-cached atomic replays is the achievable time
+        # of the method's memory operations.  frac = that time / the launch.
         "roofline": {
-            "bound": "hbm",
-            "achieved": achieved / 1e9,
-            "peak": HBM_PEAK / 1e9,
+            "bound": "atomic" if t_atom >= t_gather else "gather",
+            "achieved": ALG_BYTES_PER_STEP * rep["steps"] / (rep["transport_ms"] * 1e-3) / 1e9,
+            "peak": ALG_BYTES_PER_STEP * rep["steps"] / (t_mem * 1e-3) / 1e9,
             "unit": "GB/s",
-            "frac": achieved / HBM_PEAK,
+            "frac": t_mem / rep["transport_ms"],
             "traffic": traffic,
             "kernel": "transport_kernel",
+            "basis": "replay of the transport's own gather and FP64-atomic address stream (16 B per step); "
+                     "peak = algorithmic bytes / replay time of the binding stream",
             "avg_launch_ms": 1e3 * transport_s / launches,
             "launches_per_step": launches / args.steps,
             "bytes_per_step": ALG_BYTES_PER_STEP,
-            "stream_read_gbs": stream_read_gbs,
-            # the memory/atomic roofline of the transport's own address stream:
-            # every step's 8-B voxel gather and 8-B FP64 tally add replayed in
-            # the traced run's order, grid, workgroups, lanes and epochs
             "replay": {
-                "frac": t_mem / rep["transport_ms"],
-                "binding": "tally atomics" if t_atom >= t_gather else "voxel gathers",
-                "frac_with_trace_stream": max(rep["gather_ms"], min(rep["atomic_ms"], rep["cached_atomic_ms"]))
-                                          / rep["transport_ms"],
-                "combined_frac": (rep["combined_ms"] - t_tr) / rep["transport_ms"],
                 "transport_ms": rep["transport_ms"],
                 "gather_ms": t_gather,
                 "atomic_ms": rep["atomic_ms"] - t_tr,
                 "cached_atomic_ms": rep["cached_atomic_ms"] - t_tr,
                 "combined_ms": rep["combined_ms"] - t_tr,
+                "combined_frac": (rep["combined_ms"] - t_tr) / rep["transport_ms"],
                 "trace_stream_ms": t_tr,
                 "steps_traced_frac": rep["steps_traced"] / rep["steps"],
-                "note": "replay times net of streaming the 4-byte-per-lane-iteration trace "
-                        "(trace_stream_ms); frac = max(gathers, faster of direct or cached "
-                        "atomics) / transport launch",
+                "note": "replay times net of streaming the 4-byte-per-lane-iteration trace",
             },
+            # the same launches against HBM: 16 B per step over the average
+            # launch time, against 8 TB/s (HBM does not bind)
+            "hbm": {"achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK, "stream_read_gbs": stream_read_gbs,
+                    "traffic": traffic},
         },
         "atomic_roofline": {
             "deposits_per_step": deposits_tot / args.steps,

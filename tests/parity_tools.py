@@ -67,19 +67,36 @@ def compare(a_dose, a_var, b_dose, b_var, rho, voxel_cm, wa, wb):
         "all_within_3sigma": bool(np.all(np.abs(z) <= 3.0)),
         "z_absmax": float(np.abs(z).max()) if sel.any() else 0.0,
         "var_rel_median": float(np.median(vrel)),
+        "var_signed_median": float(np.median(va[pos] / vb[pos] - 1.0)) if pos.any() else 0.0,
         "var_rel_p99": float(np.percentile(vrel, 99)),
         "var_ratio_sum": float(va.sum() / vb.sum()) if vb.sum() > 0 else 1.0,
     }
 
 
-def assert_same_seed(m, var_median=0.02, var_p99=0.25):
+def assert_same_seed(m, k_batches=10):
     """Same-seed parity: every voxel at or above 10% of the maximum dose within
     3 sigma of the two variance estimates, and the GPU's per-voxel variance
-    equal to the oracle's (median and 99th percentile of the relative
-    difference; a missing K/(K-1) factor alone would put every voxel 10% off)."""
+    that of the oracle.
+
+    The two sides simulate the same histories, except those that a decision
+    taken in FP32 on one side and FP64 on the other turns onto another path;
+    where such histories deposit, a voxel's group tallies differ by
+    independent amounts, the spread of which the dose z-scores measure
+    (their SD, z_std, is the dose difference in units of sigma).  A group
+    tally that moves by e changes the 10-group variance estimate (Eq. 5) by
+    about 2 (D_b - mean) e, i.e. the voxel's variance by a relative amount of
+    SD 2 z_std / sqrt(K - 1).  So: the variance summed over the selected
+    voxels and the median of the per-voxel ratio agree within 2% (a missing
+    K/(K - 1) factor alone would move both by 11%), and the median and 99th
+    percentile of the absolute per-voxel difference stay within 1.5 and 6
+    times that divergence scale (plus 2% and 25% for rounding and counting
+    where nothing diverged)."""
     assert m["all_within_3sigma"], m
-    assert m["var_rel_median"] <= var_median and m["var_rel_p99"] <= var_p99, m
-    assert abs(m["var_ratio_sum"] - 1) <= var_median, m
+    scale = 2.0 * m["z_std"] / (k_batches - 1) ** 0.5
+    assert abs(m["var_ratio_sum"] - 1) <= 0.02, m
+    assert abs(m["var_signed_median"]) <= 0.02, m
+    assert m["var_rel_median"] <= 0.02 + 1.5 * scale, m
+    assert m["var_rel_p99"] <= 0.25 + 6.0 * scale, m
 
 
 def ledger_residual(s):
