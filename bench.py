@@ -326,6 +326,8 @@ def main():
     ap.add_argument("--inc-steps", type=int, default=2,
                     help="field workload: also time this many runs with non-elastic events by the "
                          "intranuclear cascade (PMC_INC; 0 = skip)")
+    ap.add_argument("--no-replay", action="store_true",
+                    help="field workload: skip the address-trace replay and the probes (counter runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device copy (counter calibration)")
     ap.add_argument("--param", action="append", default=[], metavar="NAME=VALUE",
@@ -375,6 +377,11 @@ def main():
     achieved = ALG_BYTES_PER_STEP * steps_tot / transport_s
     # the transport's own address stream replayed without the physics, and
     # the plain-read bandwidth of this device
+    if args.no_replay:
+        print(json.dumps({"histories_per_s": n_tot / elapsed, "transport_ms_per_step": 1e3 * transport_s / args.steps,
+                          "steps_per_step": steps_tot / args.steps}), flush=True)
+        eng.close()
+        return 0
     rep = pmc.pmc_roofline_replay(eng.ctx, cfg["spots"], cfg["n_histories"], cfg["seed"], stream)
     read_ms, _ = pmc.pmc_stream_probe(eng.ctx, 4 << 30, stream)
     stream_read_gbs = (4 << 30) / read_ms / 1e6
