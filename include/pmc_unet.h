@@ -103,6 +103,20 @@ pmc_status pmc_nn_conv3d_forward(const uint16_t* d_x, const uint16_t* d_w, const
 pmc_status pmc_nn_conv3d_backward_data(const uint16_t* d_dy, const uint16_t* d_w, uint16_t* d_dx,
                                        int n, int d, int h, int w, int cin, int cout,
                                        void* hip_stream);
+/* The data gradient of pmc_nn_conv3d_backward_data, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving and training
+ * loops that forbid hipMalloc): the same kernels, with the flipped-weight
+ * workspace (cin x round_up(27 cout, 32) BF16 entries) in a device-resident
+ * array of 2^20 entries (2 MiB) that the library holds on every GPU it runs
+ * on until the process ends.  No hipMalloc, hipFree or allocating library
+ * call; stream-ordered on hip_stream, does not synchronise.  Every call on a
+ * GPU shares that GPU's workspace, so calls that overlap on one GPU (other
+ * streams, other threads) race: order them.  Errors: PMC_ERR_ARG (as
+ * pmc_nn_conv3d_backward_data), PMC_ERR_RANGE (cin * round_up(27 cout, 32)
+ * above 2^20, e.g. cin = cout = 256), PMC_ERR_DEVICE. */
+pmc_status pmc_nn_conv3d_backward_data_noalloc(const uint16_t* d_dy, const uint16_t* d_w, uint16_t* d_dx,
+                                               int n, int d, int h, int w, int cin, int cout,
+                                               void* hip_stream);
 pmc_status pmc_nn_conv3d_backward_weight(const uint16_t* d_x, const uint16_t* d_dy, float* d_dw,
                                          int n, int d, int h, int w, int cin, int cout,
                                          void* hip_stream);

@@ -5,6 +5,8 @@
 
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <random>
 #include <string>
@@ -44,9 +46,42 @@ hipError_t nn_f32_to_bf16(const float* a, uint16_t* b, size_t n, hipStream_t s);
 
 using namespace pmc;
 
+// the flipped-weight workspace of pmc_nn_conv3d_backward_data_noalloc (see
+// flip_scratch below): 2^20 BF16 entries, 2 MiB
+constexpr size_t kFlipScratchElems = size_t(1) << 20;
+static __device__ __align__(256) uint16_t scratch[kFlipScratchElems];
+
 namespace {
 
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+// Workspace of the data gradient that allocates nothing
+// (pmc_nn_conv3d_backward_data_noalloc): the flipped weights [cin][kpf] as
+// BF16, at most kFlipScratchElems entries (2 MiB), in a device-resident array
+// that every GPU the library runs on holds until the process ends.  Host code
+// never passes the array's name to a kernel (on the host it only stands for
+// the symbol): the address of each device's copy is looked up once per
+// device, with that device current, and used instead.
+
+std::mutex g_scratch_mu;
+std::map<int, uint16_t*> g_scratch_ptr;   // device -> address of its copy of scratch
+
+hipError_t flip_scratch(uint16_t** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it == g_scratch_ptr.end()) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return e != hipSuccess ? e : hipErrorInvalidSymbol;
+        it = g_scratch_ptr.emplace(dev, static_cast<uint16_t*>(ptr)).first;
+    }
+    *out = it->second;
+    return hipSuccess;
+}
 
 struct Conv {
     int cin, cout, kp, kpf;
@@ -491,6 +526,22 @@ pmc_status pmc_nn_conv3d_backward_data(const uint16_t* dy, const uint16_t* w, ui
     if (e == hipSuccess) e = nn_conv3d_fwd(dy, wf, nullptr, dx, n, d, h, wd, cout, cin, kpf, 0, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(wf);
+    return e == hipSuccess ? PMC_OK : PMC_ERR_DEVICE;
+}
+
+pmc_status pmc_nn_conv3d_backward_data_noalloc(const uint16_t* dy, const uint16_t* w, uint16_t* dx, int n, int d,
+                                               int h, int wd, int cin, int cout, void* stream)
+{
+    if (!dy || !w || !dx || n < 1 || d < 1 || h < 1 || wd < 1 || cin < 8 || cout < 8 || cin % 8 || cout % 8)
+        return PMC_ERR_ARG;
+    const int kp = round_up(27 * cin, 32), kpf = round_up(27 * cout, 32);
+    // the flipped weights must fit the device-resident workspace
+    if ((size_t)cin * (size_t)kpf > kFlipScratchElems) return PMC_ERR_RANGE;
+    uint16_t* wf = nullptr;
+    if (flip_scratch(&wf) != hipSuccess) return PMC_ERR_DEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = nn_flip_weights(w, wf, cin, cout, kp, kpf, s);
+    if (e == hipSuccess) e = nn_conv3d_fwd(dy, wf, nullptr, dx, n, d, h, wd, cout, cin, kpf, 0, s);
     return e == hipSuccess ? PMC_OK : PMC_ERR_DEVICE;
 }
 

@@ -16,6 +16,7 @@ EXPORTS = ("pmc_unet_create", "pmc_unet_destroy", "pmc_unet_last_error", "pmc_un
            "pmc_unet_forward_region",
            "pmc_unet_get_grads", "pmc_unet_zero_grads", "pmc_unet_adam_step", "pmc_unet_grad_norm",
            "pmc_nn_conv3d_forward", "pmc_nn_conv3d_backward_data", "pmc_nn_conv3d_backward_weight",
+           "pmc_nn_conv3d_backward_data_noalloc",
            "pmc_gamma_index", "pmc_denoise_disagreement")
 
 _ready = False
@@ -46,6 +47,7 @@ def lib():
         L.pmc_unet_grad_norm.argtypes = [vp, C.POINTER(C.c_double), vp]
         L.pmc_nn_conv3d_forward.argtypes = [vp, vp, vp, vp, i32, i32, i32, i32, i32, i32, i32, vp]
         L.pmc_nn_conv3d_backward_data.argtypes = [vp, vp, vp, i32, i32, i32, i32, i32, i32, vp]
+        L.pmc_nn_conv3d_backward_data_noalloc.argtypes = [vp, vp, vp, i32, i32, i32, i32, i32, i32, vp]
         L.pmc_nn_conv3d_backward_weight.argtypes = [vp, vp, vp, i32, i32, i32, i32, i32, i32, vp]
         L.pmc_gamma_index.argtypes = [vp, vp, i32, i32, i32, f32, f32, f32, f32, f32, f32, f32, f32,
                                       vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), vp]
@@ -203,6 +205,16 @@ def pmc_nn_conv3d_backward_data(dy, w, dx, stream=None):
     _check(None, lib().pmc_nn_conv3d_backward_data(_bf16(dy, "dy"), _bf16(w, "w"), _bf16(dx, "dx"),
                                                    n, d, h, wd, cin, cout,
                                                    _stream(stream, dy.device)))
+
+
+def pmc_nn_conv3d_backward_data_noalloc(dy, w, dx, stream=None):
+    """As pmc_nn_conv3d_backward_data, with the library's device-resident
+    workspace (no allocation; stream-ordered, no synchronisation)."""
+    n, d, h, wd, cout = dy.shape
+    cin = dx.shape[-1]
+    _check(None, lib().pmc_nn_conv3d_backward_data_noalloc(_bf16(dy, "dy"), _bf16(w, "w"), _bf16(dx, "dx"),
+                                                           n, d, h, wd, cin, cout,
+                                                           _stream(stream, dy.device)))
 
 
 def pmc_nn_conv3d_backward_weight(x, dy, dw, stream=None):
