@@ -105,9 +105,10 @@ def copy_probe():
     return 0
 
 
-def bench_plans(args):
+def bench_plans(args, leg=False):
     """Sixteen plans (grids 96^3..256x256x200, 200-3000 spots, 1e6-1e7
-    histories each) in one persistent launch per generation."""
+    histories each) in one persistent launch per generation.  leg: return
+    the result instead of printing it."""
     import torch
     from paper_1409_8336_amd import pmc, synth
     plans = synth.plan_set(n_plans=16, seed=100)
@@ -151,6 +152,8 @@ def bench_plans(args):
                                           - s["overflow"]) / s["incident"]
                                       for sums in all_sums for s in sums)}
     eng.close()
+    if leg:
+        return out
     print(json.dumps(out), flush=True)
     return 0
 
@@ -260,10 +263,11 @@ def unet_forward_flop(d, h, w):
     return sum(2 * 27 * ci * co * vox[l] for l, ci, co in convs)
 
 
-def bench_denoiser(args):
+def bench_denoiser(args, leg=False):
     """The denoiser at 160x128x128 (one volume): inference and one training
     step (forward, backward, Adam), with the MFMA roofline of the
-    convolutions: algorithmic FLOP / time against 2.5 PFLOP/s dense BF16."""
+    convolutions: algorithmic FLOP / time against 2.5 PFLOP/s dense BF16.
+    leg: return the result instead of printing it."""
     import torch
     import numpy as np
     from paper_1409_8336_amd import unet
@@ -305,6 +309,8 @@ def bench_denoiser(args):
                         "kernel": "whole forward (7 convolutions and the elementwise kernels)",
                         "flop_per_forward": fwd,
                         "train_achieved": 3 * fwd / t_train / 1e12}}
+    if leg:
+        return out
     print(json.dumps(out), flush=True)
     return 0
 
@@ -326,6 +332,8 @@ def main():
     ap.add_argument("--inc-steps", type=int, default=2,
                     help="field workload: also time this many runs with non-elastic events by the "
                          "intranuclear cascade (PMC_INC; 0 = skip)")
+    ap.add_argument("--no-legs", dest="legs", action="store_false",
+                    help="field workload: skip the 16-plan batch and denoiser legs")
     ap.add_argument("--no-replay", action="store_true",
                     help="field workload: skip the address-trace replay and the probes (counter runs)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -541,6 +549,20 @@ def main():
                                            - s["overflow"]) / s["incident"] for s in isums),
             "steps": k,
         }
+    # the other workloads, briefly, so that the same run records them: the
+    # uneven 16-plan batch (config 5) and the denoiser (config 4)
+    if args.legs:
+        import argparse as _ap
+        la = _ap.Namespace(**vars(args))
+        la.steps, la.warmup = 2, 1
+        pb = bench_plans(la, leg=True)
+        out["plans_batch"] = {k: pb[k] for k in ("value", "unit", "ms_per_step", "steps", "config",
+                                                  "launch_shape", "transport_ms_per_step", "per_plan",
+                                                  "denoiser_per_plan", "ledger_residual_max")}
+        la.steps = 5
+        dn = bench_denoiser(la, leg=True)
+        out["denoiser"] = {k: dn[k] for k in ("value", "unit", "ms_per_step", "train_step_ms", "config",
+                                               "roofline")}
     # the same run through host buffers: spots in, dose and variance copied
     # back over PCIe (context only; not the headline value)
     t0 = time.perf_counter()
