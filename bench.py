@@ -386,21 +386,24 @@ def main():
     # the transport's own address stream replayed without the physics, and
     # the plain-read bandwidth of this device
     if args.no_replay:
-        print(json.dumps({"histories_per_s": n_tot / elapsed, "transport_ms_per_step": 1e3 * transport_s / args.steps,
-                          "steps_per_step": steps_tot / args.steps}), flush=True)
-        eng.close()
-        return 0
-    rep = pmc.pmc_roofline_replay(eng.ctx, cfg["spots"], cfg["n_histories"], cfg["seed"], stream)
-    read_ms, _ = pmc.pmc_stream_probe(eng.ctx, 4 << 30, stream)
-    stream_read_gbs = (4 << 30) / read_ms / 1e6
+        # counter runs: the timed transport runs and the legs only
+        rep = {"trace_only_ms": 0.0, "gather_ms": 0.0, "atomic_ms": 0.0, "cached_atomic_ms": 0.0,
+               "combined_ms": 0.0, "transport_ms": 1e3 * transport_s / launches,
+               "steps": steps_tot // args.steps, "steps_traced": 0}
+        stream_read_gbs = None
+    else:
+        rep = pmc.pmc_roofline_replay(eng.ctx, cfg["spots"], cfg["n_histories"], cfg["seed"], stream)
+        read_ms, _ = pmc.pmc_stream_probe(eng.ctx, 4 << 30, stream)
+        stream_read_gbs = (4 << 30) / read_ms / 1e6
     t_tr = rep["trace_only_ms"]
     t_gather = rep["gather_ms"] - t_tr
     t_atom = min(rep["atomic_ms"], rep["cached_atomic_ms"]) - t_tr
-    t_mem = max(t_gather, t_atom)
+    t_mem = max(t_gather, t_atom) if not args.no_replay else 1e3 * transport_s / launches
     deposits_tot = sum(s["tally_atomics"] for s in sums)
     atomics_tot = sum(s["global_atomics"] for s in sums)
     flush_tot = sum(s["cache_flush_atomics"] for s in sums)
-    probe_ms = pmc.pmc_atomic_probe(eng.ctx, max(1, atomics_tot // args.steps), stream)
+    probe_ms = (pmc.pmc_atomic_probe(eng.ctx, max(1, atomics_tot // args.steps), stream) if not args.no_replay
+                else 1e3 * transport_s / args.steps)
     probe_rate = (atomics_tot / args.steps) / (probe_ms * 1e-3)
     atomic_rate = atomics_tot / transport_s
     traffic = None

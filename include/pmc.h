@@ -487,7 +487,8 @@ typedef struct {
     int32_t compound;
     int32_t z_res, a_res;    /* residual after the cascade */
     int32_t z_fin, a_fin;    /* after evaporation */
-    int32_t reserved[2];
+    int32_t n_flights;       /* flights (to a collision or a shell boundary) of all cascade particles */
+    int32_t reserved;
     double e_star;           /* residual excitation from the energy balance, MeV */
     double e_star_sum;       /* the same from the holes and trapped particles (a check) */
     double e_star_fin;       /* excitation left after evaporation (photons, not followed) */
@@ -525,7 +526,8 @@ pmc_status pmc_inc_nucleus(int32_t element, double* out, int32_t n_doubles);
 /* Relative evaporation width of ejectile kind (0..5) from nucleus (z, a) at
  * excitation e_star (MeV), host only, in closed form; *sep and *barrier (may
  * be NULL) get the channel's separation energy and Coulomb barrier.  0 for a
- * closed channel or a kind outside 0..5. */
+ * closed channel, a kind outside 0..5, or a nucleus beyond the cascade's
+ * range (z outside 0..23, a outside 1..49). */
 double pmc_inc_width(int32_t z, int32_t a, double e_star, int32_t kind, double* sep, double* barrier);
 
 /* Library version string, e.g. "pmc 0.1 gfx950". */

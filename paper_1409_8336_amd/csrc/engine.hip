@@ -44,9 +44,9 @@ hipError_t launch_fill_u32(uint32_t* p, unsigned long long n, uint32_t v, hipStr
 hipError_t launch_count_steps(const uint32_t* trace, unsigned long long n, unsigned long long* out, hipStream_t st);
 hipError_t launch_inc_transport(const IncLaunch& a, int grid, hipStream_t st);
 hipError_t inc_transport_occupancy(int* blocks_per_cu);
-hipError_t launch_inc_inspect(const IncNucleus* nuclei, const int32_t* element, const double* t,
+hipError_t launch_inc_inspect(const IncNucleus* nuclei, const IncTab* tab, const int32_t* element, const double* t,
                               const unsigned long long* uid, const uint32_t* ks, int n, uint64_t seed, int evap,
-                              IncResult* res, IncParticle* out, hipStream_t st);
+                              unsigned long long* ctr, IncResult* res, IncParticle* out, hipStream_t st);
 }  // namespace pmc
 
 using namespace pmc;
@@ -137,6 +137,7 @@ struct pmc_ctx {
     // intranuclear cascade (PMC_INC): the six target nuclei, the event list
     // of a generation (IncEvent) and each generation's event count
     DevBuf<IncNucleus> d_inc_nuc;
+    DevBuf<IncTab> d_inc_tab;
     DevBuf<IncEvent> d_inc_ev;
     DevBuf<unsigned long long> d_inc_count;
     int inc_grid = 0;
@@ -377,6 +378,10 @@ pmc_status ensure_inc(pmc_ctx* c)
     HIPCHK(c->d_inc_nuc.ensure(kIncTargets), "alloc nuclei");
     HIPCHK(hipMemcpy(c->d_inc_nuc.p, nu.data(), kIncTargets * sizeof(IncNucleus), hipMemcpyHostToDevice),
            "upload nuclei");
+    IncTab tab;
+    build_inc_table(&tab);
+    HIPCHK(c->d_inc_tab.ensure(1), "alloc evaporation table");
+    HIPCHK(hipMemcpy(c->d_inc_tab.p, &tab, sizeof(IncTab), hipMemcpyHostToDevice), "upload evaporation table");
     int per_cu = 0;
     HIPCHK(inc_transport_occupancy(&per_cu), "cascade kernel occupancy");
     c->inc_grid = c->num_cu * std::max(1, std::min(per_cu, 4));
@@ -621,8 +626,10 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
         pmc_status si = ensure_inc(c);
         if (si != PMC_OK) return si;
         HIPCHK(c->d_inc_ev.ensure(cap), "alloc event list");
-        HIPCHK(c->d_inc_count.ensure(kMaxGenerations), "alloc event counters");
-        HIPCHK(launch_zero(c->d_inc_count.p, kMaxGenerations * 8, st), "zero event counters");
+        // per generation: events recorded; then per generation the eight
+        // claim counters of the cascade kernel's waves
+        HIPCHK(c->d_inc_count.ensure(9 * kMaxGenerations), "alloc event counters");
+        HIPCHK(launch_zero(c->d_inc_count.p, 9 * kMaxGenerations * 8, st), "zero event counters");
         a.inc_ev = c->d_inc_ev.p;
         a.inc_cap = cap;
     }
@@ -658,7 +665,8 @@ pmc_status run_driver(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, const 
                 if (inc) {
                     // this generation's events; their protons join the next
                     // generation's queue
-                    IncLaunch il{c->d_inc_ev.p, c->d_inc_count.p + gidx, cap, c->d_inc_nuc.p, c->d_plans.p,
+                    IncLaunch il{c->d_inc_ev.p, c->d_inc_count.p + gidx, cap, c->d_inc_nuc.p, c->d_inc_tab.p,
+                                 c->d_inc_count.p + kMaxGenerations + 8 * gidx, c->d_plans.p,
                                  np, K, let ? 1 : 0, a.q_out, cap, &c->d_gc.p[2 * (gidx + 1)],
                                  c->d_ledger.p, c->d_counters.p};
                     HIPCHK(hipEventRecord(c->ev_inc[2 * gidx], st), "event");
@@ -1336,17 +1344,20 @@ pmc_status pmc_inc_events(pmc_ctx* c, const int32_t* element, const double* t_me
     DevBuf<uint32_t> d_ks;
     DevBuf<IncResult> d_res;
     DevBuf<IncParticle> d_out;
+    DevBuf<unsigned long long> d_ctr;
     HIPCHK(d_el.ensure(n), "alloc events");
     HIPCHK(d_t.ensure(n), "alloc events");
     HIPCHK(d_uid.ensure(n), "alloc events");
     HIPCHK(d_ks.ensure(n), "alloc events");
     HIPCHK(d_res.ensure(n), "alloc results");
     HIPCHK(d_out.ensure((size_t)n * kIncMaxOut), "alloc particles");
+    HIPCHK(d_ctr.ensure(8), "alloc claim counters");
+    HIPCHK(hipMemset(d_ctr.p, 0, 64), "zero claim counters");
     HIPCHK(hipMemcpy(d_el.p, element, 4 * (size_t)n, hipMemcpyHostToDevice), "upload events");
     HIPCHK(hipMemcpy(d_t.p, t_mev, 8 * (size_t)n, hipMemcpyHostToDevice), "upload events");
     HIPCHK(hipMemcpy(d_uid.p, uid, 8 * (size_t)n, hipMemcpyHostToDevice), "upload events");
     HIPCHK(hipMemcpy(d_ks.p, ks, 4 * (size_t)n, hipMemcpyHostToDevice), "upload events");
-    HIPCHK(launch_inc_inspect(c->d_inc_nuc.p, d_el.p, d_t.p, d_uid.p, d_ks.p, n, seed, evaporate, d_res.p, d_out.p,
+    HIPCHK(launch_inc_inspect(c->d_inc_nuc.p, c->d_inc_tab.p, d_el.p, d_t.p, d_uid.p, d_ks.p, n, seed, evaporate, d_ctr.p, d_res.p, d_out.p,
                               nullptr), "cascade launch");
     HIPCHK(hipDeviceSynchronize(), "cascade");
     HIPCHK(hipMemcpy(results, d_res.p, sizeof(IncResult) * (size_t)n, hipMemcpyDeviceToHost), "read results");

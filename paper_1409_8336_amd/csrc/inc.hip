@@ -24,6 +24,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "device.hpp"
@@ -87,16 +88,18 @@ struct Channel {
     double sep, barrier, x, la, weight;
 };
 
-// channel j of nucleus (z, a) at excitation es; false when closed
-HD bool evap_channel(int z, int a, double es, int j, Channel* ch)
+// channel j of nucleus (z, a) at excitation es; false when closed.  The
+// binding energies and cube roots come from the host-built table t
+// (z <= kIncZMax, a <= kIncAMax: every nucleus an event can reach)
+HD bool evap_channel(const IncTab& t, int z, int a, double es, int j, Channel* ch)
 {
     const int zd = z - kEjZ[j], ad = a - kEjA[j];
     if (ad < 1 || zd < 0 || zd > ad) return false;
-    double bd, bp, be;
-    if (!bound_nucleus(zd, ad, &bd) || !bound_nucleus(z, a, &bp)) return false;
-    bound_nucleus(kEjZ[j], kEjA[j], &be);
+    const double bd = t.bind[zd][ad], bp = t.bind[z][a];
+    if (!(bd > -kInfD) || !(bp > -kInfD)) return false;   // unbound
+    const double be = t.bind[kEjZ[j]][kEjA[j]];
     ch->sep = bp - bd - be;
-    const double rad = 1.5 * (cbrt((double)ad) + cbrt((double)kEjA[j]));
+    const double rad = 1.5 * (t.cbrt_a[ad] + t.cbrt_a[kEjA[j]]);
     ch->barrier = kEjZ[j] ? kE2 * (double)kEjZ[j] * (double)zd / rad : 0.0;
     ch->x = es - ch->sep - ch->barrier;
     ch->la = (double)ad / 8.0;
@@ -127,9 +130,9 @@ HD double level_integral(double x, double la)
     return x * x * sum;
 }
 
-HD double evap_width(int z, int a, double es, int j, Channel* ch)
+HD double evap_width(const IncTab& t, int z, int a, double es, int j, Channel* ch)
 {
-    if (!evap_channel(z, a, es, j, ch)) return 0.0;
+    if (!evap_channel(t, z, a, es, j, ch)) return 0.0;
     return ch->weight * level_integral(ch->x, ch->la);
 }
 
@@ -298,285 +301,496 @@ HD double kinetic(const double p[3])
     return sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2] + kMN * kMN) - kMN;
 }
 
-// Per-attempt bookkeeping of the cascade.
-struct Tally {
+// ------------------------------------------------------ one event, in steps
+// An event runs as a sequence of steps over a per-event state, so that a
+// wave can run its lanes' events side by side, each lane at its own step:
+//   entry       one entry attempt of the incident proton (impact parameter
+//               uniform over the outer disc, refraction into the outer shell);
+//   flight      one flight of the particle in flight (taken from the
+//               cascade's stack when none is): to the next shell boundary
+//               (refraction or reflection; leaving through the outer one
+//               emits it) or to a collision candidate;
+//   collide     the candidate collision: a Fermi-sea partner (|p| = p_F
+//               u^(1/3), isotropic), the NN kinematics, Pauli blocking (both
+//               products above their Fermi energies, room in the cascade);
+//               an allowed collision stacks both products (the projectile
+//               continues after its partner);
+//   attempt end the cascade of an attempt that had an allowed collision
+//               ends the cascade; otherwise the next attempt (after
+//               kIncMaxAttempts the proton is absorbed: a compound nucleus);
+//   evaporate   one emission of the residual nucleus (channel by width,
+//               energy above the barrier y in (0, X] with density ~ y
+//               exp(2 sqrt(a (X - y))) -- the width's integrand with the
+//               daughter at X - y -- by rejection from y = X sqrt(u) when
+//               2 sqrt(a X) < 2, else from a Gamma(2, sqrt(X/a)) proposal,
+//               both dominating the density; direction isotropic), until no
+//               channel is open, A <= 4 or the event holds kIncMaxOut
+//               particles.
+// The steps take the draws of the event's stream in the same order whatever
+// the interleaving.  Particles that leave are emitted only once the attempt
+// has had a collision (an attempt without one is discarded, and its only
+// escape is the incident proton); emitted kinetic energy and nucleon count
+// give the residual's excitation.
+enum : int { kPhIdle = 0, kPhEntry, kPhFlight, kPhCollide, kPhAttemptEnd, kPhEvap, kPhDone };
+
+struct EvState {
+    Stream st;
+    double t_in;
+    int element;                 // 1..6
+    int phase;
+    bool evap;                   // evaporate after the cascade
+    int attempt, n_coll, next_index, ns, left_n, left_p;
     int n_esc, n_esc_p, n_kept;
     double e_sum, out_sum;
+    Part c;                      // the particle in flight
+    int flight;                  // its flights since it left the stack
+    bool live;
+    int partner;                 // pending collision: partner species and the two Fermi-sea draws
+    double uf0, uf1;
+    int ez, ea, ei;              // evaporation: the nucleus and the next emission
+    double es;
+    IncResult r;                 // the outcome
 };
 
-// One entry of the incident proton into the nucleus and the cascade it
-// starts: entry point uniform over the disc of the outer radius, refraction
-// into the outer shell; each particle flies to its next collision (free path
-// from the free NN cross sections at its local kinetic energy, on the
-// partners of the species not yet exhausted) or shell boundary; a collision
-// takes a Fermi-sea partner (|p| uniform in p^3 up to the shell's Fermi
-// momentum, isotropic) and is allowed only if both products end above their
-// Fermi energies (Pauli) and the cascade has room; particles leave through
-// the outer boundary or are trapped (below the continuum, or after too many
-// reflections).  The struck nucleon's hole and trapped particles add to the
-// excitation sum.  Returns the allowed collisions; emit() gets every
-// particle that leaves once a collision has happened (an attempt without
-// one is discarded, and its only escape is the incident proton).
-template <class Emit>
-__host__ __device__ int cascade(const IncNucleus& nu, double t_in, const Stream& st, int attempt, Part* stack, IncResult& r,
-                       Tally& ta, Emit& emit)
+HD void ev_begin(EvState& s, int element, double t, const Stream& st, bool evap)
 {
-    int ns = 0, next_index = 1, n_coll = 0;
-    int left[2] = {nu.a - nu.z, nu.z};   // target nucleons not yet struck, n and p
+    s.st = st;
+    s.t_in = t;
+    s.element = element;
+    s.evap = evap;
+    s.attempt = 0;
+    s.r = IncResult{};
+    s.phase = kPhEntry;
+}
+
+HD void ev_entry(EvState& s, const IncNucleus& nu)
+{
+    s.ns = 0;
+    s.next_index = 1;
+    s.n_coll = 0;
+    s.left_n = nu.a - nu.z;
+    s.left_p = nu.z;
+    s.n_esc = s.n_esc_p = s.n_kept = 0;
+    s.e_sum = s.out_sum = 0.0;
     const double ro = nu.r[kIncShells];
     double u[4];
-    draw4(st, cascade_tag(attempt, 0, 0), u);
+    draw4(s.st, cascade_tag(s.attempt, 0, 0), u);
     const double b = ro * sqrt(u[0]);
-    if (!(b < ro)) return 0;
-    Part q;
+    if (!(b < ro)) {
+        s.phase = kPhAttemptEnd;
+        return;
+    }
+    Part& q = s.c;
     q.x[0] = b * cos(2.0 * kPi * u[1]);
     q.x[1] = b * sin(2.0 * kPi * u[1]);
     q.x[2] = -sqrt(fmax(ro * ro - b * b, 0.0));
-    {
-        // into the outer shell from outside: tangential momentum kept, the
-        // normal component grows with the well depth
-        const double t_inside = t_in + well(nu, 1, kIncShells - 1);
-        const double n[3] = {q.x[0] / ro, q.x[1] / ro, q.x[2] / ro};
-        const double p_out = sqrt(t_in * (t_in + 2.0 * kMN));
-        const double p_in = sqrt(t_inside * (t_inside + 2.0 * kMN));
-        const double dn = n[2];
-        const double pt[3] = {-p_out * dn * n[0], -p_out * dn * n[1], p_out * (1.0 - dn * n[2])};
-        const double pt2 = pt[0] * pt[0] + pt[1] * pt[1] + pt[2] * pt[2];
-        const double pn = -sqrt(fmax(p_in * p_in - pt2, 0.0));
-        for (int i = 0; i < 3; ++i) q.d[i] = (pt[i] + pn * n[i]) / p_in;
-        q.t = t_inside;
-    }
+    // into the outer shell from outside: tangential momentum kept, the
+    // normal component grows with the well depth
+    const double t_inside = s.t_in + well(nu, 1, kIncShells - 1);
+    const double n[3] = {q.x[0] / ro, q.x[1] / ro, q.x[2] / ro};
+    const double p_out = sqrt(s.t_in * (s.t_in + 2.0 * kMN));
+    const double p_in = sqrt(t_inside * (t_inside + 2.0 * kMN));
+    const double dn = n[2];
+    const double pt[3] = {-p_out * dn * n[0], -p_out * dn * n[1], p_out * (1.0 - dn * n[2])};
+    const double pt2 = pt[0] * pt[0] + pt[1] * pt[1] + pt[2] * pt[2];
+    const double pn = -sqrt(fmax(p_in * p_in - pt2, 0.0));
+    for (int i = 0; i < 3; ++i) q.d[i] = (pt[i] + pn * n[i]) / p_in;
+    q.t = t_inside;
     q.m = 1;
     q.bits = p_bits(1, kIncShells - 1, 0, 0);
-    stack[ns++] = q;
-    while (ns > 0) {
-        Part c = stack[--ns];
-        bool done = false;
-        for (int flight = 0; !done && flight < kIncMaxFlights; ++flight) {
-            const int k = p_shell(c), sp = p_species(c);
-            if (c.t - well(nu, sp, k) <= 0.0 || p_refl(c) > kIncMaxReflect) {
-                ta.e_sum += c.t - nu.tf[sp][k];
-                done = true;
-                break;
-            }
-            const double s_out = to_sphere(c.x, c.d, nu.r[k + 1], true);
-            const double s_in = k > 0 ? to_sphere(c.x, c.d, nu.r[k], false) : kInfD;
-            const double s_b = s_in < s_out ? s_in : s_out;
-            const double rp = left[1] > 0 ? nu.rho[1][k] : 0.0, rn = left[0] > 0 ? nu.rho[0][k] : 0.0;
-            const double sg_p = nn_sigma(sp == 1, c.t), sg_n = nn_sigma(sp == 0, c.t);
-            const double sig = 0.1 * (rp * sg_p + rn * sg_n);   // 1 mb = 0.1 fm^2
-            draw4(st, cascade_tag(attempt, p_index(c), c.m), u);
-            c.m++;
-            const double s_c = sig > 0.0 ? -log(u[0]) / sig : kInfD;
-            if (s_c >= s_b) {
-                for (int i = 0; i < 3; ++i) c.x[i] += s_b * c.d[i];
-                const int j = s_in < s_out ? k - 1 : k + 1;
-                const double vj = j < kIncShells ? well(nu, sp, j) : 0.0;
-                double tn;
-                if (!refract(c.t, well(nu, sp, k), vj, c.x, c.d, &tn)) {
-                    c.bits += 1u << 13;   // one more reflection
-                    continue;
-                }
-                c.t = tn;
-                c.bits = p_bits(sp, j, p_index(c), p_refl(c));
-                if (j == kIncShells) {
-                    if (n_coll > 0 && ta.n_kept < kIncMaxOut) {
-                        emit(sp ? kEjP : kEjN, 0, 0x100u + (uint32_t)p_index(c), c.t, c.d, ta.n_kept);
-                        ta.n_kept++;
-                        ta.out_sum += c.t;
-                    }
-                    ta.n_esc++;
-                    ta.n_esc_p += sp;
-                    done = true;
-                }
-                continue;
-            }
-            // a collision candidate at distance s_c
-            for (int i = 0; i < 3; ++i) c.x[i] += s_c * c.d[i];
-            const int partner = (u[1] * (rp * sg_p + rn * sg_n) < rp * sg_p) ? 1 : 0;
-            double u2[4];
-            draw4(st, cascade_tag(attempt, p_index(c), c.m), u2);
-            c.m++;
-            // the partner from the Fermi sea: |p| = p_F u^(1/3), isotropic
-            double p2[3];
-            {
-                const double pm = nu.pf[partner][k] * cbrt(u[2]);
-                const double ct = 2.0 * u[3] - 1.0, stt = sqrt(fmax(0.0, 1.0 - ct * ct));
-                p2[0] = pm * stt * cos(2.0 * kPi * u2[0]);
-                p2[1] = pm * stt * sin(2.0 * kPi * u2[0]);
-                p2[2] = pm * ct;
-            }
-            const double t2 = kinetic(p2);
-            const double pc = sqrt(c.t * (c.t + 2.0 * kMN));
-            const double p1[3] = {pc * c.d[0], pc * c.d[1], pc * c.d[2]};
-            double o1[3], o2[3];
-            nn_collide(p1, p2, u2[1], u2[2], o1, o2);
-            int sp1 = sp, sp2 = partner;
-            if (sp1 != sp2 && u2[3] < 0.5) {   // n-p: identities exchanged (symmetric about 90 degrees)
-                sp1 = partner;
-                sp2 = sp;
-            }
-            const double t1o = kinetic(o1), t2o = kinetic(o2);
-            if (!(t1o > nu.tf[sp1][k] && t2o > nu.tf[sp2][k]) || next_index >= kIncMaxParticles ||
-                ns + 2 > kIncMaxParticles) {
-                r.n_blocked++;
-                continue;
-            }
-            n_coll++;
-            left[partner]--;
-            ta.e_sum += nu.tf[partner][k] - t2;   // the hole
-            Part a1 = c, a2 = c;
-            a1.t = t1o;
-            a1.bits = p_bits(sp1, k, p_index(c), p_refl(c));
-            a2.t = t2o;
-            a2.m = 0;
-            a2.bits = p_bits(sp2, k, next_index++, 0);
-            const double n1 = sqrt(o1[0] * o1[0] + o1[1] * o1[1] + o1[2] * o1[2]);
-            const double n2 = sqrt(o2[0] * o2[0] + o2[1] * o2[1] + o2[2] * o2[2]);
-            for (int i = 0; i < 3; ++i) {
-                a1.d[i] = o1[i] / n1;
-                a2.d[i] = o2[i] / n2;
-            }
-            stack[ns++] = a1;   // the projectile continues after its partner
-            stack[ns++] = a2;
-            done = true;
-        }
-        if (!done) ta.e_sum += c.t - nu.tf[p_species(c)][p_shell(c)];   // flight limit: trapped
-    }
-    return n_coll;
+    s.flight = 0;
+    s.live = true;
+    s.phase = kPhFlight;
 }
 
-// Evaporation of nucleus (z, a) at excitation es until no channel is open,
-// A <= 4 or the event holds kIncMaxOut particles: the channel by its width;
-// the ejectile's kinetic energy above the barrier, y in (0, X], with density
-// ~ y exp(2 sqrt(a (X - y))) (the width's integrand, the daughter left at
-// X - y), by rejection from y = X sqrt(u) (when 2 sqrt(a X) < 2) or from a
-// Gamma(2, sqrt(X/a)) proposal (otherwise), both dominating the density;
-// direction isotropic.
 template <class Emit>
-__host__ __device__ void evaporate(int z, int a, double es, const Stream& st, IncResult& r, int& n_kept, Emit& emit)
+HD void ev_flight(EvState& s, const IncNucleus& nu, Part* stack, Emit& emit)
 {
+    if (!s.live) {
+        if (s.ns == 0) {
+            s.phase = kPhAttemptEnd;
+            return;
+        }
+        s.c = stack[--s.ns];
+        s.flight = 0;
+        s.live = true;
+    }
+    Part& c = s.c;
+    const int k = p_shell(c), sp = p_species(c);
+    if (s.flight >= kIncMaxFlights) {   // flight limit: trapped
+        s.e_sum += c.t - nu.tf[sp][k];
+        s.live = false;
+        return;
+    }
+    ++s.r.n_flights;
+    if (c.t - well(nu, sp, k) <= 0.0 || p_refl(c) > kIncMaxReflect) {   // trapped
+        s.e_sum += c.t - nu.tf[sp][k];
+        s.live = false;
+        return;
+    }
+    const double s_out = to_sphere(c.x, c.d, nu.r[k + 1], true);
+    const double s_in = k > 0 ? to_sphere(c.x, c.d, nu.r[k], false) : kInfD;
+    const double s_b = s_in < s_out ? s_in : s_out;
+    const double rp = s.left_p > 0 ? nu.rho[1][k] : 0.0, rn = s.left_n > 0 ? nu.rho[0][k] : 0.0;
+    const double sg_p = nn_sigma(sp == 1, c.t), sg_n = nn_sigma(sp == 0, c.t);
+    const double sig = 0.1 * (rp * sg_p + rn * sg_n);   // 1 mb = 0.1 fm^2
     double u[4];
-    for (int i = 0; i < 255 && a > 4 && n_kept < kIncMaxOut; ++i) {
-        double width[6], total = 0.0;
-        Channel ch;
-        for (int j = 0; j < 6; ++j) {
-            width[j] = evap_width(z, a, es, j, &ch);
-            total += width[j];
+    draw4(s.st, cascade_tag(s.attempt, p_index(c), c.m), u);
+    c.m++;
+    const double s_c = sig > 0.0 ? -log(u[0]) / sig : kInfD;
+    if (s_c >= s_b) {
+        for (int i = 0; i < 3; ++i) c.x[i] += s_b * c.d[i];
+        const int j = s_in < s_out ? k - 1 : k + 1;
+        const double vj = j < kIncShells ? well(nu, sp, j) : 0.0;
+        double tn;
+        if (!refract(c.t, well(nu, sp, k), vj, c.x, c.d, &tn)) {
+            c.bits += 1u << 13;   // one more reflection
+            s.flight++;
+            return;
         }
-        if (!(total > 0.0)) break;
-        const uint32_t tag = 0x50000000u | ((uint32_t)i << 8);
-        draw4(st, tag, u);
-        int j = 0;
-        double cum = 0.0;
-        for (j = 0; j < 6; ++j) {
-            if (width[j] <= 0.0) continue;
-            cum += width[j];
-            if (u[0] * total < cum) break;
-        }
-        if (j == 6)
-            for (j = 5; width[j] <= 0.0; --j) {}
-        evap_channel(z, a, es, j, &ch);
-        const double x = ch.x, la = ch.la;
-        const double Y = 2.0 * sqrt(la * x), t0 = sqrt(x / la);
-        double y = 0.5 * x;
-        for (uint32_t att = 1; att < 256; ++att) {
-            double v[4];
-            draw4(st, tag | att, v);
-            double cand, acc;
-            if (Y < 2.0) {
-                cand = x * sqrt(v[0]);
-                acc = exp(2.0 * sqrt(la * (x - cand)) - Y);
-            } else {
-                cand = -t0 * log(v[0] * v[1]);
-                if (cand > x) continue;
-                acc = exp(2.0 * sqrt(la * (x - cand)) - Y + cand / t0);
+        c.t = tn;
+        c.bits = p_bits(sp, j, p_index(c), p_refl(c));
+        if (j == kIncShells) {
+            if (s.n_coll > 0 && s.n_kept < kIncMaxOut) {
+                emit(sp ? kEjP : kEjN, 0, 0x100u + (uint32_t)p_index(c), c.t, c.d, s.n_kept);
+                s.n_kept++;
+                s.out_sum += c.t;
             }
-            if (v[2] < acc) {
-                y = cand;
-                break;
-            }
+            s.n_esc++;
+            s.n_esc_p += sp;
+            s.live = false;
+            return;
         }
-        const double eps = ch.barrier + y;
-        const double ct = 2.0 * u[1] - 1.0, stt = sqrt(fmax(0.0, 1.0 - ct * ct));
-        const double d[3] = {stt * cos(2.0 * kPi * u[2]), stt * sin(2.0 * kPi * u[2]), ct};
-        emit(j, 1, 0x400u + (uint32_t)i, eps, d, n_kept);
-        n_kept++;
-        r.binding += ch.sep;
-        es -= ch.sep + eps;
-        z -= kEjZ[j];
-        a -= kEjA[j];
+        s.flight++;
+        return;
     }
-    r.z_fin = z;
-    r.a_fin = a;
-    r.e_star_fin = es;
+    // a collision candidate at distance s_c
+    for (int i = 0; i < 3; ++i) c.x[i] += s_c * c.d[i];
+    s.partner = (u[1] * (rp * sg_p + rn * sg_n) < rp * sg_p) ? 1 : 0;
+    s.uf0 = u[2];
+    s.uf1 = u[3];
+    s.phase = kPhCollide;
 }
 
-// One non-elastic event of a proton of kinetic energy t on nucleus nu:
-// entry attempts until one has an allowed collision (none in
-// kIncMaxAttempts: the proton is absorbed into a compound nucleus), the
-// residual's excitation from the energy balance (every escaping nucleon
-// beyond the incident one costs the separation energy), then evaporation.
-template <class Emit>
-__host__ __device__ void inc_event(const IncNucleus& nu, double t, const Stream& st, bool evap, Part* stack, IncResult& r,
-                          Emit& emit)
+HD void ev_collide(EvState& s, const IncNucleus& nu, Part* stack)
 {
-    r = IncResult{};
-    Tally ta{};
-    int attempt;
-    for (attempt = 0; attempt < kIncMaxAttempts; ++attempt) {
-        ta = Tally{};
-        r.n_coll = cascade(nu, t, st, attempt, stack, r, ta, emit);
-        if (r.n_coll > 0) break;
+    Part& c = s.c;
+    const int k = p_shell(c), sp = p_species(c), partner = s.partner;
+    double u2[4];
+    draw4(s.st, cascade_tag(s.attempt, p_index(c), c.m), u2);
+    c.m++;
+    s.phase = kPhFlight;
+    double p2[3];
+    {
+        const double pm = nu.pf[partner][k] * cbrt(s.uf0);
+        const double ct = 2.0 * s.uf1 - 1.0, stt = sqrt(fmax(0.0, 1.0 - ct * ct));
+        p2[0] = pm * stt * cos(2.0 * kPi * u2[0]);
+        p2[1] = pm * stt * sin(2.0 * kPi * u2[0]);
+        p2[2] = pm * ct;
     }
-    r.attempts = attempt < kIncMaxAttempts ? attempt + 1 : kIncMaxAttempts;
-    if (attempt == kIncMaxAttempts) {
-        ta = Tally{};
-        r.compound = 1;
-        ta.e_sum = t + kSep;
+    const double t2 = kinetic(p2);
+    const double pc = sqrt(c.t * (c.t + 2.0 * kMN));
+    const double p1[3] = {pc * c.d[0], pc * c.d[1], pc * c.d[2]};
+    double o1[3], o2[3];
+    nn_collide(p1, p2, u2[1], u2[2], o1, o2);
+    int sp1 = sp, sp2 = partner;
+    if (sp1 != sp2 && u2[3] < 0.5) {   // n-p: identities exchanged (symmetric about 90 degrees)
+        sp1 = partner;
+        sp2 = sp;
     }
-    r.n_esc = ta.n_esc;
-    r.z_res = nu.z + 1 - ta.n_esc_p;
-    r.a_res = nu.a + 1 - ta.n_esc;
-    r.e_star = t - ta.out_sum - (double)(ta.n_esc - 1) * kSep;
-    r.e_star_sum = ta.e_sum;
-    r.binding = (double)(ta.n_esc - 1) * kSep;
+    const double t1o = kinetic(o1), t2o = kinetic(o2);
+    if (!(t1o > nu.tf[sp1][k] && t2o > nu.tf[sp2][k]) || s.next_index >= kIncMaxParticles ||
+        s.ns + 2 > kIncMaxParticles) {
+        s.r.n_blocked++;
+        s.flight++;
+        return;
+    }
+    s.n_coll++;
+    if (partner) s.left_p--;
+    else s.left_n--;
+    s.e_sum += nu.tf[partner][k] - t2;   // the hole
+    Part a1 = c, a2 = c;
+    a1.t = t1o;
+    a1.bits = p_bits(sp1, k, p_index(c), p_refl(c));
+    a2.t = t2o;
+    a2.m = 0;
+    a2.bits = p_bits(sp2, k, s.next_index++, 0);
+    const double n1 = sqrt(o1[0] * o1[0] + o1[1] * o1[1] + o1[2] * o1[2]);
+    const double n2 = sqrt(o2[0] * o2[0] + o2[1] * o2[1] + o2[2] * o2[2]);
+    for (int i = 0; i < 3; ++i) {
+        a1.d[i] = o1[i] / n1;
+        a2.d[i] = o2[i] / n2;
+    }
+    stack[s.ns++] = a1;   // the projectile continues after its partner
+    stack[s.ns++] = a2;
+    s.live = false;
+}
+
+// the residual after the cascade (or the compound nucleus), and whether it
+// evaporates
+HD void ev_cascade_done(EvState& s, const IncNucleus& nu, bool compound)
+{
+    IncResult& r = s.r;
+    r.attempts = compound ? kIncMaxAttempts : s.attempt + 1;
+    r.compound = compound ? 1 : 0;
+    r.n_coll = s.n_coll;
+    r.n_esc = s.n_esc;
+    r.z_res = nu.z + 1 - s.n_esc_p;
+    r.a_res = nu.a + 1 - s.n_esc;
+    r.e_star = s.t_in - s.out_sum - (double)(s.n_esc - 1) * kSep;
+    r.e_star_sum = s.e_sum;
+    r.binding = (double)(s.n_esc - 1) * kSep;
     r.z_fin = r.z_res;
     r.a_fin = r.a_res;
     r.e_star_fin = r.e_star;
-    int n_kept = ta.n_kept;
-    if (evap && r.e_star > 0.0) evaporate(r.z_res, r.a_res, r.e_star, st, r, n_kept, emit);
-    r.n_out = n_kept;
+    if (s.evap && r.e_star > 0.0) {
+        s.ez = r.z_res;
+        s.ea = r.a_res;
+        s.es = r.e_star;
+        s.ei = 0;
+        s.phase = kPhEvap;
+    } else {
+        s.phase = kPhDone;
+    }
 }
 
-__device__ __forceinline__ void stage_nuclei(IncNucleus* dst, const IncNucleus* src)
+HD void ev_attempt_end(EvState& s, const IncNucleus& nu)
+{
+    if (s.n_coll > 0) {
+        ev_cascade_done(s, nu, false);
+        return;
+    }
+    if (++s.attempt < kIncMaxAttempts) {
+        s.phase = kPhEntry;
+        return;
+    }
+    // never an allowed collision: the proton is absorbed
+    s.n_kept = 0;
+    s.n_esc = s.n_esc_p = 0;
+    s.out_sum = 0.0;
+    s.e_sum = s.t_in + kSep;
+    ev_cascade_done(s, nu, true);
+}
+
+template <class Emit>
+HD void ev_evaporate(EvState& s, const IncTab& tab, Emit& emit)
+{
+    IncResult& r = s.r;
+    double width[6], total = 0.0;
+    Channel ch;
+    if (s.ei < 255 && s.ea > 4 && s.n_kept < kIncMaxOut) {
+        for (int j = 0; j < 6; ++j) {
+            width[j] = evap_width(tab, s.ez, s.ea, s.es, j, &ch);
+            total += width[j];
+        }
+    }
+    if (!(total > 0.0)) {
+        r.z_fin = s.ez;
+        r.a_fin = s.ea;
+        r.e_star_fin = s.es;
+        s.phase = kPhDone;
+        return;
+    }
+    const uint32_t tag = 0x50000000u | ((uint32_t)s.ei << 8);
+    double u[4];
+    draw4(s.st, tag, u);
+    int j = 0;
+    double cum = 0.0;
+    for (j = 0; j < 6; ++j) {
+        if (width[j] <= 0.0) continue;
+        cum += width[j];
+        if (u[0] * total < cum) break;
+    }
+    if (j == 6)
+        for (j = 5; width[j] <= 0.0; --j) {}
+    evap_channel(tab, s.ez, s.ea, s.es, j, &ch);
+    const double x = ch.x, la = ch.la;
+    const double Y = 2.0 * sqrt(la * x), t0 = sqrt(x / la);
+    double y = 0.5 * x;
+    for (uint32_t att = 1; att < 256; ++att) {
+        double v[4];
+        draw4(s.st, tag | att, v);
+        double cand, acc;
+        if (Y < 2.0) {
+            cand = x * sqrt(v[0]);
+            acc = exp(2.0 * sqrt(la * (x - cand)) - Y);
+        } else {
+            cand = -t0 * log(v[0] * v[1]);
+            if (cand > x) continue;
+            acc = exp(2.0 * sqrt(la * (x - cand)) - Y + cand / t0);
+        }
+        if (v[2] < acc) {
+            y = cand;
+            break;
+        }
+    }
+    const double eps = ch.barrier + y;
+    const double ct = 2.0 * u[1] - 1.0, stt = sqrt(fmax(0.0, 1.0 - ct * ct));
+    const double d[3] = {stt * cos(2.0 * kPi * u[2]), stt * sin(2.0 * kPi * u[2]), ct};
+    emit(j, 1, 0x400u + (uint32_t)s.ei, eps, d, s.n_kept);
+    s.n_kept++;
+    r.binding += ch.sep;
+    s.es -= ch.sep + eps;
+    s.ez -= kEjZ[j];
+    s.ea -= kEjA[j];
+    s.ei++;
+}
+
+// One event, its steps in sequence (the reference order; host and device).
+template <class Emit>
+HD void inc_event(const IncNucleus& nu, const IncTab& tab, double t, const Stream& st, bool evap, Part* stack,
+                  IncResult& r, Emit& emit)
+{
+    EvState s;
+    ev_begin(s, 0, t, st, evap);
+    while (s.phase != kPhDone) {
+        switch (s.phase) {
+        case kPhEntry: ev_entry(s, nu); break;
+        case kPhFlight: ev_flight(s, nu, stack, emit); break;
+        case kPhCollide: ev_collide(s, nu, stack); break;
+        case kPhAttemptEnd: ev_attempt_end(s, nu); break;
+        case kPhEvap: ev_evaporate(s, tab, emit); break;
+        default: s.phase = kPhDone; break;
+        }
+    }
+    r = s.r;
+    r.n_out = s.n_kept;
+}
+
+// copy n bytes (a multiple of 8) from global memory into LDS, all lanes
+__device__ __forceinline__ void stage_words(void* dst, const void* src, int bytes)
 {
     const double* s = reinterpret_cast<const double*>(src);
     double* d = reinterpret_cast<double*>(dst);
-    for (int i = threadIdx.x; i < kIncTargets * (int)(sizeof(IncNucleus) / 8); i += blockDim.x) d[i] = s[i];
+    for (int i = threadIdx.x; i < bytes / 8; i += blockDim.x) d[i] = s[i];
 }
 
 // ----------------------------------------------------------------- kernels
 
+// ------------------------------------------------------- wave scheduling
+// A wave runs its 64 lanes' events side by side, one step per lane and loop
+// iteration, and gives an idle lane a new event as soon as eight are idle,
+// so lanes are not held by the longest event of a batch.  The expensive
+// steps wait for company: a collision runs once kCollBatch lanes have one
+// pending (or too few lanes are still flying for that to happen), an
+// evaporation step once kEvapBatch lanes are evaporating; meanwhile the
+// other lanes keep flying.
+constexpr int kCollBatch = 16, kEvapBatch = 8, kRefillIdle = 8;
+constexpr int kClaimRanges = 8;   // the event list in 8 ranges, each with its own claim counter
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
+__device__ __forceinline__ int wave_mbcnt(unsigned long long m)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Src: n (events), claim(count) -> first index or >= n; begin(i, s);
+// emit(i, s, kind, stage, id, t, d, j); finish(i, s); flush(force)
+template <class Src>
+__device__ void run_events(Src& src, const IncNucleus* nuc, const IncTab& tab, Part* stack)
+{
+    EvState s;
+    s.phase = kPhIdle;
+    unsigned long long ev = 0;
+    bool more = src.n > 0;   // (wave-uniform)
+    for (;;) {
+        // refill: idle lanes take new events, one claim for the wave
+        const unsigned long long idle = __ballot(s.phase == kPhIdle);
+        const int n_idle = __popcll(idle);
+        if (more && (n_idle >= kRefillIdle || n_idle == 64)) {
+            int got = 0;
+            const unsigned long long base = src.claim(n_idle, &got);
+            if (got < n_idle) more = false;
+            if (s.phase == kPhIdle) {
+                const int rank = wave_mbcnt(idle);
+                if (rank < got) {
+                    ev = base + (unsigned long long)rank;
+                    src.begin(ev, s);
+                }
+            }
+        }
+        if (__ballot(s.phase != kPhIdle) == 0ull) {
+            if (!more) break;
+            continue;
+        }
+        auto emit = [&](int kind, int stage, uint32_t id, double t, const double d[3], int j) {
+            src.emit(ev, s, kind, stage, id, t, d, j);
+        };
+        if (s.phase == kPhEntry) ev_entry(s, nuc[s.element - 1]);
+        if (s.phase == kPhFlight) ev_flight(s, nuc[s.element - 1], stack, emit);
+        if (s.phase == kPhAttemptEnd) ev_attempt_end(s, nuc[s.element - 1]);
+        const int n_run = __popcll(__ballot(s.phase == kPhEntry || s.phase == kPhFlight ||
+                                            s.phase == kPhAttemptEnd));
+        const int n_col = __popcll(__ballot(s.phase == kPhCollide));
+        if (n_col >= kCollBatch || (n_col > 0 && n_run < kCollBatch)) {
+            if (s.phase == kPhCollide) ev_collide(s, nuc[s.element - 1], stack);
+        }
+        const int n_ev = __popcll(__ballot(s.phase == kPhEvap));
+        if (n_ev >= kEvapBatch || (n_ev > 0 && n_run + n_col < kEvapBatch)) {
+            if (s.phase == kPhEvap) ev_evaporate(s, tab, emit);
+        }
+        if (s.phase == kPhDone) {
+            s.r.n_out = s.n_kept;
+            src.finish(ev, s);
+            s.phase = kPhIdle;
+        }
+        src.flush(false);
+    }
+    src.flush(true);
+}
+
+// the event list split into kClaimRanges ranges with a counter each: a wave
+// claims from its workgroup's range first (spreading the atomics over 8
+// addresses), then from the others
+struct RangeClaim {
+    unsigned long long* ctr;
+    unsigned long long n;
+    int home;
+    __device__ unsigned long long claim(int want, int* got)
+    {
+        unsigned long long base = 0;
+        int g = 0;
+        if (lane_id() == 0) {
+            for (int k = 0; k < kClaimRanges && g == 0; ++k) {
+                const int rr = (home + k) % kClaimRanges;
+                const unsigned long long lo = n * (unsigned long long)rr / kClaimRanges;
+                const unsigned long long hi = n * (unsigned long long)(rr + 1) / kClaimRanges;
+                if (__hip_atomic_load(&ctr[rr], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= hi - lo) continue;
+                const unsigned long long off = atomicAdd(&ctr[rr], (unsigned long long)want);
+                if (lo + off < hi) {
+                    base = lo + off;
+                    g = (int)min((unsigned long long)want, hi - base);
+                }
+            }
+        }
+        *got = __shfl(g, 0);
+        return __shfl(base, 0);
+    }
+};
+
 // Inspection: event i on element[i] at t[i], stream (uid[i], ks[i]); the
 // outcome to res[i], the emitted particles to out[i * kIncMaxOut + j].
-__global__ void __launch_bounds__(256) inc_inspect_kernel(const IncNucleus* __restrict__ nuclei,
-                                                          const int32_t* __restrict__ element,
-                                                          const double* __restrict__ t,
-                                                          const unsigned long long* __restrict__ uid,
-                                                          const uint32_t* __restrict__ ks, int n, uint32_t k0,
-                                                          uint32_t k1, int evap, IncResult* __restrict__ res,
-                                                          IncParticle* __restrict__ out)
-{
-    __shared__ IncNucleus nuc[kIncTargets];
-    stage_nuclei(nuc, nuclei);
-    __syncthreads();
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    Part stack[kIncMaxParticles];
-    const Stream st{k0, k1, (uint32_t)uid[i], (uint32_t)(uid[i] >> 32), ks[i]};
-    IncParticle* o = out + (size_t)i * kIncMaxOut;
-    auto emit = [&](int kind, int stage, uint32_t id, double tt, const double d[3], int j) {
+// Scheduled as in the transport (ctr: kClaimRanges zeroed counters).
+struct InspectSrc {
+    RangeClaim rc;
+    unsigned long long n;
+    const int32_t* element;
+    const double* t;
+    const unsigned long long* uid;
+    const uint32_t* ks;
+    uint32_t k0, k1;
+    bool evap;
+    IncResult* res;
+    IncParticle* out;
+    __device__ unsigned long long claim(int want, int* got) { return rc.claim(want, got); }
+    __device__ void begin(unsigned long long i, EvState& s)
+    {
+        const Stream st{k0, k1, (uint32_t)uid[i], (uint32_t)(uid[i] >> 32), ks[i]};
+        ev_begin(s, element[i], t[i], st, evap);
+    }
+    __device__ void emit(unsigned long long i, const EvState&, int kind, int stage, uint32_t id, double tt,
+                         const double d[3], int j)
+    {
         IncParticle p;
         p.kind = kind;
         p.stage = stage;
@@ -586,11 +800,31 @@ __global__ void __launch_bounds__(256) inc_inspect_kernel(const IncNucleus* __re
         p.dir[0] = d[0];
         p.dir[1] = d[1];
         p.dir[2] = d[2];
-        o[j] = p;
-    };
-    IncResult r;
-    inc_event(nuc[element[i] - 1], t[i], st, evap != 0, stack, r, emit);
-    res[i] = r;
+        out[i * kIncMaxOut + (unsigned long long)j] = p;
+    }
+    __device__ void finish(unsigned long long i, const EvState& s) { res[i] = s.r; }
+    __device__ void flush(bool) {}
+};
+
+__global__ void __launch_bounds__(256) inc_inspect_kernel(const IncNucleus* __restrict__ nuclei,
+                                                          const IncTab* __restrict__ tab,
+                                                          const int32_t* __restrict__ element,
+                                                          const double* __restrict__ t,
+                                                          const unsigned long long* __restrict__ uid,
+                                                          const uint32_t* __restrict__ ks, int n, uint32_t k0,
+                                                          uint32_t k1, int evap, unsigned long long* ctr,
+                                                          IncResult* __restrict__ res,
+                                                          IncParticle* __restrict__ out)
+{
+    __shared__ IncNucleus nuc[kIncTargets];
+    __shared__ IncTab tb;
+    stage_words(nuc, nuclei, (int)sizeof(nuc));
+    stage_words(&tb, tab, (int)sizeof(IncTab));
+    __syncthreads();
+    Part stack[kIncMaxParticles];
+    InspectSrc src{{ctr, (unsigned long long)n, (int)(blockIdx.x % kClaimRanges)}, (unsigned long long)n, element,
+                   t, uid, ks, k0, k1, evap != 0, res, out};
+    run_events(src, nuc, tb, stack);
 }
 
 }  // namespace
@@ -599,123 +833,184 @@ __global__ void __launch_bounds__(256) inc_inspect_kernel(const IncNucleus* __re
 namespace {
 
 constexpr int kIncBlock = 256;
-constexpr int kIncStage = 512;   // children a workgroup stages in LDS per round
+constexpr int kIncWaves = kIncBlock / 64;
+constexpr int kStageW = 512;      // children a wave stages in LDS before writing them out
+constexpr int kStageFlush = 384;  // write out at this fill (an iteration adds at most 128)
+constexpr int kStageWords = 6;    // event index, child id, energy (FP32), direction (3 x FP32)
 
-// One event per lane in rounds of a workgroup's 256 lanes: the cascade and
-// evaporation of the event; emitted protons above the cut-off are staged in
-// LDS and written to the next generation's queue with one reservation per
-// workgroup and round; local deposits (fragments, sub-cut-off protons) go to
-// the event's voxel and group; neutrons, separation energies and the
-// excitation left for photons to the neutral ledger.
+// One child proton of event ev into slot of the next generation's queue
+// (overflow when the queue is full): its direction is the emission
+// direction d (in the frame where the parent moves along +z) turned into the
+// parent's frame -- the rotation that takes +z to the parent's direction u
+// with the azimuth convention of the transport's scattering, written with
+// cos and sin of the emission azimuth as d_x / sin(theta), d_y / sin(theta);
+// its uid the first two words of the event's block with tag 0xC0000000 | id.
+__device__ __noinline__ bool write_child(const IncLaunch& a, const IncEvent& ev, uint32_t id, float tf, float dx,
+                                         float dy, float dz, unsigned long long slot)
+{
+    if (slot >= a.q_cap) return false;
+    const PlanDesc& pd = a.plans[ev.plan];
+    const float u = ev.ux, v = ev.uy, w = ev.uz;
+    const float perp = sqrtf(u * u + v * v);
+    float cx, cy, cz;
+    if (perp < 1e-6f) {
+        cx = dx;
+        cy = dy;
+        cz = w >= 0.f ? dz : -dz;
+    } else {
+        cx = u * dz + (u * w * dx - v * dy) / perp;
+        cy = v * dz + (v * w * dx + u * dy) / perp;
+        cz = w * dz - dx * perp;
+    }
+    const uint4 cu = philox(ev.uid_lo, ev.uid_hi, ev.ks, 0xC0000000u | id, pd.key_lo, pd.key_hi);
+    const uint32_t e[kQueuePlanes] = {__float_as_uint(ev.px), __float_as_uint(ev.py), __float_as_uint(ev.pz),
+                                      __float_as_uint(cx), __float_as_uint(cy), __float_as_uint(cz),
+                                      __float_as_uint(tf), __float_as_uint(ev.w), cu.x, cu.y, ev.batch, ev.plan};
+    for (int p = 0; p < kQueuePlanes; ++p) a.q_out[(size_t)p * a.q_cap + slot] = e[p];
+    return true;
+}
+
+// The transport's events: emitted protons above the cut-off are staged in
+// the wave's part of LDS and written to the next generation's queue with one
+// reservation per write-out; local deposits (fragments, sub-cut-off
+// protons) go to the event's voxel and group; neutrons, separation energies
+// and the excitation left for photons to the neutral ledger; per-plan sums
+// and counters collect in LDS.
+struct TransportSrc {
+    const IncLaunch& a;
+    RangeClaim rc;
+    unsigned long long n;
+    uint32_t* stg;                 // this wave's stage
+    uint32_t* n_staged;            // its fill
+    double (*led)[2];
+    unsigned long long (*cnt)[3];
+    // the lane's event
+    double local, neutral, ovf;
+    unsigned long long n_sec;
+    __device__ unsigned long long claim(int want, int* got) { return rc.claim(want, got); }
+    __device__ void begin(unsigned long long i, EvState& s)
+    {
+        const IncEvent& ev = a.ev[i];
+        const PlanDesc& pd = a.plans[ev.plan];
+        const Stream st{pd.key_lo, pd.key_hi, ev.uid_lo, ev.uid_hi, ev.ks};
+        local = neutral = ovf = 0.0;
+        n_sec = 0;
+        if (ev.element >= 1 && ev.element <= (uint32_t)kIncTargets) {
+            ev_begin(s, (int)ev.element, (double)ev.e, st, true);
+        } else {
+            // no cascade target (never listed by the transport): deposited
+            ev_begin(s, 1, (double)ev.e, st, true);
+            s.phase = kPhDone;
+            local = (double)ev.e;
+        }
+    }
+    __device__ void emit(unsigned long long i, const EvState&, int kind, int, uint32_t id, double tt,
+                         const double d[3], int)
+    {
+        if (kind == kEjN) {
+            neutral += tt;
+            return;
+        }
+        if (kind != kEjP || tt <= kECutD) {
+            local += tt;
+            return;
+        }
+        // the queue holds FP32 energies: the rounding stays here, so that
+        // the ledger closes exactly
+        const float tf = (float)tt;
+        local += tt - (double)tf;
+        ++n_sec;
+        const uint32_t j = atomicAdd(n_staged, 1u);
+        if (j < (uint32_t)kStageW) {
+            uint32_t* e = stg + j * kStageWords;
+            e[0] = (uint32_t)i;
+            e[1] = id;
+            e[2] = __float_as_uint(tf);
+            e[3] = __float_as_uint((float)d[0]);
+            e[4] = __float_as_uint((float)d[1]);
+            e[5] = __float_as_uint((float)d[2]);
+            return;
+        }
+        // the stage is full: this child reserves its own slot
+        const IncEvent ev = a.ev[i];
+        if (!write_child(a, ev, id, tf, (float)d[0], (float)d[1], (float)d[2], atomicAdd(a.out_reserve, 1ull)))
+            ovf += (double)ev.w * (double)tf;
+    }
+    __device__ void finish(unsigned long long i, const EvState& s)
+    {
+        const IncEvent& ev = a.ev[i];
+        const PlanDesc& pd = a.plans[ev.plan];
+        const double w = (double)ev.w;
+        if (s.r.attempts > 0) neutral += s.r.binding + s.r.e_star_fin;
+        if (local != 0.0) {
+            const int K = a.k_batches;
+            const unsigned long long vi = ((unsigned long long)ev.vi_hi << 32) | ev.vi_lo;
+            __hip_atomic_fetch_add(pd.tally + vi * K + ev.batch, w * local, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            if (a.score_let) {
+                const unsigned long long nv = (unsigned long long)pd.nx * pd.ny * pd.nz;
+                __hip_atomic_fetch_add(pd.tally + nv * (K + 1) + vi, w * local, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        atomicAdd(&led[ev.plan][0], w * neutral);
+        if (ovf != 0.0) atomicAdd(&led[ev.plan][1], ovf);
+        atomicAdd(&cnt[ev.plan][0], 1ull);
+        if (n_sec) atomicAdd(&cnt[ev.plan][1], n_sec);
+        atomicAdd(&cnt[ev.plan][2], (unsigned long long)s.r.n_coll);
+    }
+    // the staged children to the queue, one reservation for the wave (the
+    // wave's LDS writes are complete and visible to its lanes after the fence)
+    __device__ void flush(bool force)
+    {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t fill = *n_staged;
+        if (fill == 0u || (!force && fill < (uint32_t)kStageFlush)) return;
+        const uint32_t ns = min(fill, (uint32_t)kStageW);
+        unsigned long long qb = 0;
+        if (lane_id() == 0) qb = atomicAdd(a.out_reserve, (unsigned long long)ns);
+        qb = __shfl(qb, 0);
+        for (uint32_t j = (uint32_t)lane_id(); j < ns; j += 64u) {
+            const uint32_t* e = stg + j * kStageWords;
+            const IncEvent ev = a.ev[e[0]];
+            const float tf = __uint_as_float(e[2]);
+            if (!write_child(a, ev, e[1], tf, __uint_as_float(e[3]), __uint_as_float(e[4]), __uint_as_float(e[5]),
+                             qb + j))
+                atomicAdd(&led[ev.plan][1], (double)ev.w * (double)tf);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (lane_id() == 0) *n_staged = 0u;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+};
+
 __global__ void __launch_bounds__(kIncBlock) inc_transport_kernel(IncLaunch a)
 {
     __shared__ IncNucleus nuc[kIncTargets];
+    __shared__ IncTab tb;
     __shared__ double led[kMaxPlans][2];
     __shared__ unsigned long long cnt[kMaxPlans][3];
-    __shared__ uint32_t stage_w[kIncStage][kQueuePlanes];
-    __shared__ uint32_t n_staged;
-    __shared__ unsigned long long stage_base;
-    stage_nuclei(nuc, a.nuclei);
+    __shared__ uint32_t stage[kIncWaves][kStageW * kStageWords];
+    __shared__ uint32_t n_staged[kIncWaves];
+    stage_words(nuc, a.nuclei, (int)sizeof(nuc));
+    stage_words(&tb, a.tab, (int)sizeof(IncTab));
     for (int p = threadIdx.x; p < a.n_plans; p += blockDim.x) {
         led[p][0] = led[p][1] = 0.0;
         cnt[p][0] = cnt[p][1] = cnt[p][2] = 0ull;
     }
-    if (threadIdx.x == 0) n_staged = 0u;
+    if (threadIdx.x < kIncWaves) n_staged[threadIdx.x] = 0u;
     __syncthreads();
+    const int wave = threadIdx.x >> 6;
     const unsigned long long rec = *a.ev_count;
     const unsigned long long n = rec < a.ev_cap ? rec : a.ev_cap;
-    const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
-    const int K = a.k_batches;
     Part stack[kIncMaxParticles];
-    for (unsigned long long base = (unsigned long long)blockIdx.x * blockDim.x; base < n; base += stride) {
-        const unsigned long long i = base + threadIdx.x;
-        if (i < n) {
-            const IncEvent ev = a.ev[i];
-            const PlanDesc& pd = a.plans[ev.plan];
-            const Stream st{pd.key_lo, pd.key_hi, ev.uid_lo, ev.uid_hi, ev.ks};
-            const double w = (double)ev.w;
-            double local = 0.0, neutral = 0.0, ovf = 0.0;
-            unsigned long long n_sec = 0;
-            auto emit = [&](int kind, int, uint32_t id, double tt, const double d[3], int) {
-                if (kind == kEjN) {
-                    neutral += tt;
-                    return;
-                }
-                if (kind != kEjP || tt <= kECutD) {
-                    local += tt;
-                    return;
-                }
-                // the child: the parent's direction turned by the emission angle
-                double cd[3] = {(double)ev.ux, (double)ev.uy, (double)ev.uz};
-                rotate_d(cd, d[2], sqrt(d[0] * d[0] + d[1] * d[1]), atan2(d[1], d[0]) / (2.0 * kPi));
-                const uint4 cu = philox(ev.uid_lo, ev.uid_hi, ev.ks, 0xC0000000u | id, pd.key_lo, pd.key_hi);
-                // the queue holds FP32 energies: the rounding stays here, so
-                // that the ledger closes exactly
-                const float tf = (float)tt;
-                local += tt - (double)tf;
-                const uint32_t e[kQueuePlanes] = {
-                    __float_as_uint(ev.px), __float_as_uint(ev.py), __float_as_uint(ev.pz),
-                    __float_as_uint((float)cd[0]), __float_as_uint((float)cd[1]), __float_as_uint((float)cd[2]),
-                    __float_as_uint(tf), __float_as_uint(ev.w), cu.x, cu.y, ev.batch, ev.plan};
-                ++n_sec;
-                const uint32_t j = atomicAdd(&n_staged, 1u);
-                if (j < (uint32_t)kIncStage) {
-                    for (int p = 0; p < kQueuePlanes; ++p) stage_w[j][p] = e[p];
-                    return;
-                }
-                // the stage is full: this child reserves its own slot
-                const unsigned long long slot = atomicAdd(a.out_reserve, 1ull);
-                if (slot < a.q_cap) {
-                    for (int p = 0; p < kQueuePlanes; ++p) a.q_out[(size_t)p * a.q_cap + slot] = e[p];
-                } else {
-                    ovf += w * (double)tf;
-                }
-            };
-            IncResult r;
-            if (ev.element >= 1 && ev.element <= (uint32_t)kIncTargets) {
-                inc_event(nuc[ev.element - 1], (double)ev.e, st, true, stack, r, emit);
-                neutral += r.binding + r.e_star_fin;
-            } else {
-                // no cascade target (never listed by the transport): deposited
-                r = IncResult{};
-                local += (double)ev.e;
-            }
-            if (local != 0.0) {
-                const unsigned long long vi = ((unsigned long long)ev.vi_hi << 32) | ev.vi_lo;
-                double* tally = pd.tally;
-                __hip_atomic_fetch_add(tally + vi * K + ev.batch, w * local, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-                if (a.score_let) {
-                    const unsigned long long nv = (unsigned long long)pd.nx * pd.ny * pd.nz;
-                    __hip_atomic_fetch_add(tally + nv * (K + 1) + vi, w * local, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                }
-            }
-            atomicAdd(&led[ev.plan][0], w * neutral);
-            if (ovf != 0.0) atomicAdd(&led[ev.plan][1], ovf);
-            atomicAdd(&cnt[ev.plan][0], 1ull);
-            if (n_sec) atomicAdd(&cnt[ev.plan][1], n_sec);
-            atomicAdd(&cnt[ev.plan][2], (unsigned long long)r.n_coll);
-        }
-        // the round's staged children to the queue: one reservation per workgroup
-        __syncthreads();
-        const uint32_t ns = n_staged < (uint32_t)kIncStage ? n_staged : (uint32_t)kIncStage;
-        if (threadIdx.x == 0 && ns > 0) stage_base = atomicAdd(a.out_reserve, (unsigned long long)ns);
-        __syncthreads();
-        for (uint32_t j = threadIdx.x; j < ns; j += blockDim.x) {
-            const unsigned long long slot = stage_base + j;
-            if (slot < a.q_cap) {
-                for (int p = 0; p < kQueuePlanes; ++p) a.q_out[(size_t)p * a.q_cap + slot] = stage_w[j][p];
-            } else {
-                const double ev_w = (double)__uint_as_float(stage_w[j][7]);
-                const double ev_e = (double)__uint_as_float(stage_w[j][6]);
-                atomicAdd(&led[stage_w[j][11]][1], ev_w * ev_e);
-            }
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) n_staged = 0u;
-        __syncthreads();
-    }
+    TransportSrc src{a, {a.claim, n, (int)(blockIdx.x % kClaimRanges)}, n, stage[wave], &n_staged[wave], led, cnt,
+                     0.0, 0.0, 0.0, 0ull};
+    run_events(src, nuc, tb, stack);
+    __syncthreads();
     for (int p = threadIdx.x; p < a.n_plans; p += blockDim.x) {
         if (led[p][0] != 0.0) unsafeAtomicAdd(&a.ledger[4 * p + 1], led[p][0]);
         if (led[p][1] != 0.0) unsafeAtomicAdd(&a.ledger[4 * p + 2], led[p][1]);
@@ -804,6 +1099,19 @@ void build_inc_nucleus(int element, IncNucleus* out)
     }
 }
 
+// The evaporation constants: binding energies from the formula above for
+// every (Z, A) up to (kIncZMax, kIncAMax), -infinity where unbound, and the
+// cube roots of A.
+void build_inc_table(IncTab* out)
+{
+    for (int z = 0; z <= kIncZMax; ++z)
+        for (int a = 0; a <= kIncAMax; ++a) {
+            double b = 0.0;
+            out->bind[z][a] = bound_nucleus(z, a, &b) ? b : -HUGE_VAL;
+        }
+    for (int a = 0; a <= kIncAMax; ++a) out->cbrt_a[a] = std::cbrt((double)a);
+}
+
 hipError_t launch_inc_transport(const IncLaunch& a, int grid, hipStream_t st)
 {
     hipLaunchKernelGGL(inc_transport_kernel, dim3(grid), dim3(kIncBlock), 0, st, a);
@@ -816,14 +1124,14 @@ hipError_t inc_transport_occupancy(int* blocks_per_cu)
                                                         0);
 }
 
-hipError_t launch_inc_inspect(const IncNucleus* nuclei, const int32_t* element, const double* t,
+hipError_t launch_inc_inspect(const IncNucleus* nuclei, const IncTab* tab, const int32_t* element, const double* t,
                               const unsigned long long* uid, const uint32_t* ks, int n, uint64_t seed, int evap,
-                              IncResult* res, IncParticle* out, hipStream_t st)
+                              unsigned long long* ctr, IncResult* res, IncParticle* out, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    const int grid = (n + 255) / 256;
-    hipLaunchKernelGGL(inc_inspect_kernel, dim3(grid), dim3(256), 0, st, nuclei, element, t, uid, ks, n,
-                       (uint32_t)seed, (uint32_t)(seed >> 32), evap, res, out);
+    const int grid = std::min((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(inc_inspect_kernel, dim3(grid), dim3(256), 0, st, nuclei, tab, element, t, uid, ks, n,
+                       (uint32_t)seed, (uint32_t)(seed >> 32), evap, ctr, res, out);
     return hipGetLastError();
 }
 
@@ -850,8 +1158,11 @@ extern "C" pmc_status pmc_inc_nucleus(int32_t element, double* out, int32_t n_do
 extern "C" double pmc_inc_width(int32_t z, int32_t a, double e_star, int32_t kind, double* sep, double* barrier)
 {
     pmc::Channel ch{0, 0, 0, 0, 0};
-    if (kind < 0 || kind > 5) return 0.0;
-    const double w = pmc::evap_width(z, a, e_star, kind, &ch);
+    if (kind < 0 || kind > 5 || z < 0 || a < 1 || z > pmc::kIncZMax || a > pmc::kIncAMax) return 0.0;
+    static pmc::IncTab tab;
+    static std::once_flag once;
+    std::call_once(once, [] { pmc::build_inc_table(&tab); });
+    const double w = pmc::evap_width(tab, z, a, e_star, kind, &ch);
     if (sep) *sep = ch.sep;
     if (barrier) *barrier = ch.barrier;
     return w;

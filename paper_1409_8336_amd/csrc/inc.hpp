@@ -41,6 +41,15 @@ struct IncNucleus {
 };
 static_assert(sizeof(IncNucleus) == 1024, "IncNucleus is 1 KiB");
 
+// Evaporation constants by nucleus, built on the host: binding energies of
+// every (Z, A) an event can reach (the heaviest target plus the proton;
+// -infinity where the nucleus is not bound) and the cube roots of A.
+constexpr int kIncZMax = 23, kIncAMax = 49;
+struct IncTab {
+    double bind[kIncZMax + 1][kIncAMax + 1];
+    double cbrt_a[kIncAMax + 1];
+};
+
 // A non-elastic event the transport hands to the cascade kernel (64 bytes):
 // the proton at the interaction point (position in voxel units of its plan,
 // direction, kinetic energy, weight), its random stream (uid, the step index
@@ -56,7 +65,8 @@ static_assert(sizeof(IncEvent) == 64, "IncEvent is 64 bytes");
 // path keeps only what the ledger needs).
 struct IncResult {
     int32_t n_out, n_coll, n_blocked, attempts, n_esc, compound, z_res, a_res, z_fin, a_fin;
-    int32_t pad[2];
+    int32_t n_flights;   // flights of all cascade particles, all attempts
+    int32_t pad;
     double e_star, e_star_sum, e_star_fin, binding;
 };
 
@@ -75,6 +85,8 @@ struct IncLaunch {
     const unsigned long long* ev_count;   // events recorded (beyond ev_cap: counted as overflow)
     unsigned long long ev_cap;
     const IncNucleus* nuclei;             // the six targets
+    const IncTab* tab;                    // evaporation constants
+    unsigned long long* claim;            // events taken by waves (zeroed per generation)
     const PlanDesc* plans;                // plan descriptors of the run
     int n_plans;
     int k_batches;
@@ -87,7 +99,8 @@ struct IncLaunch {
 };
 
 // Host: the six target nuclei (Woods-Saxon shells by Gauss-Legendre
-// quadrature).  element = 1..6.
+// quadrature), element = 1..6; the evaporation table.
 void build_inc_nucleus(int element, IncNucleus* out);
+void build_inc_table(IncTab* out);
 
 }  // namespace pmc

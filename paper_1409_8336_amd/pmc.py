@@ -83,7 +83,7 @@ class pmc_summary(C.Structure):
 
 class pmc_inc_result(C.Structure):
     _fields_ = [(n, C.c_int32) for n in ("n_out", "n_coll", "n_blocked", "attempts", "n_esc", "compound",
-                                         "z_res", "a_res", "z_fin", "a_fin", "reserved0", "reserved1")] + [
+                                         "z_res", "a_res", "z_fin", "a_fin", "n_flights", "reserved")] + [
         (n, C.c_double) for n in ("e_star", "e_star_sum", "e_star_fin", "binding")]
 
 
