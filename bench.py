@@ -32,8 +32,8 @@ HBM_PEAK = 8.0e12
 # HBM bytes per transport launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
 # scaled by a plain-copy calibration, valid only for the kernel source whose
 # sha256 is recorded (see profiles/); None once the kernel has changed.
-TRAFFIC = {"transport_sha256": "00e279ca51a38dab47f5f00a83e51605defd374927561f0c7adfb045afcd305e",
-           "bytes_per_launch": 6.1906e9, "let_bytes_per_launch": 1.29461e10}
+TRAFFIC = {"transport_sha256": "83fea2223ea3598eabfc2de9b7639fdb6cd38c25b7a08efeff8416bacad3fcd2",
+           "bytes_per_launch": 1.24287e10, "let_bytes_per_launch": None}
 
 
 def _kernel_sha():

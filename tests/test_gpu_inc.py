@@ -234,3 +234,85 @@ def test_cascade_in_a_batch_equals_single_plans():
         assert s["inc_events"] == s["n_nonelastic"] > 0
         np.testing.assert_allclose(got, want, rtol=1e-9, atol=1e-12 * want.max())
         assert ledger_residual(s) < 1e-5
+
+
+def test_full_size_field_with_cascade():
+    """The 256x256x200 CT with the 2000-spot field (every target nucleus, 70 to
+    230 MeV) at 1e6 histories with the cascade, in the benchmark's launch
+    configuration (device buffers, current stream, autotuned shape), against
+    the oracle on the same seed at the same bars."""
+    import torch
+    nd, mt = synth.nuclear_data(), synth.material_table()
+    cfg = synth.config_field(1_000_000)
+    n = cfg["n_histories"]
+    _say("case: full field with the cascade n=%d (GPU)" % n)
+    e = pmc.Engine(0, flags=pmc.PMC_INC)
+    e.load_physics(nd)
+    e.load_geometry(cfg["hu"], cfg["voxel_cm"], mt)
+    dd = torch.empty(cfg["hu"].shape, dtype=torch.float64, device="cuda")
+    dv = torch.empty_like(dd)
+    gs = e.run_spots_dev(cfg["spots"], n, cfg["seed"], dd, dv, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    e.close()
+    gd, gv = dd.cpu().numpy(), dv.cpu().numpy()
+    del dd, dv
+    _say("case: full field with the cascade n=%d (oracle)" % n)
+    o = O.Oracle(flags=O.INC)
+    o.load_physics(nd)
+    o.load_geometry(cfg["hu"], cfg["voxel_cm"], mt)
+    r = o.run_spots(cfg["spots"], n, cfg["seed"])
+    o.close()
+    os_ = r["summary"]
+    m = compare(gd, gv, r["dose"], r["var"], density_grid(cfg["hu"]), (0.2, 0.2, 0.2), gs["total_weight"],
+                os_["total_weight"])
+    m.update(gpu_res=ledger_residual(gs), ora_res=ledger_residual(os_),
+             gpu_steps=gs["steps"] / n, ora_steps=os_["steps"] / n,
+             gpu_ne=gs["n_nonelastic"], ora_ne=os_["n_nonelastic"], inc_events=gs["inc_events"],
+             gpu_sec=gs["secondaries"], ora_sec=os_["secondaries"], inc_ms=gs["inc_ms"],
+             gpu_neutral=gs["neutral"] / gs["incident"], ora_neutral=os_["neutral"] / os_["incident"])
+    _say("metrics field with the cascade: %s" % m)
+    _assert_transport(m)
+
+
+def test_cascade_with_let_and_options():
+    """The cascade with LET_d scored, Vavilov straggling and Molière
+    scattering in one run (CT, 150 MeV spot) against the oracle with the same
+    options: the dose bars, and LET_d slab-wise within 1% and voxel by voxel
+    closer to the oracle than two oracle seeds are to each other (the local
+    deposits of the cascade stay out of LET_d on both sides)."""
+    nd, mt = synth.nuclear_data(), synth.material_table()
+    cfg = synth.config_ct_spots(150.0, 60_000)
+    flags = pmc.PMC_INC | pmc.PMC_VAVILOV | pmc.PMC_MOLIERE
+    _say("case: cascade + LET_d + Vavilov + Moliere")
+    e = pmc.Engine(0, flags=flags)
+    e.load_physics(nd)
+    e.load_geometry(cfg["hu"], cfg["voxel_cm"], mt)
+    gd, gv, gl, gs = e.run_spots_let(cfg["spots"], cfg["n_histories"], 1)
+    e.close()
+    o = O.Oracle(flags=O.INC | O.VAVILOV | O.MOLIERE)
+    o.load_physics(nd)
+    o.load_geometry(cfg["hu"], cfg["voxel_cm"], mt)
+    r1 = o.run_spots(cfg["spots"], cfg["n_histories"], 1, let=True)
+    r2 = o.run_spots(cfg["spots"], cfg["n_histories"], 2, let=True)
+    o.close()
+    m = compare(gd, gv, r1["dose"], r1["var"], density_grid(cfg["hu"]), (0.2, 0.2, 0.2), gs["total_weight"],
+                r1["summary"]["total_weight"])
+
+    def let_metrics(a, b, dose_b):
+        sel = (dose_b >= 0.1 * dose_b.max()) & (a > 0) & (b > 0)
+        rel = a[sel] / b[sel] - 1.0
+        num_a = np.where(sel, a * dose_b, 0.0).sum(axis=(1, 2))
+        num_b = np.where(sel, b * dose_b, 0.0).sum(axis=(1, 2))
+        den = np.where(sel, dose_b, 0.0).sum(axis=(1, 2))
+        ok = den > 0
+        slab = np.abs(num_a[ok] / num_b[ok] - 1.0)
+        return {"n_sel": int(sel.sum()), "rms": float(np.sqrt(np.mean(rel ** 2))), "slab_max": float(slab.max())}
+
+    same = let_metrics(gl, r1["let"], r1["dose"])
+    indep = let_metrics(r2["let"], r1["let"], r1["dose"])
+    _say("dose %s; LET same seed %s, oracle seeds %s; cascade events %d" % (m, same, indep, gs["inc_events"]))
+    assert gs["inc_events"] == gs["n_nonelastic"] > 0
+    assert m["idd_max_rel"] <= 0.01 and m["r80_diff_mm"] <= 0.2, m
+    assert m["all_within_3sigma"], m
+    assert ledger_residual(gs) < 1e-5
+    assert same["n_sel"] > 500 and same["slab_max"] <= 0.01 and same["rms"] <= indep["rms"], (same, indep)
