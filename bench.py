@@ -80,8 +80,22 @@ def cpu_baseline(cfg, target_s=15.0, single_s=8.0):
     r1 = o1.run_spots(cfg["spots"], n1, 4)
     s1 = r1["summary"]
     o1.close()
+    # the smaller configurations in full on all threads: the water pencil
+    # (1e5 histories) and the CT's three single spots (1e6 histories each)
+    configs = {}
+    for name, c in (("water pencil 100 MeV, 1e5", synth.config_water_pencil(100_000)),
+                    ("CT spot 70 MeV, 1e6", synth.config_ct_spots(70.0, 1_000_000)),
+                    ("CT spot 150 MeV, 1e6", synth.config_ct_spots(150.0, 1_000_000)),
+                    ("CT spot 230 MeV, 1e6", synth.config_ct_spots(230.0, 1_000_000))):
+        oc = O.Oracle()
+        oc.load_physics(nd)
+        oc.load_geometry(c["hu"], c["voxel_cm"], mt)
+        rc = oc.run_spots(c["spots"], c["n_histories"], 1)["summary"]
+        oc.close()
+        configs[name] = {"histories_per_s": c["n_histories"] / rc["wall_s"], "wall_s": rc["wall_s"],
+                         "steps_per_history": rc["steps"] / c["n_histories"]}
     return {"value": n / s["wall_s"], "unit": "histories/s", "cores": int(s["threads"]),
-            "kind": "oracle",
+            "kind": "oracle", "configs": configs,
             "sample": "%d histories of the same 2000-spot field on the same CT (weights-"
                       "proportional allocation), wall %.2f s, %.1f steps/history"
                       % (n, s["wall_s"], s["steps"] / n),
@@ -213,6 +227,37 @@ def _plans_denoiser(plans, spec):
             "note": "one inference per plan on its own dose, networks sized to the plan's grid rounded up to 8"}
 
 
+def _small_configs(args):
+    """The water pencil (1e5 histories) and the CT's single spots at 70, 150
+    and 230 MeV (1e6 histories each) on the GPU: device time of a run, after
+    one untimed run that also tunes the launch shape; the oracle's rates for
+    the same runs are in cpu_baseline.configs."""
+    import torch
+    from paper_1409_8336_amd import pmc, synth
+    res = {}
+    for name, c in (("water pencil 100 MeV, 1e5", synth.config_water_pencil(100_000)),
+                    ("CT spot 70 MeV, 1e6", synth.config_ct_spots(70.0, 1_000_000)),
+                    ("CT spot 150 MeV, 1e6", synth.config_ct_spots(150.0, 1_000_000)),
+                    ("CT spot 230 MeV, 1e6", synth.config_ct_spots(230.0, 1_000_000))):
+        e = pmc.Engine(0, **args.engine_params)
+        e.load_physics(synth.nuclear_data())
+        e.load_geometry(c["hu"], c["voxel_cm"], synth.material_table())
+        d = torch.empty(c["hu"].shape, dtype=torch.float64, device="cuda:0")
+        v = torch.empty_like(d)
+        e.run_spots_dev(c["spots"], c["n_histories"], 1, d, v)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 3
+        for i in range(reps):
+            sm = e.run_spots_dev(c["spots"], c["n_histories"], 2 + i, d, v)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / reps
+        e.close()
+        res[name] = {"histories_per_s": c["n_histories"] / el, "ms_per_run": 1e3 * el,
+                     "device_ms": sm["device_ms"], "steps_per_history": sm["steps"] / c["n_histories"]}
+    return res
+
+
 def bench_ct_spots(args):
     """The 128x128x160 CT with titanium rod, one centred spot at 70, 150 and
     230 MeV, 1e6 histories each: histories/s and steps/s per energy."""
@@ -298,6 +343,9 @@ def bench_denoiser(args, leg=False):
     net.close()
     fwd = unet_forward_flop(*shape[1:])
     peak = 2.5e15
+    # the achievable matrix-core rate on this device: register-only MFMA stream
+    p_ms, p_flop = unet.pmc_nn_mfma_probe(20000)
+    probe = p_flop / (p_ms * 1e-3)
     out = {"metric": "denoiser inferences/s (160x128x128)", "value": 1.0 / t_inf, "unit": "volumes/s",
            "n_gpus": 1, "steps": reps, "warmup": args.warmup, "ms_per_step": 1e3 * t_inf,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -308,7 +356,9 @@ def bench_denoiser(args, leg=False):
                         "unit": "TFLOP/s", "frac": fwd / t_inf / peak, "traffic": None,
                         "kernel": "whole forward (7 convolutions and the elementwise kernels)",
                         "flop_per_forward": fwd,
-                        "train_achieved": 3 * fwd / t_train / 1e12}}
+                        "train_achieved": 3 * fwd / t_train / 1e12,
+                        "mfma_probe_tflops": probe / 1e12,
+                        "frac_of_probe": fwd / t_inf / probe}}
     if leg:
         return out
     print(json.dumps(out), flush=True)
@@ -430,6 +480,7 @@ def main():
                    "grid": list(cfg["hu"].shape[::-1]), "k_batches": 10,
                    "engine_params": args.engine_params},
         "steps_per_s": steps_tot / elapsed,
+        "secondaries_per_s": sum(s["secondaries"] for s in sums) / elapsed,
         "steps_per_history": steps_tot / n_tot,
         "transport_launches_per_step": launches / args.steps,
         "launch_shape": {k: sums[-1][k] for k in ("block_threads", "grid_blocks", "cache_slots",
@@ -562,6 +613,7 @@ def main():
         out["plans_batch"] = {k: pb[k] for k in ("value", "unit", "ms_per_step", "steps", "config",
                                                   "launch_shape", "transport_ms_per_step", "per_plan",
                                                   "denoiser_per_plan", "ledger_residual_max")}
+        out["small_configs"] = _small_configs(args)
         la.steps = 5
         dn = bench_denoiser(la, leg=True)
         out["denoiser"] = {k: dn[k] for k in ("value", "unit", "ms_per_step", "train_step_ms", "config",

@@ -121,6 +121,16 @@ pmc_status pmc_nn_conv3d_backward_weight(const uint16_t* d_x, const uint16_t* d_
                                          int n, int d, int h, int w, int cin, int cout,
                                          void* hip_stream);
 
+/* Matrix-core throughput probe (the achievable BF16 MFMA rate the
+ * convolutions are measured against): every wave of eight 256-lane
+ * workgroups per CU issues iters rounds of eight independent
+ * v_mfma_f32_16x16x32_bf16 on register operands; *ms_out = the best of three
+ * timed launches (after one warm-up), *flop_out = the FLOP of one launch
+ * (16,384 per instruction).  Allocates and frees a small output buffer.
+ * Errors: PMC_ERR_ARG (iters < 1, NULL outputs), PMC_ERR_NOMEM,
+ * PMC_ERR_DEVICE. */
+pmc_status pmc_nn_mfma_probe(int32_t iters, void* hip_stream, double* ms_out, double* flop_out);
+
 /* 3-D gamma index (global dose difference, distance to agreement), Low et
  * al.: for every reference voxel with ref >= cutoff_frac * max(ref),
  * gamma = min over points p of the evaluated distribution (trilinear, on a
@@ -129,7 +139,9 @@ pmc_status pmc_nn_conv3d_backward_weight(const uint16_t* d_x, const uint16_t* d_
  * ref and eval: [nz][ny][nx] float64 device arrays; d_gamma (float32, may be
  * NULL) receives gamma (or -1 below the cutoff).  *pass_rate (host) = the
  * fraction of evaluated voxels with gamma <= 1; *n_eval their count.
- * Synchronous. */
+ * Synchronous.  The reduction counters (32 bytes per device) are allocated
+ * on a device's first call of this function or pmc_denoise_disagreement and
+ * kept; calls of the two are serialised within the process. */
 pmc_status pmc_gamma_index(const double* d_ref, const double* d_eval, int nx, int ny, int nz,
                            float dx_cm, float dy_cm, float dz_cm, float dose_frac, float dta_cm,
                            float cutoff_frac, float search_cm, float step_cm, float* d_gamma,
@@ -142,7 +154,8 @@ pmc_status pmc_gamma_index(const double* d_ref, const double* d_eval, int nx, in
  * (Eq. 5).  A caller falls back to plain Monte Carlo when the fraction
  * exceeds its threshold.  d_den float32, d_mc and d_var_mc float64, n
  * elements each (device).  *frac_out and *n_out (host) receive the fraction
- * and the number of voxels above the cutoff.  Synchronous. */
+ * and the number of voxels above the cutoff.  Synchronous; shares the
+ * counters of pmc_gamma_index. */
 pmc_status pmc_denoise_disagreement(const float* d_den, const double* d_mc, const double* d_var_mc,
                                    int64_t n, float cutoff_frac, float k_sigma, double* frac_out,
                                    int64_t* n_out, void* hip_stream);

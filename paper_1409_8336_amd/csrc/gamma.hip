@@ -6,6 +6,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 
 #include "pmc_unet.h"
 
@@ -114,6 +116,29 @@ __global__ void disagreement_kernel(const float* __restrict__ den, const double*
     }
 }
 
+// The reduction counters of the two entry points below (maximum and two
+// counts): allocated on a device's first call and kept, so that a call
+// allocates nothing; the calls are serialised within the process, since
+// they share a device's counters until the result has been read back.
+std::mutex g_counter_mu;
+std::map<int, unsigned long long*> g_counters;
+
+hipError_t device_counters(unsigned long long** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    auto it = g_counters.find(dev);
+    if (it == g_counters.end()) {
+        unsigned long long* p = nullptr;
+        e = hipMalloc((void**)&p, 4 * sizeof(unsigned long long));
+        if (e != hipSuccess) return e;
+        it = g_counters.emplace(dev, p).first;
+    }
+    *out = it->second;
+    return hipSuccess;
+}
+
 }  // namespace
 
 }  // namespace pmc
@@ -123,8 +148,9 @@ extern "C" pmc_status pmc_denoise_disagreement(const float* den, const double* m
 {
     if (!den || !mc || !var || !frac_out || n <= 0 || !(cutoff >= 0) || !(k > 0)) return PMC_ERR_ARG;
     hipStream_t s = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lock(pmc::g_counter_mu);
     unsigned long long* buf = nullptr;
-    if (hipMalloc((void**)&buf, 3 * sizeof(unsigned long long)) != hipSuccess) return PMC_ERR_NOMEM;
+    if (pmc::device_counters(&buf) != hipSuccess) return PMC_ERR_NOMEM;
     hipError_t e = hipMemsetAsync(buf, 0, 3 * sizeof(unsigned long long), s);
     const unsigned blocks = (unsigned)std::min<size_t>(((size_t)n + 255) / 256, 4096);
     if (e == hipSuccess) {
@@ -139,7 +165,6 @@ extern "C" pmc_status pmc_denoise_disagreement(const float* den, const double* m
     unsigned long long h[3] = {0, 0, 0};
     if (e == hipSuccess) e = hipMemcpyAsync(h, buf, sizeof(h), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFree(buf);
     if (e != hipSuccess) return PMC_ERR_DEVICE;
     *frac_out = h[1] ? (double)h[2] / (double)h[1] : 0.0;
     if (n_out) *n_out = (int64_t)h[1];
@@ -154,8 +179,9 @@ extern "C" pmc_status pmc_gamma_index(const double* ref, const double* ev, int n
         !(dose_frac > 0) || !(dta > 0) || !(cutoff >= 0) || !(search >= 0) || !(step > 0) || search / step > 64)
         return PMC_ERR_ARG;
     hipStream_t s = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lock(pmc::g_counter_mu);
     unsigned long long* buf = nullptr;
-    if (hipMalloc((void**)&buf, 3 * sizeof(unsigned long long)) != hipSuccess) return PMC_ERR_NOMEM;
+    if (pmc::device_counters(&buf) != hipSuccess) return PMC_ERR_NOMEM;
     const size_t nv = (size_t)nx * ny * nz;
     hipError_t e = hipMemsetAsync(buf, 0, 3 * sizeof(unsigned long long), s);
     unsigned blocks = (unsigned)std::min<size_t>((nv + 255) / 256, 8192);
@@ -171,7 +197,6 @@ extern "C" pmc_status pmc_gamma_index(const double* ref, const double* ev, int n
     unsigned long long h[3] = {0, 0, 0};
     if (e == hipSuccess) e = hipMemcpyAsync(h, buf, sizeof(h), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFree(buf);
     if (e != hipSuccess) return PMC_ERR_DEVICE;
     *pass_rate = h[1] ? (double)h[2] / (double)h[1] : 1.0;
     if (n_eval) *n_eval = (int64_t)h[1];

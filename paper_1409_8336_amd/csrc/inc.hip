@@ -673,9 +673,10 @@ __device__ __forceinline__ void stage_words(void* dst, const void* src, int byte
 // so lanes are not held by the longest event of a batch.  The expensive
 // steps wait for company: a collision runs once kCollBatch lanes have one
 // pending (or too few lanes are still flying for that to happen), an
-// evaporation step once kEvapBatch lanes are evaporating; meanwhile the
-// other lanes keep flying.
-constexpr int kCollBatch = 16, kEvapBatch = 8, kRefillIdle = 8;
+// evaporation step once kEvapBatch lanes are evaporating, an entry attempt
+// once kEntryBatch lanes are entering; meanwhile the other lanes keep
+// flying.
+constexpr int kCollBatch = 24, kEvapBatch = 12, kEntryBatch = 8, kRefillIdle = 8;
 constexpr int kClaimRanges = 8;   // the event list in 8 ranges, each with its own claim counter
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
@@ -716,7 +717,14 @@ __device__ void run_events(Src& src, const IncNucleus* nuc, const IncTab& tab, P
         auto emit = [&](int kind, int stage, uint32_t id, double t, const double d[3], int j) {
             src.emit(ev, s, kind, stage, id, t, d, j);
         };
-        if (s.phase == kPhEntry) ev_entry(s, nuc[s.element - 1]);
+        // entry attempts in batches too (an event makes two or three)
+        {
+            const int n_entry = __popcll(__ballot(s.phase == kPhEntry));
+            const int n_fly = __popcll(__ballot(s.phase == kPhFlight));
+            if (n_entry >= kEntryBatch || n_fly < kCollBatch) {
+                if (s.phase == kPhEntry) ev_entry(s, nuc[s.element - 1]);
+            }
+        }
         if (s.phase == kPhFlight) ev_flight(s, nuc[s.element - 1], stack, emit);
         if (s.phase == kPhAttemptEnd) ev_attempt_end(s, nuc[s.element - 1]);
         const int n_run = __popcll(__ballot(s.phase == kPhEntry || s.phase == kPhFlight ||

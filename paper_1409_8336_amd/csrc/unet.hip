@@ -3,6 +3,7 @@
 // the kernels in unet_kernels.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -42,6 +43,7 @@ hipError_t nn_adam(float* p, float* g, float* m1, float* m2, uint16_t* p_bf, siz
                    float eps, float c1, float c2, float gs, hipStream_t s);
 hipError_t nn_sqnorm(const float* g, size_t n, double* out, hipStream_t s);
 hipError_t nn_f32_to_bf16(const float* a, uint16_t* b, size_t n, hipStream_t s);
+hipError_t nn_mfma_probe(int grid, int iters, float* sink, hipStream_t s);
 }  // namespace pmc
 
 using namespace pmc;
@@ -543,6 +545,39 @@ pmc_status pmc_nn_conv3d_backward_data_noalloc(const uint16_t* dy, const uint16_
     hipError_t e = nn_flip_weights(w, wf, cin, cout, kp, kpf, s);
     if (e == hipSuccess) e = nn_conv3d_fwd(dy, wf, nullptr, dx, n, d, h, wd, cout, cin, kpf, 0, s);
     return e == hipSuccess ? PMC_OK : PMC_ERR_DEVICE;
+}
+
+pmc_status pmc_nn_mfma_probe(int32_t iters, void* stream, double* ms_out, double* flop_out)
+{
+    if (iters < 1 || !ms_out || !flop_out) return PMC_ERR_ARG;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return PMC_ERR_DEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    const int grid = 8 * cus;   // eight 4-wave workgroups per CU: eight waves per SIMD
+    float* sink = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipMalloc((void**)&sink, (size_t)grid * 256 * sizeof(float)) != hipSuccess) return PMC_ERR_NOMEM;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    float best = 1e30f;
+    for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {   // the first launch warms up
+        e = hipEventRecord(e0, s);
+        if (e == hipSuccess) e = nn_mfma_probe(grid, iters, sink, s);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float t = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+        if (e == hipSuccess && rep > 0) best = std::min(best, t);
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(sink);
+    if (e != hipSuccess) return PMC_ERR_DEVICE;
+    *ms_out = best;
+    *flop_out = (double)grid * 4.0 * (double)iters * 8.0 * 16384.0;
+    return PMC_OK;
 }
 
 pmc_status pmc_nn_conv3d_backward_weight(const uint16_t* x, const uint16_t* dy, float* dw, int n, int d, int h,

@@ -1018,6 +1018,42 @@ hipError_t nn_f32_to_bf16(const float* a, uint16_t* b, size_t n, hipStream_t s)
     return hipGetLastError();
 }
 
+// Matrix-core throughput probe: every wave issues `iters` rounds of eight
+// independent v_mfma_f32_16x16x32_bf16 on register operands (no memory
+// traffic in the loop); the accumulators are written out once so that the
+// work stays live.  16,384 FLOP per instruction.  The instructions are
+// written out so that each accumulates in place: from the builtin the
+// register allocator rotated the eight accumulators through other registers
+// every iteration (about 18 register moves per 8 MFMAs), which measured the
+// moves, not the matrix cores.
+__global__ void __launch_bounds__(256) mfma_probe_kernel(int iters, float* __restrict__ sink)
+{
+    const int lane = threadIdx.x & 63;
+    bf16x8 a, b;
+    for (int i = 0; i < 8; ++i) {
+        a[i] = (__bf16)(0.001f * (float)(lane + i));
+        b[i] = (__bf16)(0.002f * (float)(lane - i));
+    }
+    f32x4 acc[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            asm volatile("v_mfma_f32_16x16x32_bf16 %0, %1, %2, %0" : "+a"(acc[k]) : "v"(a), "v"(b));
+    }
+    float t = 0.f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) t += acc[k][0] + acc[k][1] + acc[k][2] + acc[k][3];
+    sink[blockIdx.x * blockDim.x + threadIdx.x] = t;
+}
+
+hipError_t nn_mfma_probe(int grid, int iters, float* sink, hipStream_t s)
+{
+    hipLaunchKernelGGL(mfma_probe_kernel, dim3(grid), dim3(256), 0, s, iters, sink);
+    return hipGetLastError();
+}
+
 hipError_t nn_bf16_to_f32(const uint16_t* a, float* b, size_t n, hipStream_t s)
 {
     hipLaunchKernelGGL(bf16_to_f32_kernel, dim3(grid_for(n)), dim3(256), 0, s, a, b, n);

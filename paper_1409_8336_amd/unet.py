@@ -16,7 +16,7 @@ EXPORTS = ("pmc_unet_create", "pmc_unet_destroy", "pmc_unet_last_error", "pmc_un
            "pmc_unet_forward_region",
            "pmc_unet_get_grads", "pmc_unet_zero_grads", "pmc_unet_adam_step", "pmc_unet_grad_norm",
            "pmc_nn_conv3d_forward", "pmc_nn_conv3d_backward_data", "pmc_nn_conv3d_backward_weight",
-           "pmc_nn_conv3d_backward_data_noalloc",
+           "pmc_nn_conv3d_backward_data_noalloc", "pmc_nn_mfma_probe",
            "pmc_gamma_index", "pmc_denoise_disagreement")
 
 _ready = False
@@ -48,6 +48,7 @@ def lib():
         L.pmc_nn_conv3d_forward.argtypes = [vp, vp, vp, vp, i32, i32, i32, i32, i32, i32, i32, vp]
         L.pmc_nn_conv3d_backward_data.argtypes = [vp, vp, vp, i32, i32, i32, i32, i32, i32, vp]
         L.pmc_nn_conv3d_backward_data_noalloc.argtypes = [vp, vp, vp, i32, i32, i32, i32, i32, i32, vp]
+        L.pmc_nn_mfma_probe.argtypes = [i32, vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.pmc_nn_conv3d_backward_weight.argtypes = [vp, vp, vp, i32, i32, i32, i32, i32, i32, vp]
         L.pmc_gamma_index.argtypes = [vp, vp, i32, i32, i32, f32, f32, f32, f32, f32, f32, f32, f32,
                                       vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), vp]
@@ -215,6 +216,16 @@ def pmc_nn_conv3d_backward_data_noalloc(dy, w, dx, stream=None):
     _check(None, lib().pmc_nn_conv3d_backward_data_noalloc(_bf16(dy, "dy"), _bf16(w, "w"), _bf16(dx, "dx"),
                                                            n, d, h, wd, cin, cout,
                                                            _stream(stream, dy.device)))
+
+
+def pmc_nn_mfma_probe(iters=20000, stream=None):
+    """(best launch ms, FLOP per launch) of the matrix-core throughput probe."""
+    ms, flop = C.c_double(), C.c_double()
+    h = None
+    if stream is not None:
+        h = C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else stream)
+    _check(None, lib().pmc_nn_mfma_probe(int(iters), h, C.byref(ms), C.byref(flop)))
+    return ms.value, flop.value
 
 
 def pmc_nn_conv3d_backward_weight(x, dy, dw, stream=None):

@@ -429,3 +429,14 @@ def test_gamma_full_size_sampled():
             assert abs(g[z, y, x] - o) <= 1e-5 * max(1.0, o), (z, y, x, g[z, y, x], o)
     assert n == int((ref >= 0.1 * ref.max()).sum())
     _say("full-size gamma pass rate %.4f over %d voxels" % (rate, n))
+
+
+def test_mfma_probe_rate_is_plausible():
+    """The matrix-core probe: a register-only BF16 MFMA stream over the whole
+    device reaches a substantial part of the 2.5 PFLOP/s dense peak and never
+    exceeds it."""
+    U = _unet()
+    ms, flop = U.pmc_nn_mfma_probe(4000)
+    tflops = flop / (ms * 1e-3) / 1e12
+    _say("MFMA probe: %.1f TFLOP/s (%.3f ms for %.3g FLOP)" % (tflops, ms, flop))
+    assert 500.0 < tflops < 2600.0, tflops
