@@ -36,7 +36,10 @@
  *   secondary sampler ........ pinned (multiplicity / marginals vs table)
  *   energy ledger ............ pinned (conservation identity)
  *   10-group variance ........ pinned (numpy on the batch tallies; Eq. 5)
- *   full heterogeneous dose .. parity unpinned beyond the pieces above
+ *   composed transport ....... pinned (all physics on: a half slab of bone or
+ *                              lung shifts R80 by t (rho f - 1), the water
+ *                              side's R80 sits at the PSTAR CSDA range)
+ *   full 3-D heterogeneous dose  parity unpinned beyond the pieces above
  */
 #include "pmc_oracle.h"
 

@@ -316,3 +316,31 @@ def test_cascade_with_let_and_options():
     assert m["all_within_3sigma"], m
     assert ledger_residual(gs) < 1e-5
     assert same["n_sel"] > 500 and same["slab_max"] <= 0.01 and same["rms"] <= indep["rms"], (same, indep)
+
+
+def test_cascade_event_list_overflow_is_reported_and_ledger_closes():
+    """An event list (and generation queue) far too small for the run: the
+    events beyond it and the protons that do not fit are booked as overflow,
+    the run reports PMC_ERR_QUEUE_OVERFLOW, and the ledger still closes."""
+    import ctypes as C
+    _say("case: cascade event-list overflow (230 MeV pencil in water, 2e4 histories, capacity 64)")
+    nd, mt = synth.nuclear_data(), synth.material_table()
+    hu = synth.water_phantom(32, 32, 170)
+    e = pmc.Engine(0, flags=pmc.PMC_INC, queue_capacity=64, local_queue=-1)
+    e.load_physics(nd)
+    e.load_geometry(hu, (0.2, 0.2, 0.2), mt)
+    dose = np.zeros(hu.shape)
+    var = np.zeros(hu.shape)
+    summ = pmc.pmc_summary()
+    st = pmc.lib().pmc_run_spots(e.ctx, pmc._ptr(synth.pencil_spot(3.2, 3.2, 230.0, 0.3)), 1, 20000, 1,
+                                 pmc._ptr(dose), pmc._ptr(var), C.byref(summ))
+    s = pmc.summary_dict(summ)
+    e.close()
+    _say("status %d, events %d, non-elastic %d, overflow entries %d" % (st, s["inc_events"], s["n_nonelastic"],
+                                                                         s["n_overflow"]))
+    assert st == pmc.PMC_ERR_QUEUE_OVERFLOW
+    assert s["n_overflow"] > 0 and s["overflow"] > 0
+    # the first generation's list held 64 events; the rest of its events overflowed
+    assert 0 < s["inc_events"] < s["n_nonelastic"]
+    assert ledger_residual(s) < 1e-9
+    assert dose.sum() > 0

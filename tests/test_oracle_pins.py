@@ -15,6 +15,7 @@ import pytest
 from scipy import integrate, optimize, stats
 
 from oracle import oracle as O
+from parity_tools import r80
 from paper_1409_8336_amd import synth
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -220,6 +221,49 @@ def test_deterministic_depth_dose(lib, water_za, hu, e0):
     assert abs(idd.sum() - e0) <= 1e-9 * e0
     s = out["summary"]
     assert s["escaped"] == 0.0 and s["neutral"] == 0.0
+
+
+@pytest.mark.parametrize("hu_slab", [1000, -800])
+def test_half_slab_shifts_the_range_by_its_water_equivalent_thickness(hu_slab):
+    """The composed transport in a heterogeneous phantom, all physics on
+    (straggling, multiple scattering, nuclear interactions and secondaries):
+    water with a 2 cm slab (bone or lung) at 4-6 cm depth over the half x >=
+    6 cm only.  Under the water-equivalent scaling of Eq. 1-2 a slab of
+    density rho and stopping-power ratio f shortens the range by
+    t (rho f - 1) (lengthens it for lung); a 150 MeV pencil through the slab
+    half must show that shift in R80, the pencil through the water half none:
+    R80 there sits at the PSTAR CSDA range of water (Bortfeld's Bragg-curve
+    model puts the distal 80% point at the mean range; 0.5% allowed).  A
+    wrong voxel lookup (x and y exchanged: both pencils would cross the
+    slab), the density without f (or f without the density) or a boundary
+    crossing that loses or repeats path all move the shift by more than
+    0.3 mm.  1 mm depth voxels: with 2 mm ones, R80's linear interpolation on
+    the steep fall-off alone is off by up to 0.3 mm."""
+    nx, ny, dz = 60, 30, 0.1
+    nz = int(round(20.0 / dz))
+    hu = np.zeros((nz, ny, nx), np.int16)
+    hu[int(round(4.0 / dz)):int(round(6.0 / dz)), :, nx // 2:] = hu_slab
+    mt = synth.material_table()
+    lo = mt["hu_lo"].astype(int)
+    b = int(np.searchsorted(lo, hu_slab, side="right") - 1)
+    hi = int(lo[b + 1]) if b + 1 < len(lo) else 3000
+    rho = float(mt["rho_lo"][b]) + (float(mt["rho_hi"][b]) - float(mt["rho_lo"][b])) * (hu_slab - lo[b]) / (hi - lo[b])
+    o = O.Oracle(flags=0)
+    o.load_physics(synth.nuclear_data())
+    o.load_geometry(hu, (0.2, 0.2, dz), mt)
+    info = o.material_info(b)
+    assert not info["own"]
+    want = 2.0 * (rho * info["f"] - 1.0)
+    r80s = {}
+    for side, x in (("water", 3.0), ("slab", 9.0)):
+        out = o.run_spots(synth.pencil_spot(x, 3.0, 150.0, 0.3), 20000, 11)
+        edep = out["dose"] * np.where(hu == hu_slab, rho, 1.0)
+        half = edep[:, :, : nx // 2] if side == "water" else edep[:, :, nx // 2:]
+        r80s[side] = r80(half.sum(axis=(1, 2)), dz)
+    got = r80s["water"] - r80s["slab"]
+    assert abs(got - want) < 0.02, (got, want, r80s)
+    r_csda = [float(r[2]) for r in _golden("water_stopping_pstar.txt") if float(r[0]) == 150.0][0]
+    assert abs(r80s["water"] / r_csda - 1) < 0.005, (r80s, r_csda)
 
 
 # ---------------------------------------------------------------------------
