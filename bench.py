@@ -224,7 +224,7 @@ def _plans_denoiser(plans, spec):
         ms.append(1e3 * (time.perf_counter() - t0) / 3)
         net.close()
     return {"ms": ms, "total_ms": sum(ms),
-            "note": "one inference per plan on its own dose, networks sized to the plan's grid rounded up to 8"}
+            "note": "one inference per plan on its own dose, networks sized to the plan's grid rounded up to 8; initial (untrained) weights: the kernels and their time do not depend on the values"}
 
 
 def _small_configs(args):
@@ -382,6 +382,9 @@ def main():
     ap.add_argument("--inc-steps", type=int, default=2,
                     help="field workload: also time this many runs with non-elastic events by the "
                          "intranuclear cascade (PMC_INC; 0 = skip)")
+    ap.add_argument("--option-steps", type=int, default=2,
+                    help="field workload: also time this many runs with Vavilov-Gaussian "
+                         "straggling and, separately, Moliere scattering (0 = skip)")
     ap.add_argument("--no-legs", dest="legs", action="store_false",
                     help="field workload: skip the 16-plan batch and denoiser legs")
     ap.add_argument("--no-replay", action="store_true",
@@ -487,7 +490,7 @@ def main():
                                                    "epoch_steps", "refill_lanes", "batch_events")},
         "transport_ms_per_step": 1e3 * transport_s / args.steps,
         "ledger_residual_max": worst_res,
-        # roofline of the transport (SURVEY's protocol): its own address
+        # roofline of the transport against the replay of its own address
         # stream -- every step's 8-B voxel gather and 8-B FP64 tally add, in
         # the traced run's order, grid, workgroups, lanes and epochs -- replayed
         # without the physics; the slower of the gather replay and the faster
@@ -603,6 +606,40 @@ def main():
                                            - s["overflow"]) / s["incident"] for s in isums),
             "steps": k,
         }
+    # the transport options of Sec. II.A.2 on the same workload: each in an
+    # engine of its own (its first run tunes the launch shape)
+    if args.option_steps > 0:
+        out["options"] = {}
+        dose_rate = n_tot / elapsed
+        for name, flag in (("vavilov", pmc.PMC_VAVILOV), ("moliere", pmc.PMC_MOLIERE)):
+            params = dict(args.engine_params)
+            params["flags"] = int(params.get("flags", 0)) | flag
+            eo = pmc.Engine(0, **params)
+            eo.load_physics(synth.nuclear_data())
+            eo.load_geometry(cfg["hu"], cfg["voxel_cm"], synth.material_table())
+            eo.run_spots_dev(cfg["spots"], cfg["n_histories"], cfg["seed"], d_dose, d_var, stream)
+            torch.cuda.synchronize()
+            osums = []
+            t0 = time.perf_counter()
+            for i in range(args.option_steps):
+                osums.append(eo.run_spots_dev(cfg["spots"], cfg["n_histories"], cfg["seed"] + i, d_dose, d_var,
+                                              stream))
+            torch.cuda.synchronize()
+            o_elapsed = time.perf_counter() - t0
+            eo.close()
+            k = args.option_steps
+            out["options"][name] = {
+                "histories_per_s": k * cfg["n_histories"] / o_elapsed,
+                "rate_vs_default": (k * cfg["n_histories"] / o_elapsed) / dose_rate,
+                "ms_per_step": 1e3 * o_elapsed / k,
+                "transport_ms_per_step": sum(s["transport_ms"] for s in osums) / k,
+                "steps_per_history": sum(s["steps"] for s in osums) / (k * cfg["n_histories"]),
+                "launch_shape": {kk: osums[-1][kk] for kk in ("block_threads", "grid_blocks", "cache_slots",
+                                                              "refill_lanes", "batch_events")},
+                "ledger_residual_max": max(abs(s["incident"] - s["deposited"] - s["escaped"] - s["neutral"]
+                                               - s["overflow"]) / s["incident"] for s in osums),
+                "steps": k,
+            }
     # the other workloads, briefly, so that the same run records them: the
     # uneven 16-plan batch (config 5) and the denoiser (config 4)
     if args.legs:
