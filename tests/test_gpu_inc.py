@@ -106,6 +106,33 @@ def test_cascade_events_match_the_oracle(eng):
         assert _energy_closes(res[i], parts[i], t[i]), (i, res[i])
 
 
+def test_cascade_events_at_the_energy_extremes_match_the_oracle(eng):
+    """The ends of the accepted energy range: 0.5 and 2 MeV (far below the
+    well depth: most collision candidates Pauli-blocked, several entry
+    attempts per event), 8 MeV, and 400 and 1000 MeV (long cascades with
+    many emitted nucleons); 60 events per element and energy, every event
+    compared with the oracle's."""
+    seed = 11
+    el, t, uid, ks = _event_batch(60, (0.5, 2.0, 8.0, 400.0, 1000.0), seed=9)
+    _say("case: %d cascade events at 0.5-1000 MeV, seed %d" % (len(el), seed))
+    res, parts = pmc.pmc_inc_events(eng.ctx, el, t, uid, ks, seed)
+    differ = []
+    for i in range(len(el)):
+        o = O.inc_event(int(el[i]), float(t[i]), seed, int(uid[i]), int(ks[i]))
+        ok, why = _same_event(res[i], parts[i], o)
+        if not ok:
+            differ.append((i, float(t[i]), why))
+        assert _energy_closes(res[i], parts[i], t[i]), (i, res[i])
+    _say("events differing: %d of %d %s" % (len(differ), len(el), differ[:10]))
+    assert len(differ) <= max(1, int(0.002 * len(el))), differ[:20]
+    # the low end is dominated by Pauli blocking and repeated entries, the
+    # high end makes long cascades
+    low = np.nonzero(t < 1.0)[0]
+    assert np.mean([res[i]["n_blocked"] for i in low]) >= 5.0
+    assert np.mean([res[i]["attempts"] for i in low]) > 1.5
+    assert max(res[i]["n_out"] for i in np.nonzero(t > 900.0)[0]) >= 8
+
+
 def test_cascade_proton_spectra_match_the_oracle(eng):
     """Emitted-proton energy and polar-angle spectra of 2000 events on O-16
     and on Ti-48 at 150 MeV: the histograms of the two sides agree bin by
