@@ -759,11 +759,13 @@ struct RangeClaim {
         unsigned long long base = 0;
         int g = 0;
         if (lane_id() == 0) {
+            // (a range's counter may run past its end: the claim then
+            // moves on to the next range)
             for (int k = 0; k < kClaimRanges && g == 0; ++k) {
                 const int rr = (home + k) % kClaimRanges;
                 const unsigned long long lo = n * (unsigned long long)rr / kClaimRanges;
                 const unsigned long long hi = n * (unsigned long long)(rr + 1) / kClaimRanges;
-                if (__hip_atomic_load(&ctr[rr], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= hi - lo) continue;
+                if (lo == hi) continue;
                 const unsigned long long off = atomicAdd(&ctr[rr], (unsigned long long)want);
                 if (lo + off < hi) {
                     base = lo + off;
@@ -853,11 +855,11 @@ constexpr int kStageWords = 6;    // event index, child id, energy (FP32), direc
 // with the azimuth convention of the transport's scattering, written with
 // cos and sin of the emission azimuth as d_x / sin(theta), d_y / sin(theta);
 // its uid the first two words of the event's block with tag 0xC0000000 | id.
-__device__ __noinline__ bool write_child(const IncLaunch& a, const IncEvent& ev, uint32_t id, float tf, float dx,
-                                         float dy, float dz, unsigned long long slot)
+__device__ __noinline__ bool write_child(const IncLaunch& a, const PlanDesc* pds, const IncEvent& ev, uint32_t id,
+                                         float tf, float dx, float dy, float dz, unsigned long long slot)
 {
     if (slot >= a.q_cap) return false;
-    const PlanDesc& pd = a.plans[ev.plan];
+    const PlanDesc& pd = pds[ev.plan];
     const float u = ev.ux, v = ev.uy, w = ev.uz;
     const float perp = sqrtf(u * u + v * v);
     float cx, cy, cz;
@@ -892,6 +894,7 @@ struct TransportSrc {
     uint32_t* n_staged;            // its fill
     double (*led)[2];
     unsigned long long (*cnt)[3];
+    const PlanDesc* pds;           // the plan descriptors (LDS copy)
     // the lane's event
     double local, neutral, ovf;
     unsigned long long n_sec;
@@ -899,7 +902,7 @@ struct TransportSrc {
     __device__ void begin(unsigned long long i, EvState& s)
     {
         const IncEvent& ev = a.ev[i];
-        const PlanDesc& pd = a.plans[ev.plan];
+        const PlanDesc& pd = pds[ev.plan];
         const Stream st{pd.key_lo, pd.key_hi, ev.uid_lo, ev.uid_hi, ev.ks};
         local = neutral = ovf = 0.0;
         n_sec = 0;
@@ -941,13 +944,13 @@ struct TransportSrc {
         }
         // the stage is full: this child reserves its own slot
         const IncEvent ev = a.ev[i];
-        if (!write_child(a, ev, id, tf, (float)d[0], (float)d[1], (float)d[2], atomicAdd(a.out_reserve, 1ull)))
+        if (!write_child(a, pds, ev, id, tf, (float)d[0], (float)d[1], (float)d[2], atomicAdd(a.out_reserve, 1ull)))
             ovf += (double)ev.w * (double)tf;
     }
     __device__ void finish(unsigned long long i, const EvState& s)
     {
         const IncEvent& ev = a.ev[i];
-        const PlanDesc& pd = a.plans[ev.plan];
+        const PlanDesc& pd = pds[ev.plan];
         const double w = (double)ev.w;
         if (s.r.attempts > 0) neutral += s.r.binding + s.r.e_star_fin;
         if (local != 0.0) {
@@ -983,7 +986,7 @@ struct TransportSrc {
             const uint32_t* e = stg + j * kStageWords;
             const IncEvent ev = a.ev[e[0]];
             const float tf = __uint_as_float(e[2]);
-            if (!write_child(a, ev, e[1], tf, __uint_as_float(e[3]), __uint_as_float(e[4]), __uint_as_float(e[5]),
+            if (!write_child(a, pds, ev, e[1], tf, __uint_as_float(e[3]), __uint_as_float(e[4]), __uint_as_float(e[5]),
                              qb + j))
                 atomicAdd(&led[ev.plan][1], (double)ev.w * (double)tf);
         }
@@ -1003,8 +1006,10 @@ __global__ void __launch_bounds__(kIncBlock) inc_transport_kernel(IncLaunch a)
     __shared__ unsigned long long cnt[kMaxPlans][3];
     __shared__ uint32_t stage[kIncWaves][kStageW * kStageWords];
     __shared__ uint32_t n_staged[kIncWaves];
+    __shared__ PlanDesc pds[kMaxPlans];
     stage_words(nuc, a.nuclei, (int)sizeof(nuc));
     stage_words(&tb, a.tab, (int)sizeof(IncTab));
+    stage_words(pds, a.plans, a.n_plans * (int)sizeof(PlanDesc));
     for (int p = threadIdx.x; p < a.n_plans; p += blockDim.x) {
         led[p][0] = led[p][1] = 0.0;
         cnt[p][0] = cnt[p][1] = cnt[p][2] = 0ull;
@@ -1016,7 +1021,7 @@ __global__ void __launch_bounds__(kIncBlock) inc_transport_kernel(IncLaunch a)
     const unsigned long long n = rec < a.ev_cap ? rec : a.ev_cap;
     Part stack[kIncMaxParticles];
     TransportSrc src{a, {a.claim, n, (int)(blockIdx.x % kClaimRanges)}, n, stage[wave], &n_staged[wave], led, cnt,
-                     0.0, 0.0, 0.0, 0ull};
+                     pds, 0.0, 0.0, 0.0, 0ull};
     run_events(src, nuc, tb, stack);
     __syncthreads();
     for (int p = threadIdx.x; p < a.n_plans; p += blockDim.x) {
