@@ -1350,6 +1350,7 @@ pmc_status pmc_inc_events(pmc_ctx* c, const int32_t* element, const double* t_me
     HIPCHK(d_uid.ensure(n), "alloc events");
     HIPCHK(d_ks.ensure(n), "alloc events");
     HIPCHK(d_res.ensure(n), "alloc results");
+    HIPCHK(hipMemset(d_res.p, 0, sizeof(IncResult) * (size_t)n), "clear results");   // (unworked: attempts 0)
     HIPCHK(d_out.ensure((size_t)n * kIncMaxOut), "alloc particles");
     HIPCHK(d_ctr.ensure(8), "alloc claim counters");
     HIPCHK(hipMemset(d_ctr.p, 0, 64), "zero claim counters");

@@ -669,14 +669,14 @@ __device__ __forceinline__ void stage_words(void* dst, const void* src, int byte
 
 // ------------------------------------------------------- wave scheduling
 // A wave runs its 64 lanes' events side by side, one step per lane and loop
-// iteration, and gives an idle lane a new event as soon as eight are idle,
+// iteration, and gives an idle lane a new event as soon as six are idle,
 // so lanes are not held by the longest event of a batch.  The expensive
 // steps wait for company: a collision runs once kCollBatch lanes have one
 // pending (or too few lanes are still flying for that to happen), an
 // evaporation step once kEvapBatch lanes are evaporating, an entry attempt
 // once kEntryBatch lanes are entering; meanwhile the other lanes keep
 // flying.
-constexpr int kCollBatch = 24, kEvapBatch = 12, kEntryBatch = 8, kRefillIdle = 8;
+constexpr int kCollBatch = 24, kEvapBatch = 12, kEntryBatch = 8, kRefillIdle = 6;
 constexpr int kClaimRanges = 8;   // the event list in 8 ranges, each with its own claim counter
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
@@ -693,7 +693,10 @@ __device__ void run_events(Src& src, const IncNucleus* nuc, const IncTab& tab, P
     EvState s;
     s.phase = kPhIdle;
     unsigned long long ev = 0;
-    bool more = src.n > 0;   // (wave-uniform)
+    // (wave-uniform) the last claim found events: a claim returns fewer than
+    // asked near the end of a range of the list, none once every range is
+    // used up, and only that ends the wave's claims
+    bool more = src.n > 0;
     for (;;) {
         // refill: idle lanes take new events, one claim for the wave
         const unsigned long long idle = __ballot(s.phase == kPhIdle);
@@ -701,7 +704,7 @@ __device__ void run_events(Src& src, const IncNucleus* nuc, const IncTab& tab, P
         if (more && (n_idle >= kRefillIdle || n_idle == 64)) {
             int got = 0;
             const unsigned long long base = src.claim(n_idle, &got);
-            if (got < n_idle) more = false;
+            if (got == 0) more = false;
             if (s.phase == kPhIdle) {
                 const int rank = wave_mbcnt(idle);
                 if (rank < got) {

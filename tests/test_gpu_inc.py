@@ -133,6 +133,27 @@ def test_cascade_events_at_the_energy_extremes_match_the_oracle(eng):
     assert max(res[i]["n_out"] for i in np.nonzero(t > 900.0)[0]) >= 8
 
 
+@pytest.mark.parametrize("n", [1, 37, 300])
+def test_small_event_lists_are_worked_completely(eng, n):
+    """Lists far shorter than the grid's claims (one workgroup, several of
+    the eight claim ranges holding a handful of events or none): every event
+    is worked, and each is the oracle's."""
+    seed = 5
+    rng = np.random.default_rng(n)
+    el = rng.integers(1, 7, size=n).astype(np.int32)
+    t = rng.uniform(5.0, 250.0, size=n)
+    uid = rng.integers(0, 2**40, size=n).astype(np.uint64)
+    ks = rng.integers(0, 300, size=n).astype(np.uint32)
+    _say("case: %d cascade events" % n)
+    res, parts = pmc.pmc_inc_events(eng.ctx, el, t, uid, ks, seed)
+    for i in range(n):
+        # an event that was never worked keeps attempts == 0
+        assert res[i]["attempts"] >= 1, (i, res[i])
+        o = O.inc_event(int(el[i]), float(t[i]), seed, int(uid[i]), int(ks[i]))
+        ok, why = _same_event(res[i], parts[i], o)
+        assert ok, (i, why)
+
+
 def test_cascade_proton_spectra_match_the_oracle(eng):
     """Emitted-proton energy and polar-angle spectra of 2000 events on O-16
     and on Ti-48 at 150 MeV: the histograms of the two sides agree bin by
