@@ -16,7 +16,7 @@ import pytest
 from oracle import oracle as O
 from paper_1409_8336_amd import pmc, synth
 
-from parity_tools import assert_same_seed, compare, density_grid, ledger_residual
+from parity_tools import assert_same_seed, compare, density_grid, ledger_residual, r80
 
 pytestmark = pytest.mark.gpu
 
@@ -149,6 +149,45 @@ def test_ct_spot_parity(nd, mt, energy):
     cfg = synth.config_ct_spots(energy, 1_000_000)
     m, gs, os_ = _parity(nd, mt, cfg["hu"], cfg["spots"], cfg["n_histories"], tag="ct%g" % energy)
     _assert_parity(m)
+
+
+def test_half_slab_with_anisotropic_voxels(nd, mt):
+    """Water with 2 cm of bone (HU 1000) at 4-6 cm depth over the half x >= 6
+    cm, in 2 x 2 x 1 mm voxels (every other test uses 2 mm cubes), two
+    150 MeV pencils, one through each half: same-seed dose parity with the
+    oracle, and on the GPU's dose the slab half's R80 shorter than the water
+    half's by the slab's t (rho f - 1) within 0.2 mm (the oracle's own pin of
+    the composed transport)."""
+    nx, ny, dz = 60, 30, 0.1
+    nz = int(round(20.0 / dz))
+    hu = np.zeros((nz, ny, nx), np.int16)
+    hu[int(round(4.0 / dz)):int(round(6.0 / dz)), :, nx // 2:] = 1000
+    voxel = (0.2, 0.2, dz)
+    spots = np.concatenate([synth.pencil_spot(3.0, 3.0, 150.0, 0.3), synth.pencil_spot(9.0, 3.0, 150.0, 0.3)])
+    n = 200_000
+    _say("case: half slab, anisotropic voxels, n=%d" % n)
+    e = _engine(nd, mt, hu, voxel)
+    gd, gv, gs = e.run_spots(spots, n, 3)
+    e.close()
+    o = _oracle(nd, mt, hu, voxel)
+    r = o.run_spots(spots, n, 3)
+    lo = mt["hu_lo"].astype(int)
+    b = int(np.searchsorted(lo, 1000, side="right") - 1)
+    f = o.material_info(b)["f"]
+    o.close()
+    rho_grid = density_grid(hu)
+    m = compare(gd, gv, r["dose"], r["var"], rho_grid, voxel, gs["total_weight"], r["summary"]["total_weight"])
+    m.update(gpu_res=ledger_residual(gs), ora_res=ledger_residual(r["summary"]),
+             gpu_steps_per_hist=gs["steps"] / n, ora_steps_per_hist=r["summary"]["steps"] / n)
+    _say("metrics half slab: %s" % m)
+    _assert_parity(m)
+    rho = float(rho_grid[int(round(5.0 / dz)), 0, nx - 1])
+    edep = gd * rho_grid
+    r_water = r80(edep[:, :, : nx // 2].sum(axis=(1, 2)), dz)
+    r_slab = r80(edep[:, :, nx // 2:].sum(axis=(1, 2)), dz)
+    want = 2.0 * (rho * f - 1.0)
+    _say("R80 water %.4f slab %.4f shift %.4f want %.4f cm" % (r_water, r_slab, r_water - r_slab, want))
+    assert abs((r_water - r_slab) - want) < 0.02
 
 
 def test_independent_seeds_are_consistent(nd, mt):
