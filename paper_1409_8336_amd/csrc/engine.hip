@@ -810,38 +810,44 @@ pmc_status choose_shape(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, hipS
         *out = it->second;
         return PMC_OK;
     }
-    // calibration work: a fifth of the run, 2e5 to 2e6 histories, enough to
-    // reach the steady state of a full grid of 1024-lane workgroups.  Every
-    // plan contributes eight runs of consecutive spots spread evenly over its
-    // list (every energy layer of a field is represented), with their own
-    // history counts, up to its share of the work: consecutive spots keep the
-    // spatial coherence the deposit cache relies on.
-    const double cal_hist = std::min(2.0e6, std::max(2.0e5, 0.2 * (double)total));
-    const double f = cal_hist / (double)total;
+    // every plan contributes eight runs of consecutive spots spread evenly
+    // over its list (every energy layer of a field is represented), with
+    // their own history counts, up to a fraction f of its work: consecutive
+    // spots keep the spatial coherence the deposit cache relies on
     constexpr int kCalBlocks = 8;
-    std::vector<PlanIn> cal = plans;
-    std::vector<std::vector<pmc_spot>> cal_spots(cal.size());
-    for (size_t pi = 0; pi < cal.size(); ++pi) {
-        PlanIn& p = cal[pi];
-        double wsum = 0.0;
-        for (int i = 0; i < p.n_spots; ++i) wsum += p.spots[i].weight;
-        const double goal = f * (double)p.n_hist;
-        std::vector<pmc_spot>& sel = cal_spots[pi];
-        double acc = 0.0;
-        for (int blk = 0; blk < kCalBlocks; ++blk) {
-            int m = (int)(((long long)blk * p.n_spots) / kCalBlocks);
-            const double blk_goal = goal * (blk + 1) / kCalBlocks;
-            while (m < p.n_spots && (acc < blk_goal || sel.empty())) {
-                acc += wsum > 0.0 ? (double)p.n_hist * p.spots[m].weight / wsum : 0.0;
-                sel.push_back(p.spots[m]);
-                ++m;
+    auto sample = [&](double f, std::vector<PlanIn>& cal, std::vector<std::vector<pmc_spot>>& cal_spots) {
+        cal = plans;
+        cal_spots.assign(cal.size(), {});
+        for (size_t pi = 0; pi < cal.size(); ++pi) {
+            PlanIn& p = cal[pi];
+            p.summary = nullptr;
+            if (f >= 1.0) continue;
+            double wsum = 0.0;
+            for (int i = 0; i < p.n_spots; ++i) wsum += p.spots[i].weight;
+            const double goal = f * (double)p.n_hist;
+            std::vector<pmc_spot>& sel = cal_spots[pi];
+            double acc = 0.0;
+            for (int blk = 0; blk < kCalBlocks; ++blk) {
+                int m = (int)(((long long)blk * p.n_spots) / kCalBlocks);
+                const double blk_goal = goal * (blk + 1) / kCalBlocks;
+                while (m < p.n_spots && (acc < blk_goal || sel.empty())) {
+                    acc += wsum > 0.0 ? (double)p.n_hist * p.spots[m].weight / wsum : 0.0;
+                    sel.push_back(p.spots[m]);
+                    ++m;
+                }
             }
+            p.spots = sel.data();
+            p.n_spots = (int)sel.size();
+            p.n_hist =
+                std::max<unsigned long long>(1ull, (unsigned long long)std::llround(std::min(acc, (double)p.n_hist)));
         }
-        p.spots = sel.data();
-        p.n_spots = (int)sel.size();
-        p.n_hist = std::max<unsigned long long>(1ull, (unsigned long long)std::llround(std::min(acc, (double)p.n_hist)));
-        p.summary = nullptr;
-    }
+    };
+    // calibration work: a fifth of the run, 2e5 to 2e6 histories, enough to
+    // reach the steady state of a full grid of 1024-lane workgroups
+    const double cal_hist = std::min(2.0e6, std::max(2.0e5, 0.2 * (double)total));
+    std::vector<PlanIn> cal;
+    std::vector<std::vector<pmc_spot>> cal_spots;
+    sample(cal_hist / (double)total, cal, cal_spots);
     std::vector<Shape> cands;
     for (int b : {256, 512, 1024})
         for (int r : {8, 16})
@@ -880,10 +886,41 @@ pmc_status choose_shape(pmc_ctx* c, std::vector<PlanIn>& plans, bool multi, hipS
             if (st2 != PMC_OK) return st2;
             times[k].first = std::min(times[k].first, r.transport_ms);
         }
-    size_t best_k = 0;
-    for (size_t k = 1; k < n_final; ++k)
-        if (times[k].first < times[best_k].first) best_k = k;
-    const Shape best_s = cands[times[best_k].second];
+    std::sort(times.begin(), times.end());
+    int best_i = times[0].second;
+    // the best shape of each workgroup size once more on a sample as large
+    // as the run (up to 2e7 histories, best of two each): the workgroup size
+    // sets the occupancy and the cache size, and shapes that come out within
+    // a few per cent on the calibration sample can differ by more on the
+    // whole field
+    if (total > (unsigned long long)cal_hist) {
+        std::vector<int> finalists;
+        for (const auto& t : times) {
+            bool seen = false;
+            for (int f : finalists) seen |= cands[f].block == cands[t.second].block;
+            if (!seen) finalists.push_back(t.second);
+        }
+        if (finalists.size() > 1) {
+            std::vector<PlanIn> big;
+            std::vector<std::vector<pmc_spot>> big_spots;
+            sample(std::min(1.0, 2.0e7 / (double)total), big, big_spots);
+            double best_t = 1e300;
+            for (int f : finalists) {
+                double t_f = 1e300;
+                for (int rep = 0; rep < 2; ++rep) {
+                    RunResult r;
+                    pmc_status st2 = run_driver(c, big, multi, cands[f], st, true, &r);
+                    if (st2 != PMC_OK) return st2;
+                    t_f = std::min(t_f, r.transport_ms);
+                }
+                if (t_f < best_t) {
+                    best_t = t_f;
+                    best_i = f;
+                }
+            }
+        }
+    }
+    const Shape best_s = cands[best_i];
     c->tuned[key] = best_s;
     *out = best_s;
     return PMC_OK;
