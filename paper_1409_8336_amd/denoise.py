@@ -222,6 +222,74 @@ def evaluate(sim, net, data, rows, log=_log, sweep=SWEEP):
     return out
 
 
+def evaluate_plans(sim, params, plans, n_low=100_000, n_ref=100_000_000, log=_log, sweep=SWEEP):
+    """Time-to-gamma on the uneven plans of the batch workload: per plan the
+    reference is its n_ref-history dose, the denoiser input its n_low-history
+    dose (a network of the trained weights sized to the plan's grid rounded
+    up to multiples of 8, the plan at the origin, zero outside), and plain
+    Monte Carlo is swept over `sweep`; also the pass rate of the plan's own
+    history count."""
+    torch = sim.torch
+    out = []
+    for pi, plan in enumerate(plans):
+        sim.load(plan)
+        d, h, w = (int(v) for v in plan["hu"].shape)
+        net = unet.UNet((1,) + tuple(-(-v // 8) * 8 for v in (d, h, w)), seed=0)
+        net.set_params(params)
+        for n in sweep + (n_low, plan["n_histories"]):   # launch-shape calibration outside the timed runs
+            sim.run(plan["spots"], n, 1, var=False)
+        ref, _, t_ref = sim.run(plan["spots"], n_ref, 50_000 + pi, var=False)
+        low, var_low, t_low = sim.run(plan["spots"], n_low, 60_000 + pi)
+        own, _, t_own = sim.run(plan["spots"], plan["n_histories"], 70_000 + pi, var=False)
+        rho = sim.density()
+        low32 = low.float()
+        den = torch.empty_like(low32)
+        net.forward_region(low32, rho, den)    # warm
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        net.forward_region(low32, rho, den)
+        torch.cuda.synchronize()
+        t_inf = time.perf_counter() - t
+        net.close()
+        disagree, _ = unet.pmc_denoise_disagreement(den, low, var_low, 0.1, 4.0)
+        plain = [sim.run(plan["spots"], n, 80_000 + 16 * pi + k, var=False) for k, n in enumerate(sweep)]
+        ref_h = ref.cpu().numpy()
+        rec = {"plan": pi, "grid": [d, h, w], "spots": int(len(plan["spots"])), "n_plan": plan["n_histories"],
+               "t_plan_s": t_own, "t_ref_s": t_ref, "t_mc_low_s": t_low, "t_infer_s": t_inf,
+               "disagreement": disagree, "rule_fallback": bool(disagree > 0.02),
+               "mre_denoised": _mean_rel_error(den.double().cpu().numpy(), ref_h),
+               "mre_low": _mean_rel_error(low.cpu().numpy(), ref_h),
+               "plain_wall_s": [p_[2] for p_ in plain], "plain_n": list(sweep)}
+        for name, crit in CRITERIA.items():
+            g_den, n_eval = unet.pmc_gamma_index(ref, den.double(), vox_of(plan), **crit)
+            g_low, _ = unet.pmc_gamma_index(ref, low, vox_of(plan), **crit)
+            g_own, _ = unet.pmc_gamma_index(ref, own, vox_of(plan), **crit)
+            rates = [unet.pmc_gamma_index(ref, p_[0], vox_of(plan), **crit)[0] for p_ in plain]
+            t_plain = n_plain = None
+            for n, (_, _, tt), g in zip(sweep, plain, rates):
+                if g >= 0.98:
+                    t_plain, n_plain = tt, n
+                    break
+            ok = g_den >= 0.98
+            t_den = t_low + t_inf + (0.0 if ok else (t_plain if t_plain is not None else plain[-1][2]))
+            rec[name] = {"n_eval": n_eval, "gamma_pass_denoised": g_den, "gamma_pass_low": g_low,
+                         "gamma_pass_plan_n": g_own, "plain_gamma_pass": rates, "t_plain_s": t_plain,
+                         "n_plain": n_plain, "t_den_s": t_den, "denoised_ok": bool(ok),
+                         "speedup": (t_plain / t_den) if t_plain is not None else None}
+            log("plan %d %s: gamma den %.4f low %.4f plan-N %.4f  N_plain %s  T_plain %s  T_den %.4f s  speedup %s"
+                % (pi, name, g_den, g_low, g_own, n_plain, "%.4f" % t_plain if t_plain else "-", t_den,
+                   "%.2f" % rec[name]["speedup"] if rec[name]["speedup"] else "-"))
+        log("plan %d %s, %d spots, N %d: T_plan %.2f ms  T_MC(low) %.2f ms  T_infer %.2f ms  MRE den %.4f low %.4f"
+            % (pi, "x".join(map(str, (w, h, d))), len(plan["spots"]), plan["n_histories"], 1e3 * t_own,
+               1e3 * t_low, 1e3 * t_inf, rec["mre_denoised"], rec["mre_low"]))
+        out.append(rec)
+    return out
+
+
+def vox_of(plan):
+    return tuple(float(v) for v in plan["voxel_cm"])
+
+
 def summarize(recs):
     out = {
         "cases": len(recs),
@@ -258,9 +326,26 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", default=None)
     ap.add_argument("--save-params", default=None)
+    ap.add_argument("--load-params", default=None,
+                    help="trained weights (.npy from --save-params): skip the data set and training")
+    ap.add_argument("--plans", type=int, default=0,
+                    help="also evaluate time to gamma on this many plans of the uneven batch workload")
+    ap.add_argument("--plan-ref", type=int, default=100_000_000, help="reference histories per plan")
     a = ap.parse_args(argv)
     import torch
     sim = Simulator(0)
+    if a.load_params:
+        params = np.load(a.load_params)
+        recs = evaluate_plans(sim, params, synth.plan_set(a.plans or 16, seed=100), a.n_low, a.plan_ref)
+        summ = summarize(recs)
+        summ.update({"plans": len(recs), "n_low": a.n_low, "n_ref": a.plan_ref, "params": a.load_params})
+        _log("plan summary %s" % json.dumps(summ))
+        if a.out:
+            with open(a.out, "w") as f:
+                json.dump({"summary": summ, "plans": recs}, f, indent=1)
+        sim.close()
+        torch.cuda.synchronize()
+        return
     t0 = time.perf_counter()
     data = build_dataset(sim, range(a.cases), a.n_low, a.n_high)
     t_data = time.perf_counter() - t0
