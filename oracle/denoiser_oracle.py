@@ -297,3 +297,26 @@ def gamma_index(ref, ev, voxel_cm, dose_frac=0.02, dta_cm=0.2, cutoff_frac=0.1, 
     n = int(mask.sum())
     rate = float((g[mask] <= 1.0).mean()) if n else 1.0
     return g, rate, n
+
+
+def disagreement(den, mc, var, cutoff_frac=0.1, k_sigma=4.0):
+    """The denoiser's fallback rule written out: among the voxels with
+    mc >= cutoff_frac * max(mc) and mc > 0, the fraction where
+    |den - mc| > k_sigma * sqrt(max(var, 0)), i.e. where the denoised dose
+    departs from the Monte Carlo dose it was computed from by more than
+    k_sigma of that dose's own standard error (the 10-group estimate of
+    Eq. 5).  cutoff_frac and k_sigma are taken at float32 precision (as the
+    library receives them), den as float32 values.  Returns (fraction,
+    number of voxels above the cutoff)."""
+    c = float(np.float32(cutoff_frac))
+    k = float(np.float32(k_sigma))
+    den = np.asarray(den, np.float32).astype(np.float64).ravel()
+    mc = np.asarray(mc, np.float64).ravel()
+    var = np.asarray(var, np.float64).ravel()
+    thr = c * mc.max() if mc.size else 0.0
+    sel = (mc >= thr) & (mc > 0.0)
+    n = int(sel.sum())
+    if n == 0:
+        return 0.0, 0
+    off = np.abs(den[sel] - mc[sel]) > k * np.sqrt(np.maximum(var[sel], 0.0))
+    return float(off.sum()) / n, n

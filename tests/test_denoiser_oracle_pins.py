@@ -297,3 +297,21 @@ def test_bf16_inputs_are_exact():
     # 8 significant bits: the value times 2^k is an integer below 256
     m, e = np.frexp(vals[vals != 0])
     assert np.all(np.abs(m * 256 - np.round(m * 256)) == 0)
+
+
+def test_disagreement_rule_on_a_hand_counted_case():
+    """Four voxels, cutoff 10% of the maximum (10 -> threshold 1): voxel 2
+    (0.5) is below it; of the other three, voxel 0 departs by 5 against
+    4 sigma = 4 (out), voxel 1 by 0.5 against 4 (in), voxel 3 by 3 against
+    4 x 0.5 = 2 (out): 2 of 3."""
+    mc = np.array([10.0, 5.0, 0.5, 8.0])
+    var = np.array([1.0, 1.0, 1.0, 0.25])
+    den = np.array([15.0, 5.5, 0.5, 5.0], np.float32)
+    frac, n = D.disagreement(den, mc, var, 0.1, 4.0)
+    assert n == 3 and frac == 2.0 / 3.0
+    # no denoising, no disagreement; a zero dose has nothing above the cutoff
+    assert D.disagreement(mc.astype(np.float32), mc, var) == (0.0, 3)
+    assert D.disagreement(np.zeros(4, np.float32), np.zeros(4), var) == (0.0, 0)
+    # a negative variance estimate counts as zero: any departure is out
+    frac, n = D.disagreement(np.array([10.5], np.float32), np.array([10.0]), np.array([-1.0]))
+    assert (frac, n) == (1.0, 1)

@@ -431,6 +431,31 @@ def test_gamma_full_size_sampled():
     _say("full-size gamma pass rate %.4f over %d voxels" % (rate, n))
 
 
+@pytest.mark.parametrize("shape,k", [((160, 128, 128), 4.0), ((7, 9, 11), 2.5), ((1, 1, 1), 4.0)])
+def test_disagreement_rule_matches_oracle(shape, k):
+    """The fallback rule's fraction and count equal the oracle's exactly
+    (both sides take every decision in FP64 on the same float32 inputs):
+    a dose with a spread of values, a noisy denoised copy with a seeded set
+    of larger departures, per-voxel variances including zeros and negative
+    estimates; a full-size grid, a ragged small one, a single voxel."""
+    import torch
+    _say("case: disagreement %s k=%g" % (shape, k))
+    U = _unet()
+    rng = np.random.default_rng(71)
+    mc = rng.gamma(2.0, 1.0, size=shape) * (rng.random(shape) < 0.7)
+    var = (0.05 * mc) ** 2 * rng.uniform(0.5, 1.5, size=shape)
+    var[rng.random(shape) < 0.01] = 0.0
+    var[rng.random(shape) < 0.005] = -1e-6
+    den = (mc + rng.normal(0.0, 1.0, size=shape) * np.sqrt(np.maximum(var, 0.0))).astype(np.float32)
+    big = rng.random(shape) < 0.03
+    den[big] += (8.0 * np.sqrt(np.maximum(var[big], 1e-12))).astype(np.float32)
+    frac, n = U.pmc_denoise_disagreement(torch.from_numpy(den).cuda(), torch.from_numpy(mc).cuda(),
+                                         torch.from_numpy(var).cuda(), 0.1, k)
+    frac_o, n_o = D.disagreement(den, mc, var, 0.1, k)
+    _say("fraction %.6f of %d (oracle %.6f of %d)" % (frac, n, frac_o, n_o))
+    assert n == n_o and frac == frac_o
+
+
 def test_mfma_probe_rate_is_plausible():
     """The matrix-core probe: a register-only BF16 MFMA stream over the whole
     device reaches a substantial part of the 2.5 PFLOP/s dense peak and never
