@@ -60,3 +60,29 @@ def test_stream_probe_bandwidth_is_plausible():
     assert 500 < read_gbs < 8000 and 500 < copy_gbs < 8000
     with pytest.raises(pmc.PMCError):
         pmc.pmc_stream_probe(pmc.Engine(0).ctx, 1000)
+
+
+def test_atomic_probe_rate_is_plausible_and_leaves_the_dose():
+    """The tally-pattern atomic probe: a positive time that grows with the
+    atomic count, a rate between 1e9 and 1e11 FP64 atomics per second, a
+    geometry required, and the engine's next run unchanged (the probe adds
+    zeros into the tally)."""
+    _say("case: atomic probe")
+    nd, mt = synth.nuclear_data(), synth.material_table()
+    cfg = synth.config_water_pencil(50_000)
+    e = pmc.Engine(0)
+    e.load_physics(nd)
+    with pytest.raises(pmc.PMCError):
+        pmc.pmc_atomic_probe(e.ctx, 1000)          # no geometry yet
+    e.load_geometry(cfg["hu"], cfg["voxel_cm"], mt)
+    d0, v0, s0 = e.run_spots(cfg["spots"], cfg["n_histories"], 4)
+    t1 = pmc.pmc_atomic_probe(e.ctx, 20_000_000)
+    t2 = pmc.pmc_atomic_probe(e.ctx, 80_000_000)
+    _say("probe %.3f ms for 2e7, %.3f ms for 8e7 atomics" % (t1, t2))
+    assert 0 < t1 < t2
+    rate = 8e7 / (t2 * 1e-3)
+    assert 1e9 < rate < 1e11, rate
+    d1, v1, s1 = e.run_spots(cfg["spots"], cfg["n_histories"], 4)
+    e.close()
+    np.testing.assert_allclose(d1, d0, rtol=1e-9, atol=1e-12 * d0.max())
+    assert s1["steps"] == s0["steps"]
