@@ -392,3 +392,44 @@ def test_cascade_event_list_overflow_is_reported_and_ledger_closes():
     assert 0 < s["inc_events"] < s["n_nonelastic"]
     assert ledger_residual(s) < 1e-9
     assert dose.sum() > 0
+
+
+@pytest.mark.parametrize("k", range(5))
+def test_random_small_cases_with_the_cascade(k):
+    """The seeded random small cases of the table-model parity test, with
+    non-elastic events by the cascade: the ledger closes to rounding on the
+    GPU, the dose is finite and non-negative, and against the oracle (same
+    seed, FP64 cascade) the deposited, escaped and neutral fractions agree
+    within 1% of the incident energy, the steps per history within 2%, and
+    the event and emitted-proton counts within their counting noise."""
+    import importlib.util
+    import os
+    spec = importlib.util.spec_from_file_location("parity_cases", os.path.join(os.path.dirname(__file__),
+                                                                               "test_gpu_parity.py"))
+    P = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(P)
+    hu, vox, sp = P._random_case(k)
+    n = 20_000
+    nd, mt = synth.nuclear_data(), synth.material_table()
+    _say("case: random %d with the cascade, grid %s voxels %s spots %d" % (k, hu.shape, vox, len(sp)))
+    e = pmc.Engine(0, flags=pmc.PMC_INC)
+    e.load_physics(nd)
+    e.load_geometry(hu, vox, mt)
+    gd, gv, gs = e.run_spots(sp, n, 9)
+    e.close()
+    o = O.Oracle(flags=O.INC)
+    o.load_physics(nd)
+    o.load_geometry(hu, vox, mt)
+    r = o.run_spots(sp, n, 9)
+    o.close()
+    os_ = r["summary"]
+    assert np.all(np.isfinite(gd)) and np.all(gd >= 0) and np.all(np.isfinite(gv))
+    assert ledger_residual(gs) < 1e-9 and ledger_residual(os_) < 1e-9, (gs, os_)
+    for key in ("deposited", "escaped", "neutral"):
+        a, b = gs[key] / gs["incident"], os_[key] / os_["incident"]
+        assert abs(a - b) <= 0.01, (key, a, b)
+    assert abs(gs["steps"] / max(os_["steps"], 1) - 1) < 0.02, (gs["steps"], os_["steps"])
+    assert gs["inc_events"] == gs["n_nonelastic"]
+    for key in ("n_nonelastic", "secondaries"):
+        a, b = gs[key], os_[key]
+        assert abs(a - b) <= 4 * math.sqrt(a + b) + 3, (key, a, b)
