@@ -244,6 +244,34 @@ def test_random_small_cases_close_and_agree(nd, mt, k):
         assert abs(a - b) <= 4 * math.sqrt(a + b) + 3, (key, a, b)
 
 
+@pytest.mark.parametrize("k,flag", [(0, "vavilov"), (3, "vavilov"), (6, "vavilov"),
+                                    (1, "moliere"), (4, "moliere"), (9, "moliere")])
+def test_random_small_cases_with_options(nd, mt, k, flag):
+    """The same random cases with Vavilov-Gaussian straggling or Molière
+    scattering on both sides: ledger, energy fractions, steps and event
+    counts as for the defaults."""
+    hu, vox, sp = _random_case(k)
+    n = 20_000
+    gflag, oflag = {"vavilov": (pmc.PMC_VAVILOV, O.VAVILOV), "moliere": (pmc.PMC_MOLIERE, O.MOLIERE)}[flag]
+    _say("case: random %d with %s" % (k, flag))
+    e = _engine(nd, mt, hu, vox, flags=gflag)
+    gd, gv, gs = e.run_spots(sp, n, 9)
+    e.close()
+    o = _oracle(nd, mt, hu, vox, flags=oflag)
+    r = o.run_spots(sp, n, 9)
+    o.close()
+    os_ = r["summary"]
+    assert np.all(np.isfinite(gd)) and np.all(gd >= 0)
+    assert ledger_residual(gs) < 1e-9 and ledger_residual(os_) < 1e-9, (gs, os_)
+    for key in ("deposited", "escaped", "neutral"):
+        a, b = gs[key] / gs["incident"], os_[key] / os_["incident"]
+        assert abs(a - b) <= 0.01, (key, a, b)
+    assert abs(gs["steps"] / max(os_["steps"], 1) - 1) < 0.02, (gs["steps"], os_["steps"])
+    for key in ("n_nonelastic", "n_elastic"):
+        a, b = gs[key], os_[key]
+        assert abs(a - b) <= 4 * math.sqrt(a + b) + 3, (key, a, b)
+
+
 def test_independent_seeds_are_consistent(nd, mt):
     cfg = synth.config_water_pencil(60_000)
     m, _, _ = _parity(nd, mt, cfg["hu"], cfg["spots"], cfg["n_histories"], seed_gpu=2, seed_ora=3,
