@@ -197,3 +197,40 @@ def test_batched_options_equal_single_plans():
         for key in ("steps", "n_elastic", "n_nonelastic", "histories"):
             assert sums[p][key] == s[key], (p, key)
         assert ledger_residual(sums[p]) < 1e-9
+
+
+def test_random_small_cases_batched_equal_single_plans():
+    """The seeded random small cases of the parity tests (anisotropic voxels
+    that differ from plan to plan, every material, spots off the phantom,
+    5-250 MeV), eight of them in one batch: each plan equals its own
+    single-plan run (plan p keyed seed + p) and its ledger closes."""
+    import importlib.util
+    import os
+    import torch
+    spec_ = importlib.util.spec_from_file_location("parity_cases", os.path.join(os.path.dirname(__file__),
+                                                                                "test_gpu_parity.py"))
+    P = importlib.util.module_from_spec(spec_)
+    spec_.loader.exec_module(P)
+    _say("case: eight random small cases in one batch")
+    nd, mt = synth.nuclear_data(), synth.material_table()
+    plans = []
+    for k in range(8):
+        hu, vox, sp = P._random_case(k)
+        plans.append({"hu": hu, "voxel_cm": vox, "spots": sp, "n_histories": 10_000 + 1000 * k})
+    e, ids = _batch_engine(nd, mt, plans)
+    out, sums = _run_batch(e, ids, plans, 21)
+    e.close()
+    for p, plan in enumerate(plans):
+        single = pmc.Engine(0)
+        single.load_physics(nd)
+        single.load_geometry(plan["hu"], plan["voxel_cm"], mt)
+        d = torch.zeros(plan["hu"].shape, dtype=torch.float64, device="cuda")
+        v = torch.zeros_like(d)
+        s = single.run_spots_dev(plan["spots"], plan["n_histories"], 21 + p, d, v)
+        torch.cuda.synchronize()
+        single.close()
+        dd = d.cpu().numpy()
+        np.testing.assert_allclose(out[p][0], dd, rtol=1e-9, atol=1e-9 * max(dd.max(), 1e-300))
+        for key in ("steps", "n_elastic", "n_nonelastic", "tally_atomics", "histories"):
+            assert sums[p][key] == s[key], (p, key, sums[p][key], s[key])
+        assert ledger_residual(sums[p]) < 1e-9
