@@ -262,3 +262,45 @@ def test_let_with_vavilov_and_moliere(nd, mt):
     assert m["all_within_3sigma"], m
     assert ledger_residual(gs) < 1e-5
     assert same["slab_max"] <= 0.01 and same["rms"] <= indep["rms"], (same, indep)
+
+
+@pytest.mark.parametrize("k", [0, 3, 9])
+def test_random_small_cases_with_let(k):
+    """The seeded random small cases of the parity tests with LET_d scored
+    on both sides: the ledger closes, dose and LET_d are finite and
+    non-negative, the energy fractions agree within 1% of the incident
+    energy, and the dose-weighted mean LET_d over the voxels at or above 10%
+    of the maximum dose agrees within 2%."""
+    import importlib.util
+    import os
+    spec_ = importlib.util.spec_from_file_location("parity_cases", os.path.join(os.path.dirname(__file__),
+                                                                                "test_gpu_parity.py"))
+    P = importlib.util.module_from_spec(spec_)
+    spec_.loader.exec_module(P)
+    hu, vox, sp = P._random_case(k)
+    n = 20_000
+    nd, mt = synth.nuclear_data(), synth.material_table()
+    _say("case: random %d with LET_d" % k)
+    e = pmc.Engine(0)
+    e.load_physics(nd)
+    e.load_geometry(hu, vox, mt)
+    gd, gv, gl, gs = e.run_spots_let(sp, n, 9)
+    e.close()
+    o = O.Oracle()
+    o.load_physics(nd)
+    o.load_geometry(hu, vox, mt)
+    r = o.run_spots(sp, n, 9, let=True)
+    o.close()
+    os_ = r["summary"]
+    for a in (gd, gl, gv):
+        assert np.all(np.isfinite(a))
+    assert np.all(gd >= 0) and np.all(gl >= 0)
+    assert ledger_residual(gs) < 1e-9 and ledger_residual(os_) < 1e-9
+    for key in ("deposited", "escaped", "neutral"):
+        a, b = gs[key] / gs["incident"], os_[key] / os_["incident"]
+        assert abs(a - b) <= 0.01, (key, a, b)
+    sel = r["dose"] >= 0.1 * r["dose"].max()
+    lg = float((gl[sel] * gd[sel]).sum() / gd[sel].sum())
+    lo = float((r["let"][sel] * r["dose"][sel]).sum() / r["dose"][sel].sum())
+    _say("dose-weighted LET_d %.4f (GPU) %.4f (oracle) keV/um" % (lg, lo))
+    assert abs(lg / lo - 1) < 0.02, (lg, lo)
