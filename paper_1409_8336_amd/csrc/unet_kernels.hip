@@ -1042,6 +1042,12 @@ __global__ void __launch_bounds__(256) mfma_probe_kernel(int iters, float* __res
         for (int k = 0; k < 8; ++k)
             asm volatile("v_mfma_f32_16x16x32_bf16 %0, %1, %2, %0" : "+a"(acc[k]) : "v"(a), "v"(b));
     }
+    // the compiler does not track these instructions' results: wait out the
+    // last MFMA's passes before the accumulators are read (the accumulators
+    // pass through the wait, so no read is scheduled ahead of it)
+    asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 7"
+                 : "+a"(acc[0]), "+a"(acc[1]), "+a"(acc[2]), "+a"(acc[3]), "+a"(acc[4]), "+a"(acc[5]),
+                   "+a"(acc[6]), "+a"(acc[7]));
     float t = 0.f;
 #pragma unroll
     for (int k = 0; k < 8; ++k) t += acc[k][0] + acc[k][1] + acc[k][2] + acc[k][3];
